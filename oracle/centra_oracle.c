@@ -1,0 +1,584 @@
+/*
+ * centra_oracle.c -- plain, slow CPU oracle for the CentRA hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the
+ * benchmark's CPU-baseline leg.  Shares no code with the HIP path.
+ *
+ * Paper: L. Pellegrina, "Efficient Centrality Maximization with Rademacher
+ * Averages", KDD 2023 (arXiv 2306.03651).  Section / theorem / algorithm
+ * references below are to that paper.  Readings of points it leaves open:
+ *
+ *  R1  Randomness.  The paper fixes no generator.  All draws come from
+ *      Philox4x64-10 (Salmon et al., SC'11) with key (seed, 0) and counter
+ *      (block, sample index, instance, tag); tag 0 = path sampling, tag 1 =
+ *      Rademacher signs.  The sample index is global, so the sample of
+ *      iteration i extends the sample of iteration i-1 exactly (Algorithm 1,
+ *      H_i = H_{i-1} plus new hyperedges).
+ *  R2  Bounded draws use Lemire's multiply-and-reject method (TOMACS 2019).
+ *  R3  The pair is an ordered uniform pair s != t (Sec. 3.1 defines the
+ *      hyperedge space over all pairs u != v; Sec. 5 draws the endpoints
+ *      uniformly).
+ *  R4  Shortest-path counts are kept as normalised integers: level by level,
+ *      the raw count of a node is the sum of its predecessors' normalised
+ *      counts; if the largest raw count of the level needs more than C bits
+ *      (C = 63 - bitlen(max in-degree)), every count of that level is shifted
+ *      right by the excess, and clamped to at least 1.  While no level
+ *      exceeds 2^C the counts are exact.  (The paper samples a uniform
+ *      shortest path but does not say how counts are represented.)
+ *  R5  A single BFS from s followed by a backtrack from t replaces the
+ *      balanced bidirectional BFS of Sec. 5: the same distribution over
+ *      shortest paths, different random bits.
+ *  R6  Backtracking visits predecessors in ascending node id and always
+ *      draws, even when there is one predecessor.  An unreachable t, or t
+ *      adjacent to s, gives the empty hyperedge with no draws (Sec. 5: an
+ *      unreachable target gives the empty set; Sec. 3.1: only internal nodes
+ *      belong to the hyperedge).
+ *  R7  greedyCover breaks ties by lowest node id and stops early when the
+ *      best marginal gain is 0 (|S| <= k is allowed by the problem statement).
+ *  R8  sigma is extended column by column instead of redrawn each iteration
+ *      (Sec. 4.2 remark on incremental computation); sigma_js = +1 iff bit
+ *      (j mod 64) of word ((j mod 256) div 64) of Philox block
+ *      (j div 256, s, instance, 1) is set.
+ *  R9  The sup over |S'| <= k of sum_{u in S'} r_j^u is the sum of the
+ *      min(k, #positive) largest positive values (S' = empty is allowed).
+ *  R10 Iterations count from i = 1 with delta_i = delta / 2^i (Algorithm 1),
+ *      ln is the natural log, and the schedule is geometric with a cap m_max.
+ */
+#include "centra_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+#define UNSEEN 0xFFFFFFFFu
+
+/* ------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11, Sec. 3.4): ten rounds
+ * of two 64x64->128 multiplications with the published multipliers and a
+ * Weyl sequence on the key. */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        u128 p0 = (u128)M0 * x0;
+        u128 p1 = (u128)M1 * x2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        x0 = hi1 ^ x1 ^ k0;
+        x1 = lo1;
+        x2 = hi0 ^ x3 ^ k1;
+        x3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+void orc_stream_init(orc_stream *st, uint64_t seed, uint64_t c1, uint64_t c2, uint64_t c3)
+{
+    st->key[0] = seed;
+    st->key[1] = 0;
+    st->ctr[0] = 0;
+    st->ctr[1] = c1;
+    st->ctr[2] = c2;
+    st->ctr[3] = c3;
+    st->pos = 4;
+}
+
+uint64_t orc_stream_next(orc_stream *st)
+{
+    if (st->pos == 4) {
+        orc_philox4x64_10(st->ctr, st->key, st->buf);
+        st->ctr[0] += 1;
+        st->pos = 0;
+    }
+    return st->buf[st->pos++];
+}
+
+/* Lemire, "Fast random integer generation in an interval", TOMACS 2019,
+ * Algorithm 5: multiply a 64-bit word by W, keep the high half, and reject
+ * the low half if it falls below (2^64 - W) mod W. */
+uint64_t orc_bounded(orc_stream *st, uint64_t W)
+{
+    uint64_t x = orc_stream_next(st);
+    u128 p = (u128)x * W;
+    uint64_t low = (uint64_t)p;
+    if (low < W) {
+        uint64_t threshold = (0 - W) % W;
+        while (low < threshold) {
+            x = orc_stream_next(st);
+            p = (u128)x * W;
+            low = (uint64_t)p;
+        }
+    }
+    return (uint64_t)(p >> 64);
+}
+
+void orc_bounded_many(uint64_t seed, uint64_t c1, uint64_t c2, uint64_t c3,
+                      uint64_t W, uint64_t count, uint64_t *out)
+{
+    orc_stream st;
+    orc_stream_init(&st, seed, c1, c2, c3);
+    for (uint64_t i = 0; i < count; i++)
+        out[i] = orc_bounded(&st, W);
+}
+
+/* ------------------------------------------------------------------ */
+/* Graph helpers. */
+
+static const uint32_t *in_ptr(const orc_graph *g) { return g->directed ? g->rrow_ptr : g->row_ptr; }
+static const uint32_t *in_idx(const orc_graph *g) { return g->directed ? g->rcol_idx : g->col_idx; }
+
+static int check_rows(uint32_t n, uint64_t n_arcs, const uint32_t *ptr, const uint32_t *idx)
+{
+    if (!ptr || !idx) return -2;
+    if (ptr[0] != 0 || ptr[n] != n_arcs) return -3;
+    for (uint32_t u = 0; u < n; u++) {
+        if (ptr[u + 1] < ptr[u]) return -4;
+        for (uint32_t e = ptr[u]; e < ptr[u + 1]; e++) {
+            if (idx[e] >= n) return -5;
+            if (idx[e] == u) return -6;
+            if (e > ptr[u] && idx[e] <= idx[e - 1]) return -7;
+        }
+    }
+    return 0;
+}
+
+int orc_graph_check(const orc_graph *g)
+{
+    if (g->n < 2) return -1;
+    int rc = check_rows(g->n, g->n_arcs, g->row_ptr, g->col_idx);
+    if (rc) return rc;
+    if (g->directed) {
+        rc = check_rows(g->n, g->n_arcs, g->rrow_ptr, g->rcol_idx);
+        if (rc) return rc - 10;
+        /* the reverse rows hold exactly the reversed arcs */
+        uint64_t *cnt = calloc(g->n, sizeof(uint64_t));
+        for (uint32_t u = 0; u < g->n; u++)
+            for (uint32_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; e++)
+                cnt[g->col_idx[e]]++;
+        for (uint32_t v = 0; v < g->n; v++)
+            if (cnt[v] != (uint64_t)(g->rrow_ptr[v + 1] - g->rrow_ptr[v])) { free(cnt); return -20; }
+        free(cnt);
+    }
+    return 0;
+}
+
+static uint32_t bitlen64(uint64_t x)
+{
+    uint32_t b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+
+uint32_t orc_count_bits(const orc_graph *g)
+{
+    const uint32_t *ip = in_ptr(g);
+    uint64_t dmax = 0;
+    for (uint32_t v = 0; v < g->n; v++) {
+        uint64_t d = ip[v + 1] - ip[v];
+        if (d > dmax) dmax = d;
+    }
+    return 63 - bitlen64(dmax);
+}
+
+/* ------------------------------------------------------------------ */
+/* BFS with normalised counts (reading R4).  Expands whole levels from s
+ * until `stop` has a level, or the graph is exhausted if stop == UNSEEN.
+ * On return level[] and sigma[] hold the levels and normalised counts of
+ * every node reached, and *visited holds the reached nodes. */
+typedef struct {
+    uint32_t *level;
+    uint64_t *sigma;
+    uint32_t *visited;   /* reached nodes, in level order */
+    uint32_t n_visited;
+    uint64_t arcs_scanned;
+} bfs_state;
+
+static void bfs_from(const orc_graph *g, uint32_t c_bits, uint32_t s, uint32_t stop,
+                     bfs_state *b)
+{
+    b->n_visited = 0;
+    b->arcs_scanned = 0;
+    b->level[s] = 0;
+    b->sigma[s] = 1;
+    b->visited[b->n_visited++] = s;
+    uint32_t lo = 0, hi = 1;        /* visited[lo, hi) is the current level */
+    uint32_t L = 0;
+    while (lo < hi && (stop == UNSEEN || b->level[stop] == UNSEEN)) {
+        /* expand level L: discover level L+1 and accumulate raw counts */
+        for (uint32_t q = lo; q < hi; q++) {
+            uint32_t w = b->visited[q];
+            for (uint32_t e = g->row_ptr[w]; e < g->row_ptr[w + 1]; e++) {
+                uint32_t v = g->col_idx[e];
+                b->arcs_scanned++;
+                if (b->level[v] == UNSEEN) {
+                    b->level[v] = L + 1;
+                    b->sigma[v] = 0;
+                    b->visited[b->n_visited++] = v;
+                }
+                if (b->level[v] == L + 1)
+                    b->sigma[v] += b->sigma[w];
+            }
+        }
+        lo = hi;
+        hi = b->n_visited;
+        /* normalise level L+1: shift by the excess of its largest raw count */
+        uint64_t mx = 0;
+        for (uint32_t q = lo; q < hi; q++)
+            if (b->sigma[b->visited[q]] > mx) mx = b->sigma[b->visited[q]];
+        uint32_t bl = bitlen64(mx);
+        uint32_t shift = bl > c_bits ? bl - c_bits : 0;
+        for (uint32_t q = lo; q < hi; q++) {
+            uint64_t x = b->sigma[b->visited[q]] >> shift;
+            b->sigma[b->visited[q]] = x ? x : 1;
+        }
+        L++;
+    }
+}
+
+static void bfs_reset(bfs_state *b)
+{
+    for (uint32_t q = 0; q < b->n_visited; q++) {
+        b->level[b->visited[q]] = UNSEEN;
+        b->sigma[b->visited[q]] = 0;
+    }
+    b->n_visited = 0;
+}
+
+static int bfs_alloc(bfs_state *b, uint32_t n)
+{
+    b->level = malloc(sizeof(uint32_t) * n);
+    b->sigma = calloc(n, sizeof(uint64_t));
+    b->visited = malloc(sizeof(uint32_t) * n);
+    if (!b->level || !b->sigma || !b->visited) return -1;
+    for (uint32_t v = 0; v < n; v++) b->level[v] = UNSEEN;
+    b->n_visited = 0;
+    return 0;
+}
+
+static void bfs_free(bfs_state *b)
+{
+    free(b->level); free(b->sigma); free(b->visited);
+}
+
+void orc_bfs_counts(const orc_graph *g, uint32_t c_bits, uint32_t s,
+                    uint32_t *level, uint64_t *sigma)
+{
+    bfs_state b;
+    bfs_alloc(&b, g->n);
+    bfs_from(g, c_bits, s, UNSEEN, &b);
+    for (uint32_t v = 0; v < g->n; v++) {
+        level[v] = b.level[v];
+        sigma[v] = b.level[v] == UNSEEN ? 0 : b.sigma[v];
+    }
+    bfs_free(&b);
+}
+
+/* One hyperedge of the set-betweenness space (Sec. 3.1; sampling procedure
+ * of Sec. 5 under readings R1-R6). */
+static uint32_t sample_one(const orc_graph *g, uint32_t c_bits, uint64_t seed,
+                           uint32_t instance, uint64_t sample, uint32_t *h,
+                           orc_sample_info *info, bfs_state *b)
+{
+    orc_stream st;
+    orc_stream_init(&st, seed, sample, instance, 0);
+    uint32_t n = g->n;
+    uint32_t s = (uint32_t)orc_bounded(&st, n);
+    uint32_t tp = (uint32_t)orc_bounded(&st, n - 1);
+    uint32_t t = tp + (tp >= s ? 1u : 0u);
+
+    bfs_from(g, c_bits, s, t, b);
+    uint32_t d = b->level[t];
+    uint32_t len = 0;
+    if (d != UNSEEN && d >= 2) {
+        const uint32_t *ip = in_ptr(g), *ii = in_idx(g);
+        uint32_t v = t;
+        while (b->level[v] >= 2) {
+            uint32_t want = b->level[v] - 1;
+            uint64_t W = 0;
+            for (uint32_t e = ip[v]; e < ip[v + 1]; e++)
+                if (b->level[ii[e]] == want) W += b->sigma[ii[e]];
+            uint64_t r = orc_bounded(&st, W);
+            uint64_t acc = 0;
+            uint32_t pick = UNSEEN;
+            for (uint32_t e = ip[v]; e < ip[v + 1]; e++) {
+                uint32_t w = ii[e];
+                if (b->level[w] != want) continue;
+                acc += b->sigma[w];
+                if (acc > r) { pick = w; break; }
+            }
+            h[len++] = pick;
+            v = pick;
+        }
+    }
+    if (info) {
+        info->s = s;
+        info->t = t;
+        info->dist = d;
+        info->len = len;
+        info->arcs_scanned = b->arcs_scanned;
+        info->nodes_visited = b->n_visited;
+    }
+    bfs_reset(b);
+    return len;
+}
+
+uint32_t orc_sample_path(const orc_graph *g, uint32_t c_bits, uint64_t seed,
+                         uint32_t instance, uint64_t sample, uint32_t *h,
+                         orc_sample_info *info)
+{
+    bfs_state b;
+    if (bfs_alloc(&b, g->n)) return 0;
+    uint32_t len = sample_one(g, c_bits, seed, instance, sample, h, info, &b);
+    bfs_free(&b);
+    return len;
+}
+
+uint64_t orc_sample_paths(const orc_graph *g, uint32_t c_bits, uint64_t seed,
+                          uint32_t instance, uint64_t first, uint64_t count,
+                          uint64_t *he_off, uint32_t *he_nodes, uint64_t he_cap,
+                          orc_sample_info *infos)
+{
+    bfs_state b;
+    if (bfs_alloc(&b, g->n)) return UINT64_MAX;
+    uint32_t *h = malloc(sizeof(uint32_t) * g->n);
+    uint64_t total = 0;
+    he_off[0] = 0;
+    for (uint64_t i = 0; i < count; i++) {
+        uint32_t len = sample_one(g, c_bits, seed, instance, first + i, h,
+                                  infos ? &infos[i] : NULL, &b);
+        if (total + len > he_cap) { total = UINT64_MAX; break; }
+        memcpy(he_nodes + total, h, sizeof(uint32_t) * len);
+        total += len;
+        he_off[i + 1] = total;
+    }
+    free(h);
+    bfs_free(&b);
+    return total;
+}
+
+/* ------------------------------------------------------------------ */
+/* greedyCover(k, H) (Sec. 3.1; Algorithm 1 greedy step).  Each round
+ * recomputes, for every node, the number of not-yet-covered hyperedges it
+ * belongs to -- its marginal gain m*(C_H(S u {u}) - C_H(S)) -- and adds the
+ * node with the largest gain (reading R7). */
+uint32_t orc_greedy_cover(uint32_t n, uint64_t m, const uint64_t *he_off,
+                          const uint32_t *he_nodes, uint32_t k,
+                          uint32_t *picks, uint64_t *cov_cum)
+{
+    uint8_t *covered = calloc(m ? m : 1, 1);
+    uint64_t *gain = malloc(sizeof(uint64_t) * n);
+    uint64_t cov = 0;
+    uint32_t r;
+    for (r = 0; r < k; r++) {
+        memset(gain, 0, sizeof(uint64_t) * n);
+        for (uint64_t s = 0; s < m; s++) {
+            if (covered[s]) continue;
+            for (uint64_t e = he_off[s]; e < he_off[s + 1]; e++)
+                gain[he_nodes[e]]++;
+        }
+        uint32_t best = 0;
+        for (uint32_t u = 1; u < n; u++)
+            if (gain[u] > gain[best]) best = u;
+        if (gain[best] == 0) break;
+        for (uint64_t s = 0; s < m; s++) {
+            if (covered[s]) continue;
+            for (uint64_t e = he_off[s]; e < he_off[s + 1]; e++)
+                if (he_nodes[e] == best) { covered[s] = 1; cov++; break; }
+        }
+        picks[r] = best;
+        cov_cum[r] = cov;
+    }
+    free(covered);
+    free(gain);
+    return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* Rademacher matrix (Sec. 2.2 definition of sigma; reading R8). */
+int orc_rademacher(uint64_t seed, uint32_t instance, uint64_t s, uint32_t j)
+{
+    uint64_t ctr[4] = { j / 256u, s, instance, 1 };
+    uint64_t key[2] = { seed, 0 };
+    uint64_t out[4];
+    orc_philox4x64_10(ctr, key, out);
+    uint64_t word = out[(j % 256u) / 64u];
+    return ((word >> (j % 64u)) & 1u) ? 1 : -1;
+}
+
+/* m * r_j^u of Algorithm 1 (AMCERA step): R[u][j] = sum_s sigma_js f_u(h_s). */
+void orc_rade_sums(uint32_t n, uint64_t m, const uint64_t *he_off,
+                   const uint32_t *he_nodes, uint64_t seed, uint32_t instance,
+                   uint32_t t, int64_t *R)
+{
+    memset(R, 0, sizeof(int64_t) * (size_t)n * t);
+    int *sig = malloc(sizeof(int) * t);
+    for (uint64_t s = 0; s < m; s++) {
+        if (he_off[s + 1] == he_off[s]) continue;
+        for (uint32_t j = 0; j < t; j++)
+            sig[j] = orc_rademacher(seed, instance, s, j);
+        for (uint64_t e = he_off[s]; e < he_off[s + 1]; e++) {
+            uint32_t u = he_nodes[e];
+            for (uint32_t j = 0; j < t; j++)
+                R[(size_t)u * t + j] += sig[j];
+        }
+    }
+    free(sig);
+}
+
+static int cmp_desc_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return x < y ? 1 : (x > y ? -1 : 0);
+}
+
+static int cmp_desc_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? 1 : (x > y ? -1 : 0);
+}
+
+/* AMCERA (Sec. 4.1 definition; Algorithm 1 AMCERA steps) and the inputs of
+ * the approximate wimpy variance (Sec. 4.1 definition): the per-trial
+ * supremum is the sum of the largest positive sums (reading R9). */
+double orc_mcera(uint32_t n, uint64_t m, const uint64_t *he_off,
+                 const uint32_t *he_nodes, uint64_t seed, uint32_t instance,
+                 uint32_t t, uint32_t k, int64_t *topk_sum,
+                 uint64_t *deg_topk, uint32_t *b_max)
+{
+    int64_t *R = malloc(sizeof(int64_t) * (size_t)n * t);
+    orc_rade_sums(n, m, he_off, he_nodes, seed, instance, t, R);
+    int64_t *col = malloc(sizeof(int64_t) * n);
+    int64_t total = 0;
+    for (uint32_t j = 0; j < t; j++) {
+        uint32_t npos = 0;
+        for (uint32_t u = 0; u < n; u++) {
+            int64_t x = R[(size_t)u * t + j];
+            if (x > 0) col[npos++] = x;
+        }
+        qsort(col, npos, sizeof(int64_t), cmp_desc_i64);
+        int64_t sum = 0;
+        for (uint32_t q = 0; q < npos && q < k; q++) sum += col[q];
+        topk_sum[j] = sum;
+        total += sum;
+    }
+    free(col);
+    free(R);
+
+    uint64_t *deg = calloc(n, sizeof(uint64_t));
+    uint32_t bm = 0;
+    for (uint64_t s = 0; s < m; s++) {
+        uint64_t len = he_off[s + 1] - he_off[s];
+        if (len > bm) bm = (uint32_t)len;
+        for (uint64_t e = he_off[s]; e < he_off[s + 1]; e++) deg[he_nodes[e]]++;
+    }
+    qsort(deg, n, sizeof(uint64_t), cmp_desc_u64);
+    uint64_t dk = 0;
+    for (uint32_t q = 0; q < n && q < k; q++) dk += deg[q];
+    free(deg);
+    *deg_topk = dk;
+    *b_max = bm;
+    return (double)total / ((double)t * (double)m);
+}
+
+/* ------------------------------------------------------------------ */
+/* Theorem bound_dev (eq. epsrade) with the Algorithm 1 definition of xi and
+ * its stopping condition; a = 1 - 1/e and L = ln(5/delta_i). */
+void orc_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t,
+               uint64_t deg_topk, uint32_t b_max, double eps, double delta_i,
+               orc_bound_out *o)
+{
+    const double a = 1.0 - exp(-1.0);
+    const double md = (double)m;
+    const double L = log(5.0 / delta_i);
+    const double C = (double)cov / md;
+    const double amcera = (double)sum_topk / ((double)t * md);
+    const double wimpy = (double)b_max * (double)deg_topk / md;
+    const double xi = sqrt((L / md) * (L / md) + 2.0 * C * L / (a * md)) + L / md;
+    const double nu = C / a + xi;
+    const double rtilde = amcera + sqrt(4.0 * wimpy * L / ((double)t * md));
+    const double r = rtilde + sqrt((L / md) * (L / md) + 2.0 * L * rtilde / md) + L / md;
+    const double eta = 2.0 * r + sqrt(2.0 * L * (nu + 4.0 * r) / md) + L / (3.0 * md);
+    o->c_hat = C;
+    o->amcera = amcera;
+    o->wimpy = wimpy;
+    o->xi = xi;
+    o->nu = nu;
+    o->rtilde = rtilde;
+    o->r = r;
+    o->eta = eta;
+    o->certified = a * ((a - eps) * xi + eta) <= eps * C;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1 (progressive sampling), readings R1 and R10. */
+int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
+                    double eps, double delta, uint64_t seed, uint32_t instance,
+                    uint64_t m_init, uint64_t m_max, uint32_t growth_num,
+                    uint32_t growth_den, uint32_t *picks, orc_result *res)
+{
+    const double a = 1.0 - exp(-1.0);
+    if (k == 0 || t == 0 || !(eps > 0.0 && eps < a) || !(delta > 0.0 && delta < 1.0) ||
+        m_init == 0 || m_max < m_init || growth_den == 0 || growth_num <= growth_den)
+        return -1;
+    uint64_t cap = 1024;
+    uint64_t *he_off = malloc(sizeof(uint64_t) * (m_max + 1));
+    uint32_t *he_nodes = malloc(sizeof(uint32_t) * cap);
+    uint32_t *h = malloc(sizeof(uint32_t) * g->n);
+    uint64_t *cov_cum = malloc(sizeof(uint64_t) * k);
+    int64_t *topk = malloc(sizeof(int64_t) * t);
+    bfs_state b;
+    bfs_alloc(&b, g->n);
+    he_off[0] = 0;
+    uint64_t m_prev = 0, m_i = m_init;
+    int rc = 1;
+    memset(res, 0, sizeof(*res));
+    for (uint32_t i = 1;; i++) {
+        const double delta_i = ldexp(delta, -(int)i);
+        for (uint64_t s = m_prev; s < m_i; s++) {
+            uint32_t len = sample_one(g, c_bits, seed, instance, s, h, NULL, &b);
+            if (he_off[s] + len > cap) {
+                while (he_off[s] + len > cap) cap *= 2;
+                he_nodes = realloc(he_nodes, sizeof(uint32_t) * cap);
+            }
+            memcpy(he_nodes + he_off[s], h, sizeof(uint32_t) * len);
+            he_off[s + 1] = he_off[s] + len;
+        }
+        uint32_t np = orc_greedy_cover(g->n, m_i, he_off, he_nodes, k, picks, cov_cum);
+        uint64_t cov = np ? cov_cum[np - 1] : 0;
+        uint64_t dk;
+        uint32_t bm;
+        orc_mcera(g->n, m_i, he_off, he_nodes, seed, instance, t, k, topk, &dk, &bm);
+        int64_t sum = 0;
+        for (uint32_t j = 0; j < t; j++) sum += topk[j];
+        orc_bound_out o;
+        orc_bound(m_i, cov, sum, t, dk, bm, eps, delta_i, &o);
+        res->n_picked = np;
+        res->iterations = i;
+        res->certified = o.certified;
+        res->coverage = cov;
+        res->m_final = m_i;
+        res->c_hat = o.c_hat;
+        res->amcera = o.amcera;
+        res->wimpy = o.wimpy;
+        res->xi = o.xi;
+        res->nu = o.nu;
+        res->rtilde = o.rtilde;
+        res->r = o.r;
+        res->eta = o.eta;
+        if (o.certified) { rc = 0; break; }
+        if (m_i >= m_max) { rc = 1; break; }
+        m_prev = m_i;
+        u128 next = ((u128)m_i * growth_num + growth_den - 1) / growth_den;
+        m_i = next > m_max ? m_max : (uint64_t)next;
+    }
+    bfs_free(&b);
+    free(he_off); free(he_nodes); free(h); free(cov_cum); free(topk);
+    return rc;
+}
