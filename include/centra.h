@@ -1,0 +1,233 @@
+/*
+ * centra.h -- C ABI of the MI355X (gfx950) implementation of the CentRA hot
+ * path: progressive-sampling set-betweenness centrality maximisation with
+ * Monte-Carlo Rademacher bounds (L. Pellegrina, "Efficient Centrality
+ * Maximization with Rademacher Averages", KDD 2023, arXiv 2306.03651).
+ *
+ * Conventions (all entry points):
+ *   - Plain C types only.  Pointers documented "device" are HIP device
+ *     pointers (e.g. from torch.empty(..., device="cuda")); "host" pointers
+ *     are ordinary memory.  The caller owns every buffer it passes and keeps
+ *     it alive until the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Every entry point enqueues its work on `stream` and synchronises
+ *     `stream` before returning, so outputs are ready on return.
+ *   - Return codes: CENTRA_OK (0) on success, CENTRA_NOT_CERTIFIED (1) from
+ *     centra_progressive when the sample cap is reached, negative on error.
+ *     The text of the last error is available from centra_last_error().  No
+ *     C++ exception crosses this boundary.
+ *   - A context is not thread safe: use one per host thread.  Work of one
+ *     context runs on the HIP device given at creation.
+ *   - Randomness is counter based: for the same (seed, instance) every
+ *     hyperedge, Rademacher sign and result is a pure function of the
+ *     inputs, independent of launch shape, batch split or timing.
+ */
+#ifndef CENTRA_H
+#define CENTRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define CENTRA_API __attribute__((visibility("default")))
+#else
+#define CENTRA_API
+#endif
+
+#define CENTRA_ABI_VERSION 1u
+
+#define CENTRA_OK 0
+#define CENTRA_NOT_CERTIFIED 1
+#define CENTRA_EINVAL (-1)   /* invalid argument or malformed input */
+#define CENTRA_ENOMEM (-2)   /* the context's HBM budget or the device is exhausted */
+#define CENTRA_EHIP (-3)     /* HIP runtime error (text in centra_last_error) */
+#define CENTRA_ENOSPC (-4)   /* a caller output buffer is too small */
+#define CENTRA_ENOTSUP (-5)  /* unsupported configuration */
+
+typedef struct centra_ctx centra_ctx;
+typedef struct centra_graph centra_graph;
+
+/* Returns CENTRA_ABI_VERSION of the built library. */
+CENTRA_API uint32_t centra_abi_version(void);
+
+/* Creates a context on HIP device `hip_device`.  `hbm_budget_bytes` bounds
+ * the device memory the context allocates for its own workspaces (0 = no
+ * bound beyond the device).  *out receives the context.
+ * Errors: CENTRA_EINVAL (out == NULL), CENTRA_EHIP (no such device). */
+CENTRA_API int centra_create(int hip_device, size_t hbm_budget_bytes, centra_ctx **out);
+
+/* Frees the context and every workspace it owns.  NULL is allowed. */
+CENTRA_API void centra_destroy(centra_ctx *ctx);
+
+/* Text of the last error reported on `ctx` ("" if none).  Valid until the
+ * next call on ctx.  With ctx == NULL, the last error of centra_create. */
+CENTRA_API const char *centra_last_error(const centra_ctx *ctx);
+
+/* ------------------------------------------------------------------ */
+/* Graph G = (V, E) of the problem statement (Algorithm 1 input; Sec. 3.1),
+ * in CSR form, device pointers, caller owned:
+ *   row_ptr[n+1], col_idx[n_arcs]: out-neighbours of each node; rows sorted
+ *     ascending; no duplicate arcs; no self loops; n_arcs < 2^32.
+ *   rrow_ptr, rcol_idx: in-neighbours in the same form for a directed graph
+ *     (directed = 1); NULL for an undirected graph (directed = 0), whose
+ *     arcs come in both directions and whose in-rows are its out-rows. */
+typedef struct {
+    uint32_t n;
+    uint32_t directed;
+    uint64_t n_arcs;
+    const uint32_t *row_ptr;
+    const uint32_t *col_idx;
+    const uint32_t *rrow_ptr;
+    const uint32_t *rcol_idx;
+} centra_csr;
+
+/* Validates the CSR on the device and prepares the graph for sampling: the
+ * maximum in-degree and the bit budget C = 63 - bitlen(max in-degree) of
+ * the normalised shortest-path counts.  `count_bits_override`, if nonzero
+ * and smaller than C, replaces C (tests only).  The CSR arrays must stay
+ * alive until centra_graph_release.  *out receives the prepared graph.
+ * Errors: CENTRA_EINVAL (n < 2, unsorted row, duplicate, self loop, node id
+ * out of range, inconsistent reverse CSR), CENTRA_ENOMEM, CENTRA_EHIP. */
+CENTRA_API int centra_graph_prepare(centra_ctx *ctx, const centra_csr *csr, uint32_t count_bits_override,
+                         centra_graph **out, void *stream);
+
+/* Releases a prepared graph (not the caller's CSR arrays).  NULL is allowed. */
+CENTRA_API void centra_graph_release(centra_graph *g);
+
+/* Host outputs: maximum in-degree and count bit budget C of the graph. */
+CENTRA_API int centra_graph_info(const centra_graph *g, uint32_t *max_in_degree, uint32_t *count_bits);
+
+/* ------------------------------------------------------------------ */
+/* sampleHEs for set betweenness (Algorithm 1 sampling step; hyperedge space
+ * of Sec. 3.1; procedure of Sec. 5 with a single BFS from s instead of the
+ * bidirectional BFS).  Draws samples [first_sample, first_sample + count)
+ * of (seed, instance).  Sample number x: Philox4x64-10 stream with key
+ * (seed, 0) and counter (block, x, instance, 0); s = bounded(n), t' =
+ * bounded(n-1), t = t' + [t' >= s] (Lemire bounded draws); BFS from s with
+ * normalised path counts up to t's level; a uniformly random shortest s-t
+ * path by backtracking from t; the hyperedge is its internal nodes, t's
+ * neighbour first (empty if t is unreachable or adjacent to s).
+ *   he_off     device u64[count+1]: he_off[i] = offset of sample
+ *              first_sample+i in he_nodes, he_off[0] = 0.
+ *   he_nodes   device u32[he_cap]: node ids, sample after sample.
+ *   he_needed  host u64 (may be NULL): receives he_off[count].
+ *   st_out     optional device u32[2*count]: (s, t) of each sample.
+ *   dist_out   optional device u32[count]: d(s,t), 0xFFFFFFFF if
+ *              unreachable.
+ * Errors: CENTRA_ENOSPC if he_cap < he_off[count] (then he_off is written
+ * and *he_needed set; call again with a larger buffer), CENTRA_EINVAL,
+ * CENTRA_ENOMEM, CENTRA_EHIP. */
+CENTRA_API int centra_sample_paths(centra_ctx *ctx, const centra_graph *g, uint64_t seed, uint32_t instance,
+                        uint64_t first_sample, uint32_t count, uint64_t *he_off, uint32_t *he_nodes,
+                        uint64_t he_cap, uint64_t *he_needed, uint32_t *st_out, uint32_t *dist_out,
+                        void *stream);
+
+/* greedyCover(k, H) (Sec. 3.1 greedy algorithm; Algorithm 1 greedy step):
+ * k rounds; each adds the node covering the most not-yet-covered
+ * hyperedges, lowest node id on ties, and stops early once that number is
+ * 0.  The sample H is given as m hyperedges:
+ *   he_off   device u64[m+1], he_off[0] = 0, non-decreasing;
+ *   he_nodes device u32[he_off[m]], node ids < n, distinct within one
+ *            hyperedge.
+ * Outputs (device): picks u32[k], cov_cum u64[k] (hyperedges covered after
+ * r+1 picks), n_picked u32[1] (entries written, <= k).
+ * Errors: CENTRA_EINVAL (k == 0, n == 0, node id >= n), CENTRA_ENOMEM,
+ * CENTRA_EHIP. */
+CENTRA_API int centra_greedy_cover(centra_ctx *ctx, uint32_t n, uint64_t m, const uint64_t *he_off,
+                        const uint32_t *he_nodes, uint32_t k, uint32_t *picks, uint64_t *cov_cum,
+                        uint32_t *n_picked, void *stream);
+
+/* AMCERA ingredients (Sec. 4.1 definitions of the AMCERA and the
+ * approximate wimpy variance; Algorithm 1 AMCERA steps).  The sample is
+ * given as for centra_greedy_cover; hyperedge i is sample number i.
+ * sigma_ji = +1 iff bit (j mod 64) of word ((j mod 256) div 64) of the
+ * Philox4x64-10 block with key (seed, 0) and counter (j div 256, i,
+ * instance, 1) is set, else -1.  R[u][j] = sum over i with u in h_i of
+ * sigma_ji (= m * r_j^u).
+ * Outputs (device):
+ *   topk_sum     i64[t]: sum of the min(k, #positive) largest positive
+ *                R[.][j] (= m * r_j of Algorithm 1);
+ *   deg_topk_sum u64[1]: sum of the k largest deg_H(u);
+ *   b_max        u32[1]: max |h_i|;
+ *   R_out        optional i32[n*t], R[u][j] at u*t + j.
+ * AMCERA = sum_j topk_sum[j] / (t m); wimpy = b_max * deg_topk_sum / m.
+ * Errors: CENTRA_EINVAL (t == 0 or t > 1024, k == 0, n == 0, m == 0,
+ * m >= 2^31, node id >= n), CENTRA_ENOMEM, CENTRA_EHIP. */
+CENTRA_API int centra_mcera(centra_ctx *ctx, uint32_t n, uint64_t m, const uint64_t *he_off,
+                 const uint32_t *he_nodes, uint64_t seed, uint32_t instance, uint32_t t, uint32_t k,
+                 int64_t *topk_sum, uint64_t *deg_topk_sum, uint32_t *b_max, int32_t *R_out,
+                 void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Theorem bound_dev (eq. epsrade) with xi and the stopping condition of
+ * Algorithm 1, in FP64 on the host:  a = 1 - 1/e, L = ln(5/delta_i),
+ * C = cov/m, AMCERA = sum_topk/(t m), wimpy = b_max*deg_topk/m,
+ * xi = sqrt((L/m)^2 + 2CL/(a m)) + L/m, nu = C/a + xi,
+ * R~ = AMCERA + sqrt(4 wimpy L/(t m)), R = R~ + sqrt((L/m)^2 + 2L R~/m) + L/m,
+ * eta = 2R + sqrt(2L(nu + 4R)/m) + L/(3m);
+ * certified = a((a - eps) xi + eta) <= eps C.  All pointers host. */
+typedef struct {
+    double c_hat, amcera, wimpy, xi, nu, rtilde, r, eta;
+    int certified;
+} centra_bound_out;
+
+/* Errors: CENTRA_EINVAL (m == 0, t == 0, delta_i outside (0,1), out NULL). */
+CENTRA_API int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk,
+                 uint32_t b_max, double eps, double delta_i, centra_bound_out *out);
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1 (CentRA).  Iteration i = 1, 2, ...: delta_i = delta / 2^i;
+ * m_1 = m_init, m_{i+1} = min(ceil(m_i * growth_num / growth_den), m_max);
+ * the sample is extended to m_i hyperedges (samples 0 .. m_i-1 of (seed,
+ * instance)), then greedyCover, the AMCERA and the bound; returns as soon
+ * as the stopping condition holds.  Inputs: k >= 1, 1 <= t <= 1024,
+ * eps in (0, 1-1/e), delta in (0,1), 1 <= m_init <= m_max < 2^31,
+ * growth_num > growth_den >= 1. */
+typedef struct {
+    uint32_t k, t;
+    double eps, delta;
+    uint64_t seed;
+    uint32_t instance;
+    uint64_t m_init, m_max;
+    uint32_t growth_num, growth_den;
+} centra_params;
+
+typedef struct {
+    uint32_t n_picked, iterations;
+    int certified;
+    uint64_t coverage, m_final;
+    double c_hat, amcera, wimpy, xi, nu, rtilde, r, eta;
+    double ms_sample, ms_cover, ms_mcera, ms_total;   /* device time per phase, summed */
+} centra_result;
+
+/* Per-iteration record (optional log). */
+typedef struct {
+    uint32_t i;
+    uint64_t m;
+    uint64_t coverage;
+    int64_t sum_topk;
+    uint64_t deg_topk;
+    uint32_t b_max;
+    double delta_i, amcera, wimpy, xi, nu, rtilde, r, eta;
+    int certified;
+    double ms_sample, ms_cover, ms_mcera;
+} centra_iteration;
+
+/* picks: host u32[k] (receives result->n_picked entries); result: host.
+ * log: optional host array of log_cap records (iteration i goes to
+ * log[i-1] while i <= log_cap).
+ * Returns CENTRA_OK if certified, CENTRA_NOT_CERTIFIED if m_max was reached
+ * first (result and picks still filled), or an error. */
+CENTRA_API int centra_progressive(centra_ctx *ctx, const centra_graph *g, const centra_params *params,
+                       uint32_t *picks, centra_result *result, centra_iteration *log,
+                       uint32_t log_cap, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

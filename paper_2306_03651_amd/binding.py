@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libcentra.so (include/centra.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of the library.  Device buffers are torch tensors on a HIP device
+(PyTorch provides device memory and streams, nothing else).  If the library
+has not been built this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcentra.so")
+
+CENTRA_OK = 0
+CENTRA_NOT_CERTIFIED = 1
+CENTRA_EINVAL = -1
+CENTRA_ENOMEM = -2
+CENTRA_EHIP = -3
+CENTRA_ENOSPC = -4
+CENTRA_ENOTSUP = -5
+
+_c = ctypes
+_vp = _c.c_void_p
+
+
+class CentraError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"centra error {code}: {msg}")
+        self.code = code
+
+
+class Csr(_c.Structure):
+    _fields_ = [("n", _c.c_uint32), ("directed", _c.c_uint32), ("n_arcs", _c.c_uint64),
+                ("row_ptr", _vp), ("col_idx", _vp), ("rrow_ptr", _vp), ("rcol_idx", _vp)]
+
+
+class BoundOut(_c.Structure):
+    _fields_ = [("c_hat", _c.c_double), ("amcera", _c.c_double), ("wimpy", _c.c_double),
+                ("xi", _c.c_double), ("nu", _c.c_double), ("rtilde", _c.c_double),
+                ("r", _c.c_double), ("eta", _c.c_double), ("certified", _c.c_int)]
+
+
+class Params(_c.Structure):
+    _fields_ = [("k", _c.c_uint32), ("t", _c.c_uint32), ("eps", _c.c_double), ("delta", _c.c_double),
+                ("seed", _c.c_uint64), ("instance", _c.c_uint32), ("m_init", _c.c_uint64),
+                ("m_max", _c.c_uint64), ("growth_num", _c.c_uint32), ("growth_den", _c.c_uint32)]
+
+
+class Result(_c.Structure):
+    _fields_ = [("n_picked", _c.c_uint32), ("iterations", _c.c_uint32), ("certified", _c.c_int),
+                ("coverage", _c.c_uint64), ("m_final", _c.c_uint64),
+                ("c_hat", _c.c_double), ("amcera", _c.c_double), ("wimpy", _c.c_double),
+                ("xi", _c.c_double), ("nu", _c.c_double), ("rtilde", _c.c_double), ("r", _c.c_double),
+                ("eta", _c.c_double), ("ms_sample", _c.c_double), ("ms_cover", _c.c_double),
+                ("ms_mcera", _c.c_double), ("ms_total", _c.c_double)]
+
+
+class Iteration(_c.Structure):
+    _fields_ = [("i", _c.c_uint32), ("m", _c.c_uint64), ("coverage", _c.c_uint64), ("sum_topk", _c.c_int64),
+                ("deg_topk", _c.c_uint64), ("b_max", _c.c_uint32), ("delta_i", _c.c_double),
+                ("amcera", _c.c_double), ("wimpy", _c.c_double), ("xi", _c.c_double), ("nu", _c.c_double),
+                ("rtilde", _c.c_double), ("r", _c.c_double), ("eta", _c.c_double), ("certified", _c.c_int),
+                ("ms_sample", _c.c_double), ("ms_cover", _c.c_double), ("ms_mcera", _c.c_double)]
+
+
+# name -> (restype, argtypes); the names and order are those of centra.h
+SIGNATURES = {
+    "centra_abi_version": (_c.c_uint32, []),
+    "centra_create": (_c.c_int, [_c.c_int, _c.c_size_t, _c.POINTER(_vp)]),
+    "centra_destroy": (None, [_vp]),
+    "centra_last_error": (_c.c_char_p, [_vp]),
+    "centra_graph_prepare": (_c.c_int, [_vp, _c.POINTER(Csr), _c.c_uint32, _c.POINTER(_vp), _vp]),
+    "centra_graph_release": (None, [_vp]),
+    "centra_graph_info": (_c.c_int, [_vp, _c.POINTER(_c.c_uint32), _c.POINTER(_c.c_uint32)]),
+    "centra_sample_paths": (_c.c_int, [_vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _vp, _vp,
+                                       _c.c_uint64, _c.POINTER(_c.c_uint64), _vp, _vp, _vp]),
+    "centra_greedy_cover": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint32, _vp, _vp, _vp, _vp]),
+    "centra_mcera": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint32,
+                                _c.c_uint32, _vp, _vp, _vp, _vp, _vp]),
+    "centra_bound": (_c.c_int, [_c.c_uint64, _c.c_uint64, _c.c_int64, _c.c_uint32, _c.c_uint64, _c.c_uint32,
+                                _c.c_double, _c.c_double, _c.POINTER(BoundOut)]),
+    "centra_progressive": (_c.c_int, [_vp, _vp, _c.POINTER(Params), _vp, _c.POINTER(Result),
+                                      _c.POINTER(Iteration), _c.c_uint32, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libcentra.so; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(x):
+    """Device (or host numpy) pointer of a buffer, or None."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    if x.device.type != "cuda":
+        raise ValueError("expected a tensor on a HIP device")
+    if not x.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(rc: int, ctx=None):
+    if rc < 0:
+        raise CentraError(rc, centra_last_error(ctx))
+    return rc
+
+
+def _dtype_check(t, dtype, name):
+    if t is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+# ---------------------------------------------------------------------------
+def centra_abi_version() -> int:
+    return lib().centra_abi_version()
+
+
+def centra_create(device: int = 0, hbm_budget_bytes: int = 0):
+    out = _vp()
+    _check(lib().centra_create(device, hbm_budget_bytes, ctypes.byref(out)))
+    return out
+
+
+def centra_destroy(ctx) -> None:
+    lib().centra_destroy(ctx)
+
+
+def centra_last_error(ctx=None) -> str:
+    s = lib().centra_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def centra_graph_prepare(ctx, row_ptr, col_idx, rrow_ptr=None, rcol_idx=None, count_bits_override: int = 0,
+                         stream=None):
+    """Prepares a CSR graph held in device tensors (uint32 / torch.int32 views)."""
+    import torch
+    for name, t in (("row_ptr", row_ptr), ("col_idx", col_idx), ("rrow_ptr", rrow_ptr), ("rcol_idx", rcol_idx)):
+        _dtype_check(t, torch.int32, name)
+    directed = rrow_ptr is not None
+    csr = Csr(row_ptr.numel() - 1, 1 if directed else 0, col_idx.numel(), _ptr(row_ptr), _ptr(col_idx),
+              _ptr(rrow_ptr), _ptr(rcol_idx))
+    out = _vp()
+    _check(lib().centra_graph_prepare(ctx, ctypes.byref(csr), count_bits_override, ctypes.byref(out),
+                                      _stream(stream)), ctx)
+    return out
+
+
+def centra_graph_release(g) -> None:
+    lib().centra_graph_release(g)
+
+
+def centra_graph_info(g):
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().centra_graph_info(g, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def centra_sample_paths(ctx, g, seed: int, instance: int, first_sample: int, count: int, he_off, he_nodes,
+                        he_cap: int | None = None, st_out=None, dist_out=None, stream=None):
+    """Returns (rc, he_needed).  rc may be CENTRA_ENOSPC (no exception)."""
+    import torch
+    _dtype_check(he_off, torch.int64, "he_off")
+    _dtype_check(he_nodes, torch.int32, "he_nodes")
+    if he_cap is None:
+        he_cap = he_nodes.numel() if he_nodes is not None else 0
+    need = ctypes.c_uint64()
+    rc = lib().centra_sample_paths(ctx, g, seed, instance, first_sample, count, _ptr(he_off), _ptr(he_nodes),
+                                   he_cap, ctypes.byref(need), _ptr(st_out), _ptr(dist_out), _stream(stream))
+    if rc != CENTRA_ENOSPC:
+        _check(rc, ctx)
+    return rc, need.value
+
+
+def centra_greedy_cover(ctx, n: int, he_off, he_nodes, k: int, picks, cov_cum, n_picked, stream=None) -> int:
+    m = he_off.numel() - 1
+    return _check(lib().centra_greedy_cover(ctx, n, m, _ptr(he_off), _ptr(he_nodes), k, _ptr(picks),
+                                            _ptr(cov_cum), _ptr(n_picked), _stream(stream)), ctx)
+
+
+def centra_mcera(ctx, n: int, he_off, he_nodes, seed: int, instance: int, t: int, k: int, topk_sum, deg_topk,
+                 b_max, R_out=None, stream=None) -> int:
+    m = he_off.numel() - 1
+    return _check(lib().centra_mcera(ctx, n, m, _ptr(he_off), _ptr(he_nodes), seed, instance, t, k,
+                                     _ptr(topk_sum), _ptr(deg_topk), _ptr(b_max), _ptr(R_out), _stream(stream)),
+                  ctx)
+
+
+def centra_bound(m: int, cov: int, sum_topk: int, t: int, deg_topk: int, b_max: int, eps: float,
+                 delta_i: float) -> BoundOut:
+    out = BoundOut()
+    _check(lib().centra_bound(m, cov, sum_topk, t, deg_topk, b_max, eps, delta_i, ctypes.byref(out)))
+    return out
+
+
+def centra_progressive(ctx, g, k: int, t: int, eps: float, delta: float, seed: int, instance: int, m_init: int,
+                       m_max: int, growth_num: int = 2, growth_den: int = 1, log_cap: int = 64, stream=None):
+    """Returns (rc, picks np.uint32[n_picked], Result, [Iteration])."""
+    p = Params(k, t, eps, delta, seed, instance, m_init, m_max, growth_num, growth_den)
+    picks = np.zeros(max(1, k), dtype=np.uint32)
+    res = Result()
+    log = (Iteration * max(1, log_cap))()
+    rc = _check(lib().centra_progressive(ctx, g, ctypes.byref(p), picks.ctypes.data, ctypes.byref(res), log,
+                                         log_cap, _stream(stream)), ctx)
+    return rc, picks[: res.n_picked].copy(), res, list(log)[: min(res.iterations, log_cap)]
+
+
+# ---------------------------------------------------------------------------
+class DeviceGraph:
+    """A CSR graph uploaded to device tensors and prepared by the library."""
+
+    def __init__(self, ctx, graph, device="cuda", count_bits_override: int = 0):
+        import torch
+        self.n = graph.n
+        self.directed = graph.directed
+
+        def up(a):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to(device)
+
+        self.row_ptr = up(graph.row_ptr)
+        self.col_idx = up(graph.col_idx)
+        self.rrow_ptr = up(graph.rrow_ptr) if graph.directed else None
+        self.rcol_idx = up(graph.rcol_idx) if graph.directed else None
+        self.handle = centra_graph_prepare(ctx, self.row_ptr, self.col_idx, self.rrow_ptr, self.rcol_idx,
+                                           count_bits_override)
+
+    def info(self):
+        return centra_graph_info(self.handle)
+
+    def release(self):
+        if self.handle:
+            centra_graph_release(self.handle)
+            self.handle = None
+
+
+def sample_paths(ctx, dg: DeviceGraph, seed: int, instance: int, first: int, count: int, with_st: bool = False,
+                 device="cuda"):
+    """Samples [first, first+count) into fresh device tensors.
+    Returns (he_off int64[count+1], he_nodes int32[I]) (+ (st, dist) if with_st)."""
+    import torch
+    he_off = torch.empty(count + 1, dtype=torch.int64, device=device)
+    cap = max(16, count * 8)
+    st = torch.empty(2 * max(1, count), dtype=torch.int32, device=device) if with_st else None
+    dist = torch.empty(max(1, count), dtype=torch.int32, device=device) if with_st else None
+    he_nodes = torch.empty(cap, dtype=torch.int32, device=device)
+    rc, need = centra_sample_paths(ctx, dg.handle, seed, instance, first, count, he_off, he_nodes, cap, st, dist)
+    if rc == CENTRA_ENOSPC:
+        he_nodes = torch.empty(max(1, need), dtype=torch.int32, device=device)
+        rc, need = centra_sample_paths(ctx, dg.handle, seed, instance, first, count, he_off, he_nodes, need, st, dist)
+    out = (he_off, he_nodes[:need])
+    if with_st:
+        out = out + (st, dist)
+    return out

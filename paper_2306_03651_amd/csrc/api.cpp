@@ -1,0 +1,370 @@
+// C ABI entry points (include/centra.h): context, graph preparation, the
+// three device steps of an iteration, the host FP64 bound and the
+// progressive driver of Algorithm 1.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+using namespace centra;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// Writes the Theorem bound_dev quantities (host FP64).
+void bound_eval(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk, uint32_t b_max,
+                double eps, double delta_i, centra_bound_out* o) {
+  const double a = 1.0 - exp(-1.0);
+  const double md = static_cast<double>(m);
+  const double L = log(5.0 / delta_i);
+  const double C = static_cast<double>(cov) / md;
+  const double amcera = static_cast<double>(sum_topk) / (static_cast<double>(t) * md);
+  const double wimpy = static_cast<double>(b_max) * static_cast<double>(deg_topk) / md;
+  const double Lm = L / md;
+  const double xi = sqrt(Lm * Lm + 2.0 * C * L / (a * md)) + Lm;
+  const double nu = C / a + xi;
+  const double rtilde = amcera + sqrt(4.0 * wimpy * L / (static_cast<double>(t) * md));
+  const double r = rtilde + sqrt(Lm * Lm + 2.0 * L * rtilde / md) + Lm;
+  const double eta = 2.0 * r + sqrt(2.0 * L * (nu + 4.0 * r) / md) + L / (3.0 * md);
+  o->c_hat = C;
+  o->amcera = amcera;
+  o->wimpy = wimpy;
+  o->xi = xi;
+  o->nu = nu;
+  o->rtilde = rtilde;
+  o->r = r;
+  o->eta = eta;
+  o->certified = a * ((a - eps) * xi + eta) <= eps * C ? 1 : 0;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 0.f;
+  return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t centra_abi_version(void) { return CENTRA_ABI_VERSION; }
+
+int centra_create(int hip_device, size_t hbm_budget_bytes, centra_ctx** out) {
+  g_create_err.clear();
+  if (!out) {
+    g_create_err = "centra_create: out is NULL";
+    return CENTRA_EINVAL;
+  }
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    g_create_err = "centra_create: no HIP device available";
+    return CENTRA_EHIP;
+  }
+  if (hip_device < 0 || hip_device >= count) {
+    g_create_err = "centra_create: device index out of range";
+    return CENTRA_EINVAL;
+  }
+  DeviceGuard guard(hip_device);
+  centra_ctx* ctx = new (std::nothrow) centra_ctx();
+  if (!ctx) return CENTRA_ENOMEM;
+  ctx->device = hip_device;
+  ctx->budget = hbm_budget_bytes;
+  if (hipMalloc(reinterpret_cast<void**>(&ctx->d_flags), 256) != hipSuccess ||
+      hipMemset(ctx->d_flags, 0, 256) != hipSuccess) {
+    (void)hipGetLastError();
+    g_create_err = "centra_create: device allocation failed";
+    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    delete ctx;
+    return CENTRA_ENOMEM;
+  }
+  for (auto& ev : ctx->ev) {
+    if (hipEventCreate(&ev) != hipSuccess) {
+      g_create_err = "centra_create: event creation failed";
+      centra_destroy(ctx);
+      return CENTRA_EHIP;
+    }
+  }
+  *out = ctx;
+  return CENTRA_OK;
+}
+
+void centra_destroy(centra_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard guard(ctx->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&ctx->slot_lvl, &ctx->slot_sig, &ctx->slot_q, &ctx->stage_nodes, &ctx->stage_pos,
+                    &ctx->stage_len, &ctx->work_ctr, &ctx->scan_tmp, &ctx->deg, &ctx->inc_off,
+                    &ctx->inc_cursor, &ctx->inc, &ctx->inc_node, &ctx->gain, &ctx->covered, &ctx->best,
+                    &ctx->newcov, &ctx->words, &ctx->P, &ctx->Rtm, &ctx->topk_tmp, &ctx->misc,
+                    &ctx->store_off, &ctx->store_nodes};
+  for (DevBuf* b : bufs) release(ctx, *b);
+  if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+  for (auto& ev : ctx->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  delete ctx;
+}
+
+const char* centra_last_error(const centra_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int centra_graph_prepare(centra_ctx* ctx, const centra_csr* csr, uint32_t count_bits_override, centra_graph** out,
+                         void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (!csr || !out) return fail(ctx, CENTRA_EINVAL, "graph_prepare: NULL argument");
+  *out = nullptr;
+  if (csr->n < 2) return fail(ctx, CENTRA_EINVAL, "graph_prepare: n < 2");
+  if (csr->n_arcs >= (1ull << 32)) return fail(ctx, CENTRA_ENOTSUP, "graph_prepare: n_arcs >= 2^32");
+  if (!csr->row_ptr || (csr->n_arcs && !csr->col_idx))
+    return fail(ctx, CENTRA_EINVAL, "graph_prepare: NULL CSR array");
+  if (csr->directed && (!csr->rrow_ptr || (csr->n_arcs && !csr->rcol_idx)))
+    return fail(ctx, CENTRA_EINVAL, "graph_prepare: directed graph without reverse CSR");
+  DeviceGuard guard(ctx->device);
+  centra_graph* g = new (std::nothrow) centra_graph();
+  if (!g) return fail(ctx, CENTRA_ENOMEM, "graph_prepare: host allocation");
+  g->ctx = ctx;
+  g->n = csr->n;
+  g->directed = csr->directed ? 1u : 0u;
+  g->n_arcs = csr->n_arcs;
+  g->row_ptr = csr->row_ptr;
+  g->col_idx = csr->col_idx;
+  g->in_ptr = csr->directed ? csr->rrow_ptr : csr->row_ptr;
+  g->in_idx = csr->directed ? csr->rcol_idx : csr->col_idx;
+  const int rc = validate_graph(ctx, g, as_stream(stream));
+  if (rc) {
+    delete g;
+    return rc;
+  }
+  if (count_bits_override && count_bits_override < g->count_bits) g->count_bits = count_bits_override;
+  *out = g;
+  return CENTRA_OK;
+}
+
+void centra_graph_release(centra_graph* g) { delete g; }
+
+int centra_graph_info(const centra_graph* g, uint32_t* max_in_degree, uint32_t* count_bits) {
+  if (!g) return CENTRA_EINVAL;
+  if (max_in_degree) *max_in_degree = g->max_in_degree;
+  if (count_bits) *count_bits = g->count_bits;
+  return CENTRA_OK;
+}
+
+int centra_sample_paths(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance,
+                        uint64_t first_sample, uint32_t count, uint64_t* he_off, uint32_t* he_nodes, uint64_t he_cap,
+                        uint64_t* he_needed, uint32_t* st_out, uint32_t* dist_out, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (!g || !he_off) return fail(ctx, CENTRA_EINVAL, "sample_paths: NULL argument");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = as_stream(stream);
+  uint64_t total = 0;
+  int rc = sample_to_stage(ctx, g, seed, instance, first_sample, count, st_out, dist_out, &total, s);
+  if (rc) return rc;
+  if (he_needed) *he_needed = total;
+  if (count == 0) {
+    fill_u64(he_off, 0, 1, s);
+    CENTRA_HIP(ctx, hipStreamSynchronize(s));
+    return CENTRA_OK;
+  }
+  const bool fits = he_nodes && he_cap >= total;
+  rc = stage_to_output(ctx, count, 0, he_off, fits ? he_nodes : nullptr, s);
+  if (rc) return rc;
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  if (!fits) return fail(ctx, CENTRA_ENOSPC, "sample_paths: he_cap smaller than the sample");
+  return CENTRA_OK;
+}
+
+static int check_sample_args(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
+                             const uint32_t* he_nodes, const char* who) {
+  if (n == 0) return fail(ctx, CENTRA_EINVAL, std::string(who) + ": n == 0");
+  if (!he_off) return fail(ctx, CENTRA_EINVAL, std::string(who) + ": he_off is NULL");
+  if (m && !he_nodes) return fail(ctx, CENTRA_EINVAL, std::string(who) + ": he_nodes is NULL");
+  if (m >= (1ull << 31)) return fail(ctx, CENTRA_ENOTSUP, std::string(who) + ": m >= 2^31");
+  return CENTRA_OK;
+}
+
+int centra_greedy_cover(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes,
+                        uint32_t k, uint32_t* picks, uint64_t* cov_cum, uint32_t* n_picked, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  int rc = check_sample_args(ctx, n, m, he_off, he_nodes, "greedy_cover");
+  if (rc) return rc;
+  if (k == 0) return fail(ctx, CENTRA_EINVAL, "greedy_cover: k == 0");
+  if (!picks || !cov_cum || !n_picked) return fail(ctx, CENTRA_EINVAL, "greedy_cover: NULL output");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = as_stream(stream);
+  if ((rc = build_incidence(ctx, n, m, he_off, he_nodes, s))) return rc;
+  if ((rc = check_flags(ctx, s, "greedy_cover"))) return rc;
+  if ((rc = greedy_on_incidence(ctx, n, m, he_off, he_nodes, k, picks, cov_cum, n_picked, s))) return rc;
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  return CENTRA_OK;
+}
+
+int centra_mcera(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes,
+                 uint64_t seed, uint32_t instance, uint32_t t, uint32_t k, int64_t* topk_sum, uint64_t* deg_topk_sum,
+                 uint32_t* b_max, int32_t* R_out, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  int rc = check_sample_args(ctx, n, m, he_off, he_nodes, "mcera");
+  if (rc) return rc;
+  if (m == 0) return fail(ctx, CENTRA_EINVAL, "mcera: m == 0");
+  if (t == 0 || t > 1024) return fail(ctx, CENTRA_EINVAL, "mcera: t must be in [1, 1024]");
+  if (k == 0) return fail(ctx, CENTRA_EINVAL, "mcera: k == 0");
+  if (!topk_sum || !deg_topk_sum || !b_max) return fail(ctx, CENTRA_EINVAL, "mcera: NULL output");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = as_stream(stream);
+  if ((rc = build_incidence(ctx, n, m, he_off, he_nodes, s))) return rc;
+  if ((rc = check_flags(ctx, s, "mcera"))) return rc;
+  if ((rc = rade_words(ctx, seed, instance, 0, m, t, s))) return rc;
+  if ((rc = mcera_on_incidence(ctx, n, m, he_off, t, k, topk_sum, deg_topk_sum, b_max, R_out, s))) return rc;
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  return CENTRA_OK;
+}
+
+int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk, uint32_t b_max,
+                 double eps, double delta_i, centra_bound_out* out) {
+  if (!out || m == 0 || t == 0 || !(delta_i > 0.0 && delta_i < 1.0)) return CENTRA_EINVAL;
+  bound_eval(m, cov, sum_topk, t, deg_topk, b_max, eps, delta_i, out);
+  return CENTRA_OK;
+}
+
+int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_params* p, uint32_t* picks,
+                       centra_result* res, centra_iteration* log, uint32_t log_cap, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (!g || !p || !picks || !res) return fail(ctx, CENTRA_EINVAL, "progressive: NULL argument");
+  const double a = 1.0 - exp(-1.0);
+  if (p->k == 0 || p->t == 0 || p->t > 1024) return fail(ctx, CENTRA_EINVAL, "progressive: bad k or t");
+  if (!(p->eps > 0.0 && p->eps < a)) return fail(ctx, CENTRA_EINVAL, "progressive: eps outside (0, 1-1/e)");
+  if (!(p->delta > 0.0 && p->delta < 1.0)) return fail(ctx, CENTRA_EINVAL, "progressive: delta outside (0, 1)");
+  if (p->m_init == 0 || p->m_max < p->m_init || p->m_max >= (1ull << 31))
+    return fail(ctx, CENTRA_EINVAL, "progressive: bad m_init / m_max");
+  if (p->growth_den == 0 || p->growth_num <= p->growth_den)
+    return fail(ctx, CENTRA_EINVAL, "progressive: growth must exceed 1");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = as_stream(stream);
+  memset(res, 0, sizeof(*res));
+  const uint32_t k = p->k, t = p->t, n = g->n;
+  int rc;
+  if ((rc = ensure(ctx, ctx->store_off, (p->m_max + 1) * 8, false, s))) return rc;
+  // device result block: picks u32[k] | cov_cum u64[k] | n_picked u32 | b_max u32 | deg_topk u64 | topk i64[t]
+  const size_t o_cov = (size_t(k) * 4 + 7) & ~size_t(7);
+  const size_t o_np = o_cov + size_t(k) * 8;
+  const size_t o_bm = o_np + 4;
+  const size_t o_dk = o_np + 8;
+  const size_t o_tk = o_dk + 8;
+  const size_t misc_bytes = o_tk + size_t(t) * 8;
+  if ((rc = ensure(ctx, ctx->misc, misc_bytes, false, s))) return rc;
+  char* misc = static_cast<char*>(ctx->misc.ptr);
+  uint64_t* store_off = static_cast<uint64_t*>(ctx->store_off.ptr);
+  fill_u64(store_off, 0, 1, s);
+  std::string host_block(misc_bytes, '\0');
+  hipEvent_t* ev = ctx->ev;
+  uint64_t m_prev = 0, m_i = p->m_init, total_nodes = 0;
+  for (uint32_t i = 1;; ++i) {
+    const double delta_i = ldexp(p->delta, -static_cast<int>(i));
+    CENTRA_HIP(ctx, hipEventRecord(ev[0], s));
+    uint64_t added = 0;
+    const uint32_t cnt = static_cast<uint32_t>(m_i - m_prev);
+    if ((rc = sample_to_stage(ctx, g, p->seed, p->instance, m_prev, cnt, nullptr, nullptr, &added, s))) return rc;
+    if ((rc = ensure(ctx, ctx->store_nodes, (total_nodes + added + 1) * 4, true, s))) return rc;
+    uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
+    if ((rc = stage_to_output(ctx, cnt, total_nodes, store_off + m_prev, store_nodes + total_nodes, s))) return rc;
+    total_nodes += added;
+    CENTRA_HIP(ctx, hipEventRecord(ev[1], s));
+    if ((rc = build_incidence(ctx, n, m_i, store_off, store_nodes, s))) return rc;
+    if ((rc = greedy_on_incidence(ctx, n, m_i, store_off, store_nodes, k, reinterpret_cast<uint32_t*>(misc),
+                                  reinterpret_cast<uint64_t*>(misc + o_cov), reinterpret_cast<uint32_t*>(misc + o_np),
+                                  s)))
+      return rc;
+    CENTRA_HIP(ctx, hipEventRecord(ev[2], s));
+    if ((rc = rade_words(ctx, p->seed, p->instance, m_prev, m_i, t, s))) return rc;
+    if ((rc = mcera_on_incidence(ctx, n, m_i, store_off, t, k, reinterpret_cast<int64_t*>(misc + o_tk),
+                                 reinterpret_cast<uint64_t*>(misc + o_dk), reinterpret_cast<uint32_t*>(misc + o_bm),
+                                 nullptr, s)))
+      return rc;
+    CENTRA_HIP(ctx, hipEventRecord(ev[3], s));
+    CENTRA_HIP(ctx, hipMemcpyAsync(&host_block[0], misc, misc_bytes, hipMemcpyDeviceToHost, s));
+    CENTRA_HIP(ctx, hipStreamSynchronize(s));
+    if ((rc = check_flags(ctx, s, "progressive"))) return rc;
+    const char* hb = host_block.data();
+    uint32_t np, bm;
+    uint64_t dk;
+    memcpy(&np, hb + o_np, 4);
+    memcpy(&bm, hb + o_bm, 4);
+    memcpy(&dk, hb + o_dk, 8);
+    uint64_t cov = 0;
+    if (np) memcpy(&cov, hb + o_cov + size_t(np - 1) * 8, 8);
+    int64_t sum = 0;
+    for (uint32_t j = 0; j < t; ++j) {
+      int64_t x;
+      memcpy(&x, hb + o_tk + size_t(j) * 8, 8);
+      sum += x;
+    }
+    centra_bound_out o;
+    bound_eval(m_i, cov, sum, t, dk, bm, p->eps, delta_i, &o);
+    const double ms_s = elapsed(ev[0], ev[1]), ms_c = elapsed(ev[1], ev[2]), ms_m = elapsed(ev[2], ev[3]);
+    memcpy(picks, hb, size_t(np) * 4);
+    res->n_picked = np;
+    res->iterations = i;
+    res->certified = o.certified;
+    res->coverage = cov;
+    res->m_final = m_i;
+    res->c_hat = o.c_hat;
+    res->amcera = o.amcera;
+    res->wimpy = o.wimpy;
+    res->xi = o.xi;
+    res->nu = o.nu;
+    res->rtilde = o.rtilde;
+    res->r = o.r;
+    res->eta = o.eta;
+    res->ms_sample += ms_s;
+    res->ms_cover += ms_c;
+    res->ms_mcera += ms_m;
+    res->ms_total += ms_s + ms_c + ms_m;
+    if (log && i <= log_cap) {
+      centra_iteration& it = log[i - 1];
+      it.i = i;
+      it.m = m_i;
+      it.coverage = cov;
+      it.sum_topk = sum;
+      it.deg_topk = dk;
+      it.b_max = bm;
+      it.delta_i = delta_i;
+      it.amcera = o.amcera;
+      it.wimpy = o.wimpy;
+      it.xi = o.xi;
+      it.nu = o.nu;
+      it.rtilde = o.rtilde;
+      it.r = o.r;
+      it.eta = o.eta;
+      it.certified = o.certified;
+      it.ms_sample = ms_s;
+      it.ms_cover = ms_c;
+      it.ms_mcera = ms_m;
+    }
+    if (o.certified) return CENTRA_OK;
+    if (m_i >= p->m_max) return CENTRA_NOT_CERTIFIED;
+    m_prev = m_i;
+    const unsigned __int128 nx =
+        (static_cast<unsigned __int128>(m_i) * p->growth_num + p->growth_den - 1) / p->growth_den;
+    m_i = nx > p->m_max ? p->m_max : static_cast<uint64_t>(nx);
+  }
+}
+
+}  // extern "C"

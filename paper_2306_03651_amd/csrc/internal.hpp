@@ -1,0 +1,114 @@
+// Host-side internals of the CentRA library: context, prepared graph,
+// device workspaces and the kernel launchers shared by the entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/centra.h"
+
+namespace centra {
+
+// A device buffer owned by the context; grows on demand within the budget.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace centra
+
+struct centra_ctx {
+  int device = 0;
+  size_t budget = 0;          // 0 = unbounded
+  size_t allocated = 0;
+  std::string err;
+  uint32_t* d_flags = nullptr;   // kernel error bits (u32) + scratch counters
+  // per-BFS slot arrays (level, normalised count, visit queue), one set per
+  // concurrent BFS, sized for the largest graph seen
+  centra::DevBuf slot_lvl, slot_sig, slot_q;
+  uint32_t slots = 0;
+  uint32_t slot_n = 0;
+  // sampling staging area
+  centra::DevBuf stage_nodes, stage_pos, stage_len, work_ctr;
+  // scan scratch
+  centra::DevBuf scan_tmp;
+  // incidence (node -> samples) and greedy / AMCERA workspaces
+  centra::DevBuf deg, inc_off, inc_cursor, inc, inc_node, gain, covered, best, newcov;
+  centra::DevBuf words, P, Rtm, topk_tmp, misc;
+  // sample store of centra_progressive
+  centra::DevBuf store_off, store_nodes;
+  hipEvent_t ev[8] = {};
+};
+
+struct centra_graph {
+  centra_ctx* ctx = nullptr;
+  uint32_t n = 0;
+  uint32_t directed = 0;
+  uint64_t n_arcs = 0;
+  const uint32_t* row_ptr = nullptr;
+  const uint32_t* col_idx = nullptr;
+  const uint32_t* in_ptr = nullptr;
+  const uint32_t* in_idx = nullptr;
+  uint32_t max_in_degree = 0;
+  uint32_t count_bits = 0;
+};
+
+namespace centra {
+
+// Error helpers: set ctx->err and return a code.
+int fail(centra_ctx* ctx, int code, const std::string& msg);
+int hip_fail(centra_ctx* ctx, hipError_t e, const char* what);
+
+#define CENTRA_HIP(ctx, call)                                 \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return ::centra::hip_fail(ctx, e_, #call); \
+  } while (0)
+
+// Ensures `b` holds at least `bytes`; contents are not preserved unless
+// `keep` is set.  Respects the context budget.
+int ensure(centra_ctx* ctx, DevBuf& b, size_t bytes, bool keep = false, hipStream_t s = nullptr);
+void release(centra_ctx* ctx, DevBuf& b);
+
+// Fill kernels (used instead of hipMemsetAsync so the work stays a plain
+// kernel sequence).
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+
+// Exclusive scan of `n` u32 values into `out[0..n]` (u64, out[n] = total).
+int excl_scan_u32_to_u64(centra_ctx* ctx, const uint32_t* in, uint64_t* out, size_t n, hipStream_t s);
+
+// Graph checks (graph.hip).
+int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s);
+
+// Sampling (sample.hip): samples [first, first+count) into the staging
+// area, then lays them out at `he_off`/`he_nodes` (offsets relative,
+// plus `base` added to every offset).  *total receives the node count.
+int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance,
+                    uint64_t first, uint32_t count, uint32_t* st_out, uint32_t* dist_out,
+                    uint64_t* total, hipStream_t s);
+int stage_to_output(centra_ctx* ctx, uint32_t count, uint64_t base, uint64_t* he_off,
+                    uint32_t* he_nodes, hipStream_t s);
+
+// Incidence + greedy (cover.hip).  Builds deg/inc_off/inc/inc_node in the
+// context for a sample of m hyperedges.
+int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
+                    const uint32_t* he_nodes, hipStream_t s);
+int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
+                        const uint32_t* he_nodes, uint32_t k, uint32_t* picks, uint64_t* cov_cum,
+                        uint32_t* n_picked, hipStream_t s);
+
+// AMCERA (mcera.hip): Rademacher words for samples [s0, s1) into ctx->words
+// (Wt words per sample), then the per-trial top-k sums on the incidence.
+int rade_words(centra_ctx* ctx, uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1,
+               uint32_t t, hipStream_t s);
+int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, uint32_t t,
+                       uint32_t k, int64_t* topk_sum, uint64_t* deg_topk, uint32_t* b_max,
+                       int32_t* R_out, hipStream_t s);
+
+// Device flag word: read (after synchronising `s`) and clear.
+int check_flags(centra_ctx* ctx, hipStream_t s, const char* where);
+
+}  // namespace centra

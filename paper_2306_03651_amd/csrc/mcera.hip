@@ -1,0 +1,289 @@
+// AMCERA ingredients on gfx950: Rademacher sign words, the per-node trial
+// sums R[u][j] = sum_{s : u in h_s} sigma_js, the per-trial sums of the k
+// largest positive R[.][j], the k largest deg_H(u) and max |h|.
+//
+// Signs.  Sample s gets Wt = ceil(t/64) words; word w holds trials
+// 64w .. 64w+63 and is word (w mod 4) of Philox block (w div 4, s,
+// instance, 1), so bit (j mod 64) of word j div 64 is sigma_js.
+//
+// Trial sums.  R[u][j] = 2 P[u][j] - deg_H(u) with P[u][j] the number of
+// samples of u's incidence row whose bit j is set.  A wave walks a span of
+// the incidence (grouped by node); for each run of entries of one node
+// inside a 64-entry batch it forms, for every trial bit j, the ballot of
+// the lanes whose sign word has bit j set and adds its popcount to lane j's
+// counter.  A node's counters are flushed with one coalesced row of atomic
+// adds when the walk leaves the node (spans may split a node, hence the
+// atomics; integer sums keep the result exact and order independent).
+//
+// Top-k.  One workgroup per trial (plus one for the degrees) selects the
+// k-th largest positive value of its row by MSD radix selection: a
+// histogram over the bit length, then 12-bit digit histograms below the
+// leading bit, each with per-bin counts and sums in LDS; the answer is the
+// sum of every value above the selected one plus the remaining copies of
+// it.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace centra {
+
+__global__ void k_rade_words(uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1, uint32_t Wt,
+                             uint64_t* words) {
+  const uint32_t nblk = (Wt + 3) / 4;
+  const uint64_t total = (s1 - s0) * nblk;
+  for (uint64_t x = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; x < total;
+       x += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t s = s0 + x / nblk;
+    const uint32_t b = static_cast<uint32_t>(x % nblk);
+    const Block4 r = philox4x64_10(b, s, instance, 1, seed, 0);
+    uint64_t* dst = words + s * Wt + 4ull * b;
+    const uint32_t avail = Wt - 4 * b;
+    dst[0] = r.w0;
+    if (avail > 1) dst[1] = r.w1;
+    if (avail > 2) dst[2] = r.w2;
+    if (avail > 3) dst[3] = r.w3;
+  }
+}
+
+static unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 16384) {
+  uint64_t g = (n + block - 1) / block;
+  if (g > cap) g = cap;
+  return g ? static_cast<unsigned>(g) : 1u;
+}
+
+int rade_words(centra_ctx* ctx, uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1, uint32_t t,
+               hipStream_t s) {
+  const uint32_t Wt = (t + 63) / 64;
+  int rc = ensure(ctx, ctx->words, size_t(s1) * Wt * 8, true, s);
+  if (rc) return rc;
+  if (s1 > s0)
+    hipLaunchKernelGGL(k_rade_words, dim3(grid_for((s1 - s0) * ((Wt + 3) / 4), 256)), dim3(256), 0, s, seed,
+                       instance, s0, s1, Wt, static_cast<uint64_t*>(ctx->words.ptr));
+  CENTRA_HIP(ctx, hipGetLastError());
+  return CENTRA_OK;
+}
+
+// ---------------------------------------------------------------------------
+constexpr int kCountBlock = 256;
+constexpr uint32_t kSpan = 64 * 32;   // incidence entries per wave
+
+__global__ __launch_bounds__(kCountBlock) void k_rade_count(const uint32_t* inc, const uint32_t* inc_node,
+                                                            uint64_t I, const uint64_t* words, uint32_t Wt,
+                                                            uint32_t t, int32_t* P) {
+  const int lane = lane_id();
+  const uint32_t g = blockIdx.y;                 // word group: trials 64g .. 64g+63
+  const uint64_t wave = (blockIdx.x * uint64_t(kCountBlock) + threadIdx.x) / kWave;
+  const uint64_t e0 = wave * kSpan;
+  if (e0 >= I) return;
+  const uint64_t e1 = e0 + kSpan < I ? e0 + kSpan : I;
+  const uint32_t jt = 64 * g + lane;             // this lane's trial
+  uint32_t cur = kUnseen;
+  uint32_t acc = 0;
+  for (uint64_t base = e0; base < e1; base += kWave) {
+    const uint64_t e = base + lane;
+    const bool valid = e < e1;
+    const uint32_t u = valid ? inc_node[e] : kUnseen;
+    const uint64_t word = valid ? words[uint64_t(inc[e]) * Wt + g] : 0ull;
+    uint64_t todo = __ballot(valid);
+    while (todo) {
+      const int first = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+      const uint32_t su = __shfl(u, first, kWave);
+      const uint64_t seg = __ballot(valid && u == su);
+      if (su != cur) {
+        if (cur != kUnseen && jt < t && acc) atomicAdd(&P[uint64_t(cur) * t + jt], static_cast<int32_t>(acc));
+        cur = su;
+        acc = 0;
+      }
+      const bool in_seg = (seg >> lane) & 1ull;
+      const uint64_t wv = in_seg ? word : 0ull;
+#pragma unroll 8
+      for (int j = 0; j < kWave; ++j) {
+        const uint64_t b = __ballot((wv >> j) & 1ull);
+        if (lane == j) acc += static_cast<uint32_t>(__popcll(b));
+      }
+      todo &= ~seg;
+    }
+  }
+  if (cur != kUnseen && jt < t && acc) atomicAdd(&P[uint64_t(cur) * t + jt], static_cast<int32_t>(acc));
+}
+
+// R[j][u] = 2 P[u][j] - deg[u] (trial-major for the selection) and, if
+// requested, R_out[u][j] (node-major).  64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void k_rade_finish(const int32_t* P, const uint32_t* deg, uint32_t n, uint32_t t,
+                                                     int32_t* Rtm, int32_t* R_out) {
+  __shared__ int32_t tile[64][65];
+  const uint32_t u0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4
+  for (int r = ty; r < 64; r += 4) {
+    const uint32_t u = u0 + r, j = j0 + tx;
+    int32_t v = 0;
+    if (u < n && j < t) {
+      v = 2 * P[uint64_t(u) * t + j] - static_cast<int32_t>(deg[u]);
+      if (R_out) R_out[uint64_t(u) * t + j] = v;
+    }
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const uint32_t j = j0 + r, u = u0 + tx;
+    if (u < n && j < t) Rtm[uint64_t(j) * n + u] = tile[tx][r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+constexpr int kTopBlock = 1024;
+constexpr int kDigitBits = 12;
+constexpr int kBins = 1 << kDigitBits;
+
+struct TopShared {
+  uint32_t cnt[kBins];
+  uint64_t sum[kBins];
+  uint32_t prefix, pbits, blen, need, done;
+  int64_t acc;
+};
+
+// Row r < t: trial r of Rtm; row t: deg (values as int32).  out[r] = sum of
+// the min(k, #positive) largest positive values of the row.
+__global__ __launch_bounds__(kTopBlock) void k_topk_rows(const int32_t* Rtm, const uint32_t* deg, uint32_t n,
+                                                        uint32_t t, uint32_t k, int64_t* out) {
+  __shared__ TopShared sh;
+  const uint32_t r = blockIdx.x;
+  const int32_t* row = r < t ? Rtm + uint64_t(r) * n : reinterpret_cast<const int32_t*>(deg);
+  const int tid = threadIdx.x;
+  // pass 0: bit-length histogram (bins 1..31)
+  for (int i = tid; i < 32; i += kTopBlock) {
+    sh.cnt[i] = 0;
+    sh.sum[i] = 0;
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += kTopBlock) {
+    const int32_t x = row[i];
+    if (x > 0) {
+      const uint32_t b = bitlen32(static_cast<uint32_t>(x));
+      atomicAdd(&sh.cnt[b], 1u);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&sh.sum[b]), static_cast<unsigned long long>(x));
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t need = k;
+    int64_t acc = 0;
+    uint32_t blen = 0;
+    for (int b = 31; b >= 1; --b) {
+      if (sh.cnt[b] < need) {
+        need -= sh.cnt[b];
+        acc += static_cast<int64_t>(sh.sum[b]);
+      } else {
+        blen = b;
+        break;
+      }
+    }
+    sh.need = need;
+    sh.acc = acc;
+    sh.blen = blen;
+    sh.done = blen == 0;   // fewer than k positive values: acc is the answer
+    sh.prefix = 1;
+    sh.pbits = 1;
+  }
+  __syncthreads();
+  while (!sh.done) {
+    const uint32_t B = sh.blen, pbits = sh.pbits, prefix = sh.prefix;
+    if (pbits >= B) {
+      if (tid == 0) {
+        sh.acc += static_cast<int64_t>(sh.need) * static_cast<int64_t>(prefix);
+        sh.done = 1;
+      }
+      __syncthreads();
+      break;
+    }
+    const uint32_t nb = B - pbits < kDigitBits ? B - pbits : kDigitBits;
+    const uint32_t shift = B - pbits - nb;
+    for (int i = tid; i < (1 << nb); i += kTopBlock) {
+      sh.cnt[i] = 0;
+      sh.sum[i] = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kTopBlock) {
+      const int32_t x = row[i];
+      if (x > 0 && (static_cast<uint32_t>(x) >> (B - pbits)) == prefix) {
+        const uint32_t dg = (static_cast<uint32_t>(x) >> shift) & ((1u << nb) - 1u);
+        atomicAdd(&sh.cnt[dg], 1u);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&sh.sum[dg]), static_cast<unsigned long long>(x));
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t need = sh.need;
+      int64_t acc = sh.acc;
+      for (int d = (1 << nb) - 1; d >= 0; --d) {
+        if (sh.cnt[d] < need) {
+          need -= sh.cnt[d];
+          acc += static_cast<int64_t>(sh.sum[d]);
+        } else {
+          sh.prefix = (prefix << nb) | static_cast<uint32_t>(d);
+          break;
+        }
+      }
+      sh.pbits = pbits + nb;
+      sh.need = need;
+      sh.acc = acc;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) out[r] = sh.acc;
+}
+
+__global__ void k_bmax(const uint64_t* he_off, uint64_t m, uint32_t* b_max) {
+  uint32_t mx = 0;
+  for (uint64_t s = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; s < m; s += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t len = he_off[s + 1] - he_off[s];
+    mx = len > mx ? static_cast<uint32_t>(len) : mx;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t x = __shfl_xor(mx, o, kWave);
+    mx = x > mx ? x : mx;
+  }
+  if (lane_id() == 0 && mx) atomicMax(b_max, mx);
+}
+
+__global__ void k_mcera_out(const int64_t* rows, uint32_t t, int64_t* topk_sum, uint64_t* deg_topk) {
+  for (uint32_t j = threadIdx.x; j <= t; j += blockDim.x) {
+    if (j < t)
+      topk_sum[j] = rows[j];
+    else
+      *deg_topk = static_cast<uint64_t>(rows[t]);
+  }
+}
+
+int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, uint32_t t, uint32_t k,
+                       int64_t* topk_sum, uint64_t* deg_topk, uint32_t* b_max, int32_t* R_out, hipStream_t s) {
+  const uint32_t Wt = (t + 63) / 64;
+  uint64_t I = 0;
+  CENTRA_HIP(ctx, hipMemcpyAsync(&I, he_off + m, 8, hipMemcpyDeviceToHost, s));
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  int rc;
+  if ((rc = ensure(ctx, ctx->P, size_t(n) * t * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->Rtm, size_t(n) * t * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->topk_tmp, (size_t(t) + 1) * 8, false, s))) return rc;
+  int32_t* P = static_cast<int32_t*>(ctx->P.ptr);
+  int32_t* Rtm = static_cast<int32_t*>(ctx->Rtm.ptr);
+  int64_t* rows = static_cast<int64_t*>(ctx->topk_tmp.ptr);
+  fill_u32(reinterpret_cast<uint32_t*>(P), 0, size_t(n) * t, s);
+  if (I) {
+    const uint64_t waves = (I + kSpan - 1) / kSpan;
+    const uint64_t blocks = (waves * kWave + kCountBlock - 1) / kCountBlock;
+    hipLaunchKernelGGL(k_rade_count, dim3(static_cast<unsigned>(blocks), Wt), dim3(kCountBlock), 0, s,
+                       static_cast<const uint32_t*>(ctx->inc.ptr), static_cast<const uint32_t*>(ctx->inc_node.ptr), I,
+                       static_cast<const uint64_t*>(ctx->words.ptr), Wt, t, P);
+  }
+  hipLaunchKernelGGL(k_rade_finish, dim3((n + 63) / 64, (t + 63) / 64), dim3(256), 0, s, P,
+                     static_cast<const uint32_t*>(ctx->deg.ptr), n, t, Rtm, R_out);
+  hipLaunchKernelGGL(k_topk_rows, dim3(t + 1), dim3(kTopBlock), 0, s, Rtm, static_cast<const uint32_t*>(ctx->deg.ptr),
+                     n, t, k, rows);
+  hipLaunchKernelGGL(k_mcera_out, dim3(1), dim3(256), 0, s, rows, t, topk_sum, deg_topk);
+  fill_u32(b_max, 0, 1, s);
+  hipLaunchKernelGGL(k_bmax, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, he_off, m, b_max);
+  CENTRA_HIP(ctx, hipGetLastError());
+  return CENTRA_OK;
+}
+
+}  // namespace centra

@@ -1,0 +1,122 @@
+"""GPU parity of centra_greedy_cover and centra_mcera against the oracle on
+the same hyperedge sets (oracle-sampled paths and generator hyperedges):
+bit-exact picks, cumulative coverage, trial sums R, per-trial top-k sums,
+top-k degree sum and max hyperedge size; plus edge cases."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2306_03651_amd import binding, inputs
+from tests.gpu_util import say, to_dev_u32, to_dev_u64
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_greedy(ctx, n, off, nodes, k):
+    picks = torch.zeros(k, dtype=torch.int32, device="cuda")
+    cov = torch.zeros(k, dtype=torch.int64, device="cuda")
+    npk = torch.zeros(1, dtype=torch.int32, device="cuda")
+    binding.centra_greedy_cover(ctx, n, to_dev_u64(off), to_dev_u32(nodes), k, picks, cov, npk)
+    c = int(npk.item())
+    return picks.cpu().numpy().view(np.uint32)[:c], cov.cpu().numpy().astype(np.uint64)[:c]
+
+
+def gpu_mcera(ctx, n, off, nodes, seed, inst, t, k, with_R=False):
+    topk = torch.zeros(t, dtype=torch.int64, device="cuda")
+    dk = torch.zeros(1, dtype=torch.int64, device="cuda")
+    bm = torch.zeros(1, dtype=torch.int32, device="cuda")
+    R = torch.zeros(n * t, dtype=torch.int32, device="cuda") if with_R else None
+    binding.centra_mcera(ctx, n, to_dev_u64(off), to_dev_u32(nodes), seed, inst, t, k, topk, dk, bm, R)
+    out = (topk.cpu().numpy(), int(dk.item()), int(bm.item()))
+    if with_R:
+        out = out + (R.cpu().numpy().reshape(n, t),)
+    return out
+
+
+def he_sets():
+    g = inputs.ba_graph(2000, 5, 1)
+    off, nodes = oracle.sample_paths(g, 1, 0, 0, 10000)
+    yield "c1_paths", 2000, off, nodes
+    off, nodes = inputs.hyperedges(5000, 30000, max_len=7, skew=3, seed=4)
+    yield "synth5000", 5000, off, nodes
+    grid = inputs.grid_graph(24)
+    off, nodes = oracle.sample_paths(grid, 3, 0, 0, 3000)
+    yield "grid_paths", grid.n, off, nodes
+    # many ties: every hyperedge a single node, each node twice
+    off = np.arange(0, 201, dtype=np.uint64)
+    nodes = np.repeat(np.arange(100, dtype=np.uint32), 2)
+    yield "ties", 150, off, nodes
+
+
+@pytest.mark.parametrize("k", [1, 10, 60])
+def test_greedy_bit_exact(ctx, k):
+    for name, n, off, nodes in he_sets():
+        say(f"greedy parity {name} k={k}")
+        gp, gc = gpu_greedy(ctx, n, off, nodes, k)
+        wp, wc = oracle.greedy_cover(n, off, nodes, k)
+        assert np.array_equal(gp, wp), name
+        assert np.array_equal(gc, wc), name
+
+
+@pytest.mark.parametrize("t,k", [(1, 1), (10, 10), (64, 50), (100, 7), (130, 300), (256, 5), (300, 20)])
+def test_mcera_bit_exact(ctx, t, k):
+    for name, n, off, nodes in he_sets():
+        say(f"mcera parity {name} t={t} k={k}")
+        topk, dk, bm, R = gpu_mcera(ctx, n, off, nodes, 11, 2, t, k, with_R=True)
+        _, wtopk, wdk, wbm = oracle.mcera(n, off, nodes, 11, 2, t, k)
+        assert np.array_equal(R, oracle.rade_sums(n, off, nodes, 11, 2, t)), name
+        assert np.array_equal(topk, wtopk), name
+        assert dk == wdk and bm == wbm, name
+
+
+def test_large_values_in_topk(ctx):
+    # A few nodes in every hyperedge: R values near m, exercising every
+    # digit pass of the selection.
+    m, n = 200000, 64
+    rng = np.random.default_rng(0)
+    lens = rng.integers(1, 4, size=m)
+    off = np.zeros(m + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(lens)
+    nodes = np.concatenate([rng.choice(8, size=int(l), replace=False) for l in lens]).astype(np.uint32)
+    for k in [1, 3, 9]:
+        topk, dk, bm = gpu_mcera(ctx, n, off, nodes, 5, 0, 70, k)
+        _, wtopk, wdk, wbm = oracle.mcera(n, off, nodes, 5, 0, 70, k)
+        assert np.array_equal(topk, wtopk) and dk == wdk and bm == wbm
+
+
+def test_edge_cases(ctx):
+    # nothing to cover
+    off = np.zeros(11, dtype=np.uint64)
+    p, c = gpu_greedy(ctx, 5, off, np.zeros(0, dtype=np.uint32), 3)
+    assert len(p) == 0
+    topk, dk, bm = gpu_mcera(ctx, 5, off, np.zeros(0, dtype=np.uint32), 1, 0, 4, 3)
+    assert not topk.any() and dk == 0 and bm == 0
+    # node id out of range
+    off = np.array([0, 2], dtype=np.uint64)
+    nodes = np.array([1, 99], dtype=np.uint32)
+    with pytest.raises(binding.CentraError) as e:
+        gpu_greedy(ctx, 10, off, nodes, 2)
+    assert e.value.code == binding.CENTRA_EINVAL
+    with pytest.raises(binding.CentraError):
+        gpu_mcera(ctx, 10, off, nodes, 1, 0, 4, 2)
+    # bad t
+    with pytest.raises(binding.CentraError):
+        gpu_mcera(ctx, 10, np.array([0, 1], dtype=np.uint64), np.array([1], dtype=np.uint32), 1, 0, 0, 2)
+    # the context is still usable afterwards
+    p, c = gpu_greedy(ctx, 10, np.array([0, 1], dtype=np.uint64), np.array([3], dtype=np.uint32), 2)
+    assert list(p) == [3] and list(c) == [1]
+
+
+def test_large_sparse_scale_cover_and_mcera(ctx):
+    # Hyperedge set shaped like 4M shortest paths on BA n=10^6 (the large
+    # sparse configuration's final iteration): k = 50, t = 64.
+    n, m = 1_000_000, 4_000_000
+    off, nodes = inputs.hyperedges(n, m, max_len=8, skew=4, seed=9)
+    say(f"large cover/mcera: m={m} I={len(nodes)}")
+    gp, gc = gpu_greedy(ctx, n, off, nodes, 50)
+    wp, wc = oracle.greedy_cover(n, off, nodes, 50)
+    assert np.array_equal(gp, wp) and np.array_equal(gc, wc)
+    topk, dk, bm = gpu_mcera(ctx, n, off, nodes, 1, 0, 64, 50)
+    _, wtopk, wdk, wbm = oracle.mcera(n, off, nodes, 1, 0, 64, 50)
+    assert np.array_equal(topk, wtopk) and dk == wdk and bm == wbm

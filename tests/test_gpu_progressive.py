@@ -1,0 +1,58 @@
+"""GPU parity of centra_progressive (Algorithm 1) against the oracle's driver:
+identical iterations, sample sizes, picks and coverage; FP64 bound values
+within 1e-12 relative."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_03651_amd import binding, inputs
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["c_hat", "amcera", "wimpy", "xi", "nu", "rtilde", "r", "eta"]
+
+
+def compare(g, ctx, k, t, eps, delta, seed, inst, m_init, m_max, num=2, den=1):
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        rc, picks, res, log = binding.centra_progressive(ctx, dg.handle, k, t, eps, delta, seed, inst, m_init,
+                                                         m_max, num, den)
+    finally:
+        dg.release()
+    wrc, wpicks, wres = oracle.progressive(g, k, t, eps, delta, seed, inst, m_init, m_max, num, den)
+    assert rc == wrc
+    assert np.array_equal(picks, wpicks)
+    assert res.iterations == wres.iterations and res.m_final == wres.m_final
+    assert res.coverage == wres.coverage and res.n_picked == wres.n_picked
+    assert res.certified == wres.certified
+    for f in FIELDS:
+        assert getattr(res, f) == pytest.approx(getattr(wres, f), rel=1e-12, abs=1e-300), f
+    sched = [m_init]
+    while len(sched) < res.iterations:
+        sched.append(min(-(-sched[-1] * num // den), m_max))
+    assert [it.m for it in log] == sched
+    assert [it.i for it in log] == list(range(1, res.iterations + 1))
+    return res
+
+
+def test_c1_configuration(ctx):
+    # BA n=2000, m0=5; m = 10,000, k = 10, t = 10, eps = 0.05, delta = 0.1:
+    # one iteration (delta_1 = 0.05).
+    g = inputs.ba_graph(2000, 5, 1)
+    say("progressive C1")
+    res = compare(g, ctx, 10, 10, 0.05, 0.1, 1, 0, 10000, 10000)
+    assert res.iterations == 1
+
+
+def test_c1_continued_until_certified(ctx):
+    g = inputs.ba_graph(2000, 5, 1)
+    say("progressive C1 continued")
+    res = compare(g, ctx, 10, 10, 0.05, 0.1, 1, 0, 10000, 1_280_000)
+    assert res.certified
+
+
+def test_directed_and_non_doubling_schedule(ctx):
+    g = inputs.rmat_graph(11, 8, seed=2)
+    say("progressive rmat11 growth 6/5")
+    compare(g, ctx, 7, 33, 0.2, 0.05, 3, 2, 3000, 20000, 6, 5)

@@ -1,0 +1,171 @@
+"""GPU parity of centra_sample_paths against the oracle: bit-exact hyperedges,
+pairs and distances on graphs spanning the sampler's code paths (multi-chunk
+frontiers, hubs wider than a workgroup, count normalisation, unreachable
+targets, long diameters that overflow the staging area), batch splits, the
+first configuration in full and the large sparse configuration on sampled
+indices."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2306_03651_amd import binding, inputs
+from tests.gpu_util import nodes_np, off_np, say
+
+pytestmark = pytest.mark.gpu
+
+
+def random_digraph(n, p, seed):
+    rng = np.random.default_rng(seed)
+    src, dst = np.nonzero(rng.random((n, n)) < p)
+    return inputs.from_edges(n, src, dst, directed=True)
+
+
+def star(n):
+    return inputs.from_edges(n, np.zeros(n - 1, dtype=np.int64), np.arange(1, n), directed=False)
+
+
+def chain(n):
+    return inputs.from_edges(n, np.arange(n - 1), np.arange(1, n), directed=False)
+
+
+CASES = {
+    "ba2000": (lambda: inputs.ba_graph(2000, 5, 1), 0),
+    "grid40_c8": (lambda: inputs.grid_graph(40), 8),
+    "grid40": (lambda: inputs.grid_graph(40), 0),
+    "dir300": (lambda: random_digraph(300, 0.01, 5), 0),
+    "rmat12": (lambda: inputs.rmat_graph(12, 8, seed=3), 0),
+    "star3000": (lambda: star(3000), 0),
+    "chain1500": (lambda: chain(1500), 0),
+    "pair": (lambda: inputs.from_edges(2, [0], [1], directed=False), 0),
+    "empty2": (lambda: inputs.from_edges(2, [], [], directed=True), 0),
+}
+
+
+def check_batch(ctx, g, cbo, seed, inst, first, count):
+    dg = binding.DeviceGraph(ctx, g, count_bits_override=cbo)
+    try:
+        off, nodes, st, dist = binding.sample_paths(ctx, dg, seed, inst, first, count, with_st=True)
+        torch.cuda.synchronize()
+        c_bits = dg.info()[1]
+    finally:
+        dg.release()
+    want_off, want_nodes, infos = oracle.sample_paths(g, seed, inst, first, count, c_bits=c_bits, with_info=True)
+    got_off, got_nodes = off_np(off), nodes_np(nodes)
+    assert np.array_equal(got_off, want_off)
+    assert np.array_equal(got_nodes, want_nodes)
+    st = st.cpu().numpy().view(np.uint32)[: 2 * count]
+    dist = dist.cpu().numpy().view(np.uint32)[:count]
+    assert np.array_equal(st[0::2], np.array([i.s for i in infos], dtype=np.uint32))
+    assert np.array_equal(st[1::2], np.array([i.t for i in infos], dtype=np.uint32))
+    assert np.array_equal(dist, np.array([i.dist for i in infos], dtype=np.uint32))
+    return got_off, got_nodes
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sampler_bit_exact(ctx, name):
+    build, cbo = CASES[name]
+    g = build()
+    count = 3000 if g.n > 2 else 500
+    say(f"sampler parity {name}: n={g.n} arcs={g.n_arcs} count={count} cbo={cbo}")
+    check_batch(ctx, g, cbo, seed=7, inst=1, first=0, count=count)
+
+
+def test_c1_configuration_full(ctx):
+    # BA n=2000, m0=5, seed 1; m = 10,000 samples of seed 1, instance 0.
+    g = inputs.ba_graph(2000, 5, 1)
+    say("C1 sampler parity: 10000 samples")
+    check_batch(ctx, g, 0, seed=1, inst=0, first=0, count=10000)
+
+
+def test_batch_split_is_invariant(ctx):
+    g = inputs.ba_graph(3000, 4, 2)
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        off_a, nodes_a = binding.sample_paths(ctx, dg, 5, 0, 0, 4000)
+        off_b, nodes_b = binding.sample_paths(ctx, dg, 5, 0, 0, 1234)
+        off_c, nodes_c = binding.sample_paths(ctx, dg, 5, 0, 1234, 2766)
+        off_d, nodes_d = binding.sample_paths(ctx, dg, 5, 0, 0, 4000)   # rerun: identical
+    finally:
+        dg.release()
+    a = nodes_np(nodes_a)
+    assert np.array_equal(a, np.concatenate([nodes_np(nodes_b), nodes_np(nodes_c)]))
+    assert np.array_equal(off_np(off_a)[:1235], off_np(off_b))
+    assert np.array_equal(a, nodes_np(nodes_d)) and np.array_equal(off_np(off_a), off_np(off_d))
+
+
+def test_count_zero_and_enospc(ctx):
+    g = inputs.ba_graph(500, 3, 1)
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        off = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+        rc, need = binding.centra_sample_paths(ctx, dg.handle, 1, 0, 0, 0, off, None, 0)
+        assert rc == 0 and need == 0 and int(off[0]) == 0
+        off = torch.empty(401, dtype=torch.int64, device="cuda")
+        small = torch.empty(3, dtype=torch.int32, device="cuda")
+        rc, need = binding.centra_sample_paths(ctx, dg.handle, 1, 0, 0, 400, off, small, 3)
+        assert rc == binding.CENTRA_ENOSPC
+        want_off, want_nodes = oracle.sample_paths(g, 1, 0, 0, 400)
+        assert need == len(want_nodes)
+        assert np.array_equal(off_np(off), want_off)
+    finally:
+        dg.release()
+
+
+def test_invalid_graphs_are_rejected(ctx):
+    good = inputs.ba_graph(50, 2, 1)
+    bad_rows = []
+    col = good.col_idx.copy()
+    col[[0, 1]] = col[[1, 0]]                       # unsorted row
+    bad_rows.append(col)
+    col = good.col_idx.copy()
+    col[0] = 0                                      # self loop on node 0
+    bad_rows.append(col)
+    col = good.col_idx.copy()
+    col[5] = 1000                                   # out of range
+    bad_rows.append(col)
+    for col in bad_rows:
+        g = inputs.CSRGraph(good.n, False, good.row_ptr, col)
+        with pytest.raises(binding.CentraError) as e:
+            binding.DeviceGraph(ctx, g)
+        assert e.value.code == binding.CENTRA_EINVAL
+    d = random_digraph(40, 0.1, 1)
+    rcol = d.rcol_idx.copy()
+    # a wrong (but sorted) in-row: swap one source for another not adjacent
+    v = int(np.argmax(np.diff(d.rrow_ptr.astype(np.int64)) > 0))
+    row = set(int(x) for x in rcol[d.rrow_ptr[v]:d.rrow_ptr[v + 1]])
+    repl = next(u for u in range(40) if u not in row and u != v)
+    rcol[d.rrow_ptr[v]] = repl
+    seg = np.sort(rcol[d.rrow_ptr[v]:d.rrow_ptr[v + 1]])
+    rcol[d.rrow_ptr[v]:d.rrow_ptr[v + 1]] = seg
+    g = inputs.CSRGraph(d.n, True, d.row_ptr, d.col_idx, d.rrow_ptr, rcol)
+    with pytest.raises(binding.CentraError):
+        binding.DeviceGraph(ctx, g)
+
+
+def test_large_sparse_configuration_sampled(ctx):
+    # BA n = 10^6, m0 = 5: a batch of 20,000 samples in the launch
+    # configuration the benchmark uses; 40 indices spread over the batch are
+    # recomputed one by one by the oracle.
+    g = inputs.ba_graph(1_000_000, 5, 1)
+    dg = binding.DeviceGraph(ctx, g)
+    count = 20000
+    try:
+        say("C2 sampler: 20000 samples on BA n=1e6")
+        off, nodes, st, dist = binding.sample_paths(ctx, dg, 1, 0, 0, count, with_st=True)
+        torch.cuda.synchronize()
+        c_bits = dg.info()[1]
+    finally:
+        dg.release()
+    off, nodes = off_np(off), nodes_np(nodes)
+    og = oracle.OracleGraph(g)
+    idx = np.linspace(0, count - 1, 40).astype(np.int64)
+    for i in idx:
+        h, info = oracle.sample_path(g, 1, 0, int(i), c_bits=c_bits, og=og)
+        assert np.array_equal(nodes[int(off[i]):int(off[i + 1])], h), i
+    # properties over the whole batch: lengths = d - 1, no repeats in a path
+    d = dist.cpu().numpy().view(np.uint32)[:count]
+    lens = np.diff(off.astype(np.int64))
+    reach = d != 0xFFFFFFFF
+    assert np.array_equal(lens[reach], np.maximum(d[reach].astype(np.int64) - 1, 0))
+    assert (lens[~reach] == 0).all()
