@@ -192,24 +192,31 @@ int centra_sample_paths(centra_ctx* ctx, const centra_graph* g, uint64_t seed, u
   return CENTRA_OK;
 }
 
+// Checks the sample arguments; he_nodes may be NULL only if every hyperedge
+// is empty (he_off[m] == 0), which is read from the device.
 static int check_sample_args(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
-                             const uint32_t* he_nodes, const char* who) {
+                             const uint32_t* he_nodes, const char* who, hipStream_t s) {
   if (n == 0) return fail(ctx, CENTRA_EINVAL, std::string(who) + ": n == 0");
   if (!he_off) return fail(ctx, CENTRA_EINVAL, std::string(who) + ": he_off is NULL");
-  if (m && !he_nodes) return fail(ctx, CENTRA_EINVAL, std::string(who) + ": he_nodes is NULL");
   if (m >= (1ull << 31)) return fail(ctx, CENTRA_ENOTSUP, std::string(who) + ": m >= 2^31");
+  if (!he_nodes) {
+    uint64_t I = 0;
+    CENTRA_HIP(ctx, hipMemcpyAsync(&I, he_off + m, 8, hipMemcpyDeviceToHost, s));
+    CENTRA_HIP(ctx, hipStreamSynchronize(s));
+    if (I) return fail(ctx, CENTRA_EINVAL, std::string(who) + ": he_nodes is NULL");
+  }
   return CENTRA_OK;
 }
 
 int centra_greedy_cover(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes,
                         uint32_t k, uint32_t* picks, uint64_t* cov_cum, uint32_t* n_picked, void* stream) {
   if (!ctx) return CENTRA_EINVAL;
-  int rc = check_sample_args(ctx, n, m, he_off, he_nodes, "greedy_cover");
-  if (rc) return rc;
   if (k == 0) return fail(ctx, CENTRA_EINVAL, "greedy_cover: k == 0");
   if (!picks || !cov_cum || !n_picked) return fail(ctx, CENTRA_EINVAL, "greedy_cover: NULL output");
   DeviceGuard guard(ctx->device);
   hipStream_t s = as_stream(stream);
+  int rc = check_sample_args(ctx, n, m, he_off, he_nodes, "greedy_cover", s);
+  if (rc) return rc;
   if ((rc = build_incidence(ctx, n, m, he_off, he_nodes, s))) return rc;
   if ((rc = check_flags(ctx, s, "greedy_cover"))) return rc;
   if ((rc = greedy_on_incidence(ctx, n, m, he_off, he_nodes, k, picks, cov_cum, n_picked, s))) return rc;
@@ -221,14 +228,14 @@ int centra_mcera(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off
                  uint64_t seed, uint32_t instance, uint32_t t, uint32_t k, int64_t* topk_sum, uint64_t* deg_topk_sum,
                  uint32_t* b_max, int32_t* R_out, void* stream) {
   if (!ctx) return CENTRA_EINVAL;
-  int rc = check_sample_args(ctx, n, m, he_off, he_nodes, "mcera");
-  if (rc) return rc;
   if (m == 0) return fail(ctx, CENTRA_EINVAL, "mcera: m == 0");
   if (t == 0 || t > 1024) return fail(ctx, CENTRA_EINVAL, "mcera: t must be in [1, 1024]");
   if (k == 0) return fail(ctx, CENTRA_EINVAL, "mcera: k == 0");
   if (!topk_sum || !deg_topk_sum || !b_max) return fail(ctx, CENTRA_EINVAL, "mcera: NULL output");
   DeviceGuard guard(ctx->device);
   hipStream_t s = as_stream(stream);
+  int rc = check_sample_args(ctx, n, m, he_off, he_nodes, "mcera", s);
+  if (rc) return rc;
   if ((rc = build_incidence(ctx, n, m, he_off, he_nodes, s))) return rc;
   if ((rc = check_flags(ctx, s, "mcera"))) return rc;
   if ((rc = rade_words(ctx, seed, instance, 0, m, t, s))) return rc;
