@@ -27,7 +27,7 @@ struct centra_ctx {
   uint32_t* d_flags = nullptr;   // kernel error bits (u32) + scratch counters
   // per-BFS slot arrays (level, normalised count, visit queue), one set per
   // concurrent BFS, sized for the largest graph seen
-  centra::DevBuf slot_lvl, slot_sig, slot_q;
+  centra::DevBuf slot_lvl, slot_sig, slot_q, slot_bits;
   uint32_t slots = 0;
   uint32_t slot_n = 0;
   // sampling staging area

@@ -1,7 +1,6 @@
 // sampleHEs for set betweenness on gfx950.
 //
-// Each workgroup of a persistent grid owns one BFS slot (level, normalised
-// count and visit-queue arrays of n entries in HBM) and takes sample
+// Each workgroup of a persistent grid owns one BFS slot and takes sample
 // indices from an atomic work counter until the batch is exhausted.  One
 // sample = pair draw, level-synchronous BFS from s with normalised path
 // counts, backtrack of a uniform shortest path from t.  Every quantity the
@@ -9,22 +8,45 @@
 // scan of in-neighbours) is independent of thread timing, so the result is
 // bit-identical to a sequential implementation.
 //
+// State of a slot: a visited bitmap (n bits; in LDS when it fits, which on
+// gfx950's 160 KB LDS means n up to about 1.1M, otherwise in HBM), and in
+// HBM the level (u32), the normalised count sigma' (u64) and the visit
+// queue (u32, nodes in level order).  Invariant between samples: sigma' is
+// 0 for every node and the bitmap is clear; the level array is read only
+// for nodes whose visited bit is set, so it is never cleared.
+//
 // Level expansion (push): the frontier is processed in chunks of BLOCK
-// nodes; their out-degrees are prefix-summed in LDS and every thread takes
-// arcs e = tid, tid + BLOCK, ... of the chunk, locating its source by
+// nodes; their out-degrees are prefix-summed in LDS and each thread takes
+// UNROLL arcs per round (tid, tid + BLOCK, ...), locating their sources by
 // binary search in LDS (load balance over skewed degrees; consecutive
-// threads read consecutive col_idx entries).  A node is claimed for the next
-// level by compare-and-swap on its level word; claimed nodes are appended to
-// the visit queue with one LDS atomic per wave (ballot + popcount).  Count
-// contributions are 64-bit atomic adds, so their sum is order independent.
+// threads read consecutive col_idx entries; UNROLL independent chains keep
+// more memory requests in flight).  An arc w -> v whose target is not yet
+// visited (levels <= L live in the bitmap, which is not touched during the
+// pass) adds sigma'_w to sigma'_v with a returning 64-bit atomic: the add
+// that sees 0 is the first arrival and claims v for level L+1 (appended to
+// the queue with one LDS atomic per wave, ballot + popcount; its level is
+// written).  The returned partial sums also give the level's largest raw
+// count, so the normalisation shift needs no extra pass; only when the shift
+// is nonzero are the level's counts rewritten.
 //
-// Before expanding level L the workgroup checks whether t has an
-// in-neighbour at level L; if so d(s,t) = L + 1 and the BFS stops: the
-// largest level is never expanded, and the backtrack only needs levels
-// <= d - 1, which are complete.
+// Before expanding level L the workgroup checks whether t has a visited
+// in-neighbour (necessarily at level L); if so d(s,t) = L + 1 and the BFS
+// stops: the backtrack only needs levels <= d - 1, which are complete.
 //
-// After a sample the workgroup resets exactly the entries it visited, so
-// the slot arrays are clean for the next sample without an O(n) clear.
+// Last-level shortcut.  Otherwise, if t has an in-neighbour w at level L+1
+// (w unvisited with an in-neighbour at level L), then d(s,t) = L + 2 and the
+// backtrack's first step needs the normalised counts of exactly those w.
+// Their raw counts are sums over level L, so each is at most S_L, the sum
+// of the level-L counts; when S_L < 2^C no count of level L+1 can need a
+// shift, the normalised counts equal the raw ones, and the (largest) level
+// L+1 need not be produced at all: the first backtrack step sums the raw
+// counts of t's in-neighbours directly from level L.  When S_L >= 2^C the
+// level is produced and normalised as usual.  Both routes give the same
+// counts, hence the same hyperedge.
+#include <stdlib.h>
+
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -44,6 +66,8 @@ struct SampleArgs {
   uint32_t* lvl;      // slots * n
   uint64_t* sig;      // slots * n
   uint32_t* q;        // slots * n
+  uint32_t* bits;     // slots * bit_words (HBM bitmap variant only)
+  uint32_t bit_words;
   uint32_t* work;     // work counter
   uint32_t* stage;    // staging for hyperedge nodes
   uint64_t stage_cap;
@@ -66,9 +90,44 @@ struct SampleShared {
   uint32_t next;
 };
 
+// Saturating u64 addition (only "below 2^C" is ever asked of these sums).
+__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) {
+  const uint64_t c = a + b;
+  return c < a ? ~0ull : c;
+}
+
 template <int BLOCK>
+__device__ __forceinline__ uint64_t block_sat_sum(uint64_t v, uint64_t* scratch) {
+  constexpr int NW = BLOCK / kWave;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = sat_add(v, shfl_xor_u64(v, m));
+  if (lane_id() == 0) scratch[threadIdx.x / kWave] = v;
+  __syncthreads();
+  uint64_t r = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) r = sat_add(r, scratch[i]);
+  __syncthreads();
+  return r;
+}
+
+// Visited bitmap in LDS.
+struct BitsLds {
+  uint32_t* w;
+  __device__ __forceinline__ bool test(uint32_t v) const { return (w[v >> 5] >> (v & 31u)) & 1u; }
+  __device__ __forceinline__ void set(uint32_t v) { atomicOr(&w[v >> 5], 1u << (v & 31u)); }
+};
+
+// Visited bitmap in HBM (one per slot).
+struct BitsHbm {
+  uint32_t* w;
+  __device__ __forceinline__ bool test(uint32_t v) const { return (ld_u32(&w[v >> 5]) >> (v & 31u)) & 1u; }
+  __device__ __forceinline__ void set(uint32_t v) { atomicOr(&w[v >> 5], 1u << (v & 31u)); }
+};
+
+template <int BLOCK, int UNROLL, bool LDS_BITS>
 __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   __shared__ SampleShared<BLOCK> sh;
+  extern __shared__ uint32_t dyn_bits[];
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wid = tid / kWave;
@@ -76,7 +135,12 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   uint32_t* lvl = a.lvl + slot * a.n;
   uint64_t* sig = a.sig + slot * a.n;
   uint32_t* q = a.q + slot * a.n;
+  using Bits = typename std::conditional<LDS_BITS, BitsLds, BitsHbm>::type;
+  Bits bits{LDS_BITS ? dyn_bits : a.bits + slot * a.bit_words};
   const uint64_t lane_lt = (1ull << lane) - 1ull;
+
+  if (LDS_BITS)
+    for (uint32_t i = tid; i < a.bit_words; i += BLOCK) dyn_bits[i] = 0;
 
   for (;;) {
     if (tid == 0) sh.next = atomicAdd(a.work, 1u);
@@ -96,23 +160,52 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       st_u32(&lvl[s], 0);
       st_u64(&sig[s], 1);
       st_u32(&q[0], s);
+      bits.set(s);
       sh.qlen = 1;
     }
     __syncthreads();
 
     uint32_t lb = 0, le = 1, L = 0, d = kUnseen;
+    uint64_t sumL = 1;             // S_L: sum of the level-L counts (saturating)
+    uint64_t w_short = 0;          // nonzero: last-level shortcut taken, = W of the first step
+    const uint64_t cap = a.c_bits >= 64 ? ~0ull : (1ull << a.c_bits);
     const uint32_t tb = a.in_ptr[t], te = a.in_ptr[t + 1];
     for (;;) {
-      // does t have an in-neighbour at level L?
+      // visited in-neighbour of t?  (visited = level <= L, and any such
+      // neighbour is at level L, else an earlier check would have fired)
       int found = 0;
       for (uint32_t e = tb + tid; e < te; e += BLOCK)
-        if (ld_u32(&lvl[a.in_idx[e]]) == L) found = 1;
+        if (bits.test(a.in_idx[e])) found = 1;
       if (__syncthreads_or(found)) {
         d = L + 1;
         break;
       }
+      if (sumL < cap) {
+        // in-neighbours w of t at level L+1: raw_w = sum of sigma' over
+        // w's in-neighbours at level L (one wave per w)
+        uint64_t wsum = 0;
+        for (uint32_t e = tb + wid; e < te; e += BLOCK / kWave) {
+          const uint32_t w = a.in_idx[e];
+          if (bits.test(w)) continue;   // cannot happen here (checked above); kept for clarity
+          const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
+          uint64_t x = 0;
+          for (uint32_t f = ub + lane; f < ue; f += kWave) {
+            const uint32_t u = a.in_idx[f];
+            if (bits.test(u) && ld_u32(&lvl[u]) == L) x += ld_u64(&sig[u]);
+          }
+          wsum += wave_sum_u64(x);
+        }
+        if (lane != 0) wsum = 0;
+        wsum = block_sum_u64<BLOCK>(wsum, sh.red);
+        if (wsum) {
+          d = L + 2;
+          w_short = wsum;
+          break;
+        }
+      }
       // expand level L (queue entries [lb, le)) into level L+1
       const uint32_t nl = L + 1;
+      uint64_t mx = 0, added = 0;
       for (uint32_t cb = lb; cb < le; cb += BLOCK) {
         const uint32_t i = cb + tid;
         uint32_t deg = 0, rs = 0;
@@ -129,66 +222,86 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         sh.rs[tid] = rs;
         sh.sg[tid] = sw;
         __syncthreads();
-        for (uint32_t base = 0; base < total; base += BLOCK) {
-          const uint32_t e = base + tid;
-          bool claimed = false;
-          uint32_t v = 0;
-          if (e < total) {
-            // largest j with off[j] <= e (zero-degree entries share the
-            // offset of the next entry, so the largest match has arcs)
-            int lo = 0, hi = BLOCK - 1;
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (sh.off[mid] <= e)
-                lo = mid;
-              else
-                hi = mid - 1;
+        for (uint32_t base = 0; base < total; base += BLOCK * UNROLL) {
+          uint32_t v[UNROLL];
+          uint64_t add[UNROLL], old[UNROLL];
+          bool act[UNROLL];
+#pragma unroll
+          for (int k = 0; k < UNROLL; ++k) {
+            const uint32_t e = base + k * BLOCK + tid;
+            act[k] = e < total;
+            v[k] = 0;
+            add[k] = 0;
+            if (act[k]) {
+              // largest j with off[j] <= e (zero-degree entries share the
+              // offset of the next entry, so the largest match has arcs)
+              int lo = 0, hi = BLOCK - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sh.off[mid] <= e)
+                  lo = mid;
+                else
+                  hi = mid - 1;
+              }
+              v[k] = a.col_idx[sh.rs[lo] + (e - sh.off[lo])];
+              add[k] = sh.sg[lo];
             }
-            v = a.col_idx[sh.rs[lo] + (e - sh.off[lo])];
-            uint32_t lv = ld_u32(&lvl[v]);
-            if (lv == kUnseen) {
-              const uint32_t old = atomicCAS(&lvl[v], kUnseen, nl);
-              if (old == kUnseen) {
-                claimed = true;
-                lv = nl;
-              } else {
-                lv = old;
+          }
+#pragma unroll
+          for (int k = 0; k < UNROLL; ++k)
+            if (act[k] && bits.test(v[k])) act[k] = false;
+#pragma unroll
+          for (int k = 0; k < UNROLL; ++k) {
+            old[k] = 0;
+            if (act[k])
+              old[k] = atomicAdd(reinterpret_cast<unsigned long long*>(&sig[v[k]]),
+                                 static_cast<unsigned long long>(add[k]));
+          }
+#pragma unroll
+          for (int k = 0; k < UNROLL; ++k) {
+            const bool claimed = act[k] && old[k] == 0;
+            if (act[k]) {
+              const uint64_t x = old[k] + add[k];
+              mx = x > mx ? x : mx;
+              added = sat_add(added, add[k]);
+            }
+            // wave-aggregated append of newly claimed nodes
+            const uint64_t m = __ballot(claimed);
+            if (m) {
+              uint32_t wbase = 0;
+              const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+              if (lane == leader) wbase = atomicAdd(&sh.qlen, static_cast<uint32_t>(__popcll(m)));
+              wbase = __shfl(wbase, leader, kWave);
+              if (claimed) {
+                st_u32(&q[wbase + __popcll(m & lane_lt)], v[k]);
+                st_u32(&lvl[v[k]], nl);
               }
             }
-            if (lv == nl) atomicAdd(reinterpret_cast<unsigned long long*>(&sig[v]),
-                                    static_cast<unsigned long long>(sh.sg[lo]));
-          }
-          // wave-aggregated append of newly claimed nodes
-          const uint64_t m = __ballot(claimed);
-          if (m) {
-            uint32_t wbase = 0;
-            const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-            if (lane == leader) wbase = atomicAdd(&sh.qlen, static_cast<uint32_t>(__popcll(m)));
-            wbase = __shfl(wbase, leader, kWave);
-            if (claimed) st_u32(&q[wbase + __popcll(m & lane_lt)], v);
           }
         }
         __syncthreads();
       }
       const uint32_t ne = sh.qlen;
       if (ne == le) break;   // nothing new: t unreachable
-      // normalise level L+1 (queue entries [le, ne))
-      uint64_t mx = 0;
-      for (uint32_t i = le + tid; i < ne; i += BLOCK) {
-        const uint64_t x = ld_u64(&sig[ld_u32(&q[i])]);
-        mx = x > mx ? x : mx;
-      }
+      // level L+1 is complete: its largest raw count decides the shift;
+      // S_{L+1} is the sum of the added contributions, or of the shifted
+      // counts when a shift applies
       mx = block_max_u64<BLOCK>(mx, sh.red);
       const uint32_t bl = bitlen64(mx);
-      if (bl > a.c_bits) {
-        const uint32_t shift = bl - a.c_bits;
-        for (uint32_t i = le + tid; i < ne; i += BLOCK) {
-          const uint32_t v = ld_u32(&q[i]);
-          const uint64_t x = ld_u64(&sig[v]) >> shift;
-          st_u64(&sig[v], x ? x : 1ull);
+      const uint32_t shift = bl > a.c_bits ? bl - a.c_bits : 0u;
+      uint64_t ssum = 0;
+      for (uint32_t i = le + tid; i < ne; i += BLOCK) {
+        const uint32_t v = ld_u32(&q[i]);
+        bits.set(v);
+        if (shift) {
+          uint64_t x = ld_u64(&sig[v]) >> shift;
+          x = x ? x : 1ull;
+          st_u64(&sig[v], x);
+          ssum = sat_add(ssum, x);
         }
       }
-      __syncthreads();
+      if (!shift) ssum = added;
+      sumL = block_sat_sum<BLOCK>(ssum, sh.red);   // contains the barrier closing the level
       lb = le;
       le = ne;
       L = nl;
@@ -206,6 +319,38 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         base = shfl_u64(base, 0);
         uint32_t v = t, dv = d;
         uint32_t written = 0;
+        if (w_short) {
+          // first step through the unproduced level L+1: in-neighbours w of t
+          // in ascending order, weight raw_w = sum of level-L counts over
+          // w's in-neighbours (equal to the normalised count, see above)
+          const uint64_t r = bounded(st, w_short);
+          uint64_t acc = 0;
+          uint32_t pick = kUnseen;
+          for (uint32_t e = tb; e < te; ++e) {
+            const uint32_t w = a.in_idx[e];
+            if (bits.test(w)) continue;
+            const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
+            uint64_t x = 0;
+            for (uint32_t f = ub + lane; f < ue; f += kWave) {
+              const uint32_t u = a.in_idx[f];
+              if (bits.test(u) && ld_u32(&lvl[u]) == L) x += ld_u64(&sig[u]);
+            }
+            acc += wave_sum_u64(x);
+            if (acc > r) {
+              pick = w;
+              break;
+            }
+          }
+          if (pick == kUnseen) {
+            if (lane == 0) atomicOr(a.flags, kErrBacktrack);
+            dv = 0;
+          } else {
+            if (lane == 0 && base < a.stage_cap) a.stage[base] = pick;
+            written = 1;
+            v = pick;
+            dv = d - 1;
+          }
+        }
         while (dv >= 2) {
           const uint32_t want = dv - 1;
           const uint32_t vb = a.in_ptr[v], ve = a.in_ptr[v + 1];
@@ -215,7 +360,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
             uint64_t x = 0;
             if (e < ve) {
               const uint32_t w = a.in_idx[e];
-              if (ld_u32(&lvl[w]) == want) x = ld_u64(&sig[w]);
+              if (bits.test(w) && ld_u32(&lvl[w]) == want) x = ld_u64(&sig[w]);
             }
             W += wave_sum_u64(x);
           }
@@ -229,7 +374,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
               uint32_t w = 0;
               if (e < ve) {
                 w = a.in_idx[e];
-                if (ld_u32(&lvl[w]) == want) x = ld_u64(&sig[w]);
+                if (bits.test(w) && ld_u32(&lvl[w]) == want) x = ld_u64(&sig[w]);
               }
               const uint64_t incl = acc + wave_incl_scan_u64(x);
               const uint64_t hit = __ballot(incl > r);
@@ -261,12 +406,15 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       }
     }
     __syncthreads();
-    // reset the visited entries of this slot
+    // restore the invariant: counts of the visited nodes back to 0, bitmap clear
     const uint32_t nv = sh.qlen;
     for (uint32_t i = tid; i < nv; i += BLOCK) {
       const uint32_t v = ld_u32(&q[i]);
-      st_u32(&lvl[v], kUnseen);
       st_u64(&sig[v], 0);
+      if (LDS_BITS)
+        dyn_bits[v >> 5] = 0;
+      else
+        st_u32(&a.bits[slot * a.bit_words + (v >> 5)], 0);
     }
     __syncthreads();
   }
@@ -287,49 +435,87 @@ __global__ void k_stage_gather(uint32_t count, const uint64_t* stage_pos, const 
   for (uint32_t x = 0; x < len; ++x) he_nodes[o + x] = stage[p + x];
 }
 
-constexpr int kSampleBlock = 512;
-constexpr uint32_t kMaxSlots = 1024;
+// Launch shapes: the LDS-bitmap variant runs one 1024-thread workgroup per
+// CU (the bitmap takes most of the LDS); the HBM-bitmap variant runs
+// 512-thread workgroups, several per CU.
+constexpr int kLdsBlock = 1024;
+constexpr int kHbmBlock = 512;
+constexpr int kUnroll = 4;
+constexpr uint32_t kMaxSlots = 2048;
 
-static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, hipStream_t s) {
-  if (ctx->slots >= want && ctx->slot_n >= g->n) return CENTRA_OK;
+#define CENTRA_LDS_KERNEL k_sample_paths<kLdsBlock, kUnroll, true>
+#define CENTRA_HBM_KERNEL k_sample_paths<kHbmBlock, kUnroll, false>
+
+struct SamplePlan {
+  bool lds_bits;
+  uint32_t bit_words;
+  size_t dyn_lds;
+  uint32_t resident;   // workgroups resident at once = BFS slots
+};
+
+static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
+  SamplePlan p{};
+  p.bit_words = (n + 31) / 32;
+  int max_lds = 0, cus = 0;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess)
+    max_lds = 65536;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+    cus = 256;
+  const size_t dyn = size_t(p.bit_words) * 4;
+  // CENTRA_SAMPLER_HBM_BITMAP=1 forces the HBM-bitmap variant (tests of that path on small graphs)
+  const char* force = getenv("CENTRA_SAMPLER_HBM_BITMAP");
+  p.lds_bits = sizeof(SampleShared<kLdsBlock>) + dyn <= size_t(max_lds) && !(force && force[0] == '1');
+  int per_cu = 0;
+  if (p.lds_bits) {
+    p.dyn_lds = dyn;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&CENTRA_LDS_KERNEL),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, CENTRA_LDS_KERNEL, kLdsBlock, dyn) != hipSuccess)
+      per_cu = 1;
+  } else {
+    p.dyn_lds = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, CENTRA_HBM_KERNEL, kHbmBlock, 0) != hipSuccess)
+      per_cu = 1;
+  }
+  (void)hipGetLastError();
+  if (per_cu <= 0) per_cu = 1;
+  const uint64_t r = uint64_t(cus) * uint64_t(per_cu);
+  p.resident = r > kMaxSlots ? kMaxSlots : static_cast<uint32_t>(r);
+  return p;
+}
+
+static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, bool hbm_bits, hipStream_t s) {
+  const uint32_t words = (g->n + 31) / 32;
+  if (ctx->slots >= want && ctx->slot_n >= g->n && (!hbm_bits || ctx->slot_bits.bytes >= size_t(ctx->slots) * words * 4))
+    return CENTRA_OK;
   uint32_t slots = want > ctx->slots ? want : ctx->slots;
   const uint32_t n = g->n > ctx->slot_n ? g->n : ctx->slot_n;
+  const uint32_t nw = (n + 31) / 32;
+  const size_t per_slot = size_t(n) * (4 + 8 + 4) + (hbm_bits ? size_t(nw) * 4 : 0);
   // shrink the slot count if the budget cannot hold all of them
   for (;;) {
-    const size_t need = size_t(slots) * n * (4 + 8 + 4);
-    const size_t have = ctx->slot_lvl.bytes + ctx->slot_sig.bytes + ctx->slot_q.bytes;
+    const size_t need = size_t(slots) * per_slot;
+    const size_t have = ctx->slot_lvl.bytes + ctx->slot_sig.bytes + ctx->slot_q.bytes + ctx->slot_bits.bytes;
     if (!ctx->budget || ctx->allocated - have + need <= ctx->budget || slots <= 1) break;
     slots /= 2;
   }
   release(ctx, ctx->slot_lvl);
   release(ctx, ctx->slot_sig);
   release(ctx, ctx->slot_q);
+  release(ctx, ctx->slot_bits);
   ctx->slots = 0;
   ctx->slot_n = 0;
   int rc;
   if ((rc = ensure(ctx, ctx->slot_lvl, size_t(slots) * n * 4, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_sig, size_t(slots) * n * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_q, size_t(slots) * n * 4, false, s))) return rc;
-  fill_u32(static_cast<uint32_t*>(ctx->slot_lvl.ptr), kUnseen, size_t(slots) * n, s);
+  if (hbm_bits && (rc = ensure(ctx, ctx->slot_bits, size_t(slots) * nw * 4, false, s))) return rc;
   fill_u64(static_cast<uint64_t*>(ctx->slot_sig.ptr), 0, size_t(slots) * n, s);
+  if (hbm_bits) fill_u32(static_cast<uint32_t*>(ctx->slot_bits.ptr), 0, size_t(slots) * nw, s);
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->slots = slots;
   ctx->slot_n = n;
   return CENTRA_OK;
-}
-
-// Concurrent BFS slots: as many workgroups as the device keeps resident.
-static uint32_t resident_slots(centra_ctx* ctx) {
-  int cus = 0, per_cu = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
-    cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sample_paths<kSampleBlock>, kSampleBlock, 0) !=
-          hipSuccess ||
-      per_cu <= 0)
-    per_cu = 1;
-  (void)hipGetLastError();
-  const uint64_t r = uint64_t(cus) * uint64_t(per_cu);
-  return r > kMaxSlots ? kMaxSlots : static_cast<uint32_t>(r);
 }
 
 int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
@@ -337,9 +523,9 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
   int rc;
   *total = 0;
   if (count == 0) return CENTRA_OK;
-  const uint32_t resident = resident_slots(ctx);
-  uint32_t want = count < resident ? count : resident;
-  if ((rc = ensure_slots(ctx, g, want, s))) return rc;
+  const SamplePlan plan = plan_for(ctx, g->n);
+  uint32_t want = count < plan.resident ? count : plan.resident;
+  if ((rc = ensure_slots(ctx, g, want, !plan.lds_bits, s))) return rc;
   const uint32_t grid = count < ctx->slots ? count : ctx->slots;
   if ((rc = ensure(ctx, ctx->stage_pos, size_t(count) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->stage_len, size_t(count) * 4 + 8 + 8 * (size_t(count) + 1), false, s))) return rc;
@@ -367,6 +553,8 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     a.lvl = static_cast<uint32_t*>(ctx->slot_lvl.ptr);
     a.sig = static_cast<uint64_t*>(ctx->slot_sig.ptr);
     a.q = static_cast<uint32_t*>(ctx->slot_q.ptr);
+    a.bits = static_cast<uint32_t*>(ctx->slot_bits.ptr);
+    a.bit_words = plan.bit_words;
     a.work = work;
     a.stage = static_cast<uint32_t*>(ctx->stage_nodes.ptr);
     a.stage_cap = cap;
@@ -376,7 +564,10 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     a.st_out = st_out;
     a.dist_out = dist_out;
     a.flags = ctx->d_flags;
-    hipLaunchKernelGGL(k_sample_paths<kSampleBlock>, dim3(grid), dim3(kSampleBlock), 0, s, a);
+    if (plan.lds_bits)
+      hipLaunchKernelGGL(CENTRA_LDS_KERNEL, dim3(grid), dim3(kLdsBlock), plan.dyn_lds, s, a);
+    else
+      hipLaunchKernelGGL(CENTRA_HBM_KERNEL, dim3(grid), dim3(kHbmBlock), 0, s, a);
     CENTRA_HIP(ctx, hipGetLastError());
     uint64_t host_used = 0;
     CENTRA_HIP(ctx, hipMemcpyAsync(&host_used, used, 8, hipMemcpyDeviceToHost, s));

@@ -71,6 +71,17 @@ def test_sampler_bit_exact(ctx, name):
     check_batch(ctx, g, cbo, seed=7, inst=1, first=0, count=count)
 
 
+@pytest.mark.parametrize("name", ["ba2000", "grid40_c8", "rmat12", "star3000", "chain1500"])
+def test_sampler_hbm_bitmap_variant_bit_exact(ctx, name, monkeypatch):
+    # graphs whose visited bitmap does not fit in LDS use the HBM-bitmap
+    # kernel; force it here on small graphs
+    monkeypatch.setenv("CENTRA_SAMPLER_HBM_BITMAP", "1")
+    build, cbo = CASES[name]
+    g = build()
+    say(f"sampler parity (HBM bitmap) {name}")
+    check_batch(ctx, g, cbo, seed=9, inst=0, first=17, count=2500)
+
+
 def test_c1_configuration_full(ctx):
     # BA n=2000, m0=5, seed 1; m = 10,000 samples of seed 1, instance 0.
     g = inputs.ba_graph(2000, 5, 1)
