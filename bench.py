@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the CentRA hot path on one MI355X.
+
+Workload (the large sparse configuration): undirected Barabasi-Albert graph
+n = 1,000,000, attachment 5 (seed 1), uint32 CSR resident in HBM; Algorithm 1
+with a schedule starting at 100,000 samples and doubling up to 4,000,000,
+k = 50, t = 64, eps = 0.01, delta = 0.1.  One step = one complete run of
+Algorithm 1 from an empty sample (sampling, greedy cover, AMCERA and bound
+at every iteration) until the stopping condition holds or the cap is
+reached.  value = shortest paths sampled per second of whole-job time.
+
+Also reported:
+  - roofline: the sampling kernel's algorithmic bytes per launch
+    (4 B per CSR entry scanned + 28 B per node given a level, counted
+    exactly by the kernel) over its average launch time, measured with HIP
+    events recorded on the launch stream around every launch in the timed
+    region; `traffic` comes from the committed rocprofv3 counter summary
+    when it was taken on the current kernel source, else null;
+  - cpu_baseline: the oracle (plain C, single thread) sampling the same
+    workload's first sample indices for a bounded time on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sample_paths_ba1e6_traffic.txt")
+SAMPLER_SRC = os.path.join(ROOT, "paper_2306_03651_amd", "csrc", "sample.hip")
+
+WORKLOAD = dict(graph="barabasi_albert", n=1_000_000, m0=5, graph_seed=1, seed=1, instance=0,
+                m_init=100_000, m_max=4_000_000, growth=2, k=50, t=64, eps=0.01, delta=0.1)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(SAMPLER_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed counter summary, if it matches
+    the current sampler source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    for ln in open(TRAFFIC_SUMMARY):
+        if ":" in ln and not ln.startswith("#"):
+            k, v = ln.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("sampler_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(graph, seconds: float):
+    import oracle
+    og = oracle.OracleGraph(graph)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        oracle.sample_path(graph, WORKLOAD["seed"], WORKLOAD["instance"], done, og=og)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "paths/s", "cores": 1, "kind": "oracle",
+            "sample": f"sample indices 0..{done - 1} of the benchmark workload (seed 1, instance 0) drawn by "
+                      f"the oracle's sampler (full-level BFS with normalised counts + backtrack), one thread, "
+                      f"{dt:.1f} s; greedy cover and AMCERA excluded (under 0.1% of the oracle's time per path "
+                      f"at this size); host {platform.processor() or platform.machine()}, "
+                      f"{os.cpu_count()} logical CPUs"}
+
+
+def copy_probe():
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.int32, device="cuda")   # 1 GiB
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(8):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_probe_bytes_read_per_launch": 1 << 30, "copy_probe_bytes_written_per_launch": 1 << 30,
+                      "launches": 8, "GBps_read_plus_write": round(8 * 2 * (1 << 30) / dt / 1e9, 1)}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the oracle CPU baseline")
+    ap.add_argument("--m-max", type=int, default=WORKLOAD["m_max"], help=argparse.SUPPRESS)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy 8 times (calibrates the HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the hot path is single-GPU here); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2306_03651_amd import binding, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    W = dict(WORKLOAD, m_max=args.m_max)
+    t0 = time.time()
+    g = inputs.ba_graph(W["n"], W["m0"], W["graph_seed"])
+    log(f"graph: n={g.n} arcs={g.n_arcs} ({time.time() - t0:.1f}s)")
+    ctx = binding.centra_create(0, 0)
+    dg = binding.DeviceGraph(ctx, g)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return binding.centra_progressive(ctx, dg.handle, W["k"], W["t"], W["eps"], W["delta"], W["seed"],
+                                          W["instance"], W["m_init"], W["m_max"], W["growth"], 1,
+                                          stream=stream)
+
+    for i in range(args.warmup):
+        rc, picks, res, itlog = step()
+        log(f"warmup {i}: m={res.m_final} iters={res.iterations} certified={res.certified} "
+            f"eta={res.eta:.5f} ms={res.ms_total:.0f}")
+    binding.centra_sampler_stats_get(ctx, reset=True)
+    torch.cuda.synchronize()
+    paths = 0
+    times = []
+    results = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        rc, picks, res, itlog = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        paths += res.m_final
+        results.append((rc, picks, res, itlog))
+        log(f"step {i}: {times[-1]:.3f}s m={res.m_final} iters={res.iterations} certified={res.certified} "
+            f"eta={res.eta:.5f} c_hat={res.c_hat:.4f}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    st = binding.centra_sampler_stats_get(ctx)
+    rc, picks, res, itlog = results[-1]
+    dg.release()
+    binding.centra_destroy(ctx)
+
+    launches = max(1, st.launches)
+    bytes_per_launch = (4.0 * st.arcs + 28.0 * st.nodes) / launches
+    sec_per_launch = st.kernel_ms / 1e3 / launches
+    achieved = bytes_per_launch / sec_per_launch / 1e9
+    traffic = read_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "kernel": "k_sample_paths", "launches": st.launches,
+                "avg_launch_ms": round(st.kernel_ms / launches, 3),
+                "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                "arcs_per_path": round(st.arcs / max(1, st.samples), 1),
+                "nodes_per_path": round(st.nodes / max(1, st.samples), 1),
+                "visited_bitmap": "lds" if st.lds_bitmap else "hbm", "concurrent_bfs": st.slots}
+
+    cpu = cpu_baseline(g, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    value = paths / total
+    out = {
+        "metric": "shortest paths sampled/s",
+        "value": round(value, 1),
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "CentRA (Algorithm 1) on Barabasi-Albert n=1e6, attachment 5, seed 1; samples "
+                               "100k doubling to 4M, k=50, t=64, eps=0.01, delta=0.1",
+                   "n": W["n"], "arcs": int(g.n_arcs), "m_init": W["m_init"], "m_max": W["m_max"],
+                   "k": W["k"], "t": W["t"], "eps": W["eps"], "delta": W["delta"]},
+        "time_to_certified_s": round(sum(times) / len(times), 3) if res.certified else None,
+        "time_to_cap_s": None if res.certified else round(sum(times) / len(times), 3),
+        "certified": bool(res.certified),
+        "m_final": int(res.m_final),
+        "iterations": int(res.iterations),
+        "eta": res.eta,
+        "c_hat": res.c_hat,
+        "stop_lhs_over_rhs": (1 - 1 / 2.718281828459045) * ((1 - 1 / 2.718281828459045 - W["eps"]) * res.xi + res.eta)
+        / (W["eps"] * res.c_hat) if res.c_hat > 0 else None,
+        "phase_ms": {"sample": round(res.ms_sample, 1), "cover": round(res.ms_cover, 1),
+                     "mcera": round(res.ms_mcera, 1)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

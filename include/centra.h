@@ -162,6 +162,27 @@ CENTRA_API int centra_mcera(centra_ctx *ctx, uint32_t n, uint64_t m, const uint6
                  int64_t *topk_sum, uint64_t *deg_topk_sum, uint32_t *b_max, int32_t *R_out,
                  void *stream);
 
+/* Work and time of the sampling kernel, accumulated over every sampling
+ * launch of the context since the last reset (centra_sample_paths and the
+ * sampling steps of centra_progressive).  kernel_ms is measured with HIP
+ * events recorded on the launch stream immediately around each launch.
+ * arcs counts every CSR entry the kernel scans (level expansions, the
+ * checks around t, the backtrack is not included); nodes counts every node
+ * given a level.  A re-launch after a staging overflow counts again. */
+typedef struct {
+    uint64_t launches;
+    double kernel_ms;
+    uint64_t samples;
+    uint64_t arcs;
+    uint64_t nodes;
+    uint64_t hyperedge_nodes;
+    uint32_t lds_bitmap;   /* 1 if the last launch kept the visited bitmap in LDS */
+    uint32_t slots;        /* workgroups (concurrent BFSs) of the last launch */
+} centra_sampler_stats;
+
+/* Copies the statistics to *out (host) and, if reset != 0, zeroes them. */
+CENTRA_API int centra_sampler_stats_get(centra_ctx *ctx, centra_sampler_stats *out, int reset);
+
 /* ------------------------------------------------------------------ */
 /* Theorem bound_dev (eq. epsrade) with xi and the stopping condition of
  * Algorithm 1, in FP64 on the host:  a = 1 - 1/e, L = ln(5/delta_i),

@@ -67,6 +67,12 @@ class Iteration(_c.Structure):
                 ("ms_sample", _c.c_double), ("ms_cover", _c.c_double), ("ms_mcera", _c.c_double)]
 
 
+class SamplerStats(_c.Structure):
+    _fields_ = [("launches", _c.c_uint64), ("kernel_ms", _c.c_double), ("samples", _c.c_uint64),
+                ("arcs", _c.c_uint64), ("nodes", _c.c_uint64), ("hyperedge_nodes", _c.c_uint64),
+                ("lds_bitmap", _c.c_uint32), ("slots", _c.c_uint32)]
+
+
 # name -> (restype, argtypes); the names and order are those of centra.h
 SIGNATURES = {
     "centra_abi_version": (_c.c_uint32, []),
@@ -81,6 +87,7 @@ SIGNATURES = {
     "centra_greedy_cover": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint32, _vp, _vp, _vp, _vp]),
     "centra_mcera": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint32,
                                 _c.c_uint32, _vp, _vp, _vp, _vp, _vp]),
+    "centra_sampler_stats_get": (_c.c_int, [_vp, _c.POINTER(SamplerStats), _c.c_int]),
     "centra_bound": (_c.c_int, [_c.c_uint64, _c.c_uint64, _c.c_int64, _c.c_uint32, _c.c_uint64, _c.c_uint32,
                                 _c.c_double, _c.c_double, _c.POINTER(BoundOut)]),
     "centra_progressive": (_c.c_int, [_vp, _vp, _c.POINTER(Params), _vp, _c.POINTER(Result),
@@ -212,6 +219,12 @@ def centra_mcera(ctx, n: int, he_off, he_nodes, seed: int, instance: int, t: int
     return _check(lib().centra_mcera(ctx, n, m, _ptr(he_off), _ptr(he_nodes), seed, instance, t, k,
                                      _ptr(topk_sum), _ptr(deg_topk), _ptr(b_max), _ptr(R_out), _stream(stream)),
                   ctx)
+
+
+def centra_sampler_stats_get(ctx, reset: bool = False) -> SamplerStats:
+    out = SamplerStats()
+    _check(lib().centra_sampler_stats_get(ctx, ctypes.byref(out), 1 if reset else 0), ctx)
+    return out
 
 
 def centra_bound(m: int, cov: int, sum_topk: int, t: int, deg_topk: int, b_max: int, eps: float,

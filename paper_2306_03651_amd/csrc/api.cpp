@@ -244,6 +244,13 @@ int centra_mcera(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off
   return CENTRA_OK;
 }
 
+int centra_sampler_stats_get(centra_ctx* ctx, centra_sampler_stats* out, int reset) {
+  if (!ctx || !out) return CENTRA_EINVAL;
+  *out = ctx->st;
+  if (reset) ctx->st = centra_sampler_stats{};
+  return CENTRA_OK;
+}
+
 int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk, uint32_t b_max,
                  double eps, double delta_i, centra_bound_out* out) {
   if (!out || m == 0 || t == 0 || !(delta_i > 0.0 && delta_i < 1.0)) return CENTRA_EINVAL;

@@ -40,6 +40,7 @@ struct centra_ctx {
   // sample store of centra_progressive
   centra::DevBuf store_off, store_nodes;
   hipEvent_t ev[8] = {};
+  centra_sampler_stats st = {};
 };
 
 struct centra_graph {

@@ -77,6 +77,7 @@ struct SampleArgs {
   uint32_t* st_out;      // optional
   uint32_t* dist_out;    // optional
   uint32_t* flags;
+  uint64_t* stats;       // [0] arcs scanned, [1] nodes visited (accumulated)
 };
 
 template <int BLOCK>
@@ -141,6 +142,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
 
   if (LDS_BITS)
     for (uint32_t i = tid; i < a.bit_words; i += BLOCK) dyn_bits[i] = 0;
+  // work counters (uniform across the workgroup): arcs scanned, nodes visited
+  uint64_t n_arcs = 0, n_nodes = 0;
 
   for (;;) {
     if (tid == 0) sh.next = atomicAdd(a.work, 1u);
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       // visited in-neighbour of t?  (visited = level <= L, and any such
       // neighbour is at level L, else an earlier check would have fired)
       int found = 0;
+      n_arcs += te - tb;
       for (uint32_t e = tb + tid; e < te; e += BLOCK)
         if (bits.test(a.in_idx[e])) found = 1;
       if (__syncthreads_or(found)) {
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       if (sumL < cap) {
         // in-neighbours w of t at level L+1: raw_w = sum of sigma' over
         // w's in-neighbours at level L (one wave per w)
-        uint64_t wsum = 0;
+        uint64_t wsum = 0, wscan = 0;
         for (uint32_t e = tb + wid; e < te; e += BLOCK / kWave) {
           const uint32_t w = a.in_idx[e];
           if (bits.test(w)) continue;   // cannot happen here (checked above); kept for clarity
@@ -194,9 +198,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
             if (bits.test(u) && ld_u32(&lvl[u]) == L) x += ld_u64(&sig[u]);
           }
           wsum += wave_sum_u64(x);
+          wscan += ue - ub;
         }
-        if (lane != 0) wsum = 0;
+        if (lane != 0) {
+          wsum = 0;
+          wscan = 0;
+        }
         wsum = block_sum_u64<BLOCK>(wsum, sh.red);
+        n_arcs += block_sum_u64<BLOCK>(wscan, sh.red);
         if (wsum) {
           d = L + 2;
           w_short = wsum;
@@ -218,6 +227,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         }
         uint32_t total;
         const uint32_t off = block_excl_scan_u32<BLOCK>(deg, &total, sh.scan);
+        n_arcs += total;
         sh.off[tid] = off;
         sh.rs[tid] = rs;
         sh.sg[tid] = sw;
@@ -408,6 +418,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
     __syncthreads();
     // restore the invariant: counts of the visited nodes back to 0, bitmap clear
     const uint32_t nv = sh.qlen;
+    n_nodes += nv;
     for (uint32_t i = tid; i < nv; i += BLOCK) {
       const uint32_t v = ld_u32(&q[i]);
       st_u64(&sig[v], 0);
@@ -417,6 +428,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         st_u32(&a.bits[slot * a.bit_words + (v >> 5)], 0);
     }
     __syncthreads();
+  }
+  if (tid == 0 && a.stats && n_arcs) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[0]), static_cast<unsigned long long>(n_arcs));
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[1]), static_cast<unsigned long long>(n_nodes));
   }
 }
 
@@ -564,15 +579,30 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     a.st_out = st_out;
     a.dist_out = dist_out;
     a.flags = ctx->d_flags;
+    a.stats = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 16);
+    fill_u64(a.stats, 0, 2, s);
+    CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
     if (plan.lds_bits)
       hipLaunchKernelGGL(CENTRA_LDS_KERNEL, dim3(grid), dim3(kLdsBlock), plan.dyn_lds, s, a);
     else
       hipLaunchKernelGGL(CENTRA_HBM_KERNEL, dim3(grid), dim3(kHbmBlock), 0, s, a);
     CENTRA_HIP(ctx, hipGetLastError());
-    uint64_t host_used = 0;
-    CENTRA_HIP(ctx, hipMemcpyAsync(&host_used, used, 8, hipMemcpyDeviceToHost, s));
+    CENTRA_HIP(ctx, hipEventRecord(ctx->ev[7], s));
+    uint64_t host_ctr[4] = {0, 0, 0, 0};   // work, used, arcs, nodes
+    CENTRA_HIP(ctx, hipMemcpyAsync(host_ctr, ctx->work_ctr.ptr, 32, hipMemcpyDeviceToHost, s));
     CENTRA_HIP(ctx, hipStreamSynchronize(s));
     if ((rc = check_flags(ctx, s, "sample_paths"))) return rc;
+    const uint64_t host_used = host_ctr[1];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]) != hipSuccess) ms = 0.f;
+    ctx->st.launches += 1;
+    ctx->st.kernel_ms += ms;
+    ctx->st.samples += count;
+    ctx->st.arcs += host_ctr[2];
+    ctx->st.nodes += host_ctr[3];
+    ctx->st.hyperedge_nodes += host_used <= cap ? host_used : 0;
+    ctx->st.lds_bitmap = plan.lds_bits ? 1 : 0;
+    ctx->st.slots = grid;
     if (host_used <= cap) {
       *total = host_used;
       return CENTRA_OK;
