@@ -25,9 +25,9 @@ struct centra_ctx {
   size_t allocated = 0;
   std::string err;
   uint32_t* d_flags = nullptr;   // kernel error bits (u32) + scratch counters
-  // per-BFS slot arrays (level, normalised count, visit queue), one set per
-  // concurrent BFS, sized for the largest graph seen
-  centra::DevBuf slot_lvl, slot_sig, slot_q, slot_bits;
+  // per-BFS slot arrays (node records {count, level}, visit queue, HBM
+  // visited bitmap), one set per concurrent BFS, sized for the largest graph
+  centra::DevBuf slot_rec, slot_q, slot_bits;
   uint32_t slots = 0;
   uint32_t slot_n = 0;
   // sampling staging area

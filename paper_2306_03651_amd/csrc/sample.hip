@@ -10,10 +10,11 @@
 //
 // State of a slot: a visited bitmap (n bits; in LDS when it fits, which on
 // gfx950's 160 KB LDS means n up to about 1.1M, otherwise in HBM), and in
-// HBM the level (u32), the normalised count sigma' (u64) and the visit
-// queue (u32, nodes in level order).  Invariant between samples: sigma' is
-// 0 for every node and the bitmap is clear; the level array is read only
-// for nodes whose visited bit is set, so it is never cleared.
+// HBM one 16-byte record per node {sigma' u64, level u32} (so a node's
+// claim, level, count reads and reset touch a single cache line) and the
+// visit queue (u32, nodes in level order).  Invariant between samples:
+// sigma' is 0 for every node and the bitmap is clear; the level field is
+// read only for nodes whose visited bit is set, so it is never cleared.
 //
 // Level expansion (push): the frontier is processed in chunks of BLOCK
 // nodes; their out-degrees are prefix-summed in LDS and each thread takes
@@ -63,8 +64,7 @@ struct SampleArgs {
   uint32_t instance;
   uint64_t first;
   uint32_t count;
-  uint32_t* lvl;      // slots * n
-  uint64_t* sig;      // slots * n
+  uint64_t* rec;      // slots * n records of two words: sigma', level
   uint32_t* q;        // slots * n
   uint32_t* bits;     // slots * bit_words (HBM bitmap variant only)
   uint32_t bit_words;
@@ -80,6 +80,14 @@ struct SampleArgs {
   uint64_t* stats;       // [0] arcs scanned, [1] nodes visited (accumulated)
 };
 
+constexpr uint32_t kRawCache = 1024;
+
+// Record accessors: word 0 = sigma', low half of word 1 = level.
+__device__ __forceinline__ uint64_t* sig_of(uint64_t* rec, uint32_t v) { return rec + 2 * size_t(v); }
+__device__ __forceinline__ uint32_t* lvl_of(uint64_t* rec, uint32_t v) {
+  return reinterpret_cast<uint32_t*>(rec + 2 * size_t(v) + 1);
+}
+
 template <int BLOCK>
 struct SampleShared {
   uint32_t off[BLOCK];
@@ -87,6 +95,7 @@ struct SampleShared {
   uint64_t sg[BLOCK];
   uint32_t scan[BLOCK / kWave + 1];
   uint64_t red[BLOCK / kWave];
+  uint64_t raw[kRawCache];   // raw counts of t's first in-neighbours (last-level shortcut)
   uint32_t qlen;
   uint32_t next;
 };
@@ -133,8 +142,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   const int lane = lane_id();
   const int wid = tid / kWave;
   const size_t slot = blockIdx.x;
-  uint32_t* lvl = a.lvl + slot * a.n;
-  uint64_t* sig = a.sig + slot * a.n;
+  uint64_t* rec = a.rec + 2 * slot * a.n;
   uint32_t* q = a.q + slot * a.n;
   using Bits = typename std::conditional<LDS_BITS, BitsLds, BitsHbm>::type;
   Bits bits{LDS_BITS ? dyn_bits : a.bits + slot * a.bit_words};
@@ -160,8 +168,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
     const uint32_t t = tp + (tp >= s ? 1u : 0u);
 
     if (tid == 0) {
-      st_u32(&lvl[s], 0);
-      st_u64(&sig[s], 1);
+      st_u32(lvl_of(rec, s), 0);
+      st_u64(sig_of(rec, s), 1);
       st_u32(&q[0], s);
       bits.set(s);
       sh.qlen = 1;
@@ -189,15 +197,17 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         // w's in-neighbours at level L (one wave per w)
         uint64_t wsum = 0, wscan = 0;
         for (uint32_t e = tb + wid; e < te; e += BLOCK / kWave) {
+          // (w is unvisited: the check above found no visited in-neighbour of t)
           const uint32_t w = a.in_idx[e];
-          if (bits.test(w)) continue;   // cannot happen here (checked above); kept for clarity
           const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
           uint64_t x = 0;
           for (uint32_t f = ub + lane; f < ue; f += kWave) {
             const uint32_t u = a.in_idx[f];
-            if (bits.test(u) && ld_u32(&lvl[u]) == L) x += ld_u64(&sig[u]);
+            if (bits.test(u) && ld_u32(lvl_of(rec, u)) == L) x += ld_u64(sig_of(rec, u));
           }
-          wsum += wave_sum_u64(x);
+          const uint64_t raw = wave_sum_u64(x);
+          if (lane == 0 && e - tb < kRawCache) sh.raw[e - tb] = raw;
+          wsum += raw;
           wscan += ue - ub;
         }
         if (lane != 0) {
@@ -223,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
           const uint32_t w = ld_u32(&q[i]);
           rs = a.row_ptr[w];
           deg = a.row_ptr[w + 1] - rs;
-          sw = ld_u64(&sig[w]);
+          sw = ld_u64(sig_of(rec, w));
         }
         uint32_t total;
         const uint32_t off = block_excl_scan_u32<BLOCK>(deg, &total, sh.scan);
@@ -264,7 +274,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
           for (int k = 0; k < UNROLL; ++k) {
             old[k] = 0;
             if (act[k])
-              old[k] = atomicAdd(reinterpret_cast<unsigned long long*>(&sig[v[k]]),
+              old[k] = atomicAdd(reinterpret_cast<unsigned long long*>(sig_of(rec, v[k])),
                                  static_cast<unsigned long long>(add[k]));
           }
 #pragma unroll
@@ -284,7 +294,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
               wbase = __shfl(wbase, leader, kWave);
               if (claimed) {
                 st_u32(&q[wbase + __popcll(m & lane_lt)], v[k]);
-                st_u32(&lvl[v[k]], nl);
+                st_u32(lvl_of(rec, v[k]), nl);
               }
             }
           }
@@ -304,9 +314,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         const uint32_t v = ld_u32(&q[i]);
         bits.set(v);
         if (shift) {
-          uint64_t x = ld_u64(&sig[v]) >> shift;
+          uint64_t x = ld_u64(sig_of(rec, v)) >> shift;
           x = x ? x : 1ull;
-          st_u64(&sig[v], x);
+          st_u64(sig_of(rec, v), x);
           ssum = sat_add(ssum, x);
         }
       }
@@ -334,21 +344,35 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
           // in ascending order, weight raw_w = sum of level-L counts over
           // w's in-neighbours (equal to the normalised count, see above)
           const uint64_t r = bounded(st, w_short);
-          uint64_t acc = 0;
           uint32_t pick = kUnseen;
-          for (uint32_t e = tb; e < te; ++e) {
-            const uint32_t w = a.in_idx[e];
-            if (bits.test(w)) continue;
-            const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
-            uint64_t x = 0;
-            for (uint32_t f = ub + lane; f < ue; f += kWave) {
-              const uint32_t u = a.in_idx[f];
-              if (bits.test(u) && ld_u32(&lvl[u]) == L) x += ld_u64(&sig[u]);
+          if (te - tb <= kRawCache) {
+            uint64_t acc = 0;
+            for (uint32_t cb = 0; cb < te - tb; cb += kWave) {
+              const uint32_t i = cb + lane;
+              const uint64_t x = i < te - tb ? sh.raw[i] : 0ull;
+              const uint64_t incl = acc + wave_incl_scan_u64(x);
+              const uint64_t hit = __ballot(incl > r);
+              if (hit) {
+                pick = a.in_idx[tb + cb + __ffsll(static_cast<unsigned long long>(hit)) - 1];
+                break;
+              }
+              acc = shfl_u64(incl, kWave - 1);
             }
-            acc += wave_sum_u64(x);
-            if (acc > r) {
-              pick = w;
-              break;
+          } else {
+            uint64_t acc = 0;
+            for (uint32_t e = tb; e < te; ++e) {
+              const uint32_t w = a.in_idx[e];
+              const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
+              uint64_t x = 0;
+              for (uint32_t f = ub + lane; f < ue; f += kWave) {
+                const uint32_t u = a.in_idx[f];
+                if (bits.test(u) && ld_u32(lvl_of(rec, u)) == L) x += ld_u64(sig_of(rec, u));
+              }
+              acc += wave_sum_u64(x);
+              if (acc > r) {
+                pick = w;
+                break;
+              }
             }
           }
           if (pick == kUnseen) {
@@ -364,35 +388,67 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         while (dv >= 2) {
           const uint32_t want = dv - 1;
           const uint32_t vb = a.in_ptr[v], ve = a.in_ptr[v + 1];
-          uint64_t W = 0;
-          for (uint32_t cb = vb; cb < ve; cb += kWave) {
-            const uint32_t e = cb + lane;
-            uint64_t x = 0;
-            if (e < ve) {
-              const uint32_t w = a.in_idx[e];
-              if (bits.test(w) && ld_u32(&lvl[w]) == want) x = ld_u64(&sig[w]);
-            }
-            W += wave_sum_u64(x);
-          }
           uint32_t pick = kUnseen;
-          if (W) {
-            const uint64_t r = bounded(st, W);
-            uint64_t acc = 0;
+          if (ve - vb <= 4 * kWave) {
+            // one pass: candidates held in registers between the sum and the pick
+            uint64_t xs[4];
+            uint32_t ws[4];
+            uint64_t W = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const uint32_t e = vb + k * kWave + lane;
+              xs[k] = 0;
+              ws[k] = 0;
+              if (e < ve) {
+                const uint32_t w = a.in_idx[e];
+                ws[k] = w;
+                if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) xs[k] = ld_u64(sig_of(rec, w));
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) W += wave_sum_u64(xs[k]);
+            if (W) {
+              const uint64_t r = bounded(st, W);
+              uint64_t acc = 0;
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const uint64_t incl = acc + wave_incl_scan_u64(xs[k]);
+                const uint64_t hit = __ballot(incl > r);
+                if (hit && pick == kUnseen)
+                  pick = __shfl(ws[k], __ffsll(static_cast<unsigned long long>(hit)) - 1, kWave);
+                acc = shfl_u64(incl, kWave - 1);
+              }
+            }
+          } else {
+            uint64_t W = 0;
             for (uint32_t cb = vb; cb < ve; cb += kWave) {
               const uint32_t e = cb + lane;
               uint64_t x = 0;
-              uint32_t w = 0;
               if (e < ve) {
-                w = a.in_idx[e];
-                if (bits.test(w) && ld_u32(&lvl[w]) == want) x = ld_u64(&sig[w]);
+                const uint32_t w = a.in_idx[e];
+                if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) x = ld_u64(sig_of(rec, w));
               }
-              const uint64_t incl = acc + wave_incl_scan_u64(x);
-              const uint64_t hit = __ballot(incl > r);
-              if (hit) {
-                pick = __shfl(w, __ffsll(static_cast<unsigned long long>(hit)) - 1, kWave);
-                break;
+              W += wave_sum_u64(x);
+            }
+            if (W) {
+              const uint64_t r = bounded(st, W);
+              uint64_t acc = 0;
+              for (uint32_t cb = vb; cb < ve; cb += kWave) {
+                const uint32_t e = cb + lane;
+                uint64_t x = 0;
+                uint32_t w = 0;
+                if (e < ve) {
+                  w = a.in_idx[e];
+                  if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) x = ld_u64(sig_of(rec, w));
+                }
+                const uint64_t incl = acc + wave_incl_scan_u64(x);
+                const uint64_t hit = __ballot(incl > r);
+                if (hit) {
+                  pick = __shfl(w, __ffsll(static_cast<unsigned long long>(hit)) - 1, kWave);
+                  break;
+                }
+                acc = shfl_u64(incl, kWave - 1);
               }
-              acc = shfl_u64(incl, kWave - 1);
             }
           }
           if (pick == kUnseen) {
@@ -421,7 +477,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
     n_nodes += nv;
     for (uint32_t i = tid; i < nv; i += BLOCK) {
       const uint32_t v = ld_u32(&q[i]);
-      st_u64(&sig[v], 0);
+      st_u64(sig_of(rec, v), 0);
       if (LDS_BITS)
         dyn_bits[v >> 5] = 0;
       else
@@ -506,26 +562,24 @@ static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, b
   uint32_t slots = want > ctx->slots ? want : ctx->slots;
   const uint32_t n = g->n > ctx->slot_n ? g->n : ctx->slot_n;
   const uint32_t nw = (n + 31) / 32;
-  const size_t per_slot = size_t(n) * (4 + 8 + 4) + (hbm_bits ? size_t(nw) * 4 : 0);
+  const size_t per_slot = size_t(n) * (16 + 4) + (hbm_bits ? size_t(nw) * 4 : 0);
   // shrink the slot count if the budget cannot hold all of them
   for (;;) {
     const size_t need = size_t(slots) * per_slot;
-    const size_t have = ctx->slot_lvl.bytes + ctx->slot_sig.bytes + ctx->slot_q.bytes + ctx->slot_bits.bytes;
+    const size_t have = ctx->slot_rec.bytes + ctx->slot_q.bytes + ctx->slot_bits.bytes;
     if (!ctx->budget || ctx->allocated - have + need <= ctx->budget || slots <= 1) break;
     slots /= 2;
   }
-  release(ctx, ctx->slot_lvl);
-  release(ctx, ctx->slot_sig);
+  release(ctx, ctx->slot_rec);
   release(ctx, ctx->slot_q);
   release(ctx, ctx->slot_bits);
   ctx->slots = 0;
   ctx->slot_n = 0;
   int rc;
-  if ((rc = ensure(ctx, ctx->slot_lvl, size_t(slots) * n * 4, false, s))) return rc;
-  if ((rc = ensure(ctx, ctx->slot_sig, size_t(slots) * n * 8, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->slot_rec, size_t(slots) * n * 16, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_q, size_t(slots) * n * 4, false, s))) return rc;
   if (hbm_bits && (rc = ensure(ctx, ctx->slot_bits, size_t(slots) * nw * 4, false, s))) return rc;
-  fill_u64(static_cast<uint64_t*>(ctx->slot_sig.ptr), 0, size_t(slots) * n, s);
+  fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(slots) * n * 2, s);
   if (hbm_bits) fill_u32(static_cast<uint32_t*>(ctx->slot_bits.ptr), 0, size_t(slots) * nw, s);
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->slots = slots;
@@ -565,8 +619,7 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     a.instance = instance;
     a.first = first;
     a.count = count;
-    a.lvl = static_cast<uint32_t*>(ctx->slot_lvl.ptr);
-    a.sig = static_cast<uint64_t*>(ctx->slot_sig.ptr);
+    a.rec = static_cast<uint64_t*>(ctx->slot_rec.ptr);
     a.q = static_cast<uint32_t*>(ctx->slot_q.ptr);
     a.bits = static_cast<uint32_t*>(ctx->slot_bits.ptr);
     a.bit_words = plan.bit_words;
