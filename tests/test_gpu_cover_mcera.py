@@ -120,3 +120,17 @@ def test_large_sparse_scale_cover_and_mcera(ctx):
     topk, dk, bm = gpu_mcera(ctx, n, off, nodes, 1, 0, 64, 50)
     _, wtopk, wdk, wbm = oracle.mcera(n, off, nodes, 1, 0, 64, 50)
     assert np.array_equal(topk, wtopk) and dk == wdk and bm == wbm
+
+
+def test_skewed_directed_scale_cover_and_mcera(ctx):
+    # Shapes of the skewed directed configuration's iteration: n = 4.2M,
+    # 2M hyperedges, k = 100, t = 128.
+    n, m = 1 << 22, 2_000_000
+    off, nodes = inputs.hyperedges(n, m, max_len=6, skew=5, seed=12)
+    say(f"skewed cover/mcera: n={n} m={m} I={len(nodes)}")
+    gp, gc = gpu_greedy(ctx, n, off, nodes, 100)
+    wp, wc = oracle.greedy_cover(n, off, nodes, 100)
+    assert np.array_equal(gp, wp) and np.array_equal(gc, wc)
+    topk, dk, bm = gpu_mcera(ctx, n, off, nodes, 3, 1, 128, 100)
+    _, wtopk, wdk, wbm = oracle.mcera(n, off, nodes, 3, 1, 128, 100)
+    assert np.array_equal(topk, wtopk) and dk == wdk and bm == wbm

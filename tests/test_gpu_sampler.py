@@ -180,3 +180,57 @@ def test_large_sparse_configuration_sampled(ctx):
     reach = d != 0xFFFFFFFF
     assert np.array_equal(lens[reach], np.maximum(d[reach].astype(np.int64) - 1, 0))
     assert (lens[~reach] == 0).all()
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    return inputs.rmat_graph(22, 16, seed=1)
+
+
+def check_sampled(ctx, g, seed, inst, first, count, n_check):
+    """Samples a full batch on the GPU; recomputes n_check spread indices
+    with the oracle and checks every hyperedge's length against its
+    distance."""
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        off, nodes, st, dist = binding.sample_paths(ctx, dg, seed, inst, first, count, with_st=True)
+        torch.cuda.synchronize()
+        c_bits = dg.info()[1]
+    finally:
+        dg.release()
+    off, nodes = off_np(off), nodes_np(nodes)
+    st = st.cpu().numpy().view(np.uint32)[: 2 * count]
+    d = dist.cpu().numpy().view(np.uint32)[:count]
+    og = oracle.OracleGraph(g)
+    for i in np.linspace(0, count - 1, n_check).astype(np.int64):
+        h, info = oracle.sample_path(g, seed, inst, first + int(i), c_bits=c_bits, og=og)
+        assert np.array_equal(nodes[int(off[i]):int(off[i + 1])], h), i
+        assert (st[2 * i], st[2 * i + 1], d[i]) == (info.s, info.t, info.dist), i
+    lens = np.diff(off.astype(np.int64))
+    reach = d != 0xFFFFFFFF
+    assert np.array_equal(lens[reach], np.maximum(d[reach].astype(np.int64) - 1, 0))
+    assert (lens[~reach] == 0).all()
+    return off, nodes, d
+
+
+def test_rmat22_configuration_sampled(ctx, rmat22):
+    # The skewed directed configuration: R-MAT scale 22 (4.2M nodes, 65.2M
+    # arcs after dropping duplicates and self loops), reverse CSR; the
+    # visited bitmap does not fit in LDS, so the HBM-bitmap kernel runs.
+    say(f"R-MAT 22: n={rmat22.n} arcs={rmat22.n_arcs}; 200000 samples")
+    off, nodes, d = check_sampled(ctx, rmat22, 1, 0, 0, 200000, 16)
+    say(f"  reachable fraction {np.mean(d != 0xFFFFFFFF):.3f}")
+
+
+@pytest.mark.parametrize("L", [256, 1024])
+def test_grid_configuration_sampled(ctx, L):
+    # Grids of the uneven-instances configuration (side up to 1024, diameter
+    # up to 2046): thousands of levels, count normalisation shifts, and the
+    # last-level shortcut disabled once the level sums exceed 2^C.
+    say(f"grid {L}x{L}: 3000 samples")
+    check_sampled(ctx, inputs.grid_graph(L), 3, 5, 1000, 3000, 24)
+
+
+def test_ba_1e5_configuration_sampled(ctx):
+    say("BA n=1e5: 50000 samples")
+    check_sampled(ctx, inputs.ba_graph(100_000, 5, 7), 2, 9, 0, 50000, 40)
