@@ -69,6 +69,7 @@ int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s) {
     return fail(ctx, CENTRA_EINVAL, "graph: malformed out-CSR (row bounds, order, duplicates, self loops or range)");
   }
   g->max_in_degree = host[1];
+  g->max_out_degree = host[1];
   if (g->directed) {
     hipLaunchKernelGGL(k_validate_rows, dim3(blocks), dim3(256), 0, s, g->n, g->n_arcs, g->in_ptr, g->in_idx,
                        flags, maxd_in);

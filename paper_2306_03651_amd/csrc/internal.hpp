@@ -53,6 +53,7 @@ struct centra_graph {
   const uint32_t* in_ptr = nullptr;
   const uint32_t* in_idx = nullptr;
   uint32_t max_in_degree = 0;
+  uint32_t max_out_degree = 0;
   uint32_t count_bits = 0;
 };
 

@@ -56,6 +56,7 @@ namespace centra {
 struct SampleArgs {
   uint32_t n;
   uint32_t c_bits;
+  uint32_t max_out_deg;
   const uint32_t* row_ptr;
   const uint32_t* col_idx;
   const uint32_t* in_ptr;
@@ -80,7 +81,13 @@ struct SampleArgs {
   uint64_t* stats;       // [0] arcs scanned, [1] nodes visited (accumulated)
 };
 
-constexpr uint32_t kRawCache = 1024;
+// Ring limits: t with at most kRingCache in-neighbours gets the 2-hop test
+// on the pairs (w in in(t), u in in(w)); the 3-hop test also needs at most
+// kPairMax pairs, and runs at a level only when expanding that level would
+// scan at least 1/kConeRatio of the cone's CSR entries.
+constexpr uint32_t kRingCache = 512;
+constexpr uint32_t kPairMax = 65536;
+constexpr uint64_t kConeRatio = 3;
 
 // Record accessors: word 0 = sigma', low half of word 1 = level.
 __device__ __forceinline__ uint64_t* sig_of(uint64_t* rec, uint32_t v) { return rec + 2 * size_t(v); }
@@ -95,7 +102,14 @@ struct SampleShared {
   uint64_t sg[BLOCK];
   uint32_t scan[BLOCK / kWave + 1];
   uint64_t red[BLOCK / kWave];
-  uint64_t raw[kRawCache];   // raw counts of t's first in-neighbours (last-level shortcut)
+  uint32_t poff[kRingCache];   // pair offsets of t's in-neighbours
+  uint32_t rw[kRingCache];     // t's in-neighbours w
+  uint32_t rrs[kRingCache];    // in_ptr[w]
+  uint64_t ring_a[kRingCache];  // per in-neighbour w of t: level-(L+1) count / weights of a pick
+  uint64_t ring_b[kRingCache];  // per in-neighbour w of t: level-(L+2) count
+  uint64_t acc;
+  uint64_t base;
+  uint32_t pick;
   uint32_t qlen;
   uint32_t next;
 };
@@ -134,6 +148,115 @@ struct BitsHbm {
   __device__ __forceinline__ void set(uint32_t v) { atomicOr(&w[v >> 5], 1u << (v & 31u)); }
 };
 
+// Raw counts of one chunk of nodes, one node u per thread (kUnseen for
+// none): sh.sg[tid] = sum of sigma' over u's visited in-neighbours, 0 for a
+// visited u.  For an unvisited u every visited in-neighbour is at the last
+// produced level (a lower one would have put u in a produced level), so
+// this is u's raw count one level below.  Load balanced like the
+// expansion: in-degrees prefix-summed in LDS, UNROLL entries per thread
+// per round, sources found by binary search.  Adds the entries scanned to
+// n_arcs.  Contains barriers; sh.sg is valid on return until the next call.
+template <int BLOCK, int UNROLL, typename Bits>
+__device__ void raw_counts_chunk(const SampleArgs& a, const Bits& bits, uint64_t* rec, uint32_t u,
+                                 SampleShared<BLOCK>& sh, uint64_t& n_arcs) {
+  const int tid = threadIdx.x;
+  uint32_t deg = 0, rs = 0;
+  if (u != kUnseen && !bits.test(u)) {
+    rs = a.in_ptr[u];
+    deg = a.in_ptr[u + 1] - rs;
+  }
+  uint32_t total;
+  const uint32_t off = block_excl_scan_u32<BLOCK>(deg, &total, sh.scan);
+  n_arcs += total;
+  sh.off[tid] = off;
+  sh.rs[tid] = rs;
+  sh.sg[tid] = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < total; base += BLOCK * UNROLL) {
+    uint32_t x[UNROLL], j[UNROLL];
+#pragma unroll
+    for (int k = 0; k < UNROLL; ++k) {
+      const uint32_t e = base + k * BLOCK + tid;
+      x[k] = kUnseen;
+      j[k] = 0;
+      if (e < total) {
+        int lo = 0, hi = BLOCK - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (sh.off[mid] <= e)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        j[k] = lo;
+        x[k] = a.in_idx[sh.rs[lo] + (e - sh.off[lo])];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < UNROLL; ++k)
+      if (x[k] != kUnseen && bits.test(x[k]))
+        atomicAdd(reinterpret_cast<unsigned long long*>(&sh.sg[j[k]]),
+                  static_cast<unsigned long long>(ld_u64(sig_of(rec, x[k]))));
+  }
+  __syncthreads();
+}
+
+// Ring index of pair p: largest i with poff[i] <= p.
+__device__ __forceinline__ int ring_of(const uint32_t* poff, uint32_t dt, uint32_t p) {
+  int lo = 0, hi = static_cast<int>(dt) - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (poff[mid] <= p)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Weighted pick over the in-neighbours u of node `w` in ascending order,
+// weight of u = raw_counts_chunk's count (u's count one level below the
+// unproduced level of w).  Returns the first u whose prefix weight exceeds
+// r (uniform across the workgroup).
+template <int BLOCK, int UNROLL, typename Bits>
+__device__ uint32_t pick_through_ring(const SampleArgs& a, const Bits& bits, uint64_t* rec, uint32_t w, uint64_t r,
+                                      SampleShared<BLOCK>& sh, uint64_t& n_arcs) {
+  const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  const uint32_t wb = a.in_ptr[w], we = a.in_ptr[w + 1];
+  uint64_t acc = 0;
+  uint32_t pick = kUnseen;
+  for (uint32_t cb = wb; cb < we; cb += BLOCK) {
+    const uint32_t cnt = we - cb < BLOCK ? we - cb : BLOCK;
+    const uint32_t u = static_cast<uint32_t>(tid) < cnt ? a.in_idx[cb + tid] : kUnseen;
+    raw_counts_chunk<BLOCK, UNROLL>(a, bits, rec, u, sh, n_arcs);
+    if (wid == 0) {
+      uint32_t found = kUnseen;
+      uint64_t run = acc;
+      for (uint32_t c = 0; c < cnt; c += kWave) {
+        const uint32_t i = c + lane;
+        const uint64_t xv = i < cnt ? sh.sg[i] : 0ull;
+        const uint64_t incl = run + wave_incl_scan_u64(xv);
+        const uint64_t hit = __ballot(incl > r);
+        if (hit) {
+          found = a.in_idx[cb + c + __ffsll(static_cast<unsigned long long>(hit)) - 1];
+          break;
+        }
+        run = shfl_u64(incl, kWave - 1);
+      }
+      if (lane == 0) {
+        sh.pick = found;
+        sh.acc = run;
+      }
+    }
+    __syncthreads();
+    pick = sh.pick;
+    acc = sh.acc;
+    __syncthreads();
+    if (pick != kUnseen) break;
+  }
+  return pick;
+}
+
 template <int BLOCK, int UNROLL, bool LDS_BITS>
 __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   __shared__ SampleShared<BLOCK> sh;
@@ -147,6 +270,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   using Bits = typename std::conditional<LDS_BITS, BitsLds, BitsHbm>::type;
   Bits bits{LDS_BITS ? dyn_bits : a.bits + slot * a.bit_words};
   const uint64_t lane_lt = (1ull << lane) - 1ull;
+  const uint64_t cap = a.c_bits >= 64 ? ~0ull : (1ull << a.c_bits);
 
   if (LDS_BITS)
     for (uint32_t i = tid; i < a.bit_words; i += BLOCK) dyn_bits[i] = 0;
@@ -174,30 +298,128 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       bits.set(s);
       sh.qlen = 1;
     }
+
+    // Rings around t: R1 = in(t), the pairs (w in R1, u in in(w)) and, if
+    // the cone is small enough, in(u) for those u.  poff[i] = number of
+    // pairs before R1's i-th entry.
+    const uint32_t tb = a.in_ptr[t], te = a.in_ptr[t + 1];
+    const uint32_t dt = te - tb;
+    const bool rings = dt <= kRingCache;
+    uint32_t pairs = 0;
+    uint64_t cone = ~0ull;   // CSR entries scanned by a 3-hop test (~0: no 3-hop test)
+    if (rings) {
+      for (uint32_t cb = 0; cb < dt; cb += BLOCK) {
+        const uint32_t i = cb + tid;
+        uint32_t dw = 0;
+        if (i < dt) {
+          const uint32_t w = a.in_idx[tb + i];
+          const uint32_t r0 = a.in_ptr[w];
+          dw = a.in_ptr[w + 1] - r0;
+          sh.rw[i] = w;
+          sh.rrs[i] = r0;
+        }
+        uint32_t tot;
+        const uint32_t o = block_excl_scan_u32<BLOCK>(dw, &tot, sh.scan);
+        if (i < dt) sh.poff[i] = pairs + o;
+        pairs += tot;
+      }
+      n_arcs += dt;
+      if (pairs <= kPairMax) {
+        __syncthreads();
+        uint64_t c = 0;
+        for (uint32_t p = tid; p < pairs; p += BLOCK) {
+          const int i = ring_of(sh.poff, dt, p);
+          const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
+          c += a.in_ptr[u + 1] - a.in_ptr[u];
+        }
+        cone = block_sum_u64<BLOCK>(c, sh.red);
+        n_arcs += pairs;
+      }
+    }
+    // out-arcs of the current frontier: the cost of expanding it
+    uint64_t fcost = a.row_ptr[s + 1] - a.row_ptr[s];
     __syncthreads();
 
     uint32_t lb = 0, le = 1, L = 0, d = kUnseen;
-    uint64_t sumL = 1;             // S_L: sum of the level-L counts (saturating)
-    uint64_t w_short = 0;          // nonzero: last-level shortcut taken, = W of the first step
-    const uint64_t cap = a.c_bits >= 64 ? ~0ull : (1ull << a.c_bits);
-    const uint32_t tb = a.in_ptr[t], te = a.in_ptr[t + 1];
+    uint64_t sumL = 1;        // S_L: sum of the level-L counts (saturating)
+    uint32_t shortcut = 0;    // 2 or 3: levels L+1 (and L+2) were not produced
+    uint64_t w_short = 0;     // W of the first backtrack step when shortcut
     for (;;) {
-      // visited in-neighbour of t?  (visited = level <= L, and any such
-      // neighbour is at level L, else an earlier check would have fired)
+      // (1) a visited in-neighbour of t: it is at level L (an earlier check
+      //     would have fired otherwise), so d = L + 1
       int found = 0;
-      n_arcs += te - tb;
+      n_arcs += dt;
       for (uint32_t e = tb + tid; e < te; e += BLOCK)
         if (bits.test(a.in_idx[e])) found = 1;
       if (__syncthreads_or(found)) {
         d = L + 1;
         break;
       }
-      if (sumL < cap) {
-        // in-neighbours w of t at level L+1: raw_w = sum of sigma' over
-        // w's in-neighbours at level L (one wave per w)
+      if (rings) {
+        // (2) pairs (w, u): a visited u is at level L (w is unvisited, so a
+        //     lower level would have put w in a produced level), hence w at
+        //     L+1 and d = L+2; ring_a[i] = sum of sigma'_u over visited u,
+        //     the raw count of w_i
+        for (uint32_t i = tid; i < dt; i += BLOCK) {
+          sh.ring_a[i] = 0;
+          sh.ring_b[i] = 0;
+        }
+        __syncthreads();
+        int hit2 = 0;
+        for (uint32_t p = tid; p < pairs; p += BLOCK) {
+          const int i = ring_of(sh.poff, dt, p);
+          const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
+          if (bits.test(u)) {
+            hit2 = 1;
+            atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_a[i]),
+                      static_cast<unsigned long long>(ld_u64(sig_of(rec, u))));
+          }
+        }
+        n_arcs += pairs;
+        if (__syncthreads_or(hit2)) {
+          if (sumL < cap) {
+            // no count of level L+1 can need a shift (each <= S_L < 2^C)
+            d = L + 2;
+            shortcut = 2;
+            break;
+          }
+        } else {
+          // (3) cone: an unvisited u with visited in-neighbours is at L+1
+          //     (they are all at L), its w at L+2 and d = L+3.  Only when the
+          //     counts of levels L+1 and L+2 cannot need a shift (level L+1
+          //     counts <= S_L, level L+2 counts <= S_{L+1} <= S_L * max
+          //     out-degree) and expanding level L would cost more.
+          const uint64_t bound = (a.max_out_deg && sumL > ~0ull / a.max_out_deg) ? ~0ull : sumL * a.max_out_deg;
+          if (cone != ~0ull && sumL < cap && bound < cap && cone <= kConeRatio * fcost) {
+            int hit3 = 0;
+            for (uint32_t cb = 0; cb < pairs; cb += BLOCK) {
+              const uint32_t p = cb + tid;
+              uint32_t u = kUnseen;
+              int i = 0;
+              if (p < pairs) {
+                i = ring_of(sh.poff, dt, p);
+                u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
+              }
+              raw_counts_chunk<BLOCK, UNROLL>(a, bits, rec, u, sh, n_arcs);
+              const uint64_t raw = sh.sg[tid];
+              if (raw) {
+                hit3 = 1;
+                atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_b[i]), static_cast<unsigned long long>(raw));
+              }
+              __syncthreads();
+            }
+            if (__syncthreads_or(hit3)) {
+              d = L + 3;
+              shortcut = 3;
+              break;
+            }
+          }
+        }
+      } else if (sumL < cap) {
+        // t with more in-neighbours than the ring cache: in-neighbours w of t
+        // at level L+1, raw_w = sum of sigma' over w's in-neighbours at level L
         uint64_t wsum = 0, wscan = 0;
         for (uint32_t e = tb + wid; e < te; e += BLOCK / kWave) {
-          // (w is unvisited: the check above found no visited in-neighbour of t)
           const uint32_t w = a.in_idx[e];
           const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
           uint64_t x = 0;
@@ -205,9 +427,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
             const uint32_t u = a.in_idx[f];
             if (bits.test(u) && ld_u32(lvl_of(rec, u)) == L) x += ld_u64(sig_of(rec, u));
           }
-          const uint64_t raw = wave_sum_u64(x);
-          if (lane == 0 && e - tb < kRawCache) sh.raw[e - tb] = raw;
-          wsum += raw;
+          wsum += wave_sum_u64(x);
           wscan += ue - ub;
         }
         if (lane != 0) {
@@ -218,6 +438,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         n_arcs += block_sum_u64<BLOCK>(wscan, sh.red);
         if (wsum) {
           d = L + 2;
+          shortcut = 2;
           w_short = wsum;
           break;
         }
@@ -309,10 +530,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       mx = block_max_u64<BLOCK>(mx, sh.red);
       const uint32_t bl = bitlen64(mx);
       const uint32_t shift = bl > a.c_bits ? bl - a.c_bits : 0u;
-      uint64_t ssum = 0;
+      uint64_t ssum = 0, ncost = 0;
       for (uint32_t i = le + tid; i < ne; i += BLOCK) {
         const uint32_t v = ld_u32(&q[i]);
         bits.set(v);
+        ncost += a.row_ptr[v + 1] - a.row_ptr[v];
         if (shift) {
           uint64_t x = ld_u64(sig_of(rec, v)) >> shift;
           x = x ? x : 1ull;
@@ -322,144 +544,182 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       }
       if (!shift) ssum = added;
       sumL = block_sat_sum<BLOCK>(ssum, sh.red);   // contains the barrier closing the level
+      fcost = block_sum_u64<BLOCK>(ncost, sh.red);
       lb = le;
       le = ne;
       L = nl;
     }
 
-    // backtrack (wave 0): from v = t, pick a predecessor w at level(v) - 1
-    // with probability sigma'_w / W by scanning in-neighbours in ascending
-    // order, until level 1.
+    // backtrack: from v = t, pick a predecessor w at level(v) - 1 with
+    // probability sigma'_w / W, scanning in-neighbours in ascending order,
+    // until level 1.  Steps through unproduced levels (shortcut 2 or 3) run
+    // on the whole workgroup; the remaining steps on wave 0.
     const uint32_t len = (d != kUnseen && d >= 2) ? d - 1 : 0u;
+    if (tid == 0) {
+      sh.base = len ? atomicAdd(reinterpret_cast<unsigned long long*>(a.stage_used),
+                                static_cast<unsigned long long>(len))
+                    : 0ull;
+    }
+    uint32_t v = t, dv = len ? d : 0u, written = 0;   // no backtrack when t is unreachable or adjacent
+    if (shortcut && rings) {
+      // step from t through level d-1 with weights ring_a (shortcut 2) or
+      // ring_b (shortcut 3), summed here (all threads draw the same r)
+      __syncthreads();
+      uint64_t* wts = shortcut == 2 ? sh.ring_a : sh.ring_b;
+      uint64_t W = 0;
+      for (uint32_t i = 0; i < dt; ++i) W += wts[i];
+      const uint64_t r = bounded(st, W);
+      if (wid == 0) {
+        uint32_t found = kUnseen;
+        uint64_t run = 0;
+        for (uint32_t c = 0; c < dt; c += kWave) {
+          const uint32_t i = c + lane;
+          const uint64_t x = i < dt ? wts[i] : 0ull;
+          const uint64_t incl = run + wave_incl_scan_u64(x);
+          const uint64_t hit = __ballot(incl > r);
+          if (hit) {
+            found = a.in_idx[tb + c + __ffsll(static_cast<unsigned long long>(hit)) - 1];
+            break;
+          }
+          run = shfl_u64(incl, kWave - 1);
+        }
+        if (lane == 0) sh.pick = found;
+      }
+      __syncthreads();
+      uint32_t pick = sh.pick;
+      __syncthreads();
+      if (pick != kUnseen && tid == 0 && sh.base < a.stage_cap) a.stage[sh.base] = pick;
+      written = 1;
+      v = pick;
+      dv = d - 1;
+      if (pick != kUnseen && shortcut == 3) {
+        // step from w (level L+2) through level L+1: weight raw_u, whose sum
+        // is the ring_b entry of w, i.e. sigma'_w
+        uint64_t W2 = 0;
+        for (uint32_t i = 0; i < dt; ++i)
+          if (sh.rw[i] == pick) W2 = sh.ring_b[i];
+        const uint64_t r2 = bounded(st, W2);
+        pick = pick_through_ring<BLOCK, UNROLL>(a, bits, rec, pick, r2, sh, n_arcs);
+        if (pick != kUnseen && tid == 0 && sh.base + 1 < a.stage_cap) a.stage[sh.base + 1] = pick;
+        written = 2;
+        v = pick;
+        dv = d - 2;
+      }
+      if (pick == kUnseen) {
+        if (tid == 0) atomicOr(a.flags, kErrBacktrack);
+        dv = 0;
+      }
+    } else if (shortcut) {
+      // shortcut without the ring cache (t has many in-neighbours): the
+      // first step recomputes raw_w on wave 0
+      __syncthreads();
+      if (wid == 0) {
+        const uint64_t r = bounded(st, w_short);
+        uint64_t acc = 0;
+        uint32_t pick = kUnseen;
+        for (uint32_t e = tb; e < te; ++e) {
+          const uint32_t w = a.in_idx[e];
+          const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
+          uint64_t x = 0;
+          for (uint32_t f = ub + lane; f < ue; f += kWave) {
+            const uint32_t u = a.in_idx[f];
+            if (bits.test(u) && ld_u32(lvl_of(rec, u)) == L) x += ld_u64(sig_of(rec, u));
+          }
+          acc += wave_sum_u64(x);
+          if (acc > r) {
+            pick = w;
+            break;
+          }
+        }
+        if (pick == kUnseen) {
+          if (lane == 0) atomicOr(a.flags, kErrBacktrack);
+          dv = 0;
+        } else {
+          if (lane == 0 && sh.base < a.stage_cap) a.stage[sh.base] = pick;
+          written = 1;
+          v = pick;
+          dv = d - 1;
+        }
+      }
+    } else {
+      __syncthreads();
+    }
     if (wid == 0) {
-      uint64_t base = 0;
-      if (len) {
-        if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(a.stage_used),
-                                        static_cast<unsigned long long>(len));
-        base = shfl_u64(base, 0);
-        uint32_t v = t, dv = d;
-        uint32_t written = 0;
-        if (w_short) {
-          // first step through the unproduced level L+1: in-neighbours w of t
-          // in ascending order, weight raw_w = sum of level-L counts over
-          // w's in-neighbours (equal to the normalised count, see above)
-          const uint64_t r = bounded(st, w_short);
-          uint32_t pick = kUnseen;
-          if (te - tb <= kRawCache) {
+      const uint64_t base = sh.base;
+      while (dv >= 2) {
+        const uint32_t want = dv - 1;
+        const uint32_t vb = a.in_ptr[v], ve = a.in_ptr[v + 1];
+        uint32_t pick = kUnseen;
+        if (ve - vb <= 4 * kWave) {
+          // one pass: candidates held in registers between the sum and the pick
+          uint64_t xs[4];
+          uint32_t ws[4];
+          uint64_t W = 0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t e = vb + k * kWave + lane;
+            xs[k] = 0;
+            ws[k] = 0;
+            if (e < ve) {
+              const uint32_t w = a.in_idx[e];
+              ws[k] = w;
+              if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) xs[k] = ld_u64(sig_of(rec, w));
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) W += wave_sum_u64(xs[k]);
+          if (W) {
+            const uint64_t r = bounded(st, W);
             uint64_t acc = 0;
-            for (uint32_t cb = 0; cb < te - tb; cb += kWave) {
-              const uint32_t i = cb + lane;
-              const uint64_t x = i < te - tb ? sh.raw[i] : 0ull;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const uint64_t incl = acc + wave_incl_scan_u64(xs[k]);
+              const uint64_t hit = __ballot(incl > r);
+              if (hit && pick == kUnseen)
+                pick = __shfl(ws[k], __ffsll(static_cast<unsigned long long>(hit)) - 1, kWave);
+              acc = shfl_u64(incl, kWave - 1);
+            }
+          }
+        } else {
+          uint64_t W = 0;
+          for (uint32_t cb = vb; cb < ve; cb += kWave) {
+            const uint32_t e = cb + lane;
+            uint64_t x = 0;
+            if (e < ve) {
+              const uint32_t w = a.in_idx[e];
+              if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) x = ld_u64(sig_of(rec, w));
+            }
+            W += wave_sum_u64(x);
+          }
+          if (W) {
+            const uint64_t r = bounded(st, W);
+            uint64_t acc = 0;
+            for (uint32_t cb = vb; cb < ve; cb += kWave) {
+              const uint32_t e = cb + lane;
+              uint64_t x = 0;
+              uint32_t w = 0;
+              if (e < ve) {
+                w = a.in_idx[e];
+                if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) x = ld_u64(sig_of(rec, w));
+              }
               const uint64_t incl = acc + wave_incl_scan_u64(x);
               const uint64_t hit = __ballot(incl > r);
               if (hit) {
-                pick = a.in_idx[tb + cb + __ffsll(static_cast<unsigned long long>(hit)) - 1];
+                pick = __shfl(w, __ffsll(static_cast<unsigned long long>(hit)) - 1, kWave);
                 break;
               }
               acc = shfl_u64(incl, kWave - 1);
             }
-          } else {
-            uint64_t acc = 0;
-            for (uint32_t e = tb; e < te; ++e) {
-              const uint32_t w = a.in_idx[e];
-              const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
-              uint64_t x = 0;
-              for (uint32_t f = ub + lane; f < ue; f += kWave) {
-                const uint32_t u = a.in_idx[f];
-                if (bits.test(u) && ld_u32(lvl_of(rec, u)) == L) x += ld_u64(sig_of(rec, u));
-              }
-              acc += wave_sum_u64(x);
-              if (acc > r) {
-                pick = w;
-                break;
-              }
-            }
-          }
-          if (pick == kUnseen) {
-            if (lane == 0) atomicOr(a.flags, kErrBacktrack);
-            dv = 0;
-          } else {
-            if (lane == 0 && base < a.stage_cap) a.stage[base] = pick;
-            written = 1;
-            v = pick;
-            dv = d - 1;
           }
         }
-        while (dv >= 2) {
-          const uint32_t want = dv - 1;
-          const uint32_t vb = a.in_ptr[v], ve = a.in_ptr[v + 1];
-          uint32_t pick = kUnseen;
-          if (ve - vb <= 4 * kWave) {
-            // one pass: candidates held in registers between the sum and the pick
-            uint64_t xs[4];
-            uint32_t ws[4];
-            uint64_t W = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const uint32_t e = vb + k * kWave + lane;
-              xs[k] = 0;
-              ws[k] = 0;
-              if (e < ve) {
-                const uint32_t w = a.in_idx[e];
-                ws[k] = w;
-                if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) xs[k] = ld_u64(sig_of(rec, w));
-              }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) W += wave_sum_u64(xs[k]);
-            if (W) {
-              const uint64_t r = bounded(st, W);
-              uint64_t acc = 0;
-#pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                const uint64_t incl = acc + wave_incl_scan_u64(xs[k]);
-                const uint64_t hit = __ballot(incl > r);
-                if (hit && pick == kUnseen)
-                  pick = __shfl(ws[k], __ffsll(static_cast<unsigned long long>(hit)) - 1, kWave);
-                acc = shfl_u64(incl, kWave - 1);
-              }
-            }
-          } else {
-            uint64_t W = 0;
-            for (uint32_t cb = vb; cb < ve; cb += kWave) {
-              const uint32_t e = cb + lane;
-              uint64_t x = 0;
-              if (e < ve) {
-                const uint32_t w = a.in_idx[e];
-                if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) x = ld_u64(sig_of(rec, w));
-              }
-              W += wave_sum_u64(x);
-            }
-            if (W) {
-              const uint64_t r = bounded(st, W);
-              uint64_t acc = 0;
-              for (uint32_t cb = vb; cb < ve; cb += kWave) {
-                const uint32_t e = cb + lane;
-                uint64_t x = 0;
-                uint32_t w = 0;
-                if (e < ve) {
-                  w = a.in_idx[e];
-                  if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) x = ld_u64(sig_of(rec, w));
-                }
-                const uint64_t incl = acc + wave_incl_scan_u64(x);
-                const uint64_t hit = __ballot(incl > r);
-                if (hit) {
-                  pick = __shfl(w, __ffsll(static_cast<unsigned long long>(hit)) - 1, kWave);
-                  break;
-                }
-                acc = shfl_u64(incl, kWave - 1);
-              }
-            }
-          }
-          if (pick == kUnseen) {
-            if (lane == 0) atomicOr(a.flags, kErrBacktrack);
-            break;
-          }
-          if (lane == 0 && base + written < a.stage_cap) a.stage[base + written] = pick;
-          ++written;
-          v = pick;
-          --dv;
+        if (pick == kUnseen) {
+          if (lane == 0) atomicOr(a.flags, kErrBacktrack);
+          break;
         }
+        if (lane == 0 && base + written < a.stage_cap) a.stage[base + written] = pick;
+        ++written;
+        v = pick;
+        --dv;
       }
       if (lane == 0) {
         a.stage_pos[idx] = base;
@@ -611,6 +871,7 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     SampleArgs a;
     a.n = g->n;
     a.c_bits = g->count_bits;
+    a.max_out_deg = g->max_out_degree;
     a.row_ptr = g->row_ptr;
     a.col_idx = g->col_idx;
     a.in_ptr = g->in_ptr;

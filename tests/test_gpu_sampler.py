@@ -37,6 +37,7 @@ CASES = {
     "rmat12": (lambda: inputs.rmat_graph(12, 8, seed=3), 0),
     "star3000": (lambda: star(3000), 0),
     "chain1500": (lambda: chain(1500), 0),
+    "dense1200": (lambda: random_digraph(1200, 0.5, 8), 0),   # every target has > 512 in-neighbours
     "pair": (lambda: inputs.from_edges(2, [0], [1], directed=False), 0),
     "empty2": (lambda: inputs.from_edges(2, [], [], directed=True), 0),
 }
@@ -71,7 +72,7 @@ def test_sampler_bit_exact(ctx, name):
     check_batch(ctx, g, cbo, seed=7, inst=1, first=0, count=count)
 
 
-@pytest.mark.parametrize("name", ["ba2000", "grid40_c8", "rmat12", "star3000", "chain1500"])
+@pytest.mark.parametrize("name", ["ba2000", "grid40_c8", "rmat12", "star3000", "chain1500", "dense1200"])
 def test_sampler_hbm_bitmap_variant_bit_exact(ctx, name, monkeypatch):
     # graphs whose visited bitmap does not fit in LDS use the HBM-bitmap
     # kernel; force it here on small graphs
