@@ -45,6 +45,7 @@
 // level is produced and normalised as usual.  Both routes give the same
 // counts, hence the same hyperedge.
 #include <stdlib.h>
+#include <string.h>
 
 #include <type_traits>
 
@@ -81,11 +82,14 @@ struct SampleArgs {
   uint64_t* stats;       // [0] arcs scanned, [1] nodes visited (accumulated)
 };
 
-// Ring limits: t with at most kRingCache in-neighbours gets the 2-hop test
+// Ring limits: t with at most Ring<BLOCK>::kCache in-neighbours gets the 2-hop test
 // on the pairs (w in in(t), u in in(w)); the 3-hop test also needs at most
 // kPairMax pairs, and runs at a level only when expanding that level would
 // scan at least 1/kConeRatio of the cone's CSR entries.
-constexpr uint32_t kRingCache = 512;
+template <int BLOCK>
+struct Ring {
+  static constexpr uint32_t kCache = BLOCK >= 512 ? 512u : 256u;
+};
 constexpr uint32_t kPairMax = 65536;
 constexpr uint64_t kConeRatio = 3;
 
@@ -102,11 +106,11 @@ struct SampleShared {
   uint64_t sg[BLOCK];
   uint32_t scan[BLOCK / kWave + 1];
   uint64_t red[BLOCK / kWave];
-  uint32_t poff[kRingCache];   // pair offsets of t's in-neighbours
-  uint32_t rw[kRingCache];     // t's in-neighbours w
-  uint32_t rrs[kRingCache];    // in_ptr[w]
-  uint64_t ring_a[kRingCache];  // per in-neighbour w of t: level-(L+1) count / weights of a pick
-  uint64_t ring_b[kRingCache];  // per in-neighbour w of t: level-(L+2) count
+  uint32_t poff[Ring<BLOCK>::kCache];   // pair offsets of t's in-neighbours
+  uint32_t rw[Ring<BLOCK>::kCache];     // t's in-neighbours w
+  uint32_t rrs[Ring<BLOCK>::kCache];    // in_ptr[w]
+  uint64_t ring_a[Ring<BLOCK>::kCache];  // per in-neighbour w of t: level-(L+1) count
+  uint64_t ring_b[Ring<BLOCK>::kCache];  // per in-neighbour w of t: level-(L+2) count
   uint64_t acc;
   uint64_t base;
   uint32_t pick;
@@ -304,7 +308,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
     // pairs before R1's i-th entry.
     const uint32_t tb = a.in_ptr[t], te = a.in_ptr[t + 1];
     const uint32_t dt = te - tb;
-    const bool rings = dt <= kRingCache;
+    const bool rings = dt <= Ring<BLOCK>::kCache;
     uint32_t pairs = 0;
     uint64_t cone = ~0ull;   // CSR entries scanned by a 3-hop test (~0: no 3-hop test)
     if (rings) {
@@ -770,20 +774,30 @@ __global__ void k_stage_gather(uint32_t count, const uint64_t* stage_pos, const 
 // CU (the bitmap takes most of the LDS); the HBM-bitmap variant runs
 // 512-thread workgroups, several per CU.
 constexpr int kLdsBlock = 1024;
-constexpr int kHbmBlock = 512;
 constexpr int kUnroll = 4;
-constexpr uint32_t kMaxSlots = 2048;
+constexpr uint32_t kMaxSlots = 8192;
+constexpr size_t kSlotMemCap = size_t(48) << 30;
 
 #define CENTRA_LDS_KERNEL k_sample_paths<kLdsBlock, kUnroll, true>
-#define CENTRA_HBM_KERNEL k_sample_paths<kHbmBlock, kUnroll, false>
 
 struct SamplePlan {
   bool lds_bits;
+  int block;         // workgroup size of the HBM-bitmap variant
   uint32_t bit_words;
   size_t dyn_lds;
   uint32_t resident;   // workgroups resident at once = BFS slots
 };
 
+template <int BLOCK>
+static hipError_t hbm_occupancy(int* per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sample_paths<BLOCK, kUnroll, false>, BLOCK, 0);
+}
+
+// Variant choice.  Default: the HBM-bitmap kernel with 128-thread
+// workgroups (many concurrent BFSs per CU hide the latency of the short,
+// dependent steps of each BFS).  CENTRA_SAMPLER_VARIANT selects another:
+// "lds" (LDS bitmap, 1024 threads, when the bitmap fits), "hbm512",
+// "hbm256", "hbm128", "hbm64".
 static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
   SamplePlan p{};
   p.bit_words = (n + 31) / 32;
@@ -793,23 +807,31 @@ static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
     cus = 256;
   const size_t dyn = size_t(p.bit_words) * 4;
-  // CENTRA_SAMPLER_HBM_BITMAP=1 forces the HBM-bitmap variant (tests of that path on small graphs)
-  const char* force = getenv("CENTRA_SAMPLER_HBM_BITMAP");
-  p.lds_bits = sizeof(SampleShared<kLdsBlock>) + dyn <= size_t(max_lds) && !(force && force[0] == '1');
+  const char* env = getenv("CENTRA_SAMPLER_VARIANT");
+  const char* v = env ? env : "hbm128";
+  p.block = 128;
+  if (!strcmp(v, "hbm512")) p.block = 512;
+  if (!strcmp(v, "hbm256")) p.block = 256;
+  if (!strcmp(v, "hbm64")) p.block = 64;
+  p.lds_bits = !strcmp(v, "lds") && sizeof(SampleShared<kLdsBlock>) + dyn <= size_t(max_lds);
   int per_cu = 0;
+  hipError_t e = hipSuccess;
   if (p.lds_bits) {
     p.dyn_lds = dyn;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&CENTRA_LDS_KERNEL),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, CENTRA_LDS_KERNEL, kLdsBlock, dyn) != hipSuccess)
-      per_cu = 1;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, CENTRA_LDS_KERNEL, kLdsBlock, dyn);
   } else {
     p.dyn_lds = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, CENTRA_HBM_KERNEL, kHbmBlock, 0) != hipSuccess)
-      per_cu = 1;
+    switch (p.block) {
+      case 512: e = hbm_occupancy<512>(&per_cu); break;
+      case 256: e = hbm_occupancy<256>(&per_cu); break;
+      case 64: e = hbm_occupancy<64>(&per_cu); break;
+      default: e = hbm_occupancy<128>(&per_cu); break;
+    }
   }
+  if (e != hipSuccess || per_cu <= 0) per_cu = 1;
   (void)hipGetLastError();
-  if (per_cu <= 0) per_cu = 1;
   const uint64_t r = uint64_t(cus) * uint64_t(per_cu);
   p.resident = r > kMaxSlots ? kMaxSlots : static_cast<uint32_t>(r);
   return p;
@@ -817,12 +839,21 @@ static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
 
 static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, bool hbm_bits, hipStream_t s) {
   const uint32_t words = (g->n + 31) / 32;
+  {
+    // never ask for more slots than kSlotMemCap holds
+    const size_t per = size_t(g->n) * (16 + 4) + (hbm_bits ? size_t(words) * 4 : 0);
+    const size_t most = kSlotMemCap / (per ? per : 1);
+    if (want > most) want = most ? static_cast<uint32_t>(most) : 1u;
+  }
   if (ctx->slots >= want && ctx->slot_n >= g->n && (!hbm_bits || ctx->slot_bits.bytes >= size_t(ctx->slots) * words * 4))
     return CENTRA_OK;
   uint32_t slots = want > ctx->slots ? want : ctx->slots;
   const uint32_t n = g->n > ctx->slot_n ? g->n : ctx->slot_n;
   const uint32_t nw = (n + 31) / 32;
   const size_t per_slot = size_t(n) * (16 + 4) + (hbm_bits ? size_t(nw) * 4 : 0);
+  // at most kSlotMemCap of slot state (or the budget, if smaller)
+  if (size_t(slots) * per_slot > kSlotMemCap) slots = static_cast<uint32_t>(kSlotMemCap / per_slot);
+  if (slots == 0) slots = 1;
   // shrink the slot count if the budget cannot hold all of them
   for (;;) {
     const size_t need = size_t(slots) * per_slot;
@@ -898,8 +929,14 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
     if (plan.lds_bits)
       hipLaunchKernelGGL(CENTRA_LDS_KERNEL, dim3(grid), dim3(kLdsBlock), plan.dyn_lds, s, a);
+    else if (plan.block == 512)
+      hipLaunchKernelGGL((k_sample_paths<512, kUnroll, false>), dim3(grid), dim3(512), 0, s, a);
+    else if (plan.block == 256)
+      hipLaunchKernelGGL((k_sample_paths<256, kUnroll, false>), dim3(grid), dim3(256), 0, s, a);
+    else if (plan.block == 64)
+      hipLaunchKernelGGL((k_sample_paths<64, kUnroll, false>), dim3(grid), dim3(64), 0, s, a);
     else
-      hipLaunchKernelGGL(CENTRA_HBM_KERNEL, dim3(grid), dim3(kHbmBlock), 0, s, a);
+      hipLaunchKernelGGL((k_sample_paths<128, kUnroll, false>), dim3(grid), dim3(128), 0, s, a);
     CENTRA_HIP(ctx, hipGetLastError());
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[7], s));
     uint64_t host_ctr[4] = {0, 0, 0, 0};   // work, used, arcs, nodes

@@ -72,14 +72,16 @@ def test_sampler_bit_exact(ctx, name):
     check_batch(ctx, g, cbo, seed=7, inst=1, first=0, count=count)
 
 
+@pytest.mark.parametrize("variant", ["lds", "hbm512", "hbm256", "hbm64"])
 @pytest.mark.parametrize("name", ["ba2000", "grid40_c8", "rmat12", "star3000", "chain1500", "dense1200"])
-def test_sampler_hbm_bitmap_variant_bit_exact(ctx, name, monkeypatch):
-    # graphs whose visited bitmap does not fit in LDS use the HBM-bitmap
-    # kernel; force it here on small graphs
-    monkeypatch.setenv("CENTRA_SAMPLER_HBM_BITMAP", "1")
+def test_sampler_variants_bit_exact(ctx, name, variant, monkeypatch):
+    # every launch shape of the sampler (LDS bitmap with 1024-thread
+    # workgroups; HBM bitmap with 512/256/64; the default 128 runs in the
+    # tests above) gives the same hyperedges
+    monkeypatch.setenv("CENTRA_SAMPLER_VARIANT", variant)
     build, cbo = CASES[name]
     g = build()
-    say(f"sampler parity (HBM bitmap) {name}")
+    say(f"sampler parity ({variant}) {name}")
     check_batch(ctx, g, cbo, seed=9, inst=0, first=17, count=2500)
 
 
