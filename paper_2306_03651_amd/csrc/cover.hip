@@ -19,39 +19,117 @@
 
 namespace centra {
 
-__global__ void k_count_deg(const uint32_t* he_nodes, uint64_t I, uint32_t n, uint32_t* deg, uint32_t* flags) {
-  for (uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; e < I; e += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t u = he_nodes[e];
-    if (u < n)
-      atomicAdd(&deg[u], 1u);
-    else
-      atomicOr(flags, kErrNodeRange);
-  }
-}
-
 __global__ void k_copy_u64(const uint64_t* src, uint64_t* dst, size_t n) {
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
     dst[i] = src[i];
-}
-
-__global__ void k_scatter_inc(const uint64_t* he_off, const uint32_t* he_nodes, uint64_t m, uint32_t n,
-                              uint64_t* cursor, uint32_t* inc, uint32_t* inc_node) {
-  for (uint64_t s = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; s < m; s += uint64_t(gridDim.x) * blockDim.x) {
-    const uint64_t b = he_off[s], e = he_off[s + 1];
-    for (uint64_t x = b; x < e; ++x) {
-      const uint32_t u = he_nodes[x];
-      if (u >= n) continue;
-      const uint64_t p = atomicAdd(reinterpret_cast<unsigned long long*>(&cursor[u]), 1ull);
-      inc[p] = static_cast<uint32_t>(s);
-      inc_node[p] = u;
-    }
-  }
 }
 
 static unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 16384) {
   uint64_t g = (n + block - 1) / block;
   if (g > cap) g = cap;
   return g ? static_cast<unsigned>(g) : 1u;
+}
+
+// Per-workgroup aggregation of integer updates to a node-indexed array in
+// an LDS hash table (open addressing, linear probing over kAggProbe slots).
+// Hub nodes appear in a large fraction of the hyperedges; aggregating turns
+// their per-hyperedge atomics into one global atomic per workgroup.  A node
+// that finds no slot falls back to a direct global atomic.
+constexpr uint32_t kAggBits = 11;
+constexpr uint32_t kAggSize = 1u << kAggBits;
+constexpr uint32_t kAggProbe = 8;
+
+struct AggTable {
+  uint32_t key[kAggSize];
+  uint32_t cnt[kAggSize];
+};
+
+__device__ __forceinline__ void agg_init(AggTable& t) {
+  for (uint32_t i = threadIdx.x; i < kAggSize; i += blockDim.x) {
+    t.key[i] = kUnseen;
+    t.cnt[i] = 0;
+  }
+}
+
+// Adds 1 for node v; returns false if the table has no slot for v.
+__device__ __forceinline__ bool agg_add(AggTable& t, uint32_t v) {
+  const uint32_t h = (v * 0x9E3779B1u) >> (32 - kAggBits);
+  for (uint32_t p = 0; p < kAggProbe; ++p) {
+    const uint32_t slot = (h + p) & (kAggSize - 1);
+    uint32_t k = t.key[slot];
+    if (k == kUnseen) k = atomicCAS(&t.key[slot], kUnseen, v);
+    if (k == kUnseen || k == v) {
+      atomicAdd(&t.cnt[slot], 1u);
+      return true;
+    }
+  }
+  return false;
+}
+
+// Finds node v's slot (no insert); kUnseen if v has none.
+__device__ __forceinline__ uint32_t agg_find(const AggTable& t, uint32_t v) {
+  const uint32_t h = (v * 0x9E3779B1u) >> (32 - kAggBits);
+  for (uint32_t p = 0; p < kAggProbe; ++p) {
+    const uint32_t slot = (h + p) & (kAggSize - 1);
+    if (t.key[slot] == v) return slot;
+    if (t.key[slot] == kUnseen) return kUnseen;
+  }
+  return kUnseen;
+}
+
+// Transpose with per-workgroup range reservation: pass 1 counts this
+// workgroup's entries per node, one atomic per node reserves a range of
+// the node's row, pass 2 places the entries (the same grid-stride order in
+// both passes).  Nodes without a slot reserve per entry.
+__global__ void k_scatter_inc_agg(const uint64_t* he_off, const uint32_t* he_nodes, uint64_t m, uint32_t n,
+                                  uint64_t* cursor, uint32_t* inc, uint32_t* inc_node) {
+  __shared__ AggTable tab;
+  __shared__ uint64_t base[kAggSize];
+  agg_init(tab);
+  __syncthreads();
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  const uint64_t s0 = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
+  for (uint64_t s = s0; s < m; s += stride)
+    for (uint64_t x = he_off[s]; x < he_off[s + 1]; ++x) {
+      const uint32_t u = he_nodes[x];
+      if (u < n) (void)agg_add(tab, u);
+    }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kAggSize; i += blockDim.x) {
+    if (tab.key[i] != kUnseen)
+      base[i] = atomicAdd(reinterpret_cast<unsigned long long*>(&cursor[tab.key[i]]),
+                          static_cast<unsigned long long>(tab.cnt[i]));
+    tab.cnt[i] = 0;
+  }
+  __syncthreads();
+  for (uint64_t s = s0; s < m; s += stride)
+    for (uint64_t x = he_off[s]; x < he_off[s + 1]; ++x) {
+      const uint32_t u = he_nodes[x];
+      if (u >= n) continue;
+      const uint32_t slot = agg_find(tab, u);
+      const uint64_t p = slot != kUnseen
+                             ? base[slot] + atomicAdd(&tab.cnt[slot], 1u)
+                             : atomicAdd(reinterpret_cast<unsigned long long*>(&cursor[u]), 1ull);
+      inc[p] = static_cast<uint32_t>(s);
+      inc_node[p] = u;
+    }
+}
+
+__global__ void k_count_deg_agg(const uint32_t* he_nodes, uint64_t I, uint32_t n, uint32_t* deg, uint32_t* flags) {
+  __shared__ AggTable tab;
+  agg_init(tab);
+  __syncthreads();
+  for (uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; e < I; e += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t u = he_nodes[e];
+    if (u >= n) {
+      atomicOr(flags, kErrNodeRange);
+      continue;
+    }
+    if (!agg_add(tab, u)) atomicAdd(&deg[u], 1u);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kAggSize; i += blockDim.x)
+    if (tab.key[i] != kUnseen) atomicAdd(&deg[tab.key[i]], tab.cnt[i]);
 }
 
 int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes,
@@ -69,12 +147,14 @@ int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_
   uint64_t* off = static_cast<uint64_t*>(ctx->inc_off.ptr);
   uint64_t* cur = static_cast<uint64_t*>(ctx->inc_cursor.ptr);
   fill_u32(deg, 0, n, s);
-  if (I) hipLaunchKernelGGL(k_count_deg, dim3(grid_for(I, 256)), dim3(256), 0, s, he_nodes, I, n, deg, ctx->d_flags);
+  if (I)
+    hipLaunchKernelGGL(k_count_deg_agg, dim3(grid_for(I, 256, 2048)), dim3(256), 0, s, he_nodes, I, n, deg,
+                       ctx->d_flags);
   CENTRA_HIP(ctx, hipGetLastError());
   if ((rc = excl_scan_u32_to_u64(ctx, deg, off, n, s))) return rc;
   hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, off, cur, size_t(n));
   if (m)
-    hipLaunchKernelGGL(k_scatter_inc, dim3(grid_for(m, 256)), dim3(256), 0, s, he_off, he_nodes, m, n, cur,
+    hipLaunchKernelGGL(k_scatter_inc_agg, dim3(grid_for(m, 256, 2048)), dim3(256), 0, s, he_off, he_nodes, m, n, cur,
                        static_cast<uint32_t*>(ctx->inc.ptr), static_cast<uint32_t*>(ctx->inc_node.ptr));
   CENTRA_HIP(ctx, hipGetLastError());
   return CENTRA_OK;
@@ -107,13 +187,17 @@ __global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* best, con
                                                        const uint32_t* he_nodes, uint32_t n, uint32_t* covered,
                                                        int32_t* gain, uint64_t* newcov) {
   __shared__ uint64_t red[kCoverBlock / kWave];
+  __shared__ AggTable tab;
   const uint64_t key = *best;
   if ((key >> 32) == 0) return;
   const uint32_t u = 0xFFFFFFFFu - static_cast<uint32_t>(key);
   const uint64_t b = inc_off[u], e = inc_off[u + 1];
+  const uint64_t first = b + blockIdx.x * uint64_t(kCoverBlock);
+  if (first >= e) return;   // uniform per workgroup: nothing of the row lands here
+  agg_init(tab);
+  __syncthreads();
   uint64_t cnt = 0;
-  for (uint64_t p = b + blockIdx.x * uint64_t(kCoverBlock) + threadIdx.x; p < e;
-       p += uint64_t(gridDim.x) * kCoverBlock) {
+  for (uint64_t p = first + threadIdx.x; p < e; p += uint64_t(gridDim.x) * kCoverBlock) {
     const uint32_t s = inc[p];
     const uint32_t bit = 1u << (s & 31u);
     const uint32_t old = atomicOr(&covered[s >> 5], bit);
@@ -121,10 +205,12 @@ __global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* best, con
     ++cnt;
     for (uint64_t x = he_off[s]; x < he_off[s + 1]; ++x) {
       const uint32_t v = he_nodes[x];
-      if (v < n) atomicSub(&gain[v], 1);
+      if (v < n && !agg_add(tab, v)) atomicSub(&gain[v], 1);
     }
   }
-  cnt = block_sum_u64<kCoverBlock>(cnt, red);
+  cnt = block_sum_u64<kCoverBlock>(cnt, red);   // contains the barrier before the flush
+  for (uint32_t i = threadIdx.x; i < kAggSize; i += kCoverBlock)
+    if (tab.key[i] != kUnseen) atomicSub(&gain[tab.key[i]], static_cast<int32_t>(tab.cnt[i]));
   if (threadIdx.x == 0 && cnt) atomicAdd(reinterpret_cast<unsigned long long*>(newcov), cnt);
 }
 
