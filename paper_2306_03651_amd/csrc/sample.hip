@@ -69,6 +69,7 @@ struct SampleArgs {
   uint64_t* rec;      // slots * n records of two words: sigma', level
   uint32_t* q;        // slots * n
   uint32_t* bits;     // slots * bit_words (HBM bitmap variant only)
+  uint64_t* praw;     // slots * kPairMax: raw count of each pair's u from the last cone test
   uint32_t bit_words;
   uint32_t* work;     // work counter
   uint32_t* stage;    // staging for hyperedge nodes
@@ -218,49 +219,6 @@ __device__ __forceinline__ int ring_of(const uint32_t* poff, uint32_t dt, uint32
   return lo;
 }
 
-// Weighted pick over the in-neighbours u of node `w` in ascending order,
-// weight of u = raw_counts_chunk's count (u's count one level below the
-// unproduced level of w).  Returns the first u whose prefix weight exceeds
-// r (uniform across the workgroup).
-template <int BLOCK, int UNROLL, typename Bits>
-__device__ uint32_t pick_through_ring(const SampleArgs& a, const Bits& bits, uint64_t* rec, uint32_t w, uint64_t r,
-                                      SampleShared<BLOCK>& sh, uint64_t& n_arcs) {
-  const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-  const uint32_t wb = a.in_ptr[w], we = a.in_ptr[w + 1];
-  uint64_t acc = 0;
-  uint32_t pick = kUnseen;
-  for (uint32_t cb = wb; cb < we; cb += BLOCK) {
-    const uint32_t cnt = we - cb < BLOCK ? we - cb : BLOCK;
-    const uint32_t u = static_cast<uint32_t>(tid) < cnt ? a.in_idx[cb + tid] : kUnseen;
-    raw_counts_chunk<BLOCK, UNROLL>(a, bits, rec, u, sh, n_arcs);
-    if (wid == 0) {
-      uint32_t found = kUnseen;
-      uint64_t run = acc;
-      for (uint32_t c = 0; c < cnt; c += kWave) {
-        const uint32_t i = c + lane;
-        const uint64_t xv = i < cnt ? sh.sg[i] : 0ull;
-        const uint64_t incl = run + wave_incl_scan_u64(xv);
-        const uint64_t hit = __ballot(incl > r);
-        if (hit) {
-          found = a.in_idx[cb + c + __ffsll(static_cast<unsigned long long>(hit)) - 1];
-          break;
-        }
-        run = shfl_u64(incl, kWave - 1);
-      }
-      if (lane == 0) {
-        sh.pick = found;
-        sh.acc = run;
-      }
-    }
-    __syncthreads();
-    pick = sh.pick;
-    acc = sh.acc;
-    __syncthreads();
-    if (pick != kUnseen) break;
-  }
-  return pick;
-}
-
 template <int BLOCK, int UNROLL, bool LDS_BITS>
 __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   __shared__ SampleShared<BLOCK> sh;
@@ -271,6 +229,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   const size_t slot = blockIdx.x;
   uint64_t* rec = a.rec + 2 * slot * a.n;
   uint32_t* q = a.q + slot * a.n;
+  uint64_t* praw = a.praw + slot * kPairMax;
   using Bits = typename std::conditional<LDS_BITS, BitsLds, BitsHbm>::type;
   Bits bits{LDS_BITS ? dyn_bits : a.bits + slot * a.bit_words};
   const uint64_t lane_lt = (1ull << lane) - 1ull;
@@ -406,6 +365,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
               }
               raw_counts_chunk<BLOCK, UNROLL>(a, bits, rec, u, sh, n_arcs);
               const uint64_t raw = sh.sg[tid];
+              if (p < pairs) st_u64(&praw[p], raw);
               if (raw) {
                 hit3 = 1;
                 atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_b[i]), static_cast<unsigned long long>(raw));
@@ -565,88 +525,89 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
                     : 0ull;
     }
     uint32_t v = t, dv = len ? d : 0u, written = 0;   // no backtrack when t is unreachable or adjacent
-    if (shortcut && rings) {
-      // step from t through level d-1 with weights ring_a (shortcut 2) or
-      // ring_b (shortcut 3), summed here (all threads draw the same r)
-      __syncthreads();
-      uint64_t* wts = shortcut == 2 ? sh.ring_a : sh.ring_b;
+    __syncthreads();   // sh.base, ring sums and stored pair counts are visible
+    if (wid == 0 && shortcut && rings) {
+      // step from t through level d-1: weights ring_a (shortcut 2) or
+      // ring_b (shortcut 3) of t's in-neighbours, in ascending order
+      const uint64_t* wts = shortcut == 2 ? sh.ring_a : sh.ring_b;
       uint64_t W = 0;
-      for (uint32_t i = 0; i < dt; ++i) W += wts[i];
+      for (uint32_t c = 0; c < dt; c += kWave) W += wave_sum_u64(c + lane < dt ? wts[c + lane] : 0ull);
       const uint64_t r = bounded(st, W);
-      if (wid == 0) {
-        uint32_t found = kUnseen;
-        uint64_t run = 0;
-        for (uint32_t c = 0; c < dt; c += kWave) {
-          const uint32_t i = c + lane;
-          const uint64_t x = i < dt ? wts[i] : 0ull;
-          const uint64_t incl = run + wave_incl_scan_u64(x);
-          const uint64_t hit = __ballot(incl > r);
-          if (hit) {
-            found = a.in_idx[tb + c + __ffsll(static_cast<unsigned long long>(hit)) - 1];
-            break;
-          }
-          run = shfl_u64(incl, kWave - 1);
+      uint32_t pi = kUnseen;
+      uint64_t run = 0;
+      for (uint32_t c = 0; c < dt; c += kWave) {
+        const uint64_t incl = run + wave_incl_scan_u64(c + lane < dt ? wts[c + lane] : 0ull);
+        const uint64_t hit = __ballot(incl > r);
+        if (hit) {
+          pi = c + __ffsll(static_cast<unsigned long long>(hit)) - 1;
+          break;
         }
-        if (lane == 0) sh.pick = found;
+        run = shfl_u64(incl, kWave - 1);
       }
-      __syncthreads();
-      uint32_t pick = sh.pick;
-      __syncthreads();
-      if (pick != kUnseen && tid == 0 && sh.base < a.stage_cap) a.stage[sh.base] = pick;
-      written = 1;
-      v = pick;
-      dv = d - 1;
-      if (pick != kUnseen && shortcut == 3) {
-        // step from w (level L+2) through level L+1: weight raw_u, whose sum
-        // is the ring_b entry of w, i.e. sigma'_w
-        uint64_t W2 = 0;
-        for (uint32_t i = 0; i < dt; ++i)
-          if (sh.rw[i] == pick) W2 = sh.ring_b[i];
-        const uint64_t r2 = bounded(st, W2);
-        pick = pick_through_ring<BLOCK, UNROLL>(a, bits, rec, pick, r2, sh, n_arcs);
-        if (pick != kUnseen && tid == 0 && sh.base + 1 < a.stage_cap) a.stage[sh.base + 1] = pick;
-        written = 2;
+      uint32_t pick = pi != kUnseen ? sh.rw[pi] : kUnseen;
+      if (pick != kUnseen) {
+        if (lane == 0 && sh.base < a.stage_cap) a.stage[sh.base] = pick;
+        written = 1;
         v = pick;
-        dv = d - 2;
+        dv = d - 1;
+        if (shortcut == 3) {
+          // step from w (level L+2) through level L+1: weights raw_u of the
+          // pairs (w, u), stored by the cone test in in(w) order; their sum
+          // is ring_b of w, i.e. sigma'_w
+          const uint64_t r2 = bounded(st, sh.ring_b[pi]);
+          const uint32_t p0 = sh.poff[pi];
+          const uint32_t pn = (pi + 1 < dt ? sh.poff[pi + 1] : pairs) - p0;
+          uint32_t j = kUnseen;
+          run = 0;
+          for (uint32_t c = 0; c < pn; c += kWave) {
+            const uint64_t incl = run + wave_incl_scan_u64(c + lane < pn ? ld_u64(&praw[p0 + c + lane]) : 0ull);
+            const uint64_t hit = __ballot(incl > r2);
+            if (hit) {
+              j = c + __ffsll(static_cast<unsigned long long>(hit)) - 1;
+              break;
+            }
+            run = shfl_u64(incl, kWave - 1);
+          }
+          pick = j != kUnseen ? a.in_idx[sh.rrs[pi] + j] : kUnseen;
+          if (pick != kUnseen && lane == 0 && sh.base + 1 < a.stage_cap) a.stage[sh.base + 1] = pick;
+          written = 2;
+          v = pick;
+          dv = d - 2;
+        }
       }
       if (pick == kUnseen) {
-        if (tid == 0) atomicOr(a.flags, kErrBacktrack);
+        if (lane == 0) atomicOr(a.flags, kErrBacktrack);
         dv = 0;
       }
-    } else if (shortcut) {
+    } else if (wid == 0 && shortcut) {
       // shortcut without the ring cache (t has many in-neighbours): the
-      // first step recomputes raw_w on wave 0
-      __syncthreads();
-      if (wid == 0) {
-        const uint64_t r = bounded(st, w_short);
-        uint64_t acc = 0;
-        uint32_t pick = kUnseen;
-        for (uint32_t e = tb; e < te; ++e) {
-          const uint32_t w = a.in_idx[e];
-          const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
-          uint64_t x = 0;
-          for (uint32_t f = ub + lane; f < ue; f += kWave) {
-            const uint32_t u = a.in_idx[f];
-            if (bits.test(u) && ld_u32(lvl_of(rec, u)) == L) x += ld_u64(sig_of(rec, u));
-          }
-          acc += wave_sum_u64(x);
-          if (acc > r) {
-            pick = w;
-            break;
-          }
+      // first step recomputes raw_w
+      const uint64_t r = bounded(st, w_short);
+      uint64_t acc = 0;
+      uint32_t pick = kUnseen;
+      for (uint32_t e = tb; e < te; ++e) {
+        const uint32_t w = a.in_idx[e];
+        const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
+        uint64_t x = 0;
+        for (uint32_t f = ub + lane; f < ue; f += kWave) {
+          const uint32_t u = a.in_idx[f];
+          if (bits.test(u) && ld_u32(lvl_of(rec, u)) == L) x += ld_u64(sig_of(rec, u));
         }
-        if (pick == kUnseen) {
-          if (lane == 0) atomicOr(a.flags, kErrBacktrack);
-          dv = 0;
-        } else {
-          if (lane == 0 && sh.base < a.stage_cap) a.stage[sh.base] = pick;
-          written = 1;
-          v = pick;
-          dv = d - 1;
+        acc += wave_sum_u64(x);
+        if (acc > r) {
+          pick = w;
+          break;
         }
       }
-    } else {
-      __syncthreads();
+      if (pick == kUnseen) {
+        if (lane == 0) atomicOr(a.flags, kErrBacktrack);
+        dv = 0;
+      } else {
+        if (lane == 0 && sh.base < a.stage_cap) a.stage[sh.base] = pick;
+        written = 1;
+        v = pick;
+        dv = d - 1;
+      }
     }
     if (wid == 0) {
       const uint64_t base = sh.base;
@@ -841,7 +802,7 @@ static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, b
   const uint32_t words = (g->n + 31) / 32;
   {
     // never ask for more slots than kSlotMemCap holds
-    const size_t per = size_t(g->n) * (16 + 4) + (hbm_bits ? size_t(words) * 4 : 0);
+    const size_t per = size_t(g->n) * (16 + 4) + (hbm_bits ? size_t(words) * 4 : 0) + kPairMax * 8;
     const size_t most = kSlotMemCap / (per ? per : 1);
     if (want > most) want = most ? static_cast<uint32_t>(most) : 1u;
   }
@@ -850,24 +811,26 @@ static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, b
   uint32_t slots = want > ctx->slots ? want : ctx->slots;
   const uint32_t n = g->n > ctx->slot_n ? g->n : ctx->slot_n;
   const uint32_t nw = (n + 31) / 32;
-  const size_t per_slot = size_t(n) * (16 + 4) + (hbm_bits ? size_t(nw) * 4 : 0);
+  const size_t per_slot = size_t(n) * (16 + 4) + (hbm_bits ? size_t(nw) * 4 : 0) + kPairMax * 8;
   // at most kSlotMemCap of slot state (or the budget, if smaller)
   if (size_t(slots) * per_slot > kSlotMemCap) slots = static_cast<uint32_t>(kSlotMemCap / per_slot);
   if (slots == 0) slots = 1;
   // shrink the slot count if the budget cannot hold all of them
   for (;;) {
     const size_t need = size_t(slots) * per_slot;
-    const size_t have = ctx->slot_rec.bytes + ctx->slot_q.bytes + ctx->slot_bits.bytes;
+    const size_t have = ctx->slot_rec.bytes + ctx->slot_q.bytes + ctx->slot_bits.bytes + ctx->slot_praw.bytes;
     if (!ctx->budget || ctx->allocated - have + need <= ctx->budget || slots <= 1) break;
     slots /= 2;
   }
   release(ctx, ctx->slot_rec);
+  release(ctx, ctx->slot_praw);
   release(ctx, ctx->slot_q);
   release(ctx, ctx->slot_bits);
   ctx->slots = 0;
   ctx->slot_n = 0;
   int rc;
   if ((rc = ensure(ctx, ctx->slot_rec, size_t(slots) * n * 16, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->slot_praw, size_t(slots) * kPairMax * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_q, size_t(slots) * n * 4, false, s))) return rc;
   if (hbm_bits && (rc = ensure(ctx, ctx->slot_bits, size_t(slots) * nw * 4, false, s))) return rc;
   fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(slots) * n * 2, s);
@@ -914,6 +877,7 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     a.rec = static_cast<uint64_t*>(ctx->slot_rec.ptr);
     a.q = static_cast<uint32_t*>(ctx->slot_q.ptr);
     a.bits = static_cast<uint32_t*>(ctx->slot_bits.ptr);
+    a.praw = static_cast<uint64_t*>(ctx->slot_praw.ptr);
     a.bit_words = plan.bit_words;
     a.work = work;
     a.stage = static_cast<uint32_t*>(ctx->stage_nodes.ptr);
