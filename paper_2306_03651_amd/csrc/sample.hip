@@ -87,6 +87,10 @@ struct SampleArgs {
 // on the pairs (w in in(t), u in in(w)); the 3-hop test also needs at most
 // kPairMax pairs, and runs at a level only when expanding that level would
 // scan at least 1/kConeRatio of the cone's CSR entries.
+// Bloom filter of the visited set for the HBM-bitmap variant (see BitsHbm).
+constexpr uint32_t kBloomLog = 15;
+constexpr uint32_t kBloomWords = (1u << kBloomLog) / 32;
+
 template <int BLOCK>
 struct Ring {
   static constexpr uint32_t kCache = BLOCK >= 512 ? 512u : 256u;
@@ -112,6 +116,7 @@ struct SampleShared {
   uint32_t rrs[Ring<BLOCK>::kCache];    // in_ptr[w]
   uint64_t ring_a[Ring<BLOCK>::kCache];  // per in-neighbour w of t: level-(L+1) count
   uint64_t ring_b[Ring<BLOCK>::kCache];  // per in-neighbour w of t: level-(L+2) count
+  uint32_t bloom[BLOCK >= 1024 ? 1 : kBloomWords];   // HBM-bitmap variant (<= 512 threads): visited filter
   uint64_t acc;
   uint64_t base;
   uint32_t pick;
@@ -146,12 +151,41 @@ struct BitsLds {
   __device__ __forceinline__ void set(uint32_t v) { atomicOr(&w[v >> 5], 1u << (v & 31u)); }
 };
 
-// Visited bitmap in HBM (one per slot).
+// Visited bitmap in HBM (one per slot), fronted by a one-hash Bloom filter
+// of kBloomBits bits in LDS: a clear filter bit proves "not visited" without
+// touching HBM (most tests: the visited set is small next to n), a set one
+// defers to the exact bitmap.
+
+__device__ __forceinline__ uint32_t bloom_bit(uint32_t v) { return (v * 0x9E3779B1u) >> (32 - kBloomLog); }
+
 struct BitsHbm {
   uint32_t* w;
-  __device__ __forceinline__ bool test(uint32_t v) const { return (ld_u32(&w[v >> 5]) >> (v & 31u)) & 1u; }
-  __device__ __forceinline__ void set(uint32_t v) { atomicOr(&w[v >> 5], 1u << (v & 31u)); }
+  uint32_t* bloom;   // LDS, kBloomWords
+  __device__ __forceinline__ bool test(uint32_t v) const {
+    const uint32_t b = bloom_bit(v);
+    if (!((bloom[b >> 5] >> (b & 31u)) & 1u)) return false;
+    return (ld_u32(&w[v >> 5]) >> (v & 31u)) & 1u;
+  }
+  __device__ __forceinline__ void set(uint32_t v) {
+    atomicOr(&w[v >> 5], 1u << (v & 31u));
+    const uint32_t b = bloom_bit(v);
+    atomicOr(&bloom[b >> 5], 1u << (b & 31u));
+  }
 };
+
+template <bool LDS_BITS>
+__device__ __forceinline__ typename std::conditional<LDS_BITS, BitsLds, BitsHbm>::type make_bits(uint32_t* lds_bits,
+                                                                                              uint32_t* hbm_bits,
+                                                                                              uint32_t* bloom) {
+  if constexpr (LDS_BITS) {
+    (void)hbm_bits;
+    (void)bloom;
+    return BitsLds{lds_bits};
+  } else {
+    (void)lds_bits;
+    return BitsHbm{hbm_bits, bloom};
+  }
+}
 
 // Raw counts of one chunk of nodes, one node u per thread (kUnseen for
 // none): sh.sg[tid] = sum of sigma' over u's visited in-neighbours, 0 for a
@@ -231,7 +265,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   uint32_t* q = a.q + slot * a.n;
   uint64_t* praw = a.praw + slot * kPairMax;
   using Bits = typename std::conditional<LDS_BITS, BitsLds, BitsHbm>::type;
-  Bits bits{LDS_BITS ? dyn_bits : a.bits + slot * a.bit_words};
+  Bits bits = make_bits<LDS_BITS>(dyn_bits, a.bits + slot * a.bit_words, sh.bloom);
   const uint64_t lane_lt = (1ull << lane) - 1ull;
   const uint64_t cap = a.c_bits >= 64 ? ~0ull : (1ull << a.c_bits);
 
@@ -254,6 +288,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
     const uint32_t tp = static_cast<uint32_t>(bounded(st, a.n - 1));
     const uint32_t t = tp + (tp >= s ? 1u : 0u);
 
+    if (!LDS_BITS) {
+      for (uint32_t i = tid; i < kBloomWords; i += BLOCK) sh.bloom[i] = 0;
+      __syncthreads();
+    }
     if (tid == 0) {
       st_u32(lvl_of(rec, s), 0);
       st_u64(sig_of(rec, s), 1);
