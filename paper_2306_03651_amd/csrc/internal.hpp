@@ -27,7 +27,7 @@ struct centra_ctx {
   uint32_t* d_flags = nullptr;   // kernel error bits (u32) + scratch counters
   // per-BFS slot arrays (node records {count, level}, visit queue, HBM
   // visited bitmap), one set per concurrent BFS, sized for the largest graph
-  centra::DevBuf slot_rec, slot_q, slot_bits, slot_praw;
+  centra::DevBuf slot_rec, slot_q, slot_praw;
   uint32_t slots = 0;
   uint32_t slot_n = 0;
   // sampling staging area

@@ -8,42 +8,50 @@
 // scan of in-neighbours) is independent of thread timing, so the result is
 // bit-identical to a sequential implementation.
 //
-// State of a slot: a visited bitmap (n bits; in LDS when it fits, which on
-// gfx950's 160 KB LDS means n up to about 1.1M, otherwise in HBM), and in
-// HBM one 16-byte record per node {sigma' u64, level u32} (so a node's
-// claim, level, count reads and reset touch a single cache line) and the
-// visit queue (u32, nodes in level order).  Invariant between samples:
-// sigma' is 0 for every node and the bitmap is clear; the level field is
-// read only for nodes whose visited bit is set, so it is never cleared.
+// State of a slot, in HBM: one 16-byte record per node {sigma' u64,
+// level u32} (a node's claim, level, count reads and reset touch a single
+// cache line), the visit queue (u32, nodes in level order) and the stored
+// per-pair counts of the last 3-hop test.  Invariant between samples: every
+// record is {0, kUnseen}.  The visited set of the completed levels is an
+// exact bitmap in LDS (the 1024-thread variant, n up to about 1.1M) or a
+// Bloom filter in LDS backed by the records' level fields (the default
+// variants); no per-sample state is ever cleared in bulk: the cleanup
+// resets only the records of the visited nodes.
 //
 // Level expansion (push): the frontier is processed in chunks of BLOCK
 // nodes; their out-degrees are prefix-summed in LDS and each thread takes
 // UNROLL arcs per round (tid, tid + BLOCK, ...), locating their sources by
 // binary search in LDS (load balance over skewed degrees; consecutive
 // threads read consecutive col_idx entries; UNROLL independent chains keep
-// more memory requests in flight).  An arc w -> v whose target is not yet
-// visited (levels <= L live in the bitmap, which is not touched during the
-// pass) adds sigma'_w to sigma'_v with a returning 64-bit atomic: the add
-// that sees 0 is the first arrival and claims v for level L+1 (appended to
-// the queue with one LDS atomic per wave, ballot + popcount; its level is
-// written).  The returned partial sums also give the level's largest raw
-// count, so the normalisation shift needs no extra pass; only when the shift
-// is nonzero are the level's counts rewritten.
+// more memory requests in flight).  An arc w -> v whose target is not in a
+// completed level adds sigma'_w to sigma'_v with a returning 64-bit atomic:
+// the add that sees 0 is the first arrival and claims v for level L+1
+// (appended to the queue with one LDS atomic per wave, ballot + popcount;
+// its level is written).  The returned partial sums also give the level's
+// largest raw count, so the normalisation shift needs no extra pass; only
+// when the shift is nonzero are the level's counts rewritten.
 //
-// Before expanding level L the workgroup checks whether t has a visited
-// in-neighbour (necessarily at level L); if so d(s,t) = L + 1 and the BFS
-// stops: the backtrack only needs levels <= d - 1, which are complete.
-//
-// Last-level shortcut.  Otherwise, if t has an in-neighbour w at level L+1
-// (w unvisited with an in-neighbour at level L), then d(s,t) = L + 2 and the
-// backtrack's first step needs the normalised counts of exactly those w.
-// Their raw counts are sums over level L, so each is at most S_L, the sum
-// of the level-L counts; when S_L < 2^C no count of level L+1 can need a
-// shift, the normalised counts equal the raw ones, and the (largest) level
-// L+1 need not be produced at all: the first backtrack step sums the raw
-// counts of t's in-neighbours directly from level L.  When S_L >= 2^C the
-// level is produced and normalised as usual.  Both routes give the same
-// counts, hence the same hyperedge.
+// Early stop.  After levels 0..L are complete, every visited in-neighbour
+// of an unvisited node is at level L (a lower one would have put the node
+// in a completed level).  Before expanding level L the workgroup tests, on
+// rings of in-neighbours around t:
+//   (1) t has a visited in-neighbour: d(s,t) = L+1;
+//   (2) some pair (w in in(t), u in in(w)) has u visited: w is at L+1 and
+//       d = L+2; the raw count of each such w is the sum of its visited
+//       in-neighbours' counts;
+//   (3) some u of those pairs (unvisited) has visited in-neighbours: u is
+//       at L+1, its w at L+2 and d = L+3; the raw counts of u and w follow
+//       the same way, and the per-pair counts of u are kept for the
+//       backtrack.
+// Levels L+1 (and L+2) are then never produced.  Their normalisation
+// would be a no-op when every count of theirs is below 2^C: level L+1
+// counts are at most S_L (the sum of the level-L counts) and level L+2
+// counts at most S_L times the largest out-degree, so (2) is taken only if
+// S_L < 2^C and (3) only if also S_L * max out-degree < 2^C; otherwise the
+// levels are produced and normalised as usual.  Test (3) scans the in-rows
+// of the ring's nodes (the cone), so it runs only when the cone is at most
+// kConeRatio times the CSR entries that expanding level L would scan.  All
+// routes give the same counts, hence the same hyperedge.
 #include <stdlib.h>
 #include <string.h>
 
@@ -68,7 +76,6 @@ struct SampleArgs {
   uint32_t count;
   uint64_t* rec;      // slots * n records of two words: sigma', level
   uint32_t* q;        // slots * n
-  uint32_t* bits;     // slots * bit_words (HBM bitmap variant only)
   uint64_t* praw;     // slots * kPairMax: raw count of each pair's u from the last cone test
   uint32_t bit_words;
   uint32_t* work;     // work counter
@@ -87,7 +94,7 @@ struct SampleArgs {
 // on the pairs (w in in(t), u in in(w)); the 3-hop test also needs at most
 // kPairMax pairs, and runs at a level only when expanding that level would
 // scan at least 1/kConeRatio of the cone's CSR entries.
-// Bloom filter of the visited set for the HBM-bitmap variant (see BitsHbm).
+// Bloom filter of the visited set for the HBM variant (see BitsRec).
 constexpr uint32_t kBloomLog = 15;
 constexpr uint32_t kBloomWords = (1u << kBloomLog) / 32;
 
@@ -116,7 +123,7 @@ struct SampleShared {
   uint32_t rrs[Ring<BLOCK>::kCache];    // in_ptr[w]
   uint64_t ring_a[Ring<BLOCK>::kCache];  // per in-neighbour w of t: level-(L+1) count
   uint64_t ring_b[Ring<BLOCK>::kCache];  // per in-neighbour w of t: level-(L+2) count
-  uint32_t bloom[BLOCK >= 1024 ? 1 : kBloomWords];   // HBM-bitmap variant (<= 512 threads): visited filter
+  uint32_t bloom[BLOCK >= 1024 ? 1 : kBloomWords];   // HBM variant (<= 512 threads): visited filter
   uint64_t acc;
   uint64_t base;
   uint32_t pick;
@@ -144,46 +151,57 @@ __device__ __forceinline__ uint64_t block_sat_sum(uint64_t v, uint64_t* scratch)
   return r;
 }
 
-// Visited bitmap in LDS.
+// Visited set.  Between levels, "visited" means "in a completed level"
+// (levels 0..L).  done(v, L) is that test; maybe(v) may answer true for an
+// unvisited node but never false for a visited one (a reader that needs the
+// count anyway follows it with the count load: a visited node holds
+// sigma' >= 1, an unvisited one 0); set(v) adds v when its level closes.
+
+// LDS variant: an exact bitmap of n bits in LDS.
 struct BitsLds {
   uint32_t* w;
   __device__ __forceinline__ bool test(uint32_t v) const { return (w[v >> 5] >> (v & 31u)) & 1u; }
+  __device__ __forceinline__ bool done(uint32_t v, uint32_t) const { return test(v); }
+  __device__ __forceinline__ bool maybe(uint32_t v) const { return test(v); }
   __device__ __forceinline__ void set(uint32_t v) { atomicOr(&w[v >> 5], 1u << (v & 31u)); }
 };
 
-// Visited bitmap in HBM (one per slot), fronted by a one-hash Bloom filter
-// of kBloomBits bits in LDS: a clear filter bit proves "not visited" without
-// touching HBM (most tests: the visited set is small next to n), a set one
-// defers to the exact bitmap.
+// HBM variant: no bitmap.  A one-hash Bloom filter of kBloomBits bits in
+// LDS holds the nodes of the completed levels: a clear filter bit proves
+// "not visited" without touching HBM (most tests: the visited set is small
+// next to n); a set one defers to the node's record, whose level field is
+// kUnseen unless the node was claimed in this BFS.  A node claimed at the
+// level being produced shows kUnseen or L+1 there, never a value <= L.
 
 __device__ __forceinline__ uint32_t bloom_bit(uint32_t v) { return (v * 0x9E3779B1u) >> (32 - kBloomLog); }
 
-struct BitsHbm {
-  uint32_t* w;
+struct BitsRec {
+  uint64_t* rec;
   uint32_t* bloom;   // LDS, kBloomWords
-  __device__ __forceinline__ bool test(uint32_t v) const {
+  __device__ __forceinline__ bool maybe(uint32_t v) const {
     const uint32_t b = bloom_bit(v);
-    if (!((bloom[b >> 5] >> (b & 31u)) & 1u)) return false;
-    return (ld_u32(&w[v >> 5]) >> (v & 31u)) & 1u;
+    return (bloom[b >> 5] >> (b & 31u)) & 1u;
+  }
+  __device__ __forceinline__ bool done(uint32_t v, uint32_t L) const {
+    return maybe(v) && ld_u32(lvl_of(rec, v)) <= L;
   }
   __device__ __forceinline__ void set(uint32_t v) {
-    atomicOr(&w[v >> 5], 1u << (v & 31u));
     const uint32_t b = bloom_bit(v);
     atomicOr(&bloom[b >> 5], 1u << (b & 31u));
   }
 };
 
 template <bool LDS_BITS>
-__device__ __forceinline__ typename std::conditional<LDS_BITS, BitsLds, BitsHbm>::type make_bits(uint32_t* lds_bits,
-                                                                                              uint32_t* hbm_bits,
+__device__ __forceinline__ typename std::conditional<LDS_BITS, BitsLds, BitsRec>::type make_bits(uint32_t* lds_bits,
+                                                                                              uint64_t* rec,
                                                                                               uint32_t* bloom) {
   if constexpr (LDS_BITS) {
-    (void)hbm_bits;
+    (void)rec;
     (void)bloom;
     return BitsLds{lds_bits};
   } else {
     (void)lds_bits;
-    return BitsHbm{hbm_bits, bloom};
+    return BitsRec{rec, bloom};
   }
 }
 
@@ -196,11 +214,11 @@ __device__ __forceinline__ typename std::conditional<LDS_BITS, BitsLds, BitsHbm>
 // per round, sources found by binary search.  Adds the entries scanned to
 // n_arcs.  Contains barriers; sh.sg is valid on return until the next call.
 template <int BLOCK, int UNROLL, typename Bits>
-__device__ void raw_counts_chunk(const SampleArgs& a, const Bits& bits, uint64_t* rec, uint32_t u,
+__device__ void raw_counts_chunk(const SampleArgs& a, const Bits& bits, uint64_t* rec, uint32_t u, uint32_t L,
                                  SampleShared<BLOCK>& sh, uint64_t& n_arcs) {
   const int tid = threadIdx.x;
   uint32_t deg = 0, rs = 0;
-  if (u != kUnseen && !bits.test(u)) {
+  if (u != kUnseen && !bits.done(u, L)) {
     rs = a.in_ptr[u];
     deg = a.in_ptr[u + 1] - rs;
   }
@@ -232,12 +250,24 @@ __device__ void raw_counts_chunk(const SampleArgs& a, const Bits& bits, uint64_t
       }
     }
 #pragma unroll
-    for (int k = 0; k < UNROLL; ++k)
-      if (x[k] != kUnseen && bits.test(x[k]))
-        atomicAdd(reinterpret_cast<unsigned long long*>(&sh.sg[j[k]]),
-                  static_cast<unsigned long long>(ld_u64(sig_of(rec, x[k]))));
+    for (int k = 0; k < UNROLL; ++k) {
+      // a zero count is an unvisited in-neighbour
+      const uint64_t c = (x[k] != kUnseen && bits.maybe(x[k])) ? ld_u64(sig_of(rec, x[k])) : 0ull;
+      if (c) atomicAdd(reinterpret_cast<unsigned long long*>(&sh.sg[j[k]]), static_cast<unsigned long long>(c));
+    }
   }
   __syncthreads();
+}
+
+// Backtrack weight of in-neighbour w of a node at level want + 1: sigma'_w
+// if w is at level want, else 0.  Both loads are issued together; an
+// unvisited w has count 0 whatever its stale level field holds.
+template <typename Bits>
+__device__ __forceinline__ uint64_t pred_weight(const Bits& bits, uint64_t* rec, uint32_t w, uint32_t want) {
+  if (!bits.maybe(w)) return 0;
+  const uint32_t lv = ld_u32(lvl_of(rec, w));
+  const uint64_t c = ld_u64(sig_of(rec, w));
+  return lv == want ? c : 0ull;
 }
 
 // Ring index of pair p: largest i with poff[i] <= p.
@@ -264,8 +294,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   uint64_t* rec = a.rec + 2 * slot * a.n;
   uint32_t* q = a.q + slot * a.n;
   uint64_t* praw = a.praw + slot * kPairMax;
-  using Bits = typename std::conditional<LDS_BITS, BitsLds, BitsHbm>::type;
-  Bits bits = make_bits<LDS_BITS>(dyn_bits, a.bits + slot * a.bit_words, sh.bloom);
+  using Bits = typename std::conditional<LDS_BITS, BitsLds, BitsRec>::type;
+  Bits bits = make_bits<LDS_BITS>(dyn_bits, rec, sh.bloom);
   const uint64_t lane_lt = (1ull << lane) - 1ull;
   const uint64_t cap = a.c_bits >= 64 ? ~0ull : (1ull << a.c_bits);
 
@@ -351,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       int found = 0;
       n_arcs += dt;
       for (uint32_t e = tb + tid; e < te; e += BLOCK)
-        if (bits.test(a.in_idx[e])) found = 1;
+        if (bits.done(a.in_idx[e], L)) found = 1;
       if (__syncthreads_or(found)) {
         d = L + 1;
         break;
@@ -370,10 +400,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         for (uint32_t p = tid; p < pairs; p += BLOCK) {
           const int i = ring_of(sh.poff, dt, p);
           const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
-          if (bits.test(u)) {
+          const uint64_t c = bits.maybe(u) ? ld_u64(sig_of(rec, u)) : 0ull;   // 0: unvisited
+          if (c) {
             hit2 = 1;
-            atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_a[i]),
-                      static_cast<unsigned long long>(ld_u64(sig_of(rec, u))));
+            atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_a[i]), static_cast<unsigned long long>(c));
           }
         }
         n_arcs += pairs;
@@ -401,7 +431,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
                 i = ring_of(sh.poff, dt, p);
                 u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
               }
-              raw_counts_chunk<BLOCK, UNROLL>(a, bits, rec, u, sh, n_arcs);
+              raw_counts_chunk<BLOCK, UNROLL>(a, bits, rec, u, L, sh, n_arcs);
               const uint64_t raw = sh.sg[tid];
               if (p < pairs) st_u64(&praw[p], raw);
               if (raw) {
@@ -427,7 +457,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
           uint64_t x = 0;
           for (uint32_t f = ub + lane; f < ue; f += kWave) {
             const uint32_t u = a.in_idx[f];
-            if (bits.test(u) && ld_u32(lvl_of(rec, u)) == L) x += ld_u64(sig_of(rec, u));
+            // w is unvisited (check (1) failed), so a visited u is at level L
+            if (bits.maybe(u)) x += ld_u64(sig_of(rec, u));
           }
           wsum += wave_sum_u64(x);
           wscan += ue - ub;
@@ -492,7 +523,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
           }
 #pragma unroll
           for (int k = 0; k < UNROLL; ++k)
-            if (act[k] && bits.test(v[k])) act[k] = false;
+            if (act[k] && bits.done(v[k], L)) act[k] = false;
 #pragma unroll
           for (int k = 0; k < UNROLL; ++k) {
             old[k] = 0;
@@ -629,7 +660,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         uint64_t x = 0;
         for (uint32_t f = ub + lane; f < ue; f += kWave) {
           const uint32_t u = a.in_idx[f];
-          if (bits.test(u) && ld_u32(lvl_of(rec, u)) == L) x += ld_u64(sig_of(rec, u));
+          if (bits.maybe(u)) x += ld_u64(sig_of(rec, u));
         }
         acc += wave_sum_u64(x);
         if (acc > r) {
@@ -666,7 +697,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
             if (e < ve) {
               const uint32_t w = a.in_idx[e];
               ws[k] = w;
-              if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) xs[k] = ld_u64(sig_of(rec, w));
+              xs[k] = pred_weight(bits, rec, w, want);
             }
           }
 #pragma unroll
@@ -690,7 +721,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
             uint64_t x = 0;
             if (e < ve) {
               const uint32_t w = a.in_idx[e];
-              if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) x = ld_u64(sig_of(rec, w));
+              x = pred_weight(bits, rec, w, want);
             }
             W += wave_sum_u64(x);
           }
@@ -703,7 +734,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
               uint32_t w = 0;
               if (e < ve) {
                 w = a.in_idx[e];
-                if (bits.test(w) && ld_u32(lvl_of(rec, w)) == want) x = ld_u64(sig_of(rec, w));
+                x = pred_weight(bits, rec, w, want);
               }
               const uint64_t incl = acc + wave_incl_scan_u64(x);
               const uint64_t hit = __ballot(incl > r);
@@ -735,16 +766,15 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       }
     }
     __syncthreads();
-    // restore the invariant: counts of the visited nodes back to 0, bitmap clear
+    // restore the invariant: records of the visited nodes back to {0,
+    // kUnseen}, LDS bitmap clear
     const uint32_t nv = sh.qlen;
     n_nodes += nv;
     for (uint32_t i = tid; i < nv; i += BLOCK) {
       const uint32_t v = ld_u32(&q[i]);
       st_u64(sig_of(rec, v), 0);
-      if (LDS_BITS)
-        dyn_bits[v >> 5] = 0;
-      else
-        st_u32(&a.bits[slot * a.bit_words + (v >> 5)], 0);
+      st_u32(lvl_of(rec, v), kUnseen);
+      if (LDS_BITS) dyn_bits[v >> 5] = 0;
     }
     __syncthreads();
   }
@@ -836,43 +866,46 @@ static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
   return p;
 }
 
-static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, bool hbm_bits, hipStream_t s) {
-  const uint32_t words = (g->n + 31) / 32;
+// Records start as {sigma' 0, level kUnseen}.
+__global__ void k_fill_rec(uint64_t* rec, size_t count) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < count; i += size_t(gridDim.x) * blockDim.x) {
+    rec[2 * i] = 0;
+    rec[2 * i + 1] = kUnseen;
+  }
+}
+
+static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, hipStream_t s) {
   {
     // never ask for more slots than kSlotMemCap holds
-    const size_t per = size_t(g->n) * (16 + 4) + (hbm_bits ? size_t(words) * 4 : 0) + kPairMax * 8;
+    const size_t per = size_t(g->n) * (16 + 4) + kPairMax * 8;
     const size_t most = kSlotMemCap / (per ? per : 1);
     if (want > most) want = most ? static_cast<uint32_t>(most) : 1u;
   }
-  if (ctx->slots >= want && ctx->slot_n >= g->n && (!hbm_bits || ctx->slot_bits.bytes >= size_t(ctx->slots) * words * 4))
-    return CENTRA_OK;
+  if (ctx->slots >= want && ctx->slot_n >= g->n) return CENTRA_OK;
   uint32_t slots = want > ctx->slots ? want : ctx->slots;
   const uint32_t n = g->n > ctx->slot_n ? g->n : ctx->slot_n;
-  const uint32_t nw = (n + 31) / 32;
-  const size_t per_slot = size_t(n) * (16 + 4) + (hbm_bits ? size_t(nw) * 4 : 0) + kPairMax * 8;
+  const size_t per_slot = size_t(n) * (16 + 4) + kPairMax * 8;
   // at most kSlotMemCap of slot state (or the budget, if smaller)
   if (size_t(slots) * per_slot > kSlotMemCap) slots = static_cast<uint32_t>(kSlotMemCap / per_slot);
   if (slots == 0) slots = 1;
   // shrink the slot count if the budget cannot hold all of them
   for (;;) {
     const size_t need = size_t(slots) * per_slot;
-    const size_t have = ctx->slot_rec.bytes + ctx->slot_q.bytes + ctx->slot_bits.bytes + ctx->slot_praw.bytes;
+    const size_t have = ctx->slot_rec.bytes + ctx->slot_q.bytes + ctx->slot_praw.bytes;
     if (!ctx->budget || ctx->allocated - have + need <= ctx->budget || slots <= 1) break;
     slots /= 2;
   }
   release(ctx, ctx->slot_rec);
   release(ctx, ctx->slot_praw);
   release(ctx, ctx->slot_q);
-  release(ctx, ctx->slot_bits);
   ctx->slots = 0;
   ctx->slot_n = 0;
   int rc;
   if ((rc = ensure(ctx, ctx->slot_rec, size_t(slots) * n * 16, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_praw, size_t(slots) * kPairMax * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_q, size_t(slots) * n * 4, false, s))) return rc;
-  if (hbm_bits && (rc = ensure(ctx, ctx->slot_bits, size_t(slots) * nw * 4, false, s))) return rc;
-  fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(slots) * n * 2, s);
-  if (hbm_bits) fill_u32(static_cast<uint32_t*>(ctx->slot_bits.ptr), 0, size_t(slots) * nw, s);
+  hipLaunchKernelGGL(k_fill_rec, dim3(4096), dim3(256), 0, s, static_cast<uint64_t*>(ctx->slot_rec.ptr),
+                     size_t(slots) * n);
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->slots = slots;
   ctx->slot_n = n;
@@ -886,7 +919,7 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
   if (count == 0) return CENTRA_OK;
   const SamplePlan plan = plan_for(ctx, g->n);
   uint32_t want = count < plan.resident ? count : plan.resident;
-  if ((rc = ensure_slots(ctx, g, want, !plan.lds_bits, s))) return rc;
+  if ((rc = ensure_slots(ctx, g, want, s))) return rc;
   const uint32_t grid = count < ctx->slots ? count : ctx->slots;
   if ((rc = ensure(ctx, ctx->stage_pos, size_t(count) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->stage_len, size_t(count) * 4 + 8 + 8 * (size_t(count) + 1), false, s))) return rc;
@@ -914,7 +947,6 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     a.count = count;
     a.rec = static_cast<uint64_t*>(ctx->slot_rec.ptr);
     a.q = static_cast<uint32_t*>(ctx->slot_q.ptr);
-    a.bits = static_cast<uint32_t*>(ctx->slot_bits.ptr);
     a.praw = static_cast<uint64_t*>(ctx->slot_praw.ptr);
     a.bit_words = plan.bit_words;
     a.work = work;
