@@ -25,11 +25,13 @@ struct centra_ctx {
   size_t allocated = 0;
   std::string err;
   uint32_t* d_flags = nullptr;   // kernel error bits (u32) + scratch counters
-  // per-BFS slot arrays (node records {count, level}, visit queue, HBM
-  // visited bitmap), one set per concurrent BFS, sized for the largest graph
+  // per-BFS slot arrays (node records {count, stamp and level}, visit
+  // queue, stored pair counts), one set per concurrent BFS, sized for the
+  // largest graph
   centra::DevBuf slot_rec, slot_q, slot_praw;
   uint32_t slots = 0;
   uint32_t slot_n = 0;
+  uint32_t stamp_next = 1;   // BFS stamp of the next sample (records start at stamp 0)
   // sampling staging area
   centra::DevBuf stage_nodes, stage_pos, stage_len, work_ctr;
   // scan scratch

@@ -8,15 +8,18 @@
 // scan of in-neighbours) is independent of thread timing, so the result is
 // bit-identical to a sequential implementation.
 //
-// State of a slot, in HBM: one 16-byte record per node {sigma' u64,
-// level u32} (a node's claim, level, count reads and reset touch a single
-// cache line), the visit queue (u32, nodes in level order) and the stored
-// per-pair counts of the last 3-hop test.  Invariant between samples: every
-// record is {0, kUnseen}.  The visited set of the completed levels is an
-// exact bitmap in LDS (the 1024-thread variant, n up to about 1.1M) or a
-// Bloom filter in LDS backed by the records' level fields (the default
-// variants); no per-sample state is ever cleared in bulk: the cleanup
-// resets only the records of the visited nodes.
+// State of a slot, in HBM: one 16-byte record per node {sigma' u64, tag
+// u64} (a node's claim, level, count reads and writes touch a single cache
+// line), the visit queue (u32, nodes in level order) and the stored
+// per-pair counts of the last 3-hop test.  The tag is stamp << 32 |
+// (kUnseen - level), where the stamp numbers the BFSs of the context in
+// launch and work order: a slot's records carry only stamps older than its
+// current BFS's unless that BFS claimed them, so nothing is ever reset
+// between samples (records start at stamp 0; the stamps restart after a
+// full clear when 32 bits run out).  The visited set of the completed
+// levels is an exact bitmap in LDS (the 1024-thread variant, n up to about
+// 1.1M; cleared per visited node) or a Bloom filter in LDS backed by the
+// tags (the default variants).
 //
 // Level expansion (push): the frontier is processed in chunks of BLOCK
 // nodes; their out-degrees are prefix-summed in LDS and each thread takes
@@ -24,12 +27,15 @@
 // binary search in LDS (load balance over skewed degrees; consecutive
 // threads read consecutive col_idx entries; UNROLL independent chains keep
 // more memory requests in flight).  An arc w -> v whose target is not in a
-// completed level adds sigma'_w to sigma'_v with a returning 64-bit atomic:
-// the add that sees 0 is the first arrival and claims v for level L+1
-// (appended to the queue with one LDS atomic per wave, ballot + popcount;
-// its level is written).  The returned partial sums also give the level's
-// largest raw count, so the normalisation shift needs no extra pass; only
-// when the shift is nonzero are the level's counts rewritten.
+// completed level raises v's tag to (stamp, L+1) with a returning 64-bit
+// atomic max: the one that sees an older stamp is the first arrival, claims
+// v (appended to the queue with one LDS atomic per wave, ballot +
+// popcount) and starts its count with its own contribution; after a
+// barrier the other arrivals add theirs with returning 64-bit atomics
+// (the inverted level keeps the max from touching nodes of lower levels).
+// The returned partial sums also give the level's largest raw count, so
+// the normalisation shift needs no extra pass; only when the shift is
+// nonzero are the level's counts rewritten.
 //
 // Early stop.  After levels 0..L are complete, every visited in-neighbour
 // of an unvisited node is at level L (a lower one would have put the node
@@ -77,6 +83,7 @@ struct SampleArgs {
   uint64_t* rec;      // slots * n records of two words: sigma', level
   uint32_t* q;        // slots * n
   uint64_t* praw;     // slots * kPairMax: raw count of each pair's u from the last cone test
+  uint32_t stamp0;    // stamp of work item 0; item i has stamp0 + i
   uint32_t bit_words;
   uint32_t* work;     // work counter
   uint32_t* stage;    // staging for hyperedge nodes
@@ -105,11 +112,13 @@ struct Ring {
 constexpr uint32_t kPairMax = 65536;
 constexpr uint64_t kConeRatio = 3;
 
-// Record accessors: word 0 = sigma', low half of word 1 = level.
+// Record accessors: word 0 = sigma', word 1 = tag.  With base = stamp << 32
+// the tag of a node at level l of the current BFS is base + (kUnseen - l):
+// "claimed by this BFS" is tag >= base, "at level <= L" is
+// tag >= base + (kUnseen - L).
 __device__ __forceinline__ uint64_t* sig_of(uint64_t* rec, uint32_t v) { return rec + 2 * size_t(v); }
-__device__ __forceinline__ uint32_t* lvl_of(uint64_t* rec, uint32_t v) {
-  return reinterpret_cast<uint32_t*>(rec + 2 * size_t(v) + 1);
-}
+__device__ __forceinline__ uint64_t* tag_of(uint64_t* rec, uint32_t v) { return rec + 2 * size_t(v) + 1; }
+__device__ __forceinline__ uint64_t level_tag(uint64_t base, uint32_t level) { return base + (kUnseen - level); }
 
 template <int BLOCK>
 struct SampleShared {
@@ -152,38 +161,45 @@ __device__ __forceinline__ uint64_t block_sat_sum(uint64_t v, uint64_t* scratch)
 }
 
 // Visited set.  Between levels, "visited" means "in a completed level"
-// (levels 0..L).  done(v, L) is that test; maybe(v) may answer true for an
-// unvisited node but never false for a visited one (a reader that needs the
-// count anyway follows it with the count load: a visited node holds
-// sigma' >= 1, an unvisited one 0); set(v) adds v when its level closes.
+// (levels 0..L), which is also "claimed by this BFS".  done(v, L) is that
+// test; maybe(v) may answer true for an unvisited node but never false for
+// a visited one; count(v) is sigma'_v for a visited v, else 0; set(v) adds
+// v when its level closes.  base is the current BFS's stamp << 32.
 
 // LDS variant: an exact bitmap of n bits in LDS.
 struct BitsLds {
   uint32_t* w;
-  __device__ __forceinline__ bool test(uint32_t v) const { return (w[v >> 5] >> (v & 31u)) & 1u; }
-  __device__ __forceinline__ bool done(uint32_t v, uint32_t) const { return test(v); }
-  __device__ __forceinline__ bool maybe(uint32_t v) const { return test(v); }
+  uint64_t* rec;
+  uint64_t base;
+  __device__ __forceinline__ bool maybe(uint32_t v) const { return (w[v >> 5] >> (v & 31u)) & 1u; }
+  __device__ __forceinline__ bool done(uint32_t v, uint32_t) const { return maybe(v); }
+  __device__ __forceinline__ uint64_t count(uint32_t v) const { return maybe(v) ? ld_u64(sig_of(rec, v)) : 0ull; }
   __device__ __forceinline__ void set(uint32_t v) { atomicOr(&w[v >> 5], 1u << (v & 31u)); }
 };
 
 // HBM variant: no bitmap.  A one-hash Bloom filter of kBloomBits bits in
 // LDS holds the nodes of the completed levels: a clear filter bit proves
 // "not visited" without touching HBM (most tests: the visited set is small
-// next to n); a set one defers to the node's record, whose level field is
-// kUnseen unless the node was claimed in this BFS.  A node claimed at the
-// level being produced shows kUnseen or L+1 there, never a value <= L.
+// next to n); a set one defers to the node's tag.
 
 __device__ __forceinline__ uint32_t bloom_bit(uint32_t v) { return (v * 0x9E3779B1u) >> (32 - kBloomLog); }
 
 struct BitsRec {
   uint64_t* rec;
   uint32_t* bloom;   // LDS, kBloomWords
+  uint64_t base;
   __device__ __forceinline__ bool maybe(uint32_t v) const {
     const uint32_t b = bloom_bit(v);
     return (bloom[b >> 5] >> (b & 31u)) & 1u;
   }
   __device__ __forceinline__ bool done(uint32_t v, uint32_t L) const {
-    return maybe(v) && ld_u32(lvl_of(rec, v)) <= L;
+    return maybe(v) && ld_u64(tag_of(rec, v)) >= level_tag(base, L);
+  }
+  __device__ __forceinline__ uint64_t count(uint32_t v) const {
+    if (!maybe(v)) return 0;
+    const uint64_t tg = ld_u64(tag_of(rec, v));   // both loads in flight together
+    const uint64_t c = ld_u64(sig_of(rec, v));
+    return tg >= base ? c : 0ull;
   }
   __device__ __forceinline__ void set(uint32_t v) {
     const uint32_t b = bloom_bit(v);
@@ -196,12 +212,11 @@ __device__ __forceinline__ typename std::conditional<LDS_BITS, BitsLds, BitsRec>
                                                                                               uint64_t* rec,
                                                                                               uint32_t* bloom) {
   if constexpr (LDS_BITS) {
-    (void)rec;
     (void)bloom;
-    return BitsLds{lds_bits};
+    return BitsLds{lds_bits, rec, 0};
   } else {
     (void)lds_bits;
-    return BitsRec{rec, bloom};
+    return BitsRec{rec, bloom, 0};
   }
 }
 
@@ -251,8 +266,7 @@ __device__ void raw_counts_chunk(const SampleArgs& a, const Bits& bits, uint64_t
     }
 #pragma unroll
     for (int k = 0; k < UNROLL; ++k) {
-      // a zero count is an unvisited in-neighbour
-      const uint64_t c = (x[k] != kUnseen && bits.maybe(x[k])) ? ld_u64(sig_of(rec, x[k])) : 0ull;
+      const uint64_t c = x[k] != kUnseen ? bits.count(x[k]) : 0ull;   // 0: unvisited
       if (c) atomicAdd(reinterpret_cast<unsigned long long*>(&sh.sg[j[k]]), static_cast<unsigned long long>(c));
     }
   }
@@ -260,14 +274,13 @@ __device__ void raw_counts_chunk(const SampleArgs& a, const Bits& bits, uint64_t
 }
 
 // Backtrack weight of in-neighbour w of a node at level want + 1: sigma'_w
-// if w is at level want, else 0.  Both loads are issued together; an
-// unvisited w has count 0 whatever its stale level field holds.
+// if w is at level want of this BFS, else 0 (both loads issued together).
 template <typename Bits>
 __device__ __forceinline__ uint64_t pred_weight(const Bits& bits, uint64_t* rec, uint32_t w, uint32_t want) {
   if (!bits.maybe(w)) return 0;
-  const uint32_t lv = ld_u32(lvl_of(rec, w));
+  const uint64_t tg = ld_u64(tag_of(rec, w));
   const uint64_t c = ld_u64(sig_of(rec, w));
-  return lv == want ? c : 0ull;
+  return tg == level_tag(bits.base, want) ? c : 0ull;
 }
 
 // Ring index of pair p: largest i with poff[i] <= p.
@@ -311,6 +324,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
     __syncthreads();
     if (idx >= a.count) break;
     const uint64_t sample = a.first + idx;
+    bits.base = uint64_t(a.stamp0 + idx) << 32;
 
     // pair draw: every thread draws the same words (uniform, no broadcast)
     WordStream st(a.seed, sample, a.instance, 0);
@@ -323,7 +337,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       __syncthreads();
     }
     if (tid == 0) {
-      st_u32(lvl_of(rec, s), 0);
+      st_u64(tag_of(rec, s), level_tag(bits.base, 0));
       st_u64(sig_of(rec, s), 1);
       st_u32(&q[0], s);
       bits.set(s);
@@ -400,7 +414,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         for (uint32_t p = tid; p < pairs; p += BLOCK) {
           const int i = ring_of(sh.poff, dt, p);
           const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
-          const uint64_t c = bits.maybe(u) ? ld_u64(sig_of(rec, u)) : 0ull;   // 0: unvisited
+          const uint64_t c = bits.count(u);   // 0: unvisited
           if (c) {
             hit2 = 1;
             atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_a[i]), static_cast<unsigned long long>(c));
@@ -458,7 +472,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
           for (uint32_t f = ub + lane; f < ue; f += kWave) {
             const uint32_t u = a.in_idx[f];
             // w is unvisited (check (1) failed), so a visited u is at level L
-            if (bits.maybe(u)) x += ld_u64(sig_of(rec, u));
+            x += bits.count(u);
           }
           wsum += wave_sum_u64(x);
           wscan += ue - ub;
@@ -498,8 +512,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         __syncthreads();
         for (uint32_t base = 0; base < total; base += BLOCK * UNROLL) {
           uint32_t v[UNROLL];
-          uint64_t add[UNROLL], old[UNROLL];
-          bool act[UNROLL];
+          uint64_t add[UNROLL];
+          bool act[UNROLL], claimed[UNROLL];
 #pragma unroll
           for (int k = 0; k < UNROLL; ++k) {
             const uint32_t e = base + k * BLOCK + tid;
@@ -524,32 +538,36 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
 #pragma unroll
           for (int k = 0; k < UNROLL; ++k)
             if (act[k] && bits.done(v[k], L)) act[k] = false;
+          const uint64_t tag_new = level_tag(bits.base, nl);
 #pragma unroll
           for (int k = 0; k < UNROLL; ++k) {
-            old[k] = 0;
+            claimed[k] = false;
             if (act[k])
-              old[k] = atomicAdd(reinterpret_cast<unsigned long long*>(sig_of(rec, v[k])),
-                                 static_cast<unsigned long long>(add[k]));
+              claimed[k] = atomicMax(reinterpret_cast<unsigned long long*>(tag_of(rec, v[k])),
+                                     static_cast<unsigned long long>(tag_new)) < bits.base;
           }
 #pragma unroll
+          for (int k = 0; k < UNROLL; ++k)
+            if (claimed[k]) st_u64(sig_of(rec, v[k]), add[k]);
+          __syncthreads();   // every claimed count is started before the other arrivals add
+#pragma unroll
           for (int k = 0; k < UNROLL; ++k) {
-            const bool claimed = act[k] && old[k] == 0;
             if (act[k]) {
-              const uint64_t x = old[k] + add[k];
+              uint64_t x = add[k];
+              if (!claimed[k])
+                x += atomicAdd(reinterpret_cast<unsigned long long*>(sig_of(rec, v[k])),
+                               static_cast<unsigned long long>(add[k]));
               mx = x > mx ? x : mx;
               added = sat_add(added, add[k]);
             }
             // wave-aggregated append of newly claimed nodes
-            const uint64_t m = __ballot(claimed);
+            const uint64_t m = __ballot(claimed[k]);
             if (m) {
               uint32_t wbase = 0;
               const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
               if (lane == leader) wbase = atomicAdd(&sh.qlen, static_cast<uint32_t>(__popcll(m)));
               wbase = __shfl(wbase, leader, kWave);
-              if (claimed) {
-                st_u32(&q[wbase + __popcll(m & lane_lt)], v[k]);
-                st_u32(lvl_of(rec, v[k]), nl);
-              }
+              if (claimed[k]) st_u32(&q[wbase + __popcll(m & lane_lt)], v[k]);
             }
           }
         }
@@ -660,7 +678,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         uint64_t x = 0;
         for (uint32_t f = ub + lane; f < ue; f += kWave) {
           const uint32_t u = a.in_idx[f];
-          if (bits.maybe(u)) x += ld_u64(sig_of(rec, u));
+          x += bits.count(u);
         }
         acc += wave_sum_u64(x);
         if (acc > r) {
@@ -766,17 +784,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       }
     }
     __syncthreads();
-    // restore the invariant: records of the visited nodes back to {0,
-    // kUnseen}, LDS bitmap clear
+    // the records keep this BFS's stamp (older than any later one); only
+    // the LDS bitmap is cleared
     const uint32_t nv = sh.qlen;
     n_nodes += nv;
-    for (uint32_t i = tid; i < nv; i += BLOCK) {
-      const uint32_t v = ld_u32(&q[i]);
-      st_u64(sig_of(rec, v), 0);
-      st_u32(lvl_of(rec, v), kUnseen);
-      if (LDS_BITS) dyn_bits[v >> 5] = 0;
+    if (LDS_BITS) {
+      for (uint32_t i = tid; i < nv; i += BLOCK) dyn_bits[ld_u32(&q[i]) >> 5] = 0;
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (tid == 0 && a.stats && n_arcs) {
     atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[0]), static_cast<unsigned long long>(n_arcs));
@@ -866,14 +881,6 @@ static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
   return p;
 }
 
-// Records start as {sigma' 0, level kUnseen}.
-__global__ void k_fill_rec(uint64_t* rec, size_t count) {
-  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < count; i += size_t(gridDim.x) * blockDim.x) {
-    rec[2 * i] = 0;
-    rec[2 * i + 1] = kUnseen;
-  }
-}
-
 static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, hipStream_t s) {
   {
     // never ask for more slots than kSlotMemCap holds
@@ -904,8 +911,7 @@ static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, h
   if ((rc = ensure(ctx, ctx->slot_rec, size_t(slots) * n * 16, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_praw, size_t(slots) * kPairMax * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_q, size_t(slots) * n * 4, false, s))) return rc;
-  hipLaunchKernelGGL(k_fill_rec, dim3(4096), dim3(256), 0, s, static_cast<uint64_t*>(ctx->slot_rec.ptr),
-                     size_t(slots) * n);
+  fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(slots) * n * 2, s);   // stamp 0: never claimed
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->slots = slots;
   ctx->slot_n = n;
@@ -933,7 +939,15 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     uint64_t* used = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 8);
     fill_u32(work, 0, 1, s);
     fill_u64(used, 0, 1, s);
+    // stamps: this launch numbers its work items stamp_next, stamp_next + 1,
+    // ...; when 32 bits would run out, clear every record and restart at 1
+    if (ctx->stamp_next == 0 || uint64_t(ctx->stamp_next) + count > 0xFFFFFFFFull) {
+      fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(ctx->slots) * ctx->slot_n * 2, s);
+      ctx->stamp_next = 1;
+    }
     SampleArgs a;
+    a.stamp0 = ctx->stamp_next;
+    ctx->stamp_next += count;
     a.n = g->n;
     a.c_bits = g->count_bits;
     a.max_out_deg = g->max_out_degree;
