@@ -381,8 +381,6 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         n_arcs += pairs;
       }
     }
-    // out-arcs of the current frontier: the cost of expanding it
-    uint64_t fcost = a.row_ptr[s + 1] - a.row_ptr[s];
     __syncthreads();
 
     uint32_t lb = 0, le = 1, L = 0, d = kUnseen;
@@ -435,7 +433,25 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
           //     counts <= S_L, level L+2 counts <= S_{L+1} <= S_L * max
           //     out-degree) and expanding level L would cost more.
           const uint64_t bound = (a.max_out_deg && sumL > ~0ull / a.max_out_deg) ? ~0ull : sumL * a.max_out_deg;
-          if (cone != ~0ull && sumL < cap && bound < cap && cone <= kConeRatio * fcost) {
+          bool cheap = false;
+          if (cone != ~0ull && sumL < cap && bound < cap) {
+            // cone <= kConeRatio * (out-arcs of level L), summing the
+            // out-degrees only until the sum is large enough (most levels
+            // are never expanded, so the sum is not kept per level)
+            const uint64_t need = (cone + kConeRatio - 1) / kConeRatio;
+            uint64_t fcost = 0;
+            for (uint32_t cb = lb; cb < le && fcost < need; cb += BLOCK) {
+              const uint32_t i = cb + tid;
+              uint64_t c = 0;
+              if (i < le) {
+                const uint32_t w = ld_u32(&q[i]);
+                c = a.row_ptr[w + 1] - a.row_ptr[w];
+              }
+              fcost += block_sum_u64<BLOCK>(c, sh.red);
+            }
+            cheap = fcost >= need;
+          }
+          if (cheap) {
             int hit3 = 0;
             for (uint32_t cb = 0; cb < pairs; cb += BLOCK) {
               const uint32_t p = cb + tid;
@@ -581,11 +597,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       mx = block_max_u64<BLOCK>(mx, sh.red);
       const uint32_t bl = bitlen64(mx);
       const uint32_t shift = bl > a.c_bits ? bl - a.c_bits : 0u;
-      uint64_t ssum = 0, ncost = 0;
+      uint64_t ssum = 0;
       for (uint32_t i = le + tid; i < ne; i += BLOCK) {
         const uint32_t v = ld_u32(&q[i]);
         bits.set(v);
-        ncost += a.row_ptr[v + 1] - a.row_ptr[v];
         if (shift) {
           uint64_t x = ld_u64(sig_of(rec, v)) >> shift;
           x = x ? x : 1ull;
@@ -595,7 +610,6 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       }
       if (!shift) ssum = added;
       sumL = block_sat_sum<BLOCK>(ssum, sh.red);   // contains the barrier closing the level
-      fcost = block_sum_u64<BLOCK>(ncost, sh.red);
       lb = le;
       le = ne;
       L = nl;
