@@ -273,6 +273,81 @@ __device__ void raw_counts_chunk(const SampleArgs& a, const Bits& bits, uint64_t
   __syncthreads();
 }
 
+// Exclusive scan of one u64 per thread in thread order, with the total.
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* total, uint64_t* scratch) {
+  constexpr int NW = BLOCK / kWave;
+  const int wid = threadIdx.x / kWave;
+  const uint64_t incl = wave_incl_scan_u64(v);
+  if (lane_id() == kWave - 1) scratch[wid] = incl;
+  __syncthreads();
+  uint64_t before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const uint64_t x = scratch[i];
+    before += i < wid ? x : 0ull;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + incl - v;
+}
+
+// Weighted pick over entries j = 0 .. len-1 in ascending order, workgroup
+// wide: W = sum of weight(j) (or W_known when nonzero, the caller's exact
+// sum), r = bounded(st, W), and the result is the smallest j whose
+// inclusive prefix sum exceeds r; kUnseen when W = 0.  Each thread holds
+// kPickPer consecutive entries per round, so a round covers BLOCK *
+// kPickPer entries with that many loads in flight; rows of at most one
+// round are summed and searched from the same registers.  Uniform control
+// flow; every thread draws the same words.
+constexpr uint32_t kPickPer = 4;
+
+template <int BLOCK, typename F>
+__device__ uint32_t block_pick(uint32_t len, const F& weight, uint64_t W_known, WordStream& st,
+                               SampleShared<BLOCK>& sh) {
+  constexpr uint32_t kRound = BLOCK * kPickPer;
+  const uint32_t first = threadIdx.x * kPickPer;
+  uint64_t x[kPickPer];
+  uint64_t W = W_known, run = 0, r = 0;
+  if (len > kRound && !W) {
+    for (uint32_t c = 0; c < len; c += kRound) {
+      uint64_t ts = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < kPickPer; ++k) ts += c + first + k < len ? weight(c + first + k) : 0ull;
+      W += block_sum_u64<BLOCK>(ts, sh.red);
+    }
+    if (!W) return kUnseen;
+  }
+  if (W) r = bounded(st, W);
+  for (uint32_t c = 0; c < len; c += kRound) {
+    uint64_t ts = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPickPer; ++k) {
+      x[k] = c + first + k < len ? weight(c + first + k) : 0ull;
+      ts += x[k];
+    }
+    uint64_t tot;
+    uint64_t incl = run + block_excl_scan_u64<BLOCK>(ts, &tot, sh.red);
+    if (!W) {   // single round, sum not known before: draw now
+      W = tot;
+      if (!W) return kUnseen;
+      r = bounded(st, W);
+    }
+    if (run + tot > r) {
+      uint32_t cand = kUnseen;
+#pragma unroll
+      for (uint32_t k = 0; k < kPickPer; ++k) {
+        incl += x[k];
+        if (cand == kUnseen && incl > r) cand = c + first + k;
+      }
+      return ~static_cast<uint32_t>(block_max_u64<BLOCK>(uint64_t(~cand), sh.red));
+    }
+    run += tot;
+  }
+  return kUnseen;
+}
+
 // Backtrack weight of in-neighbour w of a node at level want + 1: sigma'_w
 // if w is at level want of this BFS, else 0 (both loads issued together).
 template <typename Bits>
@@ -617,8 +692,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
 
     // backtrack: from v = t, pick a predecessor w at level(v) - 1 with
     // probability sigma'_w / W, scanning in-neighbours in ascending order,
-    // until level 1.  Steps through unproduced levels (shortcut 2 or 3) run
-    // on the whole workgroup; the remaining steps on wave 0.
+    // until level 1.  Workgroup wide (block_pick); steps through unproduced
+    // levels (shortcut 2 or 3) take their weights from the ring sums and the
+    // stored pair counts.
     const uint32_t len = (d != kUnseen && d >= 2) ? d - 1 : 0u;
     if (tid == 0) {
       sh.base = len ? atomicAdd(reinterpret_cast<unsigned long long*>(a.stage_used),
@@ -627,175 +703,93 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
     }
     uint32_t v = t, dv = len ? d : 0u, written = 0;   // no backtrack when t is unreachable or adjacent
     __syncthreads();   // sh.base, ring sums and stored pair counts are visible
-    if (wid == 0 && shortcut && rings) {
+    const uint64_t hbase = sh.base;
+    bool ok = true;
+    if (dv && shortcut && rings) {
       // step from t through level d-1: weights ring_a (shortcut 2) or
       // ring_b (shortcut 3) of t's in-neighbours, in ascending order
       const uint64_t* wts = shortcut == 2 ? sh.ring_a : sh.ring_b;
-      uint64_t W = 0;
-      for (uint32_t c = 0; c < dt; c += kWave) W += wave_sum_u64(c + lane < dt ? wts[c + lane] : 0ull);
-      const uint64_t r = bounded(st, W);
-      uint32_t pi = kUnseen;
-      uint64_t run = 0;
-      for (uint32_t c = 0; c < dt; c += kWave) {
-        const uint64_t incl = run + wave_incl_scan_u64(c + lane < dt ? wts[c + lane] : 0ull);
-        const uint64_t hit = __ballot(incl > r);
-        if (hit) {
-          pi = c + __ffsll(static_cast<unsigned long long>(hit)) - 1;
-          break;
-        }
-        run = shfl_u64(incl, kWave - 1);
-      }
-      uint32_t pick = pi != kUnseen ? sh.rw[pi] : kUnseen;
-      if (pick != kUnseen) {
-        if (lane == 0 && sh.base < a.stage_cap) a.stage[sh.base] = pick;
+      const uint32_t pi = block_pick<BLOCK>(dt, [&](uint32_t j) { return wts[j]; }, 0, st, sh);
+      if (pi == kUnseen) {
+        ok = false;
+      } else {
+        v = sh.rw[pi];
+        if (tid == 0 && hbase < a.stage_cap) a.stage[hbase] = v;
         written = 1;
-        v = pick;
         dv = d - 1;
         if (shortcut == 3) {
           // step from w (level L+2) through level L+1: weights raw_u of the
           // pairs (w, u), stored by the cone test in in(w) order; their sum
           // is ring_b of w, i.e. sigma'_w
-          const uint64_t r2 = bounded(st, sh.ring_b[pi]);
           const uint32_t p0 = sh.poff[pi];
           const uint32_t pn = (pi + 1 < dt ? sh.poff[pi + 1] : pairs) - p0;
-          uint32_t j = kUnseen;
-          run = 0;
-          for (uint32_t c = 0; c < pn; c += kWave) {
-            const uint64_t incl = run + wave_incl_scan_u64(c + lane < pn ? ld_u64(&praw[p0 + c + lane]) : 0ull);
-            const uint64_t hit = __ballot(incl > r2);
-            if (hit) {
-              j = c + __ffsll(static_cast<unsigned long long>(hit)) - 1;
-              break;
-            }
-            run = shfl_u64(incl, kWave - 1);
+          const uint32_t j =
+              block_pick<BLOCK>(pn, [&](uint32_t jj) { return ld_u64(&praw[p0 + jj]); }, sh.ring_b[pi], st, sh);
+          if (j == kUnseen) {
+            ok = false;
+          } else {
+            v = a.in_idx[sh.rrs[pi] + j];
+            if (tid == 0 && hbase + 1 < a.stage_cap) a.stage[hbase + 1] = v;
+            written = 2;
+            dv = d - 2;
           }
-          pick = j != kUnseen ? a.in_idx[sh.rrs[pi] + j] : kUnseen;
-          if (pick != kUnseen && lane == 0 && sh.base + 1 < a.stage_cap) a.stage[sh.base + 1] = pick;
-          written = 2;
-          v = pick;
-          dv = d - 2;
         }
       }
-      if (pick == kUnseen) {
-        if (lane == 0) atomicOr(a.flags, kErrBacktrack);
-        dv = 0;
-      }
-    } else if (wid == 0 && shortcut) {
+    } else if (dv && shortcut) {
       // shortcut without the ring cache (t has many in-neighbours): the
-      // first step recomputes raw_w
+      // first step recomputes raw_w, on wave 0 (every thread draws, so the
+      // streams stay identical for the next steps)
       const uint64_t r = bounded(st, w_short);
-      uint64_t acc = 0;
-      uint32_t pick = kUnseen;
-      for (uint32_t e = tb; e < te; ++e) {
-        const uint32_t w = a.in_idx[e];
-        const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
-        uint64_t x = 0;
-        for (uint32_t f = ub + lane; f < ue; f += kWave) {
-          const uint32_t u = a.in_idx[f];
-          x += bits.count(u);
+      if (wid == 0) {
+        uint64_t acc = 0;
+        uint32_t pick = kUnseen;
+        for (uint32_t e = tb; e < te; ++e) {
+          const uint32_t w = a.in_idx[e];
+          const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
+          uint64_t x = 0;
+          for (uint32_t f = ub + lane; f < ue; f += kWave) x += bits.count(a.in_idx[f]);
+          acc += wave_sum_u64(x);
+          if (acc > r) {
+            pick = w;
+            break;
+          }
         }
-        acc += wave_sum_u64(x);
-        if (acc > r) {
-          pick = w;
-          break;
-        }
+        if (lane == 0) sh.pick = pick;
       }
+      __syncthreads();
+      const uint32_t pick = sh.pick;
       if (pick == kUnseen) {
-        if (lane == 0) atomicOr(a.flags, kErrBacktrack);
-        dv = 0;
+        ok = false;
       } else {
-        if (lane == 0 && sh.base < a.stage_cap) a.stage[sh.base] = pick;
-        written = 1;
         v = pick;
+        if (tid == 0 && hbase < a.stage_cap) a.stage[hbase] = v;
+        written = 1;
         dv = d - 1;
       }
     }
-    if (wid == 0) {
-      const uint64_t base = sh.base;
-      while (dv >= 2) {
-        const uint32_t want = dv - 1;
-        const uint32_t vb = a.in_ptr[v], ve = a.in_ptr[v + 1];
-        uint32_t pick = kUnseen;
-        if (ve - vb <= 4 * kWave) {
-          // one pass: candidates held in registers between the sum and the pick
-          uint64_t xs[4];
-          uint32_t ws[4];
-          uint64_t W = 0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const uint32_t e = vb + k * kWave + lane;
-            xs[k] = 0;
-            ws[k] = 0;
-            if (e < ve) {
-              const uint32_t w = a.in_idx[e];
-              ws[k] = w;
-              xs[k] = pred_weight(bits, rec, w, want);
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < 4; ++k) W += wave_sum_u64(xs[k]);
-          if (W) {
-            const uint64_t r = bounded(st, W);
-            uint64_t acc = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const uint64_t incl = acc + wave_incl_scan_u64(xs[k]);
-              const uint64_t hit = __ballot(incl > r);
-              if (hit && pick == kUnseen)
-                pick = __shfl(ws[k], __ffsll(static_cast<unsigned long long>(hit)) - 1, kWave);
-              acc = shfl_u64(incl, kWave - 1);
-            }
-          }
-        } else {
-          uint64_t W = 0;
-          for (uint32_t cb = vb; cb < ve; cb += kWave) {
-            const uint32_t e = cb + lane;
-            uint64_t x = 0;
-            if (e < ve) {
-              const uint32_t w = a.in_idx[e];
-              x = pred_weight(bits, rec, w, want);
-            }
-            W += wave_sum_u64(x);
-          }
-          if (W) {
-            const uint64_t r = bounded(st, W);
-            uint64_t acc = 0;
-            for (uint32_t cb = vb; cb < ve; cb += kWave) {
-              const uint32_t e = cb + lane;
-              uint64_t x = 0;
-              uint32_t w = 0;
-              if (e < ve) {
-                w = a.in_idx[e];
-                x = pred_weight(bits, rec, w, want);
-              }
-              const uint64_t incl = acc + wave_incl_scan_u64(x);
-              const uint64_t hit = __ballot(incl > r);
-              if (hit) {
-                pick = __shfl(w, __ffsll(static_cast<unsigned long long>(hit)) - 1, kWave);
-                break;
-              }
-              acc = shfl_u64(incl, kWave - 1);
-            }
-          }
-        }
-        if (pick == kUnseen) {
-          if (lane == 0) atomicOr(a.flags, kErrBacktrack);
-          break;
-        }
-        if (lane == 0 && base + written < a.stage_cap) a.stage[base + written] = pick;
-        ++written;
-        v = pick;
-        --dv;
+    while (ok && dv >= 2) {
+      const uint32_t want = dv - 1;
+      const uint32_t vb = a.in_ptr[v], ve = a.in_ptr[v + 1];
+      const uint32_t j = block_pick<BLOCK>(
+          ve - vb, [&](uint32_t jj) { return pred_weight(bits, rec, a.in_idx[vb + jj], want); }, 0, st, sh);
+      if (j == kUnseen) {
+        ok = false;
+        break;
       }
-      if (lane == 0) {
-        a.stage_pos[idx] = base;
-        a.he_len[idx] = len;
-        if (a.st_out) {
-          a.st_out[2 * size_t(idx)] = s;
-          a.st_out[2 * size_t(idx) + 1] = t;
-        }
-        if (a.dist_out) a.dist_out[idx] = d;
+      v = a.in_idx[vb + j];
+      if (tid == 0 && hbase + written < a.stage_cap) a.stage[hbase + written] = v;
+      ++written;
+      --dv;
+    }
+    if (tid == 0) {
+      if (!ok) atomicOr(a.flags, kErrBacktrack);
+      a.stage_pos[idx] = hbase;
+      a.he_len[idx] = len;
+      if (a.st_out) {
+        a.st_out[2 * size_t(idx)] = s;
+        a.st_out[2 * size_t(idx) + 1] = t;
       }
+      if (a.dist_out) a.dist_out[idx] = d;
     }
     __syncthreads();
     // the records keep this BFS's stamp (older than any later one); only

@@ -237,3 +237,38 @@ def test_grid_configuration_sampled(ctx, L):
 def test_ba_1e5_configuration_sampled(ctx):
     say("BA n=1e5: 50000 samples")
     check_sampled(ctx, inputs.ba_graph(100_000, 5, 7), 2, 9, 0, 50000, 40)
+
+
+@pytest.mark.parametrize("variant", ["hbm128", "hbm512"])
+def test_hub_targets_without_ring_cache(ctx, variant, monkeypatch):
+    # Targets with more in-neighbours than the ring cache (256 entries for
+    # workgroups below 512 threads, 512 from 512 up) take the uncached 2-hop
+    # test; with d >= 3 its first backtrack step is followed by ordinary
+    # steps, which must draw from the same stream on every thread.  The
+    # indices are selected from the GPU's own (s, t, d) output; every
+    # selected hyperedge and (s, t, d) is recomputed by the oracle.
+    monkeypatch.setenv("CENTRA_SAMPLER_VARIANT", variant)
+    cache = 512 if variant == "hbm512" else 256
+    g = inputs.ba_graph(1_000_000, 5, 1)
+    count = 200_000
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        say(f"hub targets ({variant}): {count} samples on BA n=1e6")
+        off, nodes, st, dist = binding.sample_paths(ctx, dg, 1, 0, 0, count, with_st=True)
+        torch.cuda.synchronize()
+        c_bits = dg.info()[1]
+    finally:
+        dg.release()
+    off, nodes = off_np(off), nodes_np(nodes)
+    st = st.cpu().numpy().view(np.uint32)[: 2 * count]
+    d = dist.cpu().numpy().view(np.uint32)[:count]
+    t = st[1::2].astype(np.int64)
+    indeg = (g.row_ptr[t + 1] - g.row_ptr[t]).astype(np.int64)   # undirected: in-degree = degree
+    sel = np.nonzero((indeg > cache) & (d >= 3) & (d != 0xFFFFFFFF))[0][:30]
+    say(f"  {len(sel)} selected samples")
+    assert len(sel) >= 2
+    og = oracle.OracleGraph(g)
+    for i in sel:
+        h, info = oracle.sample_path(g, 1, 0, int(i), c_bits=c_bits, og=og)
+        assert np.array_equal(nodes[int(off[i]):int(off[i + 1])], h), i
+        assert (st[2 * i], st[2 * i + 1], d[i]) == (info.s, info.t, info.dist), i
