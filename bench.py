@@ -158,19 +158,27 @@ def main():
     total = time.perf_counter() - t_start
     st = binding.centra_sampler_stats_get(ctx)
     rc, picks, res, itlog = results[-1]
-    # time to certified: the same doubling schedule without the 4M cap (outside the timed steps)
-    uncapped = None
-    if args.uncapped_max > 0:
+    # time to certified (outside the timed steps): the same doubling schedule
+    # without the 4M cap, and the paper's own schedule (growth 1.2 with the
+    # optimistic guess)
+    def uncapped_run(num, den, schedule):
         torch.cuda.synchronize()
         tu = time.perf_counter()
         urc, upicks, ures, ulog = binding.centra_progressive(
             ctx, dg.handle, W["k"], W["t"], W["eps"], W["delta"], W["seed"], W["instance"], W["m_init"],
-            args.uncapped_max, W["growth"], 1, stream=stream)
+            args.uncapped_max, num, den, stream=stream, schedule=schedule)
         torch.cuda.synchronize()
-        uncapped = {"time_s": round(time.perf_counter() - tu, 3), "certified": bool(ures.certified),
-                    "m_final": int(ures.m_final), "iterations": int(ures.iterations), "eta": ures.eta,
-                    "c_hat": ures.c_hat, "picks_head": [int(x) for x in upicks[:10]]}
+        return {"time_s": round(time.perf_counter() - tu, 3), "certified": bool(ures.certified),
+                "m_final": int(ures.m_final), "iterations": int(ures.iterations),
+                "m_schedule": [int(it.m) for it in ulog], "eta": ures.eta, "c_hat": ures.c_hat,
+                "picks_head": [int(x) for x in upicks[:10]]}
+
+    uncapped = adaptive = None
+    if args.uncapped_max > 0:
+        uncapped = uncapped_run(W["growth"], 1, binding.CENTRA_SCHEDULE_GEOMETRIC)
         log(f"uncapped: {uncapped}")
+        adaptive = uncapped_run(6, 5, binding.CENTRA_SCHEDULE_ADAPTIVE)
+        log(f"adaptive: {adaptive}")
     dg.release()
     binding.centra_destroy(ctx)
 
@@ -211,6 +219,8 @@ def main():
         (uncapped["time_s"] if uncapped and uncapped["certified"] else None),
         "time_to_cap_s": None if res.certified else round(sum(times) / len(times), 3),
         "uncapped_run": uncapped,
+        "time_to_certified_adaptive_s": adaptive["time_s"] if adaptive and adaptive["certified"] else None,
+        "uncapped_adaptive_run": adaptive,
         "certified": bool(res.certified),
         "m_final": int(res.m_final),
         "iterations": int(res.iterations),

@@ -38,7 +38,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 1u
+#define CENTRA_ABI_VERSION 2u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -202,12 +202,30 @@ CENTRA_API int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t
 
 /* ------------------------------------------------------------------ */
 /* Algorithm 1 (CentRA).  Iteration i = 1, 2, ...: delta_i = delta / 2^i;
- * m_1 = m_init, m_{i+1} = min(ceil(m_i * growth_num / growth_den), m_max);
  * the sample is extended to m_i hyperedges (samples 0 .. m_i-1 of (seed,
- * instance)), then greedyCover, the AMCERA and the bound; returns as soon
- * as the stopping condition holds.  Inputs: k >= 1, 1 <= t <= 1024,
- * eps in (0, 1-1/e), delta in (0,1), 1 <= m_init <= m_max < 2^31,
- * growth_num > growth_den >= 1. */
+ * instance)), then greedyCover, the AMCERA and the bound of Theorem
+ * bound_dev; returns as soon as the stopping condition holds.  The sample
+ * schedule (procedure samplingSchedule of Algorithm 1, Section 4):
+ *   CENTRA_SCHEDULE_GEOMETRIC: m_1 = m_init,
+ *     m_{i+1} = min(ceil(m_i * growth_num / growth_den), m_max);
+ *   CENTRA_SCHEDULE_ADAPTIVE: the geometric step combined with the paper's
+ *     optimistic guess, m_{i+1} = min(max(geometric step, m_opt), m_max),
+ *     where m_opt = ceil(m) for the m > 0 solving
+ *     sqrt(2 L / m) + L / (3 m) = eps * C_i / (1 - 1/e), i.e. eta of
+ *     Theorem bound_dev with R = 0 and nu = 1 set equal to the largest
+ *     value the stopping condition can accept; L = ln(5 / delta_{i+1}),
+ *     C_i = coverage_i / m_i of the iteration just finished (m_opt = 0
+ *     when C_i = 0); growth_num / growth_den = 6 / 5 is the paper's 1.2;
+ *   CENTRA_SCHEDULE_FIXED: a single iteration at m = m_init whose bound
+ *     uses delta itself (the fixed-sample-size use of Theorem bound_dev,
+ *     Section 5), returning its stopping test.
+ * Inputs: k >= 1, 1 <= t <= 1024, eps in (0, 1-1/e), delta in (0,1),
+ * 1 <= m_init <= m_max < 2^31, growth_num > growth_den >= 1, schedule one
+ * of the three values. */
+#define CENTRA_SCHEDULE_GEOMETRIC 0u
+#define CENTRA_SCHEDULE_ADAPTIVE 1u
+#define CENTRA_SCHEDULE_FIXED 2u
+
 typedef struct {
     uint32_t k, t;
     double eps, delta;
@@ -215,6 +233,7 @@ typedef struct {
     uint32_t instance;
     uint64_t m_init, m_max;
     uint32_t growth_num, growth_den;
+    uint32_t schedule;   /* CENTRA_SCHEDULE_* */
 } centra_params;
 
 typedef struct {

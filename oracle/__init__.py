@@ -97,7 +97,11 @@ def _load():
     lib.orc_bound.restype = None
     lib.orc_progressive.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint32, c.c_uint32, c.c_double,
                                     c.c_double, c.c_uint64, c.c_uint32, c.c_uint64, c.c_uint64,
-                                    c.c_uint32, c.c_uint32, _u32p, c.POINTER(Result)]
+                                    c.c_uint32, c.c_uint32, c.c_uint32, _u32p, c.POINTER(Result),
+                                    _u64p, c.c_uint32]
+    lib.orc_next_sample_size.argtypes = [c.c_uint64, c.c_double, c.c_double, c.c_double, c.c_uint32,
+                                         c.c_uint32, c.c_uint64, c.c_uint32]
+    lib.orc_next_sample_size.restype = c.c_uint64
     lib.orc_progressive.restype = c.c_int
     _lib = lib
     return lib
@@ -224,15 +228,29 @@ def bound(m, cov, sum_topk, t, deg_topk, b_max, eps, delta_i) -> BoundOut:
     return out
 
 
+SCHEDULE_GEOMETRIC, SCHEDULE_ADAPTIVE, SCHEDULE_FIXED = 0, 1, 2
+
+
+def next_sample_size(m_i, c_hat, eps, delta_next, growth_num, growth_den, m_max, schedule):
+    """samplingSchedule of Algorithm 1: m_{i+1} after an iteration at m_i."""
+    return int(_load().orc_next_sample_size(m_i, c_hat, eps, delta_next, growth_num, growth_den, m_max,
+                                            schedule))
+
+
 def progressive(g, k, t, eps, delta, seed, instance, m_init, m_max, growth_num=2, growth_den=1,
-                c_bits=None):
-    """Algorithm 1 with a geometric schedule; returns (rc, picks, Result)."""
+                c_bits=None, schedule=SCHEDULE_GEOMETRIC, with_m_log=False):
+    """Algorithm 1; returns (rc, picks, Result) and, with with_m_log, the
+    sample size of every iteration."""
     og = OracleGraph(g)
     lib = _load()
     if c_bits is None:
         c_bits = lib.orc_count_bits(ctypes.byref(og.c))
     picks = np.zeros(max(1, k), dtype=np.uint32)
     res = Result()
+    m_log = np.zeros(256, dtype=np.uint64)
     rc = lib.orc_progressive(ctypes.byref(og.c), c_bits, k, t, eps, delta, seed, instance, m_init, m_max,
-                             growth_num, growth_den, picks, ctypes.byref(res))
-    return rc, picks[: res.n_picked].copy(), res
+                             growth_num, growth_den, schedule, picks, ctypes.byref(res), m_log, len(m_log))
+    out = (rc, picks[: res.n_picked].copy(), res)
+    if with_m_log:
+        out = out + ([int(x) for x in m_log[: min(res.iterations, len(m_log))]],)
+    return out

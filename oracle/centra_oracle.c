@@ -518,14 +518,36 @@ void orc_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t,
 
 /* ------------------------------------------------------------------ */
 /* Algorithm 1 (progressive sampling), readings R1 and R10. */
+uint64_t orc_next_sample_size(uint64_t m_i, double c_hat, double eps, double delta_next,
+                              uint32_t growth_num, uint32_t growth_den, uint64_t m_max,
+                              uint32_t schedule)
+{
+    u128 geo = ((u128)m_i * growth_num + growth_den - 1) / growth_den;
+    uint64_t next = geo > m_max ? m_max : (uint64_t)geo;
+    if (schedule != 1 || !(c_hat > 0.0)) return next;
+    /* the optimistic eta, sqrt(2L/m) + L/(3m), is at most the target
+     * T = eps*c_hat/a exactly when y = 1/sqrt(m) is at most the positive
+     * root of (L/3) y^2 + sqrt(2L) y - T = 0, that is
+     * y = 2T / (sqrt(2L) + sqrt(2L + 4LT/3)); hence m = (1/y)^2 */
+    const double a = 1.0 - exp(-1.0);
+    const double L = log(5.0 / delta_next);
+    const double T = eps * c_hat / a;
+    const double inv_y = (sqrt(2.0 * L) + sqrt(2.0 * L + 4.0 * L * T / 3.0)) / (2.0 * T);
+    const double m = inv_y * inv_y;
+    const uint64_t opt = m < (double)m_max ? (uint64_t)ceil(m) : m_max;
+    return opt > next ? opt : next;
+}
+
 int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                     double eps, double delta, uint64_t seed, uint32_t instance,
                     uint64_t m_init, uint64_t m_max, uint32_t growth_num,
-                    uint32_t growth_den, uint32_t *picks, orc_result *res)
+                    uint32_t growth_den, uint32_t schedule, uint32_t *picks,
+                    orc_result *res, uint64_t *m_log, uint32_t m_log_cap)
 {
     const double a = 1.0 - exp(-1.0);
     if (k == 0 || t == 0 || !(eps > 0.0 && eps < a) || !(delta > 0.0 && delta < 1.0) ||
-        m_init == 0 || m_max < m_init || growth_den == 0 || growth_num <= growth_den)
+        m_init == 0 || m_max < m_init || growth_den == 0 || growth_num <= growth_den ||
+        schedule > 2)
         return -1;
     uint64_t cap = 1024;
     uint64_t *he_off = malloc(sizeof(uint64_t) * (m_max + 1));
@@ -540,7 +562,9 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
     int rc = 1;
     memset(res, 0, sizeof(*res));
     for (uint32_t i = 1;; i++) {
-        const double delta_i = ldexp(delta, -(int)i);
+        /* the fixed-size use bounds one sample with delta itself */
+        const double delta_i = schedule == 2 ? delta : ldexp(delta, -(int)i);
+        if (m_log && i <= m_log_cap) m_log[i - 1] = m_i;
         for (uint64_t s = m_prev; s < m_i; s++) {
             uint32_t len = sample_one(g, c_bits, seed, instance, s, h, NULL, &b);
             if (he_off[s] + len > cap) {
@@ -573,10 +597,10 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
         res->r = o.r;
         res->eta = o.eta;
         if (o.certified) { rc = 0; break; }
-        if (m_i >= m_max) { rc = 1; break; }
+        if (schedule == 2 || m_i >= m_max) { rc = 1; break; }
         m_prev = m_i;
-        u128 next = ((u128)m_i * growth_num + growth_den - 1) / growth_den;
-        m_i = next > m_max ? m_max : (uint64_t)next;
+        m_i = orc_next_sample_size(m_i, o.c_hat, eps, ldexp(delta, -(int)(i + 1)), growth_num,
+                                   growth_den, m_max, schedule);
     }
     bfs_free(&b);
     free(he_off); free(he_nodes); free(h); free(cov_cum); free(topk);

@@ -146,9 +146,21 @@ void orc_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t,
                uint64_t deg_topk, uint32_t b_max, double eps, double delta_i,
                orc_bound_out *out);
 
-/* Algorithm 1 with a geometric schedule m_{i+1} = min(ceil(m_i*num/den),
- * m_max).  picks has capacity k.  Returns 0 if certified, 1 if m_max was
- * reached without certification, negative on error. */
+/* samplingSchedule of Algorithm 1 (Section 4).  Geometric (schedule 0):
+ * min(ceil(m_i*num/den), m_max).  Adaptive (schedule 1): the larger of
+ * that and the optimistic size, the m at which eta of Theorem bound_dev
+ * with R = 0 and nu = 1 (sqrt(2L/m) + L/(3m), L = ln(5/delta_next)) equals
+ * eps*c_hat/(1-1/e), rounded up and capped at m_max; c_hat = 0 gives no
+ * optimistic size. */
+uint64_t orc_next_sample_size(uint64_t m_i, double c_hat, double eps, double delta_next,
+                              uint32_t growth_num, uint32_t growth_den, uint64_t m_max,
+                              uint32_t schedule);
+
+/* Algorithm 1.  schedule: 0 geometric, 1 adaptive (orc_next_sample_size),
+ * 2 fixed: one iteration at m_init whose bound uses delta itself.  picks
+ * has capacity k; m_log (optional) receives m_i of iterations 1 ..
+ * min(iterations, m_log_cap).  Returns 0 if certified, 1 if not (m_max
+ * reached, or the fixed iteration's test failed), negative on error. */
 typedef struct {
     uint32_t n_picked, iterations;
     int certified;
@@ -159,7 +171,8 @@ typedef struct {
 int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                     double eps, double delta, uint64_t seed, uint32_t instance,
                     uint64_t m_init, uint64_t m_max, uint32_t growth_num,
-                    uint32_t growth_den, uint32_t *picks, orc_result *res);
+                    uint32_t growth_den, uint32_t schedule, uint32_t *picks,
+                    orc_result *res, uint64_t *m_log, uint32_t m_log_cap);
 
 #ifdef __cplusplus
 }

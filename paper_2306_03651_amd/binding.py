@@ -23,6 +23,10 @@ CENTRA_EHIP = -3
 CENTRA_ENOSPC = -4
 CENTRA_ENOTSUP = -5
 
+CENTRA_SCHEDULE_GEOMETRIC = 0
+CENTRA_SCHEDULE_ADAPTIVE = 1
+CENTRA_SCHEDULE_FIXED = 2
+
 _c = ctypes
 _vp = _c.c_void_p
 
@@ -47,7 +51,8 @@ class BoundOut(_c.Structure):
 class Params(_c.Structure):
     _fields_ = [("k", _c.c_uint32), ("t", _c.c_uint32), ("eps", _c.c_double), ("delta", _c.c_double),
                 ("seed", _c.c_uint64), ("instance", _c.c_uint32), ("m_init", _c.c_uint64),
-                ("m_max", _c.c_uint64), ("growth_num", _c.c_uint32), ("growth_den", _c.c_uint32)]
+                ("m_max", _c.c_uint64), ("growth_num", _c.c_uint32), ("growth_den", _c.c_uint32),
+                ("schedule", _c.c_uint32)]
 
 
 class Result(_c.Structure):
@@ -235,9 +240,10 @@ def centra_bound(m: int, cov: int, sum_topk: int, t: int, deg_topk: int, b_max: 
 
 
 def centra_progressive(ctx, g, k: int, t: int, eps: float, delta: float, seed: int, instance: int, m_init: int,
-                       m_max: int, growth_num: int = 2, growth_den: int = 1, log_cap: int = 64, stream=None):
+                       m_max: int, growth_num: int = 2, growth_den: int = 1, log_cap: int = 64, stream=None,
+                       schedule: int = CENTRA_SCHEDULE_GEOMETRIC):
     """Returns (rc, picks np.uint32[n_picked], Result, [Iteration])."""
-    p = Params(k, t, eps, delta, seed, instance, m_init, m_max, growth_num, growth_den)
+    p = Params(k, t, eps, delta, seed, instance, m_init, m_max, growth_num, growth_den, schedule)
     picks = np.zeros(max(1, k), dtype=np.uint32)
     res = Result()
     log = (Iteration * max(1, log_cap))()

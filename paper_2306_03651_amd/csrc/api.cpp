@@ -55,6 +55,28 @@ void bound_eval(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t
   o->certified = a * ((a - eps) * xi + eta) <= eps * C ? 1 : 0;
 }
 
+// Next sample size (samplingSchedule of Algorithm 1): the geometric step,
+// and for the adaptive schedule the optimistic size when larger.  That size
+// is where eta of Theorem bound_dev with R = 0 and nu = 1,
+// sqrt(2L/m) + L/(3m), reaches T = eps * C / (1 - 1/e): with y = 1/sqrt(m)
+// the quadratic (L/3) y^2 + sqrt(2L) y - T = 0 has the positive root
+// y = 2T / (sqrt(2L) + sqrt(2L + 4LT/3)) (no cancellation), so m = (1/y)^2.
+uint64_t next_sample_size(const centra_params* p, uint64_t m_i, double c_hat, double delta_next) {
+  const unsigned __int128 geo =
+      (static_cast<unsigned __int128>(m_i) * p->growth_num + p->growth_den - 1) / p->growth_den;
+  uint64_t next = geo > p->m_max ? p->m_max : static_cast<uint64_t>(geo);
+  if (p->schedule == CENTRA_SCHEDULE_ADAPTIVE && c_hat > 0.0) {
+    const double a = 1.0 - exp(-1.0);
+    const double L = log(5.0 / delta_next);
+    const double T = p->eps * c_hat / a;
+    const double inv_y = (sqrt(2.0 * L) + sqrt(2.0 * L + 4.0 * L * T / 3.0)) / (2.0 * T);
+    const double m = inv_y * inv_y;
+    const uint64_t opt = m < static_cast<double>(p->m_max) ? static_cast<uint64_t>(ceil(m)) : p->m_max;
+    if (opt > next) next = opt;
+  }
+  return next;
+}
+
 float elapsed(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 0.f;
@@ -270,6 +292,8 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
     return fail(ctx, CENTRA_EINVAL, "progressive: bad m_init / m_max");
   if (p->growth_den == 0 || p->growth_num <= p->growth_den)
     return fail(ctx, CENTRA_EINVAL, "progressive: growth must exceed 1");
+  if (p->schedule > CENTRA_SCHEDULE_FIXED) return fail(ctx, CENTRA_EINVAL, "progressive: unknown schedule");
+  const bool fixed = p->schedule == CENTRA_SCHEDULE_FIXED;
   DeviceGuard guard(ctx->device);
   hipStream_t s = as_stream(stream);
   memset(res, 0, sizeof(*res));
@@ -291,7 +315,8 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
   hipEvent_t* ev = ctx->ev;
   uint64_t m_prev = 0, m_i = p->m_init, total_nodes = 0;
   for (uint32_t i = 1;; ++i) {
-    const double delta_i = ldexp(p->delta, -static_cast<int>(i));
+    // the fixed-size use bounds one sample with delta itself
+    const double delta_i = fixed ? p->delta : ldexp(p->delta, -static_cast<int>(i));
     CENTRA_HIP(ctx, hipEventRecord(ev[0], s));
     uint64_t added = 0;
     const uint32_t cnt = static_cast<uint32_t>(m_i - m_prev);
@@ -373,11 +398,9 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
       it.ms_mcera = ms_m;
     }
     if (o.certified) return CENTRA_OK;
-    if (m_i >= p->m_max) return CENTRA_NOT_CERTIFIED;
+    if (fixed || m_i >= p->m_max) return CENTRA_NOT_CERTIFIED;
     m_prev = m_i;
-    const unsigned __int128 nx =
-        (static_cast<unsigned __int128>(m_i) * p->growth_num + p->growth_den - 1) / p->growth_den;
-    m_i = nx > p->m_max ? p->m_max : static_cast<uint64_t>(nx);
+    m_i = next_sample_size(p, m_i, o.c_hat, ldexp(p->delta, -static_cast<int>(i + 1)));
   }
 }
 

@@ -13,14 +13,16 @@ pytestmark = pytest.mark.gpu
 FIELDS = ["c_hat", "amcera", "wimpy", "xi", "nu", "rtilde", "r", "eta"]
 
 
-def compare(g, ctx, k, t, eps, delta, seed, inst, m_init, m_max, num=2, den=1):
+def compare(g, ctx, k, t, eps, delta, seed, inst, m_init, m_max, num=2, den=1,
+            schedule=binding.CENTRA_SCHEDULE_GEOMETRIC):
     dg = binding.DeviceGraph(ctx, g)
     try:
         rc, picks, res, log = binding.centra_progressive(ctx, dg.handle, k, t, eps, delta, seed, inst, m_init,
-                                                         m_max, num, den)
+                                                         m_max, num, den, schedule=schedule)
     finally:
         dg.release()
-    wrc, wpicks, wres = oracle.progressive(g, k, t, eps, delta, seed, inst, m_init, m_max, num, den)
+    wrc, wpicks, wres, wlog = oracle.progressive(g, k, t, eps, delta, seed, inst, m_init, m_max, num, den,
+                                                 schedule=schedule, with_m_log=True)
     assert rc == wrc
     assert np.array_equal(picks, wpicks)
     assert res.iterations == wres.iterations and res.m_final == wres.m_final
@@ -28,10 +30,12 @@ def compare(g, ctx, k, t, eps, delta, seed, inst, m_init, m_max, num=2, den=1):
     assert res.certified == wres.certified
     for f in FIELDS:
         assert getattr(res, f) == pytest.approx(getattr(wres, f), rel=1e-12, abs=1e-300), f
-    sched = [m_init]
-    while len(sched) < res.iterations:
-        sched.append(min(-(-sched[-1] * num // den), m_max))
-    assert [it.m for it in log] == sched
+    assert [it.m for it in log] == wlog
+    if schedule == binding.CENTRA_SCHEDULE_GEOMETRIC:
+        sched = [m_init]
+        while len(sched) < res.iterations:
+            sched.append(min(-(-sched[-1] * num // den), m_max))
+        assert wlog == sched
     assert [it.i for it in log] == list(range(1, res.iterations + 1))
     return res
 
@@ -56,3 +60,30 @@ def test_directed_and_non_doubling_schedule(ctx):
     g = inputs.rmat_graph(11, 8, seed=2)
     say("progressive rmat11 growth 6/5")
     compare(g, ctx, 7, 33, 0.2, 0.05, 3, 2, 3000, 20000, 6, 5)
+
+
+def test_adaptive_schedule(ctx):
+    # the paper's schedule: growth 1.2 combined with the optimistic guess
+    g = inputs.ba_graph(2000, 5, 1)
+    say("progressive C1 adaptive")
+    res = compare(g, ctx, 10, 10, 0.05, 0.1, 1, 0, 2000, 1_280_000, 6, 5, schedule=binding.CENTRA_SCHEDULE_ADAPTIVE)
+    assert res.certified
+
+
+def test_fixed_schedule(ctx):
+    g = inputs.rmat_graph(11, 8, seed=2)
+    say("progressive fixed m")
+    for m in [500, 20000]:
+        res = compare(g, ctx, 7, 33, 0.2, 0.05, 3, 2, m, m, schedule=binding.CENTRA_SCHEDULE_FIXED)
+        assert res.iterations == 1 and res.m_final == m
+
+
+def test_bad_schedule_rejected(ctx):
+    g = inputs.ba_graph(300, 2, 1)
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        with pytest.raises(binding.CentraError) as e:
+            binding.centra_progressive(ctx, dg.handle, 3, 4, 0.1, 0.1, 1, 0, 10, 100, schedule=7)
+        assert e.value.code == binding.CENTRA_EINVAL
+    finally:
+        dg.release()
