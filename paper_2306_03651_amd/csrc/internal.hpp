@@ -28,7 +28,7 @@ struct centra_ctx {
   // per-BFS slot arrays (node records {count, stamp and level}, visit
   // queue, stored pair counts), one set per concurrent BFS, sized for the
   // largest graph
-  centra::DevBuf slot_rec, slot_q, slot_praw;
+  centra::DevBuf slot_rec, slot_q, slot_praw, slot_pinfo;
   uint32_t slots = 0;
   uint32_t slot_n = 0;
   uint32_t stamp_next = 1;   // BFS stamp of the next sample (records start at stamp 0)

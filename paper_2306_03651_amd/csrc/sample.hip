@@ -83,6 +83,7 @@ struct SampleArgs {
   uint64_t* rec;      // slots * n records of two words: sigma', level
   uint32_t* q;        // slots * n
   uint64_t* praw;     // slots * kPairMax: raw count of each pair's u from the last cone test
+  uint32_t* pinfo;    // slots * 3 * kPairMax: per pair its u, in_ptr[u] and in-degree of u
   uint32_t stamp0;    // stamp of work item 0; item i has stamp0 + i
   uint32_t bit_words;
   uint32_t* work;     // work counter
@@ -111,6 +112,10 @@ struct Ring {
 };
 constexpr uint32_t kPairMax = 65536;
 constexpr uint64_t kConeRatio = 3;
+// The 2-hop test runs at a level only when its pairs are at most kPairRatio
+// times the out-arcs expanding that level would scan (a pair costs a
+// sequential read and an LDS probe, an expanded arc a random atomic).
+constexpr uint64_t kPairRatio = 4;
 
 // Record accessors: word 0 = sigma', word 1 = tag.  With base = stamp << 32
 // the tag of a node at level l of the current BFS is base + (kUnseen - l):
@@ -221,21 +226,21 @@ __device__ __forceinline__ typename std::conditional<LDS_BITS, BitsLds, BitsRec>
 }
 
 // Raw counts of one chunk of nodes, one node u per thread (kUnseen for
-// none): sh.sg[tid] = sum of sigma' over u's visited in-neighbours, 0 for a
-// visited u.  For an unvisited u every visited in-neighbour is at the last
+// none) with its in-row (start rs_u, length deg_u): sh.sg[tid] = sum of
+// sigma' over u's visited in-neighbours, 0 for a visited u.  For an unvisited u every visited in-neighbour is at the last
 // produced level (a lower one would have put u in a produced level), so
 // this is u's raw count one level below.  Load balanced like the
 // expansion: in-degrees prefix-summed in LDS, UNROLL entries per thread
 // per round, sources found by binary search.  Adds the entries scanned to
 // n_arcs.  Contains barriers; sh.sg is valid on return until the next call.
 template <int BLOCK, int UNROLL, typename Bits>
-__device__ void raw_counts_chunk(const SampleArgs& a, const Bits& bits, uint64_t* rec, uint32_t u, uint32_t L,
-                                 SampleShared<BLOCK>& sh, uint64_t& n_arcs) {
+__device__ void raw_counts_chunk(const SampleArgs& a, const Bits& bits, uint64_t* rec, uint32_t u, uint32_t rs_u,
+                                 uint32_t deg_u, uint32_t L, SampleShared<BLOCK>& sh, uint64_t& n_arcs) {
   const int tid = threadIdx.x;
   uint32_t deg = 0, rs = 0;
   if (u != kUnseen && !bits.done(u, L)) {
-    rs = a.in_ptr[u];
-    deg = a.in_ptr[u + 1] - rs;
+    rs = rs_u;
+    deg = deg_u;
   }
   uint32_t total;
   const uint32_t off = block_excl_scan_u32<BLOCK>(deg, &total, sh.scan);
@@ -382,6 +387,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   uint64_t* rec = a.rec + 2 * slot * a.n;
   uint32_t* q = a.q + slot * a.n;
   uint64_t* praw = a.praw + slot * kPairMax;
+  uint32_t* pu = a.pinfo + slot * 3 * kPairMax;   // per pair: u, in_ptr[u], in-degree of u
+  uint32_t* prs = pu + kPairMax;
+  uint32_t* pdg = prs + kPairMax;
   using Bits = typename std::conditional<LDS_BITS, BitsLds, BitsRec>::type;
   Bits bits = make_bits<LDS_BITS>(dyn_bits, rec, sh.bloom);
   const uint64_t lane_lt = (1ull << lane) - 1ull;
@@ -421,12 +429,13 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
 
     // Rings around t: R1 = in(t), the pairs (w in R1, u in in(w)) and, if
     // the cone is small enough, in(u) for those u.  poff[i] = number of
-    // pairs before R1's i-th entry.
+    // pairs before R1's i-th entry.  The cone's size (CSR entries a 3-hop
+    // test scans) is summed lazily: pairs [0, cpos) so far.
     const uint32_t tb = a.in_ptr[t], te = a.in_ptr[t + 1];
     const uint32_t dt = te - tb;
     const bool rings = dt <= Ring<BLOCK>::kCache;
-    uint32_t pairs = 0;
-    uint64_t cone = ~0ull;   // CSR entries scanned by a 3-hop test (~0: no 3-hop test)
+    uint32_t pairs = 0, cpos = 0;
+    uint64_t cone_part = 0;
     if (rings) {
       for (uint32_t cb = 0; cb < dt; cb += BLOCK) {
         const uint32_t i = cb + tid;
@@ -444,17 +453,6 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         pairs += tot;
       }
       n_arcs += dt;
-      if (pairs <= kPairMax) {
-        __syncthreads();
-        uint64_t c = 0;
-        for (uint32_t p = tid; p < pairs; p += BLOCK) {
-          const int i = ring_of(sh.poff, dt, p);
-          const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
-          c += a.in_ptr[u + 1] - a.in_ptr[u];
-        }
-        cone = block_sum_u64<BLOCK>(c, sh.red);
-        n_arcs += pairs;
-      }
     }
     __syncthreads();
 
@@ -474,81 +472,117 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         break;
       }
       if (rings) {
-        // (2) pairs (w, u): a visited u is at level L (w is unvisited, so a
-        //     lower level would have put w in a produced level), hence w at
-        //     L+1 and d = L+2; ring_a[i] = sum of sigma'_u over visited u,
-        //     the raw count of w_i
-        for (uint32_t i = tid; i < dt; i += BLOCK) {
-          sh.ring_a[i] = 0;
-          sh.ring_b[i] = 0;
-        }
-        __syncthreads();
-        int hit2 = 0;
-        for (uint32_t p = tid; p < pairs; p += BLOCK) {
-          const int i = ring_of(sh.poff, dt, p);
-          const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
-          const uint64_t c = bits.count(u);   // 0: unvisited
-          if (c) {
-            hit2 = 1;
-            atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_a[i]), static_cast<unsigned long long>(c));
+        // out-arcs of level L (the cost of expanding it), summed in
+        // workgroup chunks only as far as a cost rule below needs: most
+        // produced levels are never expanded
+        uint32_t fpos = lb;
+        uint64_t fpart = 0;
+        auto fcost_step = [&]() {
+          const uint32_t i = fpos + tid;
+          uint64_t c = 0;
+          if (i < le) {
+            const uint32_t w = ld_u32(&q[i]);
+            c = a.row_ptr[w + 1] - a.row_ptr[w];
           }
-        }
-        n_arcs += pairs;
-        if (__syncthreads_or(hit2)) {
-          if (sumL < cap) {
-            // no count of level L+1 can need a shift (each <= S_L < 2^C)
-            d = L + 2;
-            shortcut = 2;
-            break;
+          fpart += block_sum_u64<BLOCK>(c, sh.red);
+          fpos += BLOCK;
+        };
+        const uint64_t need2 = (pairs + kPairRatio - 1) / kPairRatio;
+        while (fpos < le && fpart < need2) fcost_step();
+        if (fpart >= need2) {
+          // (2) pairs (w, u): a visited u is at level L (w is unvisited, so a
+          //     lower level would have put w in a produced level), hence w at
+          //     L+1 and d = L+2; ring_a[i] = sum of sigma'_u over visited u,
+          //     the raw count of w_i
+          for (uint32_t i = tid; i < dt; i += BLOCK) {
+            sh.ring_a[i] = 0;
+            sh.ring_b[i] = 0;
           }
-        } else {
-          // (3) cone: an unvisited u with visited in-neighbours is at L+1
-          //     (they are all at L), its w at L+2 and d = L+3.  Only when the
-          //     counts of levels L+1 and L+2 cannot need a shift (level L+1
-          //     counts <= S_L, level L+2 counts <= S_{L+1} <= S_L * max
-          //     out-degree) and expanding level L would cost more.
-          const uint64_t bound = (a.max_out_deg && sumL > ~0ull / a.max_out_deg) ? ~0ull : sumL * a.max_out_deg;
-          bool cheap = false;
-          if (cone != ~0ull && sumL < cap && bound < cap) {
-            // cone <= kConeRatio * (out-arcs of level L), summing the
-            // out-degrees only until the sum is large enough (most levels
-            // are never expanded, so the sum is not kept per level)
-            const uint64_t need = (cone + kConeRatio - 1) / kConeRatio;
-            uint64_t fcost = 0;
-            for (uint32_t cb = lb; cb < le && fcost < need; cb += BLOCK) {
-              const uint32_t i = cb + tid;
-              uint64_t c = 0;
-              if (i < le) {
-                const uint32_t w = ld_u32(&q[i]);
-                c = a.row_ptr[w + 1] - a.row_ptr[w];
-              }
-              fcost += block_sum_u64<BLOCK>(c, sh.red);
+          __syncthreads();
+          int hit2 = 0;
+          for (uint32_t p = tid; p < pairs; p += BLOCK) {
+            const int i = ring_of(sh.poff, dt, p);
+            const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
+            const uint64_t c = bits.count(u);   // 0: unvisited
+            if (c) {
+              hit2 = 1;
+              atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_a[i]), static_cast<unsigned long long>(c));
             }
-            cheap = fcost >= need;
           }
-          if (cheap) {
-            int hit3 = 0;
-            for (uint32_t cb = 0; cb < pairs; cb += BLOCK) {
-              const uint32_t p = cb + tid;
-              uint32_t u = kUnseen;
-              int i = 0;
-              if (p < pairs) {
-                i = ring_of(sh.poff, dt, p);
-                u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
-              }
-              raw_counts_chunk<BLOCK, UNROLL>(a, bits, rec, u, L, sh, n_arcs);
-              const uint64_t raw = sh.sg[tid];
-              if (p < pairs) st_u64(&praw[p], raw);
-              if (raw) {
-                hit3 = 1;
-                atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_b[i]), static_cast<unsigned long long>(raw));
-              }
-              __syncthreads();
-            }
-            if (__syncthreads_or(hit3)) {
-              d = L + 3;
-              shortcut = 3;
+          n_arcs += pairs;
+          if (__syncthreads_or(hit2)) {
+            if (sumL < cap) {
+              // no count of level L+1 can need a shift (each <= S_L < 2^C)
+              d = L + 2;
+              shortcut = 2;
               break;
+            }
+          } else if (pairs <= kPairMax) {
+            // (3) cone: an unvisited u with visited in-neighbours is at L+1
+            //     (they are all at L), its w at L+2 and d = L+3.  Only when
+            //     the counts of levels L+1 and L+2 cannot need a shift (level
+            //     L+1 counts <= S_L, level L+2 counts <= S_{L+1} <= S_L * max
+            //     out-degree) and when the cone is at most kConeRatio times
+            //     the out-arcs of level L.  That comparison grows both sums
+            //     chunk by chunk until it is decided; sizing the cone also
+            //     keeps each pair's u and in-row for the test.
+            const uint64_t bound =
+                (a.max_out_deg && sumL > ~0ull / a.max_out_deg) ? ~0ull : sumL * a.max_out_deg;
+            bool cheap = false;
+            if (sumL < cap && bound < cap) {
+              for (;;) {
+                const bool cdone = cpos >= pairs, fdone = fpos >= le;
+                if (cdone && cone_part <= kConeRatio * fpart) {
+                  cheap = true;
+                  break;
+                }
+                if (fdone && cone_part > kConeRatio * fpart) break;
+                if (!cdone && (fdone || cone_part <= kConeRatio * fpart)) {
+                  const uint32_t p = cpos + tid;
+                  uint32_t dg = 0;
+                  if (p < pairs) {
+                    const int i = ring_of(sh.poff, dt, p);
+                    const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
+                    const uint32_t r0 = a.in_ptr[u];
+                    dg = a.in_ptr[u + 1] - r0;
+                    st_u32(&pu[p], u);
+                    st_u32(&prs[p], r0);
+                    st_u32(&pdg[p], dg);
+                  }
+                  cone_part += block_sum_u64<BLOCK>(dg, sh.red);
+                  n_arcs += pairs - cpos < BLOCK ? pairs - cpos : BLOCK;
+                  cpos += BLOCK;
+                } else {
+                  fcost_step();
+                }
+              }
+            }
+            if (cheap) {
+              int hit3 = 0;
+              for (uint32_t cb = 0; cb < pairs; cb += BLOCK) {
+                const uint32_t p = cb + tid;
+                uint32_t u = kUnseen, r0 = 0, dg = 0;
+                int i = 0;
+                if (p < pairs) {
+                  i = ring_of(sh.poff, dt, p);
+                  u = ld_u32(&pu[p]);
+                  r0 = ld_u32(&prs[p]);
+                  dg = ld_u32(&pdg[p]);
+                }
+                raw_counts_chunk<BLOCK, UNROLL>(a, bits, rec, u, r0, dg, L, sh, n_arcs);
+                const uint64_t raw = sh.sg[tid];
+                if (p < pairs) st_u64(&praw[p], raw);
+                if (raw) {
+                  hit3 = 1;
+                  atomicAdd(reinterpret_cast<unsigned long long*>(&sh.ring_b[i]), static_cast<unsigned long long>(raw));
+                }
+                __syncthreads();
+              }
+              if (__syncthreads_or(hit3)) {
+                d = L + 3;
+                shortcut = 3;
+                break;
+              }
             }
           }
         }
@@ -892,32 +926,34 @@ static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
 static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, hipStream_t s) {
   {
     // never ask for more slots than kSlotMemCap holds
-    const size_t per = size_t(g->n) * (16 + 4) + kPairMax * 8;
+    const size_t per = size_t(g->n) * (16 + 4) + kPairMax * (8 + 12);
     const size_t most = kSlotMemCap / (per ? per : 1);
     if (want > most) want = most ? static_cast<uint32_t>(most) : 1u;
   }
   if (ctx->slots >= want && ctx->slot_n >= g->n) return CENTRA_OK;
   uint32_t slots = want > ctx->slots ? want : ctx->slots;
   const uint32_t n = g->n > ctx->slot_n ? g->n : ctx->slot_n;
-  const size_t per_slot = size_t(n) * (16 + 4) + kPairMax * 8;
+  const size_t per_slot = size_t(n) * (16 + 4) + kPairMax * (8 + 12);
   // at most kSlotMemCap of slot state (or the budget, if smaller)
   if (size_t(slots) * per_slot > kSlotMemCap) slots = static_cast<uint32_t>(kSlotMemCap / per_slot);
   if (slots == 0) slots = 1;
   // shrink the slot count if the budget cannot hold all of them
   for (;;) {
     const size_t need = size_t(slots) * per_slot;
-    const size_t have = ctx->slot_rec.bytes + ctx->slot_q.bytes + ctx->slot_praw.bytes;
+    const size_t have = ctx->slot_rec.bytes + ctx->slot_q.bytes + ctx->slot_praw.bytes + ctx->slot_pinfo.bytes;
     if (!ctx->budget || ctx->allocated - have + need <= ctx->budget || slots <= 1) break;
     slots /= 2;
   }
   release(ctx, ctx->slot_rec);
   release(ctx, ctx->slot_praw);
+  release(ctx, ctx->slot_pinfo);
   release(ctx, ctx->slot_q);
   ctx->slots = 0;
   ctx->slot_n = 0;
   int rc;
   if ((rc = ensure(ctx, ctx->slot_rec, size_t(slots) * n * 16, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_praw, size_t(slots) * kPairMax * 8, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->slot_pinfo, size_t(slots) * kPairMax * 12, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->slot_q, size_t(slots) * n * 4, false, s))) return rc;
   fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(slots) * n * 2, s);   // stamp 0: never claimed
   CENTRA_HIP(ctx, hipGetLastError());
@@ -970,6 +1006,7 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     a.rec = static_cast<uint64_t*>(ctx->slot_rec.ptr);
     a.q = static_cast<uint32_t*>(ctx->slot_q.ptr);
     a.praw = static_cast<uint64_t*>(ctx->slot_praw.ptr);
+    a.pinfo = static_cast<uint32_t*>(ctx->slot_pinfo.ptr);
     a.bit_words = plan.bit_words;
     a.work = work;
     a.stage = static_cast<uint32_t*>(ctx->stage_nodes.ptr);
