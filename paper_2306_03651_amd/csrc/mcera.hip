@@ -64,18 +64,30 @@ int rade_words(centra_ctx* ctx, uint64_t seed, uint32_t instance, uint64_t s0, u
 
 // ---------------------------------------------------------------------------
 constexpr int kCountBlock = 256;
-constexpr uint32_t kSpan = 64 * 32;   // incidence entries per wave
+constexpr uint32_t kSpan = 64 * 16;   // incidence entries per wave
 
+// P[u][j] += number of samples in u's incidence row whose sign bit j is set,
+// for the trials 64g .. 64g+63 of word group g = blockIdx.y.  Each wave
+// takes kSpan consecutive incidence entries (a node's entries are
+// consecutive) and walks them one at a time: the entry's node and sign word
+// are read into scalar registers (readlane) and lane j adds bit j of the
+// word to its running count, flushed with one atomic per (node, lane) when
+// the node changes.  The cost per entry is a few instructions whatever the
+// row lengths; loads are 64 entries per step, coalesced for the incidence,
+// one 8-byte gather per entry for the word.
 __global__ __launch_bounds__(kCountBlock) void k_rade_count(const uint32_t* inc, const uint32_t* inc_node,
                                                             uint64_t I, const uint64_t* words, uint32_t Wt,
                                                             uint32_t t, int32_t* P) {
   const int lane = lane_id();
-  const uint32_t g = blockIdx.y;                 // word group: trials 64g .. 64g+63
+  const uint32_t g = blockIdx.y;
   const uint64_t wave = (blockIdx.x * uint64_t(kCountBlock) + threadIdx.x) / kWave;
   const uint64_t e0 = wave * kSpan;
   if (e0 >= I) return;
   const uint64_t e1 = e0 + kSpan < I ? e0 + kSpan : I;
-  const uint32_t jt = 64 * g + lane;             // this lane's trial
+  const uint32_t jt = 64 * g + lane;   // this lane's trial
+  const bool live = jt < t;
+  const uint32_t shift = lane & 31;
+  const bool high = lane >= 32;
   uint32_t cur = kUnseen;
   uint32_t acc = 0;
   for (uint64_t base = e0; base < e1; base += kWave) {
@@ -83,27 +95,21 @@ __global__ __launch_bounds__(kCountBlock) void k_rade_count(const uint32_t* inc,
     const bool valid = e < e1;
     const uint32_t u = valid ? inc_node[e] : kUnseen;
     const uint64_t word = valid ? words[uint64_t(inc[e]) * Wt + g] : 0ull;
-    uint64_t todo = __ballot(valid);
-    while (todo) {
-      const int first = __ffsll(static_cast<unsigned long long>(todo)) - 1;
-      const uint32_t su = __shfl(u, first, kWave);
-      const uint64_t seg = __ballot(valid && u == su);
-      if (su != cur) {
-        if (cur != kUnseen && jt < t && acc) atomicAdd(&P[uint64_t(cur) * t + jt], static_cast<int32_t>(acc));
-        cur = su;
+    const uint32_t wlo = static_cast<uint32_t>(word), whi = static_cast<uint32_t>(word >> 32);
+    const uint32_t cnt = e1 - base < kWave ? static_cast<uint32_t>(e1 - base) : kWave;
+    for (uint32_t i = 0; i < cnt; ++i) {
+      const uint32_t ui = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u), static_cast<int>(i)));
+      const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wlo), static_cast<int>(i)));
+      const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(whi), static_cast<int>(i)));
+      if (ui != cur) {
+        if (cur != kUnseen && live && acc) atomicAdd(&P[uint64_t(cur) * t + jt], static_cast<int32_t>(acc));
+        cur = ui;
         acc = 0;
       }
-      const bool in_seg = (seg >> lane) & 1ull;
-      const uint64_t wv = in_seg ? word : 0ull;
-#pragma unroll 8
-      for (int j = 0; j < kWave; ++j) {
-        const uint64_t b = __ballot((wv >> j) & 1ull);
-        if (lane == j) acc += static_cast<uint32_t>(__popcll(b));
-      }
-      todo &= ~seg;
+      acc += ((high ? hi : lo) >> shift) & 1u;
     }
   }
-  if (cur != kUnseen && jt < t && acc) atomicAdd(&P[uint64_t(cur) * t + jt], static_cast<int32_t>(acc));
+  if (cur != kUnseen && live && acc) atomicAdd(&P[uint64_t(cur) * t + jt], static_cast<int32_t>(acc));
 }
 
 // R[j][u] = 2 P[u][j] - deg[u] (trial-major for the selection) and, if
