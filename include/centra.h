@@ -90,12 +90,19 @@ typedef struct {
  * the normalised shortest-path counts.  `count_bits_override`, if nonzero
  * and smaller than C, replaces C (tests only).  The CSR arrays must stay
  * alive until centra_graph_release.  *out receives the prepared graph.
+ * Preparation also builds, in context memory, a relabelled copy of the
+ * graph whose node order groups each node with its in-neighbour of largest
+ * out-degree, so that nodes visited together by a BFS have nearby ids (the
+ * sampler traverses that copy; every result is expressed in the caller's
+ * ids and does not depend on the relabelling).  The environment variable
+ * CENTRA_RELABEL=0 makes the sampler traverse the caller's CSR instead.
  * Errors: CENTRA_EINVAL (n < 2, unsorted row, duplicate, self loop, node id
  * out of range, inconsistent reverse CSR), CENTRA_ENOMEM, CENTRA_EHIP. */
 CENTRA_API int centra_graph_prepare(centra_ctx *ctx, const centra_csr *csr, uint32_t count_bits_override,
                          centra_graph **out, void *stream);
 
-/* Releases a prepared graph (not the caller's CSR arrays).  NULL is allowed. */
+/* Releases a prepared graph (not the caller's CSR arrays) and the context
+ * memory it holds; call it before destroying its context.  NULL is allowed. */
 CENTRA_API void centra_graph_release(centra_graph *g);
 
 /* Host outputs: maximum in-degree and count bit budget C of the graph. */

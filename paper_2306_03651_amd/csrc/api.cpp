@@ -2,6 +2,7 @@
 // three device steps of an iteration, the host FP64 bound and the
 // progressive driver of Algorithm 1.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -171,17 +172,33 @@ int centra_graph_prepare(centra_ctx* ctx, const centra_csr* csr, uint32_t count_
   g->col_idx = csr->col_idx;
   g->in_ptr = csr->directed ? csr->rrow_ptr : csr->row_ptr;
   g->in_idx = csr->directed ? csr->rcol_idx : csr->col_idx;
-  const int rc = validate_graph(ctx, g, as_stream(stream));
+  int rc = validate_graph(ctx, g, as_stream(stream));
   if (rc) {
     delete g;
     return rc;
   }
   if (count_bits_override && count_bits_override < g->count_bits) g->count_bits = count_bits_override;
+  g->bfs_row_ptr = g->row_ptr;
+  g->bfs_col_idx = g->col_idx;
+  g->bfs_in_ptr = g->in_ptr;
+  g->bfs_in_idx = g->in_idx;
+  const char* rl = getenv("CENTRA_RELABEL");
+  if (!(rl && !strcmp(rl, "0")) && (rc = relabel_graph(ctx, g, as_stream(stream)))) {
+    delete g;
+    return rc;
+  }
   *out = g;
   return CENTRA_OK;
 }
 
-void centra_graph_release(centra_graph* g) { delete g; }
+void centra_graph_release(centra_graph* g) {
+  if (!g) return;
+  if (g->ctx) {
+    DeviceGuard guard(g->ctx->device);
+    release_graph_buffers(g->ctx, g);
+  }
+  delete g;
+}
 
 int centra_graph_info(const centra_graph* g, uint32_t* max_in_degree, uint32_t* count_bits) {
   if (!g) return CENTRA_EINVAL;

@@ -57,6 +57,16 @@ struct centra_graph {
   uint32_t max_in_degree = 0;
   uint32_t max_out_degree = 0;
   uint32_t count_bits = 0;
+  // the arrays the sampler traverses: the locality-relabelled copy
+  // (relabel_graph) or the caller's CSR; new_of / orig_of map caller ids
+  // to traversal ids and back (both NULL without relabelling)
+  const uint32_t* bfs_row_ptr = nullptr;
+  const uint32_t* bfs_col_idx = nullptr;
+  const uint32_t* bfs_in_ptr = nullptr;
+  const uint32_t* bfs_in_idx = nullptr;
+  const uint32_t* new_of = nullptr;
+  const uint32_t* orig_of = nullptr;
+  centra::DevBuf r_row_ptr, r_col_idx, r_in_ptr, r_in_idx, r_new_of, r_orig_of;
 };
 
 namespace centra {
@@ -83,6 +93,11 @@ void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
 
 // Exclusive scan of `n` u32 values into `out[0..n]` (u64, out[n] = total).
 int excl_scan_u32_to_u64(centra_ctx* ctx, const uint32_t* in, uint64_t* out, size_t n, hipStream_t s);
+
+// Locality relabelling of a validated graph (graph.hip); fills the bfs_*
+// arrays and the id maps of g.
+int relabel_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s);
+void release_graph_buffers(centra_ctx* ctx, centra_graph* g);
 
 // Graph checks (graph.hip).
 int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s);

@@ -76,6 +76,8 @@ struct SampleArgs {
   const uint32_t* col_idx;
   const uint32_t* in_ptr;
   const uint32_t* in_idx;
+  const uint32_t* new_of;    // caller id -> traversal id (NULL: identity)
+  const uint32_t* orig_of;   // traversal id -> caller id (NULL: identity)
   uint64_t seed;
   uint32_t instance;
   uint64_t first;
@@ -363,6 +365,8 @@ __device__ __forceinline__ uint64_t pred_weight(const Bits& bits, uint64_t* rec,
   return tg == level_tag(bits.base, want) ? c : 0ull;
 }
 
+__device__ __forceinline__ uint32_t caller_id(const SampleArgs& a, uint32_t v) { return a.orig_of ? a.orig_of[v] : v; }
+
 // Ring index of pair p: largest i with poff[i] <= p.
 __device__ __forceinline__ int ring_of(const uint32_t* poff, uint32_t dt, uint32_t p) {
   int lo = 0, hi = static_cast<int>(dt) - 1;
@@ -411,9 +415,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
 
     // pair draw: every thread draws the same words (uniform, no broadcast)
     WordStream st(a.seed, sample, a.instance, 0);
-    const uint32_t s = static_cast<uint32_t>(bounded(st, a.n));
+    const uint32_t s0 = static_cast<uint32_t>(bounded(st, a.n));
     const uint32_t tp = static_cast<uint32_t>(bounded(st, a.n - 1));
-    const uint32_t t = tp + (tp >= s ? 1u : 0u);
+    const uint32_t t0 = tp + (tp >= s0 ? 1u : 0u);
+    const uint32_t s = a.new_of ? a.new_of[s0] : s0;   // traversal ids
+    const uint32_t t = a.new_of ? a.new_of[t0] : t0;
 
     if (!LDS_BITS) {
       for (uint32_t i = tid; i < kBloomWords; i += BLOCK) sh.bloom[i] = 0;
@@ -748,7 +754,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         ok = false;
       } else {
         v = sh.rw[pi];
-        if (tid == 0 && hbase < a.stage_cap) a.stage[hbase] = v;
+        if (tid == 0 && hbase < a.stage_cap) a.stage[hbase] = caller_id(a, v);
         written = 1;
         dv = d - 1;
         if (shortcut == 3) {
@@ -763,7 +769,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
             ok = false;
           } else {
             v = a.in_idx[sh.rrs[pi] + j];
-            if (tid == 0 && hbase + 1 < a.stage_cap) a.stage[hbase + 1] = v;
+            if (tid == 0 && hbase + 1 < a.stage_cap) a.stage[hbase + 1] = caller_id(a, v);
             written = 2;
             dv = d - 2;
           }
@@ -796,7 +802,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         ok = false;
       } else {
         v = pick;
-        if (tid == 0 && hbase < a.stage_cap) a.stage[hbase] = v;
+        if (tid == 0 && hbase < a.stage_cap) a.stage[hbase] = caller_id(a, v);
         written = 1;
         dv = d - 1;
       }
@@ -811,7 +817,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         break;
       }
       v = a.in_idx[vb + j];
-      if (tid == 0 && hbase + written < a.stage_cap) a.stage[hbase + written] = v;
+      if (tid == 0 && hbase + written < a.stage_cap) a.stage[hbase + written] = caller_id(a, v);
       ++written;
       --dv;
     }
@@ -820,8 +826,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
       a.stage_pos[idx] = hbase;
       a.he_len[idx] = len;
       if (a.st_out) {
-        a.st_out[2 * size_t(idx)] = s;
-        a.st_out[2 * size_t(idx) + 1] = t;
+        a.st_out[2 * size_t(idx)] = s0;
+        a.st_out[2 * size_t(idx) + 1] = t0;
       }
       if (a.dist_out) a.dist_out[idx] = d;
     }
@@ -995,10 +1001,12 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     a.n = g->n;
     a.c_bits = g->count_bits;
     a.max_out_deg = g->max_out_degree;
-    a.row_ptr = g->row_ptr;
-    a.col_idx = g->col_idx;
-    a.in_ptr = g->in_ptr;
-    a.in_idx = g->in_idx;
+    a.row_ptr = g->bfs_row_ptr;
+    a.col_idx = g->bfs_col_idx;
+    a.in_ptr = g->bfs_in_ptr;
+    a.in_idx = g->bfs_in_idx;
+    a.new_of = g->new_of;
+    a.orig_of = g->orig_of;
     a.seed = seed;
     a.instance = instance;
     a.first = first;

@@ -272,3 +272,14 @@ def test_hub_targets_without_ring_cache(ctx, variant, monkeypatch):
         h, info = oracle.sample_path(g, 1, 0, int(i), c_bits=c_bits, og=og)
         assert np.array_equal(nodes[int(off[i]):int(off[i + 1])], h), i
         assert (st[2 * i], st[2 * i + 1], d[i]) == (info.s, info.t, info.dist), i
+
+
+@pytest.mark.parametrize("name", ["ba2000", "dir300", "rmat12", "grid40_c8", "chain1500"])
+def test_sampler_without_relabelling(ctx, name, monkeypatch):
+    # The sampler normally traverses a locality-relabelled copy of the
+    # graph; traversing the caller's CSR directly must give the same bits.
+    monkeypatch.setenv("CENTRA_RELABEL", "0")
+    build, cbo = CASES[name]
+    g = build()
+    say(f"sampler parity without relabelling {name}")
+    check_batch(ctx, g, cbo, seed=7, inst=1, first=0, count=3000)
