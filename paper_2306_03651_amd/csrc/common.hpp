@@ -133,6 +133,16 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   }
   return v;
 }
+// Workgroup-uniform values read from LDS or reduced across the block: the
+// readfirstlane tells the compiler so, which keeps them (and what is derived
+// from them) in scalar registers.  Only for values every lane holds equal.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
+  return static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  return (uint64_t(uniform_u32(static_cast<uint32_t>(x >> 32))) << 32) | uniform_u32(static_cast<uint32_t>(x));
+}
+
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
@@ -175,7 +185,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* to
   }
   __syncthreads();
   const uint32_t r = scratch[wid] + incl - v;
-  *total = scratch[NW];
+  *total = uniform_u32(scratch[NW]);
   __syncthreads();
   return r;
 }
@@ -191,7 +201,7 @@ __device__ __forceinline__ uint64_t block_max_u64(uint64_t v, uint64_t* scratch)
 #pragma unroll
   for (int i = 0; i < NW; ++i) r = scratch[i] > r ? scratch[i] : r;
   __syncthreads();
-  return r;
+  return uniform_u64(r);
 }
 
 template <int BLOCK>
@@ -205,7 +215,7 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* scratch)
 #pragma unroll
   for (int i = 0; i < NW; ++i) r += scratch[i];
   __syncthreads();
-  return r;
+  return uniform_u64(r);
 }
 
 __device__ __forceinline__ uint32_t bitlen64(uint64_t x) { return x ? 64u - __clzll(x) : 0u; }

@@ -164,7 +164,7 @@ __device__ __forceinline__ uint64_t block_sat_sum(uint64_t v, uint64_t* scratch)
 #pragma unroll
   for (int i = 0; i < NW; ++i) r = sat_add(r, scratch[i]);
   __syncthreads();
-  return r;
+  return uniform_u64(r);
 }
 
 // Visited set.  Between levels, "visited" means "in a completed level"
@@ -296,7 +296,7 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* to
     tot += x;
   }
   __syncthreads();
-  *total = tot;
+  *total = uniform_u64(tot);
   return before + incl - v;
 }
 
@@ -348,7 +348,7 @@ __device__ uint32_t block_pick(uint32_t len, const F& weight, uint64_t W_known, 
         incl += x[k];
         if (cand == kUnseen && incl > r) cand = c + first + k;
       }
-      return ~static_cast<uint32_t>(block_max_u64<BLOCK>(uint64_t(~cand), sh.red));
+      return ~static_cast<uint32_t>(block_max_u64<BLOCK>(uint64_t(~cand), sh.red));   // uniform
     }
     run += tot;
   }
@@ -380,8 +380,11 @@ __device__ __forceinline__ int ring_of(const uint32_t* poff, uint32_t dt, uint32
   return lo;
 }
 
+// Up to 512 threads the kernel is held to 5 waves per SIMD (at most 96
+// VGPRs, a few bytes of spill): more resident BFSs hide more of the latency
+// of their dependent random accesses than the spill costs.
 template <int BLOCK, int UNROLL, bool LDS_BITS>
-__global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
+__global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(SampleArgs a) {
   __shared__ SampleShared<BLOCK> sh;
   extern __shared__ uint32_t dyn_bits[];
   const int tid = threadIdx.x;
@@ -407,7 +410,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
   for (;;) {
     if (tid == 0) sh.next = atomicAdd(a.work, 1u);
     __syncthreads();
-    const uint32_t idx = sh.next;
+    const uint32_t idx = uniform_u32(sh.next);
     __syncthreads();
     if (idx >= a.count) break;
     const uint64_t sample = a.first + idx;
@@ -704,7 +707,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         }
         __syncthreads();
       }
-      const uint32_t ne = sh.qlen;
+      const uint32_t ne = uniform_u32(sh.qlen);
       if (ne == le) break;   // nothing new: t unreachable
       // level L+1 is complete: its largest raw count decides the shift;
       // S_{L+1} is the sum of the added contributions, or of the shifted
@@ -743,7 +746,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
     }
     uint32_t v = t, dv = len ? d : 0u, written = 0;   // no backtrack when t is unreachable or adjacent
     __syncthreads();   // sh.base, ring sums and stored pair counts are visible
-    const uint64_t hbase = sh.base;
+    const uint64_t hbase = uniform_u64(sh.base);
     bool ok = true;
     if (dv && shortcut && rings) {
       // step from t through level d-1: weights ring_a (shortcut 2) or
@@ -797,7 +800,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
         if (lane == 0) sh.pick = pick;
       }
       __syncthreads();
-      const uint32_t pick = sh.pick;
+      const uint32_t pick = uniform_u32(sh.pick);
       if (pick == kUnseen) {
         ok = false;
       } else {
@@ -834,7 +837,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_paths(SampleArgs a) {
     __syncthreads();
     // the records keep this BFS's stamp (older than any later one); only
     // the LDS bitmap is cleared
-    const uint32_t nv = sh.qlen;
+    const uint32_t nv = uniform_u32(sh.qlen);
     n_nodes += nv;
     if (LDS_BITS) {
       for (uint32_t i = tid; i < nv; i += BLOCK) dyn_bits[ld_u32(&q[i]) >> 5] = 0;
@@ -866,9 +869,9 @@ __global__ void k_stage_gather(uint32_t count, const uint64_t* stage_pos, const 
 // CU (the bitmap takes most of the LDS); the HBM-bitmap variant runs
 // 512-thread workgroups, several per CU.
 constexpr int kLdsBlock = 1024;
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;
 constexpr uint32_t kMaxSlots = 8192;
-constexpr size_t kSlotMemCap = size_t(48) << 30;
+constexpr size_t kSlotMemCap = size_t(96) << 30;
 
 #define CENTRA_LDS_KERNEL k_sample_paths<kLdsBlock, kUnroll, true>
 
