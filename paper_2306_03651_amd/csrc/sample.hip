@@ -469,7 +469,9 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
     uint64_t sumL = 1;        // S_L: sum of the level-L counts (saturating)
     uint32_t shortcut = 0;    // 2 or 3: levels L+1 (and L+2) were not produced
     uint64_t w_short = 0;     // W of the first backtrack step when shortcut
-    for (;;) {
+    // t without in-neighbours is unreachable: no BFS at all (on skewed
+    // directed graphs such targets are common, and s may reach millions)
+    for (; dt != 0;) {
       // (1) a visited in-neighbour of t: it is at level L (an earlier check
       //     would have fired otherwise), so d = L + 1
       int found = 0;
