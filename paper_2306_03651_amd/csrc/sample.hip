@@ -464,6 +464,38 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
       n_arcs += dt;
     }
     __syncthreads();
+    // sizes the cone over the next BLOCK pairs, keeping each pair's u and
+    // in-row for the 3-hop test
+    auto cone_step = [&]() {
+      const uint32_t p = cpos + tid;
+      uint32_t dg = 0;
+      if (p < pairs) {
+        const int i = ring_of(sh.poff, dt, p);
+        const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
+        const uint32_t r0 = a.in_ptr[u];
+        dg = a.in_ptr[u + 1] - r0;
+        st_u32(&pu[p], u);
+        st_u32(&prs[p], r0);
+        st_u32(&pdg[p], dg);
+      }
+      cone_part += block_sum_u64<BLOCK>(dg, sh.red);
+      n_arcs += pairs - cpos < BLOCK ? pairs - cpos : BLOCK;
+      cpos += BLOCK;
+    };
+    // Depth of t's ancestors when the rings show it: every ancestor of t is
+    // within backward distance `depth`, so a reachable t has d <= depth and
+    // the BFS can stop once the tests have ruled out d <= depth.  Pairs = 0
+    // (t's in-neighbours have no in-neighbours) gives 1; a cone of size 0
+    // gives 2 (sized here only when the pairs fit one chunk).
+    uint32_t depth = kUnseen;
+    if (rings && dt) {
+      if (pairs == 0) {
+        depth = 1;
+      } else if (pairs <= BLOCK) {
+        cone_step();
+        if (cone_part == 0) depth = 2;
+      }
+    }
 
     uint32_t lb = 0, le = 1, L = 0, d = kUnseen;
     uint64_t sumL = 1;        // S_L: sum of the level-L counts (saturating)
@@ -482,6 +514,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
         d = L + 1;
         break;
       }
+      if (L + 1 >= depth) break;   // every d <= depth ruled out: unreachable
       if (rings) {
         // out-arcs of level L (the cost of expanding it), summed in
         // workgroup chunks only as far as a cost rule below needs: most
@@ -528,6 +561,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
               shortcut = 2;
               break;
             }
+          } else if (L + 2 >= depth) {
+            break;   // every d <= depth ruled out: unreachable
           } else if (pairs <= kPairMax) {
             // (3) cone: an unvisited u with visited in-neighbours is at L+1
             //     (they are all at L), its w at L+2 and d = L+3.  Only when
@@ -548,24 +583,10 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
                   break;
                 }
                 if (fdone && cone_part > kConeRatio * fpart) break;
-                if (!cdone && (fdone || cone_part <= kConeRatio * fpart)) {
-                  const uint32_t p = cpos + tid;
-                  uint32_t dg = 0;
-                  if (p < pairs) {
-                    const int i = ring_of(sh.poff, dt, p);
-                    const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
-                    const uint32_t r0 = a.in_ptr[u];
-                    dg = a.in_ptr[u + 1] - r0;
-                    st_u32(&pu[p], u);
-                    st_u32(&prs[p], r0);
-                    st_u32(&pdg[p], dg);
-                  }
-                  cone_part += block_sum_u64<BLOCK>(dg, sh.red);
-                  n_arcs += pairs - cpos < BLOCK ? pairs - cpos : BLOCK;
-                  cpos += BLOCK;
-                } else {
+                if (!cdone && (fdone || cone_part <= kConeRatio * fpart))
+                  cone_step();
+                else
                   fcost_step();
-                }
               }
             }
             if (cheap) {

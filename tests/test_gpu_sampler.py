@@ -29,6 +29,34 @@ def chain(n):
     return inputs.from_edges(n, np.arange(n - 1), np.arange(1, n), directed=False)
 
 
+def funnel(seed, fan_src=20, fan_t1=20):
+    # Directed: a strongly connected blob (0..999); sources 1000..1499 (no
+    # in-neighbours) feeding tier 1 (1500..1599, whose ancestors are sources
+    # only: depth 1) and the blob; tier 2 (1600..1699, ancestors tier 1 and
+    # sources: depth 2); and 1700..2999, fed by the blob.  Pairs from the
+    # blob into the tiers are unreachable; pairs from sources reach them at
+    # distance 1 or 2.  With small fans (fan_src, fan_t1) a tier-2 target's
+    # pairs fit one chunk, so its ancestor depth is known up front.
+    rng = np.random.default_rng(seed)
+    src, dst = [], []
+    a, b = np.nonzero(rng.random((1000, 1000)) < 0.01)
+    src += list(a); dst += list(b)
+    for v in range(1000, 1500):
+        for w in rng.choice(np.arange(1500, 1600), fan_src, replace=False):
+            src.append(v); dst.append(w)
+        for w in rng.choice(1000, 2, replace=False):
+            src.append(v); dst.append(w)
+    for v in range(1500, 1600):
+        for w in rng.choice(np.arange(1600, 1700), fan_t1, replace=False):
+            src.append(v); dst.append(w)
+    for v in range(1700, 3000):
+        for w in rng.choice(1000, 2, replace=False):
+            src.append(w); dst.append(v)
+    e = np.unique(np.array([src, dst]).T, axis=0)
+    e = e[e[:, 0] != e[:, 1]]
+    return inputs.from_edges(3000, e[:, 0], e[:, 1], directed=True)
+
+
 CASES = {
     "ba2000": (lambda: inputs.ba_graph(2000, 5, 1), 0),
     "grid40_c8": (lambda: inputs.grid_graph(40), 8),
@@ -38,6 +66,8 @@ CASES = {
     "star3000": (lambda: star(3000), 0),
     "chain1500": (lambda: chain(1500), 0),
     "dense1200": (lambda: random_digraph(1200, 0.5, 8), 0),   # every target has > 512 in-neighbours
+    "funnel3000": (lambda: funnel(2), 0),   # targets whose ancestors end within 1 or 2 hops
+    "funnel3000s": (lambda: funnel(3, 1, 2), 0),
     "pair": (lambda: inputs.from_edges(2, [0], [1], directed=False), 0),
     "empty2": (lambda: inputs.from_edges(2, [], [], directed=True), 0),
 }
@@ -73,7 +103,8 @@ def test_sampler_bit_exact(ctx, name):
 
 
 @pytest.mark.parametrize("variant", ["lds", "hbm512", "hbm256", "hbm64"])
-@pytest.mark.parametrize("name", ["ba2000", "grid40_c8", "rmat12", "star3000", "chain1500", "dense1200"])
+@pytest.mark.parametrize("name", ["ba2000", "grid40_c8", "rmat12", "star3000", "chain1500", "dense1200",
+                                  "funnel3000"])
 def test_sampler_variants_bit_exact(ctx, name, variant, monkeypatch):
     # every launch shape of the sampler (LDS bitmap with 1024-thread
     # workgroups; HBM bitmap with 512/256/64; the default 128 runs in the
@@ -283,3 +314,19 @@ def test_sampler_without_relabelling(ctx, name, monkeypatch):
     g = build()
     say(f"sampler parity without relabelling {name}")
     check_batch(ctx, g, cbo, seed=7, inst=1, first=0, count=3000)
+
+
+@pytest.mark.parametrize("fans,count", [((20, 20), 20000), ((1, 2), 60000)])
+def test_funnel_covers_the_ancestor_depth_cases(ctx, fans, count):
+    # The funnel graphs must actually produce the cases the early stop
+    # decides: unreachable targets with ancestors, and targets reached at
+    # exactly their ancestor depth.
+    g = funnel(2, *fans)
+    _, _, infos = oracle.sample_paths(g, 7, 1, 0, count, with_info=True)
+    t = np.array([i.t for i in infos]); d = np.array([i.dist for i in infos])
+    tier1 = (t >= 1500) & (t < 1600)
+    tier2 = (t >= 1600) & (t < 1700)
+    assert ((d == 0xFFFFFFFF) & (tier1 | tier2)).sum() > 100
+    assert ((d == 1) & tier1).sum() > 2 and ((d == 2) & tier2).sum() > 2
+    say(f"funnel {fans}: {count} samples")
+    check_batch(ctx, g, 0, seed=7, inst=1, first=0, count=count)
