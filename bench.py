@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the CentRA hot path on one MI355X.
 
-Workload (the large sparse configuration): undirected Barabasi-Albert graph
-n = 1,000,000, attachment 5 (seed 1), uint32 CSR resident in HBM; Algorithm 1
-with a schedule starting at 100,000 samples and doubling up to 4,000,000,
-k = 50, t = 64, eps = 0.01, delta = 0.1.  One step = one complete run of
-Algorithm 1 from an empty sample (sampling, greedy cover, AMCERA and bound
-at every iteration) until the stopping condition holds or the cap is
-reached.  value = shortest paths sampled per second of whole-job time.
+Workload (default, the large sparse configuration): undirected
+Barabasi-Albert graph n = 1,000,000, attachment 5 (seed 1), uint32 CSR
+resident in HBM; Algorithm 1 with a schedule starting at 100,000 samples and
+doubling up to 4,000,000, k = 50, t = 64, eps = 0.01, delta = 0.1.  One step
+= one complete run of Algorithm 1 from an empty sample (sampling, greedy
+cover, AMCERA and bound at every iteration) until the stopping condition
+holds or the cap is reached.  value = shortest paths sampled per second of
+whole-job time.
+
+`--workload skewed` runs the skewed directed configuration instead: R-MAT
+scale 22 (edge factor 16, a/b/c/d = .57/.19/.19/.05, seed 1, duplicates and
+self loops dropped) with its reverse CSR; 2,000,000 samples doubling to
+8,000,000, k = 100, t = 128, eps = 0.01, delta = 0.1.
 
 Also reported:
   - roofline: the sampling kernel's algorithmic bytes per launch
@@ -33,11 +39,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sample_paths_ba1e6_traffic.txt")
 SAMPLER_SRC = os.path.join(ROOT, "paper_2306_03651_amd", "csrc", "sample.hip")
 
-WORKLOAD = dict(graph="barabasi_albert", n=1_000_000, m0=5, graph_seed=1, seed=1, instance=0,
-                m_init=100_000, m_max=4_000_000, growth=2, k=50, t=64, eps=0.01, delta=0.1)
+WORKLOADS = {
+    "sparse": dict(graph="barabasi_albert", n=1_000_000, m0=5, graph_seed=1, seed=1, instance=0,
+                   m_init=100_000, m_max=4_000_000, growth=2, k=50, t=64, eps=0.01, delta=0.1,
+                   traffic="sample_paths_ba1e6_traffic.txt",
+                   label="CentRA (Algorithm 1) on Barabasi-Albert n=1e6, attachment 5, seed 1; samples 100k "
+                         "doubling to 4M, k=50, t=64, eps=0.01, delta=0.1"),
+    "skewed": dict(graph="rmat", scale=22, edge_factor=16, graph_seed=1, seed=1, instance=0,
+                   m_init=2_000_000, m_max=8_000_000, growth=2, k=100, t=128, eps=0.01, delta=0.1,
+                   traffic="sample_paths_rmat22_traffic.txt",
+                   label="CentRA (Algorithm 1) on R-MAT scale 22 (edge factor 16, .57/.19/.19/.05, seed 1, "
+                         "directed); samples 2M doubling to 8M, k=100, t=128, eps=0.01, delta=0.1"),
+}
+WORKLOAD = WORKLOADS["sparse"]
 
 
 def log(*a):
@@ -48,13 +64,14 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(SAMPLER_SRC, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic():
+def read_traffic(name=WORKLOAD["traffic"]):
     """HBM bytes per launch from the committed counter summary, if it matches
     the current sampler source."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
         return None
     vals = {}
-    for ln in open(TRAFFIC_SUMMARY):
+    for ln in open(path):
         if ":" in ln and not ln.startswith("#"):
             k, v = ln.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -66,13 +83,13 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(graph, seconds: float):
+def cpu_baseline(graph, seconds: float, W):
     import oracle
     og = oracle.OracleGraph(graph)
     done = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        oracle.sample_path(graph, WORKLOAD["seed"], WORKLOAD["instance"], done, og=og)
+        oracle.sample_path(graph, W["seed"], W["instance"], done, og=og)
         done += 1
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "paths/s", "cores": 1, "kind": "oracle",
@@ -104,8 +121,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the oracle CPU baseline")
     ap.add_argument("--m-max", type=int, default=WORKLOAD["m_max"], help=argparse.SUPPRESS)
-    ap.add_argument("--uncapped-max", type=int, default=128_000_000,
-                    help="sample cap of the extra run that measures time to certified (0 = skip)")
+    ap.add_argument("--uncapped-max", type=int, default=None,
+                    help="sample cap of the extra runs that measure time to certified (0 = skip; default 128M for "
+                         "the sparse workload, 32M for the skewed one)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sparse",
+                    help="sparse (default): BA n=1e6; skewed: R-MAT scale 22, directed")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy 8 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -122,9 +142,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
-    W = dict(WORKLOAD, m_max=args.m_max)
+    W = dict(WORKLOADS[args.workload])
+    if args.uncapped_max is None:
+        args.uncapped_max = 128_000_000 if args.workload == "sparse" else 32_000_000
+    if args.workload == "sparse":
+        W["m_max"] = args.m_max
     t0 = time.time()
-    g = inputs.ba_graph(W["n"], W["m0"], W["graph_seed"])
+    if W["graph"] == "rmat":
+        g = inputs.rmat_graph(W["scale"], W["edge_factor"], seed=W["graph_seed"])
+    else:
+        g = inputs.ba_graph(W["n"], W["m0"], W["graph_seed"])
     log(f"graph: n={g.n} arcs={g.n_arcs} ({time.time() - t0:.1f}s)")
     ctx = binding.centra_create(0, 0)
     dg = binding.DeviceGraph(ctx, g)
@@ -186,7 +213,7 @@ def main():
     bytes_per_launch = (4.0 * st.arcs + 28.0 * st.nodes) / launches
     sec_per_launch = st.kernel_ms / 1e3 / launches
     achieved = bytes_per_launch / sec_per_launch / 1e9
-    traffic = read_traffic()
+    traffic = read_traffic(W["traffic"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "k_sample_paths", "launches": st.launches,
@@ -196,7 +223,7 @@ def main():
                 "nodes_per_path": round(st.nodes / max(1, st.samples), 1),
                 "visited_bitmap": "lds" if st.lds_bitmap else "hbm", "concurrent_bfs": st.slots}
 
-    cpu = cpu_baseline(g, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    cpu = cpu_baseline(g, args.cpu_seconds, W) if args.cpu_seconds > 0 else None
     value = paths / total
     out = {
         "metric": "shortest paths sampled/s",
@@ -211,9 +238,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "CentRA (Algorithm 1) on Barabasi-Albert n=1e6, attachment 5, seed 1; samples "
-                               "100k doubling to 4M, k=50, t=64, eps=0.01, delta=0.1",
-                   "n": W["n"], "arcs": int(g.n_arcs), "m_init": W["m_init"], "m_max": W["m_max"],
+        "config": {"workload": W["label"],
+                   "n": int(g.n), "arcs": int(g.n_arcs), "m_init": W["m_init"], "m_max": W["m_max"],
                    "k": W["k"], "t": W["t"], "eps": W["eps"], "delta": W["delta"]},
         "time_to_certified_s": round(sum(times) / len(times), 3) if res.certified else
         (uncapped["time_s"] if uncapped and uncapped["certified"] else None),

@@ -894,7 +894,6 @@ __global__ void k_stage_gather(uint32_t count, const uint64_t* stage_pos, const 
 constexpr int kLdsBlock = 1024;
 constexpr int kUnroll = 8;
 constexpr uint32_t kMaxSlots = 8192;
-constexpr size_t kSlotMemCap = size_t(96) << 30;
 
 #define CENTRA_LDS_KERNEL k_sample_paths<kLdsBlock, kUnroll, true>
 
@@ -955,19 +954,31 @@ static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
   return p;
 }
 
+// Slot state takes at most half of the device's memory (96 GiB if the size
+// cannot be queried); the context budget, when set, limits it further.
+static size_t slot_mem_cap() {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || total_b == 0) {
+    (void)hipGetLastError();
+    return size_t(96) << 30;
+  }
+  return total_b / 2;
+}
+
 static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, hipStream_t s) {
+  const size_t cap_bytes = slot_mem_cap();
   {
-    // never ask for more slots than kSlotMemCap holds
+    // never ask for more slots than the cap holds
     const size_t per = size_t(g->n) * (16 + 4) + kPairMax * (8 + 12);
-    const size_t most = kSlotMemCap / (per ? per : 1);
+    const size_t most = cap_bytes / (per ? per : 1);
     if (want > most) want = most ? static_cast<uint32_t>(most) : 1u;
   }
   if (ctx->slots >= want && ctx->slot_n >= g->n) return CENTRA_OK;
   uint32_t slots = want > ctx->slots ? want : ctx->slots;
   const uint32_t n = g->n > ctx->slot_n ? g->n : ctx->slot_n;
   const size_t per_slot = size_t(n) * (16 + 4) + kPairMax * (8 + 12);
-  // at most kSlotMemCap of slot state (or the budget, if smaller)
-  if (size_t(slots) * per_slot > kSlotMemCap) slots = static_cast<uint32_t>(kSlotMemCap / per_slot);
+  // at most the cap of slot state (or the budget, if smaller)
+  if (size_t(slots) * per_slot > cap_bytes) slots = static_cast<uint32_t>(cap_bytes / per_slot);
   if (slots == 0) slots = 1;
   // shrink the slot count if the budget cannot hold all of them
   for (;;) {
