@@ -221,7 +221,8 @@ def main():
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
                 "arcs_per_path": round(st.arcs / max(1, st.samples), 1),
                 "nodes_per_path": round(st.nodes / max(1, st.samples), 1),
-                "visited_bitmap": "lds" if st.lds_bitmap else "hbm", "concurrent_bfs": st.slots}
+                "visited_set": "lds bitmap" if st.lds_bitmap else "lds bloom filter + hbm records",
+                "concurrent_bfs": st.slots}
 
     cpu = cpu_baseline(g, args.cpu_seconds, W) if args.cpu_seconds > 0 else None
     value = paths / total

@@ -56,8 +56,18 @@
 // S_L < 2^C and (3) only if also S_L * max out-degree < 2^C; otherwise the
 // levels are produced and normalised as usual.  Test (3) scans the in-rows
 // of the ring's nodes (the cone), so it runs only when the cone is at most
-// kConeRatio times the CSR entries that expanding level L would scan.  All
+// kConeRatio times the CSR entries that expanding level L would scan, and
+// (2) only when its pairs are at most kPairRatio times those entries.  All
 // routes give the same counts, hence the same hyperedge.
+//
+// Unreachable targets.  A t without in-neighbours skips the BFS; when the
+// rings show that every ancestor of t is within backward distance 1 or 2,
+// the BFS stops once the tests have ruled out those distances.
+//
+// Node ids.  The kernel traverses the graph's locality-relabelled copy
+// (grouped so that nodes reached from one hub have nearby ids); the pair
+// is drawn in caller ids and mapped in, and hyperedge nodes are mapped back.
+// Rows keep the caller's order, so every scan order is the caller's.
 #include <stdlib.h>
 #include <string.h>
 
@@ -82,7 +92,7 @@ struct SampleArgs {
   uint32_t instance;
   uint64_t first;
   uint32_t count;
-  uint64_t* rec;      // slots * n records of two words: sigma', level
+  uint64_t* rec;      // slots * n records of two words: sigma', tag
   uint32_t* q;        // slots * n
   uint64_t* praw;     // slots * kPairMax: raw count of each pair's u from the last cone test
   uint32_t* pinfo;    // slots * 3 * kPairMax: per pair its u, in_ptr[u] and in-degree of u
@@ -100,10 +110,10 @@ struct SampleArgs {
   uint64_t* stats;       // [0] arcs scanned, [1] nodes visited (accumulated)
 };
 
-// Ring limits: t with at most Ring<BLOCK>::kCache in-neighbours gets the 2-hop test
-// on the pairs (w in in(t), u in in(w)); the 3-hop test also needs at most
-// kPairMax pairs, and runs at a level only when expanding that level would
-// scan at least 1/kConeRatio of the cone's CSR entries.
+// Ring limits: t with at most Ring<BLOCK>::kCache in-neighbours gets the
+// 2-hop test on the pairs (w in in(t), u in in(w)); the 3-hop test also
+// needs at most kPairMax pairs.  Cost rules (kConeRatio, kPairRatio) decide
+// at which levels they run.
 // Bloom filter of the visited set for the HBM variant (see BitsRec).
 constexpr uint32_t kBloomLog = 15;
 constexpr uint32_t kBloomWords = (1u << kBloomLog) / 32;
@@ -140,7 +150,6 @@ struct SampleShared {
   uint64_t ring_a[Ring<BLOCK>::kCache];  // per in-neighbour w of t: level-(L+1) count
   uint64_t ring_b[Ring<BLOCK>::kCache];  // per in-neighbour w of t: level-(L+2) count
   uint32_t bloom[BLOCK >= 1024 ? 1 : kBloomWords];   // HBM variant (<= 512 threads): visited filter
-  uint64_t acc;
   uint64_t base;
   uint32_t pick;
   uint32_t qlen;
@@ -889,8 +898,9 @@ __global__ void k_stage_gather(uint32_t count, const uint64_t* stage_pos, const 
 }
 
 // Launch shapes: the LDS-bitmap variant runs one 1024-thread workgroup per
-// CU (the bitmap takes most of the LDS); the HBM-bitmap variant runs
-// 512-thread workgroups, several per CU.
+// CU (the bitmap takes most of the LDS); the other variants (Bloom filter in
+// LDS, visited state in the HBM records) run several workgroups of 64 to
+// 512 threads per CU.
 constexpr int kLdsBlock = 1024;
 constexpr int kUnroll = 8;
 constexpr uint32_t kMaxSlots = 8192;
@@ -899,7 +909,7 @@ constexpr uint32_t kMaxSlots = 8192;
 
 struct SamplePlan {
   bool lds_bits;
-  int block;         // workgroup size of the HBM-bitmap variant
+  int block;         // workgroup size of the Bloom-filter variants
   uint32_t bit_words;
   size_t dyn_lds;
   uint32_t resident;   // workgroups resident at once = BFS slots
@@ -910,11 +920,11 @@ static hipError_t hbm_occupancy(int* per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sample_paths<BLOCK, kUnroll, false>, BLOCK, 0);
 }
 
-// Variant choice.  Default: the HBM-bitmap kernel with 128-thread
+// Variant choice.  Default: the Bloom-filter kernel with 128-thread
 // workgroups (many concurrent BFSs per CU hide the latency of the short,
 // dependent steps of each BFS).  CENTRA_SAMPLER_VARIANT selects another:
 // "lds" (LDS bitmap, 1024 threads, when the bitmap fits), "hbm512",
-// "hbm256", "hbm128", "hbm64".
+// "hbm256", "hbm128", "hbm64" (Bloom filter, that many threads).
 static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
   SamplePlan p{};
   p.bit_words = (n + 31) / 32;

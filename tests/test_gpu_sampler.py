@@ -107,8 +107,8 @@ def test_sampler_bit_exact(ctx, name):
                                   "funnel3000"])
 def test_sampler_variants_bit_exact(ctx, name, variant, monkeypatch):
     # every launch shape of the sampler (LDS bitmap with 1024-thread
-    # workgroups; HBM bitmap with 512/256/64; the default 128 runs in the
-    # tests above) gives the same hyperedges
+    # workgroups; Bloom filter with 512/256/64 threads; the default 128 runs
+    # in the tests above) gives the same hyperedges
     monkeypatch.setenv("CENTRA_SAMPLER_VARIANT", variant)
     build, cbo = CASES[name]
     g = build()
@@ -249,8 +249,8 @@ def check_sampled(ctx, g, seed, inst, first, count, n_check):
 
 def test_rmat22_configuration_sampled(ctx, rmat22):
     # The skewed directed configuration: R-MAT scale 22 (4.2M nodes, 65.2M
-    # arcs after dropping duplicates and self loops), reverse CSR; the
-    # visited bitmap does not fit in LDS, so the HBM-bitmap kernel runs.
+    # arcs after dropping duplicates and self loops), reverse CSR; half the
+    # targets have no in-neighbour, and many pairs are unreachable.
     say(f"R-MAT 22: n={rmat22.n} arcs={rmat22.n_arcs}; 200000 samples")
     off, nodes, d = check_sampled(ctx, rmat22, 1, 0, 0, 200000, 16)
     say(f"  reachable fraction {np.mean(d != 0xFFFFFFFF):.3f}")
