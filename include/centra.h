@@ -56,7 +56,11 @@ CENTRA_API uint32_t centra_abi_version(void);
 
 /* Creates a context on HIP device `hip_device`.  `hbm_budget_bytes` bounds
  * the device memory the context allocates for its own workspaces (0 = no
- * bound beyond the device).  *out receives the context.
+ * bound beyond the device).  The sampler's per-BFS state is sized for as
+ * many concurrent BFSs as the device runs, up to half of the device's
+ * memory; with several contexts on one device, give each a budget.
+ * Contexts are independent: different contexts may be used from different
+ * host threads at the same time.  *out receives the context.
  * Errors: CENTRA_EINVAL (out == NULL), CENTRA_EHIP (no such device). */
 CENTRA_API int centra_create(int hip_device, size_t hbm_budget_bytes, centra_ctx **out);
 
