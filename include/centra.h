@@ -60,7 +60,9 @@ CENTRA_API uint32_t centra_abi_version(void);
  * many concurrent BFSs as the device runs, up to half of the device's
  * memory; with several contexts on one device, give each a budget.
  * Contexts are independent: different contexts may be used from different
- * host threads at the same time.  *out receives the context.
+ * host threads at the same time.  *out receives the context.  (Tests only:
+ * the environment variable CENTRA_STAMP_START sets the context's first BFS
+ * stamp, to exercise the sampler's 32-bit stamp wrap.)
  * Errors: CENTRA_EINVAL (out == NULL), CENTRA_EHIP (no such device). */
 CENTRA_API int centra_create(int hip_device, size_t hbm_budget_bytes, centra_ctx **out);
 

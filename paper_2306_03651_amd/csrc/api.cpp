@@ -113,6 +113,13 @@ int centra_create(int hip_device, size_t hbm_budget_bytes, centra_ctx** out) {
   if (!ctx) return CENTRA_ENOMEM;
   ctx->device = hip_device;
   ctx->budget = hbm_budget_bytes;
+  // Test hook: CENTRA_STAMP_START sets the first BFS stamp, so that tests
+  // can cross the 32-bit stamp wrap (a full record clear) within a few
+  // hundred samples.
+  if (const char* st = getenv("CENTRA_STAMP_START")) {
+    const unsigned long v = strtoul(st, nullptr, 0);
+    if (v >= 1 && v <= 0xFFFFFFFFul) ctx->stamp_next = static_cast<uint32_t>(v);
+  }
   if (hipMalloc(reinterpret_cast<void**>(&ctx->d_flags), 256) != hipSuccess ||
       hipMemset(ctx->d_flags, 0, 256) != hipSuccess) {
     (void)hipGetLastError();

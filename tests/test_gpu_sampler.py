@@ -330,3 +330,29 @@ def test_funnel_covers_the_ancestor_depth_cases(ctx, fans, count):
     assert ((d == 1) & tier1).sum() > 2 and ((d == 2) & tier2).sum() > 2
     say(f"funnel {fans}: {count} samples")
     check_batch(ctx, g, 0, seed=7, inst=1, first=0, count=count)
+
+
+def test_stamp_wrap(monkeypatch):
+    # The sampler's records carry 32-bit BFS stamps and are never reset
+    # between samples; when the stamps would wrap, every record is cleared
+    # and numbering restarts at 1.  Starting a context just below the wrap
+    # crosses it within a few batches; every batch must still match the
+    # oracle (a stale record would change a hyperedge or fail the backtrack).
+    monkeypatch.setenv("CENTRA_STAMP_START", str(0xFFFFFFFF - 5000))
+    ctx = binding.centra_create(0, 0)
+    try:
+        g = inputs.ba_graph(2000, 5, 1)
+        dg = binding.DeviceGraph(ctx, g)
+        try:
+            first = 0
+            for count in [3000, 3000, 3000]:   # the second batch crosses the wrap
+                say(f"stamp wrap: batch at {first}")
+                off, nodes = binding.sample_paths(ctx, dg, 7, 1, first, count)
+                want_off, want_nodes = oracle.sample_paths(g, 7, 1, first, count)
+                assert np.array_equal(off_np(off), want_off)
+                assert np.array_equal(nodes_np(nodes), want_nodes)
+                first += count
+        finally:
+            dg.release()
+    finally:
+        binding.centra_destroy(ctx)
