@@ -356,3 +356,33 @@ def test_stamp_wrap(monkeypatch):
             dg.release()
     finally:
         binding.centra_destroy(ctx)
+
+
+def test_hbm_budget():
+    # A budget too small for the graph's relabelled copy is refused with
+    # CENTRA_ENOMEM; a budget that holds only a few BFS slots runs fewer
+    # concurrent BFSs and gives the same hyperedges.
+    g = inputs.ba_graph(2000, 5, 1)
+    ctx = binding.centra_create(0, 64 << 10)
+    try:
+        with pytest.raises(binding.CentraError) as e:
+            binding.DeviceGraph(ctx, g)
+        assert e.value.code == binding.CENTRA_ENOMEM
+    finally:
+        binding.centra_destroy(ctx)
+    ctx = binding.centra_create(0, 48 << 20)
+    try:
+        dg = binding.DeviceGraph(ctx, g)
+        try:
+            say("budgeted context: 3000 samples")
+            binding.centra_sampler_stats_get(ctx, reset=True)
+            off, nodes = binding.sample_paths(ctx, dg, 7, 1, 0, 3000)
+            st = binding.centra_sampler_stats_get(ctx)
+            assert 1 <= st.slots < 100
+            want_off, want_nodes = oracle.sample_paths(g, 7, 1, 0, 3000)
+            assert np.array_equal(off_np(off), want_off)
+            assert np.array_equal(nodes_np(nodes), want_nodes)
+        finally:
+            dg.release()
+    finally:
+        binding.centra_destroy(ctx)
