@@ -97,8 +97,13 @@ def _load():
     lib.orc_bound.restype = None
     lib.orc_progressive.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint32, c.c_uint32, c.c_double,
                                     c.c_double, c.c_uint64, c.c_uint32, c.c_uint64, c.c_uint64,
-                                    c.c_uint32, c.c_uint32, c.c_uint32, _u32p, c.POINTER(Result),
+                                    c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, _u32p, c.POINTER(Result),
                                     _u64p, c.c_uint32]
+    lib.orc_triangles.argtypes = [c.POINTER(Graph), c.c_void_p, c.c_uint64]
+    lib.orc_triangles.restype = c.c_uint64
+    lib.orc_sample_triangles.argtypes = [c.POINTER(Graph), c.c_uint64, c.c_uint32, c.c_uint64, c.c_uint64,
+                                         _u64p, _u32p]
+    lib.orc_sample_triangles.restype = c.c_int
     lib.orc_next_sample_size.argtypes = [c.c_uint64, c.c_double, c.c_double, c.c_double, c.c_uint32,
                                          c.c_uint32, c.c_uint64, c.c_uint32]
     lib.orc_next_sample_size.restype = c.c_uint64
@@ -237,8 +242,34 @@ def next_sample_size(m_i, c_hat, eps, delta_next, growth_num, growth_den, m_max,
                                             schedule))
 
 
+SPACE_SHORTEST_PATHS, SPACE_TRIANGLES = 0, 1
+
+
+def triangles(g):
+    """All triangles (a < b < c) in rank order, as an int array of shape
+    (T, 3); None for a directed graph."""
+    og = OracleGraph(g)
+    lib = _load()
+    T = lib.orc_triangles(ctypes.byref(og.c), None, 0)
+    if T == 2**64 - 1:
+        return None
+    tri = np.zeros(3 * max(1, T), dtype=np.uint32)
+    lib.orc_triangles(ctypes.byref(og.c), tri.ctypes.data, T)
+    return tri[: 3 * T].reshape(T, 3)
+
+
+def sample_triangles(g, seed, instance, first, count):
+    """Triangle hyperedges [first, first+count): (he_off, he_nodes); None if
+    the graph is directed or has no triangle."""
+    og = OracleGraph(g)
+    off = np.zeros(count + 1, dtype=np.uint64)
+    nodes = np.zeros(3 * max(1, count), dtype=np.uint32)
+    rc = _load().orc_sample_triangles(ctypes.byref(og.c), seed, instance, first, count, off, nodes)
+    return None if rc else (off, nodes[: 3 * count])
+
+
 def progressive(g, k, t, eps, delta, seed, instance, m_init, m_max, growth_num=2, growth_den=1,
-                c_bits=None, schedule=SCHEDULE_GEOMETRIC, with_m_log=False):
+                c_bits=None, schedule=SCHEDULE_GEOMETRIC, with_m_log=False, space=SPACE_SHORTEST_PATHS):
     """Algorithm 1; returns (rc, picks, Result) and, with with_m_log, the
     sample size of every iteration."""
     og = OracleGraph(g)
@@ -249,7 +280,8 @@ def progressive(g, k, t, eps, delta, seed, instance, m_init, m_max, growth_num=2
     res = Result()
     m_log = np.zeros(256, dtype=np.uint64)
     rc = lib.orc_progressive(ctypes.byref(og.c), c_bits, k, t, eps, delta, seed, instance, m_init, m_max,
-                             growth_num, growth_den, schedule, picks, ctypes.byref(res), m_log, len(m_log))
+                             growth_num, growth_den, schedule, space, picks, ctypes.byref(res), m_log,
+                             len(m_log))
     out = (rc, picks[: res.n_picked].copy(), res)
     if with_m_log:
         out = out + ([int(x) for x in m_log[: min(res.iterations, len(m_log))]],)

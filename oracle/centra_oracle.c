@@ -518,6 +518,58 @@ void orc_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t,
 
 /* ------------------------------------------------------------------ */
 /* Algorithm 1 (progressive sampling), readings R1 and R10. */
+/* ---- triangle hyperedges (Sec. 3.1) ---- */
+
+static int adjacent(const orc_graph *g, uint32_t u, uint32_t v)
+{
+    for (uint64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; e++)
+        if (g->col_idx[e] == v) return 1;
+    return 0;
+}
+
+uint64_t orc_triangles(const orc_graph *g, uint32_t *tri, uint64_t cap)
+{
+    if (g->directed) return UINT64_MAX;
+    uint64_t T = 0;
+    for (uint32_t a = 0; a < g->n; a++)
+        for (uint64_t e = g->row_ptr[a]; e < g->row_ptr[a + 1]; e++) {
+            const uint32_t b = g->col_idx[e];
+            if (b <= a) continue;
+            for (uint64_t f = e + 1; f < g->row_ptr[a + 1]; f++) {
+                const uint32_t c = g->col_idx[f];   /* c > b: rows ascend */
+                if (!adjacent(g, b, c)) continue;
+                if (T < cap) {
+                    tri[3 * T] = a;
+                    tri[3 * T + 1] = b;
+                    tri[3 * T + 2] = c;
+                }
+                T++;
+            }
+        }
+    return T;
+}
+
+int orc_sample_triangles(const orc_graph *g, uint64_t seed, uint32_t instance,
+                         uint64_t first, uint64_t count, uint64_t *he_off,
+                         uint32_t *he_nodes)
+{
+    const uint64_t T = orc_triangles(g, NULL, 0);
+    if (T == UINT64_MAX || T == 0) return -1;
+    uint32_t *all = malloc(sizeof(uint32_t) * 3 * T);
+    if (!all) return -1;
+    orc_triangles(g, all, T);
+    he_off[0] = 0;
+    for (uint64_t i = 0; i < count; i++) {
+        orc_stream st;
+        orc_stream_init(&st, seed, first + i, instance, 5);
+        const uint64_t r = orc_bounded(&st, T);
+        memcpy(he_nodes + 3 * i, all + 3 * r, 3 * sizeof(uint32_t));
+        he_off[i + 1] = 3 * (i + 1);
+    }
+    free(all);
+    return 0;
+}
+
 uint64_t orc_next_sample_size(uint64_t m_i, double c_hat, double eps, double delta_next,
                               uint32_t growth_num, uint32_t growth_den, uint64_t m_max,
                               uint32_t schedule)
@@ -541,14 +593,23 @@ uint64_t orc_next_sample_size(uint64_t m_i, double c_hat, double eps, double del
 int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                     double eps, double delta, uint64_t seed, uint32_t instance,
                     uint64_t m_init, uint64_t m_max, uint32_t growth_num,
-                    uint32_t growth_den, uint32_t schedule, uint32_t *picks,
-                    orc_result *res, uint64_t *m_log, uint32_t m_log_cap)
+                    uint32_t growth_den, uint32_t schedule, uint32_t space,
+                    uint32_t *picks, orc_result *res, uint64_t *m_log,
+                    uint32_t m_log_cap)
 {
     const double a = 1.0 - exp(-1.0);
     if (k == 0 || t == 0 || !(eps > 0.0 && eps < a) || !(delta > 0.0 && delta < 1.0) ||
         m_init == 0 || m_max < m_init || growth_den == 0 || growth_num <= growth_den ||
-        schedule > 2)
+        schedule > 2 || space > 1)
         return -1;
+    uint32_t *tri = NULL;
+    uint64_t T = 0;
+    if (space == 1) {
+        T = orc_triangles(g, NULL, 0);
+        if (T == UINT64_MAX || T == 0) return -1;
+        tri = malloc(sizeof(uint32_t) * 3 * T);
+        orc_triangles(g, tri, T);
+    }
     uint64_t cap = 1024;
     uint64_t *he_off = malloc(sizeof(uint64_t) * (m_max + 1));
     uint32_t *he_nodes = malloc(sizeof(uint32_t) * cap);
@@ -566,7 +627,15 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
         const double delta_i = schedule == 2 ? delta : ldexp(delta, -(int)i);
         if (m_log && i <= m_log_cap) m_log[i - 1] = m_i;
         for (uint64_t s = m_prev; s < m_i; s++) {
-            uint32_t len = sample_one(g, c_bits, seed, instance, s, h, NULL, &b);
+            uint32_t len;
+            if (space == 1) {
+                orc_stream st;
+                orc_stream_init(&st, seed, s, instance, 5);
+                memcpy(h, tri + 3 * orc_bounded(&st, T), 3 * sizeof(uint32_t));
+                len = 3;
+            } else {
+                len = sample_one(g, c_bits, seed, instance, s, h, NULL, &b);
+            }
             if (he_off[s] + len > cap) {
                 while (he_off[s] + len > cap) cap *= 2;
                 he_nodes = realloc(he_nodes, sizeof(uint32_t) * cap);
@@ -603,6 +672,6 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                                    growth_den, m_max, schedule);
     }
     bfs_free(&b);
-    free(he_off); free(he_nodes); free(h); free(cov_cum); free(topk);
+    free(he_off); free(he_nodes); free(h); free(cov_cum); free(topk); free(tri);
     return rc;
 }

@@ -146,6 +146,22 @@ void orc_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t,
                uint64_t deg_topk, uint32_t b_max, double eps, double delta_i,
                orc_bound_out *out);
 
+/* Triangle hyperedges (Sec. 3.1: for the triangle centrality the space is
+ * the node sets of the triangles of an undirected G, drawn uniformly).
+ * Reading: the triangles {a < b < c} are ranked 0 .. T-1 in lexicographic
+ * order of (a, b, c); sample number x draws r = bounded(T) from the Philox
+ * stream (seed, x, instance, tag 5) and is the r-th triangle, hyperedge
+ * (a, b, c).  orc_triangles writes the first min(T, cap) triangles in rank
+ * order (3 ids each) and returns T; UINT64_MAX for a directed graph. */
+uint64_t orc_triangles(const orc_graph *g, uint32_t *tri, uint64_t cap);
+
+/* Samples [first, first+count) triangle hyperedges: he_off[i] = 3i,
+ * he_nodes holds 3*count ids.  Returns 0, or -1 for a directed graph or one
+ * without triangles. */
+int orc_sample_triangles(const orc_graph *g, uint64_t seed, uint32_t instance,
+                         uint64_t first, uint64_t count, uint64_t *he_off,
+                         uint32_t *he_nodes);
+
 /* samplingSchedule of Algorithm 1 (Section 4).  Geometric (schedule 0):
  * min(ceil(m_i*num/den), m_max).  Adaptive (schedule 1): the larger of
  * that and the optimistic size, the m at which eta of Theorem bound_dev
@@ -157,7 +173,8 @@ uint64_t orc_next_sample_size(uint64_t m_i, double c_hat, double eps, double del
                               uint32_t schedule);
 
 /* Algorithm 1.  schedule: 0 geometric, 1 adaptive (orc_next_sample_size),
- * 2 fixed: one iteration at m_init whose bound uses delta itself.  picks
+ * 2 fixed: one iteration at m_init whose bound uses delta itself.  space:
+ * 0 shortest paths (set betweenness), 1 triangles.  picks
  * has capacity k; m_log (optional) receives m_i of iterations 1 ..
  * min(iterations, m_log_cap).  Returns 0 if certified, 1 if not (m_max
  * reached, or the fixed iteration's test failed), negative on error. */
@@ -171,8 +188,9 @@ typedef struct {
 int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                     double eps, double delta, uint64_t seed, uint32_t instance,
                     uint64_t m_init, uint64_t m_max, uint32_t growth_num,
-                    uint32_t growth_den, uint32_t schedule, uint32_t *picks,
-                    orc_result *res, uint64_t *m_log, uint32_t m_log_cap);
+                    uint32_t growth_den, uint32_t schedule, uint32_t space,
+                    uint32_t *picks, orc_result *res, uint64_t *m_log,
+                    uint32_t m_log_cap);
 
 #ifdef __cplusplus
 }
