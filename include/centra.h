@@ -38,7 +38,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 2u
+#define CENTRA_ABI_VERSION 3u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -214,6 +214,26 @@ CENTRA_API int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t
                  uint32_t b_max, double eps, double delta_i, centra_bound_out *out);
 
 /* ------------------------------------------------------------------ */
+/* Triangle hyperedges: the hyperedge space of the triangle centrality
+ * (Sec. 3.1: the node sets of the triangles of an undirected G, drawn
+ * uniformly), the second space Algorithm 1 runs on (Sec. 4: the algorithm
+ * is oblivious to sampleHEs).  The triangles {a < b < c} are ranked in
+ * lexicographic order of (a, b, c); sample number x (global index) draws
+ * r = bounded(T) from the Philox stream (seed, x, instance, tag 5) and is
+ * the triangle of rank r, hyperedge (a, b, c).
+ *
+ * centra_triangle_count: *T receives the number of triangles (host).  The
+ * per-graph triangle index is built on first use and kept with g.
+ * centra_sample_triangles: samples [first, first + count) into he_off
+ * (device u64[count + 1], he_off[i] = 3 i) and he_nodes (device u32[3 count]).
+ * Errors: CENTRA_ENOTSUP (directed graph), CENTRA_EINVAL (NULL argument;
+ * sampling from a graph without triangles), CENTRA_ENOMEM, CENTRA_EHIP. */
+CENTRA_API int centra_triangle_count(centra_ctx *ctx, const centra_graph *g, uint64_t *T, void *stream);
+CENTRA_API int centra_sample_triangles(centra_ctx *ctx, const centra_graph *g, uint64_t seed, uint32_t instance,
+                            uint64_t first, uint32_t count, uint64_t *he_off, uint32_t *he_nodes,
+                            void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Algorithm 1 (CentRA).  Iteration i = 1, 2, ...: delta_i = delta / 2^i;
  * the sample is extended to m_i hyperedges (samples 0 .. m_i-1 of (seed,
  * instance)), then greedyCover, the AMCERA and the bound of Theorem
@@ -232,12 +252,17 @@ CENTRA_API int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t
  *   CENTRA_SCHEDULE_FIXED: a single iteration at m = m_init whose bound
  *     uses delta itself (the fixed-sample-size use of Theorem bound_dev,
  *     Section 5), returning its stopping test.
+ * The hyperedge space: CENTRA_SPACE_SHORTEST_PATHS (set betweenness,
+ * centra_sample_paths) or CENTRA_SPACE_TRIANGLES (triangle centrality,
+ * centra_sample_triangles).
  * Inputs: k >= 1, 1 <= t <= 1024, eps in (0, 1-1/e), delta in (0,1),
- * 1 <= m_init <= m_max < 2^31, growth_num > growth_den >= 1, schedule one
- * of the three values. */
+ * 1 <= m_init <= m_max < 2^31, growth_num > growth_den >= 1, schedule and
+ * space one of their values. */
 #define CENTRA_SCHEDULE_GEOMETRIC 0u
 #define CENTRA_SCHEDULE_ADAPTIVE 1u
 #define CENTRA_SCHEDULE_FIXED 2u
+#define CENTRA_SPACE_SHORTEST_PATHS 0u
+#define CENTRA_SPACE_TRIANGLES 1u
 
 typedef struct {
     uint32_t k, t;
@@ -247,6 +272,7 @@ typedef struct {
     uint64_t m_init, m_max;
     uint32_t growth_num, growth_den;
     uint32_t schedule;   /* CENTRA_SCHEDULE_* */
+    uint32_t space;      /* CENTRA_SPACE_* */
 } centra_params;
 
 typedef struct {

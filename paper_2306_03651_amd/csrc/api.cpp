@@ -238,6 +238,26 @@ int centra_sample_paths(centra_ctx* ctx, const centra_graph* g, uint64_t seed, u
   return CENTRA_OK;
 }
 
+int centra_triangle_count(centra_ctx* ctx, const centra_graph* g, uint64_t* T, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (!g || !T) return fail(ctx, CENTRA_EINVAL, "triangle_count: NULL argument");
+  DeviceGuard guard(ctx->device);
+  return triangle_index(ctx, const_cast<centra_graph*>(g), T, as_stream(stream));
+}
+
+int centra_sample_triangles(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
+                            uint32_t count, uint64_t* he_off, uint32_t* he_nodes, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (!g || !he_off || (count && !he_nodes)) return fail(ctx, CENTRA_EINVAL, "sample_triangles: NULL argument");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = as_stream(stream);
+  int rc = sample_triangles_into(ctx, const_cast<centra_graph*>(g), seed, instance, first, count, he_off, 0, he_nodes,
+                                 s);
+  if (rc) return rc;
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  return check_flags(ctx, s, "sample_triangles");
+}
+
 // Checks the sample arguments; he_nodes may be NULL only if every hyperedge
 // is empty (he_off[m] == 0), which is read from the device.
 static int check_sample_args(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
@@ -317,6 +337,8 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
   if (p->growth_den == 0 || p->growth_num <= p->growth_den)
     return fail(ctx, CENTRA_EINVAL, "progressive: growth must exceed 1");
   if (p->schedule > CENTRA_SCHEDULE_FIXED) return fail(ctx, CENTRA_EINVAL, "progressive: unknown schedule");
+  if (p->space > CENTRA_SPACE_TRIANGLES) return fail(ctx, CENTRA_EINVAL, "progressive: unknown hyperedge space");
+  const bool tri = p->space == CENTRA_SPACE_TRIANGLES;
   const bool fixed = p->schedule == CENTRA_SCHEDULE_FIXED;
   DeviceGuard guard(ctx->device);
   hipStream_t s = as_stream(stream);
@@ -344,11 +366,21 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
     CENTRA_HIP(ctx, hipEventRecord(ev[0], s));
     uint64_t added = 0;
     const uint32_t cnt = static_cast<uint32_t>(m_i - m_prev);
-    if ((rc = sample_to_stage(ctx, g, p->seed, p->instance, m_prev, cnt, nullptr, nullptr, &added, s))) return rc;
-    if ((rc = ensure(ctx, ctx->store_nodes, (total_nodes + added + 1) * 4, true, s))) return rc;
-    uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
-    if ((rc = stage_to_output(ctx, cnt, total_nodes, store_off + m_prev, store_nodes + total_nodes, s))) return rc;
+    if (tri) {
+      added = 3ull * cnt;
+      if ((rc = ensure(ctx, ctx->store_nodes, (total_nodes + added + 1) * 4, true, s))) return rc;
+      uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
+      if ((rc = sample_triangles_into(ctx, const_cast<centra_graph*>(g), p->seed, p->instance, m_prev, cnt,
+                                      store_off + m_prev, total_nodes, store_nodes + total_nodes, s)))
+        return rc;
+    } else {
+      if ((rc = sample_to_stage(ctx, g, p->seed, p->instance, m_prev, cnt, nullptr, nullptr, &added, s))) return rc;
+      if ((rc = ensure(ctx, ctx->store_nodes, (total_nodes + added + 1) * 4, true, s))) return rc;
+      uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
+      if ((rc = stage_to_output(ctx, cnt, total_nodes, store_off + m_prev, store_nodes + total_nodes, s))) return rc;
+    }
     total_nodes += added;
+    uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
     CENTRA_HIP(ctx, hipEventRecord(ev[1], s));
     if ((rc = build_incidence(ctx, n, m_i, store_off, store_nodes, s))) return rc;
     if ((rc = greedy_on_incidence(ctx, n, m_i, store_off, store_nodes, k, reinterpret_cast<uint32_t*>(misc),

@@ -238,6 +238,8 @@ void release_graph_buffers(centra_ctx* ctx, centra_graph* g) {
   release(ctx, g->r_in_idx);
   release(ctx, g->r_new_of);
   release(ctx, g->r_orig_of);
+  release(ctx, g->tri_src);
+  release(ctx, g->tri_prefix);
 }
 
 }  // namespace centra

@@ -67,6 +67,10 @@ struct centra_graph {
   const uint32_t* new_of = nullptr;
   const uint32_t* orig_of = nullptr;
   centra::DevBuf r_row_ptr, r_col_idx, r_in_ptr, r_in_idx, r_new_of, r_orig_of;
+  // triangle index (triangles.hip), built on first use: each arc's source and
+  // the exclusive prefix over arcs of their triangle counts
+  centra::DevBuf tri_src, tri_prefix;
+  uint64_t tri_total = ~0ull;   // number of triangles; ~0: not built
 };
 
 namespace centra {
@@ -98,6 +102,11 @@ int excl_scan_u32_to_u64(centra_ctx* ctx, const uint32_t* in, uint64_t* out, siz
 // arrays and the id maps of g.
 int relabel_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s);
 void release_graph_buffers(centra_ctx* ctx, centra_graph* g);
+
+// Triangle hyperedges (triangles.hip).
+int triangle_index(centra_ctx* ctx, centra_graph* g, uint64_t* T, hipStream_t s);
+int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
+                          uint32_t count, uint64_t* he_off, uint64_t base, uint32_t* he_nodes, hipStream_t s);
 
 // Graph checks (graph.hip).
 int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s);

@@ -1,0 +1,87 @@
+"""GPU parity of the triangle hyperedge space (the triangle centrality's
+space, Sec. 3.1) against the oracle: triangle counts, bit-exact sampled
+triangles, Algorithm 1 on this space, and the error cases."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_03651_amd import binding, inputs
+from tests.gpu_util import nodes_np, off_np, say
+from tests.test_oracle_triangles import gnp
+
+pytestmark = pytest.mark.gpu
+
+
+def undirected_rmat(scale, seed):
+    d = inputs.rmat_graph(scale, 8, seed=seed)
+    src = np.repeat(np.arange(d.n), np.diff(d.row_ptr.astype(np.int64)))
+    return inputs.from_edges(d.n, src, d.col_idx, directed=False)
+
+
+GRAPHS = {
+    "k12": lambda: inputs.from_edges(12, *zip(*itertools.combinations(range(12), 2)), directed=False),
+    "gnp40": lambda: gnp(40, 0.3, 1),
+    "gnp300": lambda: gnp(300, 0.1, 2),
+    "ba2000": lambda: inputs.ba_graph(2000, 5, 1),
+    "rmat12u": lambda: undirected_rmat(12, 3),
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_triangles_bit_exact(ctx, name):
+    g = GRAPHS[name]()
+    T = len(oracle.triangles(g))
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        assert binding.centra_triangle_count(ctx, dg.handle) == T
+        for first, count in [(0, 5000), (123456, 777)]:
+            say(f"triangles {name}: T={T}, samples [{first}, {first + count})")
+            off, nodes = binding.sample_triangles(ctx, dg, 11, 3, first, count)
+            want_off, want_nodes = oracle.sample_triangles(g, 11, 3, first, count)
+            assert np.array_equal(off_np(off), want_off)
+            assert np.array_equal(nodes_np(nodes), want_nodes)
+    finally:
+        dg.release()
+
+
+def test_triangle_errors(ctx):
+    grid = inputs.grid_graph(8)
+    dg = binding.DeviceGraph(ctx, grid)
+    try:
+        assert binding.centra_triangle_count(ctx, dg.handle) == 0
+        with pytest.raises(binding.CentraError) as e:
+            binding.sample_triangles(ctx, dg, 1, 0, 0, 10)
+        assert e.value.code == binding.CENTRA_EINVAL
+    finally:
+        dg.release()
+    d = inputs.from_edges(3, [0, 1, 2], [1, 2, 0], directed=True)
+    dg = binding.DeviceGraph(ctx, d)
+    try:
+        with pytest.raises(binding.CentraError) as e:
+            binding.centra_triangle_count(ctx, dg.handle)
+        assert e.value.code == binding.CENTRA_ENOTSUP
+    finally:
+        dg.release()
+
+
+@pytest.mark.parametrize("schedule", [binding.CENTRA_SCHEDULE_GEOMETRIC, binding.CENTRA_SCHEDULE_FIXED])
+def test_progressive_on_triangles(ctx, schedule):
+    g = undirected_rmat(12, 3)
+    k, t, eps, delta, seed = 10, 16, 0.1, 0.1, 4
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        say(f"progressive on triangles, schedule {schedule}")
+        rc, picks, res, log = binding.centra_progressive(ctx, dg.handle, k, t, eps, delta, seed, 0, 4000, 256000,
+                                                         schedule=schedule, space=binding.CENTRA_SPACE_TRIANGLES)
+    finally:
+        dg.release()
+    wrc, wpicks, wres, wlog = oracle.progressive(g, k, t, eps, delta, seed, 0, 4000, 256000, schedule=schedule,
+                                                 with_m_log=True, space=oracle.SPACE_TRIANGLES)
+    assert rc == wrc and np.array_equal(picks, wpicks)
+    assert res.iterations == wres.iterations and res.m_final == wres.m_final and res.coverage == wres.coverage
+    assert [it.m for it in log] == wlog
+    assert all(it.b_max == 3 for it in log)
+    for f in ["c_hat", "amcera", "wimpy", "xi", "nu", "rtilde", "r", "eta"]:
+        assert getattr(res, f) == pytest.approx(getattr(wres, f), rel=1e-12, abs=1e-300), f
