@@ -223,7 +223,11 @@ CENTRA_API int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t
  * the triangle of rank r, hyperedge (a, b, c).
  *
  * centra_triangle_count: *T receives the number of triangles (host).  The
- * per-graph triangle index is built on first use and kept with g.
+ * per-graph triangle index is built on first use and kept with g: 12 bytes
+ * per arc, plus 4 bytes per triangle for the ranked list of every
+ * triangle's largest node when that list fits in an eighth of device memory
+ * (samples then read it; otherwise each sample walks its arc's common
+ * neighbours; CENTRA_TRIANGLE_LIST=0 in the environment forces the walk).
  * centra_sample_triangles: samples [first, first + count) into he_off
  * (device u64[count + 1], he_off[i] = 3 i) and he_nodes (device u32[3 count]).
  * Errors: CENTRA_ENOTSUP (directed graph), CENTRA_EINVAL (NULL argument;

@@ -240,6 +240,7 @@ void release_graph_buffers(centra_ctx* ctx, centra_graph* g) {
   release(ctx, g->r_orig_of);
   release(ctx, g->tri_src);
   release(ctx, g->tri_prefix);
+  release(ctx, g->tri_c);
 }
 
 }  // namespace centra

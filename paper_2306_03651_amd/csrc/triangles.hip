@@ -12,7 +12,10 @@
 // order.  Rows are ascending, so the entries of N(a) after b are exactly
 // those above b.  One thread per arc and per sample: the per-arc work is an
 // intersection of two sorted lists, walking the shorter one and binary
-// searching the longer.
+// searching the longer.  When the list of every triangle's c (4 bytes per
+// triangle, in rank order) fits in an eighth of device memory it is kept
+// with the index, and a sample is a binary search over the arcs plus one
+// gather; otherwise the sample walks its arc's intersection.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -36,11 +39,12 @@ __device__ __forceinline__ bool contains(const uint32_t* idx, uint32_t lo, uint3
 }
 
 // The common neighbours above b of arc e = (a, b): the lists A = N(a) after
-// e and B = N(b) above b, both ascending.  Visits them in ascending order by
-// walking the shorter list; stops after `limit` matches (returning the last
-// one in *last) or at the end; returns the number visited.
+// e and B = N(b) above b, both ascending.  Passes them to visit(c) in
+// ascending order by walking the shorter list; stops after `limit` matches
+// or at the end; returns the number visited.
+template <typename Visit>
 __device__ uint32_t common_above(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t a, uint32_t e, uint32_t b,
-                                 uint32_t limit, uint32_t* last) {
+                                 uint32_t limit, Visit visit) {
   const uint32_t a0 = e + 1, a1 = row_ptr[a + 1];
   const uint32_t b1 = row_ptr[b + 1];
   const uint32_t b0 = upper(col_idx, row_ptr[b], b1, b);
@@ -52,7 +56,7 @@ __device__ uint32_t common_above(const uint32_t* row_ptr, const uint32_t* col_id
     const uint32_t c = col_idx[i];
     if (contains(col_idx, s0, s1, c)) {
       ++found;
-      *last = c;
+      visit(c);
     }
   }
   return found;
@@ -64,18 +68,28 @@ __global__ void k_arc_src(uint32_t n, const uint32_t* row_ptr, uint32_t* src) {
   for (uint32_t e = row_ptr[v] + lane_id(); e < row_ptr[v + 1]; e += kWave) src[e] = v;
 }
 
+// Writes the c of every triangle of arc e at rank order: tri_c[prefix[e] + i].
+__global__ void k_tri_list(uint64_t n_arcs, const uint32_t* row_ptr, const uint32_t* col_idx, const uint32_t* src,
+                           const uint64_t* prefix, uint32_t* tri_c) {
+  const uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
+  if (e >= n_arcs || prefix[e + 1] == prefix[e]) return;
+  uint32_t* out = tri_c + prefix[e];
+  common_above(row_ptr, col_idx, src[e], static_cast<uint32_t>(e), col_idx[e], kUnseen,
+               [&](uint32_t c) { *out++ = c; });
+}
+
 __global__ void k_tri_count(uint64_t n_arcs, const uint32_t* row_ptr, const uint32_t* col_idx, const uint32_t* src,
                             uint32_t* cnt) {
   const uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
   if (e >= n_arcs) return;
   const uint32_t a = src[e], b = col_idx[e];
-  uint32_t last = 0;
-  cnt[e] = b > a ? common_above(row_ptr, col_idx, a, static_cast<uint32_t>(e), b, kUnseen, &last) : 0u;
+  cnt[e] = b > a ? common_above(row_ptr, col_idx, a, static_cast<uint32_t>(e), b, kUnseen, [](uint32_t) {}) : 0u;
 }
 
 __global__ void k_tri_sample(uint32_t count, uint64_t first, uint64_t seed, uint32_t instance, uint64_t T,
                              uint64_t n_arcs, const uint64_t* prefix, const uint32_t* src, const uint32_t* row_ptr,
-                             const uint32_t* col_idx, uint64_t base, uint64_t* he_off, uint32_t* he_nodes) {
+                             const uint32_t* col_idx, const uint32_t* tri_c, uint64_t base, uint64_t* he_off,
+                             uint32_t* he_nodes) {
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x > count) return;
   he_off[x] = base + 3ull * x;
@@ -95,9 +109,13 @@ __global__ void k_tri_sample(uint32_t count, uint64_t first, uint64_t seed, uint
   // would also satisfy prefix <= r)
   const uint32_t e = static_cast<uint32_t>(lo);
   const uint32_t a = src[e], b = col_idx[e];
-  const uint32_t want = static_cast<uint32_t>(r - prefix[e]) + 1;
   uint32_t c = kUnseen;
-  common_above(row_ptr, col_idx, a, e, b, want, &c);
+  if (tri_c) {
+    c = tri_c[r];
+  } else {
+    const uint32_t want = static_cast<uint32_t>(r - prefix[e]) + 1;
+    common_above(row_ptr, col_idx, a, e, b, want, [&](uint32_t v) { c = v; });
+  }
   he_nodes[3ull * x] = a;
   he_nodes[3ull * x + 1] = b;
   he_nodes[3ull * x + 2] = c;
@@ -139,7 +157,27 @@ int triangle_index(centra_ctx* ctx, centra_graph* g, uint64_t* T, hipStream_t s)
     rc = fail(ctx, CENTRA_EHIP, "triangles: index failed");
   }
   release(ctx, cnt);
-  return rc;
+  if (rc || total == 0) return rc;
+  // the list of every triangle's c, when it fits (else samples walk;
+  // CENTRA_TRIANGLE_LIST=0 forces the walk, for tests of that path)
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    total_b = 0;
+  }
+  if (const char* v = getenv("CENTRA_TRIANGLE_LIST"))
+    if (v[0] == '0') total_b = 0;
+  if (total * 4 <= total_b / 8 && ensure(ctx, g->tri_c, total * 4, false, s) == CENTRA_OK) {
+    hipLaunchKernelGGL(k_tri_list, dim3(static_cast<unsigned>((A + 255) / 256)), dim3(256), 0, s, A, g->row_ptr,
+                       g->col_idx, src, prefix, static_cast<uint32_t*>(g->tri_c.ptr));
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      release(ctx, g->tri_c);
+      return fail(ctx, CENTRA_EHIP, "triangles: list failed");
+    }
+  } else {
+    ctx->err.clear();   // a refused list is not an error: samples walk instead
+  }
+  return CENTRA_OK;
 }
 
 int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
@@ -150,7 +188,8 @@ int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint3
   if (T == 0) return fail(ctx, CENTRA_EINVAL, "triangles: the graph has no triangle");
   hipLaunchKernelGGL(k_tri_sample, dim3((count + 1 + 255) / 256), dim3(256), 0, s, count, first, seed, instance, T,
                      g->n_arcs, static_cast<const uint64_t*>(g->tri_prefix.ptr),
-                     static_cast<const uint32_t*>(g->tri_src.ptr), g->row_ptr, g->col_idx, base, he_off, he_nodes);
+                     static_cast<const uint32_t*>(g->tri_src.ptr), g->row_ptr, g->col_idx,
+                     static_cast<const uint32_t*>(g->tri_c.ptr), base, he_off, he_nodes);
   CENTRA_HIP(ctx, hipGetLastError());
   return CENTRA_OK;
 }

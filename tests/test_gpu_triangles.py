@@ -29,15 +29,20 @@ GRAPHS = {
 }
 
 
+@pytest.mark.parametrize("c_of", ["list", "walk"])
 @pytest.mark.parametrize("name", list(GRAPHS))
-def test_triangles_bit_exact(ctx, name):
+def test_triangles_bit_exact(ctx, name, c_of, monkeypatch):
+    # "list": each triangle's c is read from the ranked list kept with the
+    # index; "walk": the sample walks its arc's intersection instead.
+    if c_of == "walk":
+        monkeypatch.setenv("CENTRA_TRIANGLE_LIST", "0")
     g = GRAPHS[name]()
     T = len(oracle.triangles(g))
     dg = binding.DeviceGraph(ctx, g)
     try:
         assert binding.centra_triangle_count(ctx, dg.handle) == T
         for first, count in [(0, 5000), (123456, 777)]:
-            say(f"triangles {name}: T={T}, samples [{first}, {first + count})")
+            say(f"triangles {name} ({c_of}): T={T}, samples [{first}, {first + count})")
             off, nodes = binding.sample_triangles(ctx, dg, 11, 3, first, count)
             want_off, want_nodes = oracle.sample_triangles(g, 11, 3, first, count)
             assert np.array_equal(off_np(off), want_off)
