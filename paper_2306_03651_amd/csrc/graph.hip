@@ -241,6 +241,8 @@ void release_graph_buffers(centra_ctx* ctx, centra_graph* g) {
   release(ctx, g->tri_src);
   release(ctx, g->tri_prefix);
   release(ctx, g->tri_c);
+  release(ctx, g->tri_cap);
+  g->tri_list_off = nullptr;
 }
 
 }  // namespace centra

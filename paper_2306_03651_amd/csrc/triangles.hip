@@ -10,12 +10,26 @@
 // (seed, x, instance, tag 5); the arc whose prefix interval holds r gives
 // (a, b), and c is the (r - prefix)-th common neighbour above b in ascending
 // order.  Rows are ascending, so the entries of N(a) after b are exactly
-// those above b.  One thread per arc and per sample: the per-arc work is an
-// intersection of two sorted lists, walking the shorter one and binary
-// searching the longer.  When the list of every triangle's c (4 bytes per
-// triangle, in rank order) fits in an eighth of device memory it is kept
-// with the index, and a sample is a binary search over the arcs plus one
-// gather; otherwise the sample walks its arc's intersection.
+// those above b.
+//
+// Each arc's common neighbours come from walking the shorter of its two
+// ascending lists and searching the longer one, each search starting where
+// the previous one ended.  An arc with at most kHeavy steps is walked by its
+// own lane; longer ones (hub-hub arcs: 93% of the steps on a skewed graph)
+// by the whole wave, 64 keys per step, with the matches placed in order by
+// ballot.  The index also keeps every triangle's c in rank order when it
+// fits in an eighth of device memory, so that a sample is a search over the
+// arcs plus one gather:
+//   - fused: one pass counts the matches and writes them into per-arc slots
+//     sized by the walk length (4 bytes per step of all arcs);
+//   - compact: a counting pass, then a second pass writes the matches at
+//     the triangle prefix (4 bytes per triangle);
+//   - walk (no list): each sample walks its arc's lists to its match.
+// The first that fits is taken; CENTRA_TRIANGLE_LIST=0 forces the walk and
+// CENTRA_TRIANGLE_LIST=compact the compact list (for tests of those paths).
+#include <cstdlib>
+#include <cstring>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -33,33 +47,31 @@ __device__ __forceinline__ uint32_t upper(const uint32_t* idx, uint32_t lo, uint
   return lo;
 }
 
-__device__ __forceinline__ bool contains(const uint32_t* idx, uint32_t lo, uint32_t hi, uint32_t key) {
-  const uint32_t p = upper(idx, lo, hi, key);
-  return p > lo && idx[p - 1] == key;
-}
+constexpr uint32_t kHeavy = 64;   // an arc walked by one lane has at most this many steps
 
-// The common neighbours above b of arc e = (a, b): the lists A = N(a) after
-// e and B = N(b) above b, both ascending.  Passes them to visit(c) in
-// ascending order by walking the shorter list; stops after `limit` matches
-// or at the end; returns the number visited.
-template <typename Visit>
-__device__ uint32_t common_above(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t a, uint32_t e, uint32_t b,
-                                 uint32_t limit, Visit visit) {
+// The two lists of arc e = (a, b): walk [w0, w1), search [s0, s1); empty
+// unless a < b.  A = N(a) after e, B = N(b) above b; the shorter is walked.
+struct ArcLists {
+  uint32_t w0, w1, s0, s1;
+};
+
+__device__ __forceinline__ ArcLists arc_lists(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t a,
+                                              uint32_t e, uint32_t b) {
+  ArcLists L{0, 0, 0, 0};
+  if (b <= a) return L;
   const uint32_t a0 = e + 1, a1 = row_ptr[a + 1];
   const uint32_t b1 = row_ptr[b + 1];
   const uint32_t b0 = upper(col_idx, row_ptr[b], b1, b);
   const bool walk_a = a1 - a0 <= b1 - b0;
-  const uint32_t w0 = walk_a ? a0 : b0, w1 = walk_a ? a1 : b1;
-  const uint32_t s0 = walk_a ? b0 : a0, s1 = walk_a ? b1 : a1;
-  uint32_t found = 0;
-  for (uint32_t i = w0; i < w1 && found < limit; ++i) {
-    const uint32_t c = col_idx[i];
-    if (contains(col_idx, s0, s1, c)) {
-      ++found;
-      visit(c);
-    }
-  }
-  return found;
+  L.w0 = walk_a ? a0 : b0;
+  L.w1 = walk_a ? a1 : b1;
+  L.s0 = walk_a ? b0 : a0;
+  L.s1 = walk_a ? b1 : a1;
+  return L;
+}
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int l) {
+  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l));
 }
 
 __global__ void k_arc_src(uint32_t n, const uint32_t* row_ptr, uint32_t* src) {
@@ -68,28 +80,91 @@ __global__ void k_arc_src(uint32_t n, const uint32_t* row_ptr, uint32_t* src) {
   for (uint32_t e = row_ptr[v] + lane_id(); e < row_ptr[v + 1]; e += kWave) src[e] = v;
 }
 
-// Writes the c of every triangle of arc e at rank order: tri_c[prefix[e] + i].
-__global__ void k_tri_list(uint64_t n_arcs, const uint32_t* row_ptr, const uint32_t* col_idx, const uint32_t* src,
-                           const uint64_t* prefix, uint32_t* tri_c) {
-  const uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
-  if (e >= n_arcs || prefix[e + 1] == prefix[e]) return;
-  uint32_t* out = tri_c + prefix[e];
-  common_above(row_ptr, col_idx, src[e], static_cast<uint32_t>(e), col_idx[e], kUnseen,
-               [&](uint32_t c) { *out++ = c; });
-}
-
-__global__ void k_tri_count(uint64_t n_arcs, const uint32_t* row_ptr, const uint32_t* col_idx, const uint32_t* src,
-                            uint32_t* cnt) {
+// walk length of every arc (the capacity of its slot in the fused list)
+__global__ void k_tri_cap(uint64_t n_arcs, const uint32_t* row_ptr, const uint32_t* col_idx, const uint32_t* src,
+                          uint32_t* cap) {
   const uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
   if (e >= n_arcs) return;
-  const uint32_t a = src[e], b = col_idx[e];
-  cnt[e] = b > a ? common_above(row_ptr, col_idx, a, static_cast<uint32_t>(e), b, kUnseen, [](uint32_t) {}) : 0u;
+  const ArcLists L = arc_lists(row_ptr, col_idx, src[e], static_cast<uint32_t>(e), col_idx[e]);
+  cap[e] = L.w1 - L.w0;
+}
+
+// cnt[e] = the number of common neighbours above b of arc e; with kWrite they
+// are also written, ascending, at tri_c[out_off[e]...].
+template <bool kWrite>
+__global__ void __launch_bounds__(256) k_tri_arcs(uint64_t n_arcs, const uint32_t* row_ptr, const uint32_t* col_idx,
+                                                  const uint32_t* src, const uint64_t* out_off, uint32_t* tri_c,
+                                                  uint32_t* cnt) {
+  const uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
+  const int lane = lane_id();
+  ArcLists L{0, 0, 0, 0};
+  if (e < n_arcs) L = arc_lists(row_ptr, col_idx, src[e], static_cast<uint32_t>(e), col_idx[e]);
+  const uint32_t w = L.w1 - L.w0;
+  const uint64_t off = kWrite && w ? out_off[e] : 0;
+  uint32_t found = 0;
+  if (w <= kHeavy) {
+    uint32_t lo = L.s0;
+    for (uint32_t i = L.w0; i < L.w1; ++i) {
+      const uint32_t c = col_idx[i];
+      const uint32_t p = upper(col_idx, lo, L.s1, c);
+      if (p > lo && col_idx[p - 1] == c) {
+        if (kWrite) tri_c[off + found] = c;
+        ++found;
+      }
+      lo = p;
+    }
+  }
+  // heavy arcs of this wave, one at a time, by all 64 lanes
+  uint64_t heavy = __ballot(w > kHeavy);
+  while (heavy) {
+    const int h = __ffsll(static_cast<unsigned long long>(heavy)) - 1;
+    heavy &= heavy - 1;
+    const uint32_t w0 = readlane_u32(L.w0, h), w1 = readlane_u32(L.w1, h);
+    const uint32_t s1 = readlane_u32(L.s1, h);
+    const uint64_t hoff = kWrite ? (uint64_t(readlane_u32(static_cast<uint32_t>(off >> 32), h)) << 32) |
+                                       readlane_u32(static_cast<uint32_t>(off), h)
+                                 : 0;
+    uint32_t lo = readlane_u32(L.s0, h), n = 0;
+    for (uint32_t base = w0; base < w1; base += kWave) {
+      const uint32_t i = base + lane;
+      uint32_t c = 0, p = lo;
+      bool hit = false;
+      if (i < w1) {
+        c = col_idx[i];
+        p = upper(col_idx, lo, s1, c);
+        hit = p > lo && col_idx[p - 1] == c;
+      }
+      const uint64_t m = __ballot(hit);
+      if (kWrite && hit) tri_c[hoff + n + __popcll(m & ((1ull << lane) - 1))] = c;
+      n += __popcll(m);
+      // keys ascend across steps: the next search starts at the last key's place
+      const uint32_t last = w1 - 1 - base < uint32_t(kWave) ? w1 - 1 - base : uint32_t(kWave - 1);
+      lo = readlane_u32(p, static_cast<int>(last));
+    }
+    if (lane == h) found = n;
+  }
+  if (e < n_arcs) cnt[e] = found;
+}
+
+// The want-th (1-based) common neighbour above b of arc e, walking its lists
+// (the sampler's path when no list is kept).
+__device__ uint32_t nth_common(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t a, uint32_t e, uint32_t b,
+                               uint32_t want) {
+  const ArcLists L = arc_lists(row_ptr, col_idx, a, e, b);
+  uint32_t lo = L.s0, found = 0;
+  for (uint32_t i = L.w0; i < L.w1; ++i) {
+    const uint32_t c = col_idx[i];
+    const uint32_t p = upper(col_idx, lo, L.s1, c);
+    if (p > lo && col_idx[p - 1] == c && ++found == want) return c;
+    lo = p;
+  }
+  return kUnseen;
 }
 
 __global__ void k_tri_sample(uint32_t count, uint64_t first, uint64_t seed, uint32_t instance, uint64_t T,
                              uint64_t n_arcs, const uint64_t* prefix, const uint32_t* src, const uint32_t* row_ptr,
-                             const uint32_t* col_idx, const uint32_t* tri_c, uint64_t base, uint64_t* he_off,
-                             uint32_t* he_nodes) {
+                             const uint32_t* col_idx, const uint64_t* list_off, const uint32_t* tri_c, uint64_t base,
+                             uint64_t* he_off, uint32_t* he_nodes) {
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x > count) return;
   he_off[x] = base + 3ull * x;
@@ -109,16 +184,18 @@ __global__ void k_tri_sample(uint32_t count, uint64_t first, uint64_t seed, uint
   // would also satisfy prefix <= r)
   const uint32_t e = static_cast<uint32_t>(lo);
   const uint32_t a = src[e], b = col_idx[e];
-  uint32_t c = kUnseen;
-  if (tri_c) {
-    c = tri_c[r];
-  } else {
-    const uint32_t want = static_cast<uint32_t>(r - prefix[e]) + 1;
-    common_above(row_ptr, col_idx, a, e, b, want, [&](uint32_t v) { c = v; });
-  }
+  const uint32_t c = list_off ? tri_c[list_off[e] + (r - prefix[e])]
+                              : nth_common(row_ptr, col_idx, a, e, b, static_cast<uint32_t>(r - prefix[e]) + 1);
   he_nodes[3ull * x] = a;
   he_nodes[3ull * x + 1] = b;
   he_nodes[3ull * x + 2] = c;
+}
+
+static int read_u64(centra_ctx* ctx, const uint64_t* d, uint64_t* h, hipStream_t s) {
+  CENTRA_HIP(ctx, hipGetLastError());
+  CENTRA_HIP(ctx, hipMemcpyAsync(h, d, 8, hipMemcpyDeviceToHost, s));
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  return CENTRA_OK;
 }
 
 // Builds the triangle index of an undirected graph once; *T receives the
@@ -131,52 +208,83 @@ int triangle_index(centra_ctx* ctx, centra_graph* g, uint64_t* T, hipStream_t s)
   }
   const uint64_t A = g->n_arcs;
   int rc;
-  DevBuf cnt;
   if ((rc = ensure(ctx, g->tri_src, (A ? A : 1) * 4, false, s))) return rc;
   if ((rc = ensure(ctx, g->tri_prefix, (A + 1) * 8, false, s))) return rc;
+  DevBuf cnt;
   if ((rc = ensure(ctx, cnt, (A ? A : 1) * 4, false, s))) return rc;
   uint32_t* src = static_cast<uint32_t*>(g->tri_src.ptr);
   uint64_t* prefix = static_cast<uint64_t*>(g->tri_prefix.ptr);
+  uint32_t* cn = static_cast<uint32_t*>(cnt.ptr);
+  const dim3 grid_a(static_cast<unsigned>((A + 255) / 256 ? (A + 255) / 256 : 1));
   const uint64_t wthreads = uint64_t(g->n) * kWave;
   hipLaunchKernelGGL(k_arc_src, dim3(static_cast<unsigned>((wthreads + 255) / 256)), dim3(256), 0, s, g->n,
                      g->row_ptr, src);
-  if (A)
-    hipLaunchKernelGGL(k_tri_count, dim3(static_cast<unsigned>((A + 255) / 256)), dim3(256), 0, s, A, g->row_ptr,
-                       g->col_idx, src, static_cast<uint32_t*>(cnt.ptr));
-  if (hipGetLastError() != hipSuccess) {
-    release(ctx, cnt);
-    return fail(ctx, CENTRA_EHIP, "triangles: index launch failed");
-  }
-  rc = excl_scan_u32_to_u64(ctx, static_cast<uint32_t*>(cnt.ptr), prefix, A, s);
-  uint64_t total = 0;
-  if (!rc && hipMemcpyAsync(&total, prefix + A, 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
-      hipStreamSynchronize(s) == hipSuccess) {
-    g->tri_total = total;
-    *T = total;
-  } else if (!rc) {
-    rc = fail(ctx, CENTRA_EHIP, "triangles: index failed");
-  }
-  release(ctx, cnt);
-  if (rc || total == 0) return rc;
-  // the list of every triangle's c, when it fits (else samples walk;
-  // CENTRA_TRIANGLE_LIST=0 forces the walk, for tests of that path)
+  // room for a list
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
     (void)hipGetLastError();
     total_b = 0;
   }
-  if (const char* v = getenv("CENTRA_TRIANGLE_LIST"))
-    if (v[0] == '0') total_b = 0;
-  if (total * 4 <= total_b / 8 && ensure(ctx, g->tri_c, total * 4, false, s) == CENTRA_OK) {
-    hipLaunchKernelGGL(k_tri_list, dim3(static_cast<unsigned>((A + 255) / 256)), dim3(256), 0, s, A, g->row_ptr,
-                       g->col_idx, src, prefix, static_cast<uint32_t*>(g->tri_c.ptr));
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-      release(ctx, g->tri_c);
-      return fail(ctx, CENTRA_EHIP, "triangles: list failed");
+  const char* mode = getenv("CENTRA_TRIANGLE_LIST");
+  const uint64_t room = mode && mode[0] == '0' ? 0 : total_b / 8;
+  const bool try_fused = !(mode && strcmp(mode, "compact") == 0);
+  uint32_t* list = nullptr;
+  const uint64_t* list_off = nullptr;
+  g->tri_list_off = nullptr;
+  if (A && room && try_fused) {
+    uint64_t cap_total = 0;
+    if (!(rc = ensure(ctx, g->tri_cap, (A + 1) * 8, false, s))) {
+      hipLaunchKernelGGL(k_tri_cap, grid_a, dim3(256), 0, s, A, g->row_ptr, g->col_idx, src, cn);
+      uint64_t* cap = static_cast<uint64_t*>(g->tri_cap.ptr);
+      if (!(rc = excl_scan_u32_to_u64(ctx, cn, cap, A, s))) rc = read_u64(ctx, cap + A, &cap_total, s);
     }
-  } else {
-    ctx->err.clear();   // a refused list is not an error: samples walk instead
+    if (rc == CENTRA_EHIP) {
+      release(ctx, cnt);
+      return rc;
+    }
+    if (!rc && cap_total && cap_total * 4 <= room && ensure(ctx, g->tri_c, cap_total * 4, false, s) == CENTRA_OK) {
+      list = static_cast<uint32_t*>(g->tri_c.ptr);
+      list_off = static_cast<const uint64_t*>(g->tri_cap.ptr);
+    } else {
+      release(ctx, g->tri_cap);
+      ctx->err.clear();   // no room for the fused list is not an error
+    }
+    rc = CENTRA_OK;
   }
+  if (A) {
+    if (list)
+      hipLaunchKernelGGL(k_tri_arcs<true>, grid_a, dim3(256), 0, s, A, g->row_ptr, g->col_idx, src, list_off, list,
+                         cn);
+    else
+      hipLaunchKernelGGL(k_tri_arcs<false>, grid_a, dim3(256), 0, s, A, g->row_ptr, g->col_idx, src, list_off, list,
+                         cn);
+  }
+  uint64_t total = 0;
+  if (!(rc = excl_scan_u32_to_u64(ctx, cn, prefix, A, s))) rc = read_u64(ctx, prefix + A, &total, s);
+  if (!rc && !list && total && total * 4 <= room && ensure(ctx, g->tri_c, total * 4, false, s) == CENTRA_OK) {
+    // compact list: a second pass writes the matches at the triangle prefix
+    list = static_cast<uint32_t*>(g->tri_c.ptr);
+    list_off = prefix;
+    hipLaunchKernelGGL(k_tri_arcs<true>, grid_a, dim3(256), 0, s, A, g->row_ptr, g->col_idx, src, list_off, list,
+                       cn);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      rc = fail(ctx, CENTRA_EHIP, "triangles: list failed");
+  }
+  release(ctx, cnt);
+  if (rc) {
+    release(ctx, g->tri_c);
+    release(ctx, g->tri_cap);
+    return rc;
+  }
+  ctx->err.clear();   // a refused list is not an error: samples walk instead
+  if (total == 0) {
+    release(ctx, g->tri_c);
+    release(ctx, g->tri_cap);
+    list_off = nullptr;
+  }
+  g->tri_list_off = list_off;
+  g->tri_total = total;
+  *T = total;
   return CENTRA_OK;
 }
 
@@ -188,7 +296,7 @@ int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint3
   if (T == 0) return fail(ctx, CENTRA_EINVAL, "triangles: the graph has no triangle");
   hipLaunchKernelGGL(k_tri_sample, dim3((count + 1 + 255) / 256), dim3(256), 0, s, count, first, seed, instance, T,
                      g->n_arcs, static_cast<const uint64_t*>(g->tri_prefix.ptr),
-                     static_cast<const uint32_t*>(g->tri_src.ptr), g->row_ptr, g->col_idx,
+                     static_cast<const uint32_t*>(g->tri_src.ptr), g->row_ptr, g->col_idx, g->tri_list_off,
                      static_cast<const uint32_t*>(g->tri_c.ptr), base, he_off, he_nodes);
   CENTRA_HIP(ctx, hipGetLastError());
   return CENTRA_OK;

@@ -26,16 +26,27 @@ GRAPHS = {
     "gnp300": lambda: gnp(300, 0.1, 2),
     "ba2000": lambda: inputs.ba_graph(2000, 5, 1),
     "rmat12u": lambda: undirected_rmat(12, 3),
+    # dense: 17k arcs with more than 64 walk steps (the wave-wide walk)
+    "gnp400": lambda: gnp(400, 0.5, 5),
 }
 
+# how the index keeps each triangle's largest node (environment value):
+# fused per-arc slots (default), compact list at the triangle prefix, or
+# none (samples walk their arc's lists)
+LIST_MODES = {"fused": None, "compact": "compact", "walk": "0"}
 
-@pytest.mark.parametrize("c_of", ["list", "walk"])
+
+def set_list_mode(monkeypatch, mode):
+    if LIST_MODES[mode] is None:
+        monkeypatch.delenv("CENTRA_TRIANGLE_LIST", raising=False)
+    else:
+        monkeypatch.setenv("CENTRA_TRIANGLE_LIST", LIST_MODES[mode])
+
+
+@pytest.mark.parametrize("c_of", list(LIST_MODES))
 @pytest.mark.parametrize("name", list(GRAPHS))
 def test_triangles_bit_exact(ctx, name, c_of, monkeypatch):
-    # "list": each triangle's c is read from the ranked list kept with the
-    # index; "walk": the sample walks its arc's intersection instead.
-    if c_of == "walk":
-        monkeypatch.setenv("CENTRA_TRIANGLE_LIST", "0")
+    set_list_mode(monkeypatch, c_of)
     g = GRAPHS[name]()
     T = len(oracle.triangles(g))
     dg = binding.DeviceGraph(ctx, g)
@@ -90,3 +101,30 @@ def test_progressive_on_triangles(ctx, schedule):
     assert all(it.b_max == 3 for it in log)
     for f in ["c_hat", "amcera", "wimpy", "xi", "nu", "rtilde", "r", "eta"]:
         assert getattr(res, f) == pytest.approx(getattr(wres, f), rel=1e-12, abs=1e-300), f
+
+
+def test_triangles_rmat16_all_modes(ctx, monkeypatch):
+    # Undirected R-MAT scale 16 (955k arcs, hub degree 2.5k, 72k arcs walked
+    # wave-wide): T equals trace(A^3)/6, and 200k samples are identical in
+    # the three list modes and are triangles a < b < c.
+    import scipy.sparse as sp
+    g = undirected_rmat(16, 2)
+    M = sp.csr_matrix((np.ones(g.n_arcs, np.int64), g.col_idx.astype(np.int64), g.row_ptr.astype(np.int64)),
+                      shape=(g.n, g.n))
+    T = int((M @ M).multiply(M).sum()) // 6
+    got = {}
+    for mode in LIST_MODES:
+        set_list_mode(monkeypatch, mode)
+        dg = binding.DeviceGraph(ctx, g)
+        try:
+            say(f"rmat16u triangles ({mode}): T={T}")
+            assert binding.centra_triangle_count(ctx, dg.handle) == T
+            off, nodes = binding.sample_triangles(ctx, dg, 7, 1, 1000, 200000)
+            got[mode] = nodes_np(nodes).reshape(-1, 3).copy()
+        finally:
+            dg.release()
+    assert np.array_equal(got["fused"], got["compact"]) and np.array_equal(got["fused"], got["walk"])
+    tri = got["fused"].astype(np.int64)
+    assert (tri[:, 0] < tri[:, 1]).all() and (tri[:, 1] < tri[:, 2]).all()
+    for x, y in [(0, 1), (0, 2), (1, 2)]:
+        assert np.asarray(M[tri[:, x], tri[:, y]]).ravel().all()
