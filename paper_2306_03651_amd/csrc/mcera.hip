@@ -15,12 +15,15 @@
 // adds when the walk leaves the node (spans may split a node, hence the
 // atomics; integer sums keep the result exact and order independent).
 //
-// Top-k.  One workgroup per trial (plus one for the degrees) selects the
-// k-th largest positive value of its row by MSD radix selection: a
-// histogram over the bit length, then 12-bit digit histograms below the
-// leading bit, each with per-bin counts and sums in LDS; the answer is the
-// sum of every value above the selected one plus the remaining copies of
-// it.
+// Top-k.  For every trial row (plus one row of degrees) the k-th largest
+// positive value is found by MSD radix selection: a histogram over the bit
+// length, then 10-bit digit histograms below the leading bit, each with
+// per-bin counts and sums; the answer is the sum of every value above the
+// selected one plus the remaining copies of it.  Each pass splits every row
+// over many workgroups, which build LDS histograms and merge them into the
+// row's global histogram with atomics (a row on one workgroup would leave
+// most CUs idle and serialise on a few LDS bins); a one-wave kernel per row
+// then picks the digit with a wave scan and clears the histogram.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -136,106 +139,148 @@ __global__ __launch_bounds__(256) void k_rade_finish(const int32_t* P, const uin
 }
 
 // ---------------------------------------------------------------------------
-constexpr int kTopBlock = 1024;
-constexpr int kDigitBits = 12;
-constexpr int kBins = 1 << kDigitBits;
+constexpr int kSelBlock = 256;
+constexpr int kDigitBits = 10;
+constexpr uint32_t kBins = 1u << kDigitBits;   // also holds the 32 bit-length bins
+constexpr int kDigitPasses = (30 + kDigitBits - 1) / kDigitBits;   // bits below the leading one
 
-struct TopShared {
-  uint32_t cnt[kBins];
-  uint64_t sum[kBins];
-  uint32_t prefix, pbits, blen, need, done;
+// Selection state of one row: the values still sought have bit length blen
+// and their top pbits bits equal prefix; need of them are still to be taken
+// and acc holds the sum of the values already taken.
+struct SelState {
+  uint32_t prefix, pbits, blen, need, done, pad;
   int64_t acc;
 };
 
-// Row r < t: trial r of Rtm; row t: deg (values as int32).  out[r] = sum of
-// the min(k, #positive) largest positive values of the row.
-__global__ __launch_bounds__(kTopBlock) void k_topk_rows(const int32_t* Rtm, const uint32_t* deg, uint32_t n,
-                                                        uint32_t t, uint32_t k, int64_t* out) {
-  __shared__ TopShared sh;
-  const uint32_t r = blockIdx.x;
-  const int32_t* row = r < t ? Rtm + uint64_t(r) * n : reinterpret_cast<const int32_t*>(deg);
-  const int tid = threadIdx.x;
-  // pass 0: bit-length histogram (bins 1..31)
-  for (int i = tid; i < 32; i += kTopBlock) {
-    sh.cnt[i] = 0;
-    sh.sum[i] = 0;
+__device__ __forceinline__ const int32_t* sel_row(const int32_t* Rtm, const uint32_t* deg, uint32_t n, uint32_t t,
+                                                  uint32_t r) {
+  return r < t ? Rtm + uint64_t(r) * n : reinterpret_cast<const int32_t*>(deg);
+}
+
+__global__ void k_sel_init(SelState* st, uint32_t rows, uint32_t k, uint32_t* hcnt, uint64_t* hsum) {
+  const uint64_t nb = uint64_t(rows) * kBins;
+  for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < nb; i += uint64_t(gridDim.x) * blockDim.x) {
+    hcnt[i] = 0;
+    hsum[i] = 0;
+    if (i < rows) st[i] = SelState{1, 1, 0, k, k == 0 ? 1u : 0u, 0, 0};
+  }
+}
+
+// Pass `first`: bit lengths (bins 1..31) of the positive values; else the
+// next digit of the values matching the row's prefix.  Block (x, r) takes
+// values [x chunk, (x+1) chunk) of row r.
+__global__ __launch_bounds__(kSelBlock) void k_sel_hist(const int32_t* Rtm, const uint32_t* deg, uint32_t n,
+                                                        uint32_t t, uint32_t chunk, const SelState* st, int first,
+                                                        uint32_t* hcnt, uint64_t* hsum) {
+  __shared__ uint32_t cnt[kBins];
+  __shared__ uint64_t sum[kBins];
+  const uint32_t r = blockIdx.y;
+  const SelState s = st[r];
+  if (s.done) return;
+  const uint32_t B = s.blen, up = B - s.pbits;
+  const uint32_t nb = first ? 5u : (up < uint32_t(kDigitBits) ? up : uint32_t(kDigitBits));
+  const uint32_t shift = first ? 0u : up - nb;
+  const uint32_t nbins = first ? 32u : 1u << nb;
+  for (uint32_t b = threadIdx.x; b < nbins; b += kSelBlock) {
+    cnt[b] = 0;
+    sum[b] = 0;
   }
   __syncthreads();
-  for (uint32_t i = tid; i < n; i += kTopBlock) {
+  const int32_t* row = sel_row(Rtm, deg, n, t, r);
+  const uint64_t i0 = uint64_t(blockIdx.x) * chunk;
+  const uint64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+  for (uint64_t i = i0 + threadIdx.x; i < i1; i += kSelBlock) {
     const int32_t x = row[i];
-    if (x > 0) {
-      const uint32_t b = bitlen32(static_cast<uint32_t>(x));
-      atomicAdd(&sh.cnt[b], 1u);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&sh.sum[b]), static_cast<unsigned long long>(x));
+    if (x <= 0) continue;
+    const uint32_t ux = static_cast<uint32_t>(x);
+    uint32_t bin;
+    if (first) {
+      bin = bitlen32(ux);
+    } else {
+      if ((ux >> up) != s.prefix) continue;
+      bin = (ux >> shift) & (nbins - 1u);
+    }
+    atomicAdd(&cnt[bin], 1u);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&sum[bin]), static_cast<unsigned long long>(ux));
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nbins; b += kSelBlock) {
+    if (cnt[b]) {
+      atomicAdd(&hcnt[uint64_t(r) * kBins + b], cnt[b]);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&hsum[uint64_t(r) * kBins + b]),
+                static_cast<unsigned long long>(sum[b]));
     }
   }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t need = k;
-    int64_t acc = 0;
-    uint32_t blen = 0;
-    for (int b = 31; b >= 1; --b) {
-      if (sh.cnt[b] < need) {
-        need -= sh.cnt[b];
-        acc += static_cast<int64_t>(sh.sum[b]);
+}
+
+// One wave per row: walking the bins from the top, the bin where the count
+// reaches `need` is the next digit (or bit length); the bins above it are
+// taken whole.  Clears the row's histogram for the next pass.
+__global__ __launch_bounds__(kWave) void k_sel_decide(SelState* st, int first, uint32_t* hcnt, uint64_t* hsum) {
+  const uint32_t r = blockIdx.x;
+  const int lane = lane_id();
+  SelState s = st[r];
+  if (s.done) return;
+  const uint32_t up = s.blen - s.pbits;
+  const uint32_t nb = first ? 5u : (up < uint32_t(kDigitBits) ? up : uint32_t(kDigitBits));
+  const uint32_t nbins = first ? 32u : 1u << nb;
+  const uint32_t per = nbins > uint32_t(kWave) ? nbins / kWave : 1u;
+  uint32_t* C = hcnt + uint64_t(r) * kBins;
+  uint64_t* S = hsum + uint64_t(r) * kBins;
+  // lane L owns bins [hi - per, hi) with hi = nbins - L per (top bins first)
+  const bool owns = uint32_t(lane) * per < nbins;
+  const uint32_t hi = owns ? nbins - uint32_t(lane) * per : 0u;
+  uint32_t c = 0;
+  uint64_t sm = 0;
+  for (uint32_t b = hi; b > hi - (owns ? per : 0u); --b) {
+    c += C[b - 1];
+    sm += S[b - 1];
+  }
+  const uint32_t c_incl = wave_incl_scan_u32(c);
+  const uint64_t s_incl = wave_incl_scan_u64(sm);
+  const uint32_t c_excl = c_incl - c;
+  const uint64_t f = __ballot(owns && c_excl < s.need && c_incl >= s.need);
+  if (f == 0) {
+    // fewer than `need` values left (only in the first pass: fewer than k
+    // positive values): all of them are taken
+    if (lane == kWave - 1) {
+      s.acc += static_cast<int64_t>(s_incl);
+      s.done = 1;
+      st[r] = s;
+    }
+  } else if (lane == __ffsll(static_cast<unsigned long long>(f)) - 1) {
+    uint32_t rem = s.need - c_excl;
+    int64_t acc = s.acc + static_cast<int64_t>(s_incl - sm);
+    uint32_t d = hi - 1;
+    for (uint32_t b = hi; b > hi - per; --b) {
+      d = b - 1;
+      if (C[d] < rem) {
+        rem -= C[d];
+        acc += static_cast<int64_t>(S[d]);
       } else {
-        blen = b;
         break;
       }
     }
-    sh.need = need;
-    sh.acc = acc;
-    sh.blen = blen;
-    sh.done = blen == 0;   // fewer than k positive values: acc is the answer
-    sh.prefix = 1;
-    sh.pbits = 1;
+    if (first) {
+      s.blen = d;
+      s.prefix = 1;
+      s.pbits = 1;
+    } else {
+      s.prefix = (s.prefix << nb) | d;
+      s.pbits += nb;
+    }
+    s.need = rem;
+    s.acc = acc;
+    if (s.pbits >= s.blen) {   // every bit fixed: the remaining copies of prefix
+      s.acc += static_cast<int64_t>(s.need) * static_cast<int64_t>(s.prefix);
+      s.done = 1;
+    }
+    st[r] = s;
   }
-  __syncthreads();
-  while (!sh.done) {
-    const uint32_t B = sh.blen, pbits = sh.pbits, prefix = sh.prefix;
-    if (pbits >= B) {
-      if (tid == 0) {
-        sh.acc += static_cast<int64_t>(sh.need) * static_cast<int64_t>(prefix);
-        sh.done = 1;
-      }
-      __syncthreads();
-      break;
-    }
-    const uint32_t nb = B - pbits < kDigitBits ? B - pbits : kDigitBits;
-    const uint32_t shift = B - pbits - nb;
-    for (int i = tid; i < (1 << nb); i += kTopBlock) {
-      sh.cnt[i] = 0;
-      sh.sum[i] = 0;
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < n; i += kTopBlock) {
-      const int32_t x = row[i];
-      if (x > 0 && (static_cast<uint32_t>(x) >> (B - pbits)) == prefix) {
-        const uint32_t dg = (static_cast<uint32_t>(x) >> shift) & ((1u << nb) - 1u);
-        atomicAdd(&sh.cnt[dg], 1u);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&sh.sum[dg]), static_cast<unsigned long long>(x));
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t need = sh.need;
-      int64_t acc = sh.acc;
-      for (int d = (1 << nb) - 1; d >= 0; --d) {
-        if (sh.cnt[d] < need) {
-          need -= sh.cnt[d];
-          acc += static_cast<int64_t>(sh.sum[d]);
-        } else {
-          sh.prefix = (prefix << nb) | static_cast<uint32_t>(d);
-          break;
-        }
-      }
-      sh.pbits = pbits + nb;
-      sh.need = need;
-      sh.acc = acc;
-    }
-    __syncthreads();
+  for (uint32_t b = lane; b < nbins; b += kWave) {
+    C[b] = 0;
+    S[b] = 0;
   }
-  if (tid == 0) out[r] = sh.acc;
 }
 
 __global__ void k_bmax(const uint64_t* he_off, uint64_t m, uint32_t* b_max) {
@@ -251,12 +296,12 @@ __global__ void k_bmax(const uint64_t* he_off, uint64_t m, uint32_t* b_max) {
   if (lane_id() == 0 && mx) atomicMax(b_max, mx);
 }
 
-__global__ void k_mcera_out(const int64_t* rows, uint32_t t, int64_t* topk_sum, uint64_t* deg_topk) {
+__global__ void k_mcera_out(const SelState* st, uint32_t t, int64_t* topk_sum, uint64_t* deg_topk) {
   for (uint32_t j = threadIdx.x; j <= t; j += blockDim.x) {
     if (j < t)
-      topk_sum[j] = rows[j];
+      topk_sum[j] = st[j].acc;
     else
-      *deg_topk = static_cast<uint64_t>(rows[t]);
+      *deg_topk = static_cast<uint64_t>(st[t].acc);
   }
 }
 
@@ -269,10 +314,13 @@ int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* 
   int rc;
   if ((rc = ensure(ctx, ctx->P, size_t(n) * t * 4, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->Rtm, size_t(n) * t * 4, false, s))) return rc;
-  if ((rc = ensure(ctx, ctx->topk_tmp, (size_t(t) + 1) * 8, false, s))) return rc;
+  const uint32_t rows = t + 1;
+  if ((rc = ensure(ctx, ctx->topk_tmp, size_t(rows) * (sizeof(SelState) + kBins * 12), false, s))) return rc;
   int32_t* P = static_cast<int32_t*>(ctx->P.ptr);
   int32_t* Rtm = static_cast<int32_t*>(ctx->Rtm.ptr);
-  int64_t* rows = static_cast<int64_t*>(ctx->topk_tmp.ptr);
+  SelState* st = static_cast<SelState*>(ctx->topk_tmp.ptr);
+  uint64_t* hsum = reinterpret_cast<uint64_t*>(st + rows);
+  uint32_t* hcnt = reinterpret_cast<uint32_t*>(hsum + size_t(rows) * kBins);
   fill_u32(reinterpret_cast<uint32_t*>(P), 0, size_t(n) * t, s);
   if (I) {
     const uint64_t waves = (I + kSpan - 1) / kSpan;
@@ -283,9 +331,21 @@ int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* 
   }
   hipLaunchKernelGGL(k_rade_finish, dim3((n + 63) / 64, (t + 63) / 64), dim3(256), 0, s, P,
                      static_cast<const uint32_t*>(ctx->deg.ptr), n, t, Rtm, R_out);
-  hipLaunchKernelGGL(k_topk_rows, dim3(t + 1), dim3(kTopBlock), 0, s, Rtm, static_cast<const uint32_t*>(ctx->deg.ptr),
-                     n, t, k, rows);
-  hipLaunchKernelGGL(k_mcera_out, dim3(1), dim3(256), 0, s, rows, t, topk_sum, deg_topk);
+  // selection: about 2,048 workgroups per histogram pass, at least 4,096
+  // values each
+  const uint32_t* degp = static_cast<const uint32_t*>(ctx->deg.ptr);
+  uint32_t parts = 2048 / rows ? 2048 / rows : 1u;
+  const uint32_t max_parts = (n + 4095) / 4096 ? (n + 4095) / 4096 : 1u;
+  if (parts > max_parts) parts = max_parts;
+  const uint32_t chunk = (n + parts - 1) / parts ? (n + parts - 1) / parts : 1u;
+  hipLaunchKernelGGL(k_sel_init, dim3(grid_for(uint64_t(rows) * kBins, 256)), dim3(256), 0, s, st, rows, k, hcnt,
+                     hsum);
+  for (int pass = 0; pass <= kDigitPasses; ++pass) {
+    hipLaunchKernelGGL(k_sel_hist, dim3(parts, rows), dim3(kSelBlock), 0, s, Rtm, degp, n, t, chunk, st,
+                       pass == 0 ? 1 : 0, hcnt, hsum);
+    hipLaunchKernelGGL(k_sel_decide, dim3(rows), dim3(kWave), 0, s, st, pass == 0 ? 1 : 0, hcnt, hsum);
+  }
+  hipLaunchKernelGGL(k_mcera_out, dim3(1), dim3(256), 0, s, st, t, topk_sum, deg_topk);
   fill_u32(b_max, 0, 1, s);
   hipLaunchKernelGGL(k_bmax, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, he_off, m, b_max);
   CENTRA_HIP(ctx, hipGetLastError());

@@ -134,3 +134,28 @@ def test_skewed_directed_scale_cover_and_mcera(ctx):
     topk, dk, bm = gpu_mcera(ctx, n, off, nodes, 3, 1, 128, 100)
     _, wtopk, wdk, wbm = oracle.mcera(n, off, nodes, 3, 1, 128, 100)
     assert np.array_equal(topk, wtopk) and dk == wdk and bm == wbm
+
+
+def test_topk_every_digit_pass(ctx):
+    # Node 0 is in all 3M hyperedges: its degree has bit length 22, so the
+    # degree row's selection runs the bit-length pass and three digit passes.
+    m, n = 3_000_000, 51
+    rng = np.random.default_rng(3)
+    lens = rng.integers(1, 3, size=m)
+    off = np.zeros(m + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(lens + 1)
+    rows = [np.concatenate(([0], rng.choice(np.arange(1, n), size=int(l), replace=False))) for l in lens[:1000]]
+    rest = np.stack([np.zeros(m - 1000, dtype=np.int64), 1 + rng.integers(0, n - 1, size=m - 1000),
+                     1 + rng.integers(0, n - 1, size=m - 1000)], axis=1)
+    # hyperedges after the first 1,000 have two nodes besides 0; make them distinct
+    clash = rest[:, 1] == rest[:, 2]
+    rest[clash, 2] = 1 + rest[clash, 2] % (n - 1)
+    lens[1000:] = 2
+    off[1:] = np.cumsum(lens + 1)
+    nodes = np.concatenate([np.concatenate(rows), rest.ravel()]).astype(np.uint32)
+    assert len(nodes) == off[-1]
+    for k in [1, 5, 60]:
+        say(f"top-k digit passes k={k}")
+        topk, dk, bm = gpu_mcera(ctx, n, off, nodes, 2, 0, 8, k)
+        _, wtopk, wdk, wbm = oracle.mcera(n, off, nodes, 2, 0, 8, k)
+        assert np.array_equal(topk, wtopk) and dk == wdk and bm == wbm
