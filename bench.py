@@ -10,24 +10,42 @@ cover, AMCERA and bound at every iteration) until the stopping condition
 holds or the cap is reached.  value = shortest paths sampled per second of
 whole-job time.
 
-`--workload skewed` runs the skewed directed configuration instead: R-MAT
-scale 22 (edge factor 16, a/b/c/d = .57/.19/.19/.05, seed 1, duplicates and
-self loops dropped) with its reverse CSR; 2,000,000 samples doubling to
-8,000,000, k = 100, t = 128, eps = 0.01, delta = 0.1.
+Other workloads (`--workload`):
+  skewed     the skewed directed configuration: R-MAT scale 22 (edge factor
+             16, a/b/c/d = .57/.19/.19/.05, seed 1, duplicates and self loops
+             dropped) with its reverse CSR; 2,000,000 samples doubling to
+             8,000,000, k = 100, t = 128, eps = 0.01, delta = 0.1;
+  small      the small configuration: Barabasi-Albert n = 2,000, attachment
+             5; one iteration at 10,000 samples, k = 10, t = 10,
+             eps = 0.05, delta = 0.1;
+  triangles  Algorithm 1 on the triangle hyperedge space (the triangle
+             centrality) of the R-MAT scale 20 graph above, symmetrised
+             (1,048,576 nodes, 31.4M arcs, 424M triangles); 1,000,000
+             samples doubling to 8,000,000, k = 50, t = 64, eps = 0.01,
+             delta = 0.1; the per-graph triangle index is built once before
+             the timed steps and its time is reported as index_s.
 
 Also reported:
-  - roofline: the sampling kernel's algorithmic bytes per launch
-    (4 B per CSR entry scanned + 28 B per node given a level, counted
-    exactly by the kernel) over its average launch time, measured with HIP
-    events recorded on the launch stream around every launch in the timed
-    region; `traffic` comes from the committed rocprofv3 counter summary
-    when it was taken on the current kernel source, else null;
-  - cpu_baseline: the oracle (plain C, single thread) sampling the same
-    workload's first sample indices for a bounded time on this host.
+  - roofline: the sampling kernel's algorithmic bytes per launch over its
+    average launch time, measured with HIP events recorded on the launch
+    stream around every launch in the timed region.  Shortest paths: 4 B
+    per CSR entry scanned + 28 B per node given a level, counted exactly by
+    the kernel.  Triangles: 56 B per sample (20 B written; the bracketing
+    prefix pair, the arc's source and target, its list offset and the
+    listed node read).  `traffic` comes from the committed rocprofv3
+    counter summary when it was taken on the current kernel source, else
+    null;
+  - cpu_baseline: the oracle (plain C, single thread) on a bounded sample
+    of the same workload on this host: the first sample indices for a
+    fixed time (shortest paths), or its triangle enumeration over seeded
+    uniformly drawn rows, extrapolated to all rows (triangles);
+    cpu_baseline_all_cores: the same path sampling split over the host's
+    cores (at most 16 threads), results unchanged by construction.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -52,7 +70,18 @@ WORKLOADS = {
                    traffic="sample_paths_rmat22_traffic.txt",
                    label="CentRA (Algorithm 1) on R-MAT scale 22 (edge factor 16, .57/.19/.19/.05, seed 1, "
                          "directed); samples 2M doubling to 8M, k=100, t=128, eps=0.01, delta=0.1"),
+    "small": dict(graph="barabasi_albert", n=2000, m0=5, graph_seed=1, seed=1, instance=0,
+                  m_init=10_000, m_max=10_000, growth=2, k=10, t=10, eps=0.05, delta=0.1, traffic=None,
+                  label="CentRA (Algorithm 1) on Barabasi-Albert n=2,000, attachment 5, seed 1; one iteration at "
+                        "10,000 samples, k=10, t=10, eps=0.05, delta=0.1"),
+    "triangles": dict(graph="rmat_undirected", scale=20, edge_factor=16, graph_seed=1, seed=1, instance=0,
+                      m_init=1_000_000, m_max=8_000_000, growth=2, k=50, t=64, eps=0.01, delta=0.1,
+                      space="triangles", traffic=None,
+                      label="CentRA (Algorithm 1) on the triangle hyperedge space of R-MAT scale 20 (edge factor "
+                            "16, .57/.19/.19/.05, seed 1, symmetrised); samples 1M doubling to 8M, k=50, t=64, "
+                            "eps=0.01, delta=0.1"),
 }
+TRIANGLE_SAMPLE_BYTES = 56
 WORKLOAD = WORKLOADS["sparse"]
 
 
@@ -67,6 +96,8 @@ def kernel_source_hash() -> str:
 def read_traffic(name=WORKLOAD["traffic"]):
     """HBM bytes per launch from the committed counter summary, if it matches
     the current sampler source."""
+    if not name:
+        return None
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -83,21 +114,77 @@ def read_traffic(name=WORKLOAD["traffic"]):
         return None
 
 
+def host_desc():
+    return f"host {platform.processor() or platform.machine()}, {os.cpu_count()} logical CPUs"
+
+
 def cpu_baseline(graph, seconds: float, W):
     import oracle
     og = oracle.OracleGraph(graph)
+    c_bits = oracle._load().orc_count_bits(ctypes.byref(og.c))
     done = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        oracle.sample_path(graph, W["seed"], W["instance"], done, og=og)
+        oracle.sample_path(graph, W["seed"], W["instance"], done, c_bits=c_bits, og=og)
         done += 1
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "paths/s", "cores": 1, "kind": "oracle",
             "sample": f"sample indices 0..{done - 1} of the benchmark workload (seed 1, instance 0) drawn by "
                       f"the oracle's sampler (full-level BFS with normalised counts + backtrack), one thread, "
                       f"{dt:.1f} s; greedy cover and AMCERA excluded (under 0.1% of the oracle's time per path "
-                      f"at this size); host {platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} logical CPUs"}
+                      f"at this size); {host_desc()}"}
+
+
+def cpu_baseline_all_cores(graph, seconds: float, W):
+    """The oracle's sampler with the independent per-sample loop split over
+    threads (the C calls release the GIL); each thread draws the indices
+    congruent to its number modulo the thread count."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    og = oracle.OracleGraph(graph)
+    c_bits = oracle._load().orc_count_bits(ctypes.byref(og.c))
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+
+    def work(j):
+        done = 0
+        while time.perf_counter() - t0 < seconds:
+            oracle.sample_path(graph, W["seed"], W["instance"], j + threads * done, c_bits=c_bits, og=og)
+            done += 1
+        return done
+
+    with ThreadPoolExecutor(threads) as ex:
+        counts = list(ex.map(work, range(threads)))
+    dt = time.perf_counter() - t0
+    return {"value": sum(counts) / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sum(counts)} sample indices (thread j draws j, j + {threads}, ...) of the benchmark "
+                      f"workload drawn by the oracle's sampler on {threads} threads for {dt:.1f} s; "
+                      f"{host_desc()}"}
+
+
+def cpu_baseline_triangles(graph, seconds: float, m_final: int):
+    """The oracle's triangle space: its cost is the enumeration of every
+    triangle (the draws after it are a table lookup each).  Rows a (the
+    smallest node of their triangles) are drawn uniformly with a fixed seed
+    and enumerated for a bounded time; n times the mean time per row
+    estimates the enumeration of all rows."""
+    import numpy as np
+    import oracle
+    og = oracle.OracleGraph(graph)
+    rng = np.random.default_rng(1)
+    rows = 0
+    found = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        found += oracle.row_triangle_count(graph, int(rng.integers(graph.n)), og=og)
+        rows += 1
+    dt = time.perf_counter() - t0
+    est = dt / rows * graph.n
+    return {"value": m_final / est, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+            "sample": f"the oracle's triangle enumeration on {rows} uniformly drawn rows (seed 1; {found} "
+                      f"triangles) in {dt:.1f} s, one thread, extrapolated to all {graph.n} rows: {est:.0f} s "
+                      f"before its first draw; value = the workload's {m_final} samples over that time; "
+                      f"greedy cover and AMCERA excluded; {host_desc()}"}
 
 
 def copy_probe():
@@ -123,9 +210,10 @@ def main():
     ap.add_argument("--m-max", type=int, default=WORKLOAD["m_max"], help=argparse.SUPPRESS)
     ap.add_argument("--uncapped-max", type=int, default=None,
                     help="sample cap of the extra runs that measure time to certified (0 = skip; default 128M for "
-                         "the sparse workload, 32M for the skewed one)")
+                         "the sparse workload, 32M for the skewed one, 64M for triangles, 10M for small)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sparse",
-                    help="sparse (default): BA n=1e6; skewed: R-MAT scale 22, directed")
+                    help="sparse (default): BA n=1e6; skewed: R-MAT scale 22, directed; small: BA n=2,000; "
+                         "triangles: the triangle space of R-MAT scale 20, undirected")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy 8 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -143,24 +231,42 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
     W = dict(WORKLOADS[args.workload])
+    tri = W.get("space") == "triangles"
+    space = binding.CENTRA_SPACE_TRIANGLES if tri else binding.CENTRA_SPACE_SHORTEST_PATHS
     if args.uncapped_max is None:
-        args.uncapped_max = 128_000_000 if args.workload == "sparse" else 32_000_000
+        args.uncapped_max = {"sparse": 128_000_000, "skewed": 32_000_000, "triangles": 64_000_000,
+                             "small": 10_000_000}[args.workload]
     if args.workload == "sparse":
         W["m_max"] = args.m_max
     t0 = time.time()
     if W["graph"] == "rmat":
         g = inputs.rmat_graph(W["scale"], W["edge_factor"], seed=W["graph_seed"])
+    elif W["graph"] == "rmat_undirected":
+        import numpy as np
+        d = inputs.rmat_graph(W["scale"], W["edge_factor"], seed=W["graph_seed"])
+        src = np.repeat(np.arange(d.n), np.diff(d.row_ptr.astype(np.int64)))
+        g = inputs.from_edges(d.n, src, d.col_idx, directed=False)
+        del d, src
     else:
         g = inputs.ba_graph(W["n"], W["m0"], W["graph_seed"])
     log(f"graph: n={g.n} arcs={g.n_arcs} ({time.time() - t0:.1f}s)")
     ctx = binding.centra_create(0, 0)
     dg = binding.DeviceGraph(ctx, g)
     stream = torch.cuda.current_stream()
+    index_s = None
+    n_triangles = None
+    if tri:
+        torch.cuda.synchronize()
+        ti = time.perf_counter()
+        n_triangles = binding.centra_triangle_count(ctx, dg.handle, stream=stream)
+        torch.cuda.synchronize()
+        index_s = time.perf_counter() - ti
+        log(f"triangle index: T={n_triangles} in {index_s:.3f}s")
 
     def step():
         return binding.centra_progressive(ctx, dg.handle, W["k"], W["t"], W["eps"], W["delta"], W["seed"],
                                           W["instance"], W["m_init"], W["m_max"], W["growth"], 1,
-                                          stream=stream)
+                                          stream=stream, space=space)
 
     for i in range(args.warmup):
         rc, picks, res, itlog = step()
@@ -193,7 +299,7 @@ def main():
         tu = time.perf_counter()
         urc, upicks, ures, ulog = binding.centra_progressive(
             ctx, dg.handle, W["k"], W["t"], W["eps"], W["delta"], W["seed"], W["instance"], W["m_init"],
-            args.uncapped_max, num, den, stream=stream, schedule=schedule)
+            args.uncapped_max, num, den, stream=stream, schedule=schedule, space=space)
         torch.cuda.synchronize()
         return {"time_s": round(time.perf_counter() - tu, 3), "certified": bool(ures.certified),
                 "m_final": int(ures.m_final), "iterations": int(ures.iterations),
@@ -210,26 +316,38 @@ def main():
     binding.centra_destroy(ctx)
 
     launches = max(1, st.launches)
-    bytes_per_launch = (4.0 * st.arcs + 28.0 * st.nodes) / launches
+    if tri:
+        bytes_per_launch = TRIANGLE_SAMPLE_BYTES * st.samples / launches
+    else:
+        bytes_per_launch = (4.0 * st.arcs + 28.0 * st.nodes) / launches
     sec_per_launch = st.kernel_ms / 1e3 / launches
     achieved = bytes_per_launch / sec_per_launch / 1e9
     traffic = read_traffic(W["traffic"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "k_sample_paths", "launches": st.launches,
+                "kernel": "k_tri_sample" if tri else "k_sample_paths", "launches": st.launches,
                 "avg_launch_ms": round(st.kernel_ms / launches, 3),
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                "arcs_per_path": round(st.arcs / max(1, st.samples), 1),
-                "nodes_per_path": round(st.nodes / max(1, st.samples), 1),
-                "visited_set": "lds bitmap" if st.lds_bitmap else "lds bloom filter + hbm records",
-                "concurrent_bfs": st.slots}
+                "kernel_share_of_steps": round(st.kernel_ms / 1e3 / total, 4)}
+    if not tri:
+        roofline.update({"arcs_per_path": round(st.arcs / max(1, st.samples), 1),
+                         "nodes_per_path": round(st.nodes / max(1, st.samples), 1),
+                         "visited_set": "lds bitmap" if st.lds_bitmap else "lds bloom filter + hbm records",
+                         "concurrent_bfs": st.slots})
 
-    cpu = cpu_baseline(g, args.cpu_seconds, W) if args.cpu_seconds > 0 else None
+    cpu = cpu_all = None
+    if args.cpu_seconds > 0:
+        if tri:
+            cpu = cpu_baseline_triangles(g, args.cpu_seconds, int(res.m_final))
+        else:
+            cpu = cpu_baseline(g, args.cpu_seconds, W)
+            cpu_all = cpu_baseline_all_cores(g, args.cpu_seconds, W)
+        log(f"cpu baseline: {cpu}")
     value = paths / total
     out = {
-        "metric": "shortest paths sampled/s",
+        "metric": "triangles sampled/s" if tri else "shortest paths sampled/s",
         "value": round(value, 1),
-        "unit": "paths/s",
+        "unit": "triangles/s" if tri else "paths/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -237,11 +355,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": "u32" if tri else "u64",
         "data": "synthetic",
         "config": {"workload": W["label"],
                    "n": int(g.n), "arcs": int(g.n_arcs), "m_init": W["m_init"], "m_max": W["m_max"],
                    "k": W["k"], "t": W["t"], "eps": W["eps"], "delta": W["delta"]},
+        "triangles": n_triangles,
+        "index_s": round(index_s, 4) if index_s is not None else None,
         "time_to_certified_s": round(sum(times) / len(times), 3) if res.certified else
         (uncapped["time_s"] if uncapped and uncapped["certified"] else None),
         "time_to_cap_s": None if res.certified else round(sum(times) / len(times), 3),
@@ -259,6 +379,7 @@ def main():
                      "mcera": round(res.ms_mcera, 1)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out), flush=True)

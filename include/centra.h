@@ -176,9 +176,12 @@ CENTRA_API int centra_mcera(centra_ctx *ctx, uint32_t n, uint64_t m, const uint6
                  void *stream);
 
 /* Work and time of the sampling kernel, accumulated over every sampling
- * launch of the context since the last reset (centra_sample_paths and the
- * sampling steps of centra_progressive).  kernel_ms is measured with HIP
- * events recorded on the launch stream immediately around each launch.
+ * launch of the context since the last reset: centra_sample_paths and the
+ * sampling steps of centra_progressive on either hyperedge space (the
+ * triangle sampler's launches count only inside centra_progressive, which
+ * synchronises anyway; for them arcs and nodes stay 0 and slots is 0).
+ * kernel_ms is measured with HIP events recorded on the launch stream
+ * immediately around each launch.
  * arcs counts every CSR entry the kernel scans (level expansions, the
  * checks around t, the backtrack is not included); nodes counts every node
  * given a level.  A re-launch after a staging overflow counts again. */

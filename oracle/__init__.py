@@ -101,6 +101,8 @@ def _load():
                                     _u64p, c.c_uint32]
     lib.orc_triangles.argtypes = [c.POINTER(Graph), c.c_void_p, c.c_uint64]
     lib.orc_triangles.restype = c.c_uint64
+    lib.orc_row_triangles.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_void_p, c.c_uint64]
+    lib.orc_row_triangles.restype = c.c_uint64
     lib.orc_sample_triangles.argtypes = [c.POINTER(Graph), c.c_uint64, c.c_uint32, c.c_uint64, c.c_uint64,
                                          _u64p, _u32p]
     lib.orc_sample_triangles.restype = c.c_int
@@ -256,6 +258,13 @@ def triangles(g):
     tri = np.zeros(3 * max(1, T), dtype=np.uint32)
     lib.orc_triangles(ctypes.byref(og.c), tri.ctypes.data, T)
     return tri[: 3 * T].reshape(T, 3)
+
+
+def row_triangle_count(g, a, og=None):
+    """Number of triangles whose smallest node is a (None if directed)."""
+    og = og or OracleGraph(g)
+    T = _load().orc_row_triangles(ctypes.byref(og.c), a, None, 0)
+    return None if T == 2**64 - 1 else T
 
 
 def sample_triangles(g, seed, instance, first, count):

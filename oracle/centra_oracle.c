@@ -527,25 +527,33 @@ static int adjacent(const orc_graph *g, uint32_t u, uint32_t v)
     return 0;
 }
 
+uint64_t orc_row_triangles(const orc_graph *g, uint32_t a, uint32_t *tri, uint64_t cap)
+{
+    if (g->directed) return UINT64_MAX;
+    uint64_t T = 0;
+    for (uint64_t e = g->row_ptr[a]; e < g->row_ptr[a + 1]; e++) {
+        const uint32_t b = g->col_idx[e];
+        if (b <= a) continue;
+        for (uint64_t f = e + 1; f < g->row_ptr[a + 1]; f++) {
+            const uint32_t c = g->col_idx[f];   /* c > b: rows ascend */
+            if (!adjacent(g, b, c)) continue;
+            if (T < cap) {
+                tri[3 * T] = a;
+                tri[3 * T + 1] = b;
+                tri[3 * T + 2] = c;
+            }
+            T++;
+        }
+    }
+    return T;
+}
+
 uint64_t orc_triangles(const orc_graph *g, uint32_t *tri, uint64_t cap)
 {
     if (g->directed) return UINT64_MAX;
     uint64_t T = 0;
     for (uint32_t a = 0; a < g->n; a++)
-        for (uint64_t e = g->row_ptr[a]; e < g->row_ptr[a + 1]; e++) {
-            const uint32_t b = g->col_idx[e];
-            if (b <= a) continue;
-            for (uint64_t f = e + 1; f < g->row_ptr[a + 1]; f++) {
-                const uint32_t c = g->col_idx[f];   /* c > b: rows ascend */
-                if (!adjacent(g, b, c)) continue;
-                if (T < cap) {
-                    tri[3 * T] = a;
-                    tri[3 * T + 1] = b;
-                    tri[3 * T + 2] = c;
-                }
-                T++;
-            }
-        }
+        T += orc_row_triangles(g, a, tri ? tri + 3 * T : NULL, T < cap ? cap - T : 0);
     return T;
 }
 

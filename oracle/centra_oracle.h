@@ -153,6 +153,9 @@ void orc_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t,
  * stream (seed, x, instance, tag 5) and is the r-th triangle, hyperedge
  * (a, b, c).  orc_triangles writes the first min(T, cap) triangles in rank
  * order (3 ids each) and returns T; UINT64_MAX for a directed graph. */
+/* The triangles {a < b < c} whose smallest node is a, in rank order (the
+ * slice of orc_triangles' list for row a): writes the first min(count, cap). */
+uint64_t orc_row_triangles(const orc_graph *g, uint32_t a, uint32_t *tri, uint64_t cap);
 uint64_t orc_triangles(const orc_graph *g, uint32_t *tri, uint64_t cap);
 
 /* Samples [first, first+count) triangle hyperedges: he_off[i] = 3i,

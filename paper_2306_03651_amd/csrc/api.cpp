@@ -371,7 +371,7 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
       if ((rc = ensure(ctx, ctx->store_nodes, (total_nodes + added + 1) * 4, true, s))) return rc;
       uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
       if ((rc = sample_triangles_into(ctx, const_cast<centra_graph*>(g), p->seed, p->instance, m_prev, cnt,
-                                      store_off + m_prev, total_nodes, store_nodes + total_nodes, s)))
+                                      store_off + m_prev, total_nodes, store_nodes + total_nodes, s, true)))
         return rc;
     } else {
       if ((rc = sample_to_stage(ctx, g, p->seed, p->instance, m_prev, cnt, nullptr, nullptr, &added, s))) return rc;
@@ -414,6 +414,13 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
     centra_bound_out o;
     bound_eval(m_i, cov, sum, t, dk, bm, p->eps, delta_i, &o);
     const double ms_s = elapsed(ev[0], ev[1]), ms_c = elapsed(ev[1], ev[2]), ms_m = elapsed(ev[2], ev[3]);
+    if (tri) {   // the triangle sampler's launch joins the sampling-kernel statistics
+      ctx->st.launches += 1;
+      ctx->st.kernel_ms += elapsed(ev[4], ev[5]);
+      ctx->st.samples += cnt;
+      ctx->st.hyperedge_nodes += added;
+      ctx->st.slots = 0;
+    }
     memcpy(picks, hb, size_t(np) * 4);
     res->n_picked = np;
     res->iterations = i;

@@ -107,7 +107,8 @@ void release_graph_buffers(centra_ctx* ctx, centra_graph* g);
 // Triangle hyperedges (triangles.hip).
 int triangle_index(centra_ctx* ctx, centra_graph* g, uint64_t* T, hipStream_t s);
 int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
-                          uint32_t count, uint64_t* he_off, uint64_t base, uint32_t* he_nodes, hipStream_t s);
+                          uint32_t count, uint64_t* he_off, uint64_t base, uint32_t* he_nodes, hipStream_t s,
+                          bool timed = false);   // timed: events ev[4], ev[5] around the launch
 
 // Graph checks (graph.hip).
 int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s);

@@ -289,16 +289,19 @@ int triangle_index(centra_ctx* ctx, centra_graph* g, uint64_t* T, hipStream_t s)
 }
 
 int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
-                          uint32_t count, uint64_t* he_off, uint64_t base, uint32_t* he_nodes, hipStream_t s) {
+                          uint32_t count, uint64_t* he_off, uint64_t base, uint32_t* he_nodes, hipStream_t s,
+                          bool timed) {
   uint64_t T = 0;
   int rc = triangle_index(ctx, g, &T, s);
   if (rc) return rc;
   if (T == 0) return fail(ctx, CENTRA_EINVAL, "triangles: the graph has no triangle");
+  if (timed) CENTRA_HIP(ctx, hipEventRecord(ctx->ev[4], s));
   hipLaunchKernelGGL(k_tri_sample, dim3((count + 1 + 255) / 256), dim3(256), 0, s, count, first, seed, instance, T,
                      g->n_arcs, static_cast<const uint64_t*>(g->tri_prefix.ptr),
                      static_cast<const uint32_t*>(g->tri_src.ptr), g->row_ptr, g->col_idx, g->tri_list_off,
                      static_cast<const uint32_t*>(g->tri_c.ptr), base, he_off, he_nodes);
   CENTRA_HIP(ctx, hipGetLastError());
+  if (timed) CENTRA_HIP(ctx, hipEventRecord(ctx->ev[5], s));
   return CENTRA_OK;
 }
 

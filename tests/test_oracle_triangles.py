@@ -97,3 +97,15 @@ def test_progressive_on_triangles_matches_its_parts():
     assert bm == 3
     o = oracle.bound(m, int(cov[-1]), int(topk.sum()), t, dk, bm, eps, delta / 2**res.iterations)
     assert res.eta == o.eta and (rc == 0) == bool(o.certified)
+
+
+def test_row_counts_partition_the_ranked_list():
+    # the per-row enumeration is the ranked list sliced by smallest node
+    g = gnp(40, 0.3, 7)
+    brute = brute_triangles(g)
+    og = oracle.OracleGraph(g)
+    per_row = [oracle.row_triangle_count(g, a, og=og) for a in range(g.n)]
+    assert per_row == [sum(1 for t in brute if t[0] == a) for a in range(g.n)]
+    assert sum(per_row) == len(oracle.triangles(g))
+    d = inputs.from_edges(3, [0, 1, 2], [1, 2, 0], directed=True)
+    assert oracle.row_triangle_count(d, 0) is None
