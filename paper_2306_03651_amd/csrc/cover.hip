@@ -7,10 +7,13 @@
 //
 // Greedy keeps gain[u] = number of uncovered hyperedges containing u.  A
 // round is two kernels: an argmax over gain packed as (gain << 32 | ~u),
-// so the maximum key is the largest gain with the lowest id; then the
-// covering pass over the picked node's incidence row, which marks each
-// newly covered sample in a bitmap (atomicOr decides which thread covers
-// it) and decrements the gain of every node of that hyperedge.  All updates
+// so the maximum key is the largest gain with the lowest id, each
+// workgroup writing the maximum of its slice (no atomics on one word);
+// then the covering pass, whose every workgroup first reduces those
+// per-workgroup maxima to the pick and then walks its share of the picked
+// node's incidence row, marking each newly covered sample in a bitmap
+// (atomicOr decides which thread covers it) and decrementing the gain of
+// every node of that hyperedge.  All updates
 // are integer, so the picks are exactly those of the sequential greedy.
 // The rounds run back to back on the stream; the picked node is read from
 // device memory, so no host round trip happens between rounds.
@@ -168,27 +171,36 @@ __global__ void k_gain_init(const uint32_t* deg, uint32_t n, int32_t* gain) {
 
 constexpr int kArgBlock = 256;
 
-__global__ __launch_bounds__(kArgBlock) void k_argmax(const int32_t* gain, uint32_t n, uint64_t* best) {
+constexpr unsigned kArgGrid = 512;   // workgroups of the argmax (and per-workgroup maxima)
+
+// part[b] = the largest key of the slice of workgroup b (0 if the slice has
+// no positive gain)
+__global__ __launch_bounds__(kArgBlock) void k_argmax(const int32_t* gain, uint32_t n, uint64_t* part) {
   __shared__ uint64_t red[kArgBlock / kWave];
   uint64_t key = 0;
   for (uint32_t u = blockIdx.x * kArgBlock + threadIdx.x; u < n; u += gridDim.x * kArgBlock) {
     const int32_t g = gain[u];
-    const uint64_t k = (static_cast<uint64_t>(g > 0 ? g : 0) << 32) | (0xFFFFFFFFu - u);
+    const uint64_t k = g > 0 ? (static_cast<uint64_t>(g) << 32) | (0xFFFFFFFFu - u) : 0ull;
     key = k > key ? k : key;
   }
   key = block_max_u64<kArgBlock>(key, red);
-  if (threadIdx.x == 0 && key) atomicMax(reinterpret_cast<unsigned long long*>(best), key);
+  if (threadIdx.x == 0) part[blockIdx.x] = key;
 }
 
 constexpr int kCoverBlock = 256;
 
-__global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* best, const uint64_t* inc_off,
-                                                       const uint32_t* inc, const uint64_t* he_off,
-                                                       const uint32_t* he_nodes, uint32_t n, uint32_t* covered,
-                                                       int32_t* gain, uint64_t* newcov) {
+// best = the round's pick (written by workgroup 0): the largest of the
+// n_part per-workgroup maxima of the argmax.
+__global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* part, uint32_t n_part, uint64_t* best,
+                                                       const uint64_t* inc_off, const uint32_t* inc,
+                                                       const uint64_t* he_off, const uint32_t* he_nodes, uint32_t n,
+                                                       uint32_t* covered, int32_t* gain, uint64_t* newcov) {
   __shared__ uint64_t red[kCoverBlock / kWave];
   __shared__ AggTable tab;
-  const uint64_t key = *best;
+  uint64_t key = 0;
+  for (uint32_t i = threadIdx.x; i < n_part; i += kCoverBlock) key = part[i] > key ? part[i] : key;
+  key = block_max_u64<kCoverBlock>(key, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *best = key;
   if ((key >> 32) == 0) return;
   const uint32_t u = 0xFFFFFFFFu - static_cast<uint32_t>(key);
   const uint64_t b = inc_off[u], e = inc_off[u + 1];
@@ -234,7 +246,7 @@ int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t*
   int rc;
   if ((rc = ensure(ctx, ctx->gain, size_t(n) * 4, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->covered, ((m + 31) / 32 + 1) * 4, false, s))) return rc;
-  if ((rc = ensure(ctx, ctx->best, size_t(k) * 8, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->best, (size_t(k) + kArgGrid) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->newcov, size_t(k) * 8, false, s))) return rc;
   int32_t* gain = static_cast<int32_t*>(ctx->gain.ptr);
   uint32_t* cov = static_cast<uint32_t*>(ctx->covered.ptr);
@@ -245,14 +257,15 @@ int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t*
   fill_u32(cov, 0, (m + 31) / 32 + 1, s);
   fill_u64(best, 0, k, s);
   fill_u64(newcov, 0, k, s);
-  const unsigned ga = grid_for(n, kArgBlock, 1024);
+  const unsigned ga = grid_for(n, kArgBlock, kArgGrid);
+  uint64_t* part = best + k;
   const unsigned gc = 1024;
   const uint64_t* ioff = static_cast<const uint64_t*>(ctx->inc_off.ptr);
   const uint32_t* inc = static_cast<const uint32_t*>(ctx->inc.ptr);
   for (uint32_t r = 0; r < k; ++r) {
-    hipLaunchKernelGGL(k_argmax, dim3(ga), dim3(kArgBlock), 0, s, gain, n, best + r);
-    hipLaunchKernelGGL(k_cover, dim3(gc), dim3(kCoverBlock), 0, s, best + r, ioff, inc, he_off, he_nodes, n, cov, gain,
-                       newcov + r);
+    hipLaunchKernelGGL(k_argmax, dim3(ga), dim3(kArgBlock), 0, s, gain, n, part);
+    hipLaunchKernelGGL(k_cover, dim3(gc), dim3(kCoverBlock), 0, s, part, ga, best + r, ioff, inc, he_off, he_nodes, n,
+                       cov, gain, newcov + r);
   }
   hipLaunchKernelGGL(k_greedy_finish, dim3(1), dim3(64), 0, s, best, newcov, k, picks, cov_cum, n_picked);
   CENTRA_HIP(ctx, hipGetLastError());
