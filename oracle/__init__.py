@@ -97,8 +97,14 @@ def _load():
     lib.orc_bound.restype = None
     lib.orc_progressive.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint32, c.c_uint32, c.c_double,
                                     c.c_double, c.c_uint64, c.c_uint32, c.c_uint64, c.c_uint64,
-                                    c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, _u32p, c.POINTER(Result),
-                                    _u64p, c.c_uint32]
+                                    c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, _u32p,
+                                    c.POINTER(Result), _u64p, c.c_uint32]
+    lib.orc_kpath.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint64, c.c_uint32, c.c_uint64, _u32p,
+                              c.POINTER(c.c_uint32), c.POINTER(c.c_uint32)]
+    lib.orc_kpath.restype = c.c_uint32
+    lib.orc_sample_kpaths.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint64, c.c_uint32, c.c_uint64,
+                                      c.c_uint64, _u64p, _u32p]
+    lib.orc_sample_kpaths.restype = c.c_int
     lib.orc_triangles.argtypes = [c.POINTER(Graph), c.c_void_p, c.c_uint64]
     lib.orc_triangles.restype = c.c_uint64
     lib.orc_row_triangles.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_void_p, c.c_uint64]
@@ -244,7 +250,7 @@ def next_sample_size(m_i, c_hat, eps, delta_next, growth_num, growth_den, m_max,
                                             schedule))
 
 
-SPACE_SHORTEST_PATHS, SPACE_TRIANGLES = 0, 1
+SPACE_SHORTEST_PATHS, SPACE_TRIANGLES, SPACE_KPATHS = 0, 1, 2
 
 
 def triangles(g):
@@ -277,8 +283,30 @@ def sample_triangles(g, seed, instance, first, count):
     return None if rc else (off, nodes[: 3 * count])
 
 
+def kpath(g, kappa, seed, instance, sample, og=None):
+    """Sample `sample` of the kappa-path space: (walk after its start as a
+    np.uint32 array, start s, drawn length l)."""
+    og = og or OracleGraph(g)
+    h = np.zeros(max(1, kappa), dtype=np.uint32)
+    s_out, l_out = ctypes.c_uint32(), ctypes.c_uint32()
+    ln = _load().orc_kpath(ctypes.byref(og.c), kappa, seed, instance, sample, h, ctypes.byref(s_out),
+                           ctypes.byref(l_out))
+    return h[:ln].copy(), s_out.value, l_out.value
+
+
+def sample_kpaths(g, kappa, seed, instance, first, count):
+    """kappa-path hyperedges [first, first+count): (he_off, he_nodes); None
+    if kappa == 0."""
+    og = OracleGraph(g)
+    off = np.zeros(count + 1, dtype=np.uint64)
+    nodes = np.zeros(max(1, count * kappa), dtype=np.uint32)
+    rc = _load().orc_sample_kpaths(ctypes.byref(og.c), kappa, seed, instance, first, count, off, nodes)
+    return None if rc else (off, nodes[: int(off[-1])])
+
+
 def progressive(g, k, t, eps, delta, seed, instance, m_init, m_max, growth_num=2, growth_den=1,
-                c_bits=None, schedule=SCHEDULE_GEOMETRIC, with_m_log=False, space=SPACE_SHORTEST_PATHS):
+                c_bits=None, schedule=SCHEDULE_GEOMETRIC, with_m_log=False, space=SPACE_SHORTEST_PATHS,
+                kappa=0):
     """Algorithm 1; returns (rc, picks, Result) and, with with_m_log, the
     sample size of every iteration."""
     og = OracleGraph(g)
@@ -289,7 +317,7 @@ def progressive(g, k, t, eps, delta, seed, instance, m_init, m_max, growth_num=2
     res = Result()
     m_log = np.zeros(256, dtype=np.uint64)
     rc = lib.orc_progressive(ctypes.byref(og.c), c_bits, k, t, eps, delta, seed, instance, m_init, m_max,
-                             growth_num, growth_den, schedule, space, picks, ctypes.byref(res), m_log,
+                             growth_num, growth_den, schedule, space, kappa, picks, ctypes.byref(res), m_log,
                              len(m_log))
     out = (rc, picks[: res.n_picked].copy(), res)
     if with_m_log:

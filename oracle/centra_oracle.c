@@ -578,6 +578,64 @@ int orc_sample_triangles(const orc_graph *g, uint64_t seed, uint32_t instance,
     return 0;
 }
 
+/* kappa-path hyperedges (Sec. 3.1 names the space: the node sets of simple
+ * paths of length at most kappa; the paper gives no sampler).  Reading, the
+ * random simple walk of the kappa-path centrality: from the stream (seed,
+ * sample, instance, tag 6) draw the start s = bounded(n) and the length
+ * l = 1 + bounded(kappa); then, l times, move from the current node v to
+ * the r-th (r = bounded(f)) of v's f out-neighbours that are not yet on the
+ * walk, in ascending id; stop early when f = 0.  The hyperedge is the walk
+ * after s (at most kappa nodes, the b <= kappa of Sec. 4.3). */
+static int on_walk(uint32_t x, uint32_t s, const uint32_t *h, uint32_t len)
+{
+    if (x == s) return 1;
+    for (uint32_t i = 0; i < len; i++)
+        if (h[i] == x) return 1;
+    return 0;
+}
+
+uint32_t orc_kpath(const orc_graph *g, uint32_t kappa, uint64_t seed, uint32_t instance,
+                   uint64_t sample, uint32_t *h, uint32_t *s_out, uint32_t *l_out)
+{
+    orc_stream st;
+    orc_stream_init(&st, seed, sample, instance, 6);
+    const uint32_t s = (uint32_t)orc_bounded(&st, g->n);
+    const uint32_t l = 1 + (uint32_t)orc_bounded(&st, kappa);
+    if (s_out) *s_out = s;
+    if (l_out) *l_out = l;
+    uint32_t v = s, len = 0;
+    while (len < l) {
+        uint64_t f = 0;
+        for (uint64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; e++)
+            f += !on_walk(g->col_idx[e], s, h, len);
+        if (f == 0) break;
+        uint64_t r = orc_bounded(&st, f);
+        for (uint64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; e++) {
+            const uint32_t w = g->col_idx[e];
+            if (on_walk(w, s, h, len)) continue;
+            if (r == 0) {
+                v = w;
+                break;
+            }
+            r--;
+        }
+        h[len++] = v;
+    }
+    return len;
+}
+
+int orc_sample_kpaths(const orc_graph *g, uint32_t kappa, uint64_t seed, uint32_t instance,
+                      uint64_t first, uint64_t count, uint64_t *he_off, uint32_t *he_nodes)
+{
+    if (kappa == 0 || g->n == 0) return -1;
+    he_off[0] = 0;
+    for (uint64_t i = 0; i < count; i++) {
+        const uint32_t len = orc_kpath(g, kappa, seed, instance, first + i, he_nodes + he_off[i], NULL, NULL);
+        he_off[i + 1] = he_off[i] + len;
+    }
+    return 0;
+}
+
 uint64_t orc_next_sample_size(uint64_t m_i, double c_hat, double eps, double delta_next,
                               uint32_t growth_num, uint32_t growth_den, uint64_t m_max,
                               uint32_t schedule)
@@ -601,14 +659,14 @@ uint64_t orc_next_sample_size(uint64_t m_i, double c_hat, double eps, double del
 int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                     double eps, double delta, uint64_t seed, uint32_t instance,
                     uint64_t m_init, uint64_t m_max, uint32_t growth_num,
-                    uint32_t growth_den, uint32_t schedule, uint32_t space,
+                    uint32_t growth_den, uint32_t schedule, uint32_t space, uint32_t kappa,
                     uint32_t *picks, orc_result *res, uint64_t *m_log,
                     uint32_t m_log_cap)
 {
     const double a = 1.0 - exp(-1.0);
     if (k == 0 || t == 0 || !(eps > 0.0 && eps < a) || !(delta > 0.0 && delta < 1.0) ||
         m_init == 0 || m_max < m_init || growth_den == 0 || growth_num <= growth_den ||
-        schedule > 2 || space > 1)
+        schedule > 2 || space > 2 || (space == 2 && kappa == 0))
         return -1;
     uint32_t *tri = NULL;
     uint64_t T = 0;
@@ -621,7 +679,7 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
     uint64_t cap = 1024;
     uint64_t *he_off = malloc(sizeof(uint64_t) * (m_max + 1));
     uint32_t *he_nodes = malloc(sizeof(uint32_t) * cap);
-    uint32_t *h = malloc(sizeof(uint32_t) * g->n);
+    uint32_t *h = malloc(sizeof(uint32_t) * (g->n > kappa ? g->n : kappa));
     uint64_t *cov_cum = malloc(sizeof(uint64_t) * k);
     int64_t *topk = malloc(sizeof(int64_t) * t);
     bfs_state b;
@@ -641,6 +699,8 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                 orc_stream_init(&st, seed, s, instance, 5);
                 memcpy(h, tri + 3 * orc_bounded(&st, T), 3 * sizeof(uint32_t));
                 len = 3;
+            } else if (space == 2) {
+                len = orc_kpath(g, kappa, seed, instance, s, h, NULL, NULL);
             } else {
                 len = sample_one(g, c_bits, seed, instance, s, h, NULL, &b);
             }

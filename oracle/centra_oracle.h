@@ -188,10 +188,21 @@ typedef struct {
     double c_hat, amcera, wimpy, xi, nu, rtilde, r, eta;
 } orc_result;
 
+/* kappa-path hyperedges (Sec. 3.1; the sampler is a reading, see the C
+ * file): orc_kpath writes sample `sample`'s walk after its start into h (at
+ * most kappa ids), returns its length, and reports the start and the drawn
+ * length l if asked.  orc_sample_kpaths: samples [first, first+count) into
+ * he_off[count+1] / he_nodes (capacity count * kappa); -1 if kappa == 0. */
+uint32_t orc_kpath(const orc_graph *g, uint32_t kappa, uint64_t seed, uint32_t instance,
+                   uint64_t sample, uint32_t *h, uint32_t *s_out, uint32_t *l_out);
+int orc_sample_kpaths(const orc_graph *g, uint32_t kappa, uint64_t seed, uint32_t instance,
+                      uint64_t first, uint64_t count, uint64_t *he_off, uint32_t *he_nodes);
+
+/* space: 0 shortest paths, 1 triangles, 2 kappa-paths (kappa >= 1). */
 int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                     double eps, double delta, uint64_t seed, uint32_t instance,
                     uint64_t m_init, uint64_t m_max, uint32_t growth_num,
-                    uint32_t growth_den, uint32_t schedule, uint32_t space,
+                    uint32_t growth_den, uint32_t schedule, uint32_t space, uint32_t kappa,
                     uint32_t *picks, orc_result *res, uint64_t *m_log,
                     uint32_t m_log_cap);
 

@@ -265,6 +265,21 @@ def test_grid_configuration_sampled(ctx, L):
     check_sampled(ctx, inputs.grid_graph(L), 3, 5, 1000, 3000, 24)
 
 
+def test_serving_graphs_sampled(ctx):
+    # Graph families of the serving configuration beyond the ones above:
+    # directed R-MAT scale 20 (16.1M arcs) and the 2048 x 2048 grid
+    # (diameter 4,094: up to 4,094 levels per BFS, slot count capped by the
+    # slot memory budget).
+    g = inputs.rmat_graph(20, 16, seed=1)
+    say(f"R-MAT 20 directed: n={g.n} arcs={g.n_arcs}; 100000 samples")
+    check_sampled(ctx, g, 1, 0, 0, 100000, 16)
+    del g
+    g = inputs.grid_graph(2048)
+    say(f"grid 2048x2048: n={g.n}; 600 samples")
+    off, nodes, d = check_sampled(ctx, g, 4, 2, 0, 600, 8)
+    say(f"  longest hyperedge {int(np.diff(off.astype(np.int64)).max())}")
+
+
 def test_ba_1e5_configuration_sampled(ctx):
     say("BA n=1e5: 50000 samples")
     check_sampled(ctx, inputs.ba_graph(100_000, 5, 7), 2, 9, 0, 50000, 40)
