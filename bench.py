@@ -23,7 +23,13 @@ Other workloads (`--workload`):
              (1,048,576 nodes, 31.4M arcs, 424M triangles); 1,000,000
              samples doubling to 8,000,000, k = 50, t = 64, eps = 0.01,
              delta = 0.1; the per-graph triangle index is built once before
-             the timed steps and its time is reported as index_s.
+             the timed steps and its time is reported as index_s;
+  kpaths     Algorithm 1 on the kappa-path hyperedge space (the kappa-path
+             centrality; random simple walks of length at most kappa = 5) of
+             the Barabasi-Albert n = 1,000,000 graph above; 1,000,000
+             samples doubling to 8,000,000, k = 50, t = 64, eps = 0.05,
+             delta = 0.1 (the top-50 cover about 2% of the walks, so
+             eps = 0.01 would not certify below 64M samples).
 
 Also reported:
   - roofline: the sampling kernel's algorithmic bytes per launch over its
@@ -32,7 +38,11 @@ Also reported:
     per CSR entry scanned + 28 B per node given a level, counted exactly by
     the kernel.  Triangles: 56 B per sample (20 B written; the bracketing
     prefix pair, the arc's source and target, its list offset and the
-    listed node read).  `traffic` comes from the committed rocprofv3
+    listed node read).  kappa-paths: the two passes over each walk (lengths,
+    then nodes) read 12 B per step each (the row bounds and the chosen
+    entry) and the second writes the node: 28 B per walk node, plus 12 B
+    per walk (its length written, its offset read).  `traffic` comes from
+    the committed rocprofv3
     counter summary when it was taken on the current kernel source, else
     null;
   - cpu_baseline: the oracle (plain C, single thread) on a bounded sample
@@ -74,6 +84,12 @@ WORKLOADS = {
                   m_init=10_000, m_max=10_000, growth=2, k=10, t=10, eps=0.05, delta=0.1, traffic=None,
                   label="CentRA (Algorithm 1) on Barabasi-Albert n=2,000, attachment 5, seed 1; one iteration at "
                         "10,000 samples, k=10, t=10, eps=0.05, delta=0.1"),
+    "kpaths": dict(graph="barabasi_albert", n=1_000_000, m0=5, graph_seed=1, seed=1, instance=0,
+                   m_init=1_000_000, m_max=8_000_000, growth=2, k=50, t=64, eps=0.05, delta=0.1,
+                   space="kpaths", kappa=5, traffic=None,
+                   label="CentRA (Algorithm 1) on the kappa-path hyperedge space (kappa=5) of Barabasi-Albert "
+                         "n=1e6, attachment 5, seed 1; samples 1M doubling to 8M, k=50, t=64, eps=0.05, "
+                         "delta=0.1"),
     "triangles": dict(graph="rmat_undirected", scale=20, edge_factor=16, graph_seed=1, seed=1, instance=0,
                       m_init=1_000_000, m_max=8_000_000, growth=2, k=50, t=64, eps=0.01, delta=0.1,
                       space="triangles", traffic=None,
@@ -82,6 +98,7 @@ WORKLOADS = {
                             "eps=0.01, delta=0.1"),
 }
 TRIANGLE_SAMPLE_BYTES = 56
+KPATH_NODE_BYTES, KPATH_SAMPLE_BYTES = 28, 12
 WORKLOAD = WORKLOADS["sparse"]
 
 
@@ -118,48 +135,63 @@ def host_desc():
     return f"host {platform.processor() or platform.machine()}, {os.cpu_count()} logical CPUs"
 
 
-def cpu_baseline(graph, seconds: float, W):
+def oracle_sampler(graph, W):
+    """(draw(first, count), batch, unit, description) of the oracle's sampler
+    for W's space; kappa-path walks are drawn by the oracle's own batch loop
+    (a walk takes about a microsecond, less than a Python call)."""
     import oracle
     og = oracle.OracleGraph(graph)
+    if W.get("space") == "kpaths":
+        kappa = W["kappa"]
+        lib = oracle._load()
+
+        def draw(first, count):
+            import numpy as np
+            off = np.zeros(count + 1, dtype=np.uint64)
+            nodes = np.zeros(count * kappa, dtype=np.uint32)
+            lib.orc_sample_kpaths(ctypes.byref(og.c), kappa, W["seed"], W["instance"], first, count, off, nodes)
+        return (draw, 20000, "walks/s",
+                f"the oracle's kappa-path sampler (random simple walk, kappa={kappa}, rows scanned per step)")
     c_bits = oracle._load().orc_count_bits(ctypes.byref(og.c))
+    return ((lambda first, count: oracle.sample_path(graph, W["seed"], W["instance"], first, c_bits=c_bits, og=og)),
+            1, "paths/s", "the oracle's sampler (full-level BFS with normalised counts + backtrack)")
+
+
+def cpu_baseline(graph, seconds: float, W):
+    draw, batch, unit, what = oracle_sampler(graph, W)
     done = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        oracle.sample_path(graph, W["seed"], W["instance"], done, c_bits=c_bits, og=og)
-        done += 1
+        draw(done, batch)
+        done += batch
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "paths/s", "cores": 1, "kind": "oracle",
+    return {"value": done / dt, "unit": unit, "cores": 1, "kind": "oracle",
             "sample": f"sample indices 0..{done - 1} of the benchmark workload (seed 1, instance 0) drawn by "
-                      f"the oracle's sampler (full-level BFS with normalised counts + backtrack), one thread, "
-                      f"{dt:.1f} s; greedy cover and AMCERA excluded (under 0.1% of the oracle's time per path "
-                      f"at this size); {host_desc()}"}
+                      f"{what}, one thread, {dt:.1f} s; greedy cover and AMCERA excluded; {host_desc()}"}
 
 
 def cpu_baseline_all_cores(graph, seconds: float, W):
     """The oracle's sampler with the independent per-sample loop split over
     threads (the C calls release the GIL); each thread draws the indices
     congruent to its number modulo the thread count."""
-    import oracle
     from concurrent.futures import ThreadPoolExecutor
-    og = oracle.OracleGraph(graph)
-    c_bits = oracle._load().orc_count_bits(ctypes.byref(og.c))
+    draw, batch, unit, what = oracle_sampler(graph, W)
     threads = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
 
     def work(j):
-        done = 0
+        done = 0   # batches of this thread: thread j draws batches j, j + threads, ...
         while time.perf_counter() - t0 < seconds:
-            oracle.sample_path(graph, W["seed"], W["instance"], j + threads * done, c_bits=c_bits, og=og)
+            draw((j + threads * done) * batch, batch)
             done += 1
-        return done
+        return done * batch
 
     with ThreadPoolExecutor(threads) as ex:
         counts = list(ex.map(work, range(threads)))
     dt = time.perf_counter() - t0
-    return {"value": sum(counts) / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sum(counts)} sample indices (thread j draws j, j + {threads}, ...) of the benchmark "
-                      f"workload drawn by the oracle's sampler on {threads} threads for {dt:.1f} s; "
-                      f"{host_desc()}"}
+    return {"value": sum(counts) / dt, "unit": unit, "cores": threads, "kind": "oracle",
+            "sample": f"{sum(counts)} sample indices (thread j draws batch j, j + {threads}, ... of {batch}) of the benchmark "
+                      f"workload drawn by {what} on {threads} threads for {dt:.1f} s; {host_desc()}"}
 
 
 def cpu_baseline_triangles(graph, seconds: float, m_final: int):
@@ -232,10 +264,13 @@ def main():
     torch.cuda.set_device(0)
     W = dict(WORKLOADS[args.workload])
     tri = W.get("space") == "triangles"
-    space = binding.CENTRA_SPACE_TRIANGLES if tri else binding.CENTRA_SPACE_SHORTEST_PATHS
+    kp = W.get("space") == "kpaths"
+    space = (binding.CENTRA_SPACE_TRIANGLES if tri else binding.CENTRA_SPACE_KPATHS if kp
+             else binding.CENTRA_SPACE_SHORTEST_PATHS)
+    kappa = W.get("kappa", 0)
     if args.uncapped_max is None:
         args.uncapped_max = {"sparse": 128_000_000, "skewed": 32_000_000, "triangles": 64_000_000,
-                             "small": 10_000_000}[args.workload]
+                             "kpaths": 64_000_000, "small": 10_000_000}[args.workload]
     if args.workload == "sparse":
         W["m_max"] = args.m_max
     t0 = time.time()
@@ -266,7 +301,7 @@ def main():
     def step():
         return binding.centra_progressive(ctx, dg.handle, W["k"], W["t"], W["eps"], W["delta"], W["seed"],
                                           W["instance"], W["m_init"], W["m_max"], W["growth"], 1,
-                                          stream=stream, space=space)
+                                          stream=stream, space=space, kappa=kappa)
 
     for i in range(args.warmup):
         rc, picks, res, itlog = step()
@@ -299,7 +334,7 @@ def main():
         tu = time.perf_counter()
         urc, upicks, ures, ulog = binding.centra_progressive(
             ctx, dg.handle, W["k"], W["t"], W["eps"], W["delta"], W["seed"], W["instance"], W["m_init"],
-            args.uncapped_max, num, den, stream=stream, schedule=schedule, space=space)
+            args.uncapped_max, num, den, stream=stream, schedule=schedule, space=space, kappa=kappa)
         torch.cuda.synchronize()
         return {"time_s": round(time.perf_counter() - tu, 3), "certified": bool(ures.certified),
                 "m_final": int(ures.m_final), "iterations": int(ures.iterations),
@@ -318,6 +353,8 @@ def main():
     launches = max(1, st.launches)
     if tri:
         bytes_per_launch = TRIANGLE_SAMPLE_BYTES * st.samples / launches
+    elif kp:
+        bytes_per_launch = (KPATH_NODE_BYTES * st.hyperedge_nodes + KPATH_SAMPLE_BYTES * st.samples) / launches
     else:
         bytes_per_launch = (4.0 * st.arcs + 28.0 * st.nodes) / launches
     sec_per_launch = st.kernel_ms / 1e3 / launches
@@ -325,11 +362,12 @@ def main():
     traffic = read_traffic(W["traffic"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "k_tri_sample" if tri else "k_sample_paths", "launches": st.launches,
+                "kernel": "k_tri_sample" if tri else "k_kpath (both passes)" if kp else "k_sample_paths",
+                "launches": st.launches,
                 "avg_launch_ms": round(st.kernel_ms / launches, 3),
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
                 "kernel_share_of_steps": round(st.kernel_ms / 1e3 / total, 4)}
-    if not tri:
+    if not tri and not kp:
         roofline.update({"arcs_per_path": round(st.arcs / max(1, st.samples), 1),
                          "nodes_per_path": round(st.nodes / max(1, st.samples), 1),
                          "visited_set": "lds bitmap" if st.lds_bitmap else "lds bloom filter + hbm records",
@@ -345,9 +383,9 @@ def main():
         log(f"cpu baseline: {cpu}")
     value = paths / total
     out = {
-        "metric": "triangles sampled/s" if tri else "shortest paths sampled/s",
+        "metric": "triangles sampled/s" if tri else "kappa-path walks sampled/s" if kp else "shortest paths sampled/s",
         "value": round(value, 1),
-        "unit": "triangles/s" if tri else "paths/s",
+        "unit": "triangles/s" if tri else "walks/s" if kp else "paths/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -355,7 +393,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32" if tri else "u64",
+        "dtype": "u32" if (tri or kp) else "u64",
         "data": "synthetic",
         "config": {"workload": W["label"],
                    "n": int(g.n), "arcs": int(g.n_arcs), "m_init": W["m_init"], "m_max": W["m_max"],

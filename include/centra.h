@@ -38,7 +38,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 3u
+#define CENTRA_ABI_VERSION 4u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -241,6 +241,28 @@ CENTRA_API int centra_sample_triangles(centra_ctx *ctx, const centra_graph *g, u
                             void *stream);
 
 /* ------------------------------------------------------------------ */
+/* kappa-path hyperedges: the hyperedge space of the kappa-path centrality
+ * (Sec. 3.1: the node sets of simple paths of length at most kappa), a third
+ * space for Algorithm 1 (Sec. 4: the algorithm is oblivious to sampleHEs).
+ * The paper gives no sampler; sample number x (global index) is the random
+ * simple walk of the kappa-path centrality, drawn from the Philox stream
+ * (seed, x, instance, tag 6): start s = bounded(n), length
+ * l = 1 + bounded(kappa), then l moves, each from the current node v to the
+ * r-th (r = bounded(f)) of v's f out-neighbours not yet on the walk in
+ * ascending id, stopping early when f = 0.  The hyperedge is the walk after
+ * s: at most kappa nodes (b <= kappa, Sec. 4.3), in walk order.
+ *
+ * centra_sample_kpaths: samples [first, first + count) into he_off (device
+ * u64[count + 1], relative to he_nodes) and he_nodes (device u32, capacity
+ * count * kappa).  1 <= kappa <= CENTRA_MAX_KAPPA.  Synchronous.
+ * Errors: CENTRA_EINVAL (NULL argument, kappa outside [1, 16]),
+ * CENTRA_ENOMEM, CENTRA_EHIP. */
+#define CENTRA_MAX_KAPPA 16u
+CENTRA_API int centra_sample_kpaths(centra_ctx *ctx, const centra_graph *g, uint32_t kappa, uint64_t seed,
+                         uint32_t instance, uint64_t first, uint32_t count, uint64_t *he_off,
+                         uint32_t *he_nodes, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Algorithm 1 (CentRA).  Iteration i = 1, 2, ...: delta_i = delta / 2^i;
  * the sample is extended to m_i hyperedges (samples 0 .. m_i-1 of (seed,
  * instance)), then greedyCover, the AMCERA and the bound of Theorem
@@ -260,8 +282,9 @@ CENTRA_API int centra_sample_triangles(centra_ctx *ctx, const centra_graph *g, u
  *     uses delta itself (the fixed-sample-size use of Theorem bound_dev,
  *     Section 5), returning its stopping test.
  * The hyperedge space: CENTRA_SPACE_SHORTEST_PATHS (set betweenness,
- * centra_sample_paths) or CENTRA_SPACE_TRIANGLES (triangle centrality,
- * centra_sample_triangles).
+ * centra_sample_paths), CENTRA_SPACE_TRIANGLES (triangle centrality,
+ * centra_sample_triangles) or CENTRA_SPACE_KPATHS (kappa-path centrality,
+ * centra_sample_kpaths with the params' kappa; kappa is ignored otherwise).
  * Inputs: k >= 1, 1 <= t <= 1024, eps in (0, 1-1/e), delta in (0,1),
  * 1 <= m_init <= m_max < 2^31, growth_num > growth_den >= 1, schedule and
  * space one of their values. */
@@ -270,6 +293,7 @@ CENTRA_API int centra_sample_triangles(centra_ctx *ctx, const centra_graph *g, u
 #define CENTRA_SCHEDULE_FIXED 2u
 #define CENTRA_SPACE_SHORTEST_PATHS 0u
 #define CENTRA_SPACE_TRIANGLES 1u
+#define CENTRA_SPACE_KPATHS 2u
 
 typedef struct {
     uint32_t k, t;
@@ -280,6 +304,7 @@ typedef struct {
     uint32_t growth_num, growth_den;
     uint32_t schedule;   /* CENTRA_SCHEDULE_* */
     uint32_t space;      /* CENTRA_SPACE_* */
+    uint32_t kappa;      /* path length bound of CENTRA_SPACE_KPATHS */
 } centra_params;
 
 typedef struct {

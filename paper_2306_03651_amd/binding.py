@@ -28,6 +28,8 @@ CENTRA_SCHEDULE_ADAPTIVE = 1
 CENTRA_SCHEDULE_FIXED = 2
 CENTRA_SPACE_SHORTEST_PATHS = 0
 CENTRA_SPACE_TRIANGLES = 1
+CENTRA_SPACE_KPATHS = 2
+CENTRA_MAX_KAPPA = 16
 
 _c = ctypes
 _vp = _c.c_void_p
@@ -54,7 +56,7 @@ class Params(_c.Structure):
     _fields_ = [("k", _c.c_uint32), ("t", _c.c_uint32), ("eps", _c.c_double), ("delta", _c.c_double),
                 ("seed", _c.c_uint64), ("instance", _c.c_uint32), ("m_init", _c.c_uint64),
                 ("m_max", _c.c_uint64), ("growth_num", _c.c_uint32), ("growth_den", _c.c_uint32),
-                ("schedule", _c.c_uint32), ("space", _c.c_uint32)]
+                ("schedule", _c.c_uint32), ("space", _c.c_uint32), ("kappa", _c.c_uint32)]
 
 
 class Result(_c.Structure):
@@ -98,6 +100,8 @@ SIGNATURES = {
     "centra_triangle_count": (_c.c_int, [_vp, _vp, _c.POINTER(_c.c_uint64), _vp]),
     "centra_sample_triangles": (_c.c_int, [_vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _vp, _vp,
                                            _vp]),
+    "centra_sample_kpaths": (_c.c_int, [_vp, _vp, _c.c_uint32, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32,
+                                        _vp, _vp, _vp]),
     "centra_bound": (_c.c_int, [_c.c_uint64, _c.c_uint64, _c.c_int64, _c.c_uint32, _c.c_uint64, _c.c_uint32,
                                 _c.c_double, _c.c_double, _c.POINTER(BoundOut)]),
     "centra_progressive": (_c.c_int, [_vp, _vp, _c.POINTER(Params), _vp, _c.POINTER(Result),
@@ -246,9 +250,10 @@ def centra_bound(m: int, cov: int, sum_topk: int, t: int, deg_topk: int, b_max: 
 
 def centra_progressive(ctx, g, k: int, t: int, eps: float, delta: float, seed: int, instance: int, m_init: int,
                        m_max: int, growth_num: int = 2, growth_den: int = 1, log_cap: int = 64, stream=None,
-                       schedule: int = CENTRA_SCHEDULE_GEOMETRIC, space: int = CENTRA_SPACE_SHORTEST_PATHS):
+                       schedule: int = CENTRA_SCHEDULE_GEOMETRIC, space: int = CENTRA_SPACE_SHORTEST_PATHS,
+                       kappa: int = 0):
     """Returns (rc, picks np.uint32[n_picked], Result, [Iteration])."""
-    p = Params(k, t, eps, delta, seed, instance, m_init, m_max, growth_num, growth_den, schedule, space)
+    p = Params(k, t, eps, delta, seed, instance, m_init, m_max, growth_num, growth_den, schedule, space, kappa)
     picks = np.zeros(max(1, k), dtype=np.uint32)
     res = Result()
     log = (Iteration * max(1, log_cap))()
@@ -307,6 +312,27 @@ def sample_triangles(ctx, dg, seed: int, instance: int, first: int, count: int, 
     he_nodes = torch.empty(max(1, 3 * count), dtype=torch.int32, device=device)
     centra_sample_triangles(ctx, dg.handle, seed, instance, first, count, he_off, he_nodes)
     return he_off, he_nodes[: 3 * count]
+
+
+def centra_sample_kpaths(ctx, g, kappa: int, seed: int, instance: int, first: int, count: int, he_off, he_nodes,
+                         stream=None):
+    import torch
+    _dtype_check(he_off, torch.int64, "he_off")
+    _dtype_check(he_nodes, torch.int32, "he_nodes")
+    if he_nodes.numel() < count * kappa:
+        raise ValueError("he_nodes must hold count * kappa entries")
+    _check(lib().centra_sample_kpaths(ctx, g, kappa, seed, instance, first, count, _ptr(he_off), _ptr(he_nodes),
+                                      _stream(stream)), ctx)
+
+
+def sample_kpaths(ctx, dg, kappa: int, seed: int, instance: int, first: int, count: int, device="cuda"):
+    """Samples kappa-paths [first, first+count) into fresh device tensors:
+    (he_off int64[count+1], he_nodes int32[he_off[count]])."""
+    import torch
+    he_off = torch.empty(count + 1, dtype=torch.int64, device=device)
+    he_nodes = torch.empty(max(1, count * max(1, kappa)), dtype=torch.int32, device=device)
+    centra_sample_kpaths(ctx, dg.handle, kappa, seed, instance, first, count, he_off, he_nodes)
+    return he_off, he_nodes[: int(he_off[count].item())]
 
 
 def sample_paths(ctx, dg: DeviceGraph, seed: int, instance: int, first: int, count: int, with_st: bool = False,

@@ -147,7 +147,7 @@ void centra_destroy(centra_ctx* ctx) {
                     &ctx->stage_len, &ctx->work_ctr, &ctx->scan_tmp, &ctx->deg, &ctx->inc_off,
                     &ctx->inc_cursor, &ctx->inc, &ctx->inc_node, &ctx->gain, &ctx->covered, &ctx->best,
                     &ctx->newcov, &ctx->words, &ctx->P, &ctx->Rtm, &ctx->topk_tmp, &ctx->misc,
-                    &ctx->store_off, &ctx->store_nodes};
+                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len};
   for (DevBuf* b : bufs) release(ctx, *b);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   for (auto& ev : ctx->ev)
@@ -258,6 +258,19 @@ int centra_sample_triangles(centra_ctx* ctx, const centra_graph* g, uint64_t see
   return check_flags(ctx, s, "sample_triangles");
 }
 
+int centra_sample_kpaths(centra_ctx* ctx, const centra_graph* g, uint32_t kappa, uint64_t seed, uint32_t instance,
+                         uint64_t first, uint32_t count, uint64_t* he_off, uint32_t* he_nodes, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (!g || !he_off || (count && !he_nodes)) return fail(ctx, CENTRA_EINVAL, "sample_kpaths: NULL argument");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = as_stream(stream);
+  int rc = kpath_count(ctx, g, kappa, seed, instance, first, count, he_off, s);
+  if (!rc) rc = kpath_write(ctx, g, kappa, seed, instance, first, count, he_off, 0, he_nodes, s);
+  if (rc) return rc;
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  return check_flags(ctx, s, "sample_kpaths");
+}
+
 // Checks the sample arguments; he_nodes may be NULL only if every hyperedge
 // is empty (he_off[m] == 0), which is read from the device.
 static int check_sample_args(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
@@ -337,8 +350,11 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
   if (p->growth_den == 0 || p->growth_num <= p->growth_den)
     return fail(ctx, CENTRA_EINVAL, "progressive: growth must exceed 1");
   if (p->schedule > CENTRA_SCHEDULE_FIXED) return fail(ctx, CENTRA_EINVAL, "progressive: unknown schedule");
-  if (p->space > CENTRA_SPACE_TRIANGLES) return fail(ctx, CENTRA_EINVAL, "progressive: unknown hyperedge space");
+  if (p->space > CENTRA_SPACE_KPATHS) return fail(ctx, CENTRA_EINVAL, "progressive: unknown hyperedge space");
+  if (p->space == CENTRA_SPACE_KPATHS && (p->kappa == 0 || p->kappa > CENTRA_MAX_KAPPA))
+    return fail(ctx, CENTRA_EINVAL, "progressive: kappa outside [1, 16]");
   const bool tri = p->space == CENTRA_SPACE_TRIANGLES;
+  const bool kp = p->space == CENTRA_SPACE_KPATHS;
   const bool fixed = p->schedule == CENTRA_SCHEDULE_FIXED;
   DeviceGuard guard(ctx->device);
   hipStream_t s = as_stream(stream);
@@ -372,6 +388,16 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
       uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
       if ((rc = sample_triangles_into(ctx, const_cast<centra_graph*>(g), p->seed, p->instance, m_prev, cnt,
                                       store_off + m_prev, total_nodes, store_nodes + total_nodes, s, true)))
+        return rc;
+    } else if (kp) {
+      if ((rc = kpath_count(ctx, g, p->kappa, p->seed, p->instance, m_prev, cnt, store_off + m_prev, s, true)))
+        return rc;
+      CENTRA_HIP(ctx, hipMemcpyAsync(&added, store_off + m_i, 8, hipMemcpyDeviceToHost, s));
+      CENTRA_HIP(ctx, hipStreamSynchronize(s));
+      if ((rc = ensure(ctx, ctx->store_nodes, (total_nodes + added + 1) * 4, true, s))) return rc;
+      uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
+      if ((rc = kpath_write(ctx, g, p->kappa, p->seed, p->instance, m_prev, cnt, store_off + m_prev, total_nodes,
+                            store_nodes + total_nodes, s, true)))
         return rc;
     } else {
       if ((rc = sample_to_stage(ctx, g, p->seed, p->instance, m_prev, cnt, nullptr, nullptr, &added, s))) return rc;
@@ -414,9 +440,9 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
     centra_bound_out o;
     bound_eval(m_i, cov, sum, t, dk, bm, p->eps, delta_i, &o);
     const double ms_s = elapsed(ev[0], ev[1]), ms_c = elapsed(ev[1], ev[2]), ms_m = elapsed(ev[2], ev[3]);
-    if (tri) {   // the triangle sampler's launch joins the sampling-kernel statistics
-      ctx->st.launches += 1;
-      ctx->st.kernel_ms += elapsed(ev[4], ev[5]);
+    if (tri || kp) {   // the space's sampler launches join the sampling-kernel statistics
+      ctx->st.launches += kp ? 2 : 1;
+      ctx->st.kernel_ms += elapsed(ev[4], ev[5]) + (kp ? elapsed(ev[6], ev[7]) : 0.f);
       ctx->st.samples += cnt;
       ctx->st.hyperedge_nodes += added;
       ctx->st.slots = 0;

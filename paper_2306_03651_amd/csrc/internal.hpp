@@ -41,6 +41,7 @@ struct centra_ctx {
   centra::DevBuf words, P, Rtm, topk_tmp, misc;
   // sample store of centra_progressive
   centra::DevBuf store_off, store_nodes;
+  centra::DevBuf kp_len;   // kappa-path walk lengths
   hipEvent_t ev[8] = {};
   centra_sampler_stats st = {};
 };
@@ -106,6 +107,14 @@ void release_graph_buffers(centra_ctx* ctx, centra_graph* g);
 
 // Triangle hyperedges (triangles.hip).
 int triangle_index(centra_ctx* ctx, centra_graph* g, uint64_t* T, hipStream_t s);
+// kappa-path hyperedges: walk lengths -> exclusive offsets off[count + 1]
+// (relative); then the walks' nodes at he_nodes + off[x], and base added to
+// off.  timed: events ev[4], ev[5] (count) and ev[6], ev[7] (write).
+int kpath_count(centra_ctx* ctx, const centra_graph* g, uint32_t kappa, uint64_t seed, uint32_t instance,
+                uint64_t first, uint32_t count, uint64_t* off, hipStream_t s, bool timed = false);
+int kpath_write(centra_ctx* ctx, const centra_graph* g, uint32_t kappa, uint64_t seed, uint32_t instance,
+                uint64_t first, uint32_t count, uint64_t* off, uint64_t base, uint32_t* he_nodes, hipStream_t s,
+                bool timed = false);
 int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
                           uint32_t count, uint64_t* he_off, uint64_t base, uint32_t* he_nodes, hipStream_t s,
                           bool timed = false);   // timed: events ev[4], ev[5] around the launch

@@ -1,0 +1,108 @@
+"""GPU parity of the kappa-path hyperedge space (the kappa-path centrality's
+space, Sec. 3.1) against the oracle: bit-exact sampled walks on undirected,
+directed, hub and dead-end graphs for several kappa, Algorithm 1 on this
+space, sampled walks at the large sparse scale, and the error cases."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2306_03651_amd import binding, inputs
+from tests.gpu_util import nodes_np, off_np, say
+from tests.test_gpu_sampler import chain, random_digraph, star
+from tests.test_oracle_triangles import gnp
+
+pytestmark = pytest.mark.gpu
+
+GRAPHS = {
+    "ba2000": lambda: inputs.ba_graph(2000, 5, 1),
+    "rmat12": lambda: inputs.rmat_graph(12, 8, seed=3),   # directed; many dead ends
+    "gnp40": lambda: gnp(40, 0.3, 1),                     # small: walks run into visited nodes
+    "star3000": lambda: star(3000),                       # one hub of degree 2,999
+    "chain1500": lambda: chain(1500),
+    "dense1200": lambda: random_digraph(1200, 0.5, 8),
+    "pair": lambda: inputs.from_edges(2, [0], [1], directed=False),
+}
+
+
+@pytest.mark.parametrize("kappa", [1, 4, 16])
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_kpaths_bit_exact(ctx, name, kappa):
+    g = GRAPHS[name]()
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        for first, count in [(0, 4000), (987654, 333)]:
+            say(f"kappa-paths {name} kappa={kappa}: samples [{first}, {first + count})")
+            off, nodes = binding.sample_kpaths(ctx, dg, kappa, 13, 2, first, count)
+            want_off, want_nodes = oracle.sample_kpaths(g, kappa, 13, 2, first, count)
+            assert np.array_equal(off_np(off), want_off)
+            assert np.array_equal(nodes_np(nodes), want_nodes)
+    finally:
+        dg.release()
+
+
+def test_kpath_errors(ctx):
+    g = inputs.ba_graph(300, 3, 1)
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        for kappa in [0, binding.CENTRA_MAX_KAPPA + 1]:
+            with pytest.raises(binding.CentraError) as e:
+                binding.sample_kpaths(ctx, dg, kappa, 1, 0, 0, 10)
+            assert e.value.code == binding.CENTRA_EINVAL
+        with pytest.raises(binding.CentraError) as e:
+            binding.centra_progressive(ctx, dg.handle, 5, 8, 0.1, 0.1, 1, 0, 1000, 2000,
+                                       space=binding.CENTRA_SPACE_KPATHS, kappa=0)
+        assert e.value.code == binding.CENTRA_EINVAL
+        # the context is still usable
+        off, nodes = binding.sample_kpaths(ctx, dg, 3, 1, 0, 0, 10)
+        want_off, want_nodes = oracle.sample_kpaths(g, 3, 1, 0, 0, 10)
+        assert np.array_equal(off_np(off), want_off) and np.array_equal(nodes_np(nodes), want_nodes)
+    finally:
+        dg.release()
+
+
+@pytest.mark.parametrize("schedule", [binding.CENTRA_SCHEDULE_GEOMETRIC, binding.CENTRA_SCHEDULE_ADAPTIVE,
+                                      binding.CENTRA_SCHEDULE_FIXED])
+def test_progressive_on_kpaths(ctx, schedule):
+    g = inputs.ba_graph(2000, 5, 1)
+    k, t, eps, delta, seed, kappa = 10, 16, 0.1, 0.1, 4, 5
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        say(f"progressive on kappa-paths, schedule {schedule}")
+        rc, picks, res, log = binding.centra_progressive(ctx, dg.handle, k, t, eps, delta, seed, 0, 4000, 256000,
+                                                         schedule=schedule, space=binding.CENTRA_SPACE_KPATHS,
+                                                         kappa=kappa)
+    finally:
+        dg.release()
+    wrc, wpicks, wres, wlog = oracle.progressive(g, k, t, eps, delta, seed, 0, 4000, 256000, schedule=schedule,
+                                                 with_m_log=True, space=oracle.SPACE_KPATHS, kappa=kappa)
+    assert rc == wrc and np.array_equal(picks, wpicks)
+    assert res.iterations == wres.iterations and res.m_final == wres.m_final and res.coverage == wres.coverage
+    assert [it.m for it in log] == wlog
+    assert all(it.b_max <= kappa for it in log)
+    for f in ["c_hat", "amcera", "wimpy", "xi", "nu", "rtilde", "r", "eta"]:
+        assert getattr(res, f) == pytest.approx(getattr(wres, f), rel=1e-12, abs=1e-300), f
+
+
+def test_kpaths_large_sparse_sampled(ctx):
+    # BA n = 1e6 (hubs of degree 3,560), kappa = 8: 500k walks on the GPU,
+    # 64 spread indices recomputed by the oracle; every walk is a simple
+    # path of at most kappa nodes.
+    g = inputs.ba_graph(1_000_000, 5, 1)
+    kappa, count = 8, 500_000
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        say(f"kappa-paths on BA 1e6: {count} walks")
+        off, nodes = binding.sample_kpaths(ctx, dg, kappa, 1, 0, 0, count)
+        torch.cuda.synchronize()
+    finally:
+        dg.release()
+    off, nodes = off_np(off), nodes_np(nodes)
+    lens = np.diff(off.astype(np.int64))
+    assert lens.min() >= 1 and lens.max() <= kappa   # BA has no dead ends: every walk moves
+    og = oracle.OracleGraph(g)
+    for i in np.linspace(0, count - 1, 64).astype(np.int64):
+        h, s, l = oracle.kpath(g, kappa, 1, 0, int(i), og=og)
+        seg = nodes[int(off[i]):int(off[i + 1])]
+        assert np.array_equal(seg, h), i
+        assert len(set(seg.tolist())) == len(seg) and s not in seg
