@@ -510,6 +510,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
     uint64_t sumL = 1;        // S_L: sum of the level-L counts (saturating)
     uint32_t shortcut = 0;    // 2 or 3: levels L+1 (and L+2) were not produced
     uint64_t w_short = 0;     // W of the first backtrack step when shortcut
+    uint64_t shifted = 0;     // bit l: the counts of produced level l < 64 were shifted
     // t without in-neighbours is unreachable: no BFS at all (on skewed
     // directed graphs such targets are common, and s may reach millions)
     for (; dt != 0;) {
@@ -759,6 +760,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
         }
       }
       if (!shift) ssum = added;
+      if (shift && nl < 64) shifted |= 1ull << nl;
       sumL = block_sat_sum<BLOCK>(ssum, sh.red);   // contains the barrier closing the level
       lb = le;
       le = ne;
@@ -777,6 +779,12 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
                     : 0ull;
     }
     uint32_t v = t, dv = len ? d : 0u, written = 0;   // no backtrack when t is unreachable or adjacent
+    // W of the next step when known without a summing pass: the raw count
+    // of v, i.e. the sum of its predecessors' counts (a ring sum or stored
+    // pair count after a shortcut step; sigma'_v itself when v was claimed
+    // at a level whose counts were not shifted)
+    uint64_t w_next = 0;
+    bool claimed_v = false;
     __syncthreads();   // sh.base, ring sums and stored pair counts are visible
     const uint64_t hbase = uniform_u64(sh.base);
     bool ok = true;
@@ -792,6 +800,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
         if (tid == 0 && hbase < a.stage_cap) a.stage[hbase] = caller_id(a, v);
         written = 1;
         dv = d - 1;
+        w_next = shortcut == 2 ? uniform_u64(sh.ring_a[pi]) : 0ull;
         if (shortcut == 3) {
           // step from w (level L+2) through level L+1: weights raw_u of the
           // pairs (w, u), stored by the cone test in in(w) order; their sum
@@ -803,6 +812,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
           if (j == kUnseen) {
             ok = false;
           } else {
+            w_next = uniform_u64(ld_u64(&praw[p0 + j]));
             v = a.in_idx[sh.rrs[pi] + j];
             if (tid == 0 && hbase + 1 < a.stage_cap) a.stage[hbase + 1] = caller_id(a, v);
             written = 2;
@@ -845,12 +855,18 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
     while (ok && dv >= 2) {
       const uint32_t want = dv - 1;
       const uint32_t vb = a.in_ptr[v], ve = a.in_ptr[v + 1];
+      // a known W spares rows longer than one pick round their summing pass
+      uint64_t wk = w_next;
+      if (!wk && claimed_v && dv < 64 && !((shifted >> dv) & 1ull)) wk = ld_u64(sig_of(rec, v));
+      wk = ve - vb > uint32_t(BLOCK) * kPickPer ? uniform_u64(wk) : 0ull;
       const uint32_t j = block_pick<BLOCK>(
-          ve - vb, [&](uint32_t jj) { return pred_weight(bits, rec, a.in_idx[vb + jj], want); }, 0, st, sh);
+          ve - vb, [&](uint32_t jj) { return pred_weight(bits, rec, a.in_idx[vb + jj], want); }, wk, st, sh);
       if (j == kUnseen) {
         ok = false;
         break;
       }
+      w_next = 0;
+      claimed_v = true;   // predecessors lie on produced levels
       v = a.in_idx[vb + j];
       if (tid == 0 && hbase + written < a.stage_cap) a.stage[hbase + written] = caller_id(a, v);
       ++written;
