@@ -22,6 +22,7 @@ GRAPHS = {
     "chain1500": lambda: chain(1500),
     "dense1200": lambda: random_digraph(1200, 0.5, 8),
     "pair": lambda: inputs.from_edges(2, [0], [1], directed=False),
+    "empty2": lambda: inputs.from_edges(2, [], [], directed=True),   # every walk is empty
 }
 
 
