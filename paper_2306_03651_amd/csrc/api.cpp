@@ -147,7 +147,7 @@ void centra_destroy(centra_ctx* ctx) {
                     &ctx->stage_len, &ctx->work_ctr, &ctx->scan_tmp, &ctx->deg, &ctx->inc_off,
                     &ctx->inc_cursor, &ctx->inc, &ctx->inc_node, &ctx->gain, &ctx->covered, &ctx->best,
                     &ctx->newcov, &ctx->words, &ctx->P, &ctx->Rtm, &ctx->topk_tmp, &ctx->misc,
-                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len};
+                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len, &ctx->seg_deg};
   for (DevBuf* b : bufs) release(ctx, *b);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   for (auto& ev : ctx->ev)
@@ -296,7 +296,7 @@ int centra_greedy_cover(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t*
   hipStream_t s = as_stream(stream);
   int rc = check_sample_args(ctx, n, m, he_off, he_nodes, "greedy_cover", s);
   if (rc) return rc;
-  if ((rc = build_incidence(ctx, n, m, he_off, he_nodes, s))) return rc;
+  if ((rc = build_incidence(ctx, n, 0, m, he_off, he_nodes, s))) return rc;
   if ((rc = check_flags(ctx, s, "greedy_cover"))) return rc;
   if ((rc = greedy_on_incidence(ctx, n, m, he_off, he_nodes, k, picks, cov_cum, n_picked, s))) return rc;
   CENTRA_HIP(ctx, hipStreamSynchronize(s));
@@ -315,7 +315,7 @@ int centra_mcera(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off
   hipStream_t s = as_stream(stream);
   int rc = check_sample_args(ctx, n, m, he_off, he_nodes, "mcera", s);
   if (rc) return rc;
-  if ((rc = build_incidence(ctx, n, m, he_off, he_nodes, s))) return rc;
+  if ((rc = build_incidence(ctx, n, 0, m, he_off, he_nodes, s))) return rc;
   if ((rc = check_flags(ctx, s, "mcera"))) return rc;
   if ((rc = rade_words(ctx, seed, instance, 0, m, t, s))) return rc;
   if ((rc = mcera_on_incidence(ctx, n, m, he_off, t, k, topk_sum, deg_topk_sum, b_max, R_out, s))) return rc;
@@ -408,7 +408,7 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
     total_nodes += added;
     uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
     CENTRA_HIP(ctx, hipEventRecord(ev[1], s));
-    if ((rc = build_incidence(ctx, n, m_i, store_off, store_nodes, s))) return rc;
+    if ((rc = build_incidence(ctx, n, m_prev, m_i, store_off, store_nodes, s))) return rc;
     if ((rc = greedy_on_incidence(ctx, n, m_i, store_off, store_nodes, k, reinterpret_cast<uint32_t*>(misc),
                                   reinterpret_cast<uint64_t*>(misc + o_cov), reinterpret_cast<uint32_t*>(misc + o_np),
                                   s)))

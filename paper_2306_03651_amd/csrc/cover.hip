@@ -1,9 +1,16 @@
 // Node -> sample incidence and greedyCover(k, H) on gfx950.
 //
-// The incidence is the transpose of the hyperedge lists: deg[u] =
-// deg_H(u), inc_off (exclusive scan of deg), inc[p] = sample id and
-// inc_node[p] = u for p in [inc_off[u], inc_off[u+1]).  The order of the
-// samples inside a row is irrelevant to every consumer.
+// The incidence is the transpose of the hyperedge lists, kept as segments,
+// one per batch of samples [m0, m1) appended by the progressive driver (a
+// single segment for a one-off call): segment g's offsets seg_off[g][u]
+// give u's entries [seg_off[g][u], seg_off[g][u+1]) of inc (sample ids) and
+// inc_node (= u); a segment's entries occupy the same index range of inc as
+// its hyperedges' entries do of he_nodes.  deg[u] = deg_H(u) over every
+// segment.  Appending a batch costs its own entries only, so a run whose
+// sample doubles builds each entry once instead of about twice.  At most
+// kMaxSegments segments are kept; the next append rebuilds one segment from
+// sample 0.  The order of the samples inside a row is irrelevant to every
+// consumer.
 //
 // Greedy keeps gain[u] = number of uncovered hyperedges containing u.  A
 // round is two kernels: an argmax over gain packed as (gain << 32 | ~u),
@@ -84,14 +91,14 @@ __device__ __forceinline__ uint32_t agg_find(const AggTable& t, uint32_t v) {
 // workgroup's entries per node, one atomic per node reserves a range of
 // the node's row, pass 2 places the entries (the same grid-stride order in
 // both passes).  Nodes without a slot reserve per entry.
-__global__ void k_scatter_inc_agg(const uint64_t* he_off, const uint32_t* he_nodes, uint64_t m, uint32_t n,
+__global__ void k_scatter_inc_agg(const uint64_t* he_off, const uint32_t* he_nodes, uint64_t m0, uint64_t m, uint32_t n,
                                   uint64_t* cursor, uint32_t* inc, uint32_t* inc_node) {
   __shared__ AggTable tab;
   __shared__ uint64_t base[kAggSize];
   agg_init(tab);
   __syncthreads();
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  const uint64_t s0 = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
+  const uint64_t s0 = m0 + blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
   for (uint64_t s = s0; s < m; s += stride)
     for (uint64_t x = he_off[s]; x < he_off[s + 1]; ++x) {
       const uint32_t u = he_nodes[x];
@@ -135,31 +142,56 @@ __global__ void k_count_deg_agg(const uint32_t* he_nodes, uint64_t I, uint32_t n
     if (tab.key[i] != kUnseen) atomicAdd(&deg[tab.key[i]], tab.cnt[i]);
 }
 
-int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes,
-                    hipStream_t s) {
-  uint64_t I = 0;
-  CENTRA_HIP(ctx, hipMemcpyAsync(&I, he_off + m, 8, hipMemcpyDeviceToHost, s));
+__global__ void k_add_u32_to(const uint32_t* a, uint32_t n, uint32_t* acc) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) acc[u] += a[u];
+}
+
+__global__ void k_offset_u64(uint64_t* a, uint64_t n, uint64_t add) {
+  for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+    a[i] += add;
+}
+
+int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const uint64_t* he_off,
+                    const uint32_t* he_nodes, hipStream_t s) {
+  if (m0 == 0 || ctx->inc_nseg >= kMaxSegments) {   // a new sample, or too many segments: start over
+    ctx->inc_nseg = 0;
+    m0 = 0;
+  }
+  uint64_t ends[2] = {0, 0};
+  CENTRA_HIP(ctx, hipMemcpyAsync(&ends[0], he_off + m0, 8, hipMemcpyDeviceToHost, s));
+  CENTRA_HIP(ctx, hipMemcpyAsync(&ends[1], he_off + m1, 8, hipMemcpyDeviceToHost, s));
   CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  const uint64_t I0 = ends[0], I1 = ends[1];
+  const uint32_t g = ctx->inc_nseg;
   int rc;
-  if ((rc = ensure(ctx, ctx->deg, size_t(n) * 4, false, s))) return rc;
-  if ((rc = ensure(ctx, ctx->inc_off, (size_t(n) + 1) * 8, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->deg, size_t(n) * 4, g > 0, s))) return rc;
+  if ((rc = ensure(ctx, ctx->seg_deg, size_t(n) * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->inc_off, (size_t(g) + 1) * (size_t(n) + 1) * 8, g > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->inc_cursor, size_t(n) * 8, false, s))) return rc;
-  if ((rc = ensure(ctx, ctx->inc, (I ? I : 1) * 4, false, s))) return rc;
-  if ((rc = ensure(ctx, ctx->inc_node, (I ? I : 1) * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->inc, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
+  if ((rc = ensure(ctx, ctx->inc_node, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
   uint32_t* deg = static_cast<uint32_t*>(ctx->deg.ptr);
-  uint64_t* off = static_cast<uint64_t*>(ctx->inc_off.ptr);
+  uint32_t* sdeg = static_cast<uint32_t*>(ctx->seg_deg.ptr);
+  uint64_t* off = static_cast<uint64_t*>(ctx->inc_off.ptr) + size_t(g) * (size_t(n) + 1);
   uint64_t* cur = static_cast<uint64_t*>(ctx->inc_cursor.ptr);
-  fill_u32(deg, 0, n, s);
-  if (I)
-    hipLaunchKernelGGL(k_count_deg_agg, dim3(grid_for(I, 256, 2048)), dim3(256), 0, s, he_nodes, I, n, deg,
-                       ctx->d_flags);
+  if (g == 0) fill_u32(deg, 0, n, s);
+  fill_u32(sdeg, 0, n, s);
+  if (I1 > I0)
+    hipLaunchKernelGGL(k_count_deg_agg, dim3(grid_for(I1 - I0, 256, 2048)), dim3(256), 0, s, he_nodes + I0, I1 - I0, n,
+                       sdeg, ctx->d_flags);
   CENTRA_HIP(ctx, hipGetLastError());
-  if ((rc = excl_scan_u32_to_u64(ctx, deg, off, n, s))) return rc;
+  if ((rc = excl_scan_u32_to_u64(ctx, sdeg, off, n, s))) return rc;
+  if (I0) hipLaunchKernelGGL(k_offset_u64, dim3(grid_for(uint64_t(n) + 1, 256)), dim3(256), 0, s, off, uint64_t(n) + 1, I0);
   hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, off, cur, size_t(n));
-  if (m)
-    hipLaunchKernelGGL(k_scatter_inc_agg, dim3(grid_for(m, 256, 2048)), dim3(256), 0, s, he_off, he_nodes, m, n, cur,
-                       static_cast<uint32_t*>(ctx->inc.ptr), static_cast<uint32_t*>(ctx->inc_node.ptr));
+  if (m1 > m0)
+    hipLaunchKernelGGL(k_scatter_inc_agg, dim3(grid_for(m1 - m0, 256, 2048)), dim3(256), 0, s, he_off, he_nodes, m0, m1,
+                       n, cur, static_cast<uint32_t*>(ctx->inc.ptr), static_cast<uint32_t*>(ctx->inc_node.ptr));
+  hipLaunchKernelGGL(k_add_u32_to, dim3(grid_for(n, 256)), dim3(256), 0, s, sdeg, n, deg);
   CENTRA_HIP(ctx, hipGetLastError());
+  ctx->inc_nseg = g + 1;
+  ctx->inc_m0 = m0;
+  ctx->inc_I0 = I0;
+  ctx->inc_I1 = I1;
   return CENTRA_OK;
 }
 
@@ -190,27 +222,48 @@ __global__ __launch_bounds__(kArgBlock) void k_argmax(const int32_t* gain, uint3
 constexpr int kCoverBlock = 256;
 
 // best = the round's pick (written by workgroup 0): the largest of the
-// n_part per-workgroup maxima of the argmax.
+// n_part per-workgroup maxima of the argmax.  The picked node's rows in the
+// n_seg incidence segments are walked as one row (their concatenation), so
+// the workgroups share it as they would a single segment's.
 __global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* part, uint32_t n_part, uint64_t* best,
-                                                       const uint64_t* inc_off, const uint32_t* inc,
+                                                       const uint64_t* seg_off, uint32_t n_seg, const uint32_t* inc,
                                                        const uint64_t* he_off, const uint32_t* he_nodes, uint32_t n,
                                                        uint32_t* covered, int32_t* gain, uint64_t* newcov) {
   __shared__ uint64_t red[kCoverBlock / kWave];
   __shared__ AggTable tab;
+  __shared__ uint64_t seg_beg[kMaxSegments], seg_pre[kMaxSegments + 1];
   uint64_t key = 0;
   for (uint32_t i = threadIdx.x; i < n_part; i += kCoverBlock) key = part[i] > key ? part[i] : key;
   key = block_max_u64<kCoverBlock>(key, red);
   if (blockIdx.x == 0 && threadIdx.x == 0) *best = key;
   if ((key >> 32) == 0) return;
   const uint32_t u = 0xFFFFFFFFu - static_cast<uint32_t>(key);
-  const uint64_t b = inc_off[u], e = inc_off[u + 1];
-  const uint64_t first = b + blockIdx.x * uint64_t(kCoverBlock);
-  if (first >= e) return;   // uniform per workgroup: nothing of the row lands here
+  if (threadIdx.x < kWave) {   // segment starts and the prefix of the row lengths (n_seg <= 64)
+    const uint32_t g = threadIdx.x;
+    uint64_t b = 0, len = 0;
+    if (g < n_seg) {
+      const uint64_t* o = seg_off + size_t(g) * (size_t(n) + 1);
+      b = o[u];
+      len = o[u + 1] - b;
+    }
+    const uint64_t incl = wave_incl_scan_u64(len);
+    if (g < n_seg) {
+      seg_beg[g] = b;
+      seg_pre[g + 1] = incl;
+    }
+    if (g == 0) seg_pre[0] = 0;
+  }
+  __syncthreads();
+  const uint64_t row = seg_pre[n_seg];
+  const uint64_t lead = blockIdx.x * uint64_t(kCoverBlock);
+  if (lead >= row) return;   // uniform per workgroup: nothing of the row lands here
   agg_init(tab);
   __syncthreads();
   uint64_t cnt = 0;
-  for (uint64_t p = first + threadIdx.x; p < e; p += uint64_t(gridDim.x) * kCoverBlock) {
-    const uint32_t s = inc[p];
+  uint32_t g = 0;
+  for (uint64_t q = lead + threadIdx.x; q < row; q += uint64_t(gridDim.x) * kCoverBlock) {
+    while (q >= seg_pre[g + 1]) ++g;
+    const uint32_t s = inc[seg_beg[g] + (q - seg_pre[g])];
     const uint32_t bit = 1u << (s & 31u);
     const uint32_t old = atomicOr(&covered[s >> 5], bit);
     if (old & bit) continue;
@@ -264,8 +317,8 @@ int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t*
   const uint32_t* inc = static_cast<const uint32_t*>(ctx->inc.ptr);
   for (uint32_t r = 0; r < k; ++r) {
     hipLaunchKernelGGL(k_argmax, dim3(ga), dim3(kArgBlock), 0, s, gain, n, part);
-    hipLaunchKernelGGL(k_cover, dim3(gc), dim3(kCoverBlock), 0, s, part, ga, best + r, ioff, inc, he_off, he_nodes, n,
-                       cov, gain, newcov + r);
+    hipLaunchKernelGGL(k_cover, dim3(gc), dim3(kCoverBlock), 0, s, part, ga, best + r, ioff, ctx->inc_nseg, inc, he_off,
+                       he_nodes, n, cov, gain, newcov + r);
   }
   hipLaunchKernelGGL(k_greedy_finish, dim3(1), dim3(64), 0, s, best, newcov, k, picks, cov_cum, n_picked);
   CENTRA_HIP(ctx, hipGetLastError());

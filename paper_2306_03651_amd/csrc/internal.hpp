@@ -37,7 +37,10 @@ struct centra_ctx {
   // scan scratch
   centra::DevBuf scan_tmp;
   // incidence (node -> samples) and greedy / AMCERA workspaces
-  centra::DevBuf deg, inc_off, inc_cursor, inc, inc_node, gain, covered, best, newcov;
+  centra::DevBuf deg, inc_off, inc_cursor, inc, inc_node, gain, covered, best, newcov, seg_deg;
+  uint32_t inc_nseg = 0;              // incidence segments held in inc_off / inc / inc_node
+  uint64_t inc_m0 = 0;                // first sample of the newest segment (0: it holds every sample)
+  uint64_t inc_I0 = 0, inc_I1 = 0;    // entry range of the newest segment
   centra::DevBuf words, P, Rtm, topk_tmp, misc;
   // sample store of centra_progressive
   centra::DevBuf store_off, store_nodes;
@@ -133,7 +136,11 @@ int stage_to_output(centra_ctx* ctx, uint32_t count, uint64_t base, uint64_t* he
 
 // Incidence + greedy (cover.hip).  Builds deg/inc_off/inc/inc_node in the
 // context for a sample of m hyperedges.
-int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
+// Appends the incidence segment of samples [m0, m1) (m0 = 0 starts a new
+// sample: every earlier segment is dropped; so does reaching kMaxSegments,
+// and the new segment then holds samples [0, m1)).
+constexpr uint32_t kMaxSegments = 64;
+int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const uint64_t* he_off,
                     const uint32_t* he_nodes, hipStream_t s);
 int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
                         const uint32_t* he_nodes, uint32_t k, uint32_t* picks, uint64_t* cov_cum,
@@ -143,6 +150,10 @@ int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t*
 // (Wt words per sample), then the per-trial top-k sums on the incidence.
 int rade_words(centra_ctx* ctx, uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1,
                uint32_t t, hipStream_t s);
+// Counts of the newest incidence segment (samples [inc_m0, m)) are added
+// to those of the earlier ones, kept from the previous call unless the
+// segment starts at sample 0; b_max likewise takes the new samples' maximum
+// into its previous value.
 int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, uint32_t t,
                        uint32_t k, int64_t* topk_sum, uint64_t* deg_topk, uint32_t* b_max,
                        int32_t* R_out, hipStream_t s);

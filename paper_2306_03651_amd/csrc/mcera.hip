@@ -308,11 +308,10 @@ __global__ void k_mcera_out(const SelState* st, uint32_t t, int64_t* topk_sum, u
 int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, uint32_t t, uint32_t k,
                        int64_t* topk_sum, uint64_t* deg_topk, uint32_t* b_max, int32_t* R_out, hipStream_t s) {
   const uint32_t Wt = (t + 63) / 64;
-  uint64_t I = 0;
-  CENTRA_HIP(ctx, hipMemcpyAsync(&I, he_off + m, 8, hipMemcpyDeviceToHost, s));
-  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  // the newest incidence segment holds samples [m0, m): entries [I0, I1)
+  const uint64_t m0 = ctx->inc_m0, I0 = ctx->inc_I0, I1 = ctx->inc_I1;
   int rc;
-  if ((rc = ensure(ctx, ctx->P, size_t(n) * t * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->P, size_t(n) * t * 4, m0 > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->Rtm, size_t(n) * t * 4, false, s))) return rc;
   const uint32_t rows = t + 1;
   if ((rc = ensure(ctx, ctx->topk_tmp, size_t(rows) * (sizeof(SelState) + kBins * 12), false, s))) return rc;
@@ -321,12 +320,13 @@ int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* 
   SelState* st = static_cast<SelState*>(ctx->topk_tmp.ptr);
   uint64_t* hsum = reinterpret_cast<uint64_t*>(st + rows);
   uint32_t* hcnt = reinterpret_cast<uint32_t*>(hsum + size_t(rows) * kBins);
-  fill_u32(reinterpret_cast<uint32_t*>(P), 0, size_t(n) * t, s);
-  if (I) {
-    const uint64_t waves = (I + kSpan - 1) / kSpan;
+  if (m0 == 0) fill_u32(reinterpret_cast<uint32_t*>(P), 0, size_t(n) * t, s);
+  if (I1 > I0) {
+    const uint64_t waves = (I1 - I0 + kSpan - 1) / kSpan;
     const uint64_t blocks = (waves * kWave + kCountBlock - 1) / kCountBlock;
     hipLaunchKernelGGL(k_rade_count, dim3(static_cast<unsigned>(blocks), Wt), dim3(kCountBlock), 0, s,
-                       static_cast<const uint32_t*>(ctx->inc.ptr), static_cast<const uint32_t*>(ctx->inc_node.ptr), I,
+                       static_cast<const uint32_t*>(ctx->inc.ptr) + I0,
+                       static_cast<const uint32_t*>(ctx->inc_node.ptr) + I0, I1 - I0,
                        static_cast<const uint64_t*>(ctx->words.ptr), Wt, t, P);
   }
   hipLaunchKernelGGL(k_rade_finish, dim3((n + 63) / 64, (t + 63) / 64), dim3(256), 0, s, P,
@@ -346,8 +346,9 @@ int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* 
     hipLaunchKernelGGL(k_sel_decide, dim3(rows), dim3(kWave), 0, s, st, pass == 0 ? 1 : 0, hcnt, hsum);
   }
   hipLaunchKernelGGL(k_mcera_out, dim3(1), dim3(256), 0, s, st, t, topk_sum, deg_topk);
-  fill_u32(b_max, 0, 1, s);
-  hipLaunchKernelGGL(k_bmax, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, he_off, m, b_max);
+  if (m0 == 0) fill_u32(b_max, 0, 1, s);
+  if (m > m0)
+    hipLaunchKernelGGL(k_bmax, dim3(grid_for(m - m0, 256, 4096)), dim3(256), 0, s, he_off + m0, m - m0, b_max);
   CENTRA_HIP(ctx, hipGetLastError());
   return CENTRA_OK;
 }

@@ -18,7 +18,7 @@ def compare(g, ctx, k, t, eps, delta, seed, inst, m_init, m_max, num=2, den=1,
     dg = binding.DeviceGraph(ctx, g)
     try:
         rc, picks, res, log = binding.centra_progressive(ctx, dg.handle, k, t, eps, delta, seed, inst, m_init,
-                                                         m_max, num, den, schedule=schedule)
+                                                         m_max, num, den, log_cap=256, schedule=schedule)
     finally:
         dg.release()
     wrc, wpicks, wres, wlog = oracle.progressive(g, k, t, eps, delta, seed, inst, m_init, m_max, num, den,
@@ -60,6 +60,15 @@ def test_directed_and_non_doubling_schedule(ctx):
     g = inputs.rmat_graph(11, 8, seed=2)
     say("progressive rmat11 growth 6/5")
     compare(g, ctx, 7, 33, 0.2, 0.05, 3, 2, 3000, 20000, 6, 5)
+
+
+def test_many_iterations_restart_the_incidence(ctx):
+    # Growth 1.05 from 1,000 to 150,000 samples: 104 iterations.  Each
+    # iteration appends an incidence segment; after 64 of them the driver
+    # rebuilds one segment from sample 0 and recounts the trial sums, and
+    # appends again from there.
+    say("progressive: 104 iterations at growth 21/20")
+    compare(inputs.ba_graph(2000, 5, 1), ctx, 10, 16, 0.01, 0.1, 3, 0, 1000, 150000, 21, 20)
 
 
 def test_adaptive_schedule(ctx):
