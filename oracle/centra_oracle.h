@@ -19,7 +19,7 @@
  *   - the approximate wimpy variance (Sec. 4.1 definition);
  *   - xi, nu, R~, R, eta (Theorem bound_dev, eq. epsrade) and the stopping
  *     condition of Algorithm 1;
- *   - the progressive driver (Algorithm 1).
+ *   - the progressive loop (Algorithm 1).
  *
  * Readings of points the paper leaves open are listed next to the function
  * that takes them.  Pins (checks against something other than this code) live

@@ -1,6 +1,6 @@
 // C ABI entry points (include/centra.h): context, graph preparation, the
 // three device steps of an iteration, the host FP64 bound and the
-// progressive driver of Algorithm 1.
+// progressive loop of Algorithm 1.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>

@@ -1,7 +1,7 @@
 // Node -> sample incidence and greedyCover(k, H) on gfx950.
 //
 // The incidence is the transpose of the hyperedge lists, kept as segments,
-// one per batch of samples [m0, m1) appended by the progressive driver (a
+// one per batch of samples [m0, m1) appended by the progressive loop (a
 // single segment for a one-off call): segment g's offsets seg_off[g][u]
 // give u's entries [seg_off[g][u], seg_off[g][u+1]) of inc (sample ids) and
 // inc_node (= u); a segment's entries occupy the same index range of inc as

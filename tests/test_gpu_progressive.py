@@ -1,4 +1,4 @@
-"""GPU parity of centra_progressive (Algorithm 1) against the oracle's driver:
+"""GPU parity of centra_progressive (Algorithm 1) against the oracle's progressive loop:
 identical iterations, sample sizes, picks and coverage; FP64 bound values
 within 1e-12 relative."""
 import numpy as np
@@ -64,7 +64,7 @@ def test_directed_and_non_doubling_schedule(ctx):
 
 def test_many_iterations_restart_the_incidence(ctx):
     # Growth 1.05 from 1,000 to 150,000 samples: 104 iterations.  Each
-    # iteration appends an incidence segment; after 64 of them the driver
+    # iteration appends an incidence segment; after 64 of them the loop
     # rebuilds one segment from sample 0 and recounts the trial sums, and
     # appends again from there.
     say("progressive: 104 iterations at growth 21/20")

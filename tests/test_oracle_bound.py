@@ -1,6 +1,6 @@
 """Pins for the oracle's bound arithmetic (Theorem bound_dev, eq. epsrade;
 Algorithm 1 definition of xi and stopping condition) and its progressive
-driver (Algorithm 1).
+loop (Algorithm 1).
 
 The bound is pinned to the fixed points it comes from (the proofs of
 Theorem selfboundingupperbound and Theorem bound_dev solve quadratic

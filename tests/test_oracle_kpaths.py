@@ -4,7 +4,7 @@ random simple walk of the kappa-path centrality, a reading): every walk is a
 simple path that stops only at its drawn length or a dead end; the sampled
 walks follow the exact distribution enumerated over every random choice;
 closed forms on complete graphs; the estimator against the exact kappa-path
-set centrality; and the progressive driver on this space."""
+set centrality; and the progressive loop on this space."""
 import math
 from collections import defaultdict
 

@@ -2,7 +2,7 @@
 centrality's space of node sets of triangles, drawn uniformly): the ranked
 triangle list against brute force and a closed form, the draw against the
 bounded-draw definition, uniformity, the estimator against the exact
-triangle centrality, and the progressive driver on this space."""
+triangle centrality, and the progressive loop on this space."""
 import itertools
 import math
 
