@@ -99,6 +99,9 @@ def _load():
                                     c.c_double, c.c_uint64, c.c_uint32, c.c_uint64, c.c_uint64,
                                     c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, _u32p,
                                     c.POINTER(Result), _u64p, c.c_uint32]
+    lib.orc_vc_dims.argtypes = [c.c_uint64, c.c_uint32, c.c_uint64, c.POINTER(c.c_uint32), c.POINTER(c.c_uint64),
+                                c.POINTER(c.c_uint64)]
+    lib.orc_vc_dims.restype = c.c_int
     lib.orc_kpath.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint64, c.c_uint32, c.c_uint64, _u32p,
                               c.POINTER(c.c_uint32), c.POINTER(c.c_uint32)]
     lib.orc_kpath.restype = c.c_uint32
@@ -281,6 +284,14 @@ def sample_triangles(g, seed, instance, first, count):
     nodes = np.zeros(3 * max(1, count), dtype=np.uint32)
     rc = _load().orc_sample_triangles(ctypes.byref(og.c), seed, instance, first, count, off, nodes)
     return None if rc else (off, nodes[: 3 * count])
+
+
+def vc_dims(b, k, n):
+    """(d1, dk_lemma, dk_union) of Sec. 4.3's VC bounds; None if b, k or n is 0."""
+    d1, dl, du = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+    if _load().orc_vc_dims(b, k, n, ctypes.byref(d1), ctypes.byref(dl), ctypes.byref(du)):
+        return None
+    return d1.value, dl.value, du.value
 
 
 def kpath(g, kappa, seed, instance, sample, og=None):

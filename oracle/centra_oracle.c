@@ -636,6 +636,23 @@ int orc_sample_kpaths(const orc_graph *g, uint32_t kappa, uint64_t seed, uint32_
     return 0;
 }
 
+/* VC-dimension bounds of the range spaces Q_k of Sec. 4.3 (ranges: the
+ * hyperedges met by a node set of at most k nodes).  Lemma vcboundgeneral:
+ * with hyperedges of at most b nodes, VC(Q_1) <= d1 = floor(log2(2b)),
+ * taken here as the largest j with 2^j <= 2b.  Lemma lemmavckbound:
+ * VC(Q_k) <= 2 VC(Q_1) k log2(3k), floored.  And VC(Q_k) <= log2 |R_k| <=
+ * floor(k log2 n), the union bound. */
+int orc_vc_dims(uint64_t b, uint32_t k, uint64_t n, uint32_t *d1, uint64_t *dk_lemma, uint64_t *dk_union)
+{
+    if (b == 0 || k == 0 || n == 0) return -1;
+    uint32_t j = 0;
+    while (j < 63 && ((uint64_t)1 << (j + 1)) <= b) j++;   /* then 2^j <= b < 2^(j+1): floor(log2(2b)) = j + 1 */
+    *d1 = j + 1;
+    *dk_lemma = (uint64_t)floor(2.0 * (double)(*d1) * (double)k * log2(3.0 * (double)k));
+    *dk_union = (uint64_t)floor((double)k * log2((double)n));
+    return 0;
+}
+
 uint64_t orc_next_sample_size(uint64_t m_i, double c_hat, double eps, double delta_next,
                               uint32_t growth_num, uint32_t growth_den, uint64_t m_max,
                               uint32_t schedule)

@@ -198,6 +198,12 @@ uint32_t orc_kpath(const orc_graph *g, uint32_t kappa, uint64_t seed, uint32_t i
 int orc_sample_kpaths(const orc_graph *g, uint32_t kappa, uint64_t seed, uint32_t instance,
                       uint64_t first, uint64_t count, uint64_t *he_off, uint32_t *he_nodes);
 
+/* VC-dimension bounds of Sec. 4.3 for hyperedges of at most b nodes, k
+ * picks and n nodes: d1 (Lemma vcboundgeneral), the bound of Lemma
+ * lemmavckbound on VC(Q_k), and the union bound floor(k log2 n).
+ * Returns 0, or -1 if b, k or n is 0. */
+int orc_vc_dims(uint64_t b, uint32_t k, uint64_t n, uint32_t *d1, uint64_t *dk_lemma, uint64_t *dk_union);
+
 /* space: 0 shortest paths, 1 triangles, 2 kappa-paths (kappa >= 1). */
 int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                     double eps, double delta, uint64_t seed, uint32_t instance,
