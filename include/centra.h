@@ -38,7 +38,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 4u
+#define CENTRA_ABI_VERSION 5u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -215,6 +215,24 @@ typedef struct {
 /* Errors: CENTRA_EINVAL (m == 0, t == 0, delta_i outside (0,1), out NULL). */
 CENTRA_API int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk,
                  uint32_t b_max, double eps, double delta_i, centra_bound_out *out);
+
+/* VC-dimension bounds of Sec. 4.3 for the range space Q_k (ranges: the
+ * hyperedges met by a node set of at most k nodes), host only:
+ *   d1       = floor(log2(2b)) >= VC(Q_1) when every hyperedge of the space
+ *              has at most b nodes (Lemma vcboundgeneral; b = 3 for
+ *              triangles, b <= kappa for kappa-paths, the vertex diameter
+ *              for shortest paths);
+ *   dk_lemma = floor(2 d1 k log2(3k)) >= VC(Q_k) (Lemma lemmavckbound);
+ *   dk_union = floor(k log2 n) >= VC(Q_k) (the union bound);
+ *   dk       = min(dk_lemma, dk_union).
+ * The sample sizes of Theorem vcsamplecomplexity follow from dk only up to
+ * a constant the paper does not give, so none is derived here.
+ * Errors: CENTRA_EINVAL (b, k or n is 0, out NULL). */
+typedef struct {
+    uint32_t d1;
+    uint64_t dk_lemma, dk_union, dk;
+} centra_vc_out;
+CENTRA_API int centra_vc_dims(uint64_t b, uint32_t k, uint64_t n, centra_vc_out *out);
 
 /* ------------------------------------------------------------------ */
 /* Triangle hyperedges: the hyperedge space of the triangle centrality

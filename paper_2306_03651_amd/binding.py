@@ -52,6 +52,10 @@ class BoundOut(_c.Structure):
                 ("r", _c.c_double), ("eta", _c.c_double), ("certified", _c.c_int)]
 
 
+class VcOut(_c.Structure):
+    _fields_ = [("d1", _c.c_uint32), ("dk_lemma", _c.c_uint64), ("dk_union", _c.c_uint64), ("dk", _c.c_uint64)]
+
+
 class Params(_c.Structure):
     _fields_ = [("k", _c.c_uint32), ("t", _c.c_uint32), ("eps", _c.c_double), ("delta", _c.c_double),
                 ("seed", _c.c_uint64), ("instance", _c.c_uint32), ("m_init", _c.c_uint64),
@@ -104,6 +108,7 @@ SIGNATURES = {
                                         _vp, _vp, _vp]),
     "centra_bound": (_c.c_int, [_c.c_uint64, _c.c_uint64, _c.c_int64, _c.c_uint32, _c.c_uint64, _c.c_uint32,
                                 _c.c_double, _c.c_double, _c.POINTER(BoundOut)]),
+    "centra_vc_dims": (_c.c_int, [_c.c_uint64, _c.c_uint32, _c.c_uint64, _c.POINTER(VcOut)]),
     "centra_progressive": (_c.c_int, [_vp, _vp, _c.POINTER(Params), _vp, _c.POINTER(Result),
                                       _c.POINTER(Iteration), _c.c_uint32, _vp]),
 }
@@ -245,6 +250,12 @@ def centra_bound(m: int, cov: int, sum_topk: int, t: int, deg_topk: int, b_max: 
                  delta_i: float) -> BoundOut:
     out = BoundOut()
     _check(lib().centra_bound(m, cov, sum_topk, t, deg_topk, b_max, eps, delta_i, ctypes.byref(out)))
+    return out
+
+
+def centra_vc_dims(b: int, k: int, n: int) -> VcOut:
+    out = VcOut()
+    _check(lib().centra_vc_dims(b, k, n, ctypes.byref(out)))
     return out
 
 

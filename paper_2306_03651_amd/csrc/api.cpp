@@ -330,6 +330,16 @@ int centra_sampler_stats_get(centra_ctx* ctx, centra_sampler_stats* out, int res
   return CENTRA_OK;
 }
 
+int centra_vc_dims(uint64_t b, uint32_t k, uint64_t n, centra_vc_out* out) {
+  if (!out || b == 0 || k == 0 || n == 0) return CENTRA_EINVAL;
+  // floor(log2(2b)) is the bit length of b
+  out->d1 = 64u - static_cast<uint32_t>(__builtin_clzll(b));
+  out->dk_lemma = static_cast<uint64_t>(floor(2.0 * double(out->d1) * double(k) * log2(3.0 * double(k))));
+  out->dk_union = static_cast<uint64_t>(floor(double(k) * log2(double(n))));
+  out->dk = out->dk_lemma < out->dk_union ? out->dk_lemma : out->dk_union;
+  return CENTRA_OK;
+}
+
 int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk, uint32_t b_max,
                  double eps, double delta_i, centra_bound_out* out) {
   if (!out || m == 0 || t == 0 || !(delta_i > 0.0 && delta_i < 1.0)) return CENTRA_EINVAL;

@@ -23,7 +23,7 @@ def test_header_declares_the_four_hot_path_calls():
     names = declared_functions()
     for f in ["centra_sample_paths", "centra_greedy_cover", "centra_mcera", "centra_progressive"]:
         assert f in names
-    assert len(names) == 16
+    assert len(names) == 17
 
 
 def test_library_exports_every_declared_symbol():
@@ -37,7 +37,7 @@ def test_binding_mirrors_header():
 
 
 def test_abi_version():
-    assert binding.centra_abi_version() == 4
+    assert binding.centra_abi_version() == 5
 
 
 CASES = [
@@ -66,3 +66,19 @@ def test_host_bound_rejects_bad_arguments():
         binding.centra_bound(10, 0, 0, 0, 0, 0, 0.1, 0.1)
     with pytest.raises(binding.CentraError):
         binding.centra_bound(10, 0, 0, 1, 0, 0, 0.1, 1.0)
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 5, 8, 1000, 2 ** 40 + 1, 2 ** 63, 2 ** 64 - 1])
+@pytest.mark.parametrize("k", [1, 2, 50, 500])
+def test_vc_dims_match_oracle(b, k):
+    for n in [2, 1000, 10 ** 6, 2 ** 22]:
+        got = binding.centra_vc_dims(b, k, n)
+        d1, dl, du = oracle.vc_dims(b, k, n)
+        assert (got.d1, got.dk_lemma, got.dk_union) == (d1, dl, du)
+        assert got.dk == min(dl, du)
+
+
+def test_vc_dims_rejects_zeros():
+    for args in [(0, 1, 1), (1, 0, 1), (1, 1, 0)]:
+        with pytest.raises(binding.CentraError):
+            binding.centra_vc_dims(*args)
