@@ -283,9 +283,13 @@ __global__ __launch_bounds__(kWave) void k_sel_decide(SelState* st, int first, u
   }
 }
 
-__global__ void k_bmax(const uint64_t* he_off, uint64_t m, uint32_t* b_max) {
+// b_max = max(b_max, largest |h| of samples [0, m) of he_off): one atomic
+// per workgroup (an atomic per wave on the one word serialised the kernel).
+constexpr int kBmaxBlock = 256;
+__global__ __launch_bounds__(kBmaxBlock) void k_bmax(const uint64_t* he_off, uint64_t m, uint32_t* b_max) {
+  __shared__ uint32_t red[kBmaxBlock / kWave];
   uint32_t mx = 0;
-  for (uint64_t s = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; s < m; s += uint64_t(gridDim.x) * blockDim.x) {
+  for (uint64_t s = blockIdx.x * uint64_t(kBmaxBlock) + threadIdx.x; s < m; s += uint64_t(gridDim.x) * kBmaxBlock) {
     const uint64_t len = he_off[s + 1] - he_off[s];
     mx = len > mx ? static_cast<uint32_t>(len) : mx;
   }
@@ -293,7 +297,13 @@ __global__ void k_bmax(const uint64_t* he_off, uint64_t m, uint32_t* b_max) {
     const uint32_t x = __shfl_xor(mx, o, kWave);
     mx = x > mx ? x : mx;
   }
-  if (lane_id() == 0 && mx) atomicMax(b_max, mx);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = 0;
+    for (int i = 0; i < kBmaxBlock / kWave; ++i) r = red[i] > r ? red[i] : r;
+    if (r) atomicMax(b_max, r);
+  }
 }
 
 __global__ void k_mcera_out(const SelState* st, uint32_t t, int64_t* topk_sum, uint64_t* deg_topk) {
@@ -348,7 +358,8 @@ int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* 
   hipLaunchKernelGGL(k_mcera_out, dim3(1), dim3(256), 0, s, st, t, topk_sum, deg_topk);
   if (m0 == 0) fill_u32(b_max, 0, 1, s);
   if (m > m0)
-    hipLaunchKernelGGL(k_bmax, dim3(grid_for(m - m0, 256, 4096)), dim3(256), 0, s, he_off + m0, m - m0, b_max);
+    hipLaunchKernelGGL(k_bmax, dim3(grid_for(m - m0, kBmaxBlock, 512)), dim3(kBmaxBlock), 0, s, he_off + m0, m - m0,
+                       b_max);
   CENTRA_HIP(ctx, hipGetLastError());
   return CENTRA_OK;
 }
