@@ -133,7 +133,11 @@ CENTRA_API int centra_graph_info(const centra_graph *g, uint32_t *max_in_degree,
  *              unreachable.
  * Errors: CENTRA_ENOSPC if he_cap < he_off[count] (then he_off is written
  * and *he_needed set; call again with a larger buffer), CENTRA_EINVAL,
- * CENTRA_ENOMEM, CENTRA_EHIP. */
+ * CENTRA_ENOMEM, CENTRA_EHIP.
+ * The environment variable CENTRA_SAMPLER_VARIANT selects another launch
+ * shape of the sampling kernel, for tests: "lds" (an exact LDS visited
+ * bitmap, 1024 threads, when it fits), "hbm512", "hbm256", "hbm128" (the
+ * default) or "hbm64" (that many threads per BFS).  Results are the same. */
 CENTRA_API int centra_sample_paths(centra_ctx *ctx, const centra_graph *g, uint64_t seed, uint32_t instance,
                         uint64_t first_sample, uint32_t count, uint64_t *he_off, uint32_t *he_nodes,
                         uint64_t he_cap, uint64_t *he_needed, uint32_t *st_out, uint32_t *dist_out,
