@@ -38,6 +38,19 @@ MUTANTS = {
                                "tests/test_oracle_cover_mcera.py"),
     "topk_negatives_kept": ("            if (x > 0) col[npos++] = x;", "            col[npos++] = x;",
                             "tests/test_oracle_cover_mcera.py"),
+    "philox_round_constant": ("const uint64_t M0 = 0xD2E7470EE14C6C93ULL,", "const uint64_t M0 = 0xD2E7470EE14C6C95ULL,",
+                              "tests/test_oracle_rng.py"),
+    "lemire_no_rejection": ("        while (low < threshold) {", "        while (low < threshold && 0) {",
+                            "tests/test_oracle_rng.py"),
+    "pair_may_repeat_s": ("    uint32_t t = tp + (tp >= s ? 1u : 0u);", "    uint32_t t = tp + (tp > s ? 1u : 0u);",
+                          "tests/test_oracle_sampler.py"),
+    "counts_shift_one_short": ("        uint32_t shift = bl > c_bits ? bl - c_bits : 0;",
+                               "        uint32_t shift = bl > c_bits + 1 ? bl - c_bits - 1 : 0;", "tests/test_oracle_sampler.py"),
+    "counts_no_clamp": ("            b->sigma[b->visited[q]] = x ? x : 1;", "            b->sigma[b->visited[q]] = x;",
+                        "tests/test_oracle_sampler.py"),
+    "schedule_root_term": ("const double inv_y = (sqrt(2.0 * L) + sqrt(2.0 * L + 4.0 * L * T / 3.0)) / (2.0 * T);",
+                           "const double inv_y = (sqrt(2.0 * L) + sqrt(2.0 * L + 4.0 * L * T)) / (2.0 * T);",
+                           "tests/test_oracle_schedule.py"),
     "bound_last_term_dropped": ("sqrt(2.0 * L * (nu + 4.0 * r) / md) + L / (3.0 * md);", "sqrt(2.0 * L * (nu + 4.0 * r) / md);",
                                 "tests/test_oracle_bound.py"),
 }
