@@ -233,6 +233,49 @@ def copy_probe():
                       "launches": 8, "GBps_read_plus_write": round(8 * 2 * (1 << 30) / dt / 1e9, 1)}), flush=True)
 
 
+def sweeps():
+    """Synthetic analogues of the paper's experiments on t and m (Section 5):
+    the fixed-size bound (one iteration, delta itself) on the sparse
+    workload's graph, k = 50, delta = 0.05; eta, AMCERA and phase times
+    against t at m = 500,000, and eta against m at t = 100.  Prints one
+    JSON line."""
+    import torch
+    from paper_2306_03651_amd import binding, inputs
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    W = WORKLOADS["sparse"]
+    g = inputs.ba_graph(W["n"], W["m0"], W["graph_seed"])
+    ctx = binding.centra_create(0, 0)
+    dg = binding.DeviceGraph(ctx, g)
+    stream = torch.cuda.current_stream()
+
+    def fixed(m, t):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, picks, res, _ = binding.centra_progressive(ctx, dg.handle, 50, t, 0.01, 0.05, W["seed"], W["instance"],
+                                                       m, m, 2, 1, stream=stream,
+                                                       schedule=binding.CENTRA_SCHEDULE_FIXED)
+        torch.cuda.synchronize()
+        return {"m": m, "t": t, "eta": res.eta, "amcera": res.amcera, "c_hat": res.c_hat, "r": res.r,
+                "ms_total": round(1e3 * (time.perf_counter() - t0), 2),
+                "phase_ms": {"sample": round(res.ms_sample, 2), "cover": round(res.ms_cover, 2),
+                             "mcera": round(res.ms_mcera, 2)}}
+
+    fixed(100_000, 10)   # warm-up
+    over_t = []
+    for t in [1, 10, 50, 100, 200, 500, 1000]:
+        over_t.append(fixed(500_000, t))
+        log(f"t sweep: {over_t[-1]}")
+    over_m = []
+    for m in [50_000, 100_000, 200_000, 500_000, 1_000_000]:
+        over_m.append(fixed(m, 100))
+        log(f"m sweep: {over_m[-1]}")
+    dg.release()
+    binding.centra_destroy(ctx)
+    print(json.dumps({"sweep": "fixed-size bound on " + W["label"].split(";")[0] + "; k=50, delta=0.05",
+                      "over_t": over_t, "over_m": over_m}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,11 +289,16 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sparse",
                     help="sparse (default): BA n=1e6; skewed: R-MAT scale 22, directed; small: BA n=2,000; "
                          "triangles: the triangle space of R-MAT scale 20, undirected")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run only the t and m sweeps of the fixed-size bound (one JSON line)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy 8 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.sweep:
+        sweeps()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the hot path is single-GPU here); got --gpus {args.gpus}",
