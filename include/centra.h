@@ -309,7 +309,14 @@ CENTRA_API int centra_sample_kpaths(centra_ctx *ctx, const centra_graph *g, uint
  * centra_sample_kpaths with the params' kappa; kappa is ignored otherwise).
  * Inputs: k >= 1, 1 <= t <= 1024, eps in (0, 1-1/e), delta in (0,1),
  * 1 <= m_init <= m_max < 2^31, growth_num > growth_den >= 1, schedule and
- * space one of their values. */
+ * space one of their values, 1 <= kappa <= CENTRA_MAX_KAPPA for
+ * CENTRA_SPACE_KPATHS.
+ * Work per iteration: only the new samples are drawn, and only their
+ * entries are added to the node -> sample incidence (one segment per
+ * iteration, at most 64 before one is rebuilt from sample 0) and to the
+ * per-node Rademacher counts (the incremental computation of Section 4);
+ * greedy and the per-trial top-k then run over the whole sample.
+ * Synchronous: one host synchronisation per iteration. */
 #define CENTRA_SCHEDULE_GEOMETRIC 0u
 #define CENTRA_SCHEDULE_ADAPTIVE 1u
 #define CENTRA_SCHEDULE_FIXED 2u
