@@ -86,13 +86,13 @@ WORKLOADS = {
                         "10,000 samples, k=10, t=10, eps=0.05, delta=0.1"),
     "kpaths": dict(graph="barabasi_albert", n=1_000_000, m0=5, graph_seed=1, seed=1, instance=0,
                    m_init=1_000_000, m_max=8_000_000, growth=2, k=50, t=64, eps=0.05, delta=0.1,
-                   space="kpaths", kappa=5, traffic=None,
+                   space="kpaths", kappa=5, traffic="sample_kpaths_ba1e6_traffic.txt",
                    label="CentRA (Algorithm 1) on the kappa-path hyperedge space (kappa=5) of Barabasi-Albert "
                          "n=1e6, attachment 5, seed 1; samples 1M doubling to 8M, k=50, t=64, eps=0.05, "
                          "delta=0.1"),
     "triangles": dict(graph="rmat_undirected", scale=20, edge_factor=16, graph_seed=1, seed=1, instance=0,
                       m_init=1_000_000, m_max=8_000_000, growth=2, k=50, t=64, eps=0.01, delta=0.1,
-                      space="triangles", traffic=None,
+                      space="triangles", traffic="sample_triangles_rmat20u_traffic.txt",
                       label="CentRA (Algorithm 1) on the triangle hyperedge space of R-MAT scale 20 (edge factor "
                             "16, .57/.19/.19/.05, seed 1, symmetrised); samples 1M doubling to 8M, k=50, t=64, "
                             "eps=0.01, delta=0.1"),
@@ -106,13 +106,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    return hashlib.sha256(open(SAMPLER_SRC, "rb").read()).hexdigest()[:16]
+def kernel_source_hash(src: str = SAMPLER_SRC) -> str:
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
 def read_traffic(name=WORKLOAD["traffic"]):
-    """HBM bytes per launch from the committed counter summary, if it matches
-    the current sampler source."""
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current source of its kernel (sample.hip unless the summary
+    names another)."""
     if not name:
         return None
     path = os.path.join(ROOT, "profiles", name)
@@ -123,7 +124,11 @@ def read_traffic(name=WORKLOAD["traffic"]):
         if ":" in ln and not ln.startswith("#"):
             k, v = ln.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("sampler_source_sha256_16") != kernel_source_hash():
+    if "kernel_source" in vals:
+        src = os.path.join(ROOT, "paper_2306_03651_amd", "csrc", os.path.basename(vals["kernel_source"]))
+        if not os.path.exists(src) or vals.get("kernel_source_sha256_16") != kernel_source_hash(src):
+            return None
+    elif vals.get("sampler_source_sha256_16") != kernel_source_hash():
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])

@@ -12,7 +12,7 @@ import bench
 PROFILES = os.path.join(bench.ROOT, "profiles")
 
 
-@pytest.mark.parametrize("workload", ["sparse", "skewed"])
+@pytest.mark.parametrize("workload", ["sparse", "skewed", "triangles", "kpaths"])
 def test_traffic_summary_matches_the_sampler_source(workload):
     name = bench.WORKLOADS[workload]["traffic"]
     assert bench.read_traffic(name) is not None, f"{name} was taken on another sampler source: profile again"
