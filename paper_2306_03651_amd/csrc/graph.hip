@@ -242,7 +242,9 @@ void release_graph_buffers(centra_ctx* ctx, centra_graph* g) {
   release(ctx, g->tri_prefix);
   release(ctx, g->tri_c);
   release(ctx, g->tri_cap);
+  release(ctx, g->tri_dir);
   g->tri_list_off = nullptr;
+  g->tri_dir_w = 0;
 }
 
 }  // namespace centra

@@ -73,7 +73,8 @@ struct centra_graph {
   centra::DevBuf r_row_ptr, r_col_idx, r_in_ptr, r_in_idx, r_new_of, r_orig_of;
   // triangle index (triangles.hip), built on first use: each arc's source and
   // the exclusive prefix over arcs of their triangle counts
-  centra::DevBuf tri_src, tri_prefix, tri_cap, tri_c;
+  centra::DevBuf tri_src, tri_prefix, tri_cap, tri_c, tri_dir;
+  uint64_t tri_dir_w = 0;   // rank directory bucket width; 0: no directory
   const uint64_t* tri_list_off = nullptr;   // per-arc offsets into tri_c; null: no list
   uint64_t tri_total = ~0ull;   // number of triangles; ~0: not built
 };

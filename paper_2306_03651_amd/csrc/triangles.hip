@@ -27,6 +27,13 @@
 //   - walk (no list): each sample walks its arc's lists to its match.
 // The first that fits is taken; CENTRA_TRIANGLE_LIST=0 forces the walk and
 // CENTRA_TRIANGLE_LIST=compact the compact list (for tests of those paths).
+//
+// Finding r's arc.  A binary search over the whole prefix (8 bytes per arc)
+// misses the cache at nearly every probe.  The index therefore keeps a
+// directory of the ranks: with bucket width W (at most kDirBuckets
+// buckets), dir[b] is the arc holding rank b W, and dir[nb] the arc holding
+// rank T - 1.  Rank r's arc lies in [dir[b], dir[b+1]] for b = r / W, a few
+// arcs, so the search there takes one or two lines.
 #include <cstdlib>
 #include <cstring>
 
@@ -48,6 +55,7 @@ __device__ __forceinline__ uint32_t upper(const uint32_t* idx, uint32_t lo, uint
 }
 
 constexpr uint32_t kHeavy = 64;   // an arc walked by one lane has at most this many steps
+constexpr uint64_t kDirBuckets = 1ull << 22;   // rank directory size bound (16 MB)
 
 // The two lists of arc e = (a, b): walk [w0, w1), search [s0, s1); empty
 // unless a < b.  A = N(a) after e, B = N(b) above b; the shorter is walked.
@@ -161,18 +169,38 @@ __device__ uint32_t nth_common(const uint32_t* row_ptr, const uint32_t* col_idx,
   return kUnseen;
 }
 
+// dir[b] = the arc holding rank b W for the buckets starting in arc e, and
+// dir[nb] = the arc holding rank T - 1 (every rank lies in exactly one arc
+// with a positive count)
+__global__ void k_tri_dir(uint64_t n_arcs, const uint64_t* prefix, uint64_t T, uint64_t W, uint64_t nb,
+                          uint32_t* dir) {
+  const uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
+  if (e >= n_arcs) return;
+  const uint64_t c0 = prefix[e], c1 = prefix[e + 1];
+  if (c1 == c0) return;
+  for (uint64_t b = (c0 + W - 1) / W; b * W < c1; ++b) dir[b] = static_cast<uint32_t>(e);
+  if (c0 <= T - 1 && T - 1 < c1) dir[nb] = static_cast<uint32_t>(e);
+}
+
 __global__ void k_tri_sample(uint32_t count, uint64_t first, uint64_t seed, uint32_t instance, uint64_t T,
-                             uint64_t n_arcs, const uint64_t* prefix, const uint32_t* src, const uint32_t* row_ptr,
-                             const uint32_t* col_idx, const uint64_t* list_off, const uint32_t* tri_c, uint64_t base,
-                             uint64_t* he_off, uint32_t* he_nodes) {
+                             uint64_t n_arcs, const uint64_t* prefix, const uint32_t* dir, uint64_t W,
+                             const uint32_t* src, const uint32_t* row_ptr, const uint32_t* col_idx,
+                             const uint64_t* list_off, const uint32_t* tri_c, uint64_t base, uint64_t* he_off,
+                             uint32_t* he_nodes) {
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x > count) return;
   he_off[x] = base + 3ull * x;
   if (x == count) return;
   WordStream st(seed, first + x, instance, 5);
   const uint64_t r = bounded(st, T);
-  // the arc e with prefix[e] <= r < prefix[e + 1]
+  // the arc e with prefix[e] <= r < prefix[e + 1]: prefix[lo] <= r and
+  // prefix[hi] > r (or hi = n_arcs) hold throughout
   uint64_t lo = 0, hi = n_arcs;
+  if (dir) {
+    const uint64_t b = r / W;
+    lo = dir[b];
+    hi = uint64_t(dir[b + 1]) + 1;
+  }
   while (lo + 1 < hi) {
     const uint64_t mid = lo + (hi - lo) / 2;
     if (prefix[mid] <= r)
@@ -277,6 +305,25 @@ int triangle_index(centra_ctx* ctx, centra_graph* g, uint64_t* T, hipStream_t s)
     return rc;
   }
   ctx->err.clear();   // a refused list is not an error: samples walk instead
+  g->tri_dir_w = 0;
+  if (total) {
+    // the rank directory (optional: without it samples search the whole prefix)
+    const uint64_t W = (total + kDirBuckets - 1) / kDirBuckets;
+    const uint64_t nb = (total + W - 1) / W;
+    if (A < (1ull << 32) && ensure(ctx, g->tri_dir, (nb + 1) * 4, false, s) == CENTRA_OK) {
+      hipLaunchKernelGGL(k_tri_dir, grid_a, dim3(256), 0, s, A, prefix, total, W, nb,
+                         static_cast<uint32_t*>(g->tri_dir.ptr));
+      if (hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess) {
+        g->tri_dir_w = W;
+      } else {
+        release(ctx, g->tri_dir);
+        ctx->err.clear();
+        (void)hipGetLastError();
+      }
+    } else {
+      ctx->err.clear();
+    }
+  }
   if (total == 0) {
     release(ctx, g->tri_c);
     release(ctx, g->tri_cap);
@@ -298,6 +345,7 @@ int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint3
   if (timed) CENTRA_HIP(ctx, hipEventRecord(ctx->ev[4], s));
   hipLaunchKernelGGL(k_tri_sample, dim3((count + 1 + 255) / 256), dim3(256), 0, s, count, first, seed, instance, T,
                      g->n_arcs, static_cast<const uint64_t*>(g->tri_prefix.ptr),
+                     g->tri_dir_w ? static_cast<const uint32_t*>(g->tri_dir.ptr) : nullptr, g->tri_dir_w,
                      static_cast<const uint32_t*>(g->tri_src.ptr), g->row_ptr, g->col_idx, g->tri_list_off,
                      static_cast<const uint32_t*>(g->tri_c.ptr), base, he_off, he_nodes);
   CENTRA_HIP(ctx, hipGetLastError());
