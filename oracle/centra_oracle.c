@@ -165,6 +165,16 @@ int orc_graph_check(const orc_graph *g)
         for (uint32_t v = 0; v < g->n; v++)
             if (cnt[v] != (uint64_t)(g->rrow_ptr[v + 1] - g->rrow_ptr[v])) { free(cnt); return -20; }
         free(cnt);
+        /* with equal row sizes and no duplicates, every arc u -> v having u
+         * in v's reverse row makes the reverse rows the reversed arcs */
+        for (uint32_t u = 0; u < g->n; u++)
+            for (uint32_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; e++) {
+                const uint32_t v = g->col_idx[e];
+                int found = 0;
+                for (uint32_t f = g->rrow_ptr[v]; f < g->rrow_ptr[v + 1]; f++)
+                    if (g->rcol_idx[f] == u) { found = 1; break; }
+                if (!found) return -21;
+            }
     }
     return 0;
 }

@@ -308,7 +308,14 @@ int triangle_index(centra_ctx* ctx, centra_graph* g, uint64_t* T, hipStream_t s)
   g->tri_dir_w = 0;
   if (total) {
     // the rank directory (optional: without it samples search the whole prefix)
-    const uint64_t W = (total + kDirBuckets - 1) / kDirBuckets;
+    // Test hook: CENTRA_TRIANGLE_DIR_BUCKETS lowers the bucket bound, so
+    // that small graphs get buckets wider than one rank.
+    uint64_t max_buckets = kDirBuckets;
+    if (const char* nb_env = getenv("CENTRA_TRIANGLE_DIR_BUCKETS")) {
+      const unsigned long long v = strtoull(nb_env, nullptr, 0);
+      if (v >= 1 && v < max_buckets) max_buckets = v;
+    }
+    const uint64_t W = (total + max_buckets - 1) / max_buckets;
     const uint64_t nb = (total + W - 1) / W;
     if (A < (1ull << 32) && ensure(ctx, g->tri_dir, (nb + 1) * 4, false, s) == CENTRA_OK) {
       hipLaunchKernelGGL(k_tri_dir, grid_a, dim3(256), 0, s, A, prefix, total, W, nb,

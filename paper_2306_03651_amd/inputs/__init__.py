@@ -151,3 +151,29 @@ def hyperedges(n: int, m: int, max_len: int = 8, skew: int = 3, seed: int = 1):
     he_nodes = np.zeros(max(1, m * max_len), dtype=np.uint32)
     total = int(lib.gg_hyperedges(n, m, max_len, skew, seed, he_off, he_nodes))
     return he_off, np.ascontiguousarray(he_nodes[:total])
+
+
+def layered_dag(layers: int = 40, width: int = 12, max_in: int = 8, hub_out: int = 600,
+                seed: int = 1) -> CSRGraph:
+    """Directed layered graph whose maximum in-degree differs from its maximum
+    out-degree: node 0 feeds every node of layer 1; each node of a later
+    layer has 1..max_in in-neighbours drawn from the layer before (numpy
+    generator of `seed`); a separate hub feeds `hub_out` leaves.  Path
+    counts grow about max_in/2-fold per layer, so long pairs exceed 2^C."""
+    rng = np.random.default_rng(seed)
+    src, dst = [], []
+    first = 1
+    for v in range(first, first + width):
+        src.append(0); dst.append(v)
+    for L in range(1, layers):
+        prev = first + (L - 1) * width
+        cur = first + L * width
+        for v in range(cur, cur + width):
+            k = int(rng.integers(1, max_in + 1))
+            for u in rng.choice(width, size=k, replace=False):
+                src.append(prev + int(u)); dst.append(v)
+    hub = first + layers * width
+    for j in range(hub_out):
+        src.append(hub); dst.append(hub + 1 + j)
+    n = hub + 1 + hub_out
+    return from_edges(n, src, dst, directed=True, name=f"layered_{layers}x{width}_s{seed}")

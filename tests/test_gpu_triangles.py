@@ -128,3 +128,33 @@ def test_triangles_rmat16_all_modes(ctx, monkeypatch):
     assert (tri[:, 0] < tri[:, 1]).all() and (tri[:, 1] < tri[:, 2]).all()
     for x, y in [(0, 1), (0, 2), (1, 2)]:
         assert np.asarray(M[tri[:, x], tri[:, y]]).ravel().all()
+
+
+@pytest.mark.parametrize("c_of", list(LIST_MODES))
+@pytest.mark.parametrize("W", [2, 7, 64, "all"])
+@pytest.mark.parametrize("name", ["k12", "gnp300", "rmat12u", "gnp400"])
+def test_triangles_rank_directory_widths(ctx, name, W, c_of, monkeypatch):
+    # The rank directory brackets each rank's arc by the arcs holding the
+    # ranks b W and (b + 1) W (the last bucket by the arc of rank T - 1).
+    # Large graphs get W > 1; here the bucket count is capped so that small
+    # graphs do too: W = 2, 7, 64 and a single bucket holding every rank.
+    # Enough draws hit every rank of K_12 (bucket edges and r = T - 1).
+    set_list_mode(monkeypatch, c_of)
+    g = GRAPHS[name]()
+    T = len(oracle.triangles(g))
+    buckets = 1 if W == "all" else -(-T // W)
+    w_lib = -(-T // buckets)   # the width the library derives: W, or 55 for K_12 at W = 64
+    assert w_lib == (T if W == "all" else W) or (name == "k12" and w_lib > 1)
+    monkeypatch.setenv("CENTRA_TRIANGLE_DIR_BUCKETS", str(buckets))
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        assert binding.centra_triangle_count(ctx, dg.handle) == T
+        say(f"triangles {name} ({c_of}): T={T}, directory of {buckets} buckets of width {w_lib}")
+        off, nodes = binding.sample_triangles(ctx, dg, 5, 2, 3, 20000)
+        want_off, want_nodes = oracle.sample_triangles(g, 5, 2, 3, 20000)
+        assert np.array_equal(off_np(off), want_off)
+        assert np.array_equal(nodes_np(nodes), want_nodes)
+    finally:
+        dg.release()
+    if name == "k12":
+        assert len({tuple(x) for x in nodes_np(nodes).reshape(-1, 3)}) == T

@@ -46,6 +46,12 @@ MUTANTS = {
                           "tests/test_oracle_sampler.py"),
     "counts_shift_one_short": ("        uint32_t shift = bl > c_bits ? bl - c_bits : 0;",
                                "        uint32_t shift = bl > c_bits + 1 ? bl - c_bits - 1 : 0;", "tests/test_oracle_sampler.py"),
+    "count_bits_out_degree": ("    const uint32_t *ip = in_ptr(g);\n    uint64_t dmax = 0;",
+                              "    const uint32_t *ip = g->row_ptr;\n    uint64_t dmax = 0;", "tests/test_oracle_sampler.py"),
+    "graph_check_self_loops_allowed": ("            if (idx[e] == u) return -6;", "            if (idx[e] == u && 0) return -6;",
+                                       "tests/test_oracle_sampler.py"),
+    "graph_check_reverse_sources_unchecked": ("                if (!found) return -21;", "                if (!found && 0) return -21;",
+                                              "tests/test_oracle_sampler.py"),
     "counts_no_clamp": ("            b->sigma[b->visited[q]] = x ? x : 1;", "            b->sigma[b->visited[q]] = x;",
                         "tests/test_oracle_sampler.py"),
     "schedule_root_term": ("const double inv_y = (sqrt(2.0 * L) + sqrt(2.0 * L + 4.0 * L * T / 3.0)) / (2.0 * T);",

@@ -111,6 +111,99 @@ def test_count_bits():
     assert oracle.count_bits(g) == 63 - dmax.bit_length()
 
 
+def test_count_bits_directed_uses_in_degree():
+    # Reading R4 budgets the counts by the largest in-degree (a level's raw
+    # count is a sum over in-neighbours).  On this directed graph the
+    # largest in-degree (8, from the transpose) is far below the largest
+    # out-degree (600), so C = 59, not 52; the counts from node 0 cross
+    # 2^C, and every normalised count equals a recomputation with Python
+    # integers level by level (BFS levels over out-arcs, raw sums over
+    # in-neighbours one level up, the level's shift, the clamp to 1).
+    g = inputs.layered_dag()
+    indeg = np.bincount(g.col_idx.astype(np.int64), minlength=g.n)
+    outdeg = np.diff(g.row_ptr.astype(np.int64))
+    assert indeg.max() == 8 and outdeg.max() == 600
+    C = 63 - int(indeg.max()).bit_length()
+    assert oracle.count_bits(g) == C == 59
+    level, sigma = oracle.bfs_counts(g, 0)
+    # Python reference, independent of the oracle's BFS
+    preds = [[] for _ in range(g.n)]
+    for u in range(g.n):
+        for e in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])):
+            preds[int(g.col_idx[e])].append(u)
+    lev = {0: 0}
+    frontier, d = [0], 0
+    while frontier:
+        nxt = []
+        for u in frontier:
+            for e in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])):
+                v = int(g.col_idx[e])
+                if v not in lev:
+                    lev[v] = d + 1
+                    nxt.append(v)
+        frontier, d = nxt, d + 1
+    norm = {0: 1}
+    shifted = 0
+    for L in range(1, d):
+        cells = [v for v, x in lev.items() if x == L]
+        raw = {v: sum(norm[w] for w in preds[v] if lev.get(w) == L - 1) for v in cells}
+        shift = max(0, max(raw.values()).bit_length() - C)
+        shifted += shift > 0
+        for v, x in raw.items():
+            norm[v] = max(1, x >> shift)
+    assert shifted >= 5
+    for v, L in lev.items():
+        assert int(level[v]) == L
+        assert int(sigma[v]) == norm[v], v
+    # with the out-degree budget (C = 52) the counts would differ
+    level52, sigma52 = oracle.bfs_counts(g, 0, c_bits=63 - int(outdeg.max()).bit_length())
+    assert any(int(sigma52[v]) != norm[v] for v in lev)
+
+
+BAD_GRAPHS = {
+    "n_below_2": lambda g: inputs.CSRGraph(1, False, np.array([0, 0], np.uint32), np.zeros(0, np.uint32)),
+    "unsorted_row": lambda g: _with_col(g, lambda c: c.__setitem__(slice(0, 2), c[[1, 0]])),
+    "duplicate": lambda g: _with_col(g, lambda c: c.__setitem__(1, c[0])),
+    "self_loop": lambda g: _with_col(g, lambda c: c.__setitem__(0, 0)),
+    "out_of_range": lambda g: _with_col(g, lambda c: c.__setitem__(len(c) - 1, g.n)),
+}
+
+
+def _with_col(g, edit):
+    col = g.col_idx.copy()
+    edit(col)
+    return inputs.CSRGraph(g.n, False, g.row_ptr, col)
+
+
+@pytest.mark.parametrize("name", list(BAD_GRAPHS))
+def test_graph_check_rejects(name):
+    # a star rooted at 0 whose row 0 is 1, 2, ... : each edit breaks one
+    # rule of the graph contract (rows sorted ascending, no duplicates, no
+    # self loops, ids below n, n >= 2)
+    g = inputs.from_edges(20, np.zeros(19, np.int64), np.arange(1, 20), directed=False)
+    assert oracle.graph_check(g) == 0
+    assert oracle.graph_check(BAD_GRAPHS[name](g)) != 0
+
+
+def test_graph_check_rejects_wrong_reverse_rows():
+    d = random_digraph(40, 0.1, 1)
+    assert oracle.graph_check(d) == 0
+    # a reverse CSR with one in-arc moved to another row
+    rrow = d.rrow_ptr.copy()
+    v = int(np.argmax(np.diff(rrow.astype(np.int64)) > 0))
+    rrow[v + 1] -= 1
+    bad = inputs.CSRGraph(d.n, True, d.row_ptr, d.col_idx, rrow, d.rcol_idx)
+    assert oracle.graph_check(bad) != 0
+    # a sorted in-row with one source replaced by a node that has no such arc
+    rcol = d.rcol_idx.copy()
+    row = set(int(x) for x in rcol[d.rrow_ptr[v]:d.rrow_ptr[v + 1]])
+    repl = next(u for u in range(d.n) if u not in row and u != v)
+    rcol[d.rrow_ptr[v]] = repl
+    rcol[d.rrow_ptr[v]:d.rrow_ptr[v + 1]] = np.sort(rcol[d.rrow_ptr[v]:d.rrow_ptr[v + 1]])
+    bad = inputs.CSRGraph(d.n, True, d.row_ptr, d.col_idx, d.rrow_ptr, rcol)
+    assert oracle.graph_check(bad) != 0
+
+
 @pytest.mark.parametrize("name", list(GRAPHS))
 def test_sampled_hyperedges_are_shortest_path_interiors(name):
     g = GRAPHS[name]()
