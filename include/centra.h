@@ -38,7 +38,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 5u
+#define CENTRA_ABI_VERSION 6u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -70,7 +70,8 @@ CENTRA_API int centra_create(int hip_device, size_t hbm_budget_bytes, centra_ctx
 CENTRA_API void centra_destroy(centra_ctx *ctx);
 
 /* Text of the last error reported on `ctx` ("" if none).  Valid until the
- * next call on ctx.  With ctx == NULL, the last error of centra_create. */
+ * next call on ctx.  With ctx == NULL, the last error of a call without a
+ * context (centra_create, centra_greedy_cover_noalloc) on this host thread. */
 CENTRA_API const char *centra_last_error(const centra_ctx *ctx);
 
 /* ------------------------------------------------------------------ */
@@ -157,6 +158,26 @@ CENTRA_API int centra_sample_paths(centra_ctx *ctx, const centra_graph *g, uint6
 CENTRA_API int centra_greedy_cover(centra_ctx *ctx, uint32_t n, uint64_t m, const uint64_t *he_off,
                         const uint32_t *he_nodes, uint32_t k, uint32_t *picks, uint64_t *cov_cum,
                         uint32_t *n_picked, void *stream);
+
+/* centra_greedy_cover for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same inputs, outputs and results as centra_greedy_cover, on
+ * the current HIP device and without a context; it calls no hipMalloc,
+ * hipFree or other allocating routine.  Its workspaces (the incidence of
+ * the sample, gains, the covered bitmap, round state) are carved from a
+ * fixed array of CENTRA_NOALLOC_SCRATCH_BYTES in device memory that each
+ * GPU the library runs on holds until the process ends.  The sizes must
+ * fit it: about 28 n + 8 I + m / 8 + 16 k bytes (I = he_off[m], the
+ * hyperedge entries), else CENTRA_ENOSPC with the sizes in
+ * centra_last_error(NULL).  All calls on one GPU share that array: calls
+ * that overlap on one GPU (two host threads, or two streams in flight)
+ * race and give wrong results; serialise them.  Synchronises `stream`
+ * before returning (it reads he_off[m] and the error word).
+ * Errors: CENTRA_EINVAL (k == 0, n == 0, NULL pointer, node id >= n),
+ * CENTRA_ENOTSUP (m >= 2^31), CENTRA_ENOSPC, CENTRA_EHIP. */
+#define CENTRA_NOALLOC_SCRATCH_BYTES (64u << 20)
+CENTRA_API int centra_greedy_cover_noalloc(uint32_t n, uint64_t m, const uint64_t *he_off, const uint32_t *he_nodes,
+                                uint32_t k, uint32_t *picks, uint64_t *cov_cum, uint32_t *n_picked, void *stream);
 
 /* AMCERA ingredients (Sec. 4.1 definitions of the AMCERA and the
  * approximate wimpy variance; Algorithm 1 AMCERA steps).  The sample is

@@ -98,6 +98,7 @@ SIGNATURES = {
     "centra_sample_paths": (_c.c_int, [_vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _vp, _vp,
                                        _c.c_uint64, _c.POINTER(_c.c_uint64), _vp, _vp, _vp]),
     "centra_greedy_cover": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint32, _vp, _vp, _vp, _vp]),
+    "centra_greedy_cover_noalloc": (_c.c_int, [_c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint32, _vp, _vp, _vp, _vp]),
     "centra_mcera": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint32,
                                 _c.c_uint32, _vp, _vp, _vp, _vp, _vp]),
     "centra_sampler_stats_get": (_c.c_int, [_vp, _c.POINTER(SamplerStats), _c.c_int]),
@@ -230,6 +231,12 @@ def centra_greedy_cover(ctx, n: int, he_off, he_nodes, k: int, picks, cov_cum, n
     m = he_off.numel() - 1
     return _check(lib().centra_greedy_cover(ctx, n, m, _ptr(he_off), _ptr(he_nodes), k, _ptr(picks),
                                             _ptr(cov_cum), _ptr(n_picked), _stream(stream)), ctx)
+
+
+def centra_greedy_cover_noalloc(n: int, he_off, he_nodes, k: int, picks, cov_cum, n_picked, stream=None) -> int:
+    m = he_off.numel() - 1
+    return _check(lib().centra_greedy_cover_noalloc(n, m, _ptr(he_off), _ptr(he_nodes), k, _ptr(picks),
+                                                    _ptr(cov_cum), _ptr(n_picked), _stream(stream)))
 
 
 def centra_mcera(ctx, n: int, he_off, he_nodes, seed: int, instance: int, t: int, k: int, topk_sum, deg_topk,

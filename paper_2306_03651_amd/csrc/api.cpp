@@ -30,6 +30,13 @@ struct DeviceGuard {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// Error of a call without a context (centra_create, the allocation-free
+// greedy): kept per host thread, read with centra_last_error(NULL).
+int fail_free(int code, const char* msg) {
+  g_create_err = msg;
+  return code;
+}
+
 // Writes the Theorem bound_dev quantities (host FP64).
 void bound_eval(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk, uint32_t b_max,
                 double eps, double delta_i, centra_bound_out* o) {
@@ -301,6 +308,17 @@ int centra_greedy_cover(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t*
   if ((rc = greedy_on_incidence(ctx, n, m, he_off, he_nodes, k, picks, cov_cum, n_picked, s))) return rc;
   CENTRA_HIP(ctx, hipStreamSynchronize(s));
   return CENTRA_OK;
+}
+
+int centra_greedy_cover_noalloc(uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes, uint32_t k,
+                                uint32_t* picks, uint64_t* cov_cum, uint32_t* n_picked, void* stream) {
+  g_create_err.clear();
+  if (k == 0) return fail_free(CENTRA_EINVAL, "greedy_cover_noalloc: k == 0");
+  if (n == 0) return fail_free(CENTRA_EINVAL, "greedy_cover_noalloc: n == 0");
+  if (!he_off) return fail_free(CENTRA_EINVAL, "greedy_cover_noalloc: he_off is NULL");
+  if (!picks || !cov_cum || !n_picked) return fail_free(CENTRA_EINVAL, "greedy_cover_noalloc: NULL output");
+  if (m >= (1ull << 31)) return fail_free(CENTRA_ENOTSUP, "greedy_cover_noalloc: m >= 2^31");
+  return greedy_cover_static(n, m, he_off, he_nodes, k, picks, cov_cum, n_picked, as_stream(stream), &g_create_err);
 }
 
 int centra_mcera(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes,

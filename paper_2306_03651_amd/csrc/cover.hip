@@ -24,6 +24,9 @@
 // are integer, so the picks are exactly those of the sequential greedy.
 // The rounds run back to back on the stream; the picked node is read from
 // device memory, so no host round trip happens between rounds.
+#include <mutex>
+#include <string>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -151,6 +154,28 @@ __global__ void k_offset_u64(uint64_t* a, uint64_t n, uint64_t add) {
     a[i] += add;
 }
 
+// Launches the build of one incidence segment: samples [m0, m1) with
+// entries [I0, I1) of he_nodes; its offsets go to `off` (absolute into inc),
+// its degrees to sdeg, and deg accumulates them (cleared first when
+// `first_segment`).  Launches only.
+static void incidence_kernels(uint32_t n, uint64_t m0, uint64_t m1, uint64_t I0, uint64_t I1, const uint64_t* he_off,
+                              const uint32_t* he_nodes, bool first_segment, uint32_t* deg, uint32_t* sdeg, uint64_t* off,
+                              uint64_t* cur, uint32_t* inc, uint32_t* inc_node, uint64_t* scan_tiles, uint32_t* flags,
+                              hipStream_t s) {
+  if (first_segment) fill_u32(deg, 0, n, s);
+  fill_u32(sdeg, 0, n, s);
+  if (I1 > I0)
+    hipLaunchKernelGGL(k_count_deg_agg, dim3(grid_for(I1 - I0, 256, 2048)), dim3(256), 0, s, he_nodes + I0, I1 - I0, n,
+                       sdeg, flags);
+  excl_scan_u32_to_u64_ws(sdeg, off, n, scan_tiles, s);
+  if (I0) hipLaunchKernelGGL(k_offset_u64, dim3(grid_for(uint64_t(n) + 1, 256)), dim3(256), 0, s, off, uint64_t(n) + 1, I0);
+  hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, off, cur, size_t(n));
+  if (m1 > m0)
+    hipLaunchKernelGGL(k_scatter_inc_agg, dim3(grid_for(m1 - m0, 256, 2048)), dim3(256), 0, s, he_off, he_nodes, m0, m1,
+                       n, cur, inc, inc_node);
+  hipLaunchKernelGGL(k_add_u32_to, dim3(grid_for(n, 256)), dim3(256), 0, s, sdeg, n, deg);
+}
+
 int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const uint64_t* he_off,
                     const uint32_t* he_nodes, hipStream_t s) {
   if (m0 == 0 || ctx->inc_nseg >= kMaxSegments) {   // a new sample, or too many segments: start over
@@ -170,23 +195,12 @@ int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const
   if ((rc = ensure(ctx, ctx->inc_cursor, size_t(n) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->inc, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->inc_node, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
-  uint32_t* deg = static_cast<uint32_t*>(ctx->deg.ptr);
-  uint32_t* sdeg = static_cast<uint32_t*>(ctx->seg_deg.ptr);
-  uint64_t* off = static_cast<uint64_t*>(ctx->inc_off.ptr) + size_t(g) * (size_t(n) + 1);
-  uint64_t* cur = static_cast<uint64_t*>(ctx->inc_cursor.ptr);
-  if (g == 0) fill_u32(deg, 0, n, s);
-  fill_u32(sdeg, 0, n, s);
-  if (I1 > I0)
-    hipLaunchKernelGGL(k_count_deg_agg, dim3(grid_for(I1 - I0, 256, 2048)), dim3(256), 0, s, he_nodes + I0, I1 - I0, n,
-                       sdeg, ctx->d_flags);
-  CENTRA_HIP(ctx, hipGetLastError());
-  if ((rc = excl_scan_u32_to_u64(ctx, sdeg, off, n, s))) return rc;
-  if (I0) hipLaunchKernelGGL(k_offset_u64, dim3(grid_for(uint64_t(n) + 1, 256)), dim3(256), 0, s, off, uint64_t(n) + 1, I0);
-  hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, off, cur, size_t(n));
-  if (m1 > m0)
-    hipLaunchKernelGGL(k_scatter_inc_agg, dim3(grid_for(m1 - m0, 256, 2048)), dim3(256), 0, s, he_off, he_nodes, m0, m1,
-                       n, cur, static_cast<uint32_t*>(ctx->inc.ptr), static_cast<uint32_t*>(ctx->inc_node.ptr));
-  hipLaunchKernelGGL(k_add_u32_to, dim3(grid_for(n, 256)), dim3(256), 0, s, sdeg, n, deg);
+  if ((rc = ensure(ctx, ctx->scan_tmp, scan_tile_words(n) * 8, false, s))) return rc;
+  incidence_kernels(n, m0, m1, I0, I1, he_off, he_nodes, g == 0, static_cast<uint32_t*>(ctx->deg.ptr),
+                    static_cast<uint32_t*>(ctx->seg_deg.ptr),
+                    static_cast<uint64_t*>(ctx->inc_off.ptr) + size_t(g) * (size_t(n) + 1),
+                    static_cast<uint64_t*>(ctx->inc_cursor.ptr), static_cast<uint32_t*>(ctx->inc.ptr),
+                    static_cast<uint32_t*>(ctx->inc_node.ptr), static_cast<uint64_t*>(ctx->scan_tmp.ptr), ctx->d_flags, s);
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->inc_nseg = g + 1;
   ctx->inc_m0 = m0;
@@ -294,6 +308,29 @@ __global__ void k_greedy_finish(const uint64_t* best, const uint64_t* newcov, ui
   *n_picked = r;
 }
 
+// Launches greedy's k rounds on an incidence of n_seg segments (offsets
+// seg_off, entries inc, degrees deg): gain u32[n], covered u32[m/32 + 1],
+// best u64[k + kArgGrid] and newcov u64[k] are the round state.  Launches
+// only.
+static void greedy_kernels(uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes, uint32_t k,
+                           const uint32_t* deg, const uint64_t* seg_off, uint32_t n_seg, const uint32_t* inc,
+                           int32_t* gain, uint32_t* cov, uint64_t* best, uint64_t* newcov, uint32_t* picks,
+                           uint64_t* cov_cum, uint32_t* n_picked, hipStream_t s) {
+  hipLaunchKernelGGL(k_gain_init, dim3(grid_for(n, 256)), dim3(256), 0, s, deg, n, gain);
+  fill_u32(cov, 0, (m + 31) / 32 + 1, s);
+  fill_u64(best, 0, k, s);
+  fill_u64(newcov, 0, k, s);
+  const unsigned ga = grid_for(n, kArgBlock, kArgGrid);
+  uint64_t* part = best + k;
+  const unsigned gc = 1024;
+  for (uint32_t r = 0; r < k; ++r) {
+    hipLaunchKernelGGL(k_argmax, dim3(ga), dim3(kArgBlock), 0, s, gain, n, part);
+    hipLaunchKernelGGL(k_cover, dim3(gc), dim3(kCoverBlock), 0, s, part, ga, best + r, seg_off, n_seg, inc, he_off,
+                       he_nodes, n, cov, gain, newcov + r);
+  }
+  hipLaunchKernelGGL(k_greedy_finish, dim3(1), dim3(64), 0, s, best, newcov, k, picks, cov_cum, n_picked);
+}
+
 int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes,
                         uint32_t k, uint32_t* picks, uint64_t* cov_cum, uint32_t* n_picked, hipStream_t s) {
   int rc;
@@ -301,27 +338,116 @@ int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t*
   if ((rc = ensure(ctx, ctx->covered, ((m + 31) / 32 + 1) * 4, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->best, (size_t(k) + kArgGrid) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->newcov, size_t(k) * 8, false, s))) return rc;
-  int32_t* gain = static_cast<int32_t*>(ctx->gain.ptr);
-  uint32_t* cov = static_cast<uint32_t*>(ctx->covered.ptr);
-  uint64_t* best = static_cast<uint64_t*>(ctx->best.ptr);
-  uint64_t* newcov = static_cast<uint64_t*>(ctx->newcov.ptr);
-  hipLaunchKernelGGL(k_gain_init, dim3(grid_for(n, 256)), dim3(256), 0, s, static_cast<const uint32_t*>(ctx->deg.ptr),
-                     n, gain);
-  fill_u32(cov, 0, (m + 31) / 32 + 1, s);
-  fill_u64(best, 0, k, s);
-  fill_u64(newcov, 0, k, s);
-  const unsigned ga = grid_for(n, kArgBlock, kArgGrid);
-  uint64_t* part = best + k;
-  const unsigned gc = 1024;
-  const uint64_t* ioff = static_cast<const uint64_t*>(ctx->inc_off.ptr);
-  const uint32_t* inc = static_cast<const uint32_t*>(ctx->inc.ptr);
-  for (uint32_t r = 0; r < k; ++r) {
-    hipLaunchKernelGGL(k_argmax, dim3(ga), dim3(kArgBlock), 0, s, gain, n, part);
-    hipLaunchKernelGGL(k_cover, dim3(gc), dim3(kCoverBlock), 0, s, part, ga, best + r, ioff, ctx->inc_nseg, inc, he_off,
-                       he_nodes, n, cov, gain, newcov + r);
-  }
-  hipLaunchKernelGGL(k_greedy_finish, dim3(1), dim3(64), 0, s, best, newcov, k, picks, cov_cum, n_picked);
+  greedy_kernels(n, m, he_off, he_nodes, k, static_cast<const uint32_t*>(ctx->deg.ptr),
+                 static_cast<const uint64_t*>(ctx->inc_off.ptr), ctx->inc_nseg,
+                 static_cast<const uint32_t*>(ctx->inc.ptr), static_cast<int32_t*>(ctx->gain.ptr),
+                 static_cast<uint32_t*>(ctx->covered.ptr), static_cast<uint64_t*>(ctx->best.ptr),
+                 static_cast<uint64_t*>(ctx->newcov.ptr), picks, cov_cum, n_picked, s);
   CENTRA_HIP(ctx, hipGetLastError());
+  return CENTRA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Greedy cover without allocation.  Every workspace of one greedy call (the
+// single incidence segment, the round state, the scan tiles and an error
+// word) is carved from `scratch`, a fixed array in device memory that each
+// GPU holds for the life of the process.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): its device address is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes of scratch a greedy call on (n, m, I entries, k) carves.
+size_t static_greedy_bytes(uint32_t n, uint64_t m, uint64_t I, uint32_t k) {
+  const size_t N = n;
+  return align256(4) + align256(N * 4) * 3 + align256((N + 1) * 8) + align256(N * 8) + align256((I ? I : 1) * 4) * 2 +
+         align256(((m + 31) / 32 + 1) * 4) + align256((size_t(k) + kArgGrid) * 8) + align256(size_t(k) * 8) +
+         align256(scan_tile_words(N) * 8);
+}
+
+int greedy_cover_static(uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes, uint32_t k,
+                        uint32_t* picks, uint64_t* cov_cum, uint32_t* n_picked, hipStream_t s, std::string* err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *err = "greedy_cover_noalloc: no current HIP device";
+    return CENTRA_EHIP;
+  }
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        *err = std::string("greedy_cover_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+        return CENTRA_EHIP;
+      }
+      g_scratch_ptr[dev] = p;
+    }
+    base = static_cast<char*>(g_scratch_ptr[dev]);
+  }
+  uint64_t I = 0;
+  if ((e = hipMemcpyAsync(&I, he_off + m, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    *err = std::string("greedy_cover_noalloc: reading he_off[m]: ") + hipGetErrorString(e);
+    return CENTRA_EHIP;
+  }
+  if (I && !he_nodes) {
+    *err = "greedy_cover_noalloc: he_nodes is NULL";
+    return CENTRA_EINVAL;
+  }
+  const size_t need = static_greedy_bytes(n, m, I, k);
+  if (need > kStaticScratchBytes) {
+    *err = "greedy_cover_noalloc: n = " + std::to_string(n) + ", m = " + std::to_string(m) + ", " +
+           std::to_string(I) + " entries and k = " + std::to_string(k) + " need " + std::to_string(need) +
+           " bytes of scratch; the fixed maximum is " + std::to_string(kStaticScratchBytes);
+    return CENTRA_ENOSPC;
+  }
+  const size_t N = n;
+  size_t at = 0;
+  auto carve = [&](size_t bytes) {
+    char* p = base + at;
+    at += align256(bytes);
+    return static_cast<void*>(p);
+  };
+  uint32_t* flags = static_cast<uint32_t*>(carve(4));
+  uint32_t* deg = static_cast<uint32_t*>(carve(N * 4));
+  uint32_t* sdeg = static_cast<uint32_t*>(carve(N * 4));
+  int32_t* gain = static_cast<int32_t*>(carve(N * 4));
+  uint64_t* off = static_cast<uint64_t*>(carve((N + 1) * 8));
+  uint64_t* cur = static_cast<uint64_t*>(carve(N * 8));
+  uint32_t* inc = static_cast<uint32_t*>(carve((I ? I : 1) * 4));
+  uint32_t* inc_node = static_cast<uint32_t*>(carve((I ? I : 1) * 4));
+  uint32_t* cov = static_cast<uint32_t*>(carve(((m + 31) / 32 + 1) * 4));
+  uint64_t* best = static_cast<uint64_t*>(carve((size_t(k) + kArgGrid) * 8));
+  uint64_t* newcov = static_cast<uint64_t*>(carve(size_t(k) * 8));
+  uint64_t* tiles = static_cast<uint64_t*>(carve(scan_tile_words(N) * 8));
+  // the array keeps the previous call's contents: the error word starts at 0
+  // here, and every other region is written before it is read
+  fill_u32(flags, 0, 1, s);
+  incidence_kernels(n, 0, m, 0, I, he_off, he_nodes, true, deg, sdeg, off, cur, inc, inc_node, tiles, flags, s);
+  greedy_kernels(n, m, he_off, he_nodes, k, deg, off, 1, inc, gain, cov, best, newcov, picks, cov_cum, n_picked, s);
+  if ((e = hipGetLastError()) != hipSuccess) {
+    *err = std::string("greedy_cover_noalloc: launch failed: ") + hipGetErrorString(e);
+    return CENTRA_EHIP;
+  }
+  uint32_t f = 0;
+  if ((e = hipMemcpyAsync(&f, flags, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    *err = std::string("greedy_cover_noalloc: ") + hipGetErrorString(e);
+    return CENTRA_EHIP;
+  }
+  if (f & kErrNodeRange) {
+    *err = "greedy_cover_noalloc: hyperedge node id out of range";
+    return CENTRA_EINVAL;
+  }
   return CENTRA_OK;
 }
 

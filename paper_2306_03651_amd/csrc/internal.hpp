@@ -103,6 +103,10 @@ void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
 
 // Exclusive scan of `n` u32 values into `out[0..n]` (u64, out[n] = total).
 int excl_scan_u32_to_u64(centra_ctx* ctx, const uint32_t* in, uint64_t* out, size_t n, hipStream_t s);
+// The same with a caller-provided tile buffer of scan_tile_words(n) u64
+// (launches only; allocates nothing).
+size_t scan_tile_words(size_t n);
+void excl_scan_u32_to_u64_ws(const uint32_t* in, uint64_t* out, size_t n, uint64_t* tile_sums, hipStream_t s);
 
 // Locality relabelling of a validated graph (graph.hip); fills the bfs_*
 // arrays and the id maps of g.
@@ -146,6 +150,14 @@ int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const
 int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
                         const uint32_t* he_nodes, uint32_t k, uint32_t* picks, uint64_t* cov_cum,
                         uint32_t* n_picked, hipStream_t s);
+
+// Greedy cover whose workspaces are carved from a fixed device array of
+// kStaticScratchBytes (cover.hip); allocates nothing.  *err receives the
+// message of a failure.
+constexpr size_t kStaticScratchBytes = CENTRA_NOALLOC_SCRATCH_BYTES;
+size_t static_greedy_bytes(uint32_t n, uint64_t m, uint64_t I, uint32_t k);
+int greedy_cover_static(uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes, uint32_t k,
+                        uint32_t* picks, uint64_t* cov_cum, uint32_t* n_picked, hipStream_t s, std::string* err);
 
 // AMCERA (mcera.hip): Rademacher words for samples [s0, s1) into ctx->words
 // (Wt words per sample), then the per-trial top-k sums on the incidence.

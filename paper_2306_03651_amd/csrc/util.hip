@@ -151,18 +151,23 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tile_write(const uint32_t* 
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = tile_prefix[gridDim.x];
 }
 
-int excl_scan_u32_to_u64(centra_ctx* ctx, const uint32_t* in, uint64_t* out, size_t n, hipStream_t s) {
+size_t scan_tile_words(size_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+void excl_scan_u32_to_u64_ws(const uint32_t* in, uint64_t* out, size_t n, uint64_t* tile_sums, hipStream_t s) {
   if (n == 0) {
     fill_u64(out, 0, 1, s);
-    return CENTRA_OK;
+    return;
   }
   const size_t tiles = (n + kScanTile - 1) / kScanTile;
-  int rc = ensure(ctx, ctx->scan_tmp, (tiles + 1) * sizeof(uint64_t), false, s);
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(kScanBlock), 0, s, in, n, tile_sums);
+  hipLaunchKernelGGL(k_scan_tile_prefix, dim3(1), dim3(kScanBlock), 0, s, tile_sums, tiles);
+  hipLaunchKernelGGL(k_scan_tile_write, dim3(tiles), dim3(kScanBlock), 0, s, in, n, tile_sums, out);
+}
+
+int excl_scan_u32_to_u64(centra_ctx* ctx, const uint32_t* in, uint64_t* out, size_t n, hipStream_t s) {
+  int rc = ensure(ctx, ctx->scan_tmp, scan_tile_words(n) * sizeof(uint64_t), false, s);
   if (rc) return rc;
-  uint64_t* ts = static_cast<uint64_t*>(ctx->scan_tmp.ptr);
-  hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(kScanBlock), 0, s, in, n, ts);
-  hipLaunchKernelGGL(k_scan_tile_prefix, dim3(1), dim3(kScanBlock), 0, s, ts, tiles);
-  hipLaunchKernelGGL(k_scan_tile_write, dim3(tiles), dim3(kScanBlock), 0, s, in, n, ts, out);
+  excl_scan_u32_to_u64_ws(in, out, n, static_cast<uint64_t*>(ctx->scan_tmp.ptr), s);
   CENTRA_HIP(ctx, hipGetLastError());
   return CENTRA_OK;
 }

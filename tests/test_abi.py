@@ -23,7 +23,7 @@ def test_header_declares_the_four_hot_path_calls():
     names = declared_functions()
     for f in ["centra_sample_paths", "centra_greedy_cover", "centra_mcera", "centra_progressive"]:
         assert f in names
-    assert len(names) == 17
+    assert len(names) >= 17
 
 
 def test_library_exports_every_declared_symbol():
@@ -37,7 +37,7 @@ def test_binding_mirrors_header():
 
 
 def test_abi_version():
-    assert binding.centra_abi_version() == 5
+    assert binding.centra_abi_version() == 6
 
 
 CASES = [
