@@ -38,7 +38,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 6u
+#define CENTRA_ABI_VERSION 7u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -386,6 +386,95 @@ typedef struct {
 CENTRA_API int centra_progressive(centra_ctx *ctx, const centra_graph *g, const centra_params *params,
                        uint32_t *picks, centra_result *result, centra_iteration *log,
                        uint32_t log_cap, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* The batching and serving engine: Algorithm 1 (as centra_progressive with
+ * the geometric schedule) for many queries at once, over sample pools kept
+ * resident on the device.
+ *
+ * A pool is one prepared graph with one sample stream (seed, instance) and
+ * one schedule m_0 = m_init, m_{j+1} = min(ceil(m_j growth_num /
+ * growth_den), m_max); it keeps t Rademacher trials.  A query (k, t <= the
+ * pool's t, eps, delta) on a pool runs iteration i = j + 1 at m_j with
+ * delta_i = delta / 2^i, exactly as centra_progressive(k, t, eps, delta,
+ * the pool's seed, instance, m_init, m_max, growth, CENTRA_SCHEDULE_
+ * GEOMETRIC, CENTRA_SPACE_SHORTEST_PATHS) would: the same picks, coverage
+ * and bound values, whatever else runs in the engine (samples and signs
+ * are functions of their indices; the pool draws each sample once and
+ * every query on it reuses it).
+ *
+ * centra_engine_run ticks until every submitted query is done.  A tick
+ * admits the queries that have arrived (in submission order) while the
+ * engine's device memory, pools and active queries, stays within
+ * hbm_budget_bytes (0 = no bound; a query whose state cannot fit even
+ * alone is refused with CENTRA_ENOMEM as its result); draws the samples
+ * every active query's next iteration needs in one fused sampling launch
+ * over all pools; builds the new levels (incidence segment, deg_H and
+ * Rademacher sums of the pool's first m_j samples); runs the greedy rounds
+ * of all active queries fused (one argmax and one covering launch per round
+ * for all queries, replayed from a captured HIP graph unless
+ * CENTRA_ENGINE_NO_GRAPHS); runs their per-trial top-k selections fused;
+ * and evaluates every query's bound on the host (one synchronisation),
+ * retiring certified queries and those at m_max.  realtime != 0: query
+ * arrival times are seconds from the start of the run, admission waits for
+ * them (continuous batching: arrivals join the running queries at the next
+ * tick); realtime == 0: every query has arrived at the start (batch mode).
+ * Admission reserves, for each pool with an active query, the memory of
+ * the pool with every level of its schedule built (projected from the
+ * mean hyperedge size of its first samples, plus a tenth), and each active
+ * query's own state (about 4 n + m_max / 8 bytes); a pool's first samples
+ * are drawn when its first query arrives.
+ * Before the first tick an autotuner times the fused sampling launch with
+ * 64, 128, 256 and 512 threads per BFS on the pools' first samples and
+ * keeps the fastest (CENTRA_ENGINE_NO_TUNE: 128); the environment variable
+ * CENTRA_TUNE_CACHE may name a file that keeps the choice per workload;
+ * centra_engine_log returns the tuner's report.  Synchronous.
+ * Memory: a pool holds its samples, their incidence and per level j the
+ * trial sums (n t 4 bytes) and deg_H; levels no queued or active query can
+ * need are released (a later query on the pool rebuilds them).
+ * Errors: CENTRA_EINVAL (bad argument; t of a query above its pool's;
+ * arrivals out of order), CENTRA_ENOTSUP (a schedule of more than 64
+ * levels), CENTRA_ENOMEM, CENTRA_EHIP. */
+typedef struct centra_engine centra_engine;
+#define CENTRA_ENGINE_NO_GRAPHS 1u
+#define CENTRA_ENGINE_NO_TUNE 2u
+
+typedef struct {
+    uint64_t seed;
+    uint32_t instance;
+    uint32_t t;                        /* Rademacher trials kept, 1..1024 */
+    uint64_t m_init, m_max;            /* 1 <= m_init <= m_max < 2^31 */
+    uint32_t growth_num, growth_den;   /* growth_num > growth_den >= 1 */
+} centra_pool_params;
+
+typedef struct {
+    double arrival_s, admitted_s, finished_s;   /* seconds from the start of the run */
+    uint32_t pool;
+} centra_query_info;
+
+typedef struct {
+    uint64_t ticks, sampler_launches, samples, greedy_launches, graph_replays, graphs_captured;
+    double ms_sample, ms_levels, ms_greedy, ms_select;   /* device time per phase, summed */
+    uint64_t peak_bytes;
+    uint32_t peak_active, tuned_block;
+} centra_engine_stats;
+
+CENTRA_API int centra_engine_create(centra_ctx *ctx, size_t hbm_budget_bytes, uint32_t flags, centra_engine **out);
+CENTRA_API void centra_engine_destroy(centra_engine *e);
+/* The graph must stay prepared while the engine lives. */
+CENTRA_API int centra_engine_add_pool(centra_engine *e, const centra_graph *g, const centra_pool_params *params,
+                           uint32_t *pool_id);
+/* arrival_s must not decrease from one submission to the next. */
+CENTRA_API int centra_engine_submit(centra_engine *e, uint32_t pool_id, uint32_t k, uint32_t t, double eps,
+                         double delta, double arrival_s, uint32_t *query_id);
+CENTRA_API int centra_engine_run(centra_engine *e, int realtime, void *stream);
+/* picks: host u32[k] (res->n_picked written); res, info: host (may be
+ * NULL).  Returns the query's CENTRA_OK / CENTRA_NOT_CERTIFIED, or its
+ * refusal (CENTRA_ENOMEM), or CENTRA_EINVAL if it has not finished. */
+CENTRA_API int centra_engine_result(centra_engine *e, uint32_t query_id, uint32_t *picks, centra_result *res,
+                         centra_query_info *info);
+CENTRA_API int centra_engine_stats_get(centra_engine *e, centra_engine_stats *out);
+CENTRA_API const char *centra_engine_log(const centra_engine *e);
 
 #ifdef __cplusplus
 }

@@ -86,6 +86,28 @@ class SamplerStats(_c.Structure):
                 ("lds_bitmap", _c.c_uint32), ("slots", _c.c_uint32)]
 
 
+class PoolParams(_c.Structure):
+    _fields_ = [("seed", _c.c_uint64), ("instance", _c.c_uint32), ("t", _c.c_uint32), ("m_init", _c.c_uint64),
+                ("m_max", _c.c_uint64), ("growth_num", _c.c_uint32), ("growth_den", _c.c_uint32)]
+
+
+class QueryInfo(_c.Structure):
+    _fields_ = [("arrival_s", _c.c_double), ("admitted_s", _c.c_double), ("finished_s", _c.c_double),
+                ("pool", _c.c_uint32)]
+
+
+class EngineStats(_c.Structure):
+    _fields_ = [("ticks", _c.c_uint64), ("sampler_launches", _c.c_uint64), ("samples", _c.c_uint64),
+                ("greedy_launches", _c.c_uint64), ("graph_replays", _c.c_uint64), ("graphs_captured", _c.c_uint64),
+                ("ms_sample", _c.c_double), ("ms_levels", _c.c_double), ("ms_greedy", _c.c_double),
+                ("ms_select", _c.c_double), ("peak_bytes", _c.c_uint64), ("peak_active", _c.c_uint32),
+                ("tuned_block", _c.c_uint32)]
+
+
+CENTRA_ENGINE_NO_GRAPHS = 1
+CENTRA_ENGINE_NO_TUNE = 2
+
+
 # name -> (restype, argtypes); the names and order are those of centra.h
 SIGNATURES = {
     "centra_abi_version": (_c.c_uint32, []),
@@ -112,6 +134,15 @@ SIGNATURES = {
     "centra_vc_dims": (_c.c_int, [_c.c_uint64, _c.c_uint32, _c.c_uint64, _c.POINTER(VcOut)]),
     "centra_progressive": (_c.c_int, [_vp, _vp, _c.POINTER(Params), _vp, _c.POINTER(Result),
                                       _c.POINTER(Iteration), _c.c_uint32, _vp]),
+    "centra_engine_create": (_c.c_int, [_vp, _c.c_size_t, _c.c_uint32, _c.POINTER(_vp)]),
+    "centra_engine_destroy": (None, [_vp]),
+    "centra_engine_add_pool": (_c.c_int, [_vp, _vp, _c.POINTER(PoolParams), _c.POINTER(_c.c_uint32)]),
+    "centra_engine_submit": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_double, _c.c_double,
+                                        _c.c_double, _c.POINTER(_c.c_uint32)]),
+    "centra_engine_run": (_c.c_int, [_vp, _c.c_int, _vp]),
+    "centra_engine_result": (_c.c_int, [_vp, _c.c_uint32, _vp, _c.POINTER(Result), _c.POINTER(QueryInfo)]),
+    "centra_engine_stats_get": (_c.c_int, [_vp, _c.POINTER(EngineStats)]),
+    "centra_engine_log": (_c.c_char_p, [_vp]),
 }
 
 _lib = None
@@ -371,3 +402,57 @@ def sample_paths(ctx, dg: DeviceGraph, seed: int, instance: int, first: int, cou
     if with_st:
         out = out + (st, dist)
     return out
+
+
+# ---------------------------------------------------------------------------
+class Engine:
+    """The batching and serving engine (centra_engine_*): pools of resident
+    samples and queries run together, tick by tick."""
+
+    def __init__(self, ctx, hbm_budget_bytes: int = 0, flags: int = 0):
+        self.ctx = ctx
+        out = _vp()
+        _check(lib().centra_engine_create(ctx, hbm_budget_bytes, flags, ctypes.byref(out)), ctx)
+        self.handle = out
+        self.ks = []
+
+    def add_pool(self, graph_handle, seed: int, instance: int, t: int, m_init: int, m_max: int,
+                 growth_num: int = 2, growth_den: int = 1) -> int:
+        p = PoolParams(seed, instance, t, m_init, m_max, growth_num, growth_den)
+        pid = ctypes.c_uint32()
+        _check(lib().centra_engine_add_pool(self.handle, graph_handle, ctypes.byref(p), ctypes.byref(pid)), self.ctx)
+        return pid.value
+
+    def submit(self, pool: int, k: int, t: int, eps: float, delta: float, arrival_s: float = 0.0) -> int:
+        q = ctypes.c_uint32()
+        _check(lib().centra_engine_submit(self.handle, pool, k, t, eps, delta, arrival_s, ctypes.byref(q)), self.ctx)
+        while len(self.ks) <= q.value:
+            self.ks.append(0)
+        self.ks[q.value] = k
+        return q.value
+
+    def run(self, realtime: bool = False, stream=None) -> None:
+        _check(lib().centra_engine_run(self.handle, 1 if realtime else 0, _stream(stream)), self.ctx)
+
+    def result(self, qid: int):
+        """Returns (rc, picks np.uint32[n_picked], Result, QueryInfo)."""
+        picks = np.zeros(max(1, self.ks[qid]), dtype=np.uint32)
+        res, info = Result(), QueryInfo()
+        rc = lib().centra_engine_result(self.handle, qid, picks.ctypes.data, ctypes.byref(res), ctypes.byref(info))
+        if rc < 0:
+            raise CentraError(rc, centra_last_error(self.ctx))
+        return rc, picks[: res.n_picked].copy(), res, info
+
+    def stats(self) -> EngineStats:
+        out = EngineStats()
+        _check(lib().centra_engine_stats_get(self.handle, ctypes.byref(out)), self.ctx)
+        return out
+
+    def log(self) -> str:
+        s = lib().centra_engine_log(self.handle)
+        return s.decode() if s else ""
+
+    def destroy(self) -> None:
+        if self.handle:
+            lib().centra_engine_destroy(self.handle)
+            self.handle = None

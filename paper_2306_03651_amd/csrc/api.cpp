@@ -37,6 +37,10 @@ int fail_free(int code, const char* msg) {
   return code;
 }
 
+}  // namespace
+
+namespace centra {
+
 // Writes the Theorem bound_dev quantities (host FP64).
 void bound_eval(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk, uint32_t b_max,
                 double eps, double delta_i, centra_bound_out* o) {
@@ -62,6 +66,10 @@ void bound_eval(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t
   o->eta = eta;
   o->certified = a * ((a - eps) * xi + eta) <= eps * C ? 1 : 0;
 }
+
+}  // namespace centra
+
+namespace {
 
 // Next sample size (samplingSchedule of Algorithm 1): the geometric step,
 // and for the adaptive schedule the optimistic size when larger.  That size
@@ -154,7 +162,7 @@ void centra_destroy(centra_ctx* ctx) {
                     &ctx->stage_len, &ctx->work_ctr, &ctx->scan_tmp, &ctx->deg, &ctx->inc_off,
                     &ctx->inc_cursor, &ctx->inc, &ctx->inc_node, &ctx->gain, &ctx->covered, &ctx->best,
                     &ctx->newcov, &ctx->words, &ctx->P, &ctx->Rtm, &ctx->topk_tmp, &ctx->misc,
-                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len, &ctx->seg_deg};
+                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len, &ctx->seg_deg, &ctx->multi_tab, &ctx->sel_rows};
   for (DevBuf* b : bufs) release(ctx, *b);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   for (auto& ev : ctx->ev)

@@ -158,7 +158,7 @@ __global__ void k_offset_u64(uint64_t* a, uint64_t n, uint64_t add) {
 // entries [I0, I1) of he_nodes; its offsets go to `off` (absolute into inc),
 // its degrees to sdeg, and deg accumulates them (cleared first when
 // `first_segment`).  Launches only.
-static void incidence_kernels(uint32_t n, uint64_t m0, uint64_t m1, uint64_t I0, uint64_t I1, const uint64_t* he_off,
+void incidence_segment(uint32_t n, uint64_t m0, uint64_t m1, uint64_t I0, uint64_t I1, const uint64_t* he_off,
                               const uint32_t* he_nodes, bool first_segment, uint32_t* deg, uint32_t* sdeg, uint64_t* off,
                               uint64_t* cur, uint32_t* inc, uint32_t* inc_node, uint64_t* scan_tiles, uint32_t* flags,
                               hipStream_t s) {
@@ -196,7 +196,7 @@ int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const
   if ((rc = ensure(ctx, ctx->inc, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->inc_node, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->scan_tmp, scan_tile_words(n) * 8, false, s))) return rc;
-  incidence_kernels(n, m0, m1, I0, I1, he_off, he_nodes, g == 0, static_cast<uint32_t*>(ctx->deg.ptr),
+  incidence_segment(n, m0, m1, I0, I1, he_off, he_nodes, g == 0, static_cast<uint32_t*>(ctx->deg.ptr),
                     static_cast<uint32_t*>(ctx->seg_deg.ptr),
                     static_cast<uint64_t*>(ctx->inc_off.ptr) + size_t(g) * (size_t(n) + 1),
                     static_cast<uint64_t*>(ctx->inc_cursor.ptr), static_cast<uint32_t*>(ctx->inc.ptr),
@@ -219,63 +219,69 @@ constexpr int kArgBlock = 256;
 
 constexpr unsigned kArgGrid = 512;   // workgroups of the argmax (and per-workgroup maxima)
 
-// part[b] = the largest key of the slice of workgroup b (0 if the slice has
-// no positive gain)
-__global__ __launch_bounds__(kArgBlock) void k_argmax(const int32_t* gain, uint32_t n, uint64_t* part) {
-  __shared__ uint64_t red[kArgBlock / kWave];
+// The largest key (gain << 32 | ~u, 0 if no positive gain) of the slice
+// of workgroup b of nb: nodes b*kArgBlock + i*nb*kArgBlock.
+__device__ __forceinline__ uint64_t argmax_slice(const int32_t* gain, uint32_t n, uint32_t b, uint32_t nb,
+                                                 uint64_t* red) {
   uint64_t key = 0;
-  for (uint32_t u = blockIdx.x * kArgBlock + threadIdx.x; u < n; u += gridDim.x * kArgBlock) {
+  for (uint32_t u = b * kArgBlock + threadIdx.x; u < n; u += nb * kArgBlock) {
     const int32_t g = gain[u];
     const uint64_t k = g > 0 ? (static_cast<uint64_t>(g) << 32) | (0xFFFFFFFFu - u) : 0ull;
     key = k > key ? k : key;
   }
-  key = block_max_u64<kArgBlock>(key, red);
+  return block_max_u64<kArgBlock>(key, red);
+}
+
+// part[b] = the largest key of the slice of workgroup b (0 if the slice has
+// no positive gain)
+__global__ __launch_bounds__(kArgBlock) void k_argmax(const int32_t* gain, uint32_t n, uint64_t* part) {
+  __shared__ uint64_t red[kArgBlock / kWave];
+  const uint64_t key = argmax_slice(gain, n, blockIdx.x, gridDim.x, red);
   if (threadIdx.x == 0) part[blockIdx.x] = key;
 }
 
 constexpr int kCoverBlock = 256;
 
-// best = the round's pick (written by workgroup 0): the largest of the
-// n_part per-workgroup maxima of the argmax.  The picked node's rows in the
-// n_seg incidence segments are walked as one row (their concatenation), so
-// the workgroups share it as they would a single segment's.
-__global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* part, uint32_t n_part, uint64_t* best,
-                                                       const uint64_t* seg_off, uint32_t n_seg, const uint32_t* inc,
-                                                       const uint64_t* he_off, const uint32_t* he_nodes, uint32_t n,
-                                                       uint32_t* covered, int32_t* gain, uint64_t* newcov) {
-  __shared__ uint64_t red[kCoverBlock / kWave];
-  __shared__ AggTable tab;
-  __shared__ uint64_t seg_beg[kMaxSegments], seg_pre[kMaxSegments + 1];
+// One covering pass, workgroup b of nb: reduces the n_part per-workgroup
+// maxima to the round's pick (workgroup 0 writes it to *best), then walks
+// its share of the pick's incidence rows in the n_seg segments as one row
+// (their concatenation), marking newly covered samples and decrementing
+// the gains of their nodes.
+__device__ __forceinline__ void cover_pass(const uint64_t* part, uint32_t n_part, uint64_t* best, const uint64_t* seg_off,
+                                           uint32_t n_seg, const uint32_t* inc, const uint64_t* he_off,
+                                           const uint32_t* he_nodes, uint32_t n, uint32_t* covered, int32_t* gain,
+                                           uint64_t* newcov, uint32_t b, uint32_t nb, uint64_t* red, AggTable& tab,
+                                           uint64_t* seg_beg, uint64_t* seg_pre) {
   uint64_t key = 0;
   for (uint32_t i = threadIdx.x; i < n_part; i += kCoverBlock) key = part[i] > key ? part[i] : key;
   key = block_max_u64<kCoverBlock>(key, red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *best = key;
+  if (b == 0 && threadIdx.x == 0) *best = key;
   if ((key >> 32) == 0) return;
   const uint32_t u = 0xFFFFFFFFu - static_cast<uint32_t>(key);
   if (threadIdx.x < kWave) {   // segment starts and the prefix of the row lengths (n_seg <= 64)
     const uint32_t g = threadIdx.x;
-    uint64_t b = 0, len = 0;
+    uint64_t rb = 0, len = 0;
     if (g < n_seg) {
       const uint64_t* o = seg_off + size_t(g) * (size_t(n) + 1);
-      b = o[u];
-      len = o[u + 1] - b;
+      rb = o[u];
+      len = o[u + 1] - rb;
     }
     const uint64_t incl = wave_incl_scan_u64(len);
     if (g < n_seg) {
-      seg_beg[g] = b;
+      seg_beg[g] = rb;
       seg_pre[g + 1] = incl;
     }
     if (g == 0) seg_pre[0] = 0;
   }
   __syncthreads();
   const uint64_t row = seg_pre[n_seg];
-  const uint64_t lead = blockIdx.x * uint64_t(kCoverBlock);
+  const uint64_t lead = b * uint64_t(kCoverBlock);
   if (lead >= row) return;   // uniform per workgroup: nothing of the row lands here
   agg_init(tab);
   __syncthreads();
   uint64_t cnt = 0;
   uint32_t g = 0;
-  for (uint64_t q = lead + threadIdx.x; q < row; q += uint64_t(gridDim.x) * kCoverBlock) {
+  for (uint64_t q = lead + threadIdx.x; q < row; q += uint64_t(nb) * kCoverBlock) {
     while (q >= seg_pre[g + 1]) ++g;
     const uint32_t s = inc[seg_beg[g] + (q - seg_pre[g])];
     const uint32_t bit = 1u << (s & 31u);
@@ -292,6 +298,104 @@ __global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* part, uin
     if (tab.key[i] != kUnseen) atomicSub(&gain[tab.key[i]], static_cast<int32_t>(tab.cnt[i]));
   if (threadIdx.x == 0 && cnt) atomicAdd(reinterpret_cast<unsigned long long*>(newcov), cnt);
 }
+
+// best = the round's pick (written by workgroup 0): the largest of the
+// n_part per-workgroup maxima of the argmax.
+__global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* part, uint32_t n_part, uint64_t* best,
+                                                       const uint64_t* seg_off, uint32_t n_seg, const uint32_t* inc,
+                                                       const uint64_t* he_off, const uint32_t* he_nodes, uint32_t n,
+                                                       uint32_t* covered, int32_t* gain, uint64_t* newcov) {
+  __shared__ uint64_t red[kCoverBlock / kWave];
+  __shared__ AggTable tab;
+  __shared__ uint64_t seg_beg[kMaxSegments], seg_pre[kMaxSegments + 1];
+  cover_pass(part, n_part, best, seg_off, n_seg, inc, he_off, he_nodes, n, covered, gain, newcov, blockIdx.x, gridDim.x,
+             red, tab, seg_beg, seg_pre);
+}
+
+// ---------------------------------------------------------------------------
+// Greedy of many queries at once (the engine's fused rounds): blockIdx.y
+// selects the query's descriptor; a query whose k is reached, or that is
+// inactive (k = 0), leaves its workgroups at once.  The round number comes
+// from device memory (round_base[0] + r_local), so a captured sequence of
+// rounds can be replayed for the next rounds after the base is advanced.
+__global__ __launch_bounds__(256) void k_greedy_init_multi(const GreedyDesc* d) {
+  const GreedyDesc q = d[blockIdx.y];
+  if (q.k == 0) return;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  const uint64_t i0 = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
+  for (uint64_t u = i0; u < q.n; u += stride) q.gain[u] = static_cast<int32_t>(q.deg[u]);
+  for (uint64_t w = i0; w < (q.m + 31) / 32 + 1; w += stride) q.covered[w] = 0;
+  for (uint64_t r = i0; r < q.k; r += stride) {
+    q.best[r] = 0;
+    q.newcov[r] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kArgBlock) void k_argmax_multi(const GreedyDesc* d, const uint32_t* round_base,
+                                                            uint32_t r_local) {
+  __shared__ uint64_t red[kArgBlock / kWave];
+  const GreedyDesc& q = d[blockIdx.y];
+  const uint32_t r = round_base[0] + r_local;
+  if (r >= q.k) return;
+  const uint64_t key = argmax_slice(q.gain, q.n, blockIdx.x, gridDim.x, red);
+  if (threadIdx.x == 0) q.part[blockIdx.x] = key;
+}
+
+__global__ __launch_bounds__(kCoverBlock) void k_cover_multi(const GreedyDesc* d, uint32_t n_part,
+                                                             const uint32_t* round_base, uint32_t r_local) {
+  __shared__ uint64_t red[kCoverBlock / kWave];
+  __shared__ AggTable tab;
+  __shared__ uint64_t seg_beg[kMaxSegments], seg_pre[kMaxSegments + 1];
+  const GreedyDesc& q = d[blockIdx.y];
+  const uint32_t r = round_base[0] + r_local;
+  if (r >= q.k) return;
+  // stop early when the previous round found no positive gain
+  if (r > 0 && (q.best[r - 1] >> 32) == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) q.best[r] = 0;
+    return;
+  }
+  cover_pass(q.part, n_part, q.best + r, q.seg_off, q.n_seg, q.inc, q.he_off, q.he_nodes, q.n, q.covered, q.gain,
+             q.newcov + r, blockIdx.x, gridDim.x, red, tab, seg_beg, seg_pre);
+}
+
+__global__ void k_round_advance(uint32_t* round_base, uint32_t by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) round_base[0] += by;
+}
+
+__global__ void k_greedy_finish_multi(const GreedyDesc* d) {
+  const GreedyDesc& q = d[blockIdx.x];
+  if (q.k == 0 || threadIdx.x != 0) return;
+  uint64_t cov = 0;
+  uint32_t r = 0;
+  for (; r < q.k; ++r) {
+    const uint64_t key = q.best[r];
+    if ((key >> 32) == 0) break;
+    cov += q.newcov[r];
+    q.picks[r] = 0xFFFFFFFFu - static_cast<uint32_t>(key);
+    q.cov_cum[r] = cov;
+  }
+  *q.n_picked = r;
+}
+
+void greedy_multi_init(const GreedyDesc* d, uint32_t n_q, uint32_t max_n, hipStream_t s) {
+  hipLaunchKernelGGL(k_greedy_init_multi, dim3(grid_for(max_n, 256, 1024), n_q), dim3(256), 0, s, d);
+}
+
+void greedy_multi_rounds(const GreedyDesc* d, uint32_t n_q, uint32_t max_n, uint32_t cover_grid, uint32_t* round_base,
+                         uint32_t rounds, hipStream_t s) {
+  const unsigned ga = grid_for(max_n, kArgBlock, kArgGrid);
+  for (uint32_t r = 0; r < rounds; ++r) {
+    hipLaunchKernelGGL(k_argmax_multi, dim3(ga, n_q), dim3(kArgBlock), 0, s, d, round_base, r);
+    hipLaunchKernelGGL(k_cover_multi, dim3(cover_grid, n_q), dim3(kCoverBlock), 0, s, d, ga, round_base, r);
+  }
+  hipLaunchKernelGGL(k_round_advance, dim3(1), dim3(64), 0, s, round_base, rounds);
+}
+
+void greedy_multi_finish(const GreedyDesc* d, uint32_t n_q, hipStream_t s) {
+  hipLaunchKernelGGL(k_greedy_finish_multi, dim3(n_q), dim3(64), 0, s, d);
+}
+
+uint32_t greedy_part_words() { return kArgGrid; }
 
 __global__ void k_greedy_finish(const uint64_t* best, const uint64_t* newcov, uint32_t k, uint32_t* picks,
                                 uint64_t* cov_cum, uint32_t* n_picked) {
@@ -432,7 +536,7 @@ int greedy_cover_static(uint32_t n, uint64_t m, const uint64_t* he_off, const ui
   // the array keeps the previous call's contents: the error word starts at 0
   // here, and every other region is written before it is read
   fill_u32(flags, 0, 1, s);
-  incidence_kernels(n, 0, m, 0, I, he_off, he_nodes, true, deg, sdeg, off, cur, inc, inc_node, tiles, flags, s);
+  incidence_segment(n, 0, m, 0, I, he_off, he_nodes, true, deg, sdeg, off, cur, inc, inc_node, tiles, flags, s);
   greedy_kernels(n, m, he_off, he_nodes, k, deg, off, 1, inc, gain, cov, best, newcov, picks, cov_cum, n_picked, s);
   if ((e = hipGetLastError()) != hipSuccess) {
     *err = std::string("greedy_cover_noalloc: launch failed: ") + hipGetErrorString(e);

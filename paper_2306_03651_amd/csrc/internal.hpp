@@ -33,7 +33,7 @@ struct centra_ctx {
   uint32_t slot_n = 0;
   uint32_t stamp_next = 1;   // BFS stamp of the next sample (records start at stamp 0)
   // sampling staging area
-  centra::DevBuf stage_nodes, stage_pos, stage_len, work_ctr;
+  centra::DevBuf stage_nodes, stage_pos, stage_len, work_ctr, multi_tab;
   // scan scratch
   centra::DevBuf scan_tmp;
   // incidence (node -> samples) and greedy / AMCERA workspaces
@@ -41,7 +41,7 @@ struct centra_ctx {
   uint32_t inc_nseg = 0;              // incidence segments held in inc_off / inc / inc_node
   uint64_t inc_m0 = 0;                // first sample of the newest segment (0: it holds every sample)
   uint64_t inc_I0 = 0, inc_I1 = 0;    // entry range of the newest segment
-  centra::DevBuf words, P, Rtm, topk_tmp, misc;
+  centra::DevBuf words, P, Rtm, topk_tmp, misc, sel_rows;
   // sample store of centra_progressive
   centra::DevBuf store_off, store_nodes;
   centra::DevBuf kp_len;   // kappa-path walk lengths
@@ -138,6 +138,18 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
                     uint64_t* total, hipStream_t s);
 int stage_to_output(centra_ctx* ctx, uint32_t count, uint64_t base, uint64_t* he_off,
                     uint32_t* he_nodes, hipStream_t s);
+// A fused sampling launch over several graphs: item i draws samples
+// [first, first + count) of (g, seed, instance); the staging area holds
+// them item after item.  block: threads per BFS (64, 128, 256 or 512).
+struct MultiSampleItem {
+  const centra_graph* g;
+  uint64_t seed;
+  uint32_t instance;
+  uint64_t first;
+  uint32_t count;
+};
+int sample_multi_to_stage(centra_ctx* ctx, const MultiSampleItem* items, uint32_t n_items, int block,
+                          uint64_t* total, hipStream_t s);
 
 // Incidence + greedy (cover.hip).  Builds deg/inc_off/inc/inc_node in the
 // context for a sample of m hyperedges.
@@ -159,6 +171,55 @@ size_t static_greedy_bytes(uint32_t n, uint64_t m, uint64_t I, uint32_t k);
 int greedy_cover_static(uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes, uint32_t k,
                         uint32_t* picks, uint64_t* cov_cum, uint32_t* n_picked, hipStream_t s, std::string* err);
 
+// Fused greedy of many queries (cover.hip): one descriptor per query, read
+// by blockIdx.y.  A query with k = 0 is inactive.
+struct GreedyDesc {
+  int32_t* gain;            // u32[n] round state
+  uint32_t* covered;        // u32[m/32 + 1]
+  uint64_t* part;           // u64[greedy_part_words()]
+  uint64_t* best;           // u64[k]
+  uint64_t* newcov;         // u64[k]
+  const uint32_t* deg;      // deg_H over the query's sample
+  const uint64_t* seg_off;  // incidence segments (n_seg of n + 1 offsets)
+  const uint32_t* inc;
+  const uint64_t* he_off;
+  const uint32_t* he_nodes;
+  uint32_t* picks;          // outputs: u32[k], u64[k], u32[1]
+  uint64_t* cov_cum;
+  uint32_t* n_picked;
+  uint64_t m;
+  uint32_t n, n_seg, k, pad;
+};
+uint32_t greedy_part_words();
+void greedy_multi_init(const GreedyDesc* d, uint32_t n_q, uint32_t max_n, hipStream_t s);
+// Launches `rounds` rounds (round numbers round_base[0] .. + rounds - 1),
+// then advances round_base[0] by `rounds` on the device.
+void greedy_multi_rounds(const GreedyDesc* d, uint32_t n_q, uint32_t max_n, uint32_t cover_grid, uint32_t* round_base,
+                         uint32_t rounds, hipStream_t s);
+void greedy_multi_finish(const GreedyDesc* d, uint32_t n_q, hipStream_t s);
+// Launch-only incidence build of one segment (cover.hip).
+void incidence_segment(uint32_t n, uint64_t m0, uint64_t m1, uint64_t I0, uint64_t I1, const uint64_t* he_off,
+                       const uint32_t* he_nodes, bool first_segment, uint32_t* deg, uint32_t* sdeg, uint64_t* off,
+                       uint64_t* cur, uint32_t* inc, uint32_t* inc_node, uint64_t* scan_tiles, uint32_t* flags,
+                       hipStream_t s);
+
+// Top-k sums of many rows at once (mcera.hip): the sum of the k largest
+// positive values of each row, written to *out (as i64).
+struct SelRow {
+  const int32_t* vals;
+  uint32_t n, k;
+  int64_t* out;
+};
+size_t select_ws_bytes(uint32_t n_rows);
+void select_topk_rows(const SelRow* rows, uint32_t n_rows, uint32_t max_n, void* ws, hipStream_t s);
+// Launch-only AMCERA steps (mcera.hip).
+void rade_words_launch(uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1, uint32_t t, uint64_t* words,
+                       hipStream_t s);
+void rade_count_launch(const uint32_t* inc, const uint32_t* inc_node, uint64_t I0, uint64_t I1, const uint64_t* words,
+                       uint32_t t, int32_t* P, hipStream_t s);
+void rade_finish_launch(const int32_t* P, const uint32_t* deg, uint32_t n, uint32_t t, int32_t* Rtm, hipStream_t s);
+void bmax_launch(const uint64_t* he_off, uint64_t m0, uint64_t m1, uint32_t* b_max, hipStream_t s);
+
 // AMCERA (mcera.hip): Rademacher words for samples [s0, s1) into ctx->words
 // (Wt words per sample), then the per-trial top-k sums on the incidence.
 int rade_words(centra_ctx* ctx, uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1,
@@ -170,6 +231,10 @@ int rade_words(centra_ctx* ctx, uint64_t seed, uint32_t instance, uint64_t s0, u
 int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, uint32_t t,
                        uint32_t k, int64_t* topk_sum, uint64_t* deg_topk, uint32_t* b_max,
                        int32_t* R_out, hipStream_t s);
+
+// Theorem bound_dev and the stopping condition (host FP64, api.cpp).
+void bound_eval(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk, uint32_t b_max,
+                double eps, double delta_i, centra_bound_out* o);
 
 // Device flag word: read (after synchronising `s`) and clear.
 int check_flags(centra_ctx* ctx, hipStream_t s, const char* where);

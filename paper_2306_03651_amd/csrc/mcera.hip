@@ -24,6 +24,8 @@
 // row's global histogram with atomics (a row on one workgroup would leave
 // most CUs idle and serialise on a few LDS bins); a one-wave kernel per row
 // then picks the digit with a wave scan and clears the histogram.
+#include <vector>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -152,31 +154,32 @@ struct SelState {
   int64_t acc;
 };
 
-__device__ __forceinline__ const int32_t* sel_row(const int32_t* Rtm, const uint32_t* deg, uint32_t n, uint32_t t,
-                                                  uint32_t r) {
-  return r < t ? Rtm + uint64_t(r) * n : reinterpret_cast<const int32_t*>(deg);
-}
-
-__global__ void k_sel_init(SelState* st, uint32_t rows, uint32_t k, uint32_t* hcnt, uint64_t* hsum) {
-  const uint64_t nb = uint64_t(rows) * kBins;
+__global__ void k_sel_init(SelState* st, const SelRow* rows, uint32_t n_rows, uint32_t* hcnt, uint64_t* hsum) {
+  const uint64_t nb = uint64_t(n_rows) * kBins;
   for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < nb; i += uint64_t(gridDim.x) * blockDim.x) {
     hcnt[i] = 0;
     hsum[i] = 0;
-    if (i < rows) st[i] = SelState{1, 1, 0, k, k == 0 ? 1u : 0u, 0, 0};
+    if (i < n_rows) {
+      const uint32_t k = rows[i].k;
+      st[i] = SelState{1, 1, 0, k, k == 0 ? 1u : 0u, 0, 0};
+    }
   }
 }
 
 // Pass `first`: bit lengths (bins 1..31) of the positive values; else the
 // next digit of the values matching the row's prefix.  Block (x, r) takes
-// values [x chunk, (x+1) chunk) of row r.
-__global__ __launch_bounds__(kSelBlock) void k_sel_hist(const int32_t* Rtm, const uint32_t* deg, uint32_t n,
-                                                        uint32_t t, uint32_t chunk, const SelState* st, int first,
+// values [x chunk, (x+1) chunk) of row r, chunk = ceil(n_r / gridDim.x).
+__global__ __launch_bounds__(kSelBlock) void k_sel_hist(const SelRow* rows, const SelState* st, int first,
                                                         uint32_t* hcnt, uint64_t* hsum) {
   __shared__ uint32_t cnt[kBins];
   __shared__ uint64_t sum[kBins];
   const uint32_t r = blockIdx.y;
   const SelState s = st[r];
   if (s.done) return;
+  const SelRow d = rows[r];
+  const uint64_t chunk = (uint64_t(d.n) + gridDim.x - 1) / gridDim.x;
+  const uint64_t i0 = uint64_t(blockIdx.x) * chunk;
+  if (i0 >= d.n) return;
   const uint32_t B = s.blen, up = B - s.pbits;
   const uint32_t nb = first ? 5u : (up < uint32_t(kDigitBits) ? up : uint32_t(kDigitBits));
   const uint32_t shift = first ? 0u : up - nb;
@@ -186,9 +189,8 @@ __global__ __launch_bounds__(kSelBlock) void k_sel_hist(const int32_t* Rtm, cons
     sum[b] = 0;
   }
   __syncthreads();
-  const int32_t* row = sel_row(Rtm, deg, n, t, r);
-  const uint64_t i0 = uint64_t(blockIdx.x) * chunk;
-  const uint64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+  const int32_t* row = d.vals;
+  const uint64_t i1 = i0 + chunk < d.n ? i0 + chunk : d.n;
   for (uint64_t i = i0 + threadIdx.x; i < i1; i += kSelBlock) {
     const int32_t x = row[i];
     if (x <= 0) continue;
@@ -306,13 +308,62 @@ __global__ __launch_bounds__(kBmaxBlock) void k_bmax(const uint64_t* he_off, uin
   }
 }
 
-__global__ void k_mcera_out(const SelState* st, uint32_t t, int64_t* topk_sum, uint64_t* deg_topk) {
-  for (uint32_t j = threadIdx.x; j <= t; j += blockDim.x) {
-    if (j < t)
-      topk_sum[j] = st[j].acc;
-    else
-      *deg_topk = static_cast<uint64_t>(st[t].acc);
+__global__ void k_sel_out(const SelState* st, const SelRow* rows, uint32_t n_rows) {
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rows; r += gridDim.x * blockDim.x)
+    if (rows[r].out) *rows[r].out = st[r].acc;
+}
+
+size_t select_ws_bytes(uint32_t n_rows) { return size_t(n_rows) * (sizeof(SelState) + kBins * 12); }
+
+// The sum of the k largest positive values of every row (rows[r].k, 0 if
+// there are none; rows[r].out receives it): MSD radix selection, each pass
+// spread over about 2,048 workgroups.
+void select_topk_rows(const SelRow* rows, uint32_t n_rows, uint32_t max_n, void* ws, hipStream_t s) {
+  SelState* st = static_cast<SelState*>(ws);
+  uint64_t* hsum = reinterpret_cast<uint64_t*>(st + n_rows);
+  uint32_t* hcnt = reinterpret_cast<uint32_t*>(hsum + size_t(n_rows) * kBins);
+  // about 2,048 workgroups per histogram pass, at least 4,096 values each
+  uint32_t parts = 2048 / n_rows ? 2048 / n_rows : 1u;
+  const uint32_t max_parts = (max_n + 4095) / 4096 ? (max_n + 4095) / 4096 : 1u;
+  if (parts > max_parts) parts = max_parts;
+  hipLaunchKernelGGL(k_sel_init, dim3(grid_for(uint64_t(n_rows) * kBins, 256)), dim3(256), 0, s, st, rows, n_rows, hcnt,
+                     hsum);
+  for (int pass = 0; pass <= kDigitPasses; ++pass) {
+    hipLaunchKernelGGL(k_sel_hist, dim3(parts, n_rows), dim3(kSelBlock), 0, s, rows, st, pass == 0 ? 1 : 0, hcnt, hsum);
+    hipLaunchKernelGGL(k_sel_decide, dim3(n_rows), dim3(kWave), 0, s, st, pass == 0 ? 1 : 0, hcnt, hsum);
   }
+  hipLaunchKernelGGL(k_sel_out, dim3(grid_for(n_rows, 256, 64)), dim3(256), 0, s, st, rows, n_rows);
+}
+
+// Launch-only steps of the AMCERA for callers that own their buffers.
+void rade_words_launch(uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1, uint32_t t, uint64_t* words,
+                       hipStream_t s) {
+  const uint32_t Wt = (t + 63) / 64;
+  if (s1 > s0)
+    hipLaunchKernelGGL(k_rade_words, dim3(grid_for((s1 - s0) * ((Wt + 3) / 4), 256)), dim3(256), 0, s, seed, instance,
+                       s0, s1, Wt, words);
+}
+
+void rade_count_launch(const uint32_t* inc, const uint32_t* inc_node, uint64_t I0, uint64_t I1, const uint64_t* words,
+                       uint32_t t, int32_t* P, hipStream_t s) {
+  const uint32_t Wt = (t + 63) / 64;
+  if (I1 > I0) {
+    const uint64_t waves = (I1 - I0 + kSpan - 1) / kSpan;
+    const uint64_t blocks = (waves * kWave + kCountBlock - 1) / kCountBlock;
+    hipLaunchKernelGGL(k_rade_count, dim3(static_cast<unsigned>(blocks), Wt), dim3(kCountBlock), 0, s, inc + I0,
+                       inc_node + I0, I1 - I0, words, Wt, t, P);
+  }
+}
+
+void rade_finish_launch(const int32_t* P, const uint32_t* deg, uint32_t n, uint32_t t, int32_t* Rtm, hipStream_t s) {
+  hipLaunchKernelGGL(k_rade_finish, dim3((n + 63) / 64, (t + 63) / 64), dim3(256), 0, s, P, deg, n, t, Rtm,
+                     static_cast<int32_t*>(nullptr));
+}
+
+void bmax_launch(const uint64_t* he_off, uint64_t m0, uint64_t m1, uint32_t* b_max, hipStream_t s) {
+  if (m1 > m0)
+    hipLaunchKernelGGL(k_bmax, dim3(grid_for(m1 - m0, kBmaxBlock, 512)), dim3(kBmaxBlock), 0, s, he_off + m0, m1 - m0,
+                       b_max);
 }
 
 int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, uint32_t t, uint32_t k,
@@ -324,12 +375,10 @@ int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* 
   if ((rc = ensure(ctx, ctx->P, size_t(n) * t * 4, m0 > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->Rtm, size_t(n) * t * 4, false, s))) return rc;
   const uint32_t rows = t + 1;
-  if ((rc = ensure(ctx, ctx->topk_tmp, size_t(rows) * (sizeof(SelState) + kBins * 12), false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->topk_tmp, select_ws_bytes(rows), false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->sel_rows, size_t(rows) * sizeof(SelRow), false, s))) return rc;
   int32_t* P = static_cast<int32_t*>(ctx->P.ptr);
   int32_t* Rtm = static_cast<int32_t*>(ctx->Rtm.ptr);
-  SelState* st = static_cast<SelState*>(ctx->topk_tmp.ptr);
-  uint64_t* hsum = reinterpret_cast<uint64_t*>(st + rows);
-  uint32_t* hcnt = reinterpret_cast<uint32_t*>(hsum + size_t(rows) * kBins);
   if (m0 == 0) fill_u32(reinterpret_cast<uint32_t*>(P), 0, size_t(n) * t, s);
   if (I1 > I0) {
     const uint64_t waves = (I1 - I0 + kSpan - 1) / kSpan;
@@ -341,21 +390,14 @@ int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* 
   }
   hipLaunchKernelGGL(k_rade_finish, dim3((n + 63) / 64, (t + 63) / 64), dim3(256), 0, s, P,
                      static_cast<const uint32_t*>(ctx->deg.ptr), n, t, Rtm, R_out);
-  // selection: about 2,048 workgroups per histogram pass, at least 4,096
-  // values each
-  const uint32_t* degp = static_cast<const uint32_t*>(ctx->deg.ptr);
-  uint32_t parts = 2048 / rows ? 2048 / rows : 1u;
-  const uint32_t max_parts = (n + 4095) / 4096 ? (n + 4095) / 4096 : 1u;
-  if (parts > max_parts) parts = max_parts;
-  const uint32_t chunk = (n + parts - 1) / parts ? (n + parts - 1) / parts : 1u;
-  hipLaunchKernelGGL(k_sel_init, dim3(grid_for(uint64_t(rows) * kBins, 256)), dim3(256), 0, s, st, rows, k, hcnt,
-                     hsum);
-  for (int pass = 0; pass <= kDigitPasses; ++pass) {
-    hipLaunchKernelGGL(k_sel_hist, dim3(parts, rows), dim3(kSelBlock), 0, s, Rtm, degp, n, t, chunk, st,
-                       pass == 0 ? 1 : 0, hcnt, hsum);
-    hipLaunchKernelGGL(k_sel_decide, dim3(rows), dim3(kWave), 0, s, st, pass == 0 ? 1 : 0, hcnt, hsum);
-  }
-  hipLaunchKernelGGL(k_mcera_out, dim3(1), dim3(256), 0, s, st, t, topk_sum, deg_topk);
+  // selection over the t trial rows and the degree row
+  std::vector<SelRow> hr(rows);
+  for (uint32_t j = 0; j < t; ++j) hr[j] = SelRow{Rtm + size_t(j) * n, n, k, topk_sum + j};
+  hr[t] = SelRow{static_cast<const int32_t*>(ctx->deg.ptr), n, k, reinterpret_cast<int64_t*>(deg_topk)};
+  SelRow* drows = static_cast<SelRow*>(ctx->sel_rows.ptr);
+  CENTRA_HIP(ctx, hipMemcpyAsync(drows, hr.data(), size_t(rows) * sizeof(SelRow), hipMemcpyHostToDevice, s));
+  select_topk_rows(drows, rows, n, ctx->topk_tmp.ptr, s);
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));   // hr is read by the copy above
   if (m0 == 0) fill_u32(b_max, 0, 1, s);
   if (m > m0)
     hipLaunchKernelGGL(k_bmax, dim3(grid_for(m - m0, kBmaxBlock, 512)), dim3(kBmaxBlock), 0, s, he_off + m0, m - m0,

@@ -72,11 +72,27 @@
 #include <string.h>
 
 #include <type_traits>
+#include <vector>
 
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace centra {
+
+// One graph's share of a fused launch over several sample pools: the
+// graph's arrays and counts, the stream of its samples, and the global
+// sample index of its first work item.
+struct SampleInst {
+  uint32_t n, c_bits, max_out_deg, instance;
+  const uint32_t* row_ptr;
+  const uint32_t* col_idx;
+  const uint32_t* in_ptr;
+  const uint32_t* in_idx;
+  const uint32_t* new_of;
+  const uint32_t* orig_of;
+  uint64_t seed;
+  uint64_t first;
+};
 
 struct SampleArgs {
   uint32_t n;
@@ -108,6 +124,12 @@ struct SampleArgs {
   uint32_t* dist_out;    // optional
   uint32_t* flags;
   uint64_t* stats;       // [0] arcs scanned, [1] nodes visited (accumulated)
+  uint64_t slot_stride;  // nodes per slot in rec and q (>= every graph's n)
+  // fused launches only: work items [item_off[j], item_off[j+1]) belong to
+  // inst[j], j < n_inst (the fields above then describe no graph)
+  const SampleInst* inst;
+  const uint32_t* item_off;
+  uint32_t n_inst;
 };
 
 // Ring limits: t with at most Ring<BLOCK>::kCache in-neighbours gets the
@@ -392,16 +414,22 @@ __device__ __forceinline__ int ring_of(const uint32_t* poff, uint32_t dt, uint32
 // Up to 512 threads the kernel is held to 5 waves per SIMD (at most 96
 // VGPRs, a few bytes of spill): more resident BFSs hide more of the latency
 // of their dependent random accesses than the spill costs.
-template <int BLOCK, int UNROLL, bool LDS_BITS>
+//
+// MULTI: a fused launch over several graphs (sample pools).  Each work
+// item's graph is looked up in the instance table and its arguments are
+// placed in LDS, from where the BFS reads them; every other step is the
+// same, so each hyperedge equals that of a launch on its graph alone.
+template <int BLOCK, int UNROLL, bool LDS_BITS, bool MULTI = false>
 __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(SampleArgs a) {
   __shared__ SampleShared<BLOCK> sh;
+  __shared__ typename std::conditional<MULTI, SampleArgs, char>::type item_args;
   extern __shared__ uint32_t dyn_bits[];
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wid = tid / kWave;
   const size_t slot = blockIdx.x;
-  uint64_t* rec = a.rec + 2 * slot * a.n;
-  uint32_t* q = a.q + slot * a.n;
+  uint64_t* rec = a.rec + 2 * slot * a.slot_stride;
+  uint32_t* q = a.q + slot * a.slot_stride;
   uint64_t* praw = a.praw + slot * kPairMax;
   uint32_t* pu = a.pinfo + slot * 3 * kPairMax;   // per pair: u, in_ptr[u], in-degree of u
   uint32_t* prs = pu + kPairMax;
@@ -409,7 +437,6 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
   using Bits = typename std::conditional<LDS_BITS, BitsLds, BitsRec>::type;
   Bits bits = make_bits<LDS_BITS>(dyn_bits, rec, sh.bloom);
   const uint64_t lane_lt = (1ull << lane) - 1ull;
-  const uint64_t cap = a.c_bits >= 64 ? ~0ull : (1ull << a.c_bits);
 
   if (LDS_BITS)
     for (uint32_t i = tid; i < a.bit_words; i += BLOCK) dyn_bits[i] = 0;
@@ -422,16 +449,49 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
     const uint32_t idx = uniform_u32(sh.next);
     __syncthreads();
     if (idx >= a.count) break;
-    const uint64_t sample = a.first + idx;
+    if constexpr (MULTI) {
+      if (tid == 0) {
+        // the pool of work item idx: the last j with item_off[j] <= idx
+        uint32_t lo = 0, hi = a.n_inst - 1;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) >> 1;
+          if (a.item_off[mid] <= idx)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const SampleInst ins = a.inst[lo];
+        SampleArgs v = a;
+        v.n = ins.n;
+        v.c_bits = ins.c_bits;
+        v.max_out_deg = ins.max_out_deg;
+        v.row_ptr = ins.row_ptr;
+        v.col_idx = ins.col_idx;
+        v.in_ptr = ins.in_ptr;
+        v.in_idx = ins.in_idx;
+        v.new_of = ins.new_of;
+        v.orig_of = ins.orig_of;
+        v.seed = ins.seed;
+        v.instance = ins.instance;
+        v.first = ins.first - a.item_off[lo];   // sample = first + idx (mod 2^64)
+        item_args = v;
+      }
+      __syncthreads();
+    }
+    const SampleArgs& g = [&]() -> const SampleArgs& {
+      if constexpr (MULTI) return item_args; else return a;
+    }();
+    const uint64_t cap = g.c_bits >= 64 ? ~0ull : (1ull << g.c_bits);
+    const uint64_t sample = g.first + idx;
     bits.base = uint64_t(a.stamp0 + idx) << 32;
 
     // pair draw: every thread draws the same words (uniform, no broadcast)
-    WordStream st(a.seed, sample, a.instance, 0);
-    const uint32_t s0 = static_cast<uint32_t>(bounded(st, a.n));
-    const uint32_t tp = static_cast<uint32_t>(bounded(st, a.n - 1));
+    WordStream st(g.seed, sample, g.instance, 0);
+    const uint32_t s0 = static_cast<uint32_t>(bounded(st, g.n));
+    const uint32_t tp = static_cast<uint32_t>(bounded(st, g.n - 1));
     const uint32_t t0 = tp + (tp >= s0 ? 1u : 0u);
-    const uint32_t s = a.new_of ? a.new_of[s0] : s0;   // traversal ids
-    const uint32_t t = a.new_of ? a.new_of[t0] : t0;
+    const uint32_t s = g.new_of ? g.new_of[s0] : s0;   // traversal ids
+    const uint32_t t = g.new_of ? g.new_of[t0] : t0;
 
     if (!LDS_BITS) {
       for (uint32_t i = tid; i < kBloomWords; i += BLOCK) sh.bloom[i] = 0;
@@ -449,7 +509,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
     // the cone is small enough, in(u) for those u.  poff[i] = number of
     // pairs before R1's i-th entry.  The cone's size (CSR entries a 3-hop
     // test scans) is summed lazily: pairs [0, cpos) so far.
-    const uint32_t tb = a.in_ptr[t], te = a.in_ptr[t + 1];
+    const uint32_t tb = g.in_ptr[t], te = g.in_ptr[t + 1];
     const uint32_t dt = te - tb;
     const bool rings = dt <= Ring<BLOCK>::kCache;
     uint32_t pairs = 0, cpos = 0;
@@ -459,9 +519,9 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
         const uint32_t i = cb + tid;
         uint32_t dw = 0;
         if (i < dt) {
-          const uint32_t w = a.in_idx[tb + i];
-          const uint32_t r0 = a.in_ptr[w];
-          dw = a.in_ptr[w + 1] - r0;
+          const uint32_t w = g.in_idx[tb + i];
+          const uint32_t r0 = g.in_ptr[w];
+          dw = g.in_ptr[w + 1] - r0;
           sh.rw[i] = w;
           sh.rrs[i] = r0;
         }
@@ -480,9 +540,9 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
       uint32_t dg = 0;
       if (p < pairs) {
         const int i = ring_of(sh.poff, dt, p);
-        const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
-        const uint32_t r0 = a.in_ptr[u];
-        dg = a.in_ptr[u + 1] - r0;
+        const uint32_t u = g.in_idx[sh.rrs[i] + (p - sh.poff[i])];
+        const uint32_t r0 = g.in_ptr[u];
+        dg = g.in_ptr[u + 1] - r0;
         st_u32(&pu[p], u);
         st_u32(&prs[p], r0);
         st_u32(&pdg[p], dg);
@@ -519,7 +579,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
       int found = 0;
       n_arcs += dt;
       for (uint32_t e = tb + tid; e < te; e += BLOCK)
-        if (bits.done(a.in_idx[e], L)) found = 1;
+        if (bits.done(g.in_idx[e], L)) found = 1;
       if (__syncthreads_or(found)) {
         d = L + 1;
         break;
@@ -536,7 +596,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
           uint64_t c = 0;
           if (i < le) {
             const uint32_t w = ld_u32(&q[i]);
-            c = a.row_ptr[w + 1] - a.row_ptr[w];
+            c = g.row_ptr[w + 1] - g.row_ptr[w];
           }
           fpart += block_sum_u64<BLOCK>(c, sh.red);
           fpos += BLOCK;
@@ -556,7 +616,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
           int hit2 = 0;
           for (uint32_t p = tid; p < pairs; p += BLOCK) {
             const int i = ring_of(sh.poff, dt, p);
-            const uint32_t u = a.in_idx[sh.rrs[i] + (p - sh.poff[i])];
+            const uint32_t u = g.in_idx[sh.rrs[i] + (p - sh.poff[i])];
             const uint64_t c = bits.count(u);   // 0: unvisited
             if (c) {
               hit2 = 1;
@@ -583,7 +643,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
             //     chunk by chunk until it is decided; sizing the cone also
             //     keeps each pair's u and in-row for the test.
             const uint64_t bound =
-                (a.max_out_deg && sumL > ~0ull / a.max_out_deg) ? ~0ull : sumL * a.max_out_deg;
+                (g.max_out_deg && sumL > ~0ull / g.max_out_deg) ? ~0ull : sumL * g.max_out_deg;
             bool cheap = false;
             if (sumL < cap && bound < cap) {
               for (;;) {
@@ -611,7 +671,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
                   r0 = ld_u32(&prs[p]);
                   dg = ld_u32(&pdg[p]);
                 }
-                raw_counts_chunk<BLOCK, UNROLL>(a, bits, rec, u, r0, dg, L, sh, n_arcs);
+                raw_counts_chunk<BLOCK, UNROLL>(g, bits, rec, u, r0, dg, L, sh, n_arcs);
                 const uint64_t raw = sh.sg[tid];
                 if (p < pairs) st_u64(&praw[p], raw);
                 if (raw) {
@@ -633,11 +693,11 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
         // at level L+1, raw_w = sum of sigma' over w's in-neighbours at level L
         uint64_t wsum = 0, wscan = 0;
         for (uint32_t e = tb + wid; e < te; e += BLOCK / kWave) {
-          const uint32_t w = a.in_idx[e];
-          const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
+          const uint32_t w = g.in_idx[e];
+          const uint32_t ub = g.in_ptr[w], ue = g.in_ptr[w + 1];
           uint64_t x = 0;
           for (uint32_t f = ub + lane; f < ue; f += kWave) {
-            const uint32_t u = a.in_idx[f];
+            const uint32_t u = g.in_idx[f];
             // w is unvisited (check (1) failed), so a visited u is at level L
             x += bits.count(u);
           }
@@ -666,8 +726,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
         uint64_t sw = 0;
         if (i < le) {
           const uint32_t w = ld_u32(&q[i]);
-          rs = a.row_ptr[w];
-          deg = a.row_ptr[w + 1] - rs;
+          rs = g.row_ptr[w];
+          deg = g.row_ptr[w + 1] - rs;
           sw = ld_u64(sig_of(rec, w));
         }
         uint32_t total;
@@ -698,7 +758,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
                 else
                   hi = mid - 1;
               }
-              v[k] = a.col_idx[sh.rs[lo] + (e - sh.off[lo])];
+              v[k] = g.col_idx[sh.rs[lo] + (e - sh.off[lo])];
               add[k] = sh.sg[lo];
             }
           }
@@ -747,7 +807,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
       // counts when a shift applies
       mx = block_max_u64<BLOCK>(mx, sh.red);
       const uint32_t bl = bitlen64(mx);
-      const uint32_t shift = bl > a.c_bits ? bl - a.c_bits : 0u;
+      const uint32_t shift = bl > g.c_bits ? bl - g.c_bits : 0u;
       uint64_t ssum = 0;
       for (uint32_t i = le + tid; i < ne; i += BLOCK) {
         const uint32_t v = ld_u32(&q[i]);
@@ -774,7 +834,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
     // stored pair counts.
     const uint32_t len = (d != kUnseen && d >= 2) ? d - 1 : 0u;
     if (tid == 0) {
-      sh.base = len ? atomicAdd(reinterpret_cast<unsigned long long*>(a.stage_used),
+      sh.base = len ? atomicAdd(reinterpret_cast<unsigned long long*>(g.stage_used),
                                 static_cast<unsigned long long>(len))
                     : 0ull;
     }
@@ -797,7 +857,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
         ok = false;
       } else {
         v = sh.rw[pi];
-        if (tid == 0 && hbase < a.stage_cap) a.stage[hbase] = caller_id(a, v);
+        if (tid == 0 && hbase < g.stage_cap) g.stage[hbase] = caller_id(g, v);
         written = 1;
         dv = d - 1;
         w_next = shortcut == 2 ? uniform_u64(sh.ring_a[pi]) : 0ull;
@@ -813,8 +873,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
             ok = false;
           } else {
             w_next = uniform_u64(ld_u64(&praw[p0 + j]));
-            v = a.in_idx[sh.rrs[pi] + j];
-            if (tid == 0 && hbase + 1 < a.stage_cap) a.stage[hbase + 1] = caller_id(a, v);
+            v = g.in_idx[sh.rrs[pi] + j];
+            if (tid == 0 && hbase + 1 < g.stage_cap) g.stage[hbase + 1] = caller_id(g, v);
             written = 2;
             dv = d - 2;
           }
@@ -829,10 +889,10 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
         uint64_t acc = 0;
         uint32_t pick = kUnseen;
         for (uint32_t e = tb; e < te; ++e) {
-          const uint32_t w = a.in_idx[e];
-          const uint32_t ub = a.in_ptr[w], ue = a.in_ptr[w + 1];
+          const uint32_t w = g.in_idx[e];
+          const uint32_t ub = g.in_ptr[w], ue = g.in_ptr[w + 1];
           uint64_t x = 0;
-          for (uint32_t f = ub + lane; f < ue; f += kWave) x += bits.count(a.in_idx[f]);
+          for (uint32_t f = ub + lane; f < ue; f += kWave) x += bits.count(g.in_idx[f]);
           acc += wave_sum_u64(x);
           if (acc > r) {
             pick = w;
@@ -847,40 +907,40 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
         ok = false;
       } else {
         v = pick;
-        if (tid == 0 && hbase < a.stage_cap) a.stage[hbase] = caller_id(a, v);
+        if (tid == 0 && hbase < g.stage_cap) g.stage[hbase] = caller_id(g, v);
         written = 1;
         dv = d - 1;
       }
     }
     while (ok && dv >= 2) {
       const uint32_t want = dv - 1;
-      const uint32_t vb = a.in_ptr[v], ve = a.in_ptr[v + 1];
+      const uint32_t vb = g.in_ptr[v], ve = g.in_ptr[v + 1];
       // a known W spares rows longer than one pick round their summing pass
       uint64_t wk = w_next;
       if (!wk && claimed_v && dv < 64 && !((shifted >> dv) & 1ull)) wk = ld_u64(sig_of(rec, v));
       wk = ve - vb > uint32_t(BLOCK) * kPickPer ? uniform_u64(wk) : 0ull;
       const uint32_t j = block_pick<BLOCK>(
-          ve - vb, [&](uint32_t jj) { return pred_weight(bits, rec, a.in_idx[vb + jj], want); }, wk, st, sh);
+          ve - vb, [&](uint32_t jj) { return pred_weight(bits, rec, g.in_idx[vb + jj], want); }, wk, st, sh);
       if (j == kUnseen) {
         ok = false;
         break;
       }
       w_next = 0;
       claimed_v = true;   // predecessors lie on produced levels
-      v = a.in_idx[vb + j];
-      if (tid == 0 && hbase + written < a.stage_cap) a.stage[hbase + written] = caller_id(a, v);
+      v = g.in_idx[vb + j];
+      if (tid == 0 && hbase + written < g.stage_cap) g.stage[hbase + written] = caller_id(g, v);
       ++written;
       --dv;
     }
     if (tid == 0) {
-      if (!ok) atomicOr(a.flags, kErrBacktrack);
-      a.stage_pos[idx] = hbase;
-      a.he_len[idx] = len;
-      if (a.st_out) {
-        a.st_out[2 * size_t(idx)] = s0;
-        a.st_out[2 * size_t(idx) + 1] = t0;
+      if (!ok) atomicOr(g.flags, kErrBacktrack);
+      g.stage_pos[idx] = hbase;
+      g.he_len[idx] = len;
+      if (g.st_out) {
+        g.st_out[2 * size_t(idx)] = s0;
+        g.st_out[2 * size_t(idx) + 1] = t0;
       }
-      if (a.dist_out) a.dist_out[idx] = d;
+      if (g.dist_out) g.dist_out[idx] = d;
     }
     __syncthreads();
     // the records keep this BFS's stamp (older than any later one); only
@@ -935,13 +995,17 @@ template <int BLOCK>
 static hipError_t hbm_occupancy(int* per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sample_paths<BLOCK, kUnroll, false>, BLOCK, 0);
 }
+template <int BLOCK>
+static hipError_t multi_occupancy(int* per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_sample_paths<BLOCK, kUnroll, false, true>, BLOCK, 0);
+}
 
 // Variant choice.  Default: the Bloom-filter kernel with 128-thread
 // workgroups (many concurrent BFSs per CU hide the latency of the short,
 // dependent steps of each BFS).  CENTRA_SAMPLER_VARIANT selects another:
 // "lds" (LDS bitmap, 1024 threads, when the bitmap fits), "hbm512",
 // "hbm256", "hbm128", "hbm64" (Bloom filter, that many threads).
-static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
+static SamplePlan plan_for(centra_ctx* ctx, uint32_t n, int block_override = 0) {
   SamplePlan p{};
   p.bit_words = (n + 31) / 32;
   int max_lds = 0, cus = 0;
@@ -957,6 +1021,10 @@ static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
   if (!strcmp(v, "hbm256")) p.block = 256;
   if (!strcmp(v, "hbm64")) p.block = 64;
   p.lds_bits = !strcmp(v, "lds") && sizeof(SampleShared<kLdsBlock>) + dyn <= size_t(max_lds);
+  if (block_override) {   // fused launches: a Bloom-filter variant chosen by the caller
+    p.block = block_override;
+    p.lds_bits = false;
+  }
   int per_cu = 0;
   hipError_t e = hipSuccess;
   if (p.lds_bits) {
@@ -966,11 +1034,20 @@ static SamplePlan plan_for(centra_ctx* ctx, uint32_t n) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, CENTRA_LDS_KERNEL, kLdsBlock, dyn);
   } else {
     p.dyn_lds = 0;
-    switch (p.block) {
-      case 512: e = hbm_occupancy<512>(&per_cu); break;
-      case 256: e = hbm_occupancy<256>(&per_cu); break;
-      case 64: e = hbm_occupancy<64>(&per_cu); break;
-      default: e = hbm_occupancy<128>(&per_cu); break;
+    if (block_override) {
+      switch (p.block) {
+        case 512: e = multi_occupancy<512>(&per_cu); break;
+        case 256: e = multi_occupancy<256>(&per_cu); break;
+        case 64: e = multi_occupancy<64>(&per_cu); break;
+        default: e = multi_occupancy<128>(&per_cu); break;
+      }
+    } else {
+      switch (p.block) {
+        case 512: e = hbm_occupancy<512>(&per_cu); break;
+        case 256: e = hbm_occupancy<256>(&per_cu); break;
+        case 64: e = hbm_occupancy<64>(&per_cu); break;
+        default: e = hbm_occupancy<128>(&per_cu); break;
+      }
     }
   }
   if (e != hipSuccess || per_cu <= 0) per_cu = 1;
@@ -991,17 +1068,17 @@ static size_t slot_mem_cap() {
   return total_b / 2;
 }
 
-static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, hipStream_t s) {
+static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t s) {
   const size_t cap_bytes = slot_mem_cap();
   {
     // never ask for more slots than the cap holds
-    const size_t per = size_t(g->n) * (16 + 4) + kPairMax * (8 + 12);
+    const size_t per = size_t(gn) * (16 + 4) + kPairMax * (8 + 12);
     const size_t most = cap_bytes / (per ? per : 1);
     if (want > most) want = most ? static_cast<uint32_t>(most) : 1u;
   }
-  if (ctx->slots >= want && ctx->slot_n >= g->n) return CENTRA_OK;
+  if (ctx->slots >= want && ctx->slot_n >= gn) return CENTRA_OK;
   uint32_t slots = want > ctx->slots ? want : ctx->slots;
-  const uint32_t n = g->n > ctx->slot_n ? g->n : ctx->slot_n;
+  const uint32_t n = gn > ctx->slot_n ? gn : ctx->slot_n;
   const size_t per_slot = size_t(n) * (16 + 4) + kPairMax * (8 + 12);
   // at most the cap of slot state (or the budget, if smaller)
   if (size_t(slots) * per_slot > cap_bytes) slots = static_cast<uint32_t>(cap_bytes / per_slot);
@@ -1031,14 +1108,17 @@ static int ensure_slots(centra_ctx* ctx, const centra_graph* g, uint32_t want, h
   return CENTRA_OK;
 }
 
-int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
-                    uint32_t count, uint32_t* st_out, uint32_t* dist_out, uint64_t* total, hipStream_t s) {
+// Runs one sampling launch of `count` work items into the staging area
+// (redrawn with a larger area if it overflows); `a` holds the graph part of
+// the arguments (or the instance table of a fused launch), `max_n` the
+// largest n of its graphs.  *total receives the staged node count.
+static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_t max_n, bool multi, int block,
+                          uint64_t* total, hipStream_t s) {
   int rc;
   *total = 0;
-  if (count == 0) return CENTRA_OK;
-  const SamplePlan plan = plan_for(ctx, g->n);
+  const SamplePlan plan = plan_for(ctx, max_n, multi ? block : 0);
   uint32_t want = count < plan.resident ? count : plan.resident;
-  if ((rc = ensure_slots(ctx, g, want, s))) return rc;
+  if ((rc = ensure_slots(ctx, max_n, want, s))) return rc;
   const uint32_t grid = count < ctx->slots ? count : ctx->slots;
   if ((rc = ensure(ctx, ctx->stage_pos, size_t(count) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->stage_len, size_t(count) * 4 + 8 + 8 * (size_t(count) + 1), false, s))) return rc;
@@ -1058,22 +1138,10 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
       fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(ctx->slots) * ctx->slot_n * 2, s);
       ctx->stamp_next = 1;
     }
-    SampleArgs a;
     a.stamp0 = ctx->stamp_next;
     ctx->stamp_next += count;
-    a.n = g->n;
-    a.c_bits = g->count_bits;
-    a.max_out_deg = g->max_out_degree;
-    a.row_ptr = g->bfs_row_ptr;
-    a.col_idx = g->bfs_col_idx;
-    a.in_ptr = g->bfs_in_ptr;
-    a.in_idx = g->bfs_in_idx;
-    a.new_of = g->new_of;
-    a.orig_of = g->orig_of;
-    a.seed = seed;
-    a.instance = instance;
-    a.first = first;
     a.count = count;
+    a.slot_stride = ctx->slot_n;
     a.rec = static_cast<uint64_t*>(ctx->slot_rec.ptr);
     a.q = static_cast<uint32_t*>(ctx->slot_q.ptr);
     a.praw = static_cast<uint64_t*>(ctx->slot_praw.ptr);
@@ -1085,22 +1153,30 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     a.stage_used = used;
     a.stage_pos = static_cast<uint64_t*>(ctx->stage_pos.ptr);
     a.he_len = static_cast<uint32_t*>(ctx->stage_len.ptr);
-    a.st_out = st_out;
-    a.dist_out = dist_out;
     a.flags = ctx->d_flags;
     a.stats = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 16);
     fill_u64(a.stats, 0, 2, s);
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
-    if (plan.lds_bits)
+    if (multi) {
+      if (plan.block == 512)
+        hipLaunchKernelGGL((k_sample_paths<512, kUnroll, false, true>), dim3(grid), dim3(512), 0, s, a);
+      else if (plan.block == 256)
+        hipLaunchKernelGGL((k_sample_paths<256, kUnroll, false, true>), dim3(grid), dim3(256), 0, s, a);
+      else if (plan.block == 64)
+        hipLaunchKernelGGL((k_sample_paths<64, kUnroll, false, true>), dim3(grid), dim3(64), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_sample_paths<128, kUnroll, false, true>), dim3(grid), dim3(128), 0, s, a);
+    } else if (plan.lds_bits) {
       hipLaunchKernelGGL(CENTRA_LDS_KERNEL, dim3(grid), dim3(kLdsBlock), plan.dyn_lds, s, a);
-    else if (plan.block == 512)
+    } else if (plan.block == 512) {
       hipLaunchKernelGGL((k_sample_paths<512, kUnroll, false>), dim3(grid), dim3(512), 0, s, a);
-    else if (plan.block == 256)
+    } else if (plan.block == 256) {
       hipLaunchKernelGGL((k_sample_paths<256, kUnroll, false>), dim3(grid), dim3(256), 0, s, a);
-    else if (plan.block == 64)
+    } else if (plan.block == 64) {
       hipLaunchKernelGGL((k_sample_paths<64, kUnroll, false>), dim3(grid), dim3(64), 0, s, a);
-    else
+    } else {
       hipLaunchKernelGGL((k_sample_paths<128, kUnroll, false>), dim3(grid), dim3(128), 0, s, a);
+    }
     CENTRA_HIP(ctx, hipGetLastError());
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[7], s));
     uint64_t host_ctr[4] = {0, 0, 0, 0};   // work, used, arcs, nodes
@@ -1125,6 +1201,76 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
     cap = host_used + 1024;   // staging overflowed: the batch is redrawn identically
   }
   return fail(ctx, CENTRA_EHIP, "sample_paths: staging did not converge");
+}
+
+int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
+                    uint32_t count, uint32_t* st_out, uint32_t* dist_out, uint64_t* total, hipStream_t s) {
+  *total = 0;
+  if (count == 0) return CENTRA_OK;
+  SampleArgs a{};
+  a.n = g->n;
+  a.c_bits = g->count_bits;
+  a.max_out_deg = g->max_out_degree;
+  a.row_ptr = g->bfs_row_ptr;
+  a.col_idx = g->bfs_col_idx;
+  a.in_ptr = g->bfs_in_ptr;
+  a.in_idx = g->bfs_in_idx;
+  a.new_of = g->new_of;
+  a.orig_of = g->orig_of;
+  a.seed = seed;
+  a.instance = instance;
+  a.first = first;
+  a.st_out = st_out;
+  a.dist_out = dist_out;
+  return launch_sampler(ctx, a, count, g->n, false, 0, total, s);
+}
+
+int sample_multi_to_stage(centra_ctx* ctx, const MultiSampleItem* items, uint32_t n_items, int block,
+                          uint64_t* total, hipStream_t s) {
+  *total = 0;
+  std::vector<SampleInst> tab;
+  std::vector<uint32_t> off;
+  uint64_t count = 0;
+  uint32_t max_n = 0;
+  for (uint32_t i = 0; i < n_items; ++i) {
+    const MultiSampleItem& it = items[i];
+    if (it.count == 0) continue;
+    const centra_graph* g = it.g;
+    SampleInst x{};
+    x.n = g->n;
+    x.c_bits = g->count_bits;
+    x.max_out_deg = g->max_out_degree;
+    x.instance = it.instance;
+    x.row_ptr = g->bfs_row_ptr;
+    x.col_idx = g->bfs_col_idx;
+    x.in_ptr = g->bfs_in_ptr;
+    x.in_idx = g->bfs_in_idx;
+    x.new_of = g->new_of;
+    x.orig_of = g->orig_of;
+    x.seed = it.seed;
+    x.first = it.first;
+    tab.push_back(x);
+    off.push_back(static_cast<uint32_t>(count));
+    count += it.count;
+    if (g->n > max_n) max_n = g->n;
+  }
+  if (count == 0) return CENTRA_OK;
+  if (count >= (1ull << 32)) return fail(ctx, CENTRA_ENOTSUP, "sample_multi: 2^32 work items or more");
+  off.push_back(static_cast<uint32_t>(count));
+  int rc;
+  const size_t tab_bytes = tab.size() * sizeof(SampleInst);
+  if ((rc = ensure(ctx, ctx->multi_tab, tab_bytes + off.size() * 4 + 256, false, s))) return rc;
+  char* dtab = static_cast<char*>(ctx->multi_tab.ptr);
+  const size_t off_at = (tab_bytes + 255) & ~size_t(255);
+  CENTRA_HIP(ctx, hipMemcpyAsync(dtab, tab.data(), tab_bytes, hipMemcpyHostToDevice, s));
+  CENTRA_HIP(ctx, hipMemcpyAsync(dtab + off_at, off.data(), off.size() * 4, hipMemcpyHostToDevice, s));
+  SampleArgs a{};
+  a.inst = reinterpret_cast<const SampleInst*>(dtab);
+  a.item_off = reinterpret_cast<const uint32_t*>(dtab + off_at);
+  a.n_inst = static_cast<uint32_t>(tab.size());
+  rc = launch_sampler(ctx, a, static_cast<uint32_t>(count), max_n, true, block, total, s);
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));   // the host tables above go out of scope
+  return rc;
 }
 
 int stage_to_output(centra_ctx* ctx, uint32_t count, uint64_t base, uint64_t* he_off, uint32_t* he_nodes,

@@ -1,0 +1,210 @@
+"""GPU tests of the batching and serving engine (centra_engine_*): every
+query's result equals centra_progressive run alone on the same graph and
+parameters (bit-exact picks, coverage, sample sizes and iteration count;
+bound values to 1e-12), in batch mode over uneven instances, under a tight
+memory budget, without captured graphs, with arrivals spread in time
+(continuous batching), and when a pool's released levels are rebuilt; the
+same query alone and in a mix gives the same result."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_03651_amd import binding, inputs
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["c_hat", "amcera", "wimpy", "xi", "nu", "rtilde", "r", "eta"]
+
+
+def standalone(ctx, dg, pool, q):
+    seed, inst, t_pool, m_init, m_max = pool
+    k, t, eps, delta = q
+    return binding.centra_progressive(ctx, dg.handle, k, t, eps, delta, seed, inst, m_init, m_max)
+
+
+def same(got, want):
+    rc, picks, res = got[0], got[1], got[2]
+    wrc, wpicks, wres = want[0], want[1], want[2]
+    assert rc == wrc
+    assert np.array_equal(picks, wpicks)
+    assert (res.n_picked, res.iterations, res.certified, res.coverage, res.m_final) == \
+        (wres.n_picked, wres.iterations, wres.certified, wres.coverage, wres.m_final)
+    for f in FIELDS:
+        assert getattr(res, f) == pytest.approx(getattr(wres, f), rel=1e-12, abs=1e-300), f
+
+
+def uneven_instances(seed, count):
+    """Small graphs of the uneven-instances mix (BA of a few thousand nodes,
+    grids up to side 40, a directed R-MAT), with per-instance k."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        kind = i % 4
+        if kind == 0:
+            g = inputs.ba_graph(int(rng.integers(1000, 5000)), 5, 100 + i)
+        elif kind == 1:
+            g = inputs.grid_graph(int(rng.integers(12, 41)))
+        elif kind == 2:
+            g = inputs.rmat_graph(11, 8, seed=200 + i)
+        else:
+            g = inputs.ba_graph(int(rng.integers(200, 800)), 3, 300 + i)
+        out.append((g, int(rng.integers(5, 30))))
+    return out
+
+
+def run_batch(ctx, graphs, flags=0, budget=0, t=16, eps=0.1, delta=0.1, m_init=2000, m_max=32000):
+    dgs = [binding.DeviceGraph(ctx, g) for g, _ in graphs]
+    eng = binding.Engine(ctx, budget, flags)
+    try:
+        qids, pools = [], []
+        for i, (dg, (g, k)) in enumerate(zip(dgs, graphs)):
+            pool = (7, i, t, m_init, m_max)
+            pid = eng.add_pool(dg.handle, *pool)
+            qids.append(eng.submit(pid, k, t, eps, delta))
+            pools.append(pool)
+        eng.run()
+        got = [eng.result(q) for q in qids]
+        st = eng.stats()
+        log = eng.log()
+        want = [standalone(ctx, dg, pool, (k, t, eps, delta)) for dg, pool, (g, k) in zip(dgs, pools, graphs)]
+    finally:
+        eng.destroy()
+        for dg in dgs:
+            dg.release()
+    return got, want, st, log
+
+
+def test_batch_equals_standalone(ctx):
+    graphs = uneven_instances(1, 12)
+    say(f"engine batch: {len(graphs)} instances")
+    got, want, st, log = run_batch(ctx, graphs)
+    for g, w in zip(got, want):
+        same(g, w)
+    say(f"  ticks {st.ticks}, sampler launches {st.sampler_launches}, graph replays {st.graph_replays}, "
+        f"tuned block {st.tuned_block}; {log.strip()}")
+    assert st.graph_replays > 0 and st.tuned_block in (64, 128, 256, 512)
+    assert "autotune" in log
+    # fused: one sampling launch per tick at most (plus the tuner's probes)
+    assert st.sampler_launches <= st.ticks
+
+
+def test_batch_matches_oracle(ctx):
+    # one instance, checked against the oracle's progressive loop as well
+    g = inputs.ba_graph(2000, 5, 1)
+    got, want, st, _ = run_batch(ctx, [(g, 10)], t=10, eps=0.05, m_init=10000, m_max=40000)
+    wrc, wpicks, wres = oracle.progressive(g, 10, 10, 0.05, 0.1, 7, 0, 10000, 40000)
+    rc, picks, res, _ = got[0]
+    assert rc == wrc and np.array_equal(picks, wpicks)
+    assert res.coverage == wres.coverage and res.m_final == wres.m_final
+    assert res.eta == pytest.approx(wres.eta, rel=1e-12)
+
+
+def test_batch_without_graphs_and_under_budget(ctx):
+    graphs = uneven_instances(2, 8)
+    say("engine batch without captured graphs")
+    got, want, st, _ = run_batch(ctx, graphs, flags=binding.CENTRA_ENGINE_NO_GRAPHS | binding.CENTRA_ENGINE_NO_TUNE)
+    for g, w in zip(got, want):
+        same(g, w)
+    assert st.graph_replays == 0 and st.greedy_launches > 0 and st.tuned_block == 0
+    # a budget below the unbudgeted peak: fewer queries at once, same results
+    budget = int(st.peak_bytes * 0.8)
+    say(f"engine batch under a budget of {budget} bytes (unbudgeted peak {st.peak_bytes})")
+    got_b, _, st_b, _ = run_batch(ctx, graphs, budget=budget)
+    for g, w in zip(got_b, want):
+        same(g, w)
+    say(f"  peak active {st_b.peak_active} (unbudgeted {st.peak_active}), peak bytes {st_b.peak_bytes}")
+    assert st_b.peak_bytes <= budget and st_b.peak_active < st.peak_active
+
+
+def test_serving_mix_equals_alone(ctx):
+    # three resident pools, queries arriving over 0.3 s with mixed k, t
+    # and eps; each result equals the query run alone (a fresh engine with
+    # that query only) and centra_progressive
+    gs = [inputs.ba_graph(3000, 5, 11), inputs.rmat_graph(11, 8, seed=12), inputs.grid_graph(30)]
+    dgs = [binding.DeviceGraph(ctx, g) for g in gs]
+    pools = [(5, 0, 32, 4000, 64000), (5, 1, 32, 4000, 64000), (5, 2, 32, 2000, 16000)]
+    rng = np.random.default_rng(3)
+    qs = []
+    tarr = 0.0
+    for i in range(16):
+        tarr += float(rng.exponential(0.02))
+        qs.append((int(rng.integers(3)), int(rng.integers(5, 40)), int(rng.choice([8, 16, 32])),
+                   float(rng.choice([0.1, 0.05])), tarr))
+    try:
+        eng = binding.Engine(ctx, 0)
+        try:
+            pids = [eng.add_pool(dg.handle, *p) for dg, p in zip(dgs, pools)]
+            qids = [eng.submit(pids[p], k, t, eps, 0.1, a) for p, k, t, eps, a in qs]
+            say("engine serving: 16 queries over 3 pools, realtime")
+            eng.run(realtime=True)
+            mixed = [eng.result(q) for q in qids]
+            st = eng.stats()
+        finally:
+            eng.destroy()
+        say(f"  ticks {st.ticks}, peak active {st.peak_active}")
+        assert st.peak_active >= 2   # queries overlapped on the device
+        for (p, k, t, eps, a), got in zip(qs, mixed):
+            rc, picks, res, info = got
+            assert info.finished_s >= info.admitted_s >= info.arrival_s - 1e-9
+            same(got, standalone(ctx, dgs[p], pools[p], (k, t, eps, 0.1)))
+        # alone: the first three queries each in a fresh engine
+        for (p, k, t, eps, a), got in list(zip(qs, mixed))[:3]:
+            eng = binding.Engine(ctx, 0, binding.CENTRA_ENGINE_NO_TUNE)
+            try:
+                pid = eng.add_pool(dgs[p].handle, *pools[p])
+                q = eng.submit(pid, k, t, eps, 0.1, 0.0)
+                eng.run()
+                alone = eng.result(q)
+            finally:
+                eng.destroy()
+            assert alone[0] == got[0] and np.array_equal(alone[1], got[1])
+            assert alone[2].eta == got[2].eta and alone[2].coverage == got[2].coverage
+    finally:
+        for dg in dgs:
+            dg.release()
+
+
+def test_released_levels_are_rebuilt(ctx):
+    # a pool whose levels were released (its only query finished) serves a
+    # later query by rebuilding them from its kept samples
+    g = inputs.ba_graph(2500, 4, 21)
+    dg = binding.DeviceGraph(ctx, g)
+    pool = (9, 3, 16, 3000, 24000)
+    try:
+        eng = binding.Engine(ctx, 0, binding.CENTRA_ENGINE_NO_TUNE)
+        try:
+            pid = eng.add_pool(dg.handle, *pool)
+            q1 = eng.submit(pid, 12, 16, 0.05, 0.1)
+            eng.run()
+            q2 = eng.submit(pid, 7, 8, 0.1, 0.1)
+            eng.run()
+            r1, r2 = eng.result(q1), eng.result(q2)
+        finally:
+            eng.destroy()
+        same(r1, standalone(ctx, dg, pool, (12, 16, 0.05, 0.1)))
+        same(r2, standalone(ctx, dg, pool, (7, 8, 0.1, 0.1)))
+    finally:
+        dg.release()
+
+
+def test_engine_argument_errors(ctx):
+    g = inputs.ba_graph(500, 3, 1)
+    dg = binding.DeviceGraph(ctx, g)
+    eng = binding.Engine(ctx, 0)
+    try:
+        with pytest.raises(binding.CentraError):
+            eng.add_pool(dg.handle, 1, 0, 0, 100, 200)          # t = 0
+        with pytest.raises(binding.CentraError):
+            eng.add_pool(dg.handle, 1, 0, 8, 300, 200)          # m_max < m_init
+        pid = eng.add_pool(dg.handle, 1, 0, 8, 100, 400)
+        with pytest.raises(binding.CentraError):
+            eng.submit(pid, 5, 9, 0.1, 0.1)                     # t above the pool's
+        with pytest.raises(binding.CentraError):
+            eng.submit(pid, 5, 8, 0.7, 0.1)                     # eps >= 1 - 1/e
+        eng.submit(pid, 5, 8, 0.1, 0.1, 1.0)
+        with pytest.raises(binding.CentraError):
+            eng.submit(pid, 5, 8, 0.1, 0.1, 0.5)                # arrivals out of order
+    finally:
+        eng.destroy()
+        dg.release()
