@@ -97,6 +97,21 @@ WORKLOADS = {
                             "16, .57/.19/.19/.05, seed 1, symmetrised); samples 1M doubling to 8M, k=50, t=64, "
                             "eps=0.01, delta=0.1"),
 }
+# Workloads of the batching and serving engine (one JSON line each, not the
+# default benchmark line).
+ENGINE_WORKLOADS = {
+    "batched": dict(count=256, mix_seed=1, ba_n=(1_000, 100_000), grid_side=(32, 128), k=(5, 50), t=32,
+                    m_init=50_000, m_max=50_000, eps=0.05, delta=0.1, seed=1,
+                    label="uneven instances: 256 graphs, each Barabasi-Albert n~U[1e3,1e5] (attachment 5) or an L x L "
+                          "grid L~U[32,128] (Bernoulli 1/2, numpy seed 1), 50k shortest-path samples each, "
+                          "k~U[5,50], t=32, eps=0.05, delta=0.1 (one iteration of Algorithm 1 per instance)"),
+    "serving": dict(rate=200.0, duration=2.0, arrival_seed=1, t=100, delta=0.1, eps=(0.05, 0.02, 0.01), k=(10, 500),
+                    seed=1,
+                    label="serving: 8 resident graphs (4 Barabasi-Albert n=1e6, 2 R-MAT scale 20 directed, 2 grids "
+                          "2048x2048); Poisson arrivals at 200 queries/s for 2 s, each (graph~U{0..7}, k~U[10,500], "
+                          "eps~U{0.05,0.02,0.01}, delta=0.1, t=100); pools 100k doubling to 6.4M samples "
+                          "(grids: 1k doubling to 16k), drawn and built before the stream starts"),
+}
 TRIANGLE_SAMPLE_BYTES = 56
 KPATH_NODE_BYTES, KPATH_SAMPLE_BYTES = 28, 12
 WORKLOAD = WORKLOADS["sparse"]
@@ -281,6 +296,204 @@ def sweeps():
                       "over_t": over_t, "over_m": over_m}), flush=True)
 
 
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def batched_bench(args):
+    """Plain (one centra_progressive call per instance, one after the
+    other) against the engine (every instance a pool with one query, run
+    together), on the same instances; results must be identical."""
+    import numpy as np
+    import torch
+    from paper_2306_03651_amd import binding, inputs
+    W = ENGINE_WORKLOADS["batched"]
+    mix = inputs.uneven_instances(W["count"], W["mix_seed"], W["ba_n"], W["grid_side"], W["k"])
+    t0 = time.time()
+    graphs = [inputs.instance_graph(kind, size, gs) for kind, size, gs, _ in mix]
+    log(f"{len(graphs)} graphs built in {time.time() - t0:.1f}s "
+        f"({sum(1 for m in mix if m[0] == 'ba')} BA, {sum(1 for m in mix if m[0] == 'grid')} grids)")
+    ctx = binding.centra_create(0, 0)
+    dgs = [binding.DeviceGraph(ctx, g) for g in graphs]
+    stream = torch.cuda.current_stream()
+
+    def plain():
+        out = []
+        for i, (dg, (_, _, _, k)) in enumerate(zip(dgs, mix)):
+            out.append(binding.centra_progressive(ctx, dg.handle, k, W["t"], W["eps"], W["delta"], W["seed"], i,
+                                                  W["m_init"], W["m_max"], stream=stream))
+        torch.cuda.synchronize()
+        return out
+
+    def batched(flags=0):
+        eng = binding.Engine(ctx, 0, flags)
+        try:
+            qs = []
+            for i, (dg, (_, _, _, k)) in enumerate(zip(dgs, mix)):
+                pid = eng.add_pool(dg.handle, W["seed"], i, W["t"], W["m_init"], W["m_max"])
+                qs.append(eng.submit(pid, k, W["t"], W["eps"], W["delta"]))
+            eng.run(stream=stream)
+            torch.cuda.synchronize()
+            return [eng.result(q) for q in qs], eng.stats(), eng.log()
+        finally:
+            eng.destroy()
+
+    for i in range(args.warmup):
+        batched()
+        plain()
+        log(f"warmup {i} done")
+    tp, tb = [], []
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        res_p = plain()
+        tp.append(time.perf_counter() - ts)
+        ts = time.perf_counter()
+        res_b, st, tune_log = batched()
+        tb.append(time.perf_counter() - ts)
+        log(f"step {i}: plain {tp[-1]:.3f}s, batched {tb[-1]:.3f}s")
+    same = all(a[0] == b[0] and np.array_equal(a[1], b[1]) and a[2].coverage == b[2].coverage and
+               a[2].eta == b[2].eta for a, b in zip(res_p, res_b))
+    paths = sum(int(r[2].m_final) for r in res_b)
+    mp, mb = sum(tp) / len(tp), sum(tb) / len(tb)
+    for dg in dgs:
+        dg.release()
+    binding.centra_destroy(ctx)
+    out = {"metric": "time to certified top-k over 256 uneven instances (batched vs plain)", "value": round(mb, 4),
+           "unit": "s", "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "dtype": "u64", "data": "synthetic", "config": {"workload": W["label"]},
+           "batched_s": round(mb, 4), "plain_s": round(mp, 4), "speedup_vs_plain": round(mp / mb, 3),
+           "paths_per_s_batched": round(paths / mb, 1), "paths_per_s_plain": round(paths / mp, 1),
+           "certified": sum(int(r[2].certified) for r in res_b), "instances": len(res_b),
+           "results_identical": bool(same),
+           "engine": {"ticks": st.ticks, "sampler_launches": st.sampler_launches, "graph_replays": st.graph_replays,
+                      "graphs_captured": st.graphs_captured, "tuned_block": st.tuned_block,
+                      "ms_sample": round(st.ms_sample, 2), "ms_levels": round(st.ms_levels, 2),
+                      "ms_greedy": round(st.ms_greedy, 2), "ms_select": round(st.ms_select, 2),
+                      "peak_bytes": st.peak_bytes, "autotune": tune_log.strip()},
+           "device": torch.cuda.get_device_name(0)}
+    print(json.dumps(out), flush=True)
+
+
+def serving_bench(args):
+    """A Poisson stream of queries over 8 resident graphs, served by the
+    engine in real time (continuous batching); latency = completion time -
+    arrival time of each query."""
+    import numpy as np
+    import torch
+    from paper_2306_03651_amd import binding, inputs
+    W = ENGINE_WORKLOADS["serving"]
+    t0 = time.time()
+    spec = [("ba", 1), ("ba", 2), ("ba", 3), ("ba", 4), ("rmat", 1), ("rmat", 2), ("grid", 0), ("grid", 0)]
+    graphs = []
+    for kind, gs in spec:
+        if kind == "ba":
+            graphs.append(inputs.ba_graph(1_000_000, 5, gs))
+        elif kind == "rmat":
+            graphs.append(inputs.rmat_graph(20, 16, seed=gs))
+        else:
+            graphs.append(inputs.grid_graph(2048))
+    log(f"8 graphs built in {time.time() - t0:.1f}s")
+    ctx = binding.centra_create(0, 0)
+    dgs = [binding.DeviceGraph(ctx, g) for g in graphs]
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(W["arrival_seed"])
+    queries = []
+    tarr = 0.0
+    while True:
+        tarr += float(rng.exponential(1.0 / W["rate"]))
+        if tarr > W["duration"]:
+            break
+        queries.append((int(rng.integers(8)), int(rng.integers(W["k"][0], W["k"][1] + 1)),
+                        float(rng.choice(W["eps"])), tarr))
+    eng = binding.Engine(ctx, 0)
+    try:
+        for i, (kind, _) in enumerate(spec):
+            m_init, m_max = (1_000, 16_000) if kind == "grid" else (100_000, 6_400_000)
+            eng.add_pool(dgs[i].handle, W["seed"], i, W["t"], m_init, m_max)
+        qids = [eng.submit(gi, k, W["t"], eps, W["delta"], a) for gi, k, eps, a in queries]
+        # resident sample sets: every pool drawn and built to its cap before
+        # the stream starts
+        tp = time.perf_counter()
+        for i, (kind, _) in enumerate(spec):
+            eng.prefill(i, 16_000 if kind == "grid" else 6_400_000, stream=stream)
+        torch.cuda.synchronize()
+        prefill_s = time.perf_counter() - tp
+        log(f"pools prefilled in {prefill_s:.1f}s; {len(queries)} queries over {W['duration']} s")
+        ts = time.perf_counter()
+        eng.run(realtime=True, stream=stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - ts
+        res = [eng.result(q) for q in qids]
+        st = eng.stats()
+        tune_log = eng.log()
+    finally:
+        eng.destroy()
+    lat = [r[3].finished_s - r[3].arrival_s for r in res]
+    waits = [r[3].admitted_s - r[3].arrival_s for r in res]
+    last = max(r[3].finished_s for r in res)
+    by_graph = {}
+    for (gi, k, eps, a), r, l in zip(queries, res, lat):
+        by_graph.setdefault(spec[gi][0], []).append(l)
+    # the same query alone (a fresh engine) equals its result in the mix
+    alone_same = True
+    for idx in range(min(3, len(queries))):
+        gi, k, eps, a = queries[idx]
+        e1 = binding.Engine(ctx, 0, binding.CENTRA_ENGINE_NO_TUNE)
+        try:
+            kind = spec[gi][0]
+            m_init, m_max = (1_000, 16_000) if kind == "grid" else (100_000, 6_400_000)
+            e1.add_pool(dgs[gi].handle, W["seed"], gi, W["t"], m_init, m_max)
+            q = e1.submit(0, k, W["t"], eps, W["delta"], 0.0)
+            e1.run(stream=stream)
+            r1 = e1.result(q)
+        finally:
+            e1.destroy()
+        alone_same &= bool(r1[0] == res[idx][0] and np.array_equal(r1[1], res[idx][1]) and
+                           r1[2].eta == res[idx][2].eta)
+    # the plain form on the first queries: each query alone, one after the
+    # other, with centra_progressive (no shared samples): its service time
+    plain_times = []
+    for gi, k, eps, a in queries[:args.plain_queries]:
+        kind = spec[gi][0]
+        m_init, m_max = (1_000, 16_000) if kind == "grid" else (100_000, 6_400_000)
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        binding.centra_progressive(ctx, dgs[gi].handle, k, W["t"], eps, W["delta"], W["seed"], gi, m_init, m_max,
+                                   stream=stream)
+        torch.cuda.synchronize()
+        plain_times.append(time.perf_counter() - tq)
+    for dg in dgs:
+        dg.release()
+    binding.centra_destroy(ctx)
+    served = len(res) / last if last > 0 else None
+    out = {"metric": "serving latency and throughput (continuous batching)", "value": round(served, 2),
+           "unit": "queries/s", "higher_is_better": True, "n_gpus": 1, "steps": 1, "warmup": 0, "dtype": "u64",
+           "data": "synthetic", "config": {"workload": W["label"]},
+           "queries": len(res), "offered_qps": W["rate"], "served_qps": round(served, 2),
+           "wall_s": round(wall, 3), "prefill_s": round(prefill_s, 2),
+           "latency_p50_s": round(percentile(lat, 50), 4), "latency_p99_s": round(percentile(lat, 99), 4),
+           "latency_max_s": round(max(lat), 4), "queue_wait_p50_s": round(percentile(waits, 50), 4),
+           "latency_p50_by_graph_s": {k: round(percentile(v, 50), 4) for k, v in by_graph.items()},
+           "certified": sum(int(r[2].certified) for r in res),
+           "alone_equals_mix": alone_same,
+           "plain_service_s": [round(x, 3) for x in plain_times],
+           "plain_qps_estimate": round(len(plain_times) / sum(plain_times), 3) if plain_times else None,
+           "plain_note": f"the first {len(plain_times)} queries served one at a time by centra_progressive "
+                         "(no shared samples); plain_qps_estimate = queries / their summed service time",
+           "engine": {"ticks": st.ticks, "peak_active": st.peak_active, "greedy_runs": st.greedy_runs,
+                      "sampler_launches": st.sampler_launches,
+                      "samples": st.samples, "graph_replays": st.graph_replays, "tuned_block": st.tuned_block,
+                      "ms_sample": round(st.ms_sample, 1), "ms_levels": round(st.ms_levels, 1),
+                      "ms_greedy": round(st.ms_greedy, 1), "ms_select": round(st.ms_select, 1),
+                      "peak_bytes": st.peak_bytes, "autotune": tune_log.strip()},
+           "device": torch.cuda.get_device_name(0)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,11 +504,13 @@ def main():
     ap.add_argument("--uncapped-max", type=int, default=None,
                     help="sample cap of the extra runs that measure time to certified (0 = skip; default 128M for "
                          "the sparse workload, 32M for the skewed one, 64M for triangles, 10M for small)")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sparse",
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + sorted(ENGINE_WORKLOADS), default="sparse",
                     help="sparse (default): BA n=1e6; skewed: R-MAT scale 22, directed; small: BA n=2,000; "
                          "triangles: the triangle space of R-MAT scale 20, undirected")
     ap.add_argument("--sweep", action="store_true",
                     help="run only the t and m sweeps of the fixed-size bound (one JSON line)")
+    ap.add_argument("--plain-queries", type=int, default=8,
+                    help="serving workload: queries also served one at a time by centra_progressive")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy 8 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -315,6 +530,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        batched_bench(args)
+        return
+    if args.workload == "serving":
+        serving_bench(args)
+        return
     W = dict(WORKLOADS[args.workload])
     tri = W.get("space") == "triangles"
     kp = W.get("space") == "kpaths"

@@ -411,19 +411,21 @@ CENTRA_API int centra_progressive(centra_ctx *ctx, const centra_graph *g, const 
  * every active query's next iteration needs in one fused sampling launch
  * over all pools; builds the new levels (incidence segment, deg_H and
  * Rademacher sums of the pool's first m_j samples); runs the greedy rounds
- * of all active queries fused (one argmax and one covering launch per round
- * for all queries, replayed from a captured HIP graph unless
- * CENTRA_ENGINE_NO_GRAPHS); runs their per-trial top-k selections fused;
+ * of all active queries fused (the queries at one level of one pool share
+ * one run with their largest k, as greedy's first k picks do not depend on
+ * a larger k; one set of round launches serves every run, replayed from a
+ * captured HIP graph unless CENTRA_ENGINE_NO_GRAPHS); runs their per-trial
+ * top-k selections fused;
  * and evaluates every query's bound on the host (one synchronisation),
  * retiring certified queries and those at m_max.  realtime != 0: query
  * arrival times are seconds from the start of the run, admission waits for
  * them (continuous batching: arrivals join the running queries at the next
  * tick); realtime == 0: every query has arrived at the start (batch mode).
  * Admission reserves, for each pool with an active query, the memory of
- * the pool with every level of its schedule built (projected from the
- * mean hyperedge size of its first samples, plus a tenth), and each active
- * query's own state (about 4 n + m_max / 8 bytes); a pool's first samples
- * are drawn when its first query arrives.
+ * the pool with every level of its schedule built and a greedy run's state
+ * per level (projected from the mean hyperedge size of its first samples,
+ * plus a tenth); a pool's first samples are drawn when its first query
+ * arrives.
  * Before the first tick an autotuner times the fused sampling launch with
  * 64, 128, 256 and 512 threads per BFS on the pools' first samples and
  * keeps the fastest (CENTRA_ENGINE_NO_TUNE: 128); the environment variable
@@ -453,7 +455,7 @@ typedef struct {
 } centra_query_info;
 
 typedef struct {
-    uint64_t ticks, sampler_launches, samples, greedy_launches, graph_replays, graphs_captured;
+    uint64_t ticks, sampler_launches, samples, greedy_runs, greedy_launches, graph_replays, graphs_captured;
     double ms_sample, ms_levels, ms_greedy, ms_select;   /* device time per phase, summed */
     uint64_t peak_bytes;
     uint32_t peak_active, tuned_block;
@@ -464,6 +466,11 @@ CENTRA_API void centra_engine_destroy(centra_engine *e);
 /* The graph must stay prepared while the engine lives. */
 CENTRA_API int centra_engine_add_pool(centra_engine *e, const centra_graph *g, const centra_pool_params *params,
                            uint32_t *pool_id);
+/* Draws a pool's samples up to the first level of at least m samples and
+ * builds its levels up to it, ahead of queries (sample sets made resident
+ * before serving starts); the first call also runs the autotuner.  Levels
+ * stay while queries are queued or active on the pool.  Synchronous. */
+CENTRA_API int centra_engine_prefill(centra_engine *e, uint32_t pool_id, uint64_t m, void *stream);
 /* arrival_s must not decrease from one submission to the next. */
 CENTRA_API int centra_engine_submit(centra_engine *e, uint32_t pool_id, uint32_t k, uint32_t t, double eps,
                          double delta, double arrival_s, uint32_t *query_id);

@@ -98,7 +98,7 @@ class QueryInfo(_c.Structure):
 
 class EngineStats(_c.Structure):
     _fields_ = [("ticks", _c.c_uint64), ("sampler_launches", _c.c_uint64), ("samples", _c.c_uint64),
-                ("greedy_launches", _c.c_uint64), ("graph_replays", _c.c_uint64), ("graphs_captured", _c.c_uint64),
+                ("greedy_runs", _c.c_uint64), ("greedy_launches", _c.c_uint64), ("graph_replays", _c.c_uint64), ("graphs_captured", _c.c_uint64),
                 ("ms_sample", _c.c_double), ("ms_levels", _c.c_double), ("ms_greedy", _c.c_double),
                 ("ms_select", _c.c_double), ("peak_bytes", _c.c_uint64), ("peak_active", _c.c_uint32),
                 ("tuned_block", _c.c_uint32)]
@@ -137,6 +137,7 @@ SIGNATURES = {
     "centra_engine_create": (_c.c_int, [_vp, _c.c_size_t, _c.c_uint32, _c.POINTER(_vp)]),
     "centra_engine_destroy": (None, [_vp]),
     "centra_engine_add_pool": (_c.c_int, [_vp, _vp, _c.POINTER(PoolParams), _c.POINTER(_c.c_uint32)]),
+    "centra_engine_prefill": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp]),
     "centra_engine_submit": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint32, _c.c_uint32, _c.c_double, _c.c_double,
                                         _c.c_double, _c.POINTER(_c.c_uint32)]),
     "centra_engine_run": (_c.c_int, [_vp, _c.c_int, _vp]),
@@ -422,6 +423,9 @@ class Engine:
         pid = ctypes.c_uint32()
         _check(lib().centra_engine_add_pool(self.handle, graph_handle, ctypes.byref(p), ctypes.byref(pid)), self.ctx)
         return pid.value
+
+    def prefill(self, pool: int, m: int, stream=None) -> None:
+        _check(lib().centra_engine_prefill(self.handle, pool, m, _stream(stream)), self.ctx)
 
     def submit(self, pool: int, k: int, t: int, eps: float, delta: float, arrival_s: float = 0.0) -> int:
         q = ctypes.c_uint32()

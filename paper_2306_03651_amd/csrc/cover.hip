@@ -242,22 +242,28 @@ __global__ __launch_bounds__(kArgBlock) void k_argmax(const int32_t* gain, uint3
 
 constexpr int kCoverBlock = 256;
 
-// One covering pass, workgroup b of nb: reduces the n_part per-workgroup
-// maxima to the round's pick (workgroup 0 writes it to *best), then walks
-// its share of the pick's incidence rows in the n_seg segments as one row
-// (their concatenation), marking newly covered samples and decrementing
-// the gains of their nodes.
-__device__ __forceinline__ void cover_pass(const uint64_t* part, uint32_t n_part, uint64_t* best, const uint64_t* seg_off,
-                                           uint32_t n_seg, const uint32_t* inc, const uint64_t* he_off,
-                                           const uint32_t* he_nodes, uint32_t n, uint32_t* covered, int32_t* gain,
-                                           uint64_t* newcov, uint32_t b, uint32_t nb, uint64_t* red, AggTable& tab,
-                                           uint64_t* seg_beg, uint64_t* seg_pre) {
-  uint64_t key = 0;
-  for (uint32_t i = threadIdx.x; i < n_part; i += kCoverBlock) key = part[i] > key ? part[i] : key;
-  key = block_max_u64<kCoverBlock>(key, red);
-  if (b == 0 && threadIdx.x == 0) *best = key;
-  if ((key >> 32) == 0) return;
-  const uint32_t u = 0xFFFFFFFFu - static_cast<uint32_t>(key);
+// LDS of a covering walk.
+struct CoverShared {
+  AggTable tab;
+  uint64_t red[kCoverBlock / kWave];
+  uint64_t seg_beg[kMaxSegments], seg_pre[kMaxSegments + 1];
+  uint32_t scan[kCoverBlock / kWave + 1];
+  uint32_t hs[kCoverBlock];    // newly covered samples of this step
+  uint32_t hoff[kCoverBlock];  // exclusive prefix of their hyperedge sizes
+};
+
+// The walk of one covering pass, workgroup b of nb, for the pick u: its
+// share of u's incidence rows in the n_seg segments walked as one row
+// (their concatenation), one entry per thread per step.  A step marks the
+// newly covered samples among its entries, then the workgroup decrements
+// the gains of all their nodes together (the concatenation of their
+// hyperedges split evenly over the threads), so long hyperedges (paths of
+// thousands of nodes) are spread over the workgroup instead of walked by
+// one thread.
+__device__ __forceinline__ void cover_walk(uint32_t u, const uint64_t* seg_off, uint32_t n_seg, const uint32_t* inc,
+                                           const uint64_t* he_off, const uint32_t* he_nodes, uint32_t n,
+                                           uint32_t* covered, int32_t* gain, uint64_t* newcov, uint32_t b, uint32_t nb,
+                                           CoverShared& sh) {
   if (threadIdx.x < kWave) {   // segment starts and the prefix of the row lengths (n_seg <= 64)
     const uint32_t g = threadIdx.x;
     uint64_t rb = 0, len = 0;
@@ -268,35 +274,80 @@ __device__ __forceinline__ void cover_pass(const uint64_t* part, uint32_t n_part
     }
     const uint64_t incl = wave_incl_scan_u64(len);
     if (g < n_seg) {
-      seg_beg[g] = rb;
-      seg_pre[g + 1] = incl;
+      sh.seg_beg[g] = rb;
+      sh.seg_pre[g + 1] = incl;
     }
-    if (g == 0) seg_pre[0] = 0;
+    if (g == 0) sh.seg_pre[0] = 0;
   }
   __syncthreads();
-  const uint64_t row = seg_pre[n_seg];
+  const uint64_t row = sh.seg_pre[n_seg];
   const uint64_t lead = b * uint64_t(kCoverBlock);
-  if (lead >= row) return;   // uniform per workgroup: nothing of the row lands here
-  agg_init(tab);
+  if (lead >= row) {   // uniform per workgroup: nothing of the row lands here
+    __syncthreads();   // seg_* are reused by the caller's next item
+    return;
+  }
+  agg_init(sh.tab);
   __syncthreads();
   uint64_t cnt = 0;
   uint32_t g = 0;
-  for (uint64_t q = lead + threadIdx.x; q < row; q += uint64_t(nb) * kCoverBlock) {
-    while (q >= seg_pre[g + 1]) ++g;
-    const uint32_t s = inc[seg_beg[g] + (q - seg_pre[g])];
-    const uint32_t bit = 1u << (s & 31u);
-    const uint32_t old = atomicOr(&covered[s >> 5], bit);
-    if (old & bit) continue;
-    ++cnt;
-    for (uint64_t x = he_off[s]; x < he_off[s + 1]; ++x) {
-      const uint32_t v = he_nodes[x];
-      if (v < n && !agg_add(tab, v)) atomicSub(&gain[v], 1);
+  const uint64_t stride = uint64_t(nb) * kCoverBlock;
+  for (uint64_t base = lead; base < row; base += stride) {   // uniform trip count
+    const uint64_t q = base + threadIdx.x;
+    uint32_t s = kUnseen, len = 0;
+    if (q < row) {
+      while (q >= sh.seg_pre[g + 1]) ++g;
+      s = inc[sh.seg_beg[g] + (q - sh.seg_pre[g])];
+      const uint32_t bit = 1u << (s & 31u);
+      const uint32_t old = atomicOr(&covered[s >> 5], bit);
+      if (old & bit) {
+        s = kUnseen;
+      } else {
+        ++cnt;
+        len = static_cast<uint32_t>(he_off[s + 1] - he_off[s]);
+      }
     }
+    uint32_t total;
+    const uint32_t off = block_excl_scan_u32<kCoverBlock>(len, &total, sh.scan);
+    sh.hs[threadIdx.x] = s;
+    sh.hoff[threadIdx.x] = off;
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < total; e += kCoverBlock) {
+      // the sample holding entry e: the last i with hoff[i] <= e and a
+      // nonempty hyperedge (empty ones repeat their successor's offset)
+      int lo = 0, hi = kCoverBlock - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sh.hoff[mid] <= e)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const uint32_t v = he_nodes[he_off[sh.hs[lo]] + (e - sh.hoff[lo])];
+      if (v < n && !agg_add(sh.tab, v)) atomicSub(&gain[v], 1);
+    }
+    __syncthreads();
   }
-  cnt = block_sum_u64<kCoverBlock>(cnt, red);   // contains the barrier before the flush
+  cnt = block_sum_u64<kCoverBlock>(cnt, sh.red);   // contains the barrier before the flush
   for (uint32_t i = threadIdx.x; i < kAggSize; i += kCoverBlock)
-    if (tab.key[i] != kUnseen) atomicSub(&gain[tab.key[i]], static_cast<int32_t>(tab.cnt[i]));
+    if (sh.tab.key[i] != kUnseen) atomicSub(&gain[sh.tab.key[i]], static_cast<int32_t>(sh.tab.cnt[i]));
   if (threadIdx.x == 0 && cnt) atomicAdd(reinterpret_cast<unsigned long long*>(newcov), cnt);
+  __syncthreads();   // the table and seg_* are reused by the caller's next item
+}
+
+// One covering pass, workgroup b of nb: reduces the n_part per-workgroup
+// maxima to the round's pick (workgroup 0 writes it to *best), then walks
+// its share of the pick's rows.
+__device__ __forceinline__ void cover_pass(const uint64_t* part, uint32_t n_part, uint64_t* best, const uint64_t* seg_off,
+                                           uint32_t n_seg, const uint32_t* inc, const uint64_t* he_off,
+                                           const uint32_t* he_nodes, uint32_t n, uint32_t* covered, int32_t* gain,
+                                           uint64_t* newcov, uint32_t b, uint32_t nb, CoverShared& sh) {
+  uint64_t key = 0;
+  for (uint32_t i = threadIdx.x; i < n_part; i += kCoverBlock) key = part[i] > key ? part[i] : key;
+  key = block_max_u64<kCoverBlock>(key, sh.red);
+  if (b == 0 && threadIdx.x == 0) *best = key;
+  if ((key >> 32) == 0) return;
+  cover_walk(0xFFFFFFFFu - static_cast<uint32_t>(key), seg_off, n_seg, inc, he_off, he_nodes, n, covered, gain, newcov,
+             b, nb, sh);
 }
 
 // best = the round's pick (written by workgroup 0): the largest of the
@@ -305,11 +356,9 @@ __global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* part, uin
                                                        const uint64_t* seg_off, uint32_t n_seg, const uint32_t* inc,
                                                        const uint64_t* he_off, const uint32_t* he_nodes, uint32_t n,
                                                        uint32_t* covered, int32_t* gain, uint64_t* newcov) {
-  __shared__ uint64_t red[kCoverBlock / kWave];
-  __shared__ AggTable tab;
-  __shared__ uint64_t seg_beg[kMaxSegments], seg_pre[kMaxSegments + 1];
+  __shared__ CoverShared sh;
   cover_pass(part, n_part, best, seg_off, n_seg, inc, he_off, he_nodes, n, covered, gain, newcov, blockIdx.x, gridDim.x,
-             red, tab, seg_beg, seg_pre);
+             sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -318,6 +367,42 @@ __global__ __launch_bounds__(kCoverBlock) void k_cover(const uint64_t* part, uin
 // inactive (k = 0), leaves its workgroups at once.  The round number comes
 // from device memory (round_base[0] + r_local), so a captured sequence of
 // rounds can be replayed for the next rounds after the base is advanced.
+//
+// Candidate lists.  Gains only decrease, so once every node of gain >= tau
+// has been collected into a list, every node outside the list stays below
+// tau; while the list's largest gain is >= tau, the argmax over the list
+// (largest gain, lowest id) is the argmax over all nodes, and a round reads
+// the list's gains instead of all n.  A query cycles through three modes,
+// decided after each round from device state:
+//   full     every workgroup scans its slice of all n gains and adds a
+//            histogram of them (8 bins per octave); after the round, tau is
+//            the lowest bin bound whose bins and those above hold at most
+//            kCandMax nodes (if any);
+//   compact  a full scan that also appends every node of gain >= tau to the
+//            list (at most kCandMax: gains were at most the histogram's);
+//   list     one workgroup scans the list.
+// The round after a list's largest gain falls below tau is full again.
+constexpr uint32_t kCandMax = 8192;
+constexpr uint32_t kGainBins = 256;
+constexpr uint32_t kModeFull = 0, kModeCompact = 1, kModeList = 2;
+
+// Bin of a positive gain: 8 bins per bit length, by the 3 bits below the
+// leading one (nondecreasing in g).
+__device__ __forceinline__ uint32_t gain_bin(uint32_t g) {
+  const uint32_t bl = 32u - __clz(g);
+  const uint32_t sub = bl >= 4 ? (g >> (bl - 4)) & 7u : (g << (4 - bl)) & 7u;
+  return (bl - 1) * 8 + sub;
+}
+
+// Smallest gain of bin b (or of the next nonempty bin above it).
+__device__ __forceinline__ uint32_t bin_min(uint32_t b) {
+  const uint32_t bl = b / 8 + 1, sub = b % 8;
+  if (bl >= 4) return (8u + sub) << (bl - 4);
+  for (uint32_t g = 1; g < 16; ++g)
+    if (gain_bin(g) >= b) return g;
+  return 16;
+}
+
 __global__ __launch_bounds__(256) void k_greedy_init_multi(const GreedyDesc* d) {
   const GreedyDesc q = d[blockIdx.y];
   if (q.k == 0) return;
@@ -329,33 +414,163 @@ __global__ __launch_bounds__(256) void k_greedy_init_multi(const GreedyDesc* d) 
     q.best[r] = 0;
     q.newcov[r] = 0;
   }
+  for (uint64_t b = i0; b < kGainBins; b += stride) q.hist[b] = 0;
+  if (i0 == 0) {
+    q.cst[0] = kModeFull;
+    q.cst[1] = 0;
+    q.cst[2] = 0;
+  }
 }
 
-__global__ __launch_bounds__(kArgBlock) void k_argmax_multi(const GreedyDesc* d, const uint32_t* round_base,
-                                                            uint32_t r_local) {
+// Items (query, slice b of S): the argmax of every query's slices, or of its
+// list (slice 0), grid-strided so that finished queries and list-mode
+// slices cost one check each instead of a workgroup launch.
+__global__ __launch_bounds__(kArgBlock) void k_argmax_multi(const GreedyDesc* d, uint32_t n_q, uint32_t S,
+                                                            const uint32_t* round_base, uint32_t r_local) {
   __shared__ uint64_t red[kArgBlock / kWave];
-  const GreedyDesc& q = d[blockIdx.y];
+  __shared__ uint32_t hist[kGainBins];
   const uint32_t r = round_base[0] + r_local;
-  if (r >= q.k) return;
-  const uint64_t key = argmax_slice(q.gain, q.n, blockIdx.x, gridDim.x, red);
-  if (threadIdx.x == 0) q.part[blockIdx.x] = key;
+  const uint64_t items = uint64_t(n_q) * S;
+  for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const GreedyDesc& q = d[it / S];
+    const uint32_t b = static_cast<uint32_t>(it % S);
+    if (r >= q.k) continue;
+    const uint32_t mode = q.cst[0];
+    if (mode == kModeList) {
+      if (b != 0) continue;
+      const uint32_t cnt = min(q.cst[2], kCandMax);
+      uint64_t key = 0;
+      for (uint32_t i = threadIdx.x; i < cnt; i += kArgBlock) {
+        const uint32_t u = q.cand[i];
+        const int32_t g = q.gain[u];
+        const uint64_t k = g > 0 ? (static_cast<uint64_t>(g) << 32) | (0xFFFFFFFFu - u) : 0ull;
+        key = k > key ? k : key;
+      }
+      key = block_max_u64<kArgBlock>(key, red);
+      if (threadIdx.x == 0) q.part[0] = key;
+      continue;
+    }
+    const uint32_t tau = q.cst[1];
+    if (mode == kModeFull) {
+      for (uint32_t i = threadIdx.x; i < kGainBins; i += kArgBlock) hist[i] = 0;
+      __syncthreads();
+    }
+    uint64_t key = 0;
+    for (uint32_t u = b * kArgBlock + threadIdx.x; u < q.n; u += S * kArgBlock) {
+      const int32_t g = q.gain[u];
+      if (g <= 0) continue;
+      const uint64_t k = (static_cast<uint64_t>(g) << 32) | (0xFFFFFFFFu - u);
+      key = k > key ? k : key;
+      if (mode == kModeFull) {
+        atomicAdd(&hist[gain_bin(static_cast<uint32_t>(g))], 1u);
+      } else if (static_cast<uint32_t>(g) >= tau) {
+        const uint32_t at = atomicAdd(&q.cst[2], 1u);
+        if (at < kCandMax) q.cand[at] = u;
+      }
+    }
+    key = block_max_u64<kArgBlock>(key, red);   // contains barriers
+    if (threadIdx.x == 0) q.part[b] = key;
+    if (mode == kModeFull) {
+      for (uint32_t i = threadIdx.x; i < kGainBins; i += kArgBlock)
+        if (hist[i]) atomicAdd(&q.hist[i], hist[i]);
+      __syncthreads();
+    }
+  }
 }
 
-__global__ __launch_bounds__(kCoverBlock) void k_cover_multi(const GreedyDesc* d, uint32_t n_part,
-                                                             const uint32_t* round_base, uint32_t r_local) {
-  __shared__ uint64_t red[kCoverBlock / kWave];
-  __shared__ AggTable tab;
-  __shared__ uint64_t seg_beg[kMaxSegments], seg_pre[kMaxSegments + 1];
-  const GreedyDesc& q = d[blockIdx.y];
+// One workgroup per query: the round's pick from the argmax maxima (S of
+// them, or one in list mode), written to best[r]; 0 once a round found no
+// positive gain.  cst[3] receives the pick's row length over the segments.
+__global__ __launch_bounds__(256) void k_pick_multi(const GreedyDesc* d, uint32_t S, const uint32_t* round_base,
+                                                    uint32_t r_local) {
+  __shared__ uint64_t red[256 / kWave];
+  const GreedyDesc& q = d[blockIdx.x];
   const uint32_t r = round_base[0] + r_local;
   if (r >= q.k) return;
-  // stop early when the previous round found no positive gain
   if (r > 0 && (q.best[r - 1] >> 32) == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) q.best[r] = 0;
+    if (threadIdx.x == 0) q.best[r] = 0;
     return;
   }
-  cover_pass(q.part, n_part, q.best + r, q.seg_off, q.n_seg, q.inc, q.he_off, q.he_nodes, q.n, q.covered, q.gain,
-             q.newcov + r, blockIdx.x, gridDim.x, red, tab, seg_beg, seg_pre);
+  const uint32_t parts = q.cst[0] == kModeList ? 1u : S;
+  uint64_t key = 0;
+  for (uint32_t i = threadIdx.x; i < parts; i += 256) key = q.part[i] > key ? q.part[i] : key;
+  key = block_max_u64<256>(key, red);
+  uint64_t len = 0;
+  if ((key >> 32) != 0) {
+    const uint32_t u = 0xFFFFFFFFu - static_cast<uint32_t>(key);
+    for (uint32_t g = threadIdx.x; g < q.n_seg; g += 256) {
+      const uint64_t* o = q.seg_off + size_t(g) * (size_t(q.n) + 1);
+      len += o[u + 1] - o[u];
+    }
+  }
+  len = block_sum_u64<256>(len, red);
+  if (threadIdx.x == 0) {
+    q.best[r] = key;
+    q.cst[3] = static_cast<uint32_t>(len < 0xFFFFFFFFull ? len : 0xFFFFFFFFull);
+  }
+}
+
+// Items (query, part b of S): the covering walk of each query's pick.
+__global__ __launch_bounds__(kCoverBlock) void k_cover_multi(const GreedyDesc* d, uint32_t n_q, uint32_t S,
+                                                             const uint32_t* round_base, uint32_t r_local) {
+  __shared__ CoverShared sh;
+  const uint32_t r = round_base[0] + r_local;
+  const uint64_t items = uint64_t(n_q) * S;
+  for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const GreedyDesc& q = d[it / S];
+    const uint32_t b = static_cast<uint32_t>(it % S);
+    if (r >= q.k) continue;
+    const uint64_t key = q.best[r];
+    if ((key >> 32) == 0) continue;
+    if (uint64_t(b) * kCoverBlock >= q.cst[3]) continue;   // nothing of the row lands here
+    cover_walk(0xFFFFFFFFu - static_cast<uint32_t>(key), q.seg_off, q.n_seg, q.inc, q.he_off, q.he_nodes, q.n,
+               q.covered, q.gain, q.newcov + r, b, S, sh);
+  }
+}
+
+// After a round: the next round's mode (see the candidate lists above).
+__global__ __launch_bounds__(256) void k_greedy_post_multi(const GreedyDesc* d, const uint32_t* round_base,
+                                                           uint32_t r_local) {
+  __shared__ uint64_t red[256 / kWave];
+  __shared__ uint32_t pick;
+  const GreedyDesc& q = d[blockIdx.x];
+  const uint32_t r = round_base[0] + r_local;
+  if (r >= q.k) return;
+  const uint32_t mode = q.cst[0];
+  if (mode == kModeFull) {
+    if (threadIdx.x == 0) {
+      // lowest bin whose bins and those above hold at most kCandMax nodes
+      uint32_t cum = 0, found = kGainBins;
+      for (int b = kGainBins - 1; b >= 0; --b) {
+        if (cum + q.hist[b] > kCandMax) break;
+        cum += q.hist[b];
+        found = static_cast<uint32_t>(b);
+      }
+      pick = cum > 0 && found < kGainBins ? found : kGainBins;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && pick < kGainBins) {
+      q.cst[1] = bin_min(pick);
+      q.cst[2] = 0;
+      q.cst[0] = kModeCompact;
+    }
+    for (uint32_t b = threadIdx.x; b < kGainBins; b += 256) q.hist[b] = 0;
+    return;
+  }
+  // list or compact: keep using the list while its largest gain is >= tau
+  // (a list that overflowed is incomplete: never used)
+  if (q.cst[2] > kCandMax) {
+    if (threadIdx.x == 0) q.cst[0] = kModeFull;
+    return;
+  }
+  const uint32_t cnt = q.cst[2];
+  uint64_t mx = 0;
+  for (uint32_t i = threadIdx.x; i < cnt; i += 256) {
+    const int32_t g = q.gain[q.cand[i]];
+    mx = g > 0 && static_cast<uint64_t>(g) > mx ? static_cast<uint64_t>(g) : mx;
+  }
+  mx = block_max_u64<256>(mx, red);
+  if (threadIdx.x == 0) q.cst[0] = mx >= q.cst[1] && mx > 0 ? kModeList : kModeFull;
 }
 
 __global__ void k_round_advance(uint32_t* round_base, uint32_t by) {
@@ -381,12 +596,22 @@ void greedy_multi_init(const GreedyDesc* d, uint32_t n_q, uint32_t max_n, hipStr
   hipLaunchKernelGGL(k_greedy_init_multi, dim3(grid_for(max_n, 256, 1024), n_q), dim3(256), 0, s, d);
 }
 
+// Slices per query of the multi-query argmax: at least 16 nodes per thread,
+// at most kArgGrid.
+static uint32_t argmax_slices(uint32_t max_n) {
+  return grid_for((uint64_t(max_n) + 15) / 16, kArgBlock, kArgGrid);
+}
+
 void greedy_multi_rounds(const GreedyDesc* d, uint32_t n_q, uint32_t max_n, uint32_t cover_grid, uint32_t* round_base,
                          uint32_t rounds, hipStream_t s) {
-  const unsigned ga = grid_for(max_n, kArgBlock, kArgGrid);
+  const uint32_t Sa = argmax_slices(max_n);
+  const unsigned ga = grid_for(uint64_t(n_q) * Sa, 1, 4096);
+  const unsigned gc = grid_for(uint64_t(n_q) * cover_grid, 1, 4096);
   for (uint32_t r = 0; r < rounds; ++r) {
-    hipLaunchKernelGGL(k_argmax_multi, dim3(ga, n_q), dim3(kArgBlock), 0, s, d, round_base, r);
-    hipLaunchKernelGGL(k_cover_multi, dim3(cover_grid, n_q), dim3(kCoverBlock), 0, s, d, ga, round_base, r);
+    hipLaunchKernelGGL(k_argmax_multi, dim3(ga), dim3(kArgBlock), 0, s, d, n_q, Sa, round_base, r);
+    hipLaunchKernelGGL(k_pick_multi, dim3(n_q), dim3(256), 0, s, d, Sa, round_base, r);
+    hipLaunchKernelGGL(k_cover_multi, dim3(gc), dim3(kCoverBlock), 0, s, d, n_q, cover_grid, round_base, r);
+    hipLaunchKernelGGL(k_greedy_post_multi, dim3(n_q), dim3(256), 0, s, d, round_base, r);
   }
   hipLaunchKernelGGL(k_round_advance, dim3(1), dim3(64), 0, s, round_base, rounds);
 }
@@ -394,6 +619,9 @@ void greedy_multi_rounds(const GreedyDesc* d, uint32_t n_q, uint32_t max_n, uint
 void greedy_multi_finish(const GreedyDesc* d, uint32_t n_q, hipStream_t s) {
   hipLaunchKernelGGL(k_greedy_finish_multi, dim3(n_q), dim3(64), 0, s, d);
 }
+
+uint32_t greedy_cand_words() { return kCandMax; }
+uint32_t greedy_hist_words() { return kGainBins; }
 
 uint32_t greedy_part_words() { return kArgGrid; }
 

@@ -124,7 +124,6 @@ struct EngineQuery {
   int state = 0;   // 0 queued, 1 active, 2 done
   uint32_t level = 0;
   int rc = 0;
-  DevBuf gain, covered, part, best, newcov;
   centra_result res{};
   std::vector<uint32_t> picks;
   size_t bytes = 0;
@@ -132,8 +131,17 @@ struct EngineQuery {
 
 }  // namespace centra
 
+namespace centra {
+// The device state of one greedy run of a tick (shared by the queries at
+// one level of one pool); reused from tick to tick.
+struct GreedyWs {
+  DevBuf gain, covered, part, best, cand;   // best: best | newcov; cand: list | state | histogram
+};
+}  // namespace centra
+
 struct centra_engine {
   centra_ctx* ctx = nullptr;
+  std::vector<centra::GreedyWs> ws;
   size_t budget = 0;
   uint32_t flags = 0;
   std::vector<centra::EnginePool> pools;
@@ -162,13 +170,16 @@ static size_t pool_bytes(const EnginePool& p) {
   return b;
 }
 
+static size_t ws_bytes(const GreedyWs& w);
+
 static size_t engine_bytes(const centra_engine* e) {
   size_t b = 0;
   for (const EnginePool& p : e->pools) b += pool_bytes(p);
-  for (const EngineQuery& q : e->queries)
-    if (q.state == 1) b += q.bytes;
+  for (const GreedyWs& w : e->ws) b += ws_bytes(w);
   return b;
 }
+
+static size_t cand_bytes() { return (size_t(greedy_cand_words()) + 4 + greedy_hist_words()) * 4 + 256; }
 
 // Device bytes a pool reaches with every level of its schedule built (none
 // released), from the mean hyperedge size of the samples it holds, plus a
@@ -179,46 +190,28 @@ static size_t pool_projection(const EnginePool& p) {
   const double mean_h = p.m_have ? double(p.I_have) / double(p.m_have) : 0.0;
   const size_t I = static_cast<size_t>(mean_h * double(M)) + 1;
   const size_t Wt = (t + 63) / 64;
+  // per level: R_j and deg_j, and one greedy run's state (gains, covered
+  // bitmap, candidate list, round state for k up to 1,024)
+  const size_t per_level = n * (t + 1) * 4 + n * 4 + (M / 32 + 1) * 4 + cand_bytes() + greedy_part_words() * 8 +
+                           1024 * 16;
   const size_t b = (M + 1) * 8 + I * 12 + M * Wt * 8 + n * t * 4 + L * (n + 1) * 8 + n * 24 +
-                   scan_tile_words(n) * 8 + 64 * 4 + L * n * (t + 1) * 4;
+                   scan_tile_words(n) * 8 + 64 * 4 + L * per_level;
   return b + b / 10;
 }
 
 // Memory that admission compares with the budget: each pool with an
-// active query at its projection (or its present size if larger), idle
-// pools at their present size, and the active queries' own state.
+// active query at its projection (which includes its greedy runs' state)
+// or its present size if larger, idle pools at their present size.
 static size_t engine_reserved(const centra_engine* e) {
   size_t b = 0;
   for (const EnginePool& p : e->pools) b += p.active ? std::max(pool_bytes(p), pool_projection(p)) : pool_bytes(p);
-  for (const EngineQuery& q : e->queries)
-    if (q.state == 1) b += q.bytes;
   return b;
 }
 
-// Device bytes a query's own state takes: gains, covered bitmap at the
-// pool's largest sample, round state.
-static size_t query_bytes(const EnginePool& p, uint32_t k) {
-  const size_t n = p.g->n;
-  return n * 4 + ((p.p.m_max + 31) / 32 + 1) * 4 + size_t(greedy_part_words()) * 8 + size_t(k) * 16 + 4 * 256;
-}
 
-static int alloc_query(centra_engine* e, EngineQuery& q) {
-  centra_ctx* ctx = e->ctx;
-  const EnginePool& p = e->pools[q.pool];
-  int rc;
-  if ((rc = ensure(ctx, q.gain, size_t(p.g->n) * 4))) return rc;
-  if ((rc = ensure(ctx, q.covered, ((p.p.m_max + 31) / 32 + 1) * 4))) return rc;
-  if ((rc = ensure(ctx, q.part, size_t(greedy_part_words()) * 8))) return rc;
-  if ((rc = ensure(ctx, q.best, size_t(q.k) * 8))) return rc;
-  if ((rc = ensure(ctx, q.newcov, size_t(q.k) * 8))) return rc;
-  q.bytes = q.gain.bytes + q.covered.bytes + q.part.bytes + q.best.bytes + q.newcov.bytes;
-  return CENTRA_OK;
-}
 
-static void free_query(centra_engine* e, EngineQuery& q) {
-  DevBuf* bufs[] = {&q.gain, &q.covered, &q.part, &q.best, &q.newcov};
-  for (DevBuf* b : bufs) release(e->ctx, *b);
-  q.bytes = 0;
+static size_t ws_bytes(const GreedyWs& w) {
+  return w.gain.bytes + w.covered.bytes + w.part.bytes + w.best.bytes + w.cand.bytes;
 }
 
 // Draws the samples of every pool up to its target level in one fused
@@ -436,7 +429,7 @@ static int greedy_rounds(centra_engine* e, uint32_t cap_q, uint32_t max_n, uint3
   if (e->flags & CENTRA_ENGINE_NO_GRAPHS) {
     for (uint32_t c = 0; c < chunks; ++c) greedy_multi_rounds(d, cap_q, max_n, gc, rb, kRoundChunk, s);
     CENTRA_HIP(ctx, hipGetLastError());
-    e->st.greedy_launches += uint64_t(chunks) * (2 * kRoundChunk + 1);
+    e->st.greedy_launches += uint64_t(chunks) * (4 * kRoundChunk + 1);
     return CENTRA_OK;
   }
   if (e->graphs_for != e->descs.ptr) {   // the descriptor buffer moved: drop graphs that read the old one
@@ -444,8 +437,7 @@ static int greedy_rounds(centra_engine* e, uint32_t cap_q, uint32_t max_n, uint3
     e->graphs.clear();
     e->graphs_for = e->descs.ptr;
   }
-  const unsigned ga = max_n ? (max_n + 255) / 256 : 1;
-  const auto gkey = std::make_tuple(cap_q, std::min(ga, greedy_part_words()), gc);
+  const auto gkey = std::make_tuple(cap_q, max_n, gc);
   auto it = e->graphs.find(gkey);
   if (it == e->graphs.end()) {
     hipGraph_t graph = nullptr;
@@ -530,9 +522,9 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
       if (p.active) break;
       reset_levels(e, p);
     }
-    // the query's own state and, if its pool is idle, the pool's projection
+    // if its pool is idle, the pool's projection
     const size_t pool_add = p.active ? 0 : std::max(pool_bytes(p), pool_projection(p)) - pool_bytes(p);
-    if (e->budget && engine_reserved(e) + query_bytes(p, q.k) + pool_add > e->budget) {
+    if (e->budget && engine_reserved(e) + pool_add > e->budget) {
       bool any_active = false;
       for (const EngineQuery& o : e->queries) any_active |= o.state == 1;
       if (any_active) break;   // wait for memory to free up
@@ -543,11 +535,6 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
       ++e->next_queued;
       *progress = true;
       continue;
-    }
-    if ((rc = alloc_query(e, q))) {
-      if (rc != CENTRA_ENOMEM) return rc;
-      ctx->err.clear();
-      break;
     }
     q.state = 1;
     q.level = 0;
@@ -592,59 +579,117 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
     e->st.ms_levels += ms;
   }
   // 3.-4. fused greedy and selection
+  // Greedy is prefix-consistent in k (its first k picks are the picks of
+  // any larger k on the same sample, with the same cumulative coverage), so
+  // the queries at one level of one pool share a single greedy run with the
+  // largest of their k; queries that also share k share their selection
+  // rows (the largest of their t, each query summing its first t trials).
+  struct GGroup {
+    uint32_t pool, level, k;
+    ResLayout lay;
+  };
+  struct SGroup {
+    uint32_t pool, level, k, t;
+    size_t topk, dk;
+  };
+  std::vector<GGroup> gg;
+  std::vector<SGroup> sg;
+  std::vector<uint32_t> q_gg(act.size()), q_sg(act.size());
+  {
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> gmap;
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, uint32_t> smap;
+    for (size_t a = 0; a < act.size(); ++a) {
+      const EngineQuery& q = e->queries[act[a]];
+      auto gk = std::make_pair(q.pool, q.level);
+      auto git = gmap.find(gk);
+      if (git == gmap.end()) {
+        git = gmap.emplace(gk, static_cast<uint32_t>(gg.size())).first;
+        gg.push_back(GGroup{q.pool, q.level, 0, {}});
+      }
+      gg[git->second].k = std::max(gg[git->second].k, q.k);
+      q_gg[a] = git->second;
+      auto sk = std::make_tuple(q.pool, q.level, q.k);
+      auto sit = smap.find(sk);
+      if (sit == smap.end()) {
+        sit = smap.emplace(sk, static_cast<uint32_t>(sg.size())).first;
+        sg.push_back(SGroup{q.pool, q.level, q.k, 0, 0, 0});
+      }
+      sg[sit->second].t = std::max(sg[sit->second].t, q.t);
+      q_sg[a] = sit->second;
+    }
+  }
   uint32_t cap_q = 1;
-  while (cap_q < act.size()) cap_q <<= 1;
+  while (cap_q < gg.size()) cap_q <<= 1;
   std::vector<GreedyDesc> gd(cap_q);
   memset(gd.data(), 0, gd.size() * sizeof(GreedyDesc));
-  std::vector<ResLayout> lay(act.size());
   size_t res_bytes = 0;
   uint32_t max_n = 0, kmax = 0, n_rows = 0;
   uint64_t max_m = 0;
-  for (size_t a = 0; a < act.size(); ++a) {
-    const EngineQuery& q = e->queries[act[a]];
-    lay[a] = res_layout(res_bytes, q.k, q.t);
-    res_bytes = lay[a].end;
-    n_rows += q.t + 1;
-    const EnginePool& p = e->pools[q.pool];
+  for (GGroup& G : gg) {
+    G.lay = res_layout(res_bytes, G.k, 0);
+    res_bytes = G.lay.end;
+    const EnginePool& p = e->pools[G.pool];
     max_n = std::max(max_n, p.g->n);
-    kmax = std::max(kmax, q.k);
-    max_m = std::max(max_m, p.level_m[q.level]);
+    kmax = std::max(kmax, G.k);
+    max_m = std::max(max_m, p.level_m[G.level]);
+  }
+  for (SGroup& S : sg) {
+    S.topk = res_bytes;
+    S.dk = res_bytes + size_t(S.t) * 8;
+    res_bytes = S.dk + 8;
+    n_rows += S.t + 1;
   }
   if ((rc = ensure(ctx, e->tick_res, res_bytes + 256, false, s))) return rc;
   if ((rc = ensure(ctx, e->descs, size_t(cap_q) * sizeof(GreedyDesc), false, s))) return rc;
   if ((rc = ensure(ctx, e->rows, size_t(n_rows) * sizeof(SelRow), false, s))) return rc;
   if ((rc = ensure(ctx, e->sel_ws, select_ws_bytes(n_rows), false, s))) return rc;
   if ((rc = ensure(ctx, e->round_base, 256, false, s))) return rc;
+  if (e->ws.size() < gg.size()) e->ws.resize(gg.size());
   char* res = static_cast<char*>(e->tick_res.ptr);
-  std::vector<SelRow> rows;
-  rows.reserve(n_rows);
-  for (size_t a = 0; a < act.size(); ++a) {
-    EngineQuery& q = e->queries[act[a]];
-    EnginePool& p = e->pools[q.pool];
-    const uint32_t j = q.level, n = p.g->n;
-    GreedyDesc& d = gd[a];
-    d.gain = static_cast<int32_t*>(q.gain.ptr);
-    d.covered = static_cast<uint32_t*>(q.covered.ptr);
-    d.part = static_cast<uint64_t*>(q.part.ptr);
-    d.best = static_cast<uint64_t*>(q.best.ptr);
-    d.newcov = static_cast<uint64_t*>(q.newcov.ptr);
+  for (size_t gi = 0; gi < gg.size(); ++gi) {
+    const GGroup& G = gg[gi];
+    EnginePool& p = e->pools[G.pool];
+    GreedyWs& w = e->ws[gi];
+    const uint32_t j = G.level, n = p.g->n;
+    if ((rc = ensure(ctx, w.gain, size_t(n) * 4, false, s))) return rc;
+    if ((rc = ensure(ctx, w.covered, ((p.level_m[j] + 31) / 32 + 1) * 4, false, s))) return rc;
+    if ((rc = ensure(ctx, w.part, size_t(greedy_part_words()) * 8, false, s))) return rc;
+    if ((rc = ensure(ctx, w.best, size_t(G.k) * 16, false, s))) return rc;
+    if ((rc = ensure(ctx, w.cand, cand_bytes(), false, s))) return rc;
+    GreedyDesc& d = gd[gi];
+    d.gain = static_cast<int32_t*>(w.gain.ptr);
+    d.covered = static_cast<uint32_t*>(w.covered.ptr);
+    d.part = static_cast<uint64_t*>(w.part.ptr);
+    d.best = static_cast<uint64_t*>(w.best.ptr);
+    d.newcov = d.best + G.k;
+    d.cand = static_cast<uint32_t*>(w.cand.ptr);
+    d.cst = d.cand + greedy_cand_words();
+    d.hist = d.cst + 4;
     d.deg = static_cast<const uint32_t*>(p.deg[j].ptr);
     d.seg_off = static_cast<const uint64_t*>(p.seg_off.ptr);
     d.inc = static_cast<const uint32_t*>(p.inc.ptr);
     d.he_off = static_cast<const uint64_t*>(p.off.ptr);
     d.he_nodes = static_cast<const uint32_t*>(p.nodes.ptr);
-    d.picks = reinterpret_cast<uint32_t*>(res + lay[a].picks);
-    d.cov_cum = reinterpret_cast<uint64_t*>(res + lay[a].cov);
-    d.n_picked = reinterpret_cast<uint32_t*>(res + lay[a].np);
+    d.picks = reinterpret_cast<uint32_t*>(res + G.lay.picks);
+    d.cov_cum = reinterpret_cast<uint64_t*>(res + G.lay.cov);
+    d.n_picked = reinterpret_cast<uint32_t*>(res + G.lay.np);
     d.m = p.level_m[j];
     d.n = n;
     d.n_seg = j + 1;
-    d.k = q.k;
-    const int32_t* R = static_cast<const int32_t*>(p.R[j].ptr);
-    for (uint32_t r = 0; r < q.t; ++r)
-      rows.push_back(SelRow{R + size_t(r) * n, n, q.k, reinterpret_cast<int64_t*>(res + lay[a].topk) + r});
-    rows.push_back(SelRow{reinterpret_cast<const int32_t*>(d.deg), n, q.k, reinterpret_cast<int64_t*>(res + lay[a].dk)});
+    d.k = G.k;
   }
+  std::vector<SelRow> rows;
+  rows.reserve(n_rows);
+  for (const SGroup& S : sg) {
+    const EnginePool& p = e->pools[S.pool];
+    const uint32_t n = p.g->n;
+    const int32_t* R = static_cast<const int32_t*>(p.R[S.level].ptr);
+    for (uint32_t r = 0; r < S.t; ++r)
+      rows.push_back(SelRow{R + size_t(r) * n, n, S.k, reinterpret_cast<int64_t*>(res + S.topk) + r});
+    rows.push_back(SelRow{static_cast<const int32_t*>(p.deg[S.level].ptr), n, S.k,
+                          reinterpret_cast<int64_t*>(res + S.dk)});
+  }
+  e->st.greedy_runs += gg.size();
   GreedyDesc* dd = static_cast<GreedyDesc*>(e->descs.ptr);
   SelRow* dr = static_cast<SelRow*>(e->rows.ptr);
   CENTRA_HIP(ctx, hipMemcpyAsync(dd, gd.data(), gd.size() * sizeof(GreedyDesc), hipMemcpyHostToDevice, s));
@@ -652,13 +697,17 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
   hipEvent_t* ev = ctx->ev;
   CENTRA_HIP(ctx, hipEventRecord(ev[4], s));
   greedy_multi_init(dd, cap_q, max_n, s);
-  // cover workgroups: enough for the longest incidence row a query can
-  // meet (at most its sample size), 256 entries each, at most 1,024
-  uint32_t gc = static_cast<uint32_t>(std::min<uint64_t>(1024, (max_m + 255) / 256));
+  // cover parts per run: enough for the longest incidence row a run can
+  // meet (at most its sample size) at 256 entries each, at most 256 (a
+  // part then walks its share of the row in strides)
+  uint32_t gc = static_cast<uint32_t>(std::min<uint64_t>(256, (max_m + 255) / 256));
   gc = std::max<uint32_t>(gc, 16);
   uint32_t gcp = 16;
   while (gcp < gc) gcp <<= 1;   // a few graph shapes only
-  if ((rc = greedy_rounds(e, cap_q, max_n, gcp, kmax, s))) return rc;
+  // the captured graphs are keyed by the argmax shape: round max_n up
+  uint32_t max_n_key = 4096;
+  while (max_n_key < max_n) max_n_key <<= 1;
+  if ((rc = greedy_rounds(e, cap_q, max_n_key, gcp, kmax, s))) return rc;
   greedy_multi_finish(dd, cap_q, s);
   CENTRA_HIP(ctx, hipEventRecord(ev[5], s));
   select_topk_rows(dr, n_rows, max_n, e->sel_ws.ptr, s);
@@ -675,29 +724,32 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
   e->st.ms_select += ms_s;
   // 5. bounds on the host
   const double t_done = now_s() - e->run_t0;
+  const char* hb = host.data();
   for (size_t a = 0; a < act.size(); ++a) {
     EngineQuery& q = e->queries[act[a]];
     EnginePool& p = e->pools[q.pool];
     const uint32_t j = q.level;
-    const char* hb = host.data();
+    const GGroup& G = gg[q_gg[a]];
+    const SGroup& S = sg[q_sg[a]];
     uint32_t np = 0;
-    memcpy(&np, hb + lay[a].np, 4);
+    memcpy(&np, hb + G.lay.np, 4);
+    if (np > q.k) np = q.k;   // the first k picks of the shared run
     uint64_t cov = 0;
-    if (np) memcpy(&cov, hb + lay[a].cov + size_t(np - 1) * 8, 8);
+    if (np) memcpy(&cov, hb + G.lay.cov + size_t(np - 1) * 8, 8);
     int64_t sum = 0;
     for (uint32_t r = 0; r < q.t; ++r) {
       int64_t x;
-      memcpy(&x, hb + lay[a].topk + size_t(r) * 8, 8);
+      memcpy(&x, hb + S.topk + size_t(r) * 8, 8);
       sum += x;
     }
     int64_t dk = 0;
-    memcpy(&dk, hb + lay[a].dk, 8);
+    memcpy(&dk, hb + S.dk, 8);
     const uint64_t m = p.level_m[j];
     const double delta_i = ldexp(q.delta, -static_cast<int>(j + 1));
     centra_bound_out o;
     bound_eval(m, cov, sum, q.t, static_cast<uint64_t>(dk), p.bmax_host[j], q.eps, delta_i, &o);
     q.picks.assign(q.k, 0);
-    memcpy(q.picks.data(), hb + lay[a].picks, size_t(np) * 4);
+    memcpy(q.picks.data(), hb + G.lay.picks, size_t(np) * 4);
     centra_result& r = q.res;
     r.n_picked = np;
     r.iterations = j + 1;
@@ -718,7 +770,6 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
       q.rc = o.certified ? CENTRA_OK : CENTRA_NOT_CERTIFIED;
       q.finished = t_done;
       p.active -= 1;
-      free_query(e, q);
     } else {
       q.level = j + 1;
     }
@@ -762,7 +813,10 @@ void centra_engine_destroy(centra_engine* e) {
   centra_ctx* ctx = e->ctx;
   (void)hipDeviceSynchronize();
   for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
-  for (EngineQuery& q : e->queries) free_query(e, q);
+  for (GreedyWs& w : e->ws) {
+    DevBuf* wb[] = {&w.gain, &w.covered, &w.part, &w.best, &w.cand};
+    for (DevBuf* b : wb) release(ctx, *b);
+  }
   for (EnginePool& p : e->pools) {
     DevBuf* bufs[] = {&p.off, &p.nodes, &p.inc, &p.inc_node, &p.seg_off, &p.cursor, &p.sdeg, &p.deg_cur, &p.tiles,
                       &p.words, &p.P, &p.bmax};
@@ -810,6 +864,29 @@ int centra_engine_add_pool(centra_engine* e, const centra_graph* g, const centra
   e->pools.push_back(std::move(p));
   *pool_id = static_cast<uint32_t>(e->pools.size() - 1);
   return CENTRA_OK;
+}
+
+int centra_engine_prefill(centra_engine* e, uint32_t pool_id, uint64_t m, void* stream) {
+  if (!e) return CENTRA_EINVAL;
+  centra_ctx* ctx = e->ctx;
+  if (pool_id >= e->pools.size()) return fail(ctx, CENTRA_EINVAL, "engine_prefill: no such pool");
+  EnginePool& p = e->pools[pool_id];
+  uint32_t level = 0;
+  while (level + 1 < p.level_m.size() && p.level_m[level] < m) ++level;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = CENTRA_OK;
+  if (!e->tuned_block && !(e->flags & CENTRA_ENGINE_NO_TUNE)) rc = autotune(e, s);   // before serving starts
+  std::vector<uint32_t> want(e->pools.size(), ~0u);
+  want[pool_id] = level;
+  if (!rc) rc = sample_pools(e, want, s);
+  while (!rc && p.levels_built <= level) rc = build_level(e, p, p.levels_built, s);
+  const size_t b = engine_bytes(e);
+  if (b > e->st.peak_bytes) e->st.peak_bytes = b;
+  if (prev >= 0) (void)hipSetDevice(prev);
+  return rc;
 }
 
 int centra_engine_submit(centra_engine* e, uint32_t pool_id, uint32_t k, uint32_t t, double eps, double delta,

@@ -187,10 +187,15 @@ struct GreedyDesc {
   uint32_t* picks;          // outputs: u32[k], u64[k], u32[1]
   uint64_t* cov_cum;
   uint32_t* n_picked;
+  uint32_t* cand;           // u32[greedy_cand_words()]: candidate list
+  uint32_t* cst;            // u32[4]: mode, threshold, list length
+  uint32_t* hist;           // u32[greedy_hist_words()]: gain histogram
   uint64_t m;
   uint32_t n, n_seg, k, pad;
 };
 uint32_t greedy_part_words();
+uint32_t greedy_cand_words();
+uint32_t greedy_hist_words();
 void greedy_multi_init(const GreedyDesc* d, uint32_t n_q, uint32_t max_n, hipStream_t s);
 // Launches `rounds` rounds (round numbers round_base[0] .. + rounds - 1),
 // then advances round_base[0] by `rounds` on the device.

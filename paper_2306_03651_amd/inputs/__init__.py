@@ -177,3 +177,24 @@ def layered_dag(layers: int = 40, width: int = 12, max_in: int = 8, hub_out: int
         src.append(hub); dst.append(hub + 1 + j)
     n = hub + 1 + hub_out
     return from_edges(n, src, dst, directed=True, name=f"layered_{layers}x{width}_s{seed}")
+
+
+def uneven_instances(count: int = 256, seed: int = 1, ba_n=(1000, 100_000), grid_side=(64, 1024),
+                     k=(5, 50)):
+    """The uneven-instances mix: per instance, a Bernoulli(1/2) choice of a
+    Barabasi-Albert graph (n uniform in ba_n, attachment 5) or an L x L grid
+    (L uniform in grid_side), and k uniform in k (bounds inclusive); numpy
+    generator of `seed`.  Returns [(kind, size, graph_seed, k)]; build the
+    graphs with instance_graph."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        if rng.random() < 0.5:
+            out.append(("ba", int(rng.integers(ba_n[0], ba_n[1] + 1)), 1000 + i, int(rng.integers(k[0], k[1] + 1))))
+        else:
+            out.append(("grid", int(rng.integers(grid_side[0], grid_side[1] + 1)), 0, int(rng.integers(k[0], k[1] + 1))))
+    return out
+
+
+def instance_graph(kind: str, size: int, graph_seed: int) -> CSRGraph:
+    return ba_graph(size, 5, graph_seed) if kind == "ba" else grid_graph(size)

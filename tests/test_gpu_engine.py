@@ -89,6 +89,17 @@ def test_batch_equals_standalone(ctx):
     assert st.sampler_launches <= st.ticks
 
 
+@pytest.mark.parametrize("k", [200, 600])
+def test_large_k_candidate_lists(ctx, k):
+    # many greedy rounds: the rounds run on candidate lists most of the time
+    # (full scans only to rebuild them); picks must still be exact
+    graphs = [(inputs.ba_graph(20000, 5, 31), k), (inputs.grid_graph(60), k), (inputs.rmat_graph(13, 8, seed=32), k)]
+    say(f"engine batch with k={k}")
+    got, want, st, _ = run_batch(ctx, graphs, t=8, eps=0.02, m_init=20000, m_max=80000)
+    for g, w in zip(got, want):
+        same(g, w)
+
+
 def test_batch_matches_oracle(ctx):
     # one instance, checked against the oracle's progressive loop as well
     g = inputs.ba_graph(2000, 5, 1)
