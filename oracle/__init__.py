@@ -80,6 +80,11 @@ def _load():
     lib.orc_sample_paths.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint64, c.c_uint32, c.c_uint64,
                                      c.c_uint64, _u64p, _u32p, c.c_uint64, c.c_void_p]
     lib.orc_sample_paths.restype = c.c_uint64
+    lib.orc_count_bits_out.argtypes = [c.POINTER(Graph)]
+    lib.orc_count_bits_out.restype = c.c_uint32
+    lib.orc_sample_paths_bidir.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint32, c.c_uint64, c.c_uint32,
+                                           c.c_uint64, c.c_uint64, _u64p, _u32p, c.c_uint64, c.c_void_p]
+    lib.orc_sample_paths_bidir.restype = c.c_uint64
     lib.orc_bfs_counts.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint32, _u32p, _u64p]
     lib.orc_bfs_counts.restype = None
     lib.orc_greedy_cover.argtypes = [c.c_uint32, c.c_uint64, _u64p, _u32p, c.c_uint32, _u32p, _u64p]
@@ -185,6 +190,36 @@ def sample_paths(g, seed, instance, first, count, c_bits=None, with_info=False):
         infos = (SampleInfo * max(1, count))() if with_info else None
         tot = lib.orc_sample_paths(ctypes.byref(og.c), c_bits, seed, instance, first, count, he_off,
                                    he_nodes, cap, ctypes.cast(infos, ctypes.c_void_p) if with_info else None)
+        if tot != 2**64 - 1:
+            break
+        cap *= 4
+    res = (he_off, he_nodes[:tot].copy())
+    if with_info:
+        return res + (list(infos)[:count],)
+    return res
+
+
+def count_bits_out(g) -> int:
+    og = OracleGraph(g)
+    return _load().orc_count_bits_out(ctypes.byref(og.c))
+
+
+def sample_paths_bidir(g, seed, instance, first, count, c_f=None, c_b=None, with_info=False):
+    """The balanced bidirectional sampler (reading R16): samples [first,
+    first+count) -> (he_off u64[count+1], he_nodes u32[I][, infos])."""
+    og = OracleGraph(g)
+    lib = _load()
+    if c_f is None:
+        c_f = lib.orc_count_bits(ctypes.byref(og.c))
+    if c_b is None:
+        c_b = lib.orc_count_bits_out(ctypes.byref(og.c))
+    cap = max(16, count * 8)
+    while True:
+        he_off = np.zeros(count + 1, dtype=np.uint64)
+        he_nodes = np.zeros(cap, dtype=np.uint32)
+        infos = (SampleInfo * max(1, count))() if with_info else None
+        tot = lib.orc_sample_paths_bidir(ctypes.byref(og.c), c_f, c_b, seed, instance, first, count, he_off,
+                                         he_nodes, cap, ctypes.cast(infos, ctypes.c_void_p) if with_info else None)
         if tot != 2**64 - 1:
             break
         cap *= 4

@@ -374,6 +374,252 @@ uint64_t orc_sample_paths(const orc_graph *g, uint32_t c_bits, uint64_t seed,
 }
 
 /* ------------------------------------------------------------------ */
+/* Balanced bidirectional sampler (the sampling procedure of Sec. 5, under
+ * reading R16): a search from s over out-arcs and one from t over in-arcs,
+ * each level with normalised counts (R4; the forward budget from the
+ * largest in-degree, the backward one from the largest out-degree); each
+ * step expands the side whose frontier has fewer arcs to scan (the forward
+ * side on ties).  When a new level meets the other side's last level, the
+ * meeting nodes M split every shortest path: one node of M is drawn with
+ * weight sigma_f * sigma_b (scaled so that the sum fits 63 bits), then the
+ * path is walked from it to t over the backward counts and to s over the
+ * forward counts. */
+uint32_t orc_count_bits_out(const orc_graph *g)
+{
+    uint64_t dmax = 0;
+    for (uint32_t v = 0; v < g->n; v++) {
+        uint64_t d = g->row_ptr[v + 1] - g->row_ptr[v];
+        if (d > dmax) dmax = d;
+    }
+    return 63 - bitlen64(dmax);
+}
+
+typedef struct {
+    uint32_t *level;
+    uint64_t *sigma;
+    uint32_t *visited;
+    uint32_t n_visited;
+    uint32_t lo, hi;      /* visited[lo, hi) is the last level */
+} side_state;
+
+static int side_alloc(side_state *z, uint32_t n)
+{
+    z->level = malloc(sizeof(uint32_t) * n);
+    z->sigma = calloc(n, sizeof(uint64_t));
+    z->visited = malloc(sizeof(uint32_t) * n);
+    if (!z->level || !z->sigma || !z->visited) return -1;
+    for (uint32_t v = 0; v < n; v++) z->level[v] = UNSEEN;
+    z->n_visited = 0;
+    return 0;
+}
+
+static void side_free(side_state *z) { free(z->level); free(z->sigma); free(z->visited); }
+
+static void side_reset(side_state *z)
+{
+    for (uint32_t q = 0; q < z->n_visited; q++) {
+        z->level[z->visited[q]] = UNSEEN;
+        z->sigma[z->visited[q]] = 0;
+    }
+    z->n_visited = 0;
+}
+
+static void side_start(side_state *z, uint32_t root)
+{
+    z->level[root] = 0;
+    z->sigma[root] = 1;
+    z->visited[0] = root;
+    z->n_visited = 1;
+    z->lo = 0;
+    z->hi = 1;
+}
+
+/* Arcs that expanding the side's last level would scan (rows of ptr). */
+static uint64_t side_cost(const side_state *z, const uint32_t *ptr)
+{
+    uint64_t c = 0;
+    for (uint32_t q = z->lo; q < z->hi; q++) c += ptr[z->visited[q] + 1] - ptr[z->visited[q]];
+    return c;
+}
+
+/* Expands the side's last level L over the rows (ptr, idx): level L + 1 and
+ * its raw counts, then the level's normalisation with budget c_bits. */
+static void side_expand(side_state *z, const uint32_t *ptr, const uint32_t *idx, uint32_t c_bits,
+                        uint64_t *arcs)
+{
+    const uint32_t L = z->level[z->visited[z->lo]];
+    const uint32_t lo = z->lo, hi = z->hi;
+    for (uint32_t q = lo; q < hi; q++) {
+        uint32_t w = z->visited[q];
+        for (uint32_t e = ptr[w]; e < ptr[w + 1]; e++) {
+            uint32_t v = idx[e];
+            (*arcs)++;
+            if (z->level[v] == UNSEEN) {
+                z->level[v] = L + 1;
+                z->sigma[v] = 0;
+                z->visited[z->n_visited++] = v;
+            }
+            if (z->level[v] == L + 1) z->sigma[v] += z->sigma[w];
+        }
+    }
+    z->lo = hi;
+    z->hi = z->n_visited;
+    uint64_t mx = 0;
+    for (uint32_t q = z->lo; q < z->hi; q++)
+        if (z->sigma[z->visited[q]] > mx) mx = z->sigma[z->visited[q]];
+    uint32_t bl = bitlen64(mx);
+    uint32_t shift = bl > c_bits ? bl - c_bits : 0;
+    for (uint32_t q = z->lo; q < z->hi; q++) {
+        uint64_t x = z->sigma[z->visited[q]] >> shift;
+        z->sigma[z->visited[q]] = x ? x : 1;
+    }
+}
+
+static int cmp_u32(const void *x, const void *y)
+{
+    uint32_t a = *(const uint32_t *)x, b = *(const uint32_t *)y;
+    return a < b ? -1 : a > b;
+}
+
+/* One step of a walk: among the row entries of cur (rows ptr, idx) whose
+ * level on side z is `want`, in row order, the one drawn with weight sigma. */
+static uint32_t walk_step(const side_state *z, const uint32_t *ptr, const uint32_t *idx, uint32_t cur,
+                          uint32_t want, orc_stream *st)
+{
+    uint64_t W = 0;
+    for (uint32_t e = ptr[cur]; e < ptr[cur + 1]; e++)
+        if (z->level[idx[e]] == want) W += z->sigma[idx[e]];
+    uint64_t r = orc_bounded(st, W);
+    uint64_t acc = 0;
+    for (uint32_t e = ptr[cur]; e < ptr[cur + 1]; e++) {
+        uint32_t u = idx[e];
+        if (z->level[u] != want) continue;
+        acc += z->sigma[u];
+        if (acc > r) return u;
+    }
+    return UNSEEN;
+}
+
+/* Meeting weight of v before scaling: the number of shortest s-v paths
+ * times the number of shortest v-t paths (normalised counts). */
+static unsigned __int128 meet_weight(const side_state *F, const side_state *B, uint32_t v)
+{
+    return (unsigned __int128)F->sigma[v] * B->sigma[v];
+}
+
+static uint32_t bidir_one(const orc_graph *g, uint32_t c_f, uint32_t c_b, uint64_t seed, uint32_t instance,
+                          uint64_t sample, uint32_t *h, orc_sample_info *info, side_state *F, side_state *B,
+                          uint32_t *scratch)
+{
+    orc_stream st;
+    orc_stream_init(&st, seed, sample, instance, 7);
+    uint32_t n = g->n;
+    uint32_t s = (uint32_t)orc_bounded(&st, n);
+    uint32_t tp = (uint32_t)orc_bounded(&st, n - 1);
+    uint32_t t = tp + (tp >= s ? 1u : 0u);
+    const uint32_t *ip = in_ptr(g), *ii = in_idx(g);
+    uint64_t arcs = 0;
+    side_start(F, s);
+    side_start(B, t);
+    uint32_t a = 0, b = 0, d = UNSEEN;
+    uint32_t *M = scratch, nm = 0;
+    while (F->lo < F->hi && B->lo < B->hi) {
+        if (side_cost(F, g->row_ptr) <= side_cost(B, ip)) {
+            side_expand(F, g->row_ptr, g->col_idx, c_f, &arcs);
+            a++;
+            for (uint32_t q = F->lo; q < F->hi; q++)
+                if (B->level[F->visited[q]] == b) M[nm++] = F->visited[q];
+        } else {
+            side_expand(B, ip, ii, c_b, &arcs);
+            b++;
+            for (uint32_t q = B->lo; q < B->hi; q++)
+                if (F->level[B->visited[q]] == a) M[nm++] = B->visited[q];
+        }
+        if (nm) {
+            d = a + b;
+            break;
+        }
+    }
+    uint32_t len = 0;
+    if (d != UNSEEN && d >= 2) {
+        qsort(M, nm, sizeof(uint32_t), cmp_u32);
+        /* weights sigma_f sigma_b, scaled so that their sum stays below 2^63 */
+        unsigned __int128 pmax = 0;
+        for (uint32_t i = 0; i < nm; i++) {
+            unsigned __int128 p = meet_weight(F, B, M[i]);
+            if (p > pmax) pmax = p;
+        }
+        uint32_t pbits = 0;
+        for (unsigned __int128 x = pmax; x; x >>= 1) pbits++;
+        const uint32_t room = 63 - bitlen64(nm);
+        const uint32_t shift = pbits > room ? pbits - room : 0;
+        uint64_t W = 0;
+        for (uint32_t i = 0; i < nm; i++) {
+            uint64_t w = (uint64_t)(meet_weight(F, B, M[i]) >> shift);
+            W += w ? w : 1;
+        }
+        uint64_t r = orc_bounded(&st, W), acc = 0;
+        uint32_t v = UNSEEN;
+        for (uint32_t i = 0; i < nm; i++) {
+            uint64_t w = (uint64_t)(meet_weight(F, B, M[i]) >> shift);
+            acc += w ? w : 1;
+            if (acc > r) { v = M[i]; break; }
+        }
+        /* toward t over the backward counts (successors on out-rows) */
+        uint32_t nt = 0, cur = v;
+        uint32_t *tside = scratch;   /* M is no longer needed */
+        while (B->level[cur] >= 2) {
+            cur = walk_step(B, g->row_ptr, g->col_idx, cur, B->level[cur] - 1, &st);
+            tside[nt++] = cur;
+        }
+        for (uint32_t i = nt; i > 0; i--) h[len++] = tside[i - 1];
+        if (a >= 1 && b >= 1) h[len++] = v;
+        /* toward s over the forward counts (predecessors on in-rows) */
+        cur = v;
+        while (F->level[cur] >= 2) {
+            cur = walk_step(F, ip, ii, cur, F->level[cur] - 1, &st);
+            h[len++] = cur;
+        }
+    }
+    if (info) {
+        info->s = s;
+        info->t = t;
+        info->dist = d;
+        info->len = len;
+        info->arcs_scanned = arcs;
+        info->nodes_visited = F->n_visited + B->n_visited;
+    }
+    side_reset(F);
+    side_reset(B);
+    return len;
+}
+
+uint64_t orc_sample_paths_bidir(const orc_graph *g, uint32_t c_f, uint32_t c_b, uint64_t seed,
+                                uint32_t instance, uint64_t first, uint64_t count, uint64_t *he_off,
+                                uint32_t *he_nodes, uint64_t he_cap, orc_sample_info *infos)
+{
+    side_state F, B;
+    uint32_t *h = malloc(sizeof(uint32_t) * g->n);
+    uint32_t *scratch = malloc(sizeof(uint32_t) * g->n);
+    if (!h || !scratch || side_alloc(&F, g->n) || side_alloc(&B, g->n)) return UINT64_MAX;
+    uint64_t total = 0;
+    he_off[0] = 0;
+    for (uint64_t i = 0; i < count; i++) {
+        uint32_t len = bidir_one(g, c_f, c_b, seed, instance, first + i, h, infos ? &infos[i] : NULL, &F, &B,
+                                 scratch);
+        if (total + len > he_cap) { total = UINT64_MAX; break; }
+        memcpy(he_nodes + total, h, sizeof(uint32_t) * len);
+        total += len;
+        he_off[i + 1] = total;
+    }
+    free(h);
+    free(scratch);
+    side_free(&F);
+    side_free(&B);
+    return total;
+}
+
+/* ------------------------------------------------------------------ */
 /* greedyCover(k, H) (Sec. 3.1; Algorithm 1 greedy step).  Each round
  * recomputes, for every node, the number of not-yet-covered hyperedges it
  * belongs to -- its marginal gain m*(C_H(S u {u}) - C_H(S)) -- and adds the

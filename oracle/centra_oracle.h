@@ -105,6 +105,19 @@ uint64_t orc_sample_paths(const orc_graph *g, uint32_t c_bits, uint64_t seed,
                           uint64_t *he_off, uint32_t *he_nodes, uint64_t he_cap,
                           orc_sample_info *infos);
 
+/* C_b = 63 - bitlen(max out-degree): the budget of the backward counts of
+ * the bidirectional sampler (sums over out-neighbours). */
+uint32_t orc_count_bits_out(const orc_graph *g);
+
+/* The balanced bidirectional sampler (reading R16): samples [first,
+ * first + count) of (seed, instance) from the stream with tag 7, stored as
+ * orc_sample_paths does; c_f / c_b are the forward / backward count budgets
+ * (orc_count_bits / orc_count_bits_out, or smaller test overrides).  The
+ * hyperedge is the path's internal nodes, t's neighbour first. */
+uint64_t orc_sample_paths_bidir(const orc_graph *g, uint32_t c_f, uint32_t c_b, uint64_t seed,
+                                uint32_t instance, uint64_t first, uint64_t count, uint64_t *he_off,
+                                uint32_t *he_nodes, uint64_t he_cap, orc_sample_info *infos);
+
 /* BFS levels and normalised counts from s over the whole graph (test hook):
  * level[v] = d(s,v) or 0xFFFFFFFF, sigma[v] = normalised count (0 if
  * unreachable). */

@@ -52,6 +52,11 @@ MUTANTS = {
                                        "tests/test_oracle_sampler.py"),
     "graph_check_reverse_sources_unchecked": ("                if (!found) return -21;", "                if (!found && 0) return -21;",
                                               "tests/test_oracle_sampler.py"),
+    "bidir_weight_forward_only": ("    return (unsigned __int128)F->sigma[v] * B->sigma[v];",
+                                  "    return (unsigned __int128)F->sigma[v];", "tests/test_oracle_bidir.py"),
+    "bidir_walk_wrong_side": ("            cur = walk_step(B, g->row_ptr, g->col_idx, cur, B->level[cur] - 1, &st);",
+                              "            cur = walk_step(F, g->row_ptr, g->col_idx, cur, B->level[cur] - 1, &st);",
+                              "tests/test_oracle_bidir.py"),
     "counts_no_clamp": ("            b->sigma[b->visited[q]] = x ? x : 1;", "            b->sigma[b->visited[q]] = x;",
                         "tests/test_oracle_sampler.py"),
     "schedule_root_term": ("const double inv_y = (sqrt(2.0 * L) + sqrt(2.0 * L + 4.0 * L * T / 3.0)) / (2.0 * T);",
