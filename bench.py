@@ -509,6 +509,9 @@ def main():
                          "triangles: the triangle space of R-MAT scale 20, undirected")
     ap.add_argument("--sweep", action="store_true",
                     help="run only the t and m sweeps of the fixed-size bound (one JSON line)")
+    ap.add_argument("--sampler", choices=["single", "bidir"], default="single",
+                    help="shortest-path workloads: the single-source sampler (default) or the balanced "
+                         "bidirectional one (centra_sample_paths_bidir)")
     ap.add_argument("--plain-queries", type=int, default=8,
                     help="serving workload: queries also served one at a time by centra_progressive")
     ap.add_argument("--copy-probe", action="store_true",
@@ -539,8 +542,9 @@ def main():
     W = dict(WORKLOADS[args.workload])
     tri = W.get("space") == "triangles"
     kp = W.get("space") == "kpaths"
+    bidir = args.sampler == "bidir" and not (tri or kp)
     space = (binding.CENTRA_SPACE_TRIANGLES if tri else binding.CENTRA_SPACE_KPATHS if kp
-             else binding.CENTRA_SPACE_SHORTEST_PATHS)
+             else binding.CENTRA_SPACE_PATHS_BIDIR if bidir else binding.CENTRA_SPACE_SHORTEST_PATHS)
     kappa = W.get("kappa", 0)
     if args.uncapped_max is None:
         args.uncapped_max = {"sparse": 128_000_000, "skewed": 32_000_000, "triangles": 64_000_000,
@@ -633,10 +637,11 @@ def main():
         bytes_per_launch = (4.0 * st.arcs + 28.0 * st.nodes) / launches
     sec_per_launch = st.kernel_ms / 1e3 / launches
     achieved = bytes_per_launch / sec_per_launch / 1e9
-    traffic = read_traffic(W["traffic"])
+    traffic = None if bidir else read_traffic(W["traffic"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "k_tri_sample" if tri else "k_kpath (both passes)" if kp else "k_sample_paths",
+                "kernel": "k_tri_sample" if tri else "k_kpath (both passes)" if kp else
+                "k_sample_bidir" if bidir else "k_sample_paths",
                 "launches": st.launches,
                 "avg_launch_ms": round(st.kernel_ms / launches, 3),
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
@@ -669,7 +674,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32" if (tri or kp) else "u64",
         "data": "synthetic",
-        "config": {"workload": W["label"],
+        "config": {"workload": W["label"] + ("; balanced bidirectional sampler" if bidir else ""),
                    "n": int(g.n), "arcs": int(g.n_arcs), "m_init": W["m_init"], "m_max": W["m_max"],
                    "k": W["k"], "t": W["t"], "eps": W["eps"], "delta": W["delta"]},
         "triangles": n_triangles,

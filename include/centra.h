@@ -38,7 +38,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 7u
+#define CENTRA_ABI_VERSION 8u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -143,6 +143,28 @@ CENTRA_API int centra_sample_paths(centra_ctx *ctx, const centra_graph *g, uint6
                         uint64_t first_sample, uint32_t count, uint64_t *he_off, uint32_t *he_nodes,
                         uint64_t he_cap, uint64_t *he_needed, uint32_t *st_out, uint32_t *dist_out,
                         void *stream);
+
+/* sampleHEs for set betweenness by the balanced bidirectional search of
+ * Sec. 5: the same hyperedge space and the same distribution (a uniform
+ * ordered pair, then a uniformly random shortest path) as
+ * centra_sample_paths, drawn from its own stream: Philox4x64-10 with key
+ * (seed, 0) and counter (block, x, instance, 7); s, t as above; a search
+ * from s over out-arcs and one from t over in-arcs, each level with
+ * normalised counts (the forward budget C as above, the backward budget
+ * 63 - bitlen(max out-degree); a count_bits_override lowers both), each
+ * step expanding the side whose last level has fewer arcs to scan (the
+ * forward side on ties); at the first level that meets the other side's
+ * last level, a meeting node is drawn in ascending id with weight
+ * sigma_f * sigma_b (the 128-bit product shifted so that the weights sum
+ * below 2^63, clamped to >= 1), then the path is walked to t over the
+ * backward counts (successors in row order) and to s over the forward
+ * counts (predecessors in row order), one draw per step above level 1.
+ * Arguments, outputs and errors as centra_sample_paths.  Its slot state is
+ * 40 bytes per node per concurrent search. */
+CENTRA_API int centra_sample_paths_bidir(centra_ctx *ctx, const centra_graph *g, uint64_t seed, uint32_t instance,
+                              uint64_t first_sample, uint32_t count, uint64_t *he_off, uint32_t *he_nodes,
+                              uint64_t he_cap, uint64_t *he_needed, uint32_t *st_out, uint32_t *dist_out,
+                              void *stream);
 
 /* greedyCover(k, H) (Sec. 3.1 greedy algorithm; Algorithm 1 greedy step):
  * k rounds; each adds the node covering the most not-yet-covered
@@ -327,7 +349,8 @@ CENTRA_API int centra_sample_kpaths(centra_ctx *ctx, const centra_graph *g, uint
  * The hyperedge space: CENTRA_SPACE_SHORTEST_PATHS (set betweenness,
  * centra_sample_paths), CENTRA_SPACE_TRIANGLES (triangle centrality,
  * centra_sample_triangles) or CENTRA_SPACE_KPATHS (kappa-path centrality,
- * centra_sample_kpaths with the params' kappa; kappa is ignored otherwise).
+ * centra_sample_kpaths with the params' kappa; kappa is ignored otherwise)
+ * or CENTRA_SPACE_PATHS_BIDIR (set betweenness, centra_sample_paths_bidir).
  * Inputs: k >= 1, 1 <= t <= 1024, eps in (0, 1-1/e), delta in (0,1),
  * 1 <= m_init <= m_max < 2^31, growth_num > growth_den >= 1, schedule and
  * space one of their values, 1 <= kappa <= CENTRA_MAX_KAPPA for
@@ -344,6 +367,7 @@ CENTRA_API int centra_sample_kpaths(centra_ctx *ctx, const centra_graph *g, uint
 #define CENTRA_SPACE_SHORTEST_PATHS 0u
 #define CENTRA_SPACE_TRIANGLES 1u
 #define CENTRA_SPACE_KPATHS 2u
+#define CENTRA_SPACE_PATHS_BIDIR 3u   /* shortest paths, bidirectional sampler */
 
 typedef struct {
     uint32_t k, t;

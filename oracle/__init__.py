@@ -288,7 +288,7 @@ def next_sample_size(m_i, c_hat, eps, delta_next, growth_num, growth_den, m_max,
                                             schedule))
 
 
-SPACE_SHORTEST_PATHS, SPACE_TRIANGLES, SPACE_KPATHS = 0, 1, 2
+SPACE_SHORTEST_PATHS, SPACE_TRIANGLES, SPACE_KPATHS, SPACE_PATHS_BIDIR = 0, 1, 2, 3
 
 
 def triangles(g):

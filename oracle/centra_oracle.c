@@ -939,8 +939,18 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
     const double a = 1.0 - exp(-1.0);
     if (k == 0 || t == 0 || !(eps > 0.0 && eps < a) || !(delta > 0.0 && delta < 1.0) ||
         m_init == 0 || m_max < m_init || growth_den == 0 || growth_num <= growth_den ||
-        schedule > 2 || space > 2 || (space == 2 && kappa == 0))
+        schedule > 2 || space > 3 || (space == 2 && kappa == 0))
         return -1;
+    /* space 3: the bidirectional sampler; a lowered forward budget (a test
+     * override) lowers the backward one too */
+    side_state F, B;
+    uint32_t *bscratch = NULL;
+    uint32_t c_b = orc_count_bits_out(g);
+    if (c_bits < orc_count_bits(g) && c_bits < c_b) c_b = c_bits;
+    if (space == 3) {
+        bscratch = malloc(sizeof(uint32_t) * g->n);
+        if (!bscratch || side_alloc(&F, g->n) || side_alloc(&B, g->n)) return -1;
+    }
     uint32_t *tri = NULL;
     uint64_t T = 0;
     if (space == 1) {
@@ -974,6 +984,8 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                 len = 3;
             } else if (space == 2) {
                 len = orc_kpath(g, kappa, seed, instance, s, h, NULL, NULL);
+            } else if (space == 3) {
+                len = bidir_one(g, c_bits, c_b, seed, instance, s, h, NULL, &F, &B, bscratch);
             } else {
                 len = sample_one(g, c_bits, seed, instance, s, h, NULL, &b);
             }
@@ -1013,6 +1025,11 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                                    growth_den, m_max, schedule);
     }
     bfs_free(&b);
+    if (space == 3) {
+        side_free(&F);
+        side_free(&B);
+        free(bscratch);
+    }
     free(he_off); free(he_nodes); free(h); free(cov_cum); free(topk); free(tri);
     return rc;
 }

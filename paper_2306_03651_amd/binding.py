@@ -29,6 +29,7 @@ CENTRA_SCHEDULE_FIXED = 2
 CENTRA_SPACE_SHORTEST_PATHS = 0
 CENTRA_SPACE_TRIANGLES = 1
 CENTRA_SPACE_KPATHS = 2
+CENTRA_SPACE_PATHS_BIDIR = 3
 CENTRA_MAX_KAPPA = 16
 
 _c = ctypes
@@ -119,6 +120,8 @@ SIGNATURES = {
     "centra_graph_info": (_c.c_int, [_vp, _c.POINTER(_c.c_uint32), _c.POINTER(_c.c_uint32)]),
     "centra_sample_paths": (_c.c_int, [_vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _vp, _vp,
                                        _c.c_uint64, _c.POINTER(_c.c_uint64), _vp, _vp, _vp]),
+    "centra_sample_paths_bidir": (_c.c_int, [_vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _vp,
+                                             _vp, _c.c_uint64, _c.POINTER(_c.c_uint64), _vp, _vp, _vp]),
     "centra_greedy_cover": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint32, _vp, _vp, _vp, _vp]),
     "centra_greedy_cover_noalloc": (_c.c_int, [_c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint32, _vp, _vp, _vp, _vp]),
     "centra_mcera": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint32,
@@ -259,6 +262,22 @@ def centra_sample_paths(ctx, g, seed: int, instance: int, first_sample: int, cou
     return rc, need.value
 
 
+def centra_sample_paths_bidir(ctx, g, seed: int, instance: int, first_sample: int, count: int, he_off, he_nodes,
+                              he_cap: int | None = None, st_out=None, dist_out=None, stream=None):
+    """Returns (rc, he_needed).  rc may be CENTRA_ENOSPC (no exception)."""
+    import torch
+    _dtype_check(he_off, torch.int64, "he_off")
+    _dtype_check(he_nodes, torch.int32, "he_nodes")
+    if he_cap is None:
+        he_cap = he_nodes.numel() if he_nodes is not None else 0
+    need = ctypes.c_uint64()
+    rc = lib().centra_sample_paths_bidir(ctx, g, seed, instance, first_sample, count, _ptr(he_off), _ptr(he_nodes),
+                                         he_cap, ctypes.byref(need), _ptr(st_out), _ptr(dist_out), _stream(stream))
+    if rc != CENTRA_ENOSPC:
+        _check(rc, ctx)
+    return rc, need.value
+
+
 def centra_greedy_cover(ctx, n: int, he_off, he_nodes, k: int, picks, cov_cum, n_picked, stream=None) -> int:
     m = he_off.numel() - 1
     return _check(lib().centra_greedy_cover(ctx, n, m, _ptr(he_off), _ptr(he_nodes), k, _ptr(picks),
@@ -386,19 +405,21 @@ def sample_kpaths(ctx, dg, kappa: int, seed: int, instance: int, first: int, cou
 
 
 def sample_paths(ctx, dg: DeviceGraph, seed: int, instance: int, first: int, count: int, with_st: bool = False,
-                 device="cuda"):
-    """Samples [first, first+count) into fresh device tensors.
+                 device="cuda", bidir: bool = False):
+    """Samples [first, first+count) into fresh device tensors (the balanced
+    bidirectional sampler if bidir).
     Returns (he_off int64[count+1], he_nodes int32[I]) (+ (st, dist) if with_st)."""
     import torch
+    call = centra_sample_paths_bidir if bidir else centra_sample_paths
     he_off = torch.empty(count + 1, dtype=torch.int64, device=device)
     cap = max(16, count * 8)
     st = torch.empty(2 * max(1, count), dtype=torch.int32, device=device) if with_st else None
     dist = torch.empty(max(1, count), dtype=torch.int32, device=device) if with_st else None
     he_nodes = torch.empty(cap, dtype=torch.int32, device=device)
-    rc, need = centra_sample_paths(ctx, dg.handle, seed, instance, first, count, he_off, he_nodes, cap, st, dist)
+    rc, need = call(ctx, dg.handle, seed, instance, first, count, he_off, he_nodes, cap, st, dist)
     if rc == CENTRA_ENOSPC:
         he_nodes = torch.empty(max(1, need), dtype=torch.int32, device=device)
-        rc, need = centra_sample_paths(ctx, dg.handle, seed, instance, first, count, he_off, he_nodes, need, st, dist)
+        rc, need = call(ctx, dg.handle, seed, instance, first, count, he_off, he_nodes, need, st, dist)
     out = (he_off, he_nodes[:need])
     if with_st:
         out = out + (st, dist)

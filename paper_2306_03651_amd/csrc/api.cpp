@@ -162,7 +162,8 @@ void centra_destroy(centra_ctx* ctx) {
                     &ctx->stage_len, &ctx->work_ctr, &ctx->scan_tmp, &ctx->deg, &ctx->inc_off,
                     &ctx->inc_cursor, &ctx->inc, &ctx->inc_node, &ctx->gain, &ctx->covered, &ctx->best,
                     &ctx->newcov, &ctx->words, &ctx->P, &ctx->Rtm, &ctx->topk_tmp, &ctx->misc,
-                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len, &ctx->seg_deg, &ctx->multi_tab, &ctx->sel_rows};
+                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len, &ctx->seg_deg, &ctx->multi_tab, &ctx->sel_rows, &ctx->bi_rec_f, &ctx->bi_rec_b, &ctx->bi_q_f,
+                    &ctx->bi_q_b};
   for (DevBuf* b : bufs) release(ctx, *b);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
   for (auto& ev : ctx->ev)
@@ -200,6 +201,7 @@ int centra_graph_prepare(centra_ctx* ctx, const centra_csr* csr, uint32_t count_
     return rc;
   }
   if (count_bits_override && count_bits_override < g->count_bits) g->count_bits = count_bits_override;
+  g->count_bits_override = count_bits_override;
   g->bfs_row_ptr = g->row_ptr;
   g->bfs_col_idx = g->col_idx;
   g->bfs_in_ptr = g->in_ptr;
@@ -250,6 +252,31 @@ int centra_sample_paths(centra_ctx* ctx, const centra_graph* g, uint64_t seed, u
   if (rc) return rc;
   CENTRA_HIP(ctx, hipStreamSynchronize(s));
   if (!fits) return fail(ctx, CENTRA_ENOSPC, "sample_paths: he_cap smaller than the sample");
+  return CENTRA_OK;
+}
+
+int centra_sample_paths_bidir(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance,
+                              uint64_t first_sample, uint32_t count, uint64_t* he_off, uint32_t* he_nodes,
+                              uint64_t he_cap, uint64_t* he_needed, uint32_t* st_out, uint32_t* dist_out,
+                              void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (!g || !he_off) return fail(ctx, CENTRA_EINVAL, "sample_paths_bidir: NULL argument");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = as_stream(stream);
+  uint64_t total = 0;
+  int rc = sample_bidir_to_stage(ctx, g, seed, instance, first_sample, count, st_out, dist_out, &total, s);
+  if (rc) return rc;
+  if (he_needed) *he_needed = total;
+  if (count == 0) {
+    fill_u64(he_off, 0, 1, s);
+    CENTRA_HIP(ctx, hipStreamSynchronize(s));
+    return CENTRA_OK;
+  }
+  const bool fits = he_nodes && he_cap >= total;
+  rc = stage_to_output(ctx, count, 0, he_off, fits ? he_nodes : nullptr, s);
+  if (rc) return rc;
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  if (!fits) return fail(ctx, CENTRA_ENOSPC, "sample_paths_bidir: he_cap smaller than the sample");
   return CENTRA_OK;
 }
 
@@ -386,7 +413,7 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
   if (p->growth_den == 0 || p->growth_num <= p->growth_den)
     return fail(ctx, CENTRA_EINVAL, "progressive: growth must exceed 1");
   if (p->schedule > CENTRA_SCHEDULE_FIXED) return fail(ctx, CENTRA_EINVAL, "progressive: unknown schedule");
-  if (p->space > CENTRA_SPACE_KPATHS) return fail(ctx, CENTRA_EINVAL, "progressive: unknown hyperedge space");
+  if (p->space > CENTRA_SPACE_PATHS_BIDIR) return fail(ctx, CENTRA_EINVAL, "progressive: unknown hyperedge space");
   if (p->space == CENTRA_SPACE_KPATHS && (p->kappa == 0 || p->kappa > CENTRA_MAX_KAPPA))
     return fail(ctx, CENTRA_EINVAL, "progressive: kappa outside [1, 16]");
   const bool tri = p->space == CENTRA_SPACE_TRIANGLES;
@@ -436,7 +463,10 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
                             store_nodes + total_nodes, s, true)))
         return rc;
     } else {
-      if ((rc = sample_to_stage(ctx, g, p->seed, p->instance, m_prev, cnt, nullptr, nullptr, &added, s))) return rc;
+      if ((rc = p->space == CENTRA_SPACE_PATHS_BIDIR
+                    ? sample_bidir_to_stage(ctx, g, p->seed, p->instance, m_prev, cnt, nullptr, nullptr, &added, s)
+                    : sample_to_stage(ctx, g, p->seed, p->instance, m_prev, cnt, nullptr, nullptr, &added, s)))
+        return rc;
       if ((rc = ensure(ctx, ctx->store_nodes, (total_nodes + added + 1) * 4, true, s))) return rc;
       uint32_t* store_nodes = static_cast<uint32_t*>(ctx->store_nodes.ptr);
       if ((rc = stage_to_output(ctx, cnt, total_nodes, store_off + m_prev, store_nodes + total_nodes, s))) return rc;

@@ -32,6 +32,11 @@ struct centra_ctx {
   uint32_t slots = 0;
   uint32_t slot_n = 0;
   uint32_t stamp_next = 1;   // BFS stamp of the next sample (records start at stamp 0)
+  // slot arrays of the bidirectional sampler (forward and backward records
+  // and queues); stamps are shared with the single-source sampler
+  centra::DevBuf bi_rec_f, bi_rec_b, bi_q_f, bi_q_b;
+  uint32_t bi_slots = 0;
+  uint32_t bi_n = 0;
   // sampling staging area
   centra::DevBuf stage_nodes, stage_pos, stage_len, work_ctr, multi_tab;
   // scan scratch
@@ -61,6 +66,7 @@ struct centra_graph {
   uint32_t max_in_degree = 0;
   uint32_t max_out_degree = 0;
   uint32_t count_bits = 0;
+  uint32_t count_bits_override = 0;   // test override of both count budgets (0: none)
   // the arrays the sampler traverses: the locality-relabelled copy
   // (relabel_graph) or the caller's CSR; new_of / orig_of map caller ids
   // to traversal ids and back (both NULL without relabelling)
@@ -138,6 +144,11 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
                     uint64_t* total, hipStream_t s);
 int stage_to_output(centra_ctx* ctx, uint32_t count, uint64_t base, uint64_t* he_off,
                     uint32_t* he_nodes, hipStream_t s);
+// The balanced bidirectional sampler (bidir.hip): samples [first,
+// first+count) into the staging area, as sample_to_stage.
+int sample_bidir_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance,
+                          uint64_t first, uint32_t count, uint32_t* st_out, uint32_t* dist_out,
+                          uint64_t* total, hipStream_t s);
 // A fused sampling launch over several graphs: item i draws samples
 // [first, first + count) of (g, seed, instance); the staging area holds
 // them item after item.  block: threads per BFS (64, 128, 256 or 512).

@@ -1135,7 +1135,12 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
     // stamps: this launch numbers its work items stamp_next, stamp_next + 1,
     // ...; when 32 bits would run out, clear every record and restart at 1
     if (ctx->stamp_next == 0 || uint64_t(ctx->stamp_next) + count > 0xFFFFFFFFull) {
+      // (the bidirectional sampler's records carry the same stamps)
       fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(ctx->slots) * ctx->slot_n * 2, s);
+      if (ctx->bi_rec_f.ptr) {
+        fill_u64(static_cast<uint64_t*>(ctx->bi_rec_f.ptr), 0, size_t(ctx->bi_slots) * ctx->bi_n * 2, s);
+        fill_u64(static_cast<uint64_t*>(ctx->bi_rec_b.ptr), 0, size_t(ctx->bi_slots) * ctx->bi_n * 2, s);
+      }
       ctx->stamp_next = 1;
     }
     a.stamp0 = ctx->stamp_next;

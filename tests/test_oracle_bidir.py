@@ -160,3 +160,20 @@ def test_prefix_property_and_fewer_arcs():
     _, _, inf_u = oracle.sample_paths(g, 4, 1, 0, 600, with_info=True)
     # the balanced search scans a small fraction of a whole-level BFS
     assert sum(i.arcs_scanned for i in inf_a) * 5 < sum(i.arcs_scanned for i in inf_u)
+
+
+def test_progressive_on_bidir_matches_its_parts():
+    # Algorithm 1 with the bidirectional sampler: the result equals greedy,
+    # the AMCERA and the bound recomputed on its final sample
+    g = inputs.ba_graph(400, 3, 6)
+    k, t, eps, delta, seed = 5, 8, 0.2, 0.1, 2
+    rc, picks, res, mlog = oracle.progressive(g, k, t, eps, delta, seed, 0, 1000, 64000,
+                                              space=oracle.SPACE_PATHS_BIDIR, with_m_log=True)
+    assert rc in (0, 1) and res.iterations >= 1
+    m = res.m_final
+    off, nodes = oracle.sample_paths_bidir(g, seed, 0, 0, m)
+    p2, cov = oracle.greedy_cover(g.n, off, nodes, k)
+    assert np.array_equal(picks, p2) and res.coverage == cov[-1]
+    am, topk, dk, bm = oracle.mcera(g.n, off, nodes, seed, 0, t, k)
+    o = oracle.bound(m, int(cov[-1]), int(topk.sum()), t, dk, bm, eps, delta / 2**res.iterations)
+    assert res.eta == o.eta and (rc == 0) == bool(o.certified)
