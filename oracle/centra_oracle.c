@@ -516,7 +516,7 @@ static uint32_t bidir_one(const orc_graph *g, uint32_t c_f, uint32_t c_b, uint64
     uint32_t n = g->n;
     uint32_t s = (uint32_t)orc_bounded(&st, n);
     uint32_t tp = (uint32_t)orc_bounded(&st, n - 1);
-    uint32_t t = tp + (tp >= s ? 1u : 0u);
+    uint32_t t = tp >= s ? tp + 1u : tp;   /* the pair rule of R3 */
     const uint32_t *ip = in_ptr(g), *ii = in_idx(g);
     uint64_t arcs = 0;
     side_start(F, s);

@@ -421,8 +421,8 @@ static int ensure_bidir_slots(centra_ctx* ctx, uint32_t n, uint32_t want, hipStr
   if (most == 0) most = 1;
   if (want > most) want = static_cast<uint32_t>(most);
   if (ctx->bi_slots >= want && ctx->bi_n >= n) return CENTRA_OK;
-  uint32_t slots = want > ctx->bi_slots ? want : ctx->bi_slots;
-  const uint32_t nn = n > ctx->bi_n ? n : ctx->bi_n;
+  uint32_t slots = want;   // sized for this launch alone (see ensure_slots)
+  const uint32_t nn = n;
   for (;;) {
     const size_t need = size_t(slots) * nn * 40;
     const size_t have = ctx->bi_rec_f.bytes + ctx->bi_rec_b.bytes + ctx->bi_q_f.bytes + ctx->bi_q_b.bytes;

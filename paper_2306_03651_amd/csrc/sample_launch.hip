@@ -1,0 +1,281 @@
+// Host side of the single-source path sampler: launch shape, per-BFS slot
+// state, the staging area and its redraw on overflow, the layout of the
+// staged hyperedges in sample order.  The kernel is in sample.hip.
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "sample.hpp"
+
+namespace centra {
+
+// Launch shapes: the LDS-bitmap variant runs one 1024-thread workgroup per
+// CU (the bitmap takes most of the LDS); the other variants (Bloom filter in
+// LDS, visited state in the HBM records) run several workgroups of 64 to
+// 512 threads per CU.
+constexpr uint32_t kMaxSlots = 8192;
+
+struct SamplePlan {
+  bool lds_bits;
+  int block;         // workgroup size of the Bloom-filter variants
+  uint32_t bit_words;
+  size_t dyn_lds;
+  uint32_t resident;   // workgroups resident at once = BFS slots
+};
+
+// Variant choice.  Default: the Bloom-filter kernel with 128-thread
+// workgroups (many concurrent BFSs per CU hide the latency of the short,
+// dependent steps of each BFS).  CENTRA_SAMPLER_VARIANT selects another:
+// "lds" (LDS bitmap, 1024 threads, when the bitmap fits), "hbm512",
+// "hbm256", "hbm128", "hbm64" (Bloom filter, that many threads).
+static SamplePlan plan_for(centra_ctx* ctx, uint32_t n, int block_override = 0) {
+  SamplePlan p{};
+  p.bit_words = (n + 31) / 32;
+  int max_lds = 0, cus = 0;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess)
+    max_lds = 65536;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+    cus = 256;
+  const size_t dyn = size_t(p.bit_words) * 4;
+  const char* env = getenv("CENTRA_SAMPLER_VARIANT");
+  const char* v = env ? env : "hbm128";
+  p.block = 128;
+  if (!strcmp(v, "hbm512")) p.block = 512;
+  if (!strcmp(v, "hbm256")) p.block = 256;
+  if (!strcmp(v, "hbm64")) p.block = 64;
+  p.lds_bits = !strcmp(v, "lds") && sample_lds_variant_bytes() + dyn <= size_t(max_lds);
+  if (block_override) {   // fused launches: a Bloom-filter variant chosen by the caller
+    p.block = block_override;
+    p.lds_bits = false;
+  }
+  int per_cu = 0;
+  p.dyn_lds = p.lds_bits ? dyn : 0;
+  hipError_t e = sample_kernel_occupancy(p.block, p.lds_bits, block_override != 0, p.dyn_lds, &per_cu);
+  if (e != hipSuccess || per_cu <= 0) per_cu = 1;
+  (void)hipGetLastError();
+  const uint64_t r = uint64_t(cus) * uint64_t(per_cu);
+  p.resident = r > kMaxSlots ? kMaxSlots : static_cast<uint32_t>(r);
+  return p;
+}
+
+// Slot state takes at most half of the device's memory (96 GiB if the size
+// cannot be queried); the context budget, when set, limits it further.
+static size_t slot_mem_cap() {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || total_b == 0) {
+    (void)hipGetLastError();
+    return size_t(96) << 30;
+  }
+  return total_b / 2;
+}
+
+static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t s) {
+  const size_t cap_bytes = slot_mem_cap();
+  {
+    // never ask for more slots than the cap holds
+    const size_t per = size_t(gn) * (16 + 4) + kPairMax * (8 + 12);
+    const size_t most = cap_bytes / (per ? per : 1);
+    if (want > most) want = most ? static_cast<uint32_t>(most) : 1u;
+  }
+  if (ctx->slots >= want && ctx->slot_n >= gn) return CENTRA_OK;
+  // a new allocation is sized for this launch alone: keeping the largest n
+  // ever seen with the largest slot count ever asked for would grow the
+  // state (and its zero fill) to the memory cap after one large graph
+  uint32_t slots = want;
+  const uint32_t n = gn;
+  const size_t per_slot = size_t(n) * (16 + 4) + kPairMax * (8 + 12);
+  // at most the cap of slot state (or the budget, if smaller)
+  if (size_t(slots) * per_slot > cap_bytes) slots = static_cast<uint32_t>(cap_bytes / per_slot);
+  if (slots == 0) slots = 1;
+  // shrink the slot count if the budget cannot hold all of them
+  for (;;) {
+    const size_t need = size_t(slots) * per_slot;
+    const size_t have = ctx->slot_rec.bytes + ctx->slot_q.bytes + ctx->slot_praw.bytes + ctx->slot_pinfo.bytes;
+    if (!ctx->budget || ctx->allocated - have + need <= ctx->budget || slots <= 1) break;
+    slots /= 2;
+  }
+  release(ctx, ctx->slot_rec);
+  release(ctx, ctx->slot_praw);
+  release(ctx, ctx->slot_pinfo);
+  release(ctx, ctx->slot_q);
+  ctx->slots = 0;
+  ctx->slot_n = 0;
+  int rc;
+  if ((rc = ensure(ctx, ctx->slot_rec, size_t(slots) * n * 16, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->slot_praw, size_t(slots) * kPairMax * 8, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->slot_pinfo, size_t(slots) * kPairMax * 12, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->slot_q, size_t(slots) * n * 4, false, s))) return rc;
+  fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(slots) * n * 2, s);   // stamp 0: never claimed
+  CENTRA_HIP(ctx, hipGetLastError());
+  ctx->slots = slots;
+  ctx->slot_n = n;
+  return CENTRA_OK;
+}
+
+// Runs one sampling launch of `count` work items into the staging area
+// (redrawn with a larger area if it overflows); `a` holds the graph part of
+// the arguments (or the instance table of a fused launch), `max_n` the
+// largest n of its graphs.  *total receives the staged node count.
+static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_t max_n, bool multi, int block,
+                          uint64_t* total, hipStream_t s) {
+  int rc;
+  *total = 0;
+  const SamplePlan plan = plan_for(ctx, max_n, multi ? block : 0);
+  uint32_t want = count < plan.resident ? count : plan.resident;
+  if ((rc = ensure_slots(ctx, max_n, want, s))) return rc;
+  const uint32_t grid = count < ctx->slots ? count : ctx->slots;
+  if ((rc = ensure(ctx, ctx->stage_pos, size_t(count) * 8, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->stage_len, size_t(count) * 4 + 8 + 8 * (size_t(count) + 1), false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->work_ctr, 64, false, s))) return rc;
+  uint64_t cap = size_t(count) * 8 + 1024;
+  if (ctx->stage_nodes.bytes / 4 > cap) cap = ctx->stage_nodes.bytes / 4;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    if ((rc = ensure(ctx, ctx->stage_nodes, cap * 4, false, s))) return rc;
+    cap = ctx->stage_nodes.bytes / 4;
+    uint32_t* work = static_cast<uint32_t*>(ctx->work_ctr.ptr);
+    uint64_t* used = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 8);
+    fill_u32(work, 0, 1, s);
+    fill_u64(used, 0, 1, s);
+    // stamps: this launch numbers its work items stamp_next, stamp_next + 1,
+    // ...; when 32 bits would run out, clear every record and restart at 1
+    if (ctx->stamp_next == 0 || uint64_t(ctx->stamp_next) + count > 0xFFFFFFFFull) {
+      // (the bidirectional sampler's records carry the same stamps)
+      fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(ctx->slots) * ctx->slot_n * 2, s);
+      if (ctx->bi_rec_f.ptr) {
+        fill_u64(static_cast<uint64_t*>(ctx->bi_rec_f.ptr), 0, size_t(ctx->bi_slots) * ctx->bi_n * 2, s);
+        fill_u64(static_cast<uint64_t*>(ctx->bi_rec_b.ptr), 0, size_t(ctx->bi_slots) * ctx->bi_n * 2, s);
+      }
+      ctx->stamp_next = 1;
+    }
+    a.stamp0 = ctx->stamp_next;
+    ctx->stamp_next += count;
+    a.count = count;
+    a.slot_stride = ctx->slot_n;
+    a.rec = static_cast<uint64_t*>(ctx->slot_rec.ptr);
+    a.q = static_cast<uint32_t*>(ctx->slot_q.ptr);
+    a.praw = static_cast<uint64_t*>(ctx->slot_praw.ptr);
+    a.pinfo = static_cast<uint32_t*>(ctx->slot_pinfo.ptr);
+    a.bit_words = plan.bit_words;
+    a.work = work;
+    a.stage = static_cast<uint32_t*>(ctx->stage_nodes.ptr);
+    a.stage_cap = cap;
+    a.stage_used = used;
+    a.stage_pos = static_cast<uint64_t*>(ctx->stage_pos.ptr);
+    a.he_len = static_cast<uint32_t*>(ctx->stage_len.ptr);
+    a.flags = ctx->d_flags;
+    a.stats = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 16);
+    fill_u64(a.stats, 0, 2, s);
+    CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
+    sample_kernel_launch(a, plan.block, plan.lds_bits, multi, grid, plan.dyn_lds, s);
+    CENTRA_HIP(ctx, hipGetLastError());
+    CENTRA_HIP(ctx, hipEventRecord(ctx->ev[7], s));
+    uint64_t host_ctr[4] = {0, 0, 0, 0};   // work, used, arcs, nodes
+    CENTRA_HIP(ctx, hipMemcpyAsync(host_ctr, ctx->work_ctr.ptr, 32, hipMemcpyDeviceToHost, s));
+    CENTRA_HIP(ctx, hipStreamSynchronize(s));
+    if ((rc = check_flags(ctx, s, "sample_paths"))) return rc;
+    const uint64_t host_used = host_ctr[1];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]) != hipSuccess) ms = 0.f;
+    ctx->st.launches += 1;
+    ctx->st.kernel_ms += ms;
+    ctx->st.samples += count;
+    ctx->st.arcs += host_ctr[2];
+    ctx->st.nodes += host_ctr[3];
+    ctx->st.hyperedge_nodes += host_used <= cap ? host_used : 0;
+    ctx->st.lds_bitmap = plan.lds_bits ? 1 : 0;
+    ctx->st.slots = grid;
+    if (host_used <= cap) {
+      *total = host_used;
+      return CENTRA_OK;
+    }
+    cap = host_used + 1024;   // staging overflowed: the batch is redrawn identically
+  }
+  return fail(ctx, CENTRA_EHIP, "sample_paths: staging did not converge");
+}
+
+int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
+                    uint32_t count, uint32_t* st_out, uint32_t* dist_out, uint64_t* total, hipStream_t s) {
+  *total = 0;
+  if (count == 0) return CENTRA_OK;
+  SampleArgs a{};
+  a.n = g->n;
+  a.c_bits = g->count_bits;
+  a.max_out_deg = g->max_out_degree;
+  a.row_ptr = g->bfs_row_ptr;
+  a.col_idx = g->bfs_col_idx;
+  a.in_ptr = g->bfs_in_ptr;
+  a.in_idx = g->bfs_in_idx;
+  a.new_of = g->new_of;
+  a.orig_of = g->orig_of;
+  a.seed = seed;
+  a.instance = instance;
+  a.first = first;
+  a.st_out = st_out;
+  a.dist_out = dist_out;
+  return launch_sampler(ctx, a, count, g->n, false, 0, total, s);
+}
+
+int sample_multi_to_stage(centra_ctx* ctx, const MultiSampleItem* items, uint32_t n_items, int block,
+                          uint64_t* total, hipStream_t s) {
+  *total = 0;
+  std::vector<SampleInst> tab;
+  std::vector<uint32_t> off;
+  uint64_t count = 0;
+  uint32_t max_n = 0;
+  for (uint32_t i = 0; i < n_items; ++i) {
+    const MultiSampleItem& it = items[i];
+    if (it.count == 0) continue;
+    const centra_graph* g = it.g;
+    SampleInst x{};
+    x.n = g->n;
+    x.c_bits = g->count_bits;
+    x.max_out_deg = g->max_out_degree;
+    x.instance = it.instance;
+    x.row_ptr = g->bfs_row_ptr;
+    x.col_idx = g->bfs_col_idx;
+    x.in_ptr = g->bfs_in_ptr;
+    x.in_idx = g->bfs_in_idx;
+    x.new_of = g->new_of;
+    x.orig_of = g->orig_of;
+    x.seed = it.seed;
+    x.first = it.first;
+    tab.push_back(x);
+    off.push_back(static_cast<uint32_t>(count));
+    count += it.count;
+    if (g->n > max_n) max_n = g->n;
+  }
+  if (count == 0) return CENTRA_OK;
+  if (count >= (1ull << 32)) return fail(ctx, CENTRA_ENOTSUP, "sample_multi: 2^32 work items or more");
+  off.push_back(static_cast<uint32_t>(count));
+  int rc;
+  const size_t tab_bytes = tab.size() * sizeof(SampleInst);
+  if ((rc = ensure(ctx, ctx->multi_tab, tab_bytes + off.size() * 4 + 256, false, s))) return rc;
+  char* dtab = static_cast<char*>(ctx->multi_tab.ptr);
+  const size_t off_at = (tab_bytes + 255) & ~size_t(255);
+  CENTRA_HIP(ctx, hipMemcpyAsync(dtab, tab.data(), tab_bytes, hipMemcpyHostToDevice, s));
+  CENTRA_HIP(ctx, hipMemcpyAsync(dtab + off_at, off.data(), off.size() * 4, hipMemcpyHostToDevice, s));
+  SampleArgs a{};
+  a.inst = reinterpret_cast<const SampleInst*>(dtab);
+  a.item_off = reinterpret_cast<const uint32_t*>(dtab + off_at);
+  a.n_inst = static_cast<uint32_t>(tab.size());
+  rc = launch_sampler(ctx, a, static_cast<uint32_t>(count), max_n, true, block, total, s);
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));   // the host tables above go out of scope
+  return rc;
+}
+
+int stage_to_output(centra_ctx* ctx, uint32_t count, uint64_t base, uint64_t* he_off, uint32_t* he_nodes,
+                    hipStream_t s) {
+  uint32_t* len = static_cast<uint32_t*>(ctx->stage_len.ptr);
+  uint64_t* rel = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->stage_len.ptr) + ((size_t(count) * 4 + 7) & ~size_t(7)));
+  int rc = excl_scan_u32_to_u64(ctx, len, rel, count, s);
+  if (rc) return rc;
+  stage_gather_launch(count, static_cast<const uint64_t*>(ctx->stage_pos.ptr), len, rel, base,
+                      static_cast<const uint32_t*>(ctx->stage_nodes.ptr), he_off, he_nodes, s);
+  CENTRA_HIP(ctx, hipGetLastError());
+  return CENTRA_OK;
+}
+
+}  // namespace centra

@@ -52,6 +52,8 @@ MUTANTS = {
                                        "tests/test_oracle_sampler.py"),
     "graph_check_reverse_sources_unchecked": ("                if (!found) return -21;", "                if (!found && 0) return -21;",
                                               "tests/test_oracle_sampler.py"),
+    "bidir_pair_may_repeat_s": ("    uint32_t t = tp >= s ? tp + 1u : tp;", "    uint32_t t = tp > s ? tp + 1u : tp;",
+                                "tests/test_oracle_bidir.py"),
     "bidir_weight_forward_only": ("    return (unsigned __int128)F->sigma[v] * B->sigma[v];",
                                   "    return (unsigned __int128)F->sigma[v];", "tests/test_oracle_bidir.py"),
     "bidir_walk_wrong_side": ("            cur = walk_step(B, g->row_ptr, g->col_idx, cur, B->level[cur] - 1, &st);",
