@@ -509,6 +509,8 @@ def main():
                          "triangles: the triangle space of R-MAT scale 20, undirected")
     ap.add_argument("--sweep", action="store_true",
                     help="run only the t and m sweeps of the fixed-size bound (one JSON line)")
+    ap.add_argument("--hedge", action="store_true",
+                    help="also run HEDGE-P (union bound, same schedule) to certification, outside the timed steps")
     ap.add_argument("--sampler", choices=["single", "bidir"], default="single",
                     help="shortest-path workloads: the single-source sampler (default) or the balanced "
                          "bidirectional one (centra_sample_paths_bidir)")
@@ -607,12 +609,12 @@ def main():
     # time to certified (outside the timed steps): the same doubling schedule
     # without the 4M cap, and the paper's own schedule (growth 1.2 with the
     # optimistic guess)
-    def uncapped_run(num, den, schedule):
+    def uncapped_run(num, den, schedule, method=binding.CENTRA_METHOD_CENTRA):
         torch.cuda.synchronize()
         tu = time.perf_counter()
         urc, upicks, ures, ulog = binding.centra_progressive(
             ctx, dg.handle, W["k"], W["t"], W["eps"], W["delta"], W["seed"], W["instance"], W["m_init"],
-            args.uncapped_max, num, den, stream=stream, schedule=schedule, space=space, kappa=kappa)
+            args.uncapped_max, num, den, stream=stream, schedule=schedule, space=space, kappa=kappa, method=method)
         torch.cuda.synchronize()
         return {"time_s": round(time.perf_counter() - tu, 3), "certified": bool(ures.certified),
                 "m_final": int(ures.m_final), "iterations": int(ures.iterations),
@@ -625,6 +627,12 @@ def main():
         log(f"uncapped: {uncapped}")
         adaptive = uncapped_run(6, 5, binding.CENTRA_SCHEDULE_ADAPTIVE)
         log(f"adaptive: {adaptive}")
+    hedge = None
+    if args.hedge:
+        # HEDGE-P (Sec. 5's comparison method): the same doubling schedule
+        # and sampler with the union bound in place of the AMCERA
+        hedge = uncapped_run(W["growth"], 1, binding.CENTRA_SCHEDULE_GEOMETRIC, binding.CENTRA_METHOD_HEDGE_P)
+        log(f"hedge-p: {hedge}")
     dg.release()
     binding.centra_destroy(ctx)
 
@@ -685,6 +693,7 @@ def main():
         "uncapped_run": uncapped,
         "time_to_certified_adaptive_s": adaptive["time_s"] if adaptive and adaptive["certified"] else None,
         "uncapped_adaptive_run": adaptive,
+        "hedge_p_run": hedge,
         "certified": bool(res.certified),
         "m_final": int(res.m_final),
         "iterations": int(res.iterations),

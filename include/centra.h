@@ -38,7 +38,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 8u
+#define CENTRA_ABI_VERSION 9u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -263,6 +263,20 @@ typedef struct {
 CENTRA_API int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t deg_topk,
                  uint32_t b_max, double eps, double delta_i, centra_bound_out *out);
 
+/* HEDGE-P's bound (Sec. 5 describes HEDGE-P as Algorithm 1's iterations
+ * with a union bound eta^UB in place of the AMCERA and HEDGE's stopping
+ * rule SD <= eps C(S*) / 2; the paper does not print eta^UB, so this form is
+ * this library's): with N_k = sum_{j <= k} C(n, j) node sets of at most k
+ * nodes, Hoeffding's two-sided inequality and a union bound at confidence
+ * delta_i give eta^UB = sqrt((ln(2 N_k) + ln(1 / delta_i)) / (2 m));
+ * C(S*) >= C_H(S) - eta^UB on that event, so the rule holds once
+ * eta^UB <= eps (C_H(S) - eta^UB) / 2 (out->certified).  ln N_k is summed
+ * in FP64 from lgamma terms.  Writes out->c_hat = cov / m, out->eta and
+ * out->certified; the other fields are 0.  Host only.
+ * Errors: CENTRA_EINVAL (m, n or k is 0, delta_i outside (0,1), out NULL). */
+CENTRA_API int centra_hedge_bound(uint64_t m, uint64_t cov, uint64_t n, uint32_t k, double eps, double delta_i,
+                       centra_bound_out *out);
+
 /* VC-dimension bounds of Sec. 4.3 for the range space Q_k (ranges: the
  * hyperedges met by a node set of at most k nodes), host only:
  *   d1       = floor(log2(2b)) >= VC(Q_1) when every hyperedge of the space
@@ -351,6 +365,12 @@ CENTRA_API int centra_sample_kpaths(centra_ctx *ctx, const centra_graph *g, uint
  * centra_sample_triangles) or CENTRA_SPACE_KPATHS (kappa-path centrality,
  * centra_sample_kpaths with the params' kappa; kappa is ignored otherwise)
  * or CENTRA_SPACE_PATHS_BIDIR (set betweenness, centra_sample_paths_bidir).
+ * The method: CENTRA_METHOD_CENTRA (the AMCERA and the bound of Theorem
+ * bound_dev, the stopping condition of Algorithm 1) or
+ * CENTRA_METHOD_HEDGE_P, the comparison method of Sec. 5: the same
+ * iterations with the union bound of centra_hedge_bound in place of the
+ * AMCERA (t is then unused) and its stopping rule; the result's eta is
+ * eta^UB and its AMCERA fields are 0.
  * Inputs: k >= 1, 1 <= t <= 1024, eps in (0, 1-1/e), delta in (0,1),
  * 1 <= m_init <= m_max < 2^31, growth_num > growth_den >= 1, schedule and
  * space one of their values, 1 <= kappa <= CENTRA_MAX_KAPPA for
@@ -368,6 +388,8 @@ CENTRA_API int centra_sample_kpaths(centra_ctx *ctx, const centra_graph *g, uint
 #define CENTRA_SPACE_TRIANGLES 1u
 #define CENTRA_SPACE_KPATHS 2u
 #define CENTRA_SPACE_PATHS_BIDIR 3u   /* shortest paths, bidirectional sampler */
+#define CENTRA_METHOD_CENTRA 0u
+#define CENTRA_METHOD_HEDGE_P 1u
 
 typedef struct {
     uint32_t k, t;
@@ -379,6 +401,7 @@ typedef struct {
     uint32_t schedule;   /* CENTRA_SCHEDULE_* */
     uint32_t space;      /* CENTRA_SPACE_* */
     uint32_t kappa;      /* path length bound of CENTRA_SPACE_KPATHS */
+    uint32_t method;     /* CENTRA_METHOD_* */
 } centra_params;
 
 typedef struct {

@@ -102,8 +102,13 @@ def _load():
     lib.orc_bound.restype = None
     lib.orc_progressive.argtypes = [c.POINTER(Graph), c.c_uint32, c.c_uint32, c.c_uint32, c.c_double,
                                     c.c_double, c.c_uint64, c.c_uint32, c.c_uint64, c.c_uint64,
-                                    c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, _u32p,
-                                    c.POINTER(Result), _u64p, c.c_uint32]
+                                    c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32, c.c_uint32,
+                                    _u32p, c.POINTER(Result), _u64p, c.c_uint32]
+    lib.orc_log_sets.argtypes = [c.c_uint64, c.c_uint32]
+    lib.orc_log_sets.restype = c.c_double
+    lib.orc_hedge_bound.argtypes = [c.c_uint64, c.c_uint64, c.c_uint64, c.c_uint32, c.c_double, c.c_double,
+                                    c.POINTER(BoundOut)]
+    lib.orc_hedge_bound.restype = None
     lib.orc_vc_dims.argtypes = [c.c_uint64, c.c_uint32, c.c_uint64, c.POINTER(c.c_uint32), c.POINTER(c.c_uint64),
                                 c.POINTER(c.c_uint64)]
     lib.orc_vc_dims.restype = c.c_int
@@ -350,9 +355,22 @@ def sample_kpaths(g, kappa, seed, instance, first, count):
     return None if rc else (off, nodes[: int(off[-1])])
 
 
+def log_sets(n, k) -> float:
+    return _load().orc_log_sets(n, k)
+
+
+def hedge_bound(m, cov, n, k, eps, delta_i) -> BoundOut:
+    o = BoundOut()
+    _load().orc_hedge_bound(m, cov, n, k, eps, delta_i, ctypes.byref(o))
+    return o
+
+
+METHOD_CENTRA, METHOD_HEDGE_P = 0, 1
+
+
 def progressive(g, k, t, eps, delta, seed, instance, m_init, m_max, growth_num=2, growth_den=1,
                 c_bits=None, schedule=SCHEDULE_GEOMETRIC, with_m_log=False, space=SPACE_SHORTEST_PATHS,
-                kappa=0):
+                kappa=0, method=METHOD_CENTRA):
     """Algorithm 1; returns (rc, picks, Result) and, with with_m_log, the
     sample size of every iteration."""
     og = OracleGraph(g)
@@ -363,7 +381,7 @@ def progressive(g, k, t, eps, delta, seed, instance, m_init, m_max, growth_num=2
     res = Result()
     m_log = np.zeros(256, dtype=np.uint64)
     rc = lib.orc_progressive(ctypes.byref(og.c), c_bits, k, t, eps, delta, seed, instance, m_init, m_max,
-                             growth_num, growth_den, schedule, space, kappa, picks, ctypes.byref(res), m_log,
+                             growth_num, growth_den, schedule, space, kappa, method, picks, ctypes.byref(res), m_log,
                              len(m_log))
     out = (rc, picks[: res.n_picked].copy(), res)
     if with_m_log:

@@ -772,6 +772,44 @@ void orc_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t,
     o->certified = a * ((a - eps) * xi + eta) <= eps * C;
 }
 
+/* HEDGE-P's bound (Sec. 5 describes HEDGE-P: Algorithm 1's iterations with
+ * a union-bound eta^UB in place of the AMCERA and HEDGE's stopping rule
+ * SD <= eps C(S*) / 2; the paper does not print eta^UB, so this form is the
+ * builder's own, reading R17).  There are N_k = sum_{j <= k} C(n, j) node
+ * sets of at most k nodes; for each, C_H(S) is the mean of m independent
+ * indicators with mean C(S), and Hoeffding's two-sided inequality with a
+ * union bound over all of them at confidence delta_i gives
+ *   eta^UB = sqrt((ln(2 N_k) + ln(1 / delta_i)) / (2 m)).
+ * On that event C(S*) >= C(S) >= C_H(S) - eta^UB for the greedy set S, so
+ * the rule SD <= eps C(S*) / 2 holds once eta^UB <= eps (C_H(S) - eta^UB) / 2. */
+double orc_log_sets(uint64_t n, uint32_t k)
+{
+    /* log-sum-exp of ln C(n, j), j = 0 .. min(k, n) */
+    const uint64_t top = k < n ? k : n;
+    double mx = -INFINITY;
+    for (uint64_t j = 0; j <= top; j++) {
+        double x = lgamma((double)n + 1.0) - lgamma((double)j + 1.0) - lgamma((double)(n - j) + 1.0);
+        if (x > mx) mx = x;
+    }
+    double acc = 0.0;
+    for (uint64_t j = 0; j <= top; j++) {
+        double x = lgamma((double)n + 1.0) - lgamma((double)j + 1.0) - lgamma((double)(n - j) + 1.0);
+        acc += exp(x - mx);
+    }
+    return mx + log(acc);
+}
+
+void orc_hedge_bound(uint64_t m, uint64_t cov, uint64_t n, uint32_t k, double eps, double delta_i,
+                     orc_bound_out *o)
+{
+    memset(o, 0, sizeof(*o));
+    const double C = (double)cov / (double)m;
+    const double eta = sqrt((log(2.0) + orc_log_sets(n, k) + log(1.0 / delta_i)) / (2.0 * (double)m));
+    o->c_hat = C;
+    o->eta = eta;
+    o->certified = eta <= eps * (C - eta) / 2.0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Algorithm 1 (progressive sampling), readings R1 and R10. */
 /* ---- triangle hyperedges (Sec. 3.1) ---- */
@@ -933,13 +971,13 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                     double eps, double delta, uint64_t seed, uint32_t instance,
                     uint64_t m_init, uint64_t m_max, uint32_t growth_num,
                     uint32_t growth_den, uint32_t schedule, uint32_t space, uint32_t kappa,
-                    uint32_t *picks, orc_result *res, uint64_t *m_log,
+                    uint32_t method, uint32_t *picks, orc_result *res, uint64_t *m_log,
                     uint32_t m_log_cap)
 {
     const double a = 1.0 - exp(-1.0);
     if (k == 0 || t == 0 || !(eps > 0.0 && eps < a) || !(delta > 0.0 && delta < 1.0) ||
         m_init == 0 || m_max < m_init || growth_den == 0 || growth_num <= growth_den ||
-        schedule > 2 || space > 3 || (space == 2 && kappa == 0))
+        schedule > 2 || space > 3 || (space == 2 && kappa == 0) || method > 1)
         return -1;
     /* space 3: the bidirectional sampler; a lowered forward budget (a test
      * override) lowers the backward one too */
@@ -998,13 +1036,17 @@ int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
         }
         uint32_t np = orc_greedy_cover(g->n, m_i, he_off, he_nodes, k, picks, cov_cum);
         uint64_t cov = np ? cov_cum[np - 1] : 0;
-        uint64_t dk;
-        uint32_t bm;
-        orc_mcera(g->n, m_i, he_off, he_nodes, seed, instance, t, k, topk, &dk, &bm);
-        int64_t sum = 0;
-        for (uint32_t j = 0; j < t; j++) sum += topk[j];
         orc_bound_out o;
-        orc_bound(m_i, cov, sum, t, dk, bm, eps, delta_i, &o);
+        if (method == 1) {   /* HEDGE-P: the union bound, no AMCERA */
+            orc_hedge_bound(m_i, cov, g->n, k, eps, delta_i, &o);
+        } else {
+            uint64_t dk;
+            uint32_t bm;
+            orc_mcera(g->n, m_i, he_off, he_nodes, seed, instance, t, k, topk, &dk, &bm);
+            int64_t sum = 0;
+            for (uint32_t j = 0; j < t; j++) sum += topk[j];
+            orc_bound(m_i, cov, sum, t, dk, bm, eps, delta_i, &o);
+        }
         res->n_picked = np;
         res->iterations = i;
         res->certified = o.certified;

@@ -218,12 +218,19 @@ int orc_sample_kpaths(const orc_graph *g, uint32_t kappa, uint64_t seed, uint32_
 int orc_vc_dims(uint64_t b, uint32_t k, uint64_t n, uint32_t *d1, uint64_t *dk_lemma, uint64_t *dk_union);
 
 /* space: 0 shortest paths, 1 triangles, 2 kappa-paths (kappa >= 1). */
+/* HEDGE-P's bound (reading R17): ln of the number of node sets of at most
+ * k nodes, and eta^UB with its stopping rule (o->eta, o->c_hat and
+ * o->certified are set; the other fields are 0). */
+double orc_log_sets(uint64_t n, uint32_t k);
+void orc_hedge_bound(uint64_t m, uint64_t cov, uint64_t n, uint32_t k, double eps, double delta_i,
+                     orc_bound_out *o);
+
 int orc_progressive(const orc_graph *g, uint32_t c_bits, uint32_t k, uint32_t t,
                     double eps, double delta, uint64_t seed, uint32_t instance,
                     uint64_t m_init, uint64_t m_max, uint32_t growth_num,
                     uint32_t growth_den, uint32_t schedule, uint32_t space, uint32_t kappa,
-                    uint32_t *picks, orc_result *res, uint64_t *m_log,
-                    uint32_t m_log_cap);
+                    uint32_t method, uint32_t *picks, orc_result *res, uint64_t *m_log,
+                    uint32_t m_log_cap);   /* method 0: CentRA; 1: HEDGE-P (reading R17) */
 
 #ifdef __cplusplus
 }

@@ -30,6 +30,8 @@ CENTRA_SPACE_SHORTEST_PATHS = 0
 CENTRA_SPACE_TRIANGLES = 1
 CENTRA_SPACE_KPATHS = 2
 CENTRA_SPACE_PATHS_BIDIR = 3
+CENTRA_METHOD_CENTRA = 0
+CENTRA_METHOD_HEDGE_P = 1
 CENTRA_MAX_KAPPA = 16
 
 _c = ctypes
@@ -61,7 +63,8 @@ class Params(_c.Structure):
     _fields_ = [("k", _c.c_uint32), ("t", _c.c_uint32), ("eps", _c.c_double), ("delta", _c.c_double),
                 ("seed", _c.c_uint64), ("instance", _c.c_uint32), ("m_init", _c.c_uint64),
                 ("m_max", _c.c_uint64), ("growth_num", _c.c_uint32), ("growth_den", _c.c_uint32),
-                ("schedule", _c.c_uint32), ("space", _c.c_uint32), ("kappa", _c.c_uint32)]
+                ("schedule", _c.c_uint32), ("space", _c.c_uint32), ("kappa", _c.c_uint32),
+                ("method", _c.c_uint32)]
 
 
 class Result(_c.Structure):
@@ -134,6 +137,8 @@ SIGNATURES = {
                                         _vp, _vp, _vp]),
     "centra_bound": (_c.c_int, [_c.c_uint64, _c.c_uint64, _c.c_int64, _c.c_uint32, _c.c_uint64, _c.c_uint32,
                                 _c.c_double, _c.c_double, _c.POINTER(BoundOut)]),
+    "centra_hedge_bound": (_c.c_int, [_c.c_uint64, _c.c_uint64, _c.c_uint64, _c.c_uint32, _c.c_double, _c.c_double,
+                                      _c.POINTER(BoundOut)]),
     "centra_vc_dims": (_c.c_int, [_c.c_uint64, _c.c_uint32, _c.c_uint64, _c.POINTER(VcOut)]),
     "centra_progressive": (_c.c_int, [_vp, _vp, _c.POINTER(Params), _vp, _c.POINTER(Result),
                                       _c.POINTER(Iteration), _c.c_uint32, _vp]),
@@ -311,6 +316,12 @@ def centra_bound(m: int, cov: int, sum_topk: int, t: int, deg_topk: int, b_max: 
     return out
 
 
+def centra_hedge_bound(m: int, cov: int, n: int, k: int, eps: float, delta_i: float) -> BoundOut:
+    out = BoundOut()
+    _check(lib().centra_hedge_bound(m, cov, n, k, eps, delta_i, ctypes.byref(out)))
+    return out
+
+
 def centra_vc_dims(b: int, k: int, n: int) -> VcOut:
     out = VcOut()
     _check(lib().centra_vc_dims(b, k, n, ctypes.byref(out)))
@@ -320,9 +331,10 @@ def centra_vc_dims(b: int, k: int, n: int) -> VcOut:
 def centra_progressive(ctx, g, k: int, t: int, eps: float, delta: float, seed: int, instance: int, m_init: int,
                        m_max: int, growth_num: int = 2, growth_den: int = 1, log_cap: int = 64, stream=None,
                        schedule: int = CENTRA_SCHEDULE_GEOMETRIC, space: int = CENTRA_SPACE_SHORTEST_PATHS,
-                       kappa: int = 0):
+                       kappa: int = 0, method: int = 0):
     """Returns (rc, picks np.uint32[n_picked], Result, [Iteration])."""
-    p = Params(k, t, eps, delta, seed, instance, m_init, m_max, growth_num, growth_den, schedule, space, kappa)
+    p = Params(k, t, eps, delta, seed, instance, m_init, m_max, growth_num, growth_den, schedule, space, kappa,
+               method)
     picks = np.zeros(max(1, k), dtype=np.uint32)
     res = Result()
     log = (Iteration * max(1, log_cap))()

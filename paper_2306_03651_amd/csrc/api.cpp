@@ -67,6 +67,33 @@ void bound_eval(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_t
   o->certified = a * ((a - eps) * xi + eta) <= eps * C ? 1 : 0;
 }
 
+// ln of the number of node sets of at most k nodes, sum_{j <= k} C(n, j),
+// by a log-sum-exp of lgamma terms; then HEDGE-P's union bound and rule.
+static double log_node_sets(uint64_t n, uint32_t k) {
+  const uint64_t top = k < n ? k : n;
+  const double ln_n1 = lgamma(static_cast<double>(n) + 1.0);
+  double mx = -INFINITY;
+  for (uint64_t j = 0; j <= top; ++j) {
+    const double x = ln_n1 - lgamma(static_cast<double>(j) + 1.0) - lgamma(static_cast<double>(n - j) + 1.0);
+    if (x > mx) mx = x;
+  }
+  double acc = 0.0;
+  for (uint64_t j = 0; j <= top; ++j) {
+    const double x = ln_n1 - lgamma(static_cast<double>(j) + 1.0) - lgamma(static_cast<double>(n - j) + 1.0);
+    acc += exp(x - mx);
+  }
+  return mx + log(acc);
+}
+
+void hedge_eval(uint64_t m, uint64_t cov, uint64_t n, uint32_t k, double eps, double delta_i, centra_bound_out* o) {
+  memset(o, 0, sizeof(*o));
+  const double C = static_cast<double>(cov) / static_cast<double>(m);
+  const double eta = sqrt((log(2.0) + log_node_sets(n, k) + log(1.0 / delta_i)) / (2.0 * static_cast<double>(m)));
+  o->c_hat = C;
+  o->eta = eta;
+  o->certified = eta <= eps * (C - eta) / 2.0 ? 1 : 0;
+}
+
 }  // namespace centra
 
 namespace {
@@ -383,6 +410,13 @@ int centra_sampler_stats_get(centra_ctx* ctx, centra_sampler_stats* out, int res
   return CENTRA_OK;
 }
 
+int centra_hedge_bound(uint64_t m, uint64_t cov, uint64_t n, uint32_t k, double eps, double delta_i,
+                       centra_bound_out* out) {
+  if (!out || m == 0 || n == 0 || k == 0 || !(delta_i > 0.0 && delta_i < 1.0)) return CENTRA_EINVAL;
+  hedge_eval(m, cov, n, k, eps, delta_i, out);
+  return CENTRA_OK;
+}
+
 int centra_vc_dims(uint64_t b, uint32_t k, uint64_t n, centra_vc_out* out) {
   if (!out || b == 0 || k == 0 || n == 0) return CENTRA_EINVAL;
   // floor(log2(2b)) is the bit length of b
@@ -416,6 +450,8 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
   if (p->space > CENTRA_SPACE_PATHS_BIDIR) return fail(ctx, CENTRA_EINVAL, "progressive: unknown hyperedge space");
   if (p->space == CENTRA_SPACE_KPATHS && (p->kappa == 0 || p->kappa > CENTRA_MAX_KAPPA))
     return fail(ctx, CENTRA_EINVAL, "progressive: kappa outside [1, 16]");
+  if (p->method > CENTRA_METHOD_HEDGE_P) return fail(ctx, CENTRA_EINVAL, "progressive: unknown method");
+  const bool hedge = p->method == CENTRA_METHOD_HEDGE_P;
   const bool tri = p->space == CENTRA_SPACE_TRIANGLES;
   const bool kp = p->space == CENTRA_SPACE_KPATHS;
   const bool fixed = p->schedule == CENTRA_SCHEDULE_FIXED;
@@ -436,6 +472,7 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
   char* misc = static_cast<char*>(ctx->misc.ptr);
   uint64_t* store_off = static_cast<uint64_t*>(ctx->store_off.ptr);
   fill_u64(store_off, 0, 1, s);
+  fill_u64(reinterpret_cast<uint64_t*>(misc), 0, misc_bytes / 8, s);   // HEDGE-P leaves the AMCERA fields at 0
   std::string host_block(misc_bytes, '\0');
   hipEvent_t* ev = ctx->ev;
   uint64_t m_prev = 0, m_i = p->m_init, total_nodes = 0;
@@ -480,11 +517,13 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
                                   s)))
       return rc;
     CENTRA_HIP(ctx, hipEventRecord(ev[2], s));
-    if ((rc = rade_words(ctx, p->seed, p->instance, m_prev, m_i, t, s))) return rc;
-    if ((rc = mcera_on_incidence(ctx, n, m_i, store_off, t, k, reinterpret_cast<int64_t*>(misc + o_tk),
-                                 reinterpret_cast<uint64_t*>(misc + o_dk), reinterpret_cast<uint32_t*>(misc + o_bm),
-                                 nullptr, s)))
-      return rc;
+    if (!hedge) {   // HEDGE-P bounds the deviation without the AMCERA
+      if ((rc = rade_words(ctx, p->seed, p->instance, m_prev, m_i, t, s))) return rc;
+      if ((rc = mcera_on_incidence(ctx, n, m_i, store_off, t, k, reinterpret_cast<int64_t*>(misc + o_tk),
+                                   reinterpret_cast<uint64_t*>(misc + o_dk), reinterpret_cast<uint32_t*>(misc + o_bm),
+                                   nullptr, s)))
+        return rc;
+    }
     CENTRA_HIP(ctx, hipEventRecord(ev[3], s));
     CENTRA_HIP(ctx, hipMemcpyAsync(&host_block[0], misc, misc_bytes, hipMemcpyDeviceToHost, s));
     CENTRA_HIP(ctx, hipStreamSynchronize(s));
@@ -504,7 +543,10 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
       sum += x;
     }
     centra_bound_out o;
-    bound_eval(m_i, cov, sum, t, dk, bm, p->eps, delta_i, &o);
+    if (hedge)
+      hedge_eval(m_i, cov, n, k, p->eps, delta_i, &o);
+    else
+      bound_eval(m_i, cov, sum, t, dk, bm, p->eps, delta_i, &o);
     const double ms_s = elapsed(ev[0], ev[1]), ms_c = elapsed(ev[1], ev[2]), ms_m = elapsed(ev[2], ev[3]);
     if (tri || kp) {   // the space's sampler launches join the sampling-kernel statistics
       ctx->st.launches += kp ? 2 : 1;

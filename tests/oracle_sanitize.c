@@ -102,16 +102,24 @@ static void exercise(const orc_graph *g, uint32_t c_bits, int triangles)
     uint64_t *koff = malloc(sizeof(uint64_t) * (count + 1));
     uint32_t *knodes = malloc(sizeof(uint32_t) * count * 6);
     CHECK(orc_sample_kpaths(g, 6, 2, 0, 7, count, koff, knodes) == 0);
-    for (uint32_t space = 0; space <= 2; space++) {
+    for (uint32_t space = 0; space <= 3; space++) {
         if (space == 1 && !triangles) continue;
         for (uint32_t sched = 0; sched <= 2; sched++) {
-            uint32_t p[5];
-            orc_result res;
-            uint64_t mlog[64];
-            const int rc = orc_progressive(g, c_bits, 5, 9, 0.2, 0.1, 4, 0, 200, 3000, 2, 1, sched, space, 4, p, &res,
-                                           mlog, 64);
-            CHECK(rc == 0 || rc == 1);
+            for (uint32_t method = 0; method <= 1; method++) {
+                uint32_t p[5];
+                orc_result res;
+                uint64_t mlog[64];
+                const int rc = orc_progressive(g, c_bits, 5, 9, 0.2, 0.1, 4, 0, 200, 3000, 2, 1, sched, space, 4,
+                                               method, p, &res, mlog, 64);
+                CHECK(rc == 0 || rc == 1);
+            }
         }
+    }
+    {
+        uint64_t boff[41];
+        uint32_t bnodes[40 * 64];
+        CHECK(orc_sample_paths_bidir(g, c_bits, orc_count_bits_out(g), 3, 1, 0, 40, boff, bnodes, 40 * 64, NULL) !=
+              UINT64_MAX || g->n > 64);
     }
     if (triangles) {
         const uint64_t T = orc_triangles(g, NULL, 0);

@@ -37,7 +37,7 @@ def test_binding_mirrors_header():
 
 
 def test_abi_version():
-    assert binding.centra_abi_version() == 8
+    assert binding.centra_abi_version() == 9
 
 
 CASES = [
@@ -82,3 +82,12 @@ def test_vc_dims_rejects_zeros():
     for args in [(0, 1, 1), (1, 0, 1), (1, 1, 0)]:
         with pytest.raises(binding.CentraError):
             binding.centra_vc_dims(*args)
+
+
+@pytest.mark.parametrize("m,cov,n,k,eps,delta_i", [(50000, 20000, 1000, 1, 0.1, 0.05), (10**6, 512000, 10**6, 50, 0.01, 0.1 / 8),
+                                                  (100, 0, 2, 2, 0.3, 0.5), (2**30, 2**29, 2**30, 500, 0.05, 1e-9)])
+def test_hedge_bound_matches_oracle(m, cov, n, k, eps, delta_i):
+    got = binding.centra_hedge_bound(m, cov, n, k, eps, delta_i)
+    want = oracle.hedge_bound(m, cov, n, k, eps, delta_i)
+    assert got.eta == pytest.approx(want.eta, rel=1e-12) and got.c_hat == want.c_hat
+    assert got.certified == want.certified and got.amcera == 0.0

@@ -96,3 +96,24 @@ def test_bad_schedule_rejected(ctx):
         assert e.value.code == binding.CENTRA_EINVAL
     finally:
         dg.release()
+
+
+@pytest.mark.parametrize("name", ["ba2000", "dir"])
+def test_hedge_p_matches_oracle(ctx, name):
+    # HEDGE-P (Sec. 5's comparison method): the same iterations with the
+    # union bound; picks, coverage, sample sizes bit-exact and eta^UB within
+    # 1e-12 of the oracle's
+    g = inputs.ba_graph(2000, 5, 1) if name == "ba2000" else inputs.rmat_graph(11, 8, seed=4)
+    dg = binding.DeviceGraph(ctx, g)
+    try:
+        say(f"HEDGE-P on {name}")
+        rc, picks, res, log = binding.centra_progressive(ctx, dg.handle, 5, 8, 0.2, 0.1, 3, 0, 2000, 1 << 20,
+                                                         method=binding.CENTRA_METHOD_HEDGE_P)
+    finally:
+        dg.release()
+    wrc, wpicks, wres, wlog = oracle.progressive(g, 5, 8, 0.2, 0.1, 3, 0, 2000, 1 << 20, with_m_log=True,
+                                                 method=oracle.METHOD_HEDGE_P)
+    assert rc == wrc and np.array_equal(picks, wpicks)
+    assert (res.iterations, res.m_final, res.coverage) == (wres.iterations, wres.m_final, wres.coverage)
+    assert [it.m for it in log] == wlog
+    assert res.eta == pytest.approx(wres.eta, rel=1e-12) and res.amcera == 0.0

@@ -145,3 +145,65 @@ def test_proposition_main_failure_rate():
         if C(set(int(x) for x in picks)) < (A - eps) * opt:
             fails += 1
     assert fails <= max(1, int(delta * runs))
+
+
+# ---------------------------------------------------------------------------
+# HEDGE-P's union bound (reading R17)
+def test_log_sets_matches_exact_binomial_sums():
+    # ln sum_{j <= k} C(n, j) against Python's exact integers
+    for n, k in [(2, 1), (10, 3), (40, 40), (1000, 5), (10**6, 50), (2**30, 100)]:
+        exact = math.log(sum(math.comb(n, j) for j in range(min(k, n) + 1)))
+        assert oracle.log_sets(n, k) == pytest.approx(exact, rel=1e-9)
+
+
+def test_hedge_bound_closed_forms():
+    # k = 1: N_1 = n + 1 sets, eta = sqrt(ln(2 (n + 1) / delta) / (2 m))
+    n, m, delta = 1000, 50000, 0.05
+    o = oracle.hedge_bound(m, 20000, n, 1, 0.1, delta)
+    assert o.eta == pytest.approx(math.sqrt(math.log(2 * (n + 1) / delta) / (2 * m)), rel=1e-12)
+    assert o.c_hat == 0.4
+    # the stopping rule: eta <= eps (C - eta) / 2, tested on both sides of
+    # the sample size that first satisfies it
+    eps = 0.1
+    lo = 1
+    while not oracle.hedge_bound(lo, lo // 2, n, 3, eps, delta).certified:
+        lo *= 2
+    hi = lo
+    lo //= 2
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if oracle.hedge_bound(mid, mid // 2, n, 3, eps, delta).certified:
+            hi = mid
+        else:
+            lo = mid
+    for mm, want in [(hi, True), (lo, False)]:
+        o = oracle.hedge_bound(mm, mm // 2, n, 3, eps, delta)
+        assert bool(o.certified) == want
+        assert (o.eta <= eps * (o.c_hat - o.eta) / 2) == want
+    # eta ~ 1/sqrt(m) and grows with k and 1/delta
+    a = oracle.hedge_bound(10**4, 5000, n, 5, eps, delta).eta
+    b = oracle.hedge_bound(4 * 10**4, 20000, n, 5, eps, delta).eta
+    assert a == pytest.approx(2 * b, rel=1e-12)
+    assert oracle.hedge_bound(10**4, 5000, n, 6, eps, delta).eta > a
+    assert oracle.hedge_bound(10**4, 5000, n, 5, eps, delta / 10).eta > a
+
+
+def test_hedge_p_progressive_matches_its_parts():
+    # HEDGE-P: Algorithm 1's loop with eta^UB; the result equals greedy and
+    # the union bound recomputed on the final sample, with delta_i = delta/2^i
+    from paper_2306_03651_amd import inputs
+    g = inputs.ba_graph(300, 3, 4)
+    k, eps, delta = 5, 0.2, 0.1
+    rc, picks, res, mlog = oracle.progressive(g, k, 8, eps, delta, 2, 0, 1000, 2**22, with_m_log=True,
+                                              method=oracle.METHOD_HEDGE_P)
+    assert rc == 0
+    off, nodes = oracle.sample_paths(g, 2, 0, 0, res.m_final)
+    p2, cov = oracle.greedy_cover(g.n, off, nodes, k)
+    assert np.array_equal(picks, p2) and res.coverage == cov[-1]
+    o = oracle.hedge_bound(res.m_final, int(cov[-1]), g.n, k, eps, delta / 2**res.iterations)
+    assert o.certified and res.eta == o.eta and res.amcera == 0
+    if res.iterations > 1:
+        prev = mlog[-2]
+        off, nodes = oracle.sample_paths(g, 2, 0, 0, prev)
+        _, cov = oracle.greedy_cover(g.n, off, nodes, k)
+        assert not oracle.hedge_bound(prev, int(cov[-1]), g.n, k, eps, delta / 2**(res.iterations - 1)).certified

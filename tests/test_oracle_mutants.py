@@ -59,6 +59,9 @@ MUTANTS = {
     "bidir_walk_wrong_side": ("            cur = walk_step(B, g->row_ptr, g->col_idx, cur, B->level[cur] - 1, &st);",
                               "            cur = walk_step(F, g->row_ptr, g->col_idx, cur, B->level[cur] - 1, &st);",
                               "tests/test_oracle_bidir.py"),
+    "hedge_one_sided": ("    const double eta = sqrt((log(2.0) + orc_log_sets(n, k) + log(1.0 / delta_i)) / (2.0 * (double)m));",
+                        "    const double eta = sqrt((orc_log_sets(n, k) + log(1.0 / delta_i)) / (2.0 * (double)m));",
+                        "tests/test_oracle_bound.py"),
     "counts_no_clamp": ("            b->sigma[b->visited[q]] = x ? x : 1;", "            b->sigma[b->visited[q]] = x;",
                         "tests/test_oracle_sampler.py"),
     "schedule_root_term": ("const double inv_y = (sqrt(2.0 * L) + sqrt(2.0 * L + 4.0 * L * T / 3.0)) / (2.0 * T);",
