@@ -11,7 +11,10 @@
  *     it alive until the call returns.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     Every entry point enqueues its work on `stream` and synchronises
- *     `stream` before returning, so outputs are ready on return.
+ *     `stream` before returning, so outputs are ready on return -- except
+ *     the stream-ordered calls (centra_sample_paths_append, centra_extend),
+ *     which only enqueue: their outputs are ready when `stream` reaches
+ *     them, and their device-side errors are reported by centra_check.
  *   - Return codes: CENTRA_OK (0) on success, CENTRA_NOT_CERTIFIED (1) from
  *     centra_progressive when the sample cap is reached, negative on error.
  *     The text of the last error is available from centra_last_error().  No
@@ -38,7 +41,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 9u
+#define CENTRA_ABI_VERSION 10u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -221,6 +224,107 @@ CENTRA_API int centra_mcera(centra_ctx *ctx, uint32_t n, uint64_t m, const uint6
                  const uint32_t *he_nodes, uint64_t seed, uint32_t instance, uint32_t t, uint32_t k,
                  int64_t *topk_sum, uint64_t *deg_topk_sum, uint32_t *b_max, int32_t *R_out,
                  void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Stream-ordered calls.  They read nothing back to the host: the sizes
+ * they need come from the caller (capacities), the sizes they produce stay
+ * in device memory, and errors found on the device are raised into the
+ * context's error word for centra_check.  A call may still wait for the
+ * device when it has to grow one of the context's workspaces (allocation);
+ * centra_reserve grows them ahead so that the calls after it only enqueue.
+ * Calls on one context must be issued on one stream (or ordered by the
+ * caller), as they share the context's workspaces. */
+
+/* sampleHEs into a growing hyperedge store (Algorithm 1 sampling step; the
+ * hyperedge space and the draws of centra_sample_paths, same results).
+ * Samples [first_sample, first_sample + count) of (seed, instance) are
+ * appended to the store after the entries already in it:
+ *   he_off     device u64[count+1]: the store's offsets from the first new
+ *              sample on (the caller passes store_off + first index);
+ *              he_off[0] must hold the store's current size (entries) when
+ *              the stream reaches the call (0 for an empty store); he_off[i]
+ *              for i >= 1 receives the offset after new sample i-1.
+ *   he_nodes   device u32[he_cap]: the whole store.
+ *   he_total   device u64[1] (may be NULL): receives the store's new size,
+ *              he_off[0] + entries of the new samples.
+ * If the new size exceeds he_cap the new samples are stored as empty
+ * hyperedges (he_off[i] = he_off[0]: the store stays consistent), *he_total
+ * still receives the size they need, and centra_check reports
+ * CENTRA_ENOSPC; the caller then grows the store and draws them again.
+ * Not counted in centra_sampler_stats.  The staging area it uses holds
+ * he_cap entries.
+ * Errors (returned): CENTRA_EINVAL (NULL ctx, graph, he_off, or he_nodes
+ * with he_cap > 0), CENTRA_ENOMEM, CENTRA_EHIP. */
+CENTRA_API int centra_sample_paths_append(centra_ctx *ctx, const centra_graph *g, uint64_t seed, uint32_t instance,
+                               uint64_t first_sample, uint32_t count, uint64_t *he_off, uint32_t *he_nodes,
+                               uint64_t he_cap, uint64_t *he_total, void *stream);
+
+/* One iteration's greedy and AMCERA steps on a sample that grows between
+ * calls (Algorithm 1: greedyCover on the sample, then the AMCERA and the
+ * wimpy-variance ingredients of Sec. 4.1), stream-ordered and incremental:
+ * the context keeps the incidence of the store and the AMCERA counts, and
+ * a call adds only the samples after m_prev.  Results equal those of
+ * centra_greedy_cover and centra_mcera on samples [0, m). */
+typedef struct {
+    uint32_t n;                 /* nodes; every node id < n */
+    uint32_t k;                 /* greedy rounds and top-k size, >= 1 */
+    uint64_t m_prev;            /* samples [0, m_prev) of the store are unchanged since
+                                   the previous centra_extend on this context (0: none
+                                   are; the state is rebuilt) */
+    uint64_t m;                 /* samples in the store now, 0 < m < 2^31, m >= m_prev */
+    const uint64_t *he_off;     /* device u64[m+1]: the store's offsets, he_off[0] = 0,
+                                   non-decreasing */
+    const uint32_t *he_nodes;   /* device u32[he_cap]: the store's node ids */
+    uint64_t he_cap;            /* entries he_nodes holds; he_off[m] must not exceed it
+                                   (else the incidence is left empty and centra_check
+                                   reports CENTRA_ENOSPC) */
+    /* greedyCover outputs (device, as centra_greedy_cover); all NULL: skipped */
+    uint32_t *picks;            /* u32[k] */
+    uint64_t *cov_cum;          /* u64[k] */
+    uint32_t *n_picked;         /* u32[1] */
+    /* AMCERA (as centra_mcera); t = 0: skipped */
+    uint32_t t;                 /* trials, <= 1024 */
+    uint32_t instance;
+    uint64_t seed;
+    int64_t *topk_sum;          /* device i64[t] */
+    uint64_t *deg_topk_sum;     /* device u64[1] */
+    uint32_t *b_max;            /* device u32[1]: max |h_i| over samples [0, m) */
+    int32_t *R_out;             /* optional device i32[n*t] */
+} centra_extend_args;
+
+/* Runs the steps of *a on `stream` without synchronising it.  State kept
+ * from the previous call is reused when this call names the same store
+ * (he_off, he_nodes, he_cap and n equal), m_prev covers what the state
+ * holds, and, for the AMCERA, (seed, instance, t) are unchanged; otherwise
+ * it is rebuilt from sample 0 (same results, more work).  Any other call
+ * on the context that builds an incidence or AMCERA counts
+ * (centra_greedy_cover, centra_mcera, centra_progressive) ends that state.
+ * Errors (returned): CENTRA_EINVAL (NULL ctx or a, n == 0, k == 0, m == 0,
+ * m < m_prev, NULL store pointers, greedy outputs partly NULL, t > 1024,
+ * NULL AMCERA outputs with t > 0), CENTRA_ENOTSUP (m >= 2^31),
+ * CENTRA_ENOMEM, CENTRA_EHIP.  Device-side: node ids >= n and decreasing
+ * offsets (CENTRA_EINVAL), he_off[m] > he_cap (CENTRA_ENOSPC), reported
+ * by centra_check. */
+CENTRA_API int centra_extend(centra_ctx *ctx, const centra_extend_args *a, void *stream);
+
+/* Grows the context's workspaces for stream-ordered calls up to the given
+ * sizes, so that those calls only enqueue: sampling batches of up to
+ * `batch` samples of graph g (NULL: no sampling) into a store of he_cap
+ * entries, and centra_extend on n nodes, up to m_max samples, k picks, t
+ * trials and 16 incidence segments (a longer run of extensions, or a
+ * rebuild after 64 segments, may grow a workspace again).  Synchronises
+ * `stream`.
+ * Errors: CENTRA_EINVAL (NULL ctx, n == 0, g's node count != n,
+ * t > 1024), CENTRA_ENOMEM, CENTRA_EHIP. */
+CENTRA_API int centra_reserve(centra_ctx *ctx, const centra_graph *g, uint32_t n, uint32_t batch, uint64_t m_max,
+                   uint64_t he_cap, uint32_t k, uint32_t t, void *stream);
+
+/* Waits for `stream` and reports the errors that kernels of this context
+ * raised since the last check (the stream-ordered calls' device-side
+ * errors), clearing them: CENTRA_OK if none, else CENTRA_ENOSPC (only a
+ * store capacity was exceeded), CENTRA_EINVAL (malformed input) or
+ * CENTRA_EHIP, with the text in centra_last_error. */
+CENTRA_API int centra_check(centra_ctx *ctx, void *stream);
 
 /* Work and time of the sampling kernel, accumulated over every sampling
  * launch of the context since the last reset: centra_sample_paths and the

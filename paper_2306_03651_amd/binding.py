@@ -108,6 +108,14 @@ class EngineStats(_c.Structure):
                 ("tuned_block", _c.c_uint32)]
 
 
+class ExtendArgs(_c.Structure):
+    _fields_ = [("n", _c.c_uint32), ("k", _c.c_uint32), ("m_prev", _c.c_uint64), ("m", _c.c_uint64),
+                ("he_off", _vp), ("he_nodes", _vp), ("he_cap", _c.c_uint64),
+                ("picks", _vp), ("cov_cum", _vp), ("n_picked", _vp),
+                ("t", _c.c_uint32), ("instance", _c.c_uint32), ("seed", _c.c_uint64),
+                ("topk_sum", _vp), ("deg_topk_sum", _vp), ("b_max", _vp), ("R_out", _vp)]
+
+
 CENTRA_ENGINE_NO_GRAPHS = 1
 CENTRA_ENGINE_NO_TUNE = 2
 
@@ -129,6 +137,12 @@ SIGNATURES = {
     "centra_greedy_cover_noalloc": (_c.c_int, [_c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint32, _vp, _vp, _vp, _vp]),
     "centra_mcera": (_c.c_int, [_vp, _c.c_uint32, _c.c_uint64, _vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint32,
                                 _c.c_uint32, _vp, _vp, _vp, _vp, _vp]),
+    "centra_sample_paths_append": (_c.c_int, [_vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _vp,
+                                              _vp, _c.c_uint64, _vp, _vp]),
+    "centra_extend": (_c.c_int, [_vp, _c.POINTER(ExtendArgs), _vp]),
+    "centra_reserve": (_c.c_int, [_vp, _vp, _c.c_uint32, _c.c_uint32, _c.c_uint64, _c.c_uint64, _c.c_uint32,
+                                  _c.c_uint32, _vp]),
+    "centra_check": (_c.c_int, [_vp, _vp]),
     "centra_sampler_stats_get": (_c.c_int, [_vp, _c.POINTER(SamplerStats), _c.c_int]),
     "centra_triangle_count": (_c.c_int, [_vp, _vp, _c.POINTER(_c.c_uint64), _vp]),
     "centra_sample_triangles": (_c.c_int, [_vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _vp, _vp,
@@ -301,6 +315,44 @@ def centra_mcera(ctx, n: int, he_off, he_nodes, seed: int, instance: int, t: int
     return _check(lib().centra_mcera(ctx, n, m, _ptr(he_off), _ptr(he_nodes), seed, instance, t, k,
                                      _ptr(topk_sum), _ptr(deg_topk), _ptr(b_max), _ptr(R_out), _stream(stream)),
                   ctx)
+
+
+def centra_sample_paths_append(ctx, g, seed: int, instance: int, first_sample: int, count: int, he_off, he_nodes,
+                               he_cap: int | None = None, he_total=None, stream=None) -> int:
+    """Stream-ordered: he_off is the store's offset array from the first new
+    sample on (a slice store_off[m_before:]); nothing is synchronised."""
+    import torch
+    _dtype_check(he_off, torch.int64, "he_off")
+    _dtype_check(he_nodes, torch.int32, "he_nodes")
+    if he_cap is None:
+        he_cap = he_nodes.numel() if he_nodes is not None else 0
+    return _check(lib().centra_sample_paths_append(ctx, g, seed, instance, first_sample, count, _ptr(he_off),
+                                                   _ptr(he_nodes), he_cap, _ptr(he_total), _stream(stream)), ctx)
+
+
+def centra_extend(ctx, n: int, k: int, m_prev: int, m: int, he_off, he_nodes, he_cap: int | None = None,
+                  picks=None, cov_cum=None, n_picked=None, t: int = 0, seed: int = 0, instance: int = 0,
+                  topk_sum=None, deg_topk=None, b_max=None, R_out=None, stream=None) -> int:
+    """Stream-ordered greedy + AMCERA on samples [0, m) of a growing store."""
+    if he_cap is None:
+        he_cap = he_nodes.numel() if he_nodes is not None else 0
+    a = ExtendArgs(n=n, k=k, m_prev=m_prev, m=m, he_off=_ptr(he_off), he_nodes=_ptr(he_nodes), he_cap=he_cap,
+                   picks=_ptr(picks), cov_cum=_ptr(cov_cum), n_picked=_ptr(n_picked), t=t, instance=instance,
+                   seed=seed, topk_sum=_ptr(topk_sum), deg_topk_sum=_ptr(deg_topk), b_max=_ptr(b_max),
+                   R_out=_ptr(R_out))
+    return _check(lib().centra_extend(ctx, ctypes.byref(a), _stream(stream)), ctx)
+
+
+def centra_reserve(ctx, g, n: int, batch: int, m_max: int, he_cap: int, k: int, t: int, stream=None) -> int:
+    return _check(lib().centra_reserve(ctx, g, n, batch, m_max, he_cap, k, t, _stream(stream)), ctx)
+
+
+def centra_check(ctx, stream=None) -> int:
+    """Returns CENTRA_OK or CENTRA_ENOSPC; raises on other device-side errors."""
+    rc = lib().centra_check(ctx, _stream(stream))
+    if rc != CENTRA_ENOSPC:
+        _check(rc, ctx)
+    return rc
 
 
 def centra_sampler_stats_get(ctx, reset: bool = False) -> SamplerStats:

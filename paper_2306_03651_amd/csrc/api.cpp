@@ -189,7 +189,7 @@ void centra_destroy(centra_ctx* ctx) {
                     &ctx->stage_len, &ctx->work_ctr, &ctx->scan_tmp, &ctx->deg, &ctx->inc_off,
                     &ctx->inc_cursor, &ctx->inc, &ctx->inc_node, &ctx->gain, &ctx->covered, &ctx->best,
                     &ctx->newcov, &ctx->words, &ctx->P, &ctx->Rtm, &ctx->topk_tmp, &ctx->misc,
-                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len, &ctx->seg_deg, &ctx->multi_tab, &ctx->sel_rows, &ctx->bi_rec_f, &ctx->bi_rec_b, &ctx->bi_q_f,
+                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len, &ctx->seg_deg, &ctx->multi_tab, &ctx->sel_rows, &ctx->ext_bmax, &ctx->bi_rec_f, &ctx->bi_rec_b, &ctx->bi_q_f,
                     &ctx->bi_q_b};
   for (DevBuf* b : bufs) release(ctx, *b);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);
@@ -398,9 +398,110 @@ int centra_mcera(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off
   if ((rc = build_incidence(ctx, n, 0, m, he_off, he_nodes, s))) return rc;
   if ((rc = check_flags(ctx, s, "mcera"))) return rc;
   if ((rc = rade_words(ctx, seed, instance, 0, m, t, s))) return rc;
-  if ((rc = mcera_on_incidence(ctx, n, m, he_off, t, k, topk_sum, deg_topk_sum, b_max, R_out, s))) return rc;
+  if ((rc = mcera_on_incidence(ctx, n, m, ctx->inc_m0, he_off, t, k, topk_sum, deg_topk_sum, b_max, R_out, s))) return rc;
   CENTRA_HIP(ctx, hipStreamSynchronize(s));
   return CENTRA_OK;
+}
+
+int centra_sample_paths_append(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance,
+                               uint64_t first_sample, uint32_t count, uint64_t* he_off, uint32_t* he_nodes,
+                               uint64_t he_cap, uint64_t* he_total, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (!g) return fail(ctx, CENTRA_EINVAL, "sample_paths_append: graph is NULL");
+  if (!he_off) return fail(ctx, CENTRA_EINVAL, "sample_paths_append: he_off is NULL");
+  if (!he_nodes && he_cap) return fail(ctx, CENTRA_EINVAL, "sample_paths_append: he_nodes is NULL");
+  DeviceGuard guard(ctx->device);
+  return sample_append(ctx, g, seed, instance, first_sample, count, he_off, he_nodes, he_cap, he_total,
+                       as_stream(stream));
+}
+
+int centra_extend(centra_ctx* ctx, const centra_extend_args* a, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (!a) return fail(ctx, CENTRA_EINVAL, "extend: args are NULL");
+  if (a->n == 0 || a->k == 0 || a->m == 0) return fail(ctx, CENTRA_EINVAL, "extend: n, k and m must be positive");
+  if (a->m < a->m_prev) return fail(ctx, CENTRA_EINVAL, "extend: m < m_prev");
+  if (a->m >= (1ull << 31)) return fail(ctx, CENTRA_ENOTSUP, "extend: m >= 2^31");
+  if (!a->he_off || (!a->he_nodes && a->he_cap)) return fail(ctx, CENTRA_EINVAL, "extend: NULL store pointer");
+  const int outs = (a->picks != nullptr) + (a->cov_cum != nullptr) + (a->n_picked != nullptr);
+  if (outs != 0 && outs != 3) return fail(ctx, CENTRA_EINVAL, "extend: greedy outputs partly NULL");
+  if (a->t > 1024) return fail(ctx, CENTRA_EINVAL, "extend: t > 1024");
+  if (a->t && (!a->topk_sum || !a->deg_topk_sum || !a->b_max))
+    return fail(ctx, CENTRA_EINVAL, "extend: NULL AMCERA output");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = as_stream(stream);
+  const uint32_t n = a->n;
+  const uint64_t m = a->m;
+  const bool same = ctx->ext_off == a->he_off && ctx->ext_nodes == a->he_nodes && ctx->ext_cap == a->he_cap &&
+                    ctx->ext_n == n;
+  if (!same) ctx->mc_ok = false;
+  // AMCERA counts of [0, mc_m) stay usable if those samples are unchanged
+  bool keep_p = a->t && same && ctx->mc_ok && a->m_prev > 0 && ctx->mc_m <= a->m_prev && ctx->mc_m <= m &&
+                ctx->mc_seed == a->seed && ctx->mc_instance == a->instance && ctx->mc_t == a->t;
+  int rc;
+  // incidence of samples [0, m): the segments already built, plus one for
+  // the new samples
+  if (a->m_prev > 0 && same && ctx->ext_inc && ctx->inc_m1 <= a->m_prev) {
+    if (m > ctx->inc_m1 &&
+        (rc = build_incidence(ctx, n, ctx->inc_m1, m, a->he_off, a->he_nodes, s, a->he_cap)))
+      return rc;
+  } else if ((rc = build_incidence(ctx, n, 0, m, a->he_off, a->he_nodes, s, a->he_cap))) {
+    return rc;
+  }
+  ctx->ext_inc = true;
+  ctx->ext_off = a->he_off;
+  ctx->ext_nodes = a->he_nodes;
+  ctx->ext_cap = a->he_cap;
+  ctx->ext_n = n;
+  if (a->picks &&
+      (rc = greedy_on_incidence(ctx, n, m, a->he_off, a->he_nodes, a->k, a->picks, a->cov_cum, a->n_picked, s)))
+    return rc;
+  if (a->t) {
+    // the counts extend from mc_m only if it starts a segment (the entries
+    // of samples [mc_m, m) are then contiguous in the incidence)
+    if (keep_p && ctx->mc_m != m) {
+      bool boundary = false;
+      for (uint32_t g = 0; g < ctx->inc_nseg; ++g) boundary = boundary || ctx->inc_seg_m0[g] == ctx->mc_m;
+      keep_p = boundary;
+    }
+    const uint64_t from = keep_p ? ctx->mc_m : 0;
+    if ((rc = mcera_reserve(ctx, n, m, a->t, s))) return rc;
+    if ((rc = rade_words(ctx, a->seed, a->instance, from, m, a->t, s))) return rc;
+    uint32_t* bm = static_cast<uint32_t*>(ctx->ext_bmax.ptr);
+    if ((rc = mcera_on_incidence(ctx, n, m, from, a->he_off, a->t, a->k, a->topk_sum, a->deg_topk_sum, bm, a->R_out,
+                                 s)))
+      return rc;
+    CENTRA_HIP(ctx, hipMemcpyAsync(a->b_max, bm, 4, hipMemcpyDeviceToDevice, s));
+    ctx->mc_ok = true;
+    ctx->mc_m = m;
+    ctx->mc_seed = a->seed;
+    ctx->mc_instance = a->instance;
+    ctx->mc_t = a->t;
+  }
+  CENTRA_HIP(ctx, hipGetLastError());
+  return CENTRA_OK;
+}
+
+int centra_reserve(centra_ctx* ctx, const centra_graph* g, uint32_t n, uint32_t batch, uint64_t m_max, uint64_t he_cap,
+                   uint32_t k, uint32_t t, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  if (n == 0) return fail(ctx, CENTRA_EINVAL, "reserve: n == 0");
+  if (g && g->n != n) return fail(ctx, CENTRA_EINVAL, "reserve: the graph's node count differs from n");
+  if (t > 1024) return fail(ctx, CENTRA_EINVAL, "reserve: t > 1024");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = as_stream(stream);
+  int rc;
+  if (g && batch && (rc = sample_reserve(ctx, g, batch, he_cap, s))) return rc;
+  if ((rc = incidence_reserve(ctx, n, he_cap, 16, s))) return rc;
+  if (k && (rc = greedy_reserve(ctx, n, m_max, k, s))) return rc;
+  if (t && (rc = mcera_reserve(ctx, n, m_max, t, s))) return rc;
+  CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  return CENTRA_OK;
+}
+
+int centra_check(centra_ctx* ctx, void* stream) {
+  if (!ctx) return CENTRA_EINVAL;
+  DeviceGuard guard(ctx->device);
+  return check_flags(ctx, as_stream(stream), "check");
 }
 
 int centra_sampler_stats_get(centra_ctx* ctx, centra_sampler_stats* out, int reset) {
@@ -519,7 +620,7 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
     CENTRA_HIP(ctx, hipEventRecord(ev[2], s));
     if (!hedge) {   // HEDGE-P bounds the deviation without the AMCERA
       if ((rc = rade_words(ctx, p->seed, p->instance, m_prev, m_i, t, s))) return rc;
-      if ((rc = mcera_on_incidence(ctx, n, m_i, store_off, t, k, reinterpret_cast<int64_t*>(misc + o_tk),
+      if ((rc = mcera_on_incidence(ctx, n, m_i, ctx->inc_m0, store_off, t, k, reinterpret_cast<int64_t*>(misc + o_tk),
                                    reinterpret_cast<uint64_t*>(misc + o_dk), reinterpret_cast<uint32_t*>(misc + o_bm),
                                    nullptr, s)))
         return rc;

@@ -13,6 +13,8 @@ constexpr int kWave = 64;
 constexpr uint32_t kErrNodeRange = 1u;      // a hyperedge names a node >= n
 constexpr uint32_t kErrBacktrack = 2u;      // no predecessor found (impossible on valid input)
 constexpr uint32_t kErrGraph = 4u;          // malformed CSR
+constexpr uint32_t kErrCapacity = 8u;       // a hyperedge store exceeds its stated capacity
+constexpr uint32_t kErrOffsets = 16u;       // hyperedge offsets decrease
 
 // ---------------------------------------------------------------------------
 // Coherent accesses.  The per-BFS arrays are updated with device-scope

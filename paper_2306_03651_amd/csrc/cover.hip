@@ -94,19 +94,31 @@ __device__ __forceinline__ uint32_t agg_find(const AggTable& t, uint32_t v) {
 // workgroup's entries per node, one atomic per node reserves a range of
 // the node's row, pass 2 places the entries (the same grid-stride order in
 // both passes).  Nodes without a slot reserve per entry.
+// Entries go to [he_off[m0], he_off[m]) of inc; nothing is written unless
+// that range lies within the `limit` entries inc holds, and no write lands
+// outside it whatever the offsets (decreasing offsets raise kErrOffsets).
 __global__ void k_scatter_inc_agg(const uint64_t* he_off, const uint32_t* he_nodes, uint64_t m0, uint64_t m, uint32_t n,
-                                  uint64_t* cursor, uint32_t* inc, uint32_t* inc_node) {
+                                  uint64_t limit, uint64_t* cursor, uint32_t* inc, uint32_t* inc_node,
+                                  uint32_t* flags) {
   __shared__ AggTable tab;
   __shared__ uint64_t base[kAggSize];
+  const uint64_t I0 = he_off[m0], I1 = he_off[m];
+  if (I1 > limit || I0 > I1) return;   // uniform: k_count_deg_agg raised the error
   agg_init(tab);
   __syncthreads();
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   const uint64_t s0 = m0 + blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
-  for (uint64_t s = s0; s < m; s += stride)
-    for (uint64_t x = he_off[s]; x < he_off[s + 1]; ++x) {
+  for (uint64_t s = s0; s < m; s += stride) {
+    const uint64_t b = he_off[s], e = he_off[s + 1];
+    if (b > e) {
+      atomicOr(flags, kErrOffsets);
+      continue;
+    }
+    for (uint64_t x = b < I0 ? I0 : b; x < (e < I1 ? e : I1); ++x) {
       const uint32_t u = he_nodes[x];
       if (u < n) (void)agg_add(tab, u);
     }
+  }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < kAggSize; i += blockDim.x) {
     if (tab.key[i] != kUnseen)
@@ -115,24 +127,40 @@ __global__ void k_scatter_inc_agg(const uint64_t* he_off, const uint32_t* he_nod
     tab.cnt[i] = 0;
   }
   __syncthreads();
-  for (uint64_t s = s0; s < m; s += stride)
-    for (uint64_t x = he_off[s]; x < he_off[s + 1]; ++x) {
+  for (uint64_t s = s0; s < m; s += stride) {
+    const uint64_t b = he_off[s], e = he_off[s + 1];
+    if (b > e) continue;
+    for (uint64_t x = b < I0 ? I0 : b; x < (e < I1 ? e : I1); ++x) {
       const uint32_t u = he_nodes[x];
       if (u >= n) continue;
       const uint32_t slot = agg_find(tab, u);
       const uint64_t p = slot != kUnseen
                              ? base[slot] + atomicAdd(&tab.cnt[slot], 1u)
                              : atomicAdd(reinterpret_cast<unsigned long long*>(&cursor[u]), 1ull);
+      if (p >= I1) {   // only with decreasing offsets (flagged above)
+        atomicOr(flags, kErrOffsets);
+        continue;
+      }
       inc[p] = static_cast<uint32_t>(s);
       inc_node[p] = u;
     }
+  }
 }
 
-__global__ void k_count_deg_agg(const uint32_t* he_nodes, uint64_t I, uint32_t n, uint32_t* deg, uint32_t* flags) {
+// deg[u] += entries of u among he_nodes[he_off[m0], he_off[m1]) (the entry
+// range is read on the device; a range beyond `limit` entries counts
+// nothing and raises kErrCapacity).
+__global__ void k_count_deg_agg(const uint64_t* he_off, uint64_t m0, uint64_t m1, const uint32_t* he_nodes, uint32_t n,
+                                uint64_t limit, uint32_t* deg, uint32_t* flags) {
   __shared__ AggTable tab;
+  const uint64_t I0 = he_off[m0], I1 = he_off[m1];
+  if (I1 > limit || I0 > I1) {   // uniform over the grid
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flags, I0 > I1 ? kErrOffsets : kErrCapacity);
+    return;
+  }
   agg_init(tab);
   __syncthreads();
-  for (uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; e < I; e += uint64_t(gridDim.x) * blockDim.x) {
+  for (uint64_t e = I0 + blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; e < I1; e += uint64_t(gridDim.x) * blockDim.x) {
     const uint32_t u = he_nodes[e];
     if (u >= n) {
       atomicOr(flags, kErrNodeRange);
@@ -149,44 +177,56 @@ __global__ void k_add_u32_to(const uint32_t* a, uint32_t n, uint32_t* acc) {
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) acc[u] += a[u];
 }
 
-__global__ void k_offset_u64(uint64_t* a, uint64_t n, uint64_t add) {
+// a[i] += *add for i < n (the addend read on the device).
+__global__ void k_offset_u64(uint64_t* a, uint64_t n, const uint64_t* add) {
+  const uint64_t x = *add;
+  if (x == 0) return;
   for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
-    a[i] += add;
+    a[i] += x;
 }
 
-// Launches the build of one incidence segment: samples [m0, m1) with
-// entries [I0, I1) of he_nodes; its offsets go to `off` (absolute into inc),
-// its degrees to sdeg, and deg accumulates them (cleared first when
-// `first_segment`).  Launches only.
-void incidence_segment(uint32_t n, uint64_t m0, uint64_t m1, uint64_t I0, uint64_t I1, const uint64_t* he_off,
-                              const uint32_t* he_nodes, bool first_segment, uint32_t* deg, uint32_t* sdeg, uint64_t* off,
-                              uint64_t* cur, uint32_t* inc, uint32_t* inc_node, uint64_t* scan_tiles, uint32_t* flags,
-                              hipStream_t s) {
+// Launches the build of one incidence segment: samples [m0, m1), whose
+// entries [he_off[m0], he_off[m1]) of he_nodes are located on the device
+// (span_cap bounds their number, for the launch shapes only; inc and
+// inc_node hold `limit` entries, and a segment reaching beyond them is
+// left empty with kErrCapacity raised); its offsets go to `off` (absolute
+// into inc), its degrees to sdeg, and deg accumulates them (cleared first
+// when `first_segment`).  Launches only.
+void incidence_segment(uint32_t n, uint64_t m0, uint64_t m1, uint64_t span_cap, uint64_t limit, const uint64_t* he_off,
+                       const uint32_t* he_nodes, bool first_segment, uint32_t* deg, uint32_t* sdeg, uint64_t* off,
+                       uint64_t* cur, uint32_t* inc, uint32_t* inc_node, uint64_t* scan_tiles, uint32_t* flags,
+                       hipStream_t s) {
   if (first_segment) fill_u32(deg, 0, n, s);
   fill_u32(sdeg, 0, n, s);
-  if (I1 > I0)
-    hipLaunchKernelGGL(k_count_deg_agg, dim3(grid_for(I1 - I0, 256, 2048)), dim3(256), 0, s, he_nodes + I0, I1 - I0, n,
-                       sdeg, flags);
+  if (m1 > m0 && span_cap)
+    hipLaunchKernelGGL(k_count_deg_agg, dim3(grid_for(span_cap, 256, 2048)), dim3(256), 0, s, he_off, m0, m1, he_nodes, n,
+                       limit, sdeg, flags);
   excl_scan_u32_to_u64_ws(sdeg, off, n, scan_tiles, s);
-  if (I0) hipLaunchKernelGGL(k_offset_u64, dim3(grid_for(uint64_t(n) + 1, 256)), dim3(256), 0, s, off, uint64_t(n) + 1, I0);
+  if (m0) hipLaunchKernelGGL(k_offset_u64, dim3(grid_for(uint64_t(n) + 1, 256)), dim3(256), 0, s, off, uint64_t(n) + 1,
+                             he_off + m0);
   hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, off, cur, size_t(n));
   if (m1 > m0)
     hipLaunchKernelGGL(k_scatter_inc_agg, dim3(grid_for(m1 - m0, 256, 2048)), dim3(256), 0, s, he_off, he_nodes, m0, m1,
-                       n, cur, inc, inc_node);
+                       n, limit, cur, inc, inc_node, flags);
   hipLaunchKernelGGL(k_add_u32_to, dim3(grid_for(n, 256)), dim3(256), 0, s, sdeg, n, deg);
 }
 
 int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const uint64_t* he_off,
-                    const uint32_t* he_nodes, hipStream_t s) {
+                    const uint32_t* he_nodes, hipStream_t s, uint64_t entry_cap) {
+  ctx->ext_inc = false;   // the extend calls' state is valid only after their own builds
   if (m0 == 0 || ctx->inc_nseg >= kMaxSegments) {   // a new sample, or too many segments: start over
     ctx->inc_nseg = 0;
     m0 = 0;
   }
-  uint64_t ends[2] = {0, 0};
-  CENTRA_HIP(ctx, hipMemcpyAsync(&ends[0], he_off + m0, 8, hipMemcpyDeviceToHost, s));
-  CENTRA_HIP(ctx, hipMemcpyAsync(&ends[1], he_off + m1, 8, hipMemcpyDeviceToHost, s));
-  CENTRA_HIP(ctx, hipStreamSynchronize(s));
-  const uint64_t I0 = ends[0], I1 = ends[1];
+  uint64_t I0 = 0, I1 = entry_cap;
+  if (entry_cap == ~0ull) {   // sizes read from the device (one synchronisation)
+    uint64_t ends[2] = {0, 0};
+    CENTRA_HIP(ctx, hipMemcpyAsync(&ends[0], he_off + m0, 8, hipMemcpyDeviceToHost, s));
+    CENTRA_HIP(ctx, hipMemcpyAsync(&ends[1], he_off + m1, 8, hipMemcpyDeviceToHost, s));
+    CENTRA_HIP(ctx, hipStreamSynchronize(s));
+    I0 = ends[0];
+    I1 = ends[1];
+  }
   const uint32_t g = ctx->inc_nseg;
   int rc;
   if ((rc = ensure(ctx, ctx->deg, size_t(n) * 4, g > 0, s))) return rc;
@@ -196,7 +236,7 @@ int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const
   if ((rc = ensure(ctx, ctx->inc, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->inc_node, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->scan_tmp, scan_tile_words(n) * 8, false, s))) return rc;
-  incidence_segment(n, m0, m1, I0, I1, he_off, he_nodes, g == 0, static_cast<uint32_t*>(ctx->deg.ptr),
+  incidence_segment(n, m0, m1, I1 - I0, I1, he_off, he_nodes, g == 0, static_cast<uint32_t*>(ctx->deg.ptr),
                     static_cast<uint32_t*>(ctx->seg_deg.ptr),
                     static_cast<uint64_t*>(ctx->inc_off.ptr) + size_t(g) * (size_t(n) + 1),
                     static_cast<uint64_t*>(ctx->inc_cursor.ptr), static_cast<uint32_t*>(ctx->inc.ptr),
@@ -204,9 +244,23 @@ int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->inc_nseg = g + 1;
   ctx->inc_m0 = m0;
-  ctx->inc_I0 = I0;
-  ctx->inc_I1 = I1;
+  ctx->inc_span_cap = I1 - I0;
+  ctx->inc_m1 = m1;
+  ctx->inc_limit = I1;
+  if (ctx->inc_seg_m0.size() < size_t(g) + 1) ctx->inc_seg_m0.resize(size_t(g) + 1);
+  ctx->inc_seg_m0[g] = m0;
   return CENTRA_OK;
+}
+
+int incidence_reserve(centra_ctx* ctx, uint32_t n, uint64_t entries, uint32_t segments, hipStream_t s) {
+  int rc;
+  if ((rc = ensure(ctx, ctx->deg, size_t(n) * 4, true, s))) return rc;
+  if ((rc = ensure(ctx, ctx->seg_deg, size_t(n) * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->inc_off, (size_t(segments) + 1) * (size_t(n) + 1) * 8, true, s))) return rc;
+  if ((rc = ensure(ctx, ctx->inc_cursor, size_t(n) * 8, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->inc, (entries ? entries : 1) * 4, true, s))) return rc;
+  if ((rc = ensure(ctx, ctx->inc_node, (entries ? entries : 1) * 4, true, s))) return rc;
+  return ensure(ctx, ctx->scan_tmp, scan_tile_words(n) * 8, false, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -663,6 +717,14 @@ static void greedy_kernels(uint32_t n, uint64_t m, const uint64_t* he_off, const
   hipLaunchKernelGGL(k_greedy_finish, dim3(1), dim3(64), 0, s, best, newcov, k, picks, cov_cum, n_picked);
 }
 
+int greedy_reserve(centra_ctx* ctx, uint32_t n, uint64_t m, uint32_t k, hipStream_t s) {
+  int rc;
+  if ((rc = ensure(ctx, ctx->gain, size_t(n) * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->covered, ((m + 31) / 32 + 1) * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->best, (size_t(k) + kArgGrid) * 8, false, s))) return rc;
+  return ensure(ctx, ctx->newcov, size_t(k) * 8, false, s);
+}
+
 int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, const uint32_t* he_nodes,
                         uint32_t k, uint32_t* picks, uint64_t* cov_cum, uint32_t* n_picked, hipStream_t s) {
   int rc;
@@ -764,7 +826,7 @@ int greedy_cover_static(uint32_t n, uint64_t m, const uint64_t* he_off, const ui
   // the array keeps the previous call's contents: the error word starts at 0
   // here, and every other region is written before it is read
   fill_u32(flags, 0, 1, s);
-  incidence_segment(n, 0, m, 0, I, he_off, he_nodes, true, deg, sdeg, off, cur, inc, inc_node, tiles, flags, s);
+  incidence_segment(n, 0, m, I, I, he_off, he_nodes, true, deg, sdeg, off, cur, inc, inc_node, tiles, flags, s);
   greedy_kernels(n, m, he_off, he_nodes, k, deg, off, 1, inc, gain, cov, best, newcov, picks, cov_cum, n_picked, s);
   if ((e = hipGetLastError()) != hipSuccess) {
     *err = std::string("greedy_cover_noalloc: launch failed: ") + hipGetErrorString(e);
@@ -778,6 +840,10 @@ int greedy_cover_static(uint32_t n, uint64_t m, const uint64_t* he_off, const ui
   }
   if (f & kErrNodeRange) {
     *err = "greedy_cover_noalloc: hyperedge node id out of range";
+    return CENTRA_EINVAL;
+  }
+  if (f) {
+    *err = "greedy_cover_noalloc: hyperedge offsets decrease";
     return CENTRA_EINVAL;
   }
   return CENTRA_OK;

@@ -313,7 +313,7 @@ static int build_level(centra_engine* e, EnginePool& p, uint32_t j, hipStream_t 
   if ((rc = ensure(ctx, p.deg[j], size_t(n) * 4, false, s))) return rc;
   if ((rc = ensure(ctx, p.R[j], size_t(n) * t * 4, false, s))) return rc;
   uint32_t* deg_cur = static_cast<uint32_t*>(p.deg_cur.ptr);
-  incidence_segment(n, m0, m1, I0, I1, off, static_cast<const uint32_t*>(p.nodes.ptr), j == 0, deg_cur,
+  incidence_segment(n, m0, m1, I1 - I0, I1, off, static_cast<const uint32_t*>(p.nodes.ptr), j == 0, deg_cur,
                     static_cast<uint32_t*>(p.sdeg.ptr), static_cast<uint64_t*>(p.seg_off.ptr) + size_t(j) * (n + 1),
                     static_cast<uint64_t*>(p.cursor.ptr), static_cast<uint32_t*>(p.inc.ptr),
                     static_cast<uint32_t*>(p.inc_node.ptr), static_cast<uint64_t*>(p.tiles.ptr), ctx->d_flags, s);
@@ -323,8 +323,8 @@ static int build_level(centra_engine* e, EnginePool& p, uint32_t j, hipStream_t 
   rade_words_launch(p.p.seed, p.p.instance, m0, m1, t, words, s);
   int32_t* P = static_cast<int32_t*>(p.P.ptr);
   if (j == 0) fill_u32(reinterpret_cast<uint32_t*>(P), 0, size_t(n) * t, s);
-  rade_count_launch(static_cast<const uint32_t*>(p.inc.ptr), static_cast<const uint32_t*>(p.inc_node.ptr), I0, I1,
-                    words, t, P, s);
+  rade_count_launch(static_cast<const uint32_t*>(p.inc.ptr), static_cast<const uint32_t*>(p.inc_node.ptr), off, m0, m1,
+                    I1 - I0, I1, words, t, P, s);
   rade_finish_launch(P, degj, n, t, static_cast<int32_t*>(p.R[j].ptr), s);
   uint32_t* bm = static_cast<uint32_t*>(p.bmax.ptr);
   if (j == 0)

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/centra.h"
 
@@ -45,7 +46,22 @@ struct centra_ctx {
   centra::DevBuf deg, inc_off, inc_cursor, inc, inc_node, gain, covered, best, newcov, seg_deg;
   uint32_t inc_nseg = 0;              // incidence segments held in inc_off / inc / inc_node
   uint64_t inc_m0 = 0;                // first sample of the newest segment (0: it holds every sample)
-  uint64_t inc_I0 = 0, inc_I1 = 0;    // entry range of the newest segment
+  uint64_t inc_m1 = 0;                // samples the incidence covers
+  uint64_t inc_span_cap = 0;          // bound on the newest segment's entries (launch shapes)
+  uint64_t inc_limit = 0;             // entries inc / inc_node are sized for
+  std::vector<uint64_t> inc_seg_m0;   // first sample of each segment
+  // State of centra_extend: the incidence is that of the store (ext_off,
+  // ext_nodes, ext_cap) over ext_n nodes while ext_inc; the AMCERA counts P,
+  // the words and ext_bmax cover samples [0, mc_m) of (mc_seed,
+  // mc_instance) with mc_t trials while mc_ok.  Any other build clears them.
+  bool ext_inc = false, mc_ok = false;
+  const uint64_t* ext_off = nullptr;
+  const uint32_t* ext_nodes = nullptr;
+  uint64_t ext_cap = 0;
+  uint32_t ext_n = 0;
+  uint64_t mc_m = 0, mc_seed = 0;
+  uint32_t mc_instance = 0, mc_t = 0;
+  centra::DevBuf ext_bmax;
   centra::DevBuf words, P, Rtm, topk_tmp, misc, sel_rows;
   // sample store of centra_progressive
   centra::DevBuf store_off, store_nodes;
@@ -136,6 +152,21 @@ int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint3
 // Graph checks (graph.hip).
 int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s);
 
+// Workspace growth ahead of the stream-ordered calls (each grows the
+// buffers its step would grow; keep-contents buffers keep them).
+int sample_reserve(centra_ctx* ctx, const centra_graph* g, uint32_t count, uint64_t stage_entries, hipStream_t s);
+int incidence_reserve(centra_ctx* ctx, uint32_t n, uint64_t entries, uint32_t segments, hipStream_t s);
+int greedy_reserve(centra_ctx* ctx, uint32_t n, uint64_t m, uint32_t k, hipStream_t s);
+int mcera_reserve(centra_ctx* ctx, uint32_t n, uint64_t m, uint32_t t, hipStream_t s);
+
+// Stream-ordered sampling into a growing store (sample_launch.hip): samples
+// [first, first+count) are appended after the he_off[0] entries already in
+// the store (read on the device); *he_total (device) receives the store's
+// new size; nodes are written only if it fits he_cap.  No synchronisation.
+int sample_append(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
+                  uint32_t count, uint64_t* he_off, uint32_t* he_nodes, uint64_t he_cap, uint64_t* he_total,
+                  hipStream_t s);
+
 // Sampling (sample.hip): samples [first, first+count) into the staging
 // area, then lays them out at `he_off`/`he_nodes` (offsets relative,
 // plus `base` added to every offset).  *total receives the node count.
@@ -168,8 +199,11 @@ int sample_multi_to_stage(centra_ctx* ctx, const MultiSampleItem* items, uint32_
 // sample: every earlier segment is dropped; so does reaching kMaxSegments,
 // and the new segment then holds samples [0, m1)).
 constexpr uint32_t kMaxSegments = 64;
+// entry_cap: a bound on the store's entries, which sizes the incidence
+// without reading the sample's size from the device (no synchronisation);
+// ~0 reads the exact size.
 int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const uint64_t* he_off,
-                    const uint32_t* he_nodes, hipStream_t s);
+                    const uint32_t* he_nodes, hipStream_t s, uint64_t entry_cap = ~0ull);
 int greedy_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off,
                         const uint32_t* he_nodes, uint32_t k, uint32_t* picks, uint64_t* cov_cum,
                         uint32_t* n_picked, hipStream_t s);
@@ -214,7 +248,7 @@ void greedy_multi_rounds(const GreedyDesc* d, uint32_t n_q, uint32_t max_n, uint
                          uint32_t rounds, hipStream_t s);
 void greedy_multi_finish(const GreedyDesc* d, uint32_t n_q, hipStream_t s);
 // Launch-only incidence build of one segment (cover.hip).
-void incidence_segment(uint32_t n, uint64_t m0, uint64_t m1, uint64_t I0, uint64_t I1, const uint64_t* he_off,
+void incidence_segment(uint32_t n, uint64_t m0, uint64_t m1, uint64_t span_cap, uint64_t limit, const uint64_t* he_off,
                        const uint32_t* he_nodes, bool first_segment, uint32_t* deg, uint32_t* sdeg, uint64_t* off,
                        uint64_t* cur, uint32_t* inc, uint32_t* inc_node, uint64_t* scan_tiles, uint32_t* flags,
                        hipStream_t s);
@@ -231,8 +265,8 @@ void select_topk_rows(const SelRow* rows, uint32_t n_rows, uint32_t max_n, void*
 // Launch-only AMCERA steps (mcera.hip).
 void rade_words_launch(uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1, uint32_t t, uint64_t* words,
                        hipStream_t s);
-void rade_count_launch(const uint32_t* inc, const uint32_t* inc_node, uint64_t I0, uint64_t I1, const uint64_t* words,
-                       uint32_t t, int32_t* P, hipStream_t s);
+void rade_count_launch(const uint32_t* inc, const uint32_t* inc_node, const uint64_t* he_off, uint64_t m0, uint64_t m1,
+                       uint64_t span_cap, uint64_t limit, const uint64_t* words, uint32_t t, int32_t* P, hipStream_t s);
 void rade_finish_launch(const int32_t* P, const uint32_t* deg, uint32_t n, uint32_t t, int32_t* Rtm, hipStream_t s);
 void bmax_launch(const uint64_t* he_off, uint64_t m0, uint64_t m1, uint32_t* b_max, hipStream_t s);
 
@@ -240,11 +274,12 @@ void bmax_launch(const uint64_t* he_off, uint64_t m0, uint64_t m1, uint32_t* b_m
 // (Wt words per sample), then the per-trial top-k sums on the incidence.
 int rade_words(centra_ctx* ctx, uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1,
                uint32_t t, hipStream_t s);
-// Counts of the newest incidence segment (samples [inc_m0, m)) are added
-// to those of the earlier ones, kept from the previous call unless the
-// segment starts at sample 0; b_max likewise takes the new samples' maximum
-// into its previous value.
-int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, uint32_t t,
+// Counts of samples [m0, m) are added to those of the earlier ones, kept
+// from the previous call unless m0 is 0; b_max likewise takes the new
+// samples' maximum into its previous value.
+// m0 must be a segment start of the incidence (normally the newest one's,
+// ctx->inc_m0) with P holding the counts of samples [0, m0).
+int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, uint64_t m0, const uint64_t* he_off, uint32_t t,
                        uint32_t k, int64_t* topk_sum, uint64_t* deg_topk, uint32_t* b_max,
                        int32_t* R_out, hipStream_t s);
 

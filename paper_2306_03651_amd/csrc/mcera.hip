@@ -58,6 +58,7 @@ static unsigned grid_for(uint64_t n, unsigned block, unsigned cap = 16384) {
 int rade_words(centra_ctx* ctx, uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1, uint32_t t,
                hipStream_t s) {
   const uint32_t Wt = (t + 63) / 64;
+  ctx->mc_ok = false;   // the extend calls' AMCERA state is valid only after their own updates
   int rc = ensure(ctx, ctx->words, size_t(s1) * Wt * 8, true, s);
   if (rc) return rc;
   if (s1 > s0)
@@ -81,12 +82,16 @@ constexpr uint32_t kSpan = 64 * 16;   // incidence entries per wave
 // row lengths; loads are 64 entries per step, coalesced for the incidence,
 // one 8-byte gather per entry for the word.
 __global__ __launch_bounds__(kCountBlock) void k_rade_count(const uint32_t* inc, const uint32_t* inc_node,
-                                                            uint64_t I, const uint64_t* words, uint32_t Wt,
+                                                            const uint64_t* he_off, uint64_t m0, uint64_t m1,
+                                                            uint64_t limit, const uint64_t* words, uint32_t Wt,
                                                             uint32_t t, int32_t* P) {
   const int lane = lane_id();
   const uint32_t g = blockIdx.y;
+  // the segment's entries [he_off[m0], he_off[m1]) of inc, read on the device
+  const uint64_t I0 = he_off[m0], I = he_off[m1];
+  if (I > limit || I0 > I) return;   // beyond the incidence (the build raised the error)
   const uint64_t wave = (blockIdx.x * uint64_t(kCountBlock) + threadIdx.x) / kWave;
-  const uint64_t e0 = wave * kSpan;
+  const uint64_t e0 = I0 + wave * kSpan;
   if (e0 >= I) return;
   const uint64_t e1 = e0 + kSpan < I ? e0 + kSpan : I;
   const uint32_t jt = 64 * g + lane;   // this lane's trial
@@ -344,14 +349,14 @@ void rade_words_launch(uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s
                        s0, s1, Wt, words);
 }
 
-void rade_count_launch(const uint32_t* inc, const uint32_t* inc_node, uint64_t I0, uint64_t I1, const uint64_t* words,
-                       uint32_t t, int32_t* P, hipStream_t s) {
+void rade_count_launch(const uint32_t* inc, const uint32_t* inc_node, const uint64_t* he_off, uint64_t m0, uint64_t m1,
+                       uint64_t span_cap, uint64_t limit, const uint64_t* words, uint32_t t, int32_t* P, hipStream_t s) {
   const uint32_t Wt = (t + 63) / 64;
-  if (I1 > I0) {
-    const uint64_t waves = (I1 - I0 + kSpan - 1) / kSpan;
+  if (m1 > m0 && span_cap) {
+    const uint64_t waves = (span_cap + kSpan - 1) / kSpan;
     const uint64_t blocks = (waves * kWave + kCountBlock - 1) / kCountBlock;
-    hipLaunchKernelGGL(k_rade_count, dim3(static_cast<unsigned>(blocks), Wt), dim3(kCountBlock), 0, s, inc + I0,
-                       inc_node + I0, I1 - I0, words, Wt, t, P);
+    hipLaunchKernelGGL(k_rade_count, dim3(static_cast<unsigned>(blocks), Wt), dim3(kCountBlock), 0, s, inc, inc_node,
+                       he_off, m0, m1, limit, words, Wt, t, P);
   }
 }
 
@@ -366,11 +371,32 @@ void bmax_launch(const uint64_t* he_off, uint64_t m0, uint64_t m1, uint32_t* b_m
                        b_max);
 }
 
-int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* he_off, uint32_t t, uint32_t k,
-                       int64_t* topk_sum, uint64_t* deg_topk, uint32_t* b_max, int32_t* R_out, hipStream_t s) {
+int mcera_reserve(centra_ctx* ctx, uint32_t n, uint64_t m, uint32_t t, hipStream_t s) {
   const uint32_t Wt = (t + 63) / 64;
-  // the newest incidence segment holds samples [m0, m): entries [I0, I1)
-  const uint64_t m0 = ctx->inc_m0, I0 = ctx->inc_I0, I1 = ctx->inc_I1;
+  int rc;
+  if ((rc = ensure(ctx, ctx->words, size_t(m) * Wt * 8, true, s))) return rc;
+  if ((rc = ensure(ctx, ctx->P, size_t(n) * t * 4, true, s))) return rc;
+  if ((rc = ensure(ctx, ctx->Rtm, size_t(n) * t * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->topk_tmp, select_ws_bytes(t + 1), false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->sel_rows, size_t(t + 1) * sizeof(SelRow), false, s))) return rc;
+  return ensure(ctx, ctx->ext_bmax, 256, true, s);
+}
+
+// The selection rows of the AMCERA: trial j's row of Rtm, then the degree
+// row (built on the device, so that no host buffer has to outlive the call).
+__global__ void k_mcera_rows(SelRow* rows, const int32_t* Rtm, const int32_t* deg, uint32_t n, uint32_t t, uint32_t k,
+                             int64_t* topk_sum, int64_t* deg_topk) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > t) return;
+  rows[j] = j < t ? SelRow{Rtm + size_t(j) * n, n, k, topk_sum + j} : SelRow{deg, n, k, deg_topk};
+}
+
+int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, uint64_t m0, const uint64_t* he_off, uint32_t t,
+                       uint32_t k, int64_t* topk_sum, uint64_t* deg_topk, uint32_t* b_max, int32_t* R_out,
+                       hipStream_t s) {
+  // samples [m0, m) are counted: entries [he_off[m0], he_off[m]) of the
+  // incidence, at most the newest segment's span when that is where m0 is
+  const uint64_t span_cap = m0 == ctx->inc_m0 ? ctx->inc_span_cap : ctx->inc_limit;
   int rc;
   if ((rc = ensure(ctx, ctx->P, size_t(n) * t * 4, m0 > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->Rtm, size_t(n) * t * 4, false, s))) return rc;
@@ -380,24 +406,15 @@ int mcera_on_incidence(centra_ctx* ctx, uint32_t n, uint64_t m, const uint64_t* 
   int32_t* P = static_cast<int32_t*>(ctx->P.ptr);
   int32_t* Rtm = static_cast<int32_t*>(ctx->Rtm.ptr);
   if (m0 == 0) fill_u32(reinterpret_cast<uint32_t*>(P), 0, size_t(n) * t, s);
-  if (I1 > I0) {
-    const uint64_t waves = (I1 - I0 + kSpan - 1) / kSpan;
-    const uint64_t blocks = (waves * kWave + kCountBlock - 1) / kCountBlock;
-    hipLaunchKernelGGL(k_rade_count, dim3(static_cast<unsigned>(blocks), Wt), dim3(kCountBlock), 0, s,
-                       static_cast<const uint32_t*>(ctx->inc.ptr) + I0,
-                       static_cast<const uint32_t*>(ctx->inc_node.ptr) + I0, I1 - I0,
-                       static_cast<const uint64_t*>(ctx->words.ptr), Wt, t, P);
-  }
+  rade_count_launch(static_cast<const uint32_t*>(ctx->inc.ptr), static_cast<const uint32_t*>(ctx->inc_node.ptr), he_off,
+                    m0, m, span_cap, ctx->inc_limit, static_cast<const uint64_t*>(ctx->words.ptr), t, P, s);
   hipLaunchKernelGGL(k_rade_finish, dim3((n + 63) / 64, (t + 63) / 64), dim3(256), 0, s, P,
                      static_cast<const uint32_t*>(ctx->deg.ptr), n, t, Rtm, R_out);
   // selection over the t trial rows and the degree row
-  std::vector<SelRow> hr(rows);
-  for (uint32_t j = 0; j < t; ++j) hr[j] = SelRow{Rtm + size_t(j) * n, n, k, topk_sum + j};
-  hr[t] = SelRow{static_cast<const int32_t*>(ctx->deg.ptr), n, k, reinterpret_cast<int64_t*>(deg_topk)};
   SelRow* drows = static_cast<SelRow*>(ctx->sel_rows.ptr);
-  CENTRA_HIP(ctx, hipMemcpyAsync(drows, hr.data(), size_t(rows) * sizeof(SelRow), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_mcera_rows, dim3((rows + 255) / 256), dim3(256), 0, s, drows, Rtm,
+                     static_cast<const int32_t*>(ctx->deg.ptr), n, t, k, topk_sum, reinterpret_cast<int64_t*>(deg_topk));
   select_topk_rows(drows, rows, n, ctx->topk_tmp.ptr, s);
-  CENTRA_HIP(ctx, hipStreamSynchronize(s));   // hr is read by the copy above
   if (m0 == 0) fill_u32(b_max, 0, 1, s);
   if (m > m0)
     hipLaunchKernelGGL(k_bmax, dim3(grid_for(m - m0, kBmaxBlock, 512)), dim3(kBmaxBlock), 0, s, he_off + m0, m - m0,

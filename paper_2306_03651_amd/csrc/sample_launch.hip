@@ -119,8 +119,11 @@ static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t
 // (redrawn with a larger area if it overflows); `a` holds the graph part of
 // the arguments (or the instance table of a fused launch), `max_n` the
 // largest n of its graphs.  *total receives the staged node count.
+// async_cap != 0: stream-ordered form; the staging area holds async_cap
+// entries, the launch is not redrawn, nothing is read back (the caller
+// learns the size from the device).
 static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_t max_n, bool multi, int block,
-                          uint64_t* total, hipStream_t s) {
+                          uint64_t* total, hipStream_t s, uint64_t async_cap = 0) {
   int rc;
   *total = 0;
   const SamplePlan plan = plan_for(ctx, max_n, multi ? block : 0);
@@ -130,7 +133,7 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
   if ((rc = ensure(ctx, ctx->stage_pos, size_t(count) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->stage_len, size_t(count) * 4 + 8 + 8 * (size_t(count) + 1), false, s))) return rc;
   if ((rc = ensure(ctx, ctx->work_ctr, 64, false, s))) return rc;
-  uint64_t cap = size_t(count) * 8 + 1024;
+  uint64_t cap = async_cap ? async_cap : size_t(count) * 8 + 1024;
   if (ctx->stage_nodes.bytes / 4 > cap) cap = ctx->stage_nodes.bytes / 4;
   for (int attempt = 0; attempt < 3; ++attempt) {
     if ((rc = ensure(ctx, ctx->stage_nodes, cap * 4, false, s))) return rc;
@@ -171,6 +174,7 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
     sample_kernel_launch(a, plan.block, plan.lds_bits, multi, grid, plan.dyn_lds, s);
     CENTRA_HIP(ctx, hipGetLastError());
+    if (async_cap) return CENTRA_OK;
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[7], s));
     uint64_t host_ctr[4] = {0, 0, 0, 0};   // work, used, arcs, nodes
     CENTRA_HIP(ctx, hipMemcpyAsync(host_ctr, ctx->work_ctr.ptr, 32, hipMemcpyDeviceToHost, s));
@@ -264,6 +268,76 @@ int sample_multi_to_stage(centra_ctx* ctx, const MultiSampleItem* items, uint32_
   rc = launch_sampler(ctx, a, static_cast<uint32_t>(count), max_n, true, block, total, s);
   CENTRA_HIP(ctx, hipStreamSynchronize(s));   // the host tables above go out of scope
   return rc;
+}
+
+// Lays staged hyperedges out after the base = he_off[0] entries already in
+// the store: he_off[i] = base + rel[i] and the nodes at he_nodes + base +
+// rel[i] when end = base + rel[count] fits `cap`; otherwise every new
+// hyperedge is stored empty (he_off[i] = base, nothing beyond the store
+// is referenced) and kErrCapacity is raised.  *total = end either way.
+// he_off[0] (rel[0] = 0) is read by every thread and written by none.
+__global__ void k_stage_append(uint32_t count, const uint64_t* stage_pos, const uint32_t* he_len, const uint64_t* rel,
+                               const uint32_t* stage, uint64_t* he_off, uint32_t* he_nodes, uint64_t cap,
+                               uint64_t* total, uint32_t* flags) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > count) return;
+  const uint64_t base = he_off[0];
+  const uint64_t end = base + rel[count];
+  const bool fits = end <= cap;
+  if (i > 0) he_off[i] = fits ? base + rel[i] : base;
+  if (i == count) {
+    if (total) *total = end;
+    if (!fits) atomicOr(flags, kErrCapacity);
+    return;
+  }
+  if (!fits) return;
+  const uint64_t p = stage_pos[i];
+  const uint64_t o = base + rel[i];
+  const uint32_t len = he_len[i];
+  for (uint32_t x = 0; x < len; ++x) he_nodes[o + x] = stage[p + x];
+}
+
+int sample_reserve(centra_ctx* ctx, const centra_graph* g, uint32_t count, uint64_t stage_entries, hipStream_t s) {
+  const SamplePlan plan = plan_for(ctx, g->n);
+  const uint32_t want = count < plan.resident ? count : plan.resident;
+  int rc;
+  if ((rc = ensure_slots(ctx, g->n, want ? want : 1, s))) return rc;
+  if ((rc = ensure(ctx, ctx->stage_pos, size_t(count) * 8, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->stage_len, size_t(count) * 4 + 8 + 8 * (size_t(count) + 1), false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->work_ctr, 64, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->stage_nodes, (stage_entries ? stage_entries : 1) * 4, false, s))) return rc;
+  return ensure(ctx, ctx->scan_tmp, scan_tile_words(count) * 8, false, s);
+}
+
+int sample_append(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_t instance, uint64_t first,
+                  uint32_t count, uint64_t* he_off, uint32_t* he_nodes, uint64_t he_cap, uint64_t* he_total,
+                  hipStream_t s) {
+  if (count == 0) return CENTRA_OK;
+  SampleArgs a{};
+  a.n = g->n;
+  a.c_bits = g->count_bits;
+  a.max_out_deg = g->max_out_degree;
+  a.row_ptr = g->bfs_row_ptr;
+  a.col_idx = g->bfs_col_idx;
+  a.in_ptr = g->bfs_in_ptr;
+  a.in_idx = g->bfs_in_idx;
+  a.new_of = g->new_of;
+  a.orig_of = g->orig_of;
+  a.seed = seed;
+  a.instance = instance;
+  a.first = first;
+  uint64_t total = 0;
+  int rc = launch_sampler(ctx, a, count, g->n, false, 0, &total, s, he_cap ? he_cap : 1);
+  if (rc) return rc;
+  uint32_t* len = static_cast<uint32_t*>(ctx->stage_len.ptr);
+  uint64_t* rel = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->stage_len.ptr) + ((size_t(count) * 4 + 7) & ~size_t(7)));
+  if ((rc = excl_scan_u32_to_u64(ctx, len, rel, count, s))) return rc;
+  hipLaunchKernelGGL(k_stage_append, dim3((count + 1 + 255) / 256), dim3(256), 0, s, count,
+                     static_cast<const uint64_t*>(ctx->stage_pos.ptr), len, rel,
+                     static_cast<const uint32_t*>(ctx->stage_nodes.ptr), he_off, he_nodes, he_cap, he_total,
+                     ctx->d_flags);
+  CENTRA_HIP(ctx, hipGetLastError());
+  return CENTRA_OK;
 }
 
 int stage_to_output(centra_ctx* ctx, uint32_t count, uint64_t base, uint64_t* he_off, uint32_t* he_nodes,

@@ -183,7 +183,10 @@ int check_flags(centra_ctx* ctx, hipStream_t s, const char* where) {
     if (f & kErrNodeRange) msg += " hyperedge node id out of range;";
     if (f & kErrBacktrack) msg += " backtrack found no predecessor;";
     if (f & kErrGraph) msg += " malformed graph;";
-    return fail(ctx, (f & kErrBacktrack) ? CENTRA_EHIP : CENTRA_EINVAL, msg);
+    if (f & kErrCapacity) msg += " hyperedge store capacity exceeded;";
+    if (f & kErrOffsets) msg += " hyperedge offsets decrease;";
+    const int code = (f & kErrBacktrack) ? CENTRA_EHIP : (f & ~kErrCapacity) ? CENTRA_EINVAL : CENTRA_ENOSPC;
+    return fail(ctx, code, msg);
   }
   return CENTRA_OK;
 }

@@ -37,7 +37,7 @@ def test_binding_mirrors_header():
 
 
 def test_abi_version():
-    assert binding.centra_abi_version() == 9
+    assert binding.centra_abi_version() == 10
 
 
 CASES = [
@@ -91,3 +91,37 @@ def test_hedge_bound_matches_oracle(m, cov, n, k, eps, delta_i):
     want = oracle.hedge_bound(m, cov, n, k, eps, delta_i)
     assert got.eta == pytest.approx(want.eta, rel=1e-12) and got.c_hat == want.c_hat
     assert got.certified == want.certified and got.amcera == 0.0
+
+
+STRUCTS = {"centra_csr": "Csr", "centra_extend_args": "ExtendArgs", "centra_sampler_stats": "SamplerStats",
+           "centra_bound_out": "BoundOut", "centra_vc_out": "VcOut", "centra_params": "Params",
+           "centra_result": "Result", "centra_iteration": "Iteration", "centra_pool_params": "PoolParams",
+           "centra_query_info": "QueryInfo", "centra_engine_stats": "EngineStats"}
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    # the C compiler's sizeof / offsetof of every struct of the header
+    # against the ctypes mirrors (same field names, same offsets)
+    import ctypes
+    import subprocess
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "centra.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(binding, pyname)
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.split() for line in out if line)
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(binding, pyname)
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, f"{cname}.{f}"
+    # every struct the header defines is mirrored
+    text = open(HEADER).read()
+    assert sorted(re.findall(r"}\s*(centra_\w+);", text)) == sorted(STRUCTS)
