@@ -45,6 +45,7 @@ extern "C" {
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
+#define CENTRA_STOPPED 2     /* centra_progressive_resumable stopped where asked */
 #define CENTRA_EINVAL (-1)   /* invalid argument or malformed input */
 #define CENTRA_ENOMEM (-2)   /* the context's HBM budget or the device is exhausted */
 #define CENTRA_EHIP (-3)     /* HIP runtime error (text in centra_last_error) */
@@ -117,6 +118,14 @@ CENTRA_API void centra_graph_release(centra_graph *g);
 
 /* Host outputs: maximum in-degree and count bit budget C of the graph. */
 CENTRA_API int centra_graph_info(const centra_graph *g, uint32_t *max_in_degree, uint32_t *count_bits);
+
+/* Host output: a 64-bit fingerprint of the caller's graph, computed when
+ * it was prepared: mix(n | directed << 32) + the sum over the arcs u -> v
+ * of the out-CSR of mix(u << 32 | v), modulo 2^64, where mix is the
+ * splitmix64 output function (z ^= z >> 30; z *= 0xBF58476D1CE4E5B9;
+ * z ^= z >> 27; z *= 0x94D049BB133111EB; z ^= z >> 31).  Checkpoints
+ * carry it. */
+CENTRA_API int centra_graph_hash(const centra_graph *g, uint64_t *hash);
 
 /* ------------------------------------------------------------------ */
 /* sampleHEs for set betweenness (Algorithm 1 sampling step; hyperedge space
@@ -527,6 +536,10 @@ typedef struct {
     double delta_i, amcera, wimpy, xi, nu, rtilde, r, eta;
     int certified;
     double ms_sample, ms_cover, ms_mcera;
+    uint64_t arcs, nodes;   /* the iteration's sampling work (centra_sampler_stats
+                               arcs and nodes; 0 for the triangle and k-path spaces;
+                               the first iteration of a resume that redraws the
+                               sample counts the redraw too) */
 } centra_iteration;
 
 /* picks: host u32[k] (receives result->n_picked entries); result: host.
@@ -537,6 +550,52 @@ typedef struct {
 CENTRA_API int centra_progressive(centra_ctx *ctx, const centra_graph *g, const centra_params *params,
                        uint32_t *picks, centra_result *result, centra_iteration *log,
                        uint32_t log_cap, void *stream);
+
+/* Checkpoint of Algorithm 1 after iteration i: everything iteration i + 1
+ * depends on.  Samples, Rademacher signs and counts are functions of
+ * (graph, seed, instance) and the sample indices, so the sample of m_i
+ * hyperedges is redrawn on resume (or kept, on the same context). */
+#define CENTRA_CHECKPOINT_VERSION 1u
+typedef struct {
+    uint32_t version;       /* CENTRA_CHECKPOINT_VERSION */
+    uint32_t i;             /* iterations completed, >= 1 */
+    uint64_t graph_hash;    /* centra_graph_hash of the graph */
+    uint64_t params_hash;   /* centra_params_hash of the parameters */
+    uint64_t m_i;           /* samples of iteration i */
+    uint64_t m_next;        /* samples of iteration i + 1 (the schedule's state) */
+    uint64_t entries;       /* hyperedge entries of samples [0, m_i), checked on resume */
+} centra_checkpoint;
+
+/* Host output: FNV-1a (64-bit) over the little-endian bytes of the fields
+ * of *params in declaration order (k, t, eps and delta as their IEEE-754
+ * bits, seed, instance, m_init, m_max, growth_num, growth_den, schedule,
+ * space, kappa, method), each at its own width. */
+CENTRA_API int centra_params_hash(const centra_params *params, uint64_t *hash);
+
+/* centra_progressive that can stop and resume (same results as one
+ * uninterrupted centra_progressive: picks, coverage, sample sizes, bound
+ * values and iteration numbers).
+ *   resume      host, may be NULL: start after iteration resume->i, at
+ *               m = resume->m_next; its graph and parameter hashes must
+ *               match.  On the context that wrote it (no other incidence
+ *               or AMCERA build on the context since), the kept sample and
+ *               counts are extended; elsewhere samples [0, m_next) are
+ *               drawn anew and the entries of [0, m_i) are checked.
+ *   ckpt        host, may be NULL: after every iteration that does not end
+ *               the run, receives the checkpoint to resume after it.
+ *   stop_after  0, or an iteration number: return CENTRA_STOPPED after the
+ *               first iteration numbered >= stop_after that does not end
+ *               the run (result, picks and *ckpt then hold its state).
+ *   log         as centra_progressive: iteration i goes to log[i-1].
+ * The fixed-size schedule has a single iteration and takes no resume.
+ * Returns CENTRA_OK, CENTRA_NOT_CERTIFIED, CENTRA_STOPPED, or an error
+ * (CENTRA_EINVAL also for a checkpoint of another graph, other parameters,
+ * another version, inconsistent sizes, or a redrawn sample whose entries
+ * differ). */
+CENTRA_API int centra_progressive_resumable(centra_ctx *ctx, const centra_graph *g, const centra_params *params,
+                                 const centra_checkpoint *resume, centra_checkpoint *ckpt,
+                                 uint32_t stop_after, uint32_t *picks, centra_result *result,
+                                 centra_iteration *log, uint32_t log_cap, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* The batching and serving engine: Algorithm 1 (as centra_progressive with

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcentra.so")
 
 CENTRA_OK = 0
 CENTRA_NOT_CERTIFIED = 1
+CENTRA_STOPPED = 2
 CENTRA_EINVAL = -1
 CENTRA_ENOMEM = -2
 CENTRA_EHIP = -3
@@ -81,7 +82,24 @@ class Iteration(_c.Structure):
                 ("deg_topk", _c.c_uint64), ("b_max", _c.c_uint32), ("delta_i", _c.c_double),
                 ("amcera", _c.c_double), ("wimpy", _c.c_double), ("xi", _c.c_double), ("nu", _c.c_double),
                 ("rtilde", _c.c_double), ("r", _c.c_double), ("eta", _c.c_double), ("certified", _c.c_int),
-                ("ms_sample", _c.c_double), ("ms_cover", _c.c_double), ("ms_mcera", _c.c_double)]
+                ("ms_sample", _c.c_double), ("ms_cover", _c.c_double), ("ms_mcera", _c.c_double),
+                ("arcs", _c.c_uint64), ("nodes", _c.c_uint64)]
+
+
+CENTRA_CHECKPOINT_VERSION = 1
+
+
+class Checkpoint(_c.Structure):
+    _fields_ = [("version", _c.c_uint32), ("i", _c.c_uint32), ("graph_hash", _c.c_uint64),
+                ("params_hash", _c.c_uint64), ("m_i", _c.c_uint64), ("m_next", _c.c_uint64),
+                ("entries", _c.c_uint64)]
+
+    def to_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Checkpoint":
+        return cls(**{f: int(d[f]) for f, _ in cls._fields_})
 
 
 class SamplerStats(_c.Structure):
@@ -129,6 +147,7 @@ SIGNATURES = {
     "centra_graph_prepare": (_c.c_int, [_vp, _c.POINTER(Csr), _c.c_uint32, _c.POINTER(_vp), _vp]),
     "centra_graph_release": (None, [_vp]),
     "centra_graph_info": (_c.c_int, [_vp, _c.POINTER(_c.c_uint32), _c.POINTER(_c.c_uint32)]),
+    "centra_graph_hash": (_c.c_int, [_vp, _c.POINTER(_c.c_uint64)]),
     "centra_sample_paths": (_c.c_int, [_vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _vp, _vp,
                                        _c.c_uint64, _c.POINTER(_c.c_uint64), _vp, _vp, _vp]),
     "centra_sample_paths_bidir": (_c.c_int, [_vp, _vp, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _vp,
@@ -156,6 +175,10 @@ SIGNATURES = {
     "centra_vc_dims": (_c.c_int, [_c.c_uint64, _c.c_uint32, _c.c_uint64, _c.POINTER(VcOut)]),
     "centra_progressive": (_c.c_int, [_vp, _vp, _c.POINTER(Params), _vp, _c.POINTER(Result),
                                       _c.POINTER(Iteration), _c.c_uint32, _vp]),
+    "centra_params_hash": (_c.c_int, [_c.POINTER(Params), _c.POINTER(_c.c_uint64)]),
+    "centra_progressive_resumable": (_c.c_int, [_vp, _vp, _c.POINTER(Params), _c.POINTER(Checkpoint),
+                                                _c.POINTER(Checkpoint), _c.c_uint32, _vp, _c.POINTER(Result),
+                                                _c.POINTER(Iteration), _c.c_uint32, _vp]),
     "centra_engine_create": (_c.c_int, [_vp, _c.c_size_t, _c.c_uint32, _c.POINTER(_vp)]),
     "centra_engine_destroy": (None, [_vp]),
     "centra_engine_add_pool": (_c.c_int, [_vp, _vp, _c.POINTER(PoolParams), _c.POINTER(_c.c_uint32)]),
@@ -395,6 +418,36 @@ def centra_progressive(ctx, g, k: int, t: int, eps: float, delta: float, seed: i
     return rc, picks[: res.n_picked].copy(), res, list(log)[: min(res.iterations, log_cap)]
 
 
+def centra_params_hash(p: Params) -> int:
+    out = ctypes.c_uint64()
+    _check(lib().centra_params_hash(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def centra_graph_hash(g) -> int:
+    out = ctypes.c_uint64()
+    _check(lib().centra_graph_hash(g, ctypes.byref(out)))
+    return out.value
+
+
+def centra_progressive_resumable(ctx, g, p: Params, resume: Checkpoint | None = None, stop_after: int = 0,
+                                 log_cap: int = 64, stream=None):
+    """Returns (rc, picks np.uint32[n_picked], Result, {i: Iteration} of the
+    iterations this call ran, Checkpoint or None).  rc is CENTRA_OK,
+    CENTRA_NOT_CERTIFIED or CENTRA_STOPPED."""
+    picks = np.zeros(max(1, p.k), dtype=np.uint32)
+    res = Result()
+    log = (Iteration * max(1, log_cap))()
+    ck = Checkpoint()
+    rc = _check(lib().centra_progressive_resumable(ctx, g, ctypes.byref(p),
+                                                   ctypes.byref(resume) if resume is not None else None,
+                                                   ctypes.byref(ck), stop_after, picks.ctypes.data,
+                                                   ctypes.byref(res), log, log_cap, _stream(stream)), ctx)
+    first = resume.i + 1 if resume is not None else 1
+    its = {i: log[i - 1] for i in range(first, min(res.iterations, log_cap) + 1)}
+    return rc, picks[: res.n_picked].copy(), res, its, (ck if ck.version else None)
+
+
 # ---------------------------------------------------------------------------
 class DeviceGraph:
     """A CSR graph uploaded to device tensors and prepared by the library."""
@@ -416,6 +469,9 @@ class DeviceGraph:
 
     def info(self):
         return centra_graph_info(self.handle)
+
+    def hash(self) -> int:
+        return centra_graph_hash(self.handle)
 
     def release(self):
         if self.handle:

@@ -535,8 +535,43 @@ int centra_bound(uint64_t m, uint64_t cov, int64_t sum_topk, uint32_t t, uint64_
   return CENTRA_OK;
 }
 
-int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_params* p, uint32_t* picks,
-                       centra_result* res, centra_iteration* log, uint32_t log_cap, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// FNV-1a (64-bit) over the little-endian bytes of each field.
+struct Fnv {
+  uint64_t h = 0xCBF29CE484222325ull;
+  template <typename T>
+  void add(T v) {
+    unsigned char b[sizeof(T)];
+    memcpy(b, &v, sizeof(T));
+    for (unsigned char c : b) h = (h ^ c) * 0x100000001B3ull;
+  }
+};
+
+uint64_t params_hash(const centra_params* p) {
+  Fnv f;
+  f.add(p->k);
+  f.add(p->t);
+  f.add(p->eps);
+  f.add(p->delta);
+  f.add(p->seed);
+  f.add(p->instance);
+  f.add(p->m_init);
+  f.add(p->m_max);
+  f.add(p->growth_num);
+  f.add(p->growth_den);
+  f.add(p->schedule);
+  f.add(p->space);
+  f.add(p->kappa);
+  f.add(p->method);
+  return f.h;
+}
+
+int progressive_run(centra_ctx* ctx, const centra_graph* g, const centra_params* p, const centra_checkpoint* from,
+                    centra_checkpoint* ck, uint32_t stop_after, uint32_t* picks, centra_result* res,
+                    centra_iteration* log, uint32_t log_cap, void* stream) {
   if (!ctx) return CENTRA_EINVAL;
   if (!g || !p || !picks || !res) return fail(ctx, CENTRA_EINVAL, "progressive: NULL argument");
   const double a = 1.0 - exp(-1.0);
@@ -556,12 +591,28 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
   const bool tri = p->space == CENTRA_SPACE_TRIANGLES;
   const bool kp = p->space == CENTRA_SPACE_KPATHS;
   const bool fixed = p->schedule == CENTRA_SCHEDULE_FIXED;
+  const uint64_t phash = params_hash(p);
+  if (from) {
+    if (from->version != CENTRA_CHECKPOINT_VERSION) return fail(ctx, CENTRA_EINVAL, "resume: checkpoint version");
+    if (from->graph_hash != g->hash) return fail(ctx, CENTRA_EINVAL, "resume: checkpoint of another graph");
+    if (from->params_hash != phash) return fail(ctx, CENTRA_EINVAL, "resume: checkpoint of other parameters");
+    if (fixed) return fail(ctx, CENTRA_EINVAL, "resume: the fixed-size schedule has one iteration");
+    if (from->i == 0 || from->i > 60 || from->m_i < p->m_init || from->m_i >= p->m_max ||
+        from->m_next <= from->m_i || from->m_next > p->m_max)
+      return fail(ctx, CENTRA_EINVAL, "resume: inconsistent checkpoint");
+  }
   DeviceGuard guard(ctx->device);
   hipStream_t s = as_stream(stream);
   memset(res, 0, sizeof(*res));
   const uint32_t k = p->k, t = p->t, n = g->n;
+  // continue the state this context holds, or start (over) from sample 0
+  const bool keep = from && ctx->prog_ok && ctx->prog_g == g && ctx->prog_ghash == g->hash &&
+                    ctx->prog_phash == phash && ctx->prog_i == from->i && ctx->prog_m == from->m_i &&
+                    ctx->prog_entries == from->entries && ctx->prog_inc_gen == ctx->inc_gen &&
+                    (hedge || ctx->prog_words_gen == ctx->words_gen);
+  ctx->prog_ok = false;
   int rc;
-  if ((rc = ensure(ctx, ctx->store_off, (p->m_max + 1) * 8, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->store_off, (p->m_max + 1) * 8, keep, s))) return rc;
   // device result block: picks u32[k] | cov_cum u64[k] | n_picked u32 | b_max u32 | deg_topk u64 | topk i64[t]
   const size_t o_cov = (size_t(k) * 4 + 7) & ~size_t(7);
   const size_t o_np = o_cov + size_t(k) * 8;
@@ -569,17 +620,21 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
   const size_t o_dk = o_np + 8;
   const size_t o_tk = o_dk + 8;
   const size_t misc_bytes = o_tk + size_t(t) * 8;
-  if ((rc = ensure(ctx, ctx->misc, misc_bytes, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->misc, misc_bytes, keep, s))) return rc;
   char* misc = static_cast<char*>(ctx->misc.ptr);
   uint64_t* store_off = static_cast<uint64_t*>(ctx->store_off.ptr);
-  fill_u64(store_off, 0, 1, s);
-  fill_u64(reinterpret_cast<uint64_t*>(misc), 0, misc_bytes / 8, s);   // HEDGE-P leaves the AMCERA fields at 0
+  if (!keep) {
+    fill_u64(store_off, 0, 1, s);
+    fill_u64(reinterpret_cast<uint64_t*>(misc), 0, misc_bytes / 8, s);   // HEDGE-P leaves the AMCERA fields at 0
+  }
   std::string host_block(misc_bytes, '\0');
   hipEvent_t* ev = ctx->ev;
-  uint64_t m_prev = 0, m_i = p->m_init, total_nodes = 0;
-  for (uint32_t i = 1;; ++i) {
+  uint64_t m_prev = keep ? from->m_i : 0, m_i = from ? from->m_next : p->m_init, total_nodes = keep ? from->entries : 0;
+  const bool redrawn = from && !keep;   // samples [0, from->m_i) drawn again: check their entries
+  for (uint32_t i = from ? from->i + 1 : 1;; ++i) {
     // the fixed-size use bounds one sample with delta itself
     const double delta_i = fixed ? p->delta : ldexp(p->delta, -static_cast<int>(i));
+    const uint64_t arcs0 = ctx->st.arcs, nodes0 = ctx->st.nodes;
     CENTRA_HIP(ctx, hipEventRecord(ev[0], s));
     uint64_t added = 0;
     const uint32_t cnt = static_cast<uint32_t>(m_i - m_prev);
@@ -626,9 +681,14 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
         return rc;
     }
     CENTRA_HIP(ctx, hipEventRecord(ev[3], s));
+    uint64_t entries_then = 0;
+    if (redrawn && m_prev == 0)
+      CENTRA_HIP(ctx, hipMemcpyAsync(&entries_then, store_off + from->m_i, 8, hipMemcpyDeviceToHost, s));
     CENTRA_HIP(ctx, hipMemcpyAsync(&host_block[0], misc, misc_bytes, hipMemcpyDeviceToHost, s));
     CENTRA_HIP(ctx, hipStreamSynchronize(s));
     if ((rc = check_flags(ctx, s, "progressive"))) return rc;
+    if (redrawn && m_prev == 0 && entries_then != from->entries)
+      return fail(ctx, CENTRA_EINVAL, "resume: the redrawn sample does not match the checkpoint's entries");
     const char* hb = host_block.data();
     uint32_t np, bm;
     uint64_t dk;
@@ -694,12 +754,55 @@ int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_para
       it.ms_sample = ms_s;
       it.ms_cover = ms_c;
       it.ms_mcera = ms_m;
+      it.arcs = ctx->st.arcs - arcs0;
+      it.nodes = ctx->st.nodes - nodes0;
     }
     if (o.certified) return CENTRA_OK;
     if (fixed || m_i >= p->m_max) return CENTRA_NOT_CERTIFIED;
+    const uint64_t m_next = next_sample_size(p, m_i, o.c_hat, ldexp(p->delta, -static_cast<int>(i + 1)));
+    // the state after iteration i, for a resume on this context or elsewhere
+    ctx->prog_ok = true;
+    ctx->prog_g = g;
+    ctx->prog_ghash = g->hash;
+    ctx->prog_phash = phash;
+    ctx->prog_i = i;
+    ctx->prog_m = m_i;
+    ctx->prog_entries = total_nodes;
+    ctx->prog_inc_gen = ctx->inc_gen;
+    ctx->prog_words_gen = ctx->words_gen;
+    if (ck) *ck = centra_checkpoint{CENTRA_CHECKPOINT_VERSION, i, g->hash, phash, m_i, m_next, total_nodes};
+    if (stop_after && i >= stop_after) return CENTRA_STOPPED;
     m_prev = m_i;
-    m_i = next_sample_size(p, m_i, o.c_hat, ldexp(p->delta, -static_cast<int>(i + 1)));
+    m_i = m_next;
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int centra_progressive(centra_ctx* ctx, const centra_graph* g, const centra_params* p, uint32_t* picks,
+                       centra_result* res, centra_iteration* log, uint32_t log_cap, void* stream) {
+  return progressive_run(ctx, g, p, nullptr, nullptr, 0, picks, res, log, log_cap, stream);
+}
+
+int centra_progressive_resumable(centra_ctx* ctx, const centra_graph* g, const centra_params* p,
+                                 const centra_checkpoint* resume, centra_checkpoint* ckpt, uint32_t stop_after,
+                                 uint32_t* picks, centra_result* res, centra_iteration* log, uint32_t log_cap,
+                                 void* stream) {
+  return progressive_run(ctx, g, p, resume, ckpt, stop_after, picks, res, log, log_cap, stream);
+}
+
+int centra_params_hash(const centra_params* p, uint64_t* hash) {
+  if (!p || !hash) return CENTRA_EINVAL;
+  *hash = params_hash(p);
+  return CENTRA_OK;
+}
+
+int centra_graph_hash(const centra_graph* g, uint64_t* hash) {
+  if (!g || !hash) return CENTRA_EINVAL;
+  *hash = g->hash;
+  return CENTRA_OK;
 }
 
 }  // extern "C"

@@ -243,6 +243,7 @@ int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const
                     static_cast<uint32_t*>(ctx->inc_node.ptr), static_cast<uint64_t*>(ctx->scan_tmp.ptr), ctx->d_flags, s);
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->inc_nseg = g + 1;
+  ++ctx->inc_gen;
   ctx->inc_m0 = m0;
   ctx->inc_span_cap = I1 - I0;
   ctx->inc_m1 = m1;

@@ -4,10 +4,19 @@
 
 namespace centra {
 
+// The splitmix64 output function (Steele, Lea and Flood, "Fast splittable
+// pseudorandom number generators", 2014; constants of Stafford's Mix13).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // One thread per node: row bounds, ascending ids, range, no self loops;
-// records the maximum in-degree.  A bad row raises kErrGraph.
+// records the maximum in-degree.  A bad row raises kErrGraph.  With `hash`,
+// the sum of mix64(u << 32 | v) over the row's arcs u -> v is added to it.
 __global__ void k_validate_rows(uint32_t n, uint64_t n_arcs, const uint32_t* ptr, const uint32_t* idx,
-                                uint32_t* flags, uint32_t* max_deg) {
+                                uint32_t* flags, uint32_t* max_deg, unsigned long long* hash) {
   const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u == 0 && (ptr[0] != 0 || ptr[n] != n_arcs)) atomicOr(flags, kErrGraph);
   if (u >= n) return;
@@ -17,6 +26,7 @@ __global__ void k_validate_rows(uint32_t n, uint64_t n_arcs, const uint32_t* ptr
     return;
   }
   uint32_t prev = 0;
+  uint64_t h = 0;
   for (uint32_t a = b; a < e; ++a) {
     const uint32_t v = idx[a];
     if (v >= n || v == u || (a > b && v <= prev)) {
@@ -24,8 +34,10 @@ __global__ void k_validate_rows(uint32_t n, uint64_t n_arcs, const uint32_t* ptr
       return;
     }
     prev = v;
+    h += mix64((uint64_t(u) << 32) | v);
   }
   atomicMax(max_deg, e - b);
+  if (hash && h) atomicAdd(hash, static_cast<unsigned long long>(h));
 }
 
 // Directed graphs: every arc u -> v must appear as u in v's in-row.  With
@@ -52,18 +64,30 @@ __global__ void k_validate_reverse(uint32_t n, const uint32_t* ptr, const uint32
   }
 }
 
+// Host side of the graph hash: the arc sum plus mix64 of n | directed << 32.
+uint64_t graph_hash_finish(uint32_t n, uint32_t directed, uint64_t arc_sum) {
+  uint64_t z = uint64_t(n) | (uint64_t(directed) << 32);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return arc_sum + (z ^ (z >> 31));
+}
+
 int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s) {
   uint32_t* flags = ctx->d_flags;
   uint32_t* maxd = ctx->d_flags + 1;
   uint32_t* maxd_in = ctx->d_flags + 2;
-  fill_u32(flags, 0, 3, s);
+  unsigned long long* hash = reinterpret_cast<unsigned long long*>(ctx->d_flags + 4);
+  fill_u32(flags, 0, 6, s);
   const unsigned blocks = (g->n + 255) / 256;
   hipLaunchKernelGGL(k_validate_rows, dim3(blocks), dim3(256), 0, s, g->n, g->n_arcs, g->row_ptr, g->col_idx,
-                     flags, maxd);
+                     flags, maxd, hash);
   CENTRA_HIP(ctx, hipGetLastError());
   uint32_t host[3] = {0, 0, 0};
+  uint64_t arc_hash = 0;
   CENTRA_HIP(ctx, hipMemcpyAsync(host, ctx->d_flags, sizeof(host), hipMemcpyDeviceToHost, s));
+  CENTRA_HIP(ctx, hipMemcpyAsync(&arc_hash, hash, 8, hipMemcpyDeviceToHost, s));
   CENTRA_HIP(ctx, hipStreamSynchronize(s));
+  g->hash = graph_hash_finish(g->n, g->directed, arc_hash);
   if (host[0]) {
     fill_u32(flags, 0, 3, s);
     return fail(ctx, CENTRA_EINVAL, "graph: malformed out-CSR (row bounds, order, duplicates, self loops or range)");
@@ -72,7 +96,7 @@ int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s) {
   g->max_out_degree = host[1];
   if (g->directed) {
     hipLaunchKernelGGL(k_validate_rows, dim3(blocks), dim3(256), 0, s, g->n, g->n_arcs, g->in_ptr, g->in_idx,
-                       flags, maxd_in);
+                       flags, maxd_in, static_cast<unsigned long long*>(nullptr));
     CENTRA_HIP(ctx, hipGetLastError());
     CENTRA_HIP(ctx, hipMemcpyAsync(host, ctx->d_flags, sizeof(host), hipMemcpyDeviceToHost, s));
     CENTRA_HIP(ctx, hipStreamSynchronize(s));
@@ -91,7 +115,7 @@ int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s) {
     }
     g->max_in_degree = host[2];
   }
-  fill_u32(flags, 0, 3, s);
+  fill_u32(flags, 0, 6, s);
   uint32_t bl = 0;
   for (uint32_t d = g->max_in_degree; d; d >>= 1) ++bl;
   g->count_bits = 63u - bl;

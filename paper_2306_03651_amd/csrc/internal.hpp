@@ -62,6 +62,14 @@ struct centra_ctx {
   uint64_t mc_m = 0, mc_seed = 0;
   uint32_t mc_instance = 0, mc_t = 0;
   centra::DevBuf ext_bmax;
+  // Builds of the incidence and of the Rademacher words so far; the state a
+  // progressive run leaves (store, incidence, counts, running b_max) is
+  // continued by a resume on this context only if no other build came since.
+  uint64_t inc_gen = 0, words_gen = 0;
+  bool prog_ok = false;
+  const centra_graph* prog_g = nullptr;
+  uint64_t prog_ghash = 0, prog_phash = 0, prog_m = 0, prog_entries = 0, prog_inc_gen = 0, prog_words_gen = 0;
+  uint32_t prog_i = 0;
   centra::DevBuf words, P, Rtm, topk_tmp, misc, sel_rows;
   // sample store of centra_progressive
   centra::DevBuf store_off, store_nodes;
@@ -83,6 +91,7 @@ struct centra_graph {
   uint32_t max_out_degree = 0;
   uint32_t count_bits = 0;
   uint32_t count_bits_override = 0;   // test override of both count budgets (0: none)
+  uint64_t hash = 0;                  // centra_graph_hash
   // the arrays the sampler traverses: the locality-relabelled copy
   // (relabel_graph) or the caller's CSR; new_of / orig_of map caller ids
   // to traversal ids and back (both NULL without relabelling)
@@ -151,6 +160,7 @@ int sample_triangles_into(centra_ctx* ctx, centra_graph* g, uint64_t seed, uint3
 
 // Graph checks (graph.hip).
 int validate_graph(centra_ctx* ctx, centra_graph* g, hipStream_t s);
+uint64_t graph_hash_finish(uint32_t n, uint32_t directed, uint64_t arc_sum);
 
 // Workspace growth ahead of the stream-ordered calls (each grows the
 // buffers its step would grow; keep-contents buffers keep them).

@@ -59,6 +59,7 @@ int rade_words(centra_ctx* ctx, uint64_t seed, uint32_t instance, uint64_t s0, u
                hipStream_t s) {
   const uint32_t Wt = (t + 63) / 64;
   ctx->mc_ok = false;   // the extend calls' AMCERA state is valid only after their own updates
+  ++ctx->words_gen;
   int rc = ensure(ctx, ctx->words, size_t(s1) * Wt * 8, true, s);
   if (rc) return rc;
   if (s1 > s0)

@@ -96,7 +96,7 @@ def test_hedge_bound_matches_oracle(m, cov, n, k, eps, delta_i):
 STRUCTS = {"centra_csr": "Csr", "centra_extend_args": "ExtendArgs", "centra_sampler_stats": "SamplerStats",
            "centra_bound_out": "BoundOut", "centra_vc_out": "VcOut", "centra_params": "Params",
            "centra_result": "Result", "centra_iteration": "Iteration", "centra_pool_params": "PoolParams",
-           "centra_query_info": "QueryInfo", "centra_engine_stats": "EngineStats"}
+           "centra_query_info": "QueryInfo", "centra_engine_stats": "EngineStats", "centra_checkpoint": "Checkpoint"}
 
 
 def test_binding_structs_match_header_layout(tmp_path):
@@ -125,3 +125,17 @@ def test_binding_structs_match_header_layout(tmp_path):
     # every struct the header defines is mirrored
     text = open(HEADER).read()
     assert sorted(re.findall(r"}\s*(centra_\w+);", text)) == sorted(STRUCTS)
+
+
+def test_params_hash_is_fnv1a_of_the_fields():
+    # FNV-1a 64 over each field's little-endian bytes, in declaration order
+    import struct
+    p = binding.Params(50, 64, 0.01, 0.1, 12345678901, 7, 100000, 4000000, 2, 1, 1, 3, 0, 1)
+    data = struct.pack("<IIddQIQQIIIIII", p.k, p.t, p.eps, p.delta, p.seed, p.instance, p.m_init, p.m_max,
+                       p.growth_num, p.growth_den, p.schedule, p.space, p.kappa, p.method)
+    h = 0xCBF29CE484222325
+    for b in data:
+        h = ((h ^ b) * 0x100000001B3) & ((1 << 64) - 1)
+    assert binding.centra_params_hash(p) == h
+    q = binding.Params(50, 64, 0.01, 0.1, 12345678901, 7, 100000, 4000000, 2, 1, 1, 3, 0, 0)
+    assert binding.centra_params_hash(q) != h
