@@ -657,6 +657,7 @@ def main():
     if not tri and not kp:
         roofline.update({"arcs_per_path": round(st.arcs / max(1, st.samples), 1),
                          "nodes_per_path": round(st.nodes / max(1, st.samples), 1),
+                         "entries_per_path": round(st.hyperedge_nodes / max(1, st.samples), 3),
                          "visited_set": "lds bitmap" if st.lds_bitmap else "lds bloom filter + hbm records",
                          "concurrent_bfs": st.slots})
 

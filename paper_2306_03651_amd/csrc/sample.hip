@@ -85,7 +85,7 @@ namespace centra {
 // needs at most kPairMax pairs.  Cost rules (kConeRatio, kPairRatio) decide
 // at which levels they run.
 // Bloom filter of the visited set for the HBM variant (see BitsRec).
-constexpr uint32_t kBloomLog = 15;
+constexpr uint32_t kBloomLog = 14;
 constexpr uint32_t kBloomWords = (1u << kBloomLog) / 32;
 
 template <int BLOCK>
@@ -120,6 +120,8 @@ struct SampleShared {
   uint64_t ring_b[Ring<BLOCK>::kCache];  // per in-neighbour w of t: level-(L+2) count
   uint32_t bloom[BLOCK >= 1024 ? 1 : kBloomWords];   // HBM variant (<= 512 threads): visited filter
   uint64_t base;
+  uint64_t hub_pairs;
+  uint32_t hpos;
   uint32_t pick;
   uint32_t qlen;
   uint32_t next;
@@ -345,6 +347,60 @@ __device__ __forceinline__ uint64_t pred_weight(const Bits& bits, uint64_t* rec,
 
 __device__ __forceinline__ uint32_t caller_id(const SampleArgs& a, uint32_t v) { return a.orig_of ? a.orig_of[v] : v; }
 
+// Cost rule of the hub 2-hop test at a level (queue entries [lb, le)):
+// true when the in-rows of t's dt in-neighbours (starting at in_idx[tb])
+// hold at most kPairRatio times the out-arcs of the level.  Both sums grow
+// chunk by chunk only until the comparison is decided; the in-row sum and
+// its position persist in sh across levels.  Uniform; contains barriers.
+template <int BLOCK>
+__device__ __forceinline__ bool hub_rule(const SampleArgs& g, const uint32_t* q, uint32_t tb, uint32_t dt, uint32_t lb,
+                                      uint32_t le, SampleShared<BLOCK>& sh, uint64_t& n_arcs) {
+  const uint32_t tid = threadIdx.x;
+  uint32_t hpos = uniform_u32(sh.hpos);
+  uint64_t hub = uniform_u64(sh.hub_pairs);
+  uint32_t fpos = lb;
+  uint64_t fpart = 0;
+  bool run;
+  for (;;) {
+    const bool hdone = hpos >= dt, fdone = fpos >= le;
+    if (hdone && hub <= kPairRatio * fpart) {
+      run = true;
+      break;
+    }
+    if (fdone && hub > kPairRatio * fpart) {
+      run = false;
+      break;
+    }
+    if (!hdone && (fdone || hub <= kPairRatio * fpart)) {
+      const uint32_t e = hpos + tid;
+      uint64_t c = 0;
+      if (e < dt) {
+        const uint32_t w = g.in_idx[tb + e];
+        c = g.in_ptr[w + 1] - g.in_ptr[w];
+      }
+      hub += block_sum_u64<BLOCK>(c, sh.red);
+      n_arcs += dt - hpos < uint32_t(BLOCK) ? dt - hpos : uint32_t(BLOCK);
+      hpos += BLOCK;
+    } else {
+      const uint32_t i = fpos + tid;
+      uint64_t c = 0;
+      if (i < le) {
+        const uint32_t w = ld_u32(&q[i]);
+        c = g.row_ptr[w + 1] - g.row_ptr[w];
+      }
+      fpart += block_sum_u64<BLOCK>(c, sh.red);
+      fpos += BLOCK;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    sh.hpos = hpos;
+    sh.hub_pairs = hub;
+  }
+  __syncthreads();
+  return run;
+}
+
 // Ring index of pair p: largest i with poff[i] <= p.
 __device__ __forceinline__ int ring_of(const uint32_t* poff, uint32_t dt, uint32_t p) {
   int lo = 0, hi = static_cast<int>(dt) - 1;
@@ -358,16 +414,17 @@ __device__ __forceinline__ int ring_of(const uint32_t* poff, uint32_t dt, uint32
   return lo;
 }
 
-// Up to 512 threads the kernel is held to 5 waves per SIMD (at most 96
-// VGPRs, a few bytes of spill): more resident BFSs hide more of the latency
-// of their dependent random accesses than the spill costs.
+// Up to 512 threads the kernel is held to 6 waves per SIMD (at most 80
+// VGPRs, some spill; with the 16 Kbit filter 12 workgroups of 128 threads
+// fit a CU's LDS): more resident BFSs hide more of the latency of their
+// dependent random accesses than the spill costs.
 //
 // MULTI: a fused launch over several graphs (sample pools).  Each work
 // item's graph is looked up in the instance table and its arguments are
 // placed in LDS, from where the BFS reads them; every other step is the
 // same, so each hyperedge equals that of a launch on its graph alone.
 template <int BLOCK, int UNROLL, bool LDS_BITS, bool MULTI = false>
-__global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(SampleArgs a) {
+__global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 6 : 1) void k_sample_paths(SampleArgs a) {
   __shared__ SampleShared<BLOCK> sh;
   __shared__ typename std::conditional<MULTI, SampleArgs, char>::type item_args;
   extern __shared__ uint32_t dyn_bits[];
@@ -513,6 +570,16 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
       }
     }
 
+    // The 2-hop test of a t with more in-neighbours than the ring cache
+    // scans the in-rows of all of them (sh.hub_pairs entries, sized lazily
+    // over in(t) entries [0, sh.hpos); kept in LDS, as they are read once
+    // per level); like test (2) it runs at a level only when those entries
+    // are at most kPairRatio times the out-arcs expanding the level would
+    // scan.
+    if (tid == 0) {
+      sh.hpos = 0;
+      sh.hub_pairs = 0;
+    }
     uint32_t lb = 0, le = 1, L = 0, d = kUnseen;
     uint64_t sumL = 1;        // S_L: sum of the level-L counts (saturating)
     uint32_t shortcut = 0;    // 2 or 3: levels L+1 (and L+2) were not produced
@@ -635,7 +702,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 5 : 1) void k_sample_paths(Sa
             }
           }
         }
-      } else if (sumL < cap) {
+      } else if (sumL < cap && hub_rule<BLOCK>(g, q, tb, dt, lb, le, sh, n_arcs)) {
         // t with more in-neighbours than the ring cache: in-neighbours w of t
         // at level L+1, raw_w = sum of sigma' over w's in-neighbours at level L
         uint64_t wsum = 0, wscan = 0;
