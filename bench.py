@@ -38,10 +38,10 @@ Also reported:
     per CSR entry scanned + 28 B per node given a level, counted exactly by
     the kernel.  Triangles: 56 B per sample (20 B written; the bracketing
     prefix pair, the arc's source and target, its list offset and the
-    listed node read).  kappa-paths: the two passes over each walk (lengths,
-    then nodes) read 12 B per step each (the row bounds and the chosen
-    entry) and the second writes the node: 28 B per walk node, plus 12 B
-    per walk (its length written, its offset read).  `traffic` comes from
+    listed node read).  kappa-paths: the walk pass reads 12 B per step (the
+    row bounds and the chosen entry) and stages the node (4 B), the gather
+    reads and writes it (8 B): 24 B per walk node, plus 12 B per walk (its
+    length written, its offset read).  `traffic` comes from
     the committed rocprofv3
     counter summary when it was taken on the current kernel source, else
     null;
@@ -113,7 +113,7 @@ ENGINE_WORKLOADS = {
                           "(grids: 1k doubling to 16k), drawn and built before the stream starts"),
 }
 TRIANGLE_SAMPLE_BYTES = 56
-KPATH_NODE_BYTES, KPATH_SAMPLE_BYTES = 28, 12
+KPATH_NODE_BYTES, KPATH_SAMPLE_BYTES = 24, 12
 WORKLOAD = WORKLOADS["sparse"]
 
 
@@ -648,7 +648,7 @@ def main():
     traffic = None if bidir else read_traffic(W["traffic"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "k_tri_sample" if tri else "k_kpath (both passes)" if kp else
+                "kernel": "k_tri_sample" if tri else "k_kpath + k_kpath_gather" if kp else
                 "k_sample_bidir" if bidir else "k_sample_paths",
                 "launches": st.launches,
                 "avg_launch_ms": round(st.kernel_ms / launches, 3),

@@ -73,7 +73,8 @@ struct centra_ctx {
   centra::DevBuf words, P, Rtm, topk_tmp, misc, sel_rows;
   // sample store of centra_progressive
   centra::DevBuf store_off, store_nodes;
-  centra::DevBuf kp_len;   // kappa-path walk lengths
+  centra::DevBuf kp_len;     // kappa-path walk lengths
+  centra::DevBuf kp_stage;   // kappa-path walk nodes, kappa slots per walk
   hipEvent_t ev[8] = {};
   centra_sampler_stats st = {};
 };

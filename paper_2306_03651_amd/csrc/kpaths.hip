@@ -14,9 +14,9 @@
 // and the r-th free entry is r's index shifted past every occupied position
 // at or before it.  So a step costs O(kappa log deg(v)) loads whatever the
 // degree, which matters on hubs, where degree-biased walks spend their
-// steps.  Two passes: the first writes each walk's length, a scan turns the
-// lengths into offsets, and the second redraws the same walks (the stream is
-// counter-based) and writes their nodes there.
+// steps.  One walk pass writes each walk's nodes to a staging slab of kappa
+// entries and its length; a scan turns the lengths into offsets, and a
+// streaming gather lays the nodes out in sample order.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -36,13 +36,10 @@ __device__ __forceinline__ uint32_t lower_pos(const uint32_t* idx, uint32_t lo, 
   return lo;
 }
 
-// kWrite = false: lens[x] = the walk's length; true: its nodes at
-// he_nodes[off[x] ...].
-template <bool kWrite>
+// Walk x: lens[x] = its length, its nodes at stage[x * kappa ...].
 __global__ __launch_bounds__(256) void k_kpath(uint32_t count, uint64_t first, uint64_t seed, uint32_t instance,
                                                uint32_t n, uint32_t kappa, const uint32_t* row_ptr,
-                                               const uint32_t* col_idx, uint32_t* lens, const uint64_t* off,
-                                               uint32_t* he_nodes) {
+                                               const uint32_t* col_idx, uint32_t* lens, uint32_t* stage) {
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= count) return;
   WordStream st(seed, first + x, instance, 6);
@@ -52,7 +49,7 @@ __global__ __launch_bounds__(256) void k_kpath(uint32_t count, uint64_t first, u
   uint32_t pos[kMaxKappa + 1];
   walk[0] = s;
   uint32_t len = 0, v = s;
-  uint32_t* out = kWrite ? he_nodes + off[x] : nullptr;
+  uint32_t* out = stage + size_t(x) * kappa;
   while (len < l) {
     const uint32_t lo = row_ptr[v], hi = row_ptr[v + 1];
     // row positions of the walk's nodes, ascending (insertion sort)
@@ -75,9 +72,20 @@ __global__ __launch_bounds__(256) void k_kpath(uint32_t count, uint64_t first, u
     for (uint32_t j = 0; j < np && pos[j] <= idx; ++j) ++idx;
     v = col_idx[idx];
     walk[++len] = v;
-    if (kWrite) out[len - 1] = v;
+    out[len - 1] = v;
   }
-  if (!kWrite) lens[x] = len;
+  lens[x] = len;
+}
+
+// he_nodes[off[x] - off[0] + i] = stage[x * kappa + i], i < lens[x]: one
+// thread per staged entry slot (coalesced reads of the slabs).
+__global__ void k_kpath_gather(uint32_t count, uint32_t kappa, const uint32_t* lens, const uint32_t* stage,
+                               const uint64_t* off, uint32_t* he_nodes) {
+  const uint64_t e = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
+  const uint64_t x = e / kappa;
+  if (x >= count) return;
+  const uint32_t i = static_cast<uint32_t>(e - x * kappa);
+  if (i < lens[x]) he_nodes[off[x] - off[0] + i] = stage[e];
 }
 
 __global__ void k_add_u64(uint64_t* a, uint64_t n, uint64_t add) {
@@ -92,11 +100,12 @@ int kpath_count(centra_ctx* ctx, const centra_graph* g, uint32_t kappa, uint64_t
   if (kappa == 0 || kappa > kMaxKappa) return fail(ctx, CENTRA_EINVAL, "kappa-paths: kappa outside [1, 16]");
   int rc = ensure(ctx, ctx->kp_len, (size_t(count) + 1) * 4, false, s);
   if (rc) return rc;
+  if ((rc = ensure(ctx, ctx->kp_stage, (size_t(count) * kappa + 1) * 4, false, s))) return rc;
   uint32_t* lens = static_cast<uint32_t*>(ctx->kp_len.ptr);
   if (timed) CENTRA_HIP(ctx, hipEventRecord(ctx->ev[4], s));
   if (count)
-    hipLaunchKernelGGL(k_kpath<false>, grid_of(count), dim3(256), 0, s, count, first, seed, instance, g->n, kappa,
-                       g->row_ptr, g->col_idx, lens, nullptr, nullptr);
+    hipLaunchKernelGGL(k_kpath, grid_of(count), dim3(256), 0, s, count, first, seed, instance, g->n, kappa, g->row_ptr,
+                       g->col_idx, lens, static_cast<uint32_t*>(ctx->kp_stage.ptr));
   CENTRA_HIP(ctx, hipGetLastError());
   if (timed) CENTRA_HIP(ctx, hipEventRecord(ctx->ev[5], s));
   return excl_scan_u32_to_u64(ctx, lens, off, count, s);
@@ -107,8 +116,9 @@ int kpath_write(centra_ctx* ctx, const centra_graph* g, uint32_t kappa, uint64_t
                 bool timed) {
   if (timed) CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
   if (count)
-    hipLaunchKernelGGL(k_kpath<true>, grid_of(count), dim3(256), 0, s, count, first, seed, instance, g->n, kappa,
-                       g->row_ptr, g->col_idx, nullptr, off, he_nodes);
+    hipLaunchKernelGGL(k_kpath_gather, grid_of(uint64_t(count) * kappa), dim3(256), 0, s, count, kappa,
+                       static_cast<const uint32_t*>(ctx->kp_len.ptr), static_cast<const uint32_t*>(ctx->kp_stage.ptr),
+                       off, he_nodes);
   CENTRA_HIP(ctx, hipGetLastError());
   if (timed) CENTRA_HIP(ctx, hipEventRecord(ctx->ev[7], s));
   if (base) hipLaunchKernelGGL(k_add_u64, grid_of(uint64_t(count) + 1), dim3(256), 0, s, off, uint64_t(count) + 1, base);
