@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libcentra.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["util.hip", "graph.hip", "sample.hip", "sample_launch.hip", "triangles.hip", "kpaths.hip", "cover.hip", "mcera.hip", "engine.hip", "bidir.hip",
+SOURCES = ["util.hip", "graph.hip", "sample.hip", "sample_launch.hip", "triangles.hip", "kpaths.hip", "cover.hip", "incidence.hip", "mcera.hip", "engine.hip", "bidir.hip",
            "api.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch={ARCH}", "-Wall",

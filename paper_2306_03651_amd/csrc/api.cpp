@@ -189,7 +189,7 @@ void centra_destroy(centra_ctx* ctx) {
                     &ctx->stage_len, &ctx->work_ctr, &ctx->scan_tmp, &ctx->deg, &ctx->inc_off,
                     &ctx->inc_cursor, &ctx->inc, &ctx->inc_node, &ctx->gain, &ctx->covered, &ctx->best,
                     &ctx->newcov, &ctx->words, &ctx->P, &ctx->Rtm, &ctx->topk_tmp, &ctx->misc,
-                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len, &ctx->kp_stage, &ctx->seg_deg, &ctx->multi_tab, &ctx->sel_rows, &ctx->ext_bmax, &ctx->bi_rec_f, &ctx->bi_rec_b, &ctx->bi_q_f,
+                    &ctx->store_off, &ctx->store_nodes, &ctx->kp_len, &ctx->kp_stage, &ctx->inc_ws, &ctx->seg_deg, &ctx->multi_tab, &ctx->sel_rows, &ctx->ext_bmax, &ctx->bi_rec_f, &ctx->bi_rec_b, &ctx->bi_q_f,
                     &ctx->bi_q_b};
   for (DevBuf* b : bufs) release(ctx, *b);
   if (ctx->d_flags) (void)hipFree(ctx->d_flags);

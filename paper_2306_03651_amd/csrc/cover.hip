@@ -236,11 +236,21 @@ int build_incidence(centra_ctx* ctx, uint32_t n, uint64_t m0, uint64_t m1, const
   if ((rc = ensure(ctx, ctx->inc, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->inc_node, (I1 ? I1 : 1) * 4, g > 0, s))) return rc;
   if ((rc = ensure(ctx, ctx->scan_tmp, scan_tile_words(n) * 8, false, s))) return rc;
-  incidence_segment(n, m0, m1, I1 - I0, I1, he_off, he_nodes, g == 0, static_cast<uint32_t*>(ctx->deg.ptr),
-                    static_cast<uint32_t*>(ctx->seg_deg.ptr),
-                    static_cast<uint64_t*>(ctx->inc_off.ptr) + size_t(g) * (size_t(n) + 1),
-                    static_cast<uint64_t*>(ctx->inc_cursor.ptr), static_cast<uint32_t*>(ctx->inc.ptr),
-                    static_cast<uint32_t*>(ctx->inc_node.ptr), static_cast<uint64_t*>(ctx->scan_tmp.ptr), ctx->d_flags, s);
+  if (n <= kIncBucketMaxNodes) {
+    if ((rc = ensure(ctx, ctx->inc_ws, incidence_ws_bytes(n, I1 - I0), false, s))) return rc;
+    incidence_segment_bucketed(n, m0, m1, I1 - I0, I1, he_off, he_nodes, g == 0, static_cast<uint32_t*>(ctx->deg.ptr),
+                               static_cast<uint32_t*>(ctx->seg_deg.ptr),
+                               static_cast<uint64_t*>(ctx->inc_off.ptr) + size_t(g) * (size_t(n) + 1),
+                               static_cast<uint64_t*>(ctx->inc_cursor.ptr), static_cast<uint32_t*>(ctx->inc.ptr),
+                               static_cast<uint32_t*>(ctx->inc_node.ptr), ctx->inc_ws.ptr, ctx->d_flags, s);
+  } else {
+    incidence_segment(n, m0, m1, I1 - I0, I1, he_off, he_nodes, g == 0, static_cast<uint32_t*>(ctx->deg.ptr),
+                      static_cast<uint32_t*>(ctx->seg_deg.ptr),
+                      static_cast<uint64_t*>(ctx->inc_off.ptr) + size_t(g) * (size_t(n) + 1),
+                      static_cast<uint64_t*>(ctx->inc_cursor.ptr), static_cast<uint32_t*>(ctx->inc.ptr),
+                      static_cast<uint32_t*>(ctx->inc_node.ptr), static_cast<uint64_t*>(ctx->scan_tmp.ptr), ctx->d_flags,
+                      s);
+  }
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->inc_nseg = g + 1;
   ++ctx->inc_gen;
@@ -261,6 +271,7 @@ int incidence_reserve(centra_ctx* ctx, uint32_t n, uint64_t entries, uint32_t se
   if ((rc = ensure(ctx, ctx->inc_cursor, size_t(n) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->inc, (entries ? entries : 1) * 4, true, s))) return rc;
   if ((rc = ensure(ctx, ctx->inc_node, (entries ? entries : 1) * 4, true, s))) return rc;
+  if (n <= kIncBucketMaxNodes && (rc = ensure(ctx, ctx->inc_ws, incidence_ws_bytes(n, entries), false, s))) return rc;
   return ensure(ctx, ctx->scan_tmp, scan_tile_words(n) * 8, false, s);
 }
 

@@ -313,10 +313,18 @@ static int build_level(centra_engine* e, EnginePool& p, uint32_t j, hipStream_t 
   if ((rc = ensure(ctx, p.deg[j], size_t(n) * 4, false, s))) return rc;
   if ((rc = ensure(ctx, p.R[j], size_t(n) * t * 4, false, s))) return rc;
   uint32_t* deg_cur = static_cast<uint32_t*>(p.deg_cur.ptr);
-  incidence_segment(n, m0, m1, I1 - I0, I1, off, static_cast<const uint32_t*>(p.nodes.ptr), j == 0, deg_cur,
-                    static_cast<uint32_t*>(p.sdeg.ptr), static_cast<uint64_t*>(p.seg_off.ptr) + size_t(j) * (n + 1),
-                    static_cast<uint64_t*>(p.cursor.ptr), static_cast<uint32_t*>(p.inc.ptr),
-                    static_cast<uint32_t*>(p.inc_node.ptr), static_cast<uint64_t*>(p.tiles.ptr), ctx->d_flags, s);
+  if (n <= kIncBucketMaxNodes) {
+    if ((rc = ensure(ctx, ctx->inc_ws, incidence_ws_bytes(n, I1 - I0), false, s))) return rc;
+    incidence_segment_bucketed(n, m0, m1, I1 - I0, I1, off, static_cast<const uint32_t*>(p.nodes.ptr), j == 0, deg_cur,
+                               static_cast<uint32_t*>(p.sdeg.ptr), static_cast<uint64_t*>(p.seg_off.ptr) + size_t(j) * (n + 1),
+                               static_cast<uint64_t*>(p.cursor.ptr), static_cast<uint32_t*>(p.inc.ptr),
+                               static_cast<uint32_t*>(p.inc_node.ptr), ctx->inc_ws.ptr, ctx->d_flags, s);
+  } else {
+    incidence_segment(n, m0, m1, I1 - I0, I1, off, static_cast<const uint32_t*>(p.nodes.ptr), j == 0, deg_cur,
+                      static_cast<uint32_t*>(p.sdeg.ptr), static_cast<uint64_t*>(p.seg_off.ptr) + size_t(j) * (n + 1),
+                      static_cast<uint64_t*>(p.cursor.ptr), static_cast<uint32_t*>(p.inc.ptr),
+                      static_cast<uint32_t*>(p.inc_node.ptr), static_cast<uint64_t*>(p.tiles.ptr), ctx->d_flags, s);
+  }
   uint32_t* degj = static_cast<uint32_t*>(p.deg[j].ptr);
   hipLaunchKernelGGL(k_copy_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, deg_cur, degj, uint64_t(n));
   uint64_t* words = static_cast<uint64_t*>(p.words.ptr);

@@ -44,6 +44,7 @@ struct centra_ctx {
   centra::DevBuf scan_tmp;
   // incidence (node -> samples) and greedy / AMCERA workspaces
   centra::DevBuf deg, inc_off, inc_cursor, inc, inc_node, gain, covered, best, newcov, seg_deg;
+  centra::DevBuf inc_ws;              // workspace of the bucketed incidence build
   uint32_t inc_nseg = 0;              // incidence segments held in inc_off / inc / inc_node
   uint64_t inc_m0 = 0;                // first sample of the newest segment (0: it holds every sample)
   uint64_t inc_m1 = 0;                // samples the incidence covers
@@ -263,6 +264,16 @@ void incidence_segment(uint32_t n, uint64_t m0, uint64_t m1, uint64_t span_cap, 
                        const uint32_t* he_nodes, bool first_segment, uint32_t* deg, uint32_t* sdeg, uint64_t* off,
                        uint64_t* cur, uint32_t* inc, uint32_t* inc_node, uint64_t* scan_tiles, uint32_t* flags,
                        hipStream_t s);
+
+// Bucketed build of one incidence segment (incidence.hip): the arguments
+// and results of incidence_segment, with no global atomic per entry; ws
+// holds incidence_ws_bytes(n, span_cap) bytes.  For n <= kIncBucketMaxNodes.
+constexpr uint32_t kIncBucketMaxNodes = 4096u * 2048u;
+size_t incidence_ws_bytes(uint32_t n, uint64_t span_cap);
+void incidence_segment_bucketed(uint32_t n, uint64_t m0, uint64_t m1, uint64_t span_cap, uint64_t limit,
+                                const uint64_t* he_off, const uint32_t* he_nodes, bool first_segment, uint32_t* deg,
+                                uint32_t* sdeg, uint64_t* off, uint64_t* cur, uint32_t* inc, uint32_t* inc_node,
+                                void* ws, uint32_t* flags, hipStream_t s);
 
 // Top-k sums of many rows at once (mcera.hip): the sum of the k largest
 // positive values of each row, written to *out (as i64).
