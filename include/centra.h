@@ -625,8 +625,8 @@ CENTRA_API int centra_progressive_resumable(centra_ctx *ctx, const centra_graph 
  * one run with their largest k, as greedy's first k picks do not depend on
  * a larger k; one set of round launches serves every run, replayed from a
  * captured HIP graph unless CENTRA_ENGINE_NO_GRAPHS); runs their per-trial
- * top-k selections fused;
- * and evaluates every query's bound on the host (one synchronisation),
+ * top-k selections fused; and evaluates every query's bound on the host
+ * (one synchronisation),
  * retiring certified queries and those at m_max.  realtime != 0: query
  * arrival times are seconds from the start of the run, admission waits for
  * them (continuous batching: arrivals join the running queries at the next
@@ -641,6 +641,13 @@ CENTRA_API int centra_progressive_resumable(centra_ctx *ctx, const centra_graph 
  * keeps the fastest (CENTRA_ENGINE_NO_TUNE: 128); the environment variable
  * CENTRA_TUNE_CACHE may name a file that keeps the choice per workload;
  * centra_engine_log returns the tuner's report.  Synchronous.
+ * Level caches (unless CENTRA_ENGINE_NO_CACHE): the results of a level
+ * depend only on its samples, so the engine keeps, per level of a pool,
+ * the picks of a greedy run of the largest k submitted on the pool and the
+ * per-trial (and degree) top-k sums for every k up to it (one selection of
+ * each row's largest values, sorted and prefix-summed; up to k = 2,048),
+ * and a later query at that level takes them from there: the same results,
+ * without its own greedy run or selection.
  * Memory: a pool holds its samples, their incidence and per level j the
  * trial sums (n t 4 bytes) and deg_H; levels no queued or active query can
  * need are released (a later query on the pool rebuilds them).
@@ -650,6 +657,7 @@ CENTRA_API int centra_progressive_resumable(centra_ctx *ctx, const centra_graph 
 typedef struct centra_engine centra_engine;
 #define CENTRA_ENGINE_NO_GRAPHS 1u
 #define CENTRA_ENGINE_NO_TUNE 2u
+#define CENTRA_ENGINE_NO_CACHE 4u
 
 typedef struct {
     uint64_t seed;

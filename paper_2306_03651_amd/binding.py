@@ -136,6 +136,7 @@ class ExtendArgs(_c.Structure):
 
 CENTRA_ENGINE_NO_GRAPHS = 1
 CENTRA_ENGINE_NO_TUNE = 2
+CENTRA_ENGINE_NO_CACHE = 4
 
 
 # name -> (restype, argtypes); the names and order are those of centra.h

@@ -103,9 +103,28 @@ double now_s() {
 
 }  // namespace
 
+// Results of one level of a pool, kept for later queries at that level:
+// they depend only on the level's samples (functions of their indices), so
+// a query reuses them bit for bit.  Greedy: the picks of a run of gk rounds
+// (gnp < gk: it stopped early, so every larger k has the same picks).
+// Selection: for each trial row and the degree row, the sum of its i + 1
+// largest positive values for every i < sK (ssat: every row has fewer than
+// sK positive values, so any k takes them all).
+struct LevelCache {
+  uint32_t gk = 0, gnp = 0;
+  std::vector<uint32_t> picks;
+  std::vector<uint64_t> cov;
+  uint32_t sK = 0, st = 0;
+  bool ssat = false;
+  std::vector<int64_t> topk;   // [trial][i], st x sK
+  std::vector<int64_t> dk;     // [i], sK
+};
+
 struct EnginePool {
   const centra_graph* g = nullptr;
   centra_pool_params p{};
+  uint32_t k_hint = 0;                 // the largest k submitted on the pool
+  std::vector<LevelCache> cache;       // per level
   std::vector<uint64_t> level_m;   // the schedule m_0 < m_1 < ... <= m_max
   uint32_t levels_built = 0;
   uint64_t m_have = 0, I_have = 0;
@@ -590,8 +609,14 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
   // Greedy is prefix-consistent in k (its first k picks are the picks of
   // any larger k on the same sample, with the same cumulative coverage), so
   // the queries at one level of one pool share a single greedy run with the
-  // largest of their k; queries that also share k share their selection
-  // rows (the largest of their t, each query summing its first t trials).
+  // largest of their k.  With the level caches (the default), a run takes
+  // the largest k submitted on the pool, its picks are kept, and so are,
+  // for every k up to that size, the per-trial top-k sums of the level
+  // (one selection per level, prefix sums of each row's sorted largest
+  // values): a later query at the level reuses both.  Without them, queries
+  // that share k share their selection rows (the largest of their t, each
+  // query summing its first t trials).
+  const bool cached = !(e->flags & CENTRA_ENGINE_NO_CACHE);
   struct GGroup {
     uint32_t pool, level, k;
     ResLayout lay;
@@ -602,36 +627,69 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
   };
   std::vector<GGroup> gg;
   std::vector<SGroup> sg;
-  std::vector<uint32_t> q_gg(act.size()), q_sg(act.size());
+  std::vector<uint32_t> q_gg(act.size(), ~0u), q_sg(act.size(), ~0u);
+  uint32_t K_sel = 0;   // cached selections: the prefix length of this tick
   {
     std::map<std::pair<uint32_t, uint32_t>, uint32_t> gmap;
     std::map<std::tuple<uint32_t, uint32_t, uint32_t>, uint32_t> smap;
     for (size_t a = 0; a < act.size(); ++a) {
       const EngineQuery& q = e->queries[act[a]];
-      auto gk = std::make_pair(q.pool, q.level);
-      auto git = gmap.find(gk);
-      if (git == gmap.end()) {
-        git = gmap.emplace(gk, static_cast<uint32_t>(gg.size())).first;
-        gg.push_back(GGroup{q.pool, q.level, 0, {}});
+      EnginePool& p = e->pools[q.pool];
+      if (p.cache.size() < p.level_m.size()) p.cache.resize(p.level_m.size());
+      const LevelCache& C = p.cache[q.level];
+      const bool g_hit = cached && C.gk && (C.gk >= q.k || C.gnp < C.gk);
+      const bool s_hit = cached && C.sK && C.st >= q.t && (q.k <= C.sK || C.ssat);
+      if (!g_hit) {
+        auto gk = std::make_pair(q.pool, q.level);
+        auto git = gmap.find(gk);
+        if (git == gmap.end()) {
+          git = gmap.emplace(gk, static_cast<uint32_t>(gg.size())).first;
+          gg.push_back(GGroup{q.pool, q.level, 0, {}});
+        }
+        gg[git->second].k = std::max(gg[git->second].k, cached ? std::max(q.k, p.k_hint) : q.k);
+        q_gg[a] = git->second;
       }
-      gg[git->second].k = std::max(gg[git->second].k, q.k);
-      q_gg[a] = git->second;
+      if (!s_hit) {
+        const uint32_t kk = cached ? 0u : q.k;
+        auto sk = std::make_tuple(q.pool, q.level, kk);
+        auto sit = smap.find(sk);
+        if (sit == smap.end()) {
+          sit = smap.emplace(sk, static_cast<uint32_t>(sg.size())).first;
+          sg.push_back(SGroup{q.pool, q.level, kk, 0, 0, 0});
+        }
+        SGroup& S = sg[sit->second];
+        S.t = cached ? p.p.t : std::max(S.t, q.t);
+        if (cached) K_sel = std::max(K_sel, std::max(q.k, p.k_hint));
+        q_sg[a] = sit->second;
+      }
+    }
+  }
+  // a prefix longer than the sort can hold: this tick's selections by
+  // exact k (not kept)
+  const bool sel_prefix = cached && K_sel <= kSelPrefixMax;
+  if (cached && !sel_prefix) {
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, uint32_t> smap;
+    std::vector<SGroup> sg2;
+    for (size_t a = 0; a < act.size(); ++a) {
+      if (q_sg[a] == ~0u) continue;
+      const EngineQuery& q = e->queries[act[a]];
       auto sk = std::make_tuple(q.pool, q.level, q.k);
       auto sit = smap.find(sk);
       if (sit == smap.end()) {
-        sit = smap.emplace(sk, static_cast<uint32_t>(sg.size())).first;
-        sg.push_back(SGroup{q.pool, q.level, q.k, 0, 0, 0});
+        sit = smap.emplace(sk, static_cast<uint32_t>(sg2.size())).first;
+        sg2.push_back(SGroup{q.pool, q.level, q.k, 0, 0, 0});
       }
-      sg[sit->second].t = std::max(sg[sit->second].t, q.t);
+      sg2[sit->second].t = std::max(sg2[sit->second].t, q.t);
       q_sg[a] = sit->second;
     }
+    sg.swap(sg2);
   }
   uint32_t cap_q = 1;
   while (cap_q < gg.size()) cap_q <<= 1;
   std::vector<GreedyDesc> gd(cap_q);
   memset(gd.data(), 0, gd.size() * sizeof(GreedyDesc));
   size_t res_bytes = 0;
-  uint32_t max_n = 0, kmax = 0, n_rows = 0;
+  uint32_t max_n = 0, kmax = 0, n_rows = 0, max_n_sel = 0;
   uint64_t max_m = 0;
   for (GGroup& G : gg) {
     G.lay = res_layout(res_bytes, G.k, 0);
@@ -642,15 +700,24 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
     max_m = std::max(max_m, p.level_m[G.level]);
   }
   for (SGroup& S : sg) {
-    S.topk = res_bytes;
-    S.dk = res_bytes + size_t(S.t) * 8;
-    res_bytes = S.dk + 8;
+    if (sel_prefix) {
+      S.k = K_sel;
+      S.topk = res_bytes;
+      S.dk = res_bytes + size_t(S.t) * K_sel * 8;
+      res_bytes = S.dk + size_t(K_sel) * 8;
+    } else {
+      S.topk = res_bytes;
+      S.dk = res_bytes + size_t(S.t) * 8;
+      res_bytes = S.dk + 8;
+    }
     n_rows += S.t + 1;
+    max_n_sel = std::max(max_n_sel, e->pools[S.pool].g->n);
   }
+  const size_t sel_bytes = sel_prefix ? select_prefix_ws_bytes(n_rows, K_sel) : select_ws_bytes(n_rows);
   if ((rc = ensure(ctx, e->tick_res, res_bytes + 256, false, s))) return rc;
   if ((rc = ensure(ctx, e->descs, size_t(cap_q) * sizeof(GreedyDesc), false, s))) return rc;
-  if ((rc = ensure(ctx, e->rows, size_t(n_rows) * sizeof(SelRow), false, s))) return rc;
-  if ((rc = ensure(ctx, e->sel_ws, select_ws_bytes(n_rows), false, s))) return rc;
+  if ((rc = ensure(ctx, e->rows, size_t(n_rows ? n_rows : 1) * sizeof(SelRow), false, s))) return rc;
+  if ((rc = ensure(ctx, e->sel_ws, sel_bytes, false, s))) return rc;
   if ((rc = ensure(ctx, e->round_base, 256, false, s))) return rc;
   if (e->ws.size() < gg.size()) e->ws.resize(gg.size());
   char* res = static_cast<char*>(e->tick_res.ptr);
@@ -693,36 +760,44 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
     const uint32_t n = p.g->n;
     const int32_t* R = static_cast<const int32_t*>(p.R[S.level].ptr);
     for (uint32_t r = 0; r < S.t; ++r)
-      rows.push_back(SelRow{R + size_t(r) * n, n, S.k, reinterpret_cast<int64_t*>(res + S.topk) + r});
+      rows.push_back(SelRow{R + size_t(r) * n, n, S.k, sel_prefix ? nullptr : reinterpret_cast<int64_t*>(res + S.topk) + r});
     rows.push_back(SelRow{static_cast<const int32_t*>(p.deg[S.level].ptr), n, S.k,
-                          reinterpret_cast<int64_t*>(res + S.dk)});
+                          sel_prefix ? nullptr : reinterpret_cast<int64_t*>(res + S.dk)});
   }
   e->st.greedy_runs += gg.size();
   GreedyDesc* dd = static_cast<GreedyDesc*>(e->descs.ptr);
   SelRow* dr = static_cast<SelRow*>(e->rows.ptr);
-  CENTRA_HIP(ctx, hipMemcpyAsync(dd, gd.data(), gd.size() * sizeof(GreedyDesc), hipMemcpyHostToDevice, s));
-  CENTRA_HIP(ctx, hipMemcpyAsync(dr, rows.data(), rows.size() * sizeof(SelRow), hipMemcpyHostToDevice, s));
+  if (!gg.empty()) CENTRA_HIP(ctx, hipMemcpyAsync(dd, gd.data(), gd.size() * sizeof(GreedyDesc), hipMemcpyHostToDevice, s));
+  if (n_rows) CENTRA_HIP(ctx, hipMemcpyAsync(dr, rows.data(), rows.size() * sizeof(SelRow), hipMemcpyHostToDevice, s));
   hipEvent_t* ev = ctx->ev;
   CENTRA_HIP(ctx, hipEventRecord(ev[4], s));
-  greedy_multi_init(dd, cap_q, max_n, s);
-  // cover parts per run: enough for the longest incidence row a run can
-  // meet (at most its sample size) at 256 entries each, at most 256 (a
-  // part then walks its share of the row in strides)
-  uint32_t gc = static_cast<uint32_t>(std::min<uint64_t>(256, (max_m + 255) / 256));
-  gc = std::max<uint32_t>(gc, 16);
-  uint32_t gcp = 16;
-  while (gcp < gc) gcp <<= 1;   // a few graph shapes only
-  // the captured graphs are keyed by the argmax shape: round max_n up
-  uint32_t max_n_key = 4096;
-  while (max_n_key < max_n) max_n_key <<= 1;
-  if ((rc = greedy_rounds(e, cap_q, max_n_key, gcp, kmax, s))) return rc;
-  greedy_multi_finish(dd, cap_q, s);
+  if (!gg.empty()) {
+    greedy_multi_init(dd, cap_q, max_n, s);
+    // cover parts per run: enough for the longest incidence row a run can
+    // meet (at most its sample size) at 256 entries each, at most 256 (a
+    // part then walks its share of the row in strides)
+    uint32_t gc = static_cast<uint32_t>(std::min<uint64_t>(256, (max_m + 255) / 256));
+    gc = std::max<uint32_t>(gc, 16);
+    uint32_t gcp = 16;
+    while (gcp < gc) gcp <<= 1;   // a few graph shapes only
+    // the captured graphs are keyed by the argmax shape: round max_n up
+    uint32_t max_n_key = 4096;
+    while (max_n_key < max_n) max_n_key <<= 1;
+    if ((rc = greedy_rounds(e, cap_q, max_n_key, gcp, kmax, s))) return rc;
+    greedy_multi_finish(dd, cap_q, s);
+  }
   CENTRA_HIP(ctx, hipEventRecord(ev[5], s));
-  select_topk_rows(dr, n_rows, max_n, e->sel_ws.ptr, s);
+  if (n_rows) {
+    if (sel_prefix)
+      select_prefix_rows(dr, n_rows, max_n_sel, K_sel, e->sel_ws.ptr,
+                         reinterpret_cast<int64_t*>(res + (sg.empty() ? 0 : sg[0].topk)), s);
+    else
+      select_topk_rows(dr, n_rows, max_n_sel, e->sel_ws.ptr, s);
+  }
   CENTRA_HIP(ctx, hipGetLastError());
   CENTRA_HIP(ctx, hipEventRecord(ev[6], s));
   std::string host(res_bytes, '\0');
-  CENTRA_HIP(ctx, hipMemcpyAsync(&host[0], res, res_bytes, hipMemcpyDeviceToHost, s));
+  if (res_bytes) CENTRA_HIP(ctx, hipMemcpyAsync(&host[0], res, res_bytes, hipMemcpyDeviceToHost, s));
   CENTRA_HIP(ctx, hipStreamSynchronize(s));
   if ((rc = check_flags(ctx, s, "engine tick"))) return rc;
   float ms_g = 0.f, ms_s = 0.f;
@@ -730,34 +805,84 @@ static int tick(centra_engine* e, double now, bool* progress, hipStream_t s) {
   (void)hipEventElapsedTime(&ms_s, ev[5], ev[6]);
   e->st.ms_greedy += ms_g;
   e->st.ms_select += ms_s;
+  const char* hb = host.data();
+  // keep this tick's results in the level caches
+  if (cached) {
+    for (const GGroup& G : gg) {
+      LevelCache& C = e->pools[G.pool].cache[G.level];
+      uint32_t np = 0;
+      memcpy(&np, hb + G.lay.np, 4);
+      C.gk = G.k;
+      C.gnp = np;
+      C.picks.assign(np, 0);
+      C.cov.assign(np, 0);
+      memcpy(C.picks.data(), hb + G.lay.picks, size_t(np) * 4);
+      memcpy(C.cov.data(), hb + G.lay.cov, size_t(np) * 8);
+    }
+    if (sel_prefix) {
+      for (const SGroup& S : sg) {
+        LevelCache& C = e->pools[S.pool].cache[S.level];
+        C.sK = K_sel;
+        C.st = S.t;
+        C.topk.assign(size_t(S.t) * K_sel, 0);
+        C.dk.assign(K_sel, 0);
+        memcpy(C.topk.data(), hb + S.topk, C.topk.size() * 8);
+        memcpy(C.dk.data(), hb + S.dk, C.dk.size() * 8);
+        bool sat = true;   // every row flat at its end: fewer than K_sel positive values
+        for (uint32_t r = 0; r <= S.t && sat; ++r) {
+          const int64_t* row = r < S.t ? C.topk.data() + size_t(r) * K_sel : C.dk.data();
+          sat = K_sel >= 2 ? row[K_sel - 1] == row[K_sel - 2] : row[0] == 0;
+        }
+        C.ssat = sat;
+      }
+    }
+  }
   // 5. bounds on the host
   const double t_done = now_s() - e->run_t0;
-  const char* hb = host.data();
   for (size_t a = 0; a < act.size(); ++a) {
     EngineQuery& q = e->queries[act[a]];
     EnginePool& p = e->pools[q.pool];
     const uint32_t j = q.level;
-    const GGroup& G = gg[q_gg[a]];
-    const SGroup& S = sg[q_sg[a]];
+    static const LevelCache kNone;
+    const LevelCache& C = cached ? p.cache[j] : kNone;
     uint32_t np = 0;
-    memcpy(&np, hb + G.lay.np, 4);
-    if (np > q.k) np = q.k;   // the first k picks of the shared run
     uint64_t cov = 0;
-    if (np) memcpy(&cov, hb + G.lay.cov + size_t(np - 1) * 8, 8);
-    int64_t sum = 0;
-    for (uint32_t r = 0; r < q.t; ++r) {
-      int64_t x;
-      memcpy(&x, hb + S.topk + size_t(r) * 8, 8);
-      sum += x;
+    const uint32_t* picks_src = nullptr;
+    if (cached) {   // greedy from the cache (filled above when it missed)
+      np = std::min(C.gnp, q.k);
+      if (np) cov = C.cov[np - 1];
+      picks_src = C.picks.data();
+    } else {
+      const GGroup& G = gg[q_gg[a]];
+      memcpy(&np, hb + G.lay.np, 4);
+      if (np > q.k) np = q.k;   // the first k picks of the shared run
+      if (np) memcpy(&cov, hb + G.lay.cov + size_t(np - 1) * 8, 8);
+      picks_src = reinterpret_cast<const uint32_t*>(hb + G.lay.picks);
     }
-    int64_t dk = 0;
-    memcpy(&dk, hb + S.dk, 8);
+    int64_t sum = 0, dk = 0;
+    if (cached && q_sg[a] == ~0u) {   // selection from the cache
+      const uint32_t i = std::min(q.k, C.sK) - 1;
+      for (uint32_t r = 0; r < q.t; ++r) sum += C.topk[size_t(r) * C.sK + i];
+      dk = C.dk[i];
+    } else if (sel_prefix) {   // kept above; read from the cache
+      const uint32_t i = std::min(q.k, C.sK) - 1;
+      for (uint32_t r = 0; r < q.t; ++r) sum += C.topk[size_t(r) * C.sK + i];
+      dk = C.dk[i];
+    } else {
+      const SGroup& S = sg[q_sg[a]];
+      for (uint32_t r = 0; r < q.t; ++r) {
+        int64_t x;
+        memcpy(&x, hb + S.topk + size_t(r) * 8, 8);
+        sum += x;
+      }
+      memcpy(&dk, hb + S.dk, 8);
+    }
     const uint64_t m = p.level_m[j];
     const double delta_i = ldexp(q.delta, -static_cast<int>(j + 1));
     centra_bound_out o;
     bound_eval(m, cov, sum, q.t, static_cast<uint64_t>(dk), p.bmax_host[j], q.eps, delta_i, &o);
     q.picks.assign(q.k, 0);
-    memcpy(q.picks.data(), hb + G.lay.picks, size_t(np) * 4);
+    memcpy(q.picks.data(), picks_src, size_t(np) * 4);
     centra_result& r = q.res;
     r.n_picked = np;
     r.iterations = j + 1;
@@ -918,6 +1043,7 @@ int centra_engine_submit(centra_engine* e, uint32_t pool_id, uint32_t k, uint32_
   q.arrival = arrival_s;
   e->queries.push_back(std::move(q));
   e->pools[pool_id].queued += 1;
+  e->pools[pool_id].k_hint = std::max(e->pools[pool_id].k_hint, k);
   *query_id = static_cast<uint32_t>(e->queries.size() - 1);
   return CENTRA_OK;
 }

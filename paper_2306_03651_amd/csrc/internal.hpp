@@ -284,6 +284,12 @@ struct SelRow {
 };
 size_t select_ws_bytes(uint32_t n_rows);
 void select_topk_rows(const SelRow* rows, uint32_t n_rows, uint32_t max_n, void* ws, hipStream_t s);
+// Sums of the k largest positive values of every row for every k <= K
+// (rows[r].k must be K, K <= kSelPrefixMax): out[r * K + k - 1].
+constexpr uint32_t kSelPrefixMax = 2048;
+size_t select_prefix_ws_bytes(uint32_t n_rows, uint32_t K);
+void select_prefix_rows(const SelRow* rows, uint32_t n_rows, uint32_t max_n, uint32_t K, void* ws, int64_t* out,
+                        hipStream_t s);
 // Launch-only AMCERA steps (mcera.hip).
 void rade_words_launch(uint64_t seed, uint32_t instance, uint64_t s0, uint64_t s1, uint32_t t, uint64_t* words,
                        hipStream_t s);

@@ -155,9 +155,13 @@ constexpr int kDigitPasses = (30 + kDigitBits - 1) / kDigitBits;   // bits below
 // Selection state of one row: the values still sought have bit length blen
 // and their top pbits bits equal prefix; need of them are still to be taken
 // and acc holds the sum of the values already taken.
+// When done, the row's k largest are its values above tau and `ties`
+// copies of tau (tau = 0, ties = 0: all of its positive values, fewer than
+// k).
 struct SelState {
-  uint32_t prefix, pbits, blen, need, done, pad;
+  uint32_t prefix, pbits, blen, need, done, ties;
   int64_t acc;
+  uint32_t tau, pad;
 };
 
 __global__ void k_sel_init(SelState* st, const SelRow* rows, uint32_t n_rows, uint32_t* hcnt, uint64_t* hsum) {
@@ -167,7 +171,7 @@ __global__ void k_sel_init(SelState* st, const SelRow* rows, uint32_t n_rows, ui
     hsum[i] = 0;
     if (i < n_rows) {
       const uint32_t k = rows[i].k;
-      st[i] = SelState{1, 1, 0, k, k == 0 ? 1u : 0u, 0, 0};
+      st[i] = SelState{1, 1, 0, k, k == 0 ? 1u : 0u, 0, 0, 0, 0};
     }
   }
 }
@@ -254,6 +258,8 @@ __global__ __launch_bounds__(kWave) void k_sel_decide(SelState* st, int first, u
     if (lane == kWave - 1) {
       s.acc += static_cast<int64_t>(s_incl);
       s.done = 1;
+      s.tau = 0;
+      s.ties = 0;
       st[r] = s;
     }
   } else if (lane == __ffsll(static_cast<unsigned long long>(f)) - 1) {
@@ -281,6 +287,8 @@ __global__ __launch_bounds__(kWave) void k_sel_decide(SelState* st, int first, u
     s.acc = acc;
     if (s.pbits >= s.blen) {   // every bit fixed: the remaining copies of prefix
       s.acc += static_cast<int64_t>(s.need) * static_cast<int64_t>(s.prefix);
+      s.tau = s.prefix;
+      s.ties = s.need;
       s.done = 1;
     }
     st[r] = s;
@@ -339,6 +347,100 @@ void select_topk_rows(const SelRow* rows, uint32_t n_rows, uint32_t max_n, void*
     hipLaunchKernelGGL(k_sel_decide, dim3(n_rows), dim3(kWave), 0, s, st, pass == 0 ? 1 : 0, hcnt, hsum);
   }
   hipLaunchKernelGGL(k_sel_out, dim3(grid_for(n_rows, 256, 64)), dim3(256), 0, s, st, rows, n_rows);
+}
+
+// Top-k sums of every row for every k <= K at once: after the selection
+// at K, the row's values above its threshold are gathered (at most K of
+// them), sorted in LDS together with the threshold's copies, and
+// prefix-summed: out[r * K + i] = the sum of the i + 1 largest positive
+// values (flat once they run out).
+constexpr uint32_t kPrefixMax = 2048;
+
+__global__ __launch_bounds__(kSelBlock) void k_sel_gather(const SelRow* rows, const SelState* st, uint32_t K,
+                                                          uint32_t* gcount, int32_t* buf) {
+  const uint32_t r = blockIdx.y;
+  const SelRow d = rows[r];
+  const uint32_t tau = st[r].tau;
+  const uint64_t chunk = (uint64_t(d.n) + gridDim.x - 1) / gridDim.x;
+  const uint64_t i0 = uint64_t(blockIdx.x) * chunk;
+  const uint64_t i1 = i0 + chunk < d.n ? i0 + chunk : d.n;
+  for (uint64_t i = i0 + threadIdx.x; i < i1; i += kSelBlock) {
+    const int32_t x = d.vals[i];
+    if (x <= 0 || static_cast<uint32_t>(x) <= tau) continue;
+    const uint32_t at = atomicAdd(&gcount[r], 1u);
+    if (at < K) buf[size_t(r) * K + at] = x;
+  }
+}
+
+__global__ __launch_bounds__(kSelBlock) void k_sel_prefix(const SelState* st, const uint32_t* gcount,
+                                                          const int32_t* buf, uint32_t K, uint32_t Kpad,
+                                                          int64_t* out) {
+  __shared__ int32_t v[kPrefixMax];
+  __shared__ int64_t wsum[kSelBlock / kWave];
+  const uint32_t r = blockIdx.x;
+  const SelState s = st[r];
+  const uint32_t g = gcount[r] < K ? gcount[r] : K;
+  for (uint32_t i = threadIdx.x; i < Kpad; i += kSelBlock) {
+    int32_t x = 0;
+    if (i < g)
+      x = buf[size_t(r) * K + i];
+    else if (i < g + s.ties && i < K)
+      x = static_cast<int32_t>(s.tau);
+    v[i] = x;
+  }
+  __syncthreads();
+  // bitonic sort, descending
+  for (uint32_t size = 2; size <= Kpad; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < Kpad; i += kSelBlock) {
+        const uint32_t j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;
+          const int32_t a = v[i], b = v[j];
+          if (desc ? a < b : a > b) {
+            v[i] = b;
+            v[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // prefix sums: each thread sums Kpad / kSelBlock consecutive entries
+  const uint32_t per = Kpad / kSelBlock ? Kpad / kSelBlock : 1u;
+  const uint32_t b0 = threadIdx.x * per;
+  int64_t loc = 0;
+  for (uint32_t i = b0; i < b0 + per && i < Kpad; ++i) loc += v[i];
+  const int64_t incl = static_cast<int64_t>(wave_incl_scan_u64(static_cast<uint64_t>(loc)));
+  if (lane_id() == kWave - 1) wsum[threadIdx.x / kWave] = incl;
+  __syncthreads();
+  int64_t run = incl - loc;
+  for (uint32_t w = 0; w < threadIdx.x / kWave; ++w) run += wsum[w];
+  for (uint32_t i = b0; i < b0 + per && i < Kpad; ++i) {
+    run += v[i];
+    if (i < K) out[size_t(r) * K + i] = run;
+  }
+}
+
+size_t select_prefix_ws_bytes(uint32_t n_rows, uint32_t K) {
+  return select_ws_bytes(n_rows) + size_t(n_rows) * 4 + size_t(n_rows) * K * 4 + 256;
+}
+
+void select_prefix_rows(const SelRow* rows, uint32_t n_rows, uint32_t max_n, uint32_t K, void* ws, int64_t* out,
+                        hipStream_t s) {
+  select_topk_rows(rows, n_rows, max_n, ws, s);
+  const SelState* st = static_cast<const SelState*>(ws);
+  uint32_t* gcount = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + select_ws_bytes(n_rows));
+  int32_t* buf = reinterpret_cast<int32_t*>(gcount + n_rows);
+  fill_u32(gcount, 0, n_rows, s);
+  uint32_t parts = 2048 / n_rows ? 2048 / n_rows : 1u;
+  const uint32_t max_parts = (max_n + 4095) / 4096 ? (max_n + 4095) / 4096 : 1u;
+  if (parts > max_parts) parts = max_parts;
+  hipLaunchKernelGGL(k_sel_gather, dim3(parts, n_rows), dim3(kSelBlock), 0, s, rows, st, K, gcount, buf);
+  uint32_t Kpad = kSelBlock;
+  while (Kpad < K) Kpad <<= 1;
+  hipLaunchKernelGGL(k_sel_prefix, dim3(n_rows), dim3(kSelBlock), 0, s, st, static_cast<const uint32_t*>(gcount),
+                     static_cast<const int32_t*>(buf), K, Kpad, out);
 }
 
 // Launch-only steps of the AMCERA for callers that own their buffers.

@@ -219,3 +219,42 @@ def test_engine_argument_errors(ctx):
     finally:
         eng.destroy()
         dg.release()
+
+
+def test_level_caches_are_exact(ctx):
+    # many queries on two pools with mixed k (up to past the prefix sort's
+    # 2,048: those ticks select by exact k), t and eps: the cached run
+    # (greedy picks and top-k prefix sums kept per level) equals the run
+    # without caches and each query alone, with fewer greedy runs
+    gs = [inputs.ba_graph(2500, 4, 51), inputs.grid_graph(24)]
+    dgs = [binding.DeviceGraph(ctx, g) for g in gs]
+    pools = [(3, 0, 24, 2000, 32000), (3, 1, 24, 1000, 8000)]
+    rng = np.random.default_rng(8)
+    qs = [(int(rng.integers(2)), int(rng.choice([3, 17, 60, 250])), int(rng.choice([8, 24])),
+           float(rng.choice([0.1, 0.05, 0.02]))) for _ in range(14)]
+    qs.append((0, 2100, 24, 0.05))
+    try:
+        out = {}
+        for flags in (binding.CENTRA_ENGINE_NO_TUNE, binding.CENTRA_ENGINE_NO_TUNE | binding.CENTRA_ENGINE_NO_CACHE):
+            eng = binding.Engine(ctx, 0, flags)
+            try:
+                pids = [eng.add_pool(dg.handle, *p) for dg, p in zip(dgs, pools)]
+                # two runs: the second one's queries meet the levels the
+                # first one computed (the caches are kept across runs)
+                qids = [eng.submit(pids[p], k, t, eps, 0.1) for p, k, t, eps in qs[:8]]
+                eng.run()
+                qids += [eng.submit(pids[p], k, t, eps, 0.1) for p, k, t, eps in qs[8:]]
+                eng.run()
+                out[flags] = ([eng.result(q) for q in qids], eng.stats())
+            finally:
+                eng.destroy()
+        (with_c, st_c), (without, st_n) = out.values()
+        say(f"engine caches: greedy runs {st_c.greedy_runs} cached, {st_n.greedy_runs} without")
+        for a, b in zip(with_c, without):
+            same(a, b)
+        assert st_c.greedy_runs < st_n.greedy_runs
+        for (p, k, t, eps), got in list(zip(qs, with_c))[:4] + [(qs[-1], with_c[-1])]:
+            same(got, standalone(ctx, dgs[p], pools[p], (k, t, eps, 0.1)))
+    finally:
+        for dg in dgs:
+            dg.release()
