@@ -314,7 +314,7 @@ struct CoverShared {
   uint64_t red[kCoverBlock / kWave];
   uint64_t seg_beg[kMaxSegments], seg_pre[kMaxSegments + 1];
   uint32_t scan[kCoverBlock / kWave + 1];
-  uint32_t hs[kCoverBlock];    // newly covered samples of this step
+  uint64_t hbeg[kCoverBlock];  // he_off of the step's newly covered samples
   uint32_t hoff[kCoverBlock];  // exclusive prefix of their hyperedge sizes
 };
 
@@ -359,22 +359,25 @@ __device__ __forceinline__ void cover_walk(uint32_t u, const uint64_t* seg_off, 
   const uint64_t stride = uint64_t(nb) * kCoverBlock;
   for (uint64_t base = lead; base < row; base += stride) {   // uniform trip count
     const uint64_t q = base + threadIdx.x;
-    uint32_t s = kUnseen, len = 0;
+    uint32_t len = 0;
+    uint64_t h0 = 0;
     if (q < row) {
       while (q >= sh.seg_pre[g + 1]) ++g;
-      s = inc[sh.seg_beg[g] + (q - sh.seg_pre[g])];
+      const uint32_t s = inc[sh.seg_beg[g] + (q - sh.seg_pre[g])];
+      // the hyperedge's bounds are loaded before the covering atomic
+      // returns, so the two round trips overlap
+      h0 = he_off[s];
+      const uint64_t h1 = he_off[s + 1];
       const uint32_t bit = 1u << (s & 31u);
       const uint32_t old = atomicOr(&covered[s >> 5], bit);
-      if (old & bit) {
-        s = kUnseen;
-      } else {
+      if (!(old & bit)) {   // newly covered
         ++cnt;
-        len = static_cast<uint32_t>(he_off[s + 1] - he_off[s]);
+        len = static_cast<uint32_t>(h1 - h0);
       }
     }
     uint32_t total;
     const uint32_t off = block_excl_scan_u32<kCoverBlock>(len, &total, sh.scan);
-    sh.hs[threadIdx.x] = s;
+    sh.hbeg[threadIdx.x] = h0;
     sh.hoff[threadIdx.x] = off;
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < total; e += kCoverBlock) {
@@ -388,7 +391,7 @@ __device__ __forceinline__ void cover_walk(uint32_t u, const uint64_t* seg_off, 
         else
           hi = mid - 1;
       }
-      const uint32_t v = he_nodes[he_off[sh.hs[lo]] + (e - sh.hoff[lo])];
+      const uint32_t v = he_nodes[sh.hbeg[lo] + (e - sh.hoff[lo])];
       if (v < n && !agg_add(sh.tab, v)) atomicSub(&gain[v], 1);
     }
     __syncthreads();
