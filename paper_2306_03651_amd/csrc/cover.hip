@@ -285,15 +285,44 @@ constexpr int kArgBlock = 256;
 
 constexpr unsigned kArgGrid = 512;   // workgroups of the argmax (and per-workgroup maxima)
 
+constexpr int kArgUnroll = 4;       // 4-node groups a thread loads at once
+
+__device__ __forceinline__ uint64_t gain_key(int32_t g, uint32_t u) {
+  return g > 0 ? (static_cast<uint64_t>(g) << 32) | (0xFFFFFFFFu - u) : 0ull;
+}
+
 // The largest key (gain << 32 | ~u, 0 if no positive gain) of the slice
-// of workgroup b of nb: nodes b*kArgBlock + i*nb*kArgBlock.
+// of workgroup b of nb: the 4-node groups b*kArgBlock + i*nb*kArgBlock
+// (gain is 16-byte aligned), kArgUnroll groups per thread loaded together
+// so that their round trips overlap; workgroup 0 also takes the n % 4
+// nodes past the last group.  The maximum of the keys does not depend on
+// how the nodes are split.
 __device__ __forceinline__ uint64_t argmax_slice(const int32_t* gain, uint32_t n, uint32_t b, uint32_t nb,
                                                  uint64_t* red) {
   uint64_t key = 0;
-  for (uint32_t u = b * kArgBlock + threadIdx.x; u < n; u += nb * kArgBlock) {
-    const int32_t g = gain[u];
-    const uint64_t k = g > 0 ? (static_cast<uint64_t>(g) << 32) | (0xFFFFFFFFu - u) : 0ull;
-    key = k > key ? k : key;
+  const uint32_t nv = n >> 2;
+  const int4* g4 = reinterpret_cast<const int4*>(gain);
+  const uint32_t stride = nb * kArgBlock;
+  for (uint32_t w = b * kArgBlock + threadIdx.x; w < nv; w += kArgUnroll * stride) {
+    int4 x[kArgUnroll];
+#pragma unroll
+    for (int j = 0; j < kArgUnroll; ++j) {
+      const uint32_t wj = w + j * stride;
+      x[j] = wj < nv ? g4[wj] : make_int4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < kArgUnroll; ++j) {
+      const uint32_t u = (w + j * stride) * 4;   // groups past nv hold zeros: key 0
+      uint64_t k = gain_key(x[j].x, u);
+      k = max(k, gain_key(x[j].y, u + 1));
+      k = max(k, gain_key(x[j].z, u + 2));
+      k = max(k, gain_key(x[j].w, u + 3));
+      key = max(key, k);
+    }
+  }
+  if (b == 0 && threadIdx.x < (n & 3u)) {
+    const uint32_t u = (nv << 2) + threadIdx.x;
+    key = max(key, gain_key(gain[u], u));
   }
   return block_max_u64<kArgBlock>(key, red);
 }
@@ -410,9 +439,10 @@ __device__ __forceinline__ void cover_pass(const uint64_t* part, uint32_t n_part
                                            uint32_t n_seg, const uint32_t* inc, const uint64_t* he_off,
                                            const uint32_t* he_nodes, uint32_t n, uint32_t* covered, int32_t* gain,
                                            uint64_t* newcov, uint32_t b, uint32_t nb, CoverShared& sh) {
-  uint64_t key = 0;
-  for (uint32_t i = threadIdx.x; i < n_part; i += kCoverBlock) key = part[i] > key ? part[i] : key;
-  key = block_max_u64<kCoverBlock>(key, sh.red);
+  static_assert(kArgGrid <= 2 * kCoverBlock, "two maxima per thread");
+  const uint64_t p0 = threadIdx.x < n_part ? part[threadIdx.x] : 0ull;
+  const uint64_t p1 = threadIdx.x + kCoverBlock < n_part ? part[threadIdx.x + kCoverBlock] : 0ull;
+  const uint64_t key = block_max_u64<kCoverBlock>(p0 > p1 ? p0 : p1, sh.red);
   if (b == 0 && threadIdx.x == 0) *best = key;
   if ((key >> 32) == 0) return;
   cover_walk(0xFFFFFFFFu - static_cast<uint32_t>(key), seg_off, n_seg, inc, he_off, he_nodes, n, covered, gain, newcov,
