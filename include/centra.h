@@ -637,8 +637,9 @@ CENTRA_API int centra_progressive_resumable(centra_ctx *ctx, const centra_graph 
  * plus a tenth); a pool's first samples are drawn when its first query
  * arrives.
  * Before the first tick an autotuner times the fused sampling launch with
- * 64, 128, 256 and 512 threads per BFS on the pools' first samples and
- * keeps the fastest (CENTRA_ENGINE_NO_TUNE: 128); the environment variable
+ * 128, 256 and 512 threads per BFS on the pools' first samples and keeps
+ * the fastest, unless it beats 128 by under 2% (CENTRA_ENGINE_NO_TUNE:
+ * 128; a cached choice may also be 64); the environment variable
  * CENTRA_TUNE_CACHE may name a file that keeps the choice per workload;
  * centra_engine_log returns the tuner's report.  Synchronous.
  * Level caches (unless CENTRA_ENGINE_NO_CACHE): the results of a level

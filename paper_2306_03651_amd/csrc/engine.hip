@@ -371,10 +371,15 @@ static int build_level(centra_engine* e, EnginePool& p, uint32_t j, hipStream_t 
 }
 
 // Autotuner: times the fused sampling launch of a probe batch (the first
-// samples of every pool) with each workgroup size and keeps the fastest.
-// The probe's samples are the pools' own, and every variant draws the same
-// hyperedges, so the choice changes no result.  CENTRA_TUNE_CACHE names a
-// file of "key block" lines that keeps choices across runs.
+// samples of every pool) with workgroups of 128, 256 and 512 threads, the
+// best of two timed launches after one that pays the slot set-up, and keeps
+// the fastest unless it beats the default 128 by under 2% (differences
+// within the probe's noise did not carry over to full launches).  64-thread
+// workgroups are not tried: they won short probes but lost full launches,
+// whose twice as many slots carry twice the slot state.  The probe's
+// samples are the pools' own, and every variant draws the same hyperedges,
+// so the choice changes no result.  CENTRA_TUNE_CACHE names a file of
+// "key block" lines that keeps choices across runs.
 static int autotune(centra_engine* e, hipStream_t s) {
   centra_ctx* ctx = e->ctx;
   char key[160];
@@ -404,24 +409,29 @@ static int autotune(centra_engine* e, hipStream_t s) {
     const uint64_t c = std::min<uint64_t>(p.level_m[0], std::max<uint64_t>(64, 16384 / e->pools.size()));
     probe.push_back(MultiSampleItem{p.g, p.p.seed, p.p.instance, 0, static_cast<uint32_t>(c)});
   }
-  const int blocks[] = {64, 128, 256, 512};
-  float best_ms = 0.f;
-  int best = 128;
+  const int blocks[] = {128, 256, 512};
+  constexpr int kDefaultBlock = 128;
+  float best_ms = 0.f, default_ms = 0.f;
+  int best = kDefaultBlock;
   std::string line = std::string("autotune: ") + key + ":";
   for (int b : blocks) {
     uint64_t total = 0;
     float ms = 0.f;
-    for (int rep = 0; rep < 2; ++rep) {   // the first run pays the slot set-up
+    for (int rep = 0; rep < 3; ++rep) {   // the first run pays the slot set-up
       int rc = sample_multi_to_stage(ctx, probe.data(), static_cast<uint32_t>(probe.size()), b, &total, s);
       if (rc) return rc;
-      if (hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]) != hipSuccess) ms = 0.f;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ctx->ev[6], ctx->ev[7]) != hipSuccess) t = 0.f;
+      if (rep == 1 || (rep > 1 && t < ms)) ms = t;
     }
     line += " " + std::to_string(b) + "=" + std::to_string(ms) + "ms";
+    if (b == kDefaultBlock) default_ms = ms;
     if (best_ms == 0.f || ms < best_ms) {
       best_ms = ms;
       best = b;
     }
   }
+  if (best != kDefaultBlock && default_ms > 0.f && best_ms > 0.98f * default_ms) best = kDefaultBlock;
   e->tuned_block = best;
   e->log += line + " -> block " + std::to_string(best) + "\n";
   if (cache)
