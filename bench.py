@@ -633,6 +633,7 @@ def main():
         # and sampler with the union bound in place of the AMCERA
         hedge = uncapped_run(W["growth"], 1, binding.CENTRA_SCHEDULE_GEOMETRIC, binding.CENTRA_METHOD_HEDGE_P)
         log(f"hedge-p: {hedge}")
+    ctx_log = binding.centra_context_log(ctx).strip()
     dg.release()
     binding.centra_destroy(ctx)
 
@@ -705,6 +706,7 @@ def main():
         "phase_ms": {"sample": round(res.ms_sample, 1), "cover": round(res.ms_cover, 1),
                      "mcera": round(res.ms_mcera, 1)},
         "roofline": roofline,
+        "slot_placement": ctx_log or None,
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "device": torch.cuda.get_device_name(0),

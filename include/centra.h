@@ -41,7 +41,7 @@ extern "C" {
 #define CENTRA_API
 #endif
 
-#define CENTRA_ABI_VERSION 10u
+#define CENTRA_ABI_VERSION 11u
 
 #define CENTRA_OK 0
 #define CENTRA_NOT_CERTIFIED 1
@@ -64,7 +64,15 @@ CENTRA_API uint32_t centra_abi_version(void);
  * many concurrent BFSs as the device runs, up to half of the device's
  * memory; with several contexts on one device, give each a budget.
  * Contexts are independent: different contexts may be used from different
- * host threads at the same time.  *out receives the context.  (Tests only:
+ * host threads at the same time.  *out receives the context.
+ * Placement: the sampler's speed depends on where the device allocator puts
+ * the pages of that per-BFS state (the same launch varies by up to ~18%
+ * from one allocation to the next, and not within one).  When a
+ * synchronous sampling call allocates at least 4 GiB of it, the context
+ * times a launch of the call's first 65,536 work items on each of up to
+ * four allocations, holding two at a time, and keeps the fastest; results
+ * do not depend on it.  The environment variable CENTRA_SLOT_SEARCH=0
+ * turns this off; centra_context_log reports the times.  (Tests only:
  * the environment variable CENTRA_STAMP_START sets the context's first BFS
  * stamp, to exercise the sampler's 32-bit stamp wrap.)
  * Errors: CENTRA_EINVAL (out == NULL), CENTRA_EHIP (no such device). */
@@ -77,6 +85,11 @@ CENTRA_API void centra_destroy(centra_ctx *ctx);
  * next call on ctx.  With ctx == NULL, the last error of a call without a
  * context (centra_create, centra_greedy_cover_noalloc) on this host thread. */
 CENTRA_API const char *centra_last_error(const centra_ctx *ctx);
+
+/* The context's log of one-time choices, one line each (the slot placement
+ * search: each allocation's probe time and the one kept); "" if none or if
+ * ctx == NULL.  Valid until the next call on ctx. */
+CENTRA_API const char *centra_context_log(const centra_ctx *ctx);
 
 /* ------------------------------------------------------------------ */
 /* Graph G = (V, E) of the problem statement (Algorithm 1 input; Sec. 3.1),

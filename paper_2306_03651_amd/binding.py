@@ -145,6 +145,7 @@ SIGNATURES = {
     "centra_create": (_c.c_int, [_c.c_int, _c.c_size_t, _c.POINTER(_vp)]),
     "centra_destroy": (None, [_vp]),
     "centra_last_error": (_c.c_char_p, [_vp]),
+    "centra_context_log": (_c.c_char_p, [_vp]),
     "centra_graph_prepare": (_c.c_int, [_vp, _c.POINTER(Csr), _c.c_uint32, _c.POINTER(_vp), _vp]),
     "centra_graph_release": (None, [_vp]),
     "centra_graph_info": (_c.c_int, [_vp, _c.POINTER(_c.c_uint32), _c.POINTER(_c.c_uint32)]),
@@ -261,6 +262,11 @@ def centra_destroy(ctx) -> None:
 
 def centra_last_error(ctx=None) -> str:
     s = lib().centra_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def centra_context_log(ctx) -> str:
+    s = lib().centra_context_log(ctx)
     return s.decode() if s else ""
 
 

@@ -132,6 +132,8 @@ extern "C" {
 
 uint32_t centra_abi_version(void) { return CENTRA_ABI_VERSION; }
 
+const char* centra_context_log(const centra_ctx* ctx) { return ctx ? ctx->log.c_str() : ""; }
+
 int centra_create(int hip_device, size_t hbm_budget_bytes, centra_ctx** out) {
   g_create_err.clear();
   if (!out) {

@@ -30,6 +30,7 @@ struct centra_ctx {
   // queue, stored pair counts), one set per concurrent BFS, sized for the
   // largest graph
   centra::DevBuf slot_rec, slot_q, slot_praw, slot_pinfo;
+  std::string log;   // one-time choices of the context (slot placement), one line each
   uint32_t slots = 0;
   uint32_t slot_n = 0;
   uint32_t stamp_next = 1;   // BFS stamp of the next sample (records start at stamp 0)

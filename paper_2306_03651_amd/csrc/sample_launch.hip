@@ -4,6 +4,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <string>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -72,7 +74,8 @@ static size_t slot_mem_cap() {
   return total_b / 2;
 }
 
-static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t s) {
+static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t s, bool* fresh) {
+  *fresh = false;
   const size_t cap_bytes = slot_mem_cap();
   {
     // never ask for more slots than the cap holds
@@ -112,6 +115,136 @@ static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->slots = slots;
   ctx->slot_n = n;
+  *fresh = true;
+  return CENTRA_OK;
+}
+
+// Placement of the slot state.  How fast the sampler runs on a given slot
+// state depends on where the allocator put its pages: the same launch on
+// BA 10^6 takes anywhere from 51 to 61 ms from one allocation to the next,
+// the same within one allocation to 0.5%, and unchanged when the graph is
+// uploaded again.  A short launch ranks allocations as the full one does,
+// so a fresh slot state of at least kPlaceMinBytes is chosen among
+// kPlaceCandidates allocations by timing the batch's first kPlaceProbe work
+// items on each (second of two launches; results discarded, stamps used up
+// as by any launch).  The search holds two slot states at a time and stops
+// early if the budget or the device cannot; CENTRA_SLOT_SEARCH=0 turns it
+// off.  It synchronises the stream, so stream-ordered launches skip it.
+constexpr int kPlaceCandidates = 4;
+constexpr uint32_t kPlaceProbe = 65536;
+constexpr size_t kPlaceMinBytes = size_t(4) << 30;
+
+static bool slot_search_enabled() {
+  const char* e = getenv("CENTRA_SLOT_SEARCH");
+  return !(e && !strcmp(e, "0"));
+}
+
+// Sets the per-launch fields of `a` for `count` work items on the current
+// slot state and staging area (stage_cap entries).
+static void launch_args(centra_ctx* ctx, SampleArgs& a, const SamplePlan& plan, uint32_t count, uint64_t stage_cap) {
+  a.stamp0 = ctx->stamp_next;
+  ctx->stamp_next += count;
+  a.count = count;
+  a.slot_stride = ctx->slot_n;
+  a.rec = static_cast<uint64_t*>(ctx->slot_rec.ptr);
+  a.q = static_cast<uint32_t*>(ctx->slot_q.ptr);
+  a.praw = static_cast<uint64_t*>(ctx->slot_praw.ptr);
+  a.pinfo = static_cast<uint32_t*>(ctx->slot_pinfo.ptr);
+  a.bit_words = plan.bit_words;
+  a.work = static_cast<uint32_t*>(ctx->work_ctr.ptr);
+  a.stage = static_cast<uint32_t*>(ctx->stage_nodes.ptr);
+  a.stage_cap = stage_cap;
+  a.stage_used = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 8);
+  a.stage_pos = static_cast<uint64_t*>(ctx->stage_pos.ptr);
+  a.he_len = static_cast<uint32_t*>(ctx->stage_len.ptr);
+  a.flags = ctx->d_flags;
+  a.stats = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 16);
+}
+
+// Stamps: a launch numbers its work items stamp_next, stamp_next + 1, ...;
+// before the first launch, and when 32 bits would run out, every record is
+// cleared and numbering restarts at 1 (the bidirectional sampler's records
+// carry the same stamps).
+static void reserve_stamps(centra_ctx* ctx, uint32_t count, hipStream_t s) {
+  if (ctx->stamp_next == 0 || uint64_t(ctx->stamp_next) + count > 0xFFFFFFFFull) {
+    fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(ctx->slots) * ctx->slot_n * 2, s);
+    if (ctx->bi_rec_f.ptr) {
+      fill_u64(static_cast<uint64_t*>(ctx->bi_rec_f.ptr), 0, size_t(ctx->bi_slots) * ctx->bi_n * 2, s);
+      fill_u64(static_cast<uint64_t*>(ctx->bi_rec_b.ptr), 0, size_t(ctx->bi_slots) * ctx->bi_n * 2, s);
+    }
+    ctx->stamp_next = 1;
+  }
+}
+
+// Times two launches of the first `count` work items on the current slot
+// state and returns the second's milliseconds in *ms.
+static int probe_slots(centra_ctx* ctx, SampleArgs a, const SamplePlan& plan, bool multi, uint32_t count,
+                       hipStream_t s, float* ms) {
+  for (int rep = 0; rep < 2; ++rep) {
+    reserve_stamps(ctx, count, s);
+    fill_u32(static_cast<uint32_t*>(ctx->work_ctr.ptr), 0, 1, s);
+    fill_u64(reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 8), 0, 3, s);
+    launch_args(ctx, a, plan, count, ctx->stage_nodes.bytes / 4);
+    const uint32_t grid = count < ctx->slots ? count : ctx->slots;
+    CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
+    sample_kernel_launch(a, plan.block, plan.lds_bits, multi, grid, plan.dyn_lds, s);
+    CENTRA_HIP(ctx, hipGetLastError());
+    CENTRA_HIP(ctx, hipEventRecord(ctx->ev[7], s));
+    CENTRA_HIP(ctx, hipStreamSynchronize(s));
+    int rc;
+    if ((rc = check_flags(ctx, s, "sample_paths (placement probe)"))) return rc;
+    if (hipEventElapsedTime(ms, ctx->ev[6], ctx->ev[7]) != hipSuccess) *ms = 0.f;
+  }
+  return CENTRA_OK;
+}
+
+// Chooses the fastest of kPlaceCandidates allocations of the (fresh) slot
+// records and queues, by probe_slots.
+static int place_slots(centra_ctx* ctx, const SampleArgs& a, const SamplePlan& plan, bool multi, uint32_t count,
+                       hipStream_t s) {
+  const size_t rec_b = ctx->slot_rec.bytes, q_b = ctx->slot_q.bytes;
+  if (rec_b + q_b < kPlaceMinBytes) return CENTRA_OK;
+  const uint32_t pc = count < kPlaceProbe ? count : kPlaceProbe;
+  // every slot state held during the search must stay consistent with the
+  // stamps: start numbering if nothing has been drawn yet, and skip the
+  // search if its launches would run the stamps out (a restart clears only
+  // the slot state in use)
+  reserve_stamps(ctx, 0, s);
+  if (uint64_t(ctx->stamp_next) + uint64_t(2 * kPlaceCandidates) * pc + count > 0xFFFFFFFFull) return CENTRA_OK;
+  float best = 0.f;
+  int rc;
+  if ((rc = probe_slots(ctx, a, plan, multi, pc, s, &best))) return rc;
+  std::string line = "slot placement: " + std::to_string(best);
+  for (int c = 1; c < kPlaceCandidates && best > 0.f; ++c) {
+    if (ctx->budget && ctx->allocated + rec_b + q_b > ctx->budget) break;
+    void *r2 = nullptr, *q2 = nullptr;
+    if (hipMalloc(&r2, rec_b) != hipSuccess) {
+      (void)hipGetLastError();
+      break;
+    }
+    if (hipMalloc(&q2, q_b) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(r2);
+      break;
+    }
+    fill_u64(static_cast<uint64_t*>(r2), 0, rec_b / 8, s);   // stamp 0: never claimed
+    std::swap(ctx->slot_rec.ptr, r2);
+    std::swap(ctx->slot_q.ptr, q2);
+    float ms = 0.f;
+    rc = probe_slots(ctx, a, plan, multi, pc, s, &ms);
+    line += " " + std::to_string(ms);
+    if (rc || !(ms > 0.f && ms < best)) {   // keep the previous one
+      std::swap(ctx->slot_rec.ptr, r2);
+      std::swap(ctx->slot_q.ptr, q2);
+    } else {
+      best = ms;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(r2);
+    (void)hipFree(q2);
+    if (rc) return rc;
+  }
+  ctx->log += line + " ms -> " + std::to_string(best) + " ms\n";
   return CENTRA_OK;
 }
 
@@ -128,11 +261,13 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
   *total = 0;
   const SamplePlan plan = plan_for(ctx, max_n, multi ? block : 0);
   uint32_t want = count < plan.resident ? count : plan.resident;
-  if ((rc = ensure_slots(ctx, max_n, want, s))) return rc;
+  bool fresh = false;
+  if ((rc = ensure_slots(ctx, max_n, want, s, &fresh))) return rc;
   const uint32_t grid = count < ctx->slots ? count : ctx->slots;
   if ((rc = ensure(ctx, ctx->stage_pos, size_t(count) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->stage_len, size_t(count) * 4 + 8 + 8 * (size_t(count) + 1), false, s))) return rc;
   if ((rc = ensure(ctx, ctx->work_ctr, 64, false, s))) return rc;
+  if (fresh && !async_cap && slot_search_enabled() && (rc = place_slots(ctx, a, plan, multi, count, s))) return rc;
   uint64_t cap = async_cap ? async_cap : size_t(count) * 8 + 1024;
   if (ctx->stage_nodes.bytes / 4 > cap) cap = ctx->stage_nodes.bytes / 4;
   for (int attempt = 0; attempt < 3; ++attempt) {
@@ -142,34 +277,8 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
     uint64_t* used = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 8);
     fill_u32(work, 0, 1, s);
     fill_u64(used, 0, 1, s);
-    // stamps: this launch numbers its work items stamp_next, stamp_next + 1,
-    // ...; when 32 bits would run out, clear every record and restart at 1
-    if (ctx->stamp_next == 0 || uint64_t(ctx->stamp_next) + count > 0xFFFFFFFFull) {
-      // (the bidirectional sampler's records carry the same stamps)
-      fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(ctx->slots) * ctx->slot_n * 2, s);
-      if (ctx->bi_rec_f.ptr) {
-        fill_u64(static_cast<uint64_t*>(ctx->bi_rec_f.ptr), 0, size_t(ctx->bi_slots) * ctx->bi_n * 2, s);
-        fill_u64(static_cast<uint64_t*>(ctx->bi_rec_b.ptr), 0, size_t(ctx->bi_slots) * ctx->bi_n * 2, s);
-      }
-      ctx->stamp_next = 1;
-    }
-    a.stamp0 = ctx->stamp_next;
-    ctx->stamp_next += count;
-    a.count = count;
-    a.slot_stride = ctx->slot_n;
-    a.rec = static_cast<uint64_t*>(ctx->slot_rec.ptr);
-    a.q = static_cast<uint32_t*>(ctx->slot_q.ptr);
-    a.praw = static_cast<uint64_t*>(ctx->slot_praw.ptr);
-    a.pinfo = static_cast<uint32_t*>(ctx->slot_pinfo.ptr);
-    a.bit_words = plan.bit_words;
-    a.work = work;
-    a.stage = static_cast<uint32_t*>(ctx->stage_nodes.ptr);
-    a.stage_cap = cap;
-    a.stage_used = used;
-    a.stage_pos = static_cast<uint64_t*>(ctx->stage_pos.ptr);
-    a.he_len = static_cast<uint32_t*>(ctx->stage_len.ptr);
-    a.flags = ctx->d_flags;
-    a.stats = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 16);
+    reserve_stamps(ctx, count, s);
+    launch_args(ctx, a, plan, count, cap);
     fill_u64(a.stats, 0, 2, s);
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
     sample_kernel_launch(a, plan.block, plan.lds_bits, multi, grid, plan.dyn_lds, s);
@@ -301,7 +410,8 @@ int sample_reserve(centra_ctx* ctx, const centra_graph* g, uint32_t count, uint6
   const SamplePlan plan = plan_for(ctx, g->n);
   const uint32_t want = count < plan.resident ? count : plan.resident;
   int rc;
-  if ((rc = ensure_slots(ctx, g->n, want ? want : 1, s))) return rc;
+  bool fresh = false;   // no placement search here: there is no launch to time
+  if ((rc = ensure_slots(ctx, g->n, want ? want : 1, s, &fresh))) return rc;
   if ((rc = ensure(ctx, ctx->stage_pos, size_t(count) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->stage_len, size_t(count) * 4 + 8 + 8 * (size_t(count) + 1), false, s))) return rc;
   if ((rc = ensure(ctx, ctx->work_ctr, 64, false, s))) return rc;

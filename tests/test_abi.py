@@ -37,7 +37,7 @@ def test_binding_mirrors_header():
 
 
 def test_abi_version():
-    assert binding.centra_abi_version() == 10
+    assert binding.centra_abi_version() == 11
 
 
 CASES = [

@@ -401,3 +401,68 @@ def test_hbm_budget():
             dg.release()
     finally:
         binding.centra_destroy(ctx)
+
+
+def _sample_in_fresh_context(g, count, first=0):
+    ctx = binding.centra_create(0, 0)
+    try:
+        dg = binding.DeviceGraph(ctx, g)
+        try:
+            off, nodes = binding.sample_paths(ctx, dg, 1, 0, first, count)
+            torch.cuda.synchronize()
+            return off_np(off), nodes_np(nodes), binding.centra_context_log(ctx)
+        finally:
+            dg.release()
+    finally:
+        binding.centra_destroy(ctx)
+
+
+def test_slot_placement_search(monkeypatch):
+    # A fresh slot state of at least 4 GiB (BA 10^6: 61 GB) is chosen among
+    # up to four allocations by timing the batch's first 65,536 samples on
+    # each.  The hyperedges are those of a context without the search, and
+    # of the oracle on sampled indices.
+    g = inputs.ba_graph(1_000_000, 5, 1)
+    count = 100_000
+    monkeypatch.setenv("CENTRA_SLOT_SEARCH", "0")
+    say("placement search off: 100000 samples on BA n=1e6")
+    off0, nodes0, log0 = _sample_in_fresh_context(g, count)
+    assert "slot placement" not in log0
+    monkeypatch.delenv("CENTRA_SLOT_SEARCH")
+    say("placement search on: 100000 samples on BA n=1e6")
+    off1, nodes1, log1 = _sample_in_fresh_context(g, count)
+    say(f"  {log1.strip()}")
+    line = [x for x in log1.splitlines() if x.startswith("slot placement:")]
+    assert len(line) == 1
+    times = [float(x) for x in line[0].split(":")[1].split("ms")[0].split()]
+    assert 1 <= len(times) <= 4 and all(t > 0 for t in times)
+    assert np.array_equal(off0, off1) and np.array_equal(nodes0, nodes1)
+    idx = np.linspace(0, count - 1, 200).astype(np.int64)
+    for i, (h, info) in zip(idx, oracle_paths(g, 1, 0, idx, oracle.count_bits(g))):
+        assert np.array_equal(nodes1[int(off1[i]):int(off1[i + 1])], h), i
+
+
+def test_slot_placement_search_skipped_near_stamp_wrap(monkeypatch):
+    # The search would use about 524k stamps; a context that has fewer left
+    # before the 32-bit wrap skips it (the held slot states must agree with
+    # the stamps), and the batches across the wrap still match the oracle.
+    monkeypatch.setenv("CENTRA_STAMP_START", str(0xFFFFFFFF - 150_000))
+    g = inputs.ba_graph(1_000_000, 5, 1)
+    ctx = binding.centra_create(0, 0)
+    try:
+        dg = binding.DeviceGraph(ctx, g)
+        try:
+            first = 0
+            for count in [100_000, 100_000]:   # the second batch crosses the wrap
+                say(f"near-wrap context: batch at {first}")
+                off, nodes = binding.sample_paths(ctx, dg, 1, 0, first, count)
+                off, nodes = off_np(off), nodes_np(nodes)
+                idx = np.linspace(0, count - 1, 50).astype(np.int64)
+                for i, (h, info) in zip(idx, oracle_paths(g, 1, 0, idx + first, oracle.count_bits(g))):
+                    assert np.array_equal(nodes[int(off[i]):int(off[i + 1])], h), i
+                first += count
+            assert "slot placement" not in binding.centra_context_log(ctx)
+        finally:
+            dg.release()
+    finally:
+        binding.centra_destroy(ctx)
