@@ -66,12 +66,12 @@ CENTRA_API uint32_t centra_abi_version(void);
  * Contexts are independent: different contexts may be used from different
  * host threads at the same time.  *out receives the context.
  * Placement: the sampler's speed depends on where the device allocator puts
- * the pages of that per-BFS state (the same launch varies by up to ~18%
- * from one allocation to the next, and not within one).  When a
- * synchronous sampling call allocates at least 4 GiB of it, the context
- * times a launch of the call's first 65,536 work items on each of up to
- * four allocations, holding two at a time, and keeps the fastest; results
- * do not depend on it.  The environment variable CENTRA_SLOT_SEARCH=0
+ * the pages of that state's per-BFS node records (the same launch varies
+ * by up to ~18% from one allocation to the next, and not within one).
+ * When a synchronous sampling call allocates at least 4 GiB of records, the
+ * context times a launch of the call's first 65,536 work items on each of
+ * up to four allocations of them, holding two at a time, and keeps the
+ * fastest; results do not depend on it.  The environment variable CENTRA_SLOT_SEARCH=0
  * turns this off; centra_context_log reports the times.  (Tests only:
  * the environment variable CENTRA_STAMP_START sets the context's first BFS
  * stamp, to exercise the sampler's 32-bit stamp wrap.)

@@ -119,17 +119,18 @@ static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t
   return CENTRA_OK;
 }
 
-// Placement of the slot state.  How fast the sampler runs on a given slot
-// state depends on where the allocator put its pages: the same launch on
-// BA 10^6 takes anywhere from 51 to 61 ms from one allocation to the next,
-// the same within one allocation to 0.5%, and unchanged when the graph is
-// uploaded again.  A short launch ranks allocations as the full one does,
-// so a fresh slot state of at least kPlaceMinBytes is chosen among
-// kPlaceCandidates allocations by timing the batch's first kPlaceProbe work
-// items on each (second of two launches; results discarded, stamps used up
-// as by any launch).  The search holds two slot states at a time and stops
-// early if the budget or the device cannot; CENTRA_SLOT_SEARCH=0 turns it
-// off.  It synchronises the stream, so stream-ordered launches skip it.
+// Placement of the slot records.  How fast the sampler runs depends on
+// where the allocator put the pages of the per-BFS records: the same launch
+// on BA 10^6 takes anywhere from 51 to 61 ms from one allocation of them to
+// the next, the same within one allocation to 0.5%, and unchanged when the
+// queues or the graph are allocated again.  A short launch ranks
+// allocations as the full one does, so fresh records of at least
+// kPlaceMinBytes are chosen among kPlaceCandidates allocations by timing
+// the batch's first kPlaceProbe work items on each (second of two launches;
+// results discarded, stamps used up as by any launch).  The search holds
+// two record arrays at a time and stops early if the budget or the device
+// cannot; CENTRA_SLOT_SEARCH=0 turns it off.  It synchronises the stream,
+// so stream-ordered launches skip it.
 constexpr int kPlaceCandidates = 4;
 constexpr uint32_t kPlaceProbe = 65536;
 constexpr size_t kPlaceMinBytes = size_t(4) << 30;
@@ -199,11 +200,11 @@ static int probe_slots(centra_ctx* ctx, SampleArgs a, const SamplePlan& plan, bo
 }
 
 // Chooses the fastest of kPlaceCandidates allocations of the (fresh) slot
-// records and queues, by probe_slots.
+// records, by probe_slots.
 static int place_slots(centra_ctx* ctx, const SampleArgs& a, const SamplePlan& plan, bool multi, uint32_t count,
                        hipStream_t s) {
-  const size_t rec_b = ctx->slot_rec.bytes, q_b = ctx->slot_q.bytes;
-  if (rec_b + q_b < kPlaceMinBytes) return CENTRA_OK;
+  const size_t rec_b = ctx->slot_rec.bytes;
+  if (rec_b < kPlaceMinBytes) return CENTRA_OK;
   const uint32_t pc = count < kPlaceProbe ? count : kPlaceProbe;
   // every slot state held during the search must stay consistent with the
   // stamps: start numbering if nothing has been drawn yet, and skip the
@@ -216,32 +217,21 @@ static int place_slots(centra_ctx* ctx, const SampleArgs& a, const SamplePlan& p
   if ((rc = probe_slots(ctx, a, plan, multi, pc, s, &best))) return rc;
   std::string line = "slot placement: " + std::to_string(best);
   for (int c = 1; c < kPlaceCandidates && best > 0.f; ++c) {
-    if (ctx->budget && ctx->allocated + rec_b + q_b > ctx->budget) break;
-    void *r2 = nullptr, *q2 = nullptr;
+    if (ctx->budget && ctx->allocated + rec_b > ctx->budget) break;
+    void* r2 = nullptr;
     if (hipMalloc(&r2, rec_b) != hipSuccess) {
       (void)hipGetLastError();
       break;
     }
-    if (hipMalloc(&q2, q_b) != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hipFree(r2);
-      break;
-    }
     fill_u64(static_cast<uint64_t*>(r2), 0, rec_b / 8, s);   // stamp 0: never claimed
     std::swap(ctx->slot_rec.ptr, r2);
-    std::swap(ctx->slot_q.ptr, q2);
     float ms = 0.f;
     rc = probe_slots(ctx, a, plan, multi, pc, s, &ms);
     line += " " + std::to_string(ms);
-    if (rc || !(ms > 0.f && ms < best)) {   // keep the previous one
-      std::swap(ctx->slot_rec.ptr, r2);
-      std::swap(ctx->slot_q.ptr, q2);
-    } else {
-      best = ms;
-    }
+    if (rc || !(ms > 0.f && ms < best)) std::swap(ctx->slot_rec.ptr, r2);   // keep the previous one
+    else best = ms;
     (void)hipStreamSynchronize(s);
     (void)hipFree(r2);
-    (void)hipFree(q2);
     if (rc) return rc;
   }
   ctx->log += line + " ms -> " + std::to_string(best) + " ms\n";
