@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <chrono>
 #include <string>
 #include <utility>
 #include <vector>
@@ -212,6 +213,7 @@ static int place_slots(centra_ctx* ctx, const SampleArgs& a, const SamplePlan& p
   // the slot state in use)
   reserve_stamps(ctx, 0, s);
   if (uint64_t(ctx->stamp_next) + uint64_t(2 * kPlaceCandidates) * pc + count > 0xFFFFFFFFull) return CENTRA_OK;
+  const auto t0 = std::chrono::steady_clock::now();
   float best = 0.f;
   int rc;
   if ((rc = probe_slots(ctx, a, plan, multi, pc, s, &best))) return rc;
@@ -234,7 +236,8 @@ static int place_slots(centra_ctx* ctx, const SampleArgs& a, const SamplePlan& p
     (void)hipFree(r2);
     if (rc) return rc;
   }
-  ctx->log += line + " ms -> " + std::to_string(best) + " ms\n";
+  const double took = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ctx->log += line + " ms -> " + std::to_string(best) + " ms (search " + std::to_string(took) + " ms)\n";
   return CENTRA_OK;
 }
 
