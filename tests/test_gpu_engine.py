@@ -258,3 +258,21 @@ def test_level_caches_are_exact(ctx):
     finally:
         for dg in dgs:
             dg.release()
+
+
+def test_fused_launch_after_placement_search():
+    # A pool on BA 10^6 gives the fused sampling launch 49 GB of slot
+    # records, so the context chooses their placement on the first fused
+    # (tuner) launch; every result must still equal its standalone run.
+    ctx = binding.centra_create(0, 0)
+    try:
+        graphs = [(inputs.ba_graph(1_000_000, 5, 1), 10), (inputs.ba_graph(2000, 5, 2), 5)]
+        say("engine batch with a BA 1e6 pool (fresh context)")
+        got, want, st, log = run_batch(ctx, graphs, t=8, eps=0.1, m_init=100_000, m_max=200_000)
+        for g, w in zip(got, want):
+            same(g, w)
+        clog = binding.centra_context_log(ctx)
+        say(f"  {clog.strip()}")
+        assert "slot placement:" in clog
+    finally:
+        binding.centra_destroy(ctx)
