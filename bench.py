@@ -660,7 +660,9 @@ def main():
                          "nodes_per_path": round(st.nodes / max(1, st.samples), 1),
                          "entries_per_path": round(st.hyperedge_nodes / max(1, st.samples), 3),
                          "visited_set": "lds bitmap" if st.lds_bitmap else "lds bloom filter + hbm records",
-                         "concurrent_bfs": st.slots})
+                         "concurrent_bfs": st.slots, "wide_samples": st.wide,
+                         "wide_ms_per_step": round(st.wide_ms / max(1, args.steps), 2),
+                         "wide_arcs_per_wide_sample": round(st.wide_arcs / max(1, st.wide))})
 
     cpu = cpu_all = None
     if args.cpu_seconds > 0:

@@ -357,7 +357,17 @@ CENTRA_API int centra_check(centra_ctx *ctx, void *stream);
  * immediately around each launch.
  * arcs counts every CSR entry the kernel scans (level expansions, the
  * checks around t, the backtrack is not included); nodes counts every node
- * given a level.  A re-launch after a staging overflow counts again. */
+ * given a level.  A re-launch after a staging overflow counts again.
+ * Wide samples: a BFS about to expand a level of more than 65,536 nodes,
+ * or that has scanned more than 2^21 CSR entries (a flood of a skewed
+ * graph's reachable set), is handed from its workgroup to a device-wide BFS that redraws the sample level by level
+ * with the whole GPU (same hyperedge).  kernel_ms, arcs and nodes stay
+ * those of the workgroup kernel (a handed-over BFS's partial work
+ * included); `wide` counts such samples, wide_ms is the wall time of their
+ * device-wide BFSs (launches and the per-level synchronisation) and
+ * wide_arcs the CSR entries those scanned (full levels).  Only the
+ * synchronous single-graph launches do this (CENTRA_WIDE=0 turns it off;
+ * tests only: CENTRA_WIDE_NODES lowers the level size that triggers it). */
 typedef struct {
     uint64_t launches;
     double kernel_ms;
@@ -367,6 +377,9 @@ typedef struct {
     uint64_t hyperedge_nodes;
     uint32_t lds_bitmap;   /* 1 if the last launch kept the visited bitmap in LDS */
     uint32_t slots;        /* workgroups (concurrent BFSs) of the last launch */
+    uint64_t wide;         /* samples finished by the device-wide BFS */
+    double wide_ms;
+    uint64_t wide_arcs;
 } centra_sampler_stats;
 
 /* Copies the statistics to *out (host) and, if reset != 0, zeroes them. */

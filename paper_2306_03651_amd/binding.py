@@ -105,7 +105,8 @@ class Checkpoint(_c.Structure):
 class SamplerStats(_c.Structure):
     _fields_ = [("launches", _c.c_uint64), ("kernel_ms", _c.c_double), ("samples", _c.c_uint64),
                 ("arcs", _c.c_uint64), ("nodes", _c.c_uint64), ("hyperedge_nodes", _c.c_uint64),
-                ("lds_bitmap", _c.c_uint32), ("slots", _c.c_uint32)]
+                ("lds_bitmap", _c.c_uint32), ("slots", _c.c_uint32), ("wide", _c.c_uint64),
+                ("wide_ms", _c.c_double), ("wide_arcs", _c.c_uint64)]
 
 
 class PoolParams(_c.Structure):

@@ -30,6 +30,7 @@ struct centra_ctx {
   // queue, stored pair counts), one set per concurrent BFS, sized for the
   // largest graph
   centra::DevBuf slot_rec, slot_q, slot_praw, slot_pinfo;
+  centra::DevBuf wide_ws;   // device-wide BFS: u64 ctl[8], then the deferred work items
   std::string log;   // one-time choices of the context (slot placement), one line each
   uint32_t slots = 0;
   uint32_t slot_n = 0;

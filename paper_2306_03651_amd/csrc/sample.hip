@@ -71,6 +71,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <type_traits>
 #include <vector>
 
@@ -347,6 +348,21 @@ __device__ __forceinline__ uint64_t pred_weight(const Bits& bits, uint64_t* rec,
 
 __device__ __forceinline__ uint32_t caller_id(const SampleArgs& a, uint32_t v) { return a.orig_of ? a.orig_of[v] : v; }
 
+// Appends work item idx to the deferred list (workgroup uniform); true if
+// it fit, the sample then being left to the device-wide BFS.
+template <int BLOCK>
+__device__ __forceinline__ bool defer_sample(const SampleArgs& a, uint32_t idx, SampleShared<BLOCK>& sh) {
+  if (threadIdx.x == 0) {
+    const uint32_t at = atomicAdd(a.defer_count, 1u);
+    if (at < a.defer_cap) a.defer_list[at] = idx;
+    sh.pick = at;
+  }
+  __syncthreads();
+  const uint32_t at = uniform_u32(sh.pick);
+  __syncthreads();
+  return at < a.defer_cap;
+}
+
 // Cost rule of the hub 2-hop test at a level (queue entries [lb, le)):
 // true when the in-rows of t's dt in-neighbours (starting at in_idx[tb])
 // hold at most kPairRatio times the out-arcs of the level.  Both sums grow
@@ -587,6 +603,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 6 : 1) void k_sample_paths(Sa
     uint64_t shifted = 0;     // bit l: the counts of produced level l < 64 were shifted
     // t without in-neighbours is unreachable: no BFS at all (on skewed
     // directed graphs such targets are common, and s may reach millions)
+    bool deferred = false;
+    const uint64_t arcs0 = n_arcs;   // this BFS's scans are n_arcs - arcs0
     for (; dt != 0;) {
       // (1) a visited in-neighbour of t: it is at level L (an earlier check
       //     would have fired otherwise), so d = L + 1
@@ -731,6 +749,16 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 6 : 1) void k_sample_paths(Sa
           break;
         }
       }
+      if constexpr (!LDS_BITS && !MULTI) {
+        // a level too wide for one workgroup, or a BFS that has already
+        // scanned millions of entries: the sample goes to the device-wide
+        // BFS (if the list has room), which redraws it in full
+        if (a.defer_nodes && (le - lb > a.defer_nodes || n_arcs - arcs0 > a.defer_arcs) &&
+            defer_sample<BLOCK>(a, idx, sh)) {
+          deferred = true;
+          break;
+        }
+      }
       // expand level L (queue entries [lb, le)) into level L+1
       const uint32_t nl = L + 1;
       uint64_t mx = 0, added = 0;
@@ -747,6 +775,15 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 6 : 1) void k_sample_paths(Sa
         uint32_t total;
         const uint32_t off = block_excl_scan_u32<BLOCK>(deg, &total, sh.scan);
         n_arcs += total;
+        if constexpr (!LDS_BITS && !MULTI) {
+          // a level whose arcs run past the scan budget (hub frontiers): the
+          // device-wide BFS redraws the sample (uniform; the partial level
+          // is abandoned with the BFS's stamp)
+          if (a.defer_nodes && n_arcs - arcs0 > a.defer_arcs && defer_sample<BLOCK>(a, idx, sh)) {
+            deferred = true;
+            break;
+          }
+        }
         sh.off[tid] = off;
         sh.rs[tid] = rs;
         sh.sg[tid] = sw;
@@ -814,6 +851,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 6 : 1) void k_sample_paths(Sa
         }
         __syncthreads();
       }
+      if (deferred) break;   // uniform
       const uint32_t ne = uniform_u32(sh.qlen);
       if (ne == le) break;   // nothing new: t unreachable
       // level L+1 is complete: its largest raw count decides the shift;
@@ -839,6 +877,12 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 6 : 1) void k_sample_paths(Sa
       lb = le;
       le = ne;
       L = nl;
+    }
+
+    if (deferred) {   // uniform: nothing is staged for this sample here
+      n_nodes += uniform_u32(sh.qlen);
+      __syncthreads();
+      continue;
     }
 
     // backtrack: from v = t, pick a predecessor w at level(v) - 1 with
@@ -1041,6 +1085,246 @@ void sample_kernel_launch(const SampleArgs& a, int block, bool lds_bits, bool mu
       break;
   }
 #undef CENTRA_LAUNCH
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide BFS of a deferred sample.  A few samples of skewed graphs
+// flood millions of nodes (R-MAT scale 22: one in about 300k floods the 2M
+// nodes its source reaches, 63M arcs), which takes one 128-thread workgroup
+// about a second and holds its launch that long.  Such a sample is redrawn
+// here with each level expanded by the whole GPU: full levels (no ring
+// tests), which give the same levels, normalised counts and predecessor
+// weights as the shortcuts do, then the same backtrack over the same word
+// stream, so the hyperedge is the one the workgroup kernel would stage.
+// The state is slot 0's records and queue (the launch that deferred the
+// sample has finished) under a stamp of its own.
+constexpr int kWideBlock = 256;
+constexpr unsigned kWideGrid = 2048;
+
+// ctl: [0] queue length, [1] largest raw count of the new level, [2] 1 if
+// t is on the new level, [3] s, [4] t (traversal ids), [5] 0, [6] arcs
+// scanned, [7] nodes given a level
+__global__ void k_wide_start(SampleArgs a, uint32_t idx, uint64_t base, uint64_t* ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  WordStream st(a.seed, a.first + idx, a.instance, 0);
+  const uint32_t s0 = static_cast<uint32_t>(bounded(st, a.n));
+  const uint32_t tp = static_cast<uint32_t>(bounded(st, a.n - 1));
+  const uint32_t t0 = tp + (tp >= s0 ? 1u : 0u);
+  const uint32_t s = a.new_of ? a.new_of[s0] : s0;
+  const uint32_t t = a.new_of ? a.new_of[t0] : t0;
+  st_u64(tag_of(a.rec, s), level_tag(base, 0));
+  st_u64(sig_of(a.rec, s), 1);
+  st_u32(&a.q[0], s);
+  ctl[0] = 1;
+  ctl[1] = 0;
+  ctl[2] = 0;
+  ctl[3] = s;
+  ctl[4] = t;
+  ctl[5] = 0;
+  ctl[6] = 0;
+  ctl[7] = 1;
+}
+
+// Level nl - 1 = queue entries [lb, le) expanded by every workgroup, a
+// chunk of kWideBlock frontier nodes at a time: pass 0 claims the new
+// level's nodes (returning atomic max on the tag; the claimer zeroes the
+// count and appends the node, one queue atomic per wave), pass 1 adds each
+// frontier node's count to its new-level out-neighbours.
+template <int PASS>
+__global__ __launch_bounds__(kWideBlock) void k_wide_level(SampleArgs a, uint32_t lb, uint32_t le, uint64_t base,
+                                                           uint32_t nl, uint64_t* ctl) {
+  __shared__ uint32_t off[kWideBlock], rs[kWideBlock], scan[kWideBlock / kWave + 1];
+  __shared__ uint64_t sg[kWideBlock];
+  const int tid = threadIdx.x, lane = lane_id();
+  const uint64_t tag_new = level_tag(base, nl);
+  const uint64_t lane_lt = (1ull << lane) - 1ull;
+  uint64_t arcs = 0;
+  for (uint64_t cb = lb + uint64_t(blockIdx.x) * kWideBlock; cb < le; cb += uint64_t(gridDim.x) * kWideBlock) {
+    const uint64_t i = cb + tid;
+    uint32_t deg = 0, r0 = 0;
+    uint64_t sw = 0;
+    if (i < le) {
+      const uint32_t w = ld_u32(&a.q[i]);
+      r0 = a.row_ptr[w];
+      deg = a.row_ptr[w + 1] - r0;
+      if (PASS == 1) sw = ld_u64(sig_of(a.rec, w));
+    }
+    uint32_t total;
+    const uint32_t o = block_excl_scan_u32<kWideBlock>(deg, &total, scan);
+    off[tid] = o;
+    rs[tid] = r0;
+    sg[tid] = sw;
+    arcs += total;
+    __syncthreads();
+    for (uint32_t e0 = 0; e0 < total; e0 += kWideBlock) {   // uniform trip count
+      const uint32_t e = e0 + tid;
+      bool claimed = false;
+      uint32_t v = 0;
+      if (e < total) {
+        int lo = 0, hi = kWideBlock - 1;   // the last j with off[j] <= e (it has arcs)
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (off[mid] <= e)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        v = a.col_idx[rs[lo] + (e - off[lo])];
+        if (PASS == 0) {
+          // most arcs of a flood reach visited nodes: a plain look at the
+          // tag spares them the returning atomic
+          if (ld_u64(tag_of(a.rec, v)) < base)
+            claimed = atomicMax(reinterpret_cast<unsigned long long*>(tag_of(a.rec, v)),
+                                static_cast<unsigned long long>(tag_new)) < base;
+          if (claimed) st_u64(sig_of(a.rec, v), 0);
+        } else if (ld_u64(tag_of(a.rec, v)) == tag_new) {
+          atomicAdd(reinterpret_cast<unsigned long long*>(sig_of(a.rec, v)), static_cast<unsigned long long>(sg[lo]));
+        }
+      }
+      if (PASS == 0) {
+        const uint64_t m = __ballot(claimed);
+        if (m) {
+          const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+          uint64_t wb = 0;
+          if (lane == leader)
+            wb = atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[0]), static_cast<unsigned long long>(__popcll(m)));
+          wb = __shfl(wb, leader, kWave);
+          if (claimed) st_u32(&a.q[wb + __popcll(m & lane_lt)], v);
+        }
+      }
+    }
+    __syncthreads();   // off, rs and sg are reused by the next chunk
+  }
+  // arcs is uniform over the workgroup (each chunk's total): one add
+  if (PASS == 0 && a.stats && tid == 0 && arcs)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[0]), static_cast<unsigned long long>(arcs));
+}
+
+// The new level [le, ne = ctl[0]): its largest raw count into ctl[1]
+// (zeroed by the caller), whether t is on it into ctl[2], its size into
+// the node statistics.
+__global__ __launch_bounds__(kWideBlock) void k_wide_close(SampleArgs a, uint32_t le, uint64_t base, uint32_t nl,
+                                                           uint32_t t, uint64_t* ctl) {
+  __shared__ uint64_t red[kWideBlock / kWave];
+  const uint32_t ne = static_cast<uint32_t>(ctl[0]);
+  uint64_t mx = 0;
+  for (uint64_t i = le + uint64_t(blockIdx.x) * kWideBlock + threadIdx.x; i < ne; i += uint64_t(gridDim.x) * kWideBlock) {
+    const uint64_t x = ld_u64(sig_of(a.rec, ld_u32(&a.q[i])));
+    mx = x > mx ? x : mx;
+  }
+  mx = block_max_u64<kWideBlock>(mx, red);
+  if (threadIdx.x == 0 && mx) atomicMax(reinterpret_cast<unsigned long long*>(&ctl[1]), static_cast<unsigned long long>(mx));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[2] = ld_u64(tag_of(a.rec, t)) == level_tag(base, nl) ? 1u : 0u;
+    if (a.stats) atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[1]), static_cast<unsigned long long>(ne - le));
+  }
+}
+
+// Normalisation of the new level: sigma' = max(1, raw >> shift).
+__global__ void k_wide_shift(SampleArgs a, uint32_t le, uint32_t ne, uint32_t shift) {
+  for (uint64_t i = le + uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < ne; i += uint64_t(gridDim.x) * blockDim.x) {
+    uint64_t* p = sig_of(a.rec, ld_u32(&a.q[i]));
+    const uint64_t x = ld_u64(p) >> shift;
+    st_u64(p, x ? x : 1ull);
+  }
+}
+
+// The backtrack of the sample (t at distance d, kUnseen if unreachable) by
+// one workgroup over the same word stream as the workgroup kernel (the
+// pair's words, then one bounded draw per step), staged the same way.
+__global__ __launch_bounds__(kWideBlock) void k_wide_backtrack(SampleArgs a, uint32_t idx, uint64_t base, uint32_t d) {
+  __shared__ SampleShared<kWideBlock> sh;
+  const int tid = threadIdx.x;
+  WordStream st(a.seed, a.first + idx, a.instance, 0);
+  const uint32_t s0 = static_cast<uint32_t>(bounded(st, a.n));
+  const uint32_t tp = static_cast<uint32_t>(bounded(st, a.n - 1));
+  const uint32_t t0 = tp + (tp >= s0 ? 1u : 0u);
+  const uint32_t t = a.new_of ? a.new_of[t0] : t0;
+  const uint32_t len = (d != kUnseen && d >= 2) ? d - 1 : 0u;
+  if (tid == 0)
+    sh.base = len ? atomicAdd(reinterpret_cast<unsigned long long*>(a.stage_used), static_cast<unsigned long long>(len))
+                  : 0ull;
+  __syncthreads();
+  const uint64_t hbase = uniform_u64(sh.base);
+  uint32_t v = t, dv = len ? d : 0u, written = 0;
+  bool ok = true;
+  while (dv >= 2) {
+    const uint32_t want = dv - 1;
+    const uint64_t tag_want = level_tag(base, want);
+    const uint32_t vb = a.in_ptr[v], ve = a.in_ptr[v + 1];
+    const uint32_t j = block_pick<kWideBlock>(
+        ve - vb,
+        [&](uint32_t jj) {
+          const uint32_t w = a.in_idx[vb + jj];
+          const uint64_t tg = ld_u64(tag_of(a.rec, w));
+          const uint64_t c = ld_u64(sig_of(a.rec, w));
+          return tg == tag_want ? c : 0ull;
+        },
+        0, st, sh);
+    if (j == kUnseen) {
+      ok = false;
+      break;
+    }
+    v = a.in_idx[vb + j];
+    if (tid == 0 && hbase + written < a.stage_cap) a.stage[hbase + written] = caller_id(a, v);
+    ++written;
+    --dv;
+  }
+  if (tid == 0) {
+    if (!ok) atomicOr(a.flags, kErrBacktrack);
+    a.stage_pos[idx] = hbase;
+    a.he_len[idx] = len;
+    if (a.st_out) {
+      a.st_out[2 * size_t(idx)] = s0;
+      a.st_out[2 * size_t(idx) + 1] = t0;
+    }
+    if (a.dist_out) a.dist_out[idx] = d;
+  }
+}
+
+int wide_sample(const SampleArgs& a_in, uint32_t idx, uint64_t base, uint64_t* ctl, uint64_t* host_ctl,
+                uint32_t* d_out, hipStream_t s) {
+  SampleArgs a = a_in;
+  a.stats = ctl + 6;   // this BFS's arcs and nodes, apart from the workgroup kernel's
+  hipLaunchKernelGGL(k_wide_start, dim3(1), dim3(64), 0, s, a, idx, base, ctl);
+  if (hipMemcpyAsync(host_ctl, ctl, 5 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CENTRA_EHIP;
+  const uint32_t t = static_cast<uint32_t>(host_ctl[4]);
+  uint32_t lb = 0, le = 1, L = 0, d = kUnseen;
+  // one synchronisation per level: claims, counts and the level's close,
+  // then the host reads its size, maximum and whether t is on it
+  for (;;) {
+    const uint32_t nl = L + 1;
+    const unsigned grid = std::min<uint64_t>(kWideGrid, (uint64_t(le - lb) + kWideBlock - 1) / kWideBlock);
+    fill_u64(ctl + 1, 0, 2, s);
+    hipLaunchKernelGGL(k_wide_level<0>, dim3(grid), dim3(kWideBlock), 0, s, a, lb, le, base, nl, ctl);
+    hipLaunchKernelGGL(k_wide_level<1>, dim3(grid), dim3(kWideBlock), 0, s, a, lb, le, base, nl, ctl);
+    hipLaunchKernelGGL(k_wide_close, dim3(kWideGrid), dim3(kWideBlock), 0, s, a, le, base, nl, t, ctl);
+    if (hipMemcpyAsync(host_ctl, ctl, 3 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return CENTRA_EHIP;
+    const uint32_t ne = static_cast<uint32_t>(host_ctl[0]);
+    if (ne == le) break;   // nothing new: t unreachable
+    if (host_ctl[2]) {     // t on level nl: its predecessors' levels are final
+      d = nl;
+      break;
+    }
+    uint32_t bl = 0;
+    for (uint64_t x = host_ctl[1]; x; x >>= 1) ++bl;
+    const uint32_t shift = bl > a.c_bits ? bl - a.c_bits : 0u;
+    if (shift) {
+      const unsigned gc = std::min<uint64_t>(kWideGrid, (uint64_t(ne - le) + kWideBlock - 1) / kWideBlock);
+      hipLaunchKernelGGL(k_wide_shift, dim3(gc), dim3(kWideBlock), 0, s, a, le, ne, shift);
+    }
+    lb = le;
+    le = ne;
+    L = nl;
+  }
+  hipLaunchKernelGGL(k_wide_backtrack, dim3(1), dim3(kWideBlock), 0, s, a, idx, base, d);
+  if (hipGetLastError() != hipSuccess) return CENTRA_EHIP;
+  if (hipMemcpyAsync(host_ctl + 6, ctl + 6, 16, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CENTRA_EHIP;
+  *d_out = d;
+  return CENTRA_OK;
 }
 
 void stage_gather_launch(uint32_t count, const uint64_t* stage_pos, const uint32_t* he_len, const uint64_t* rel_off,

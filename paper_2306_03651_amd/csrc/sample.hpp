@@ -62,12 +62,31 @@ struct SampleArgs {
   const SampleInst* inst;
   const uint32_t* item_off;
   uint32_t n_inst;
+  // deferral (single-graph launches only; defer_nodes = 0: none): a BFS
+  // about to expand a level of more than defer_nodes nodes, or after
+  // scanning more than defer_arcs CSR entries, appends its work item to
+  // defer_list (at most defer_cap, counted in *defer_count) and leaves it
+  // to the device-wide BFS (wide_sample)
+  uint32_t defer_nodes;
+  uint64_t defer_arcs;
+  uint32_t defer_cap;
+  uint32_t* defer_list;
+  uint32_t* defer_count;
 };
 
 hipError_t sample_kernel_occupancy(int block, bool lds_bits, bool multi, size_t dyn_lds, int* per_cu);
 size_t sample_lds_variant_bytes();
 void sample_kernel_launch(const SampleArgs& a, int block, bool lds_bits, bool multi, uint32_t grid, size_t dyn_lds,
                           hipStream_t s);
+// Device-wide BFS of one deferred work item idx of a single-graph launch
+// (a.first, a.seed, a.instance and the graph as in that launch): every
+// level expanded by the whole GPU (claims, then counts, then the level's
+// normalisation), the backtrack by one workgroup, the hyperedge staged
+// like the workgroup kernel's.  Uses slot 0's records and queue with stamp
+// base >> 32; ctl: u64[8] of device memory.  Returns the distance of t
+// (kUnseen if unreachable) through *d; synchronises the stream per level.
+int wide_sample(const SampleArgs& a, uint32_t idx, uint64_t base, uint64_t* ctl, uint64_t* host_ctl, uint32_t* d,
+                hipStream_t s);
 void stage_gather_launch(uint32_t count, const uint64_t* stage_pos, const uint32_t* he_len, const uint64_t* rel_off,
                          uint64_t base, const uint32_t* stage, uint64_t* he_off, uint32_t* he_nodes, hipStream_t s);
 

@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <string>
 #include <utility>
@@ -101,17 +102,22 @@ static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t
     if (!ctx->budget || ctx->allocated - have + need <= ctx->budget || slots <= 1) break;
     slots /= 2;
   }
-  release(ctx, ctx->slot_rec);
-  release(ctx, ctx->slot_praw);
-  release(ctx, ctx->slot_pinfo);
-  release(ctx, ctx->slot_q);
-  ctx->slots = 0;
-  ctx->slot_n = 0;
   int rc;
-  if ((rc = ensure(ctx, ctx->slot_rec, size_t(slots) * n * 16, false, s))) return rc;
-  if ((rc = ensure(ctx, ctx->slot_praw, size_t(slots) * kPairMax * 8, false, s))) return rc;
-  if ((rc = ensure(ctx, ctx->slot_pinfo, size_t(slots) * kPairMax * 12, false, s))) return rc;
-  if ((rc = ensure(ctx, ctx->slot_q, size_t(slots) * n * 4, false, s))) return rc;
+  for (;;) {   // halve the slot count while the device cannot hold the state
+    release(ctx, ctx->slot_rec);
+    release(ctx, ctx->slot_praw);
+    release(ctx, ctx->slot_pinfo);
+    release(ctx, ctx->slot_q);
+    ctx->slots = 0;
+    ctx->slot_n = 0;
+    rc = ensure(ctx, ctx->slot_rec, size_t(slots) * n * 16, false, s);
+    if (!rc) rc = ensure(ctx, ctx->slot_praw, size_t(slots) * kPairMax * 8, false, s);
+    if (!rc) rc = ensure(ctx, ctx->slot_pinfo, size_t(slots) * kPairMax * 12, false, s);
+    if (!rc) rc = ensure(ctx, ctx->slot_q, size_t(slots) * n * 4, false, s);
+    if (rc != CENTRA_ENOMEM || slots <= 64) break;
+    slots /= 2;
+  }
+  if (rc) return rc;
   fill_u64(static_cast<uint64_t*>(ctx->slot_rec.ptr), 0, size_t(slots) * n * 2, s);   // stamp 0: never claimed
   CENTRA_HIP(ctx, hipGetLastError());
   ctx->slots = slots;
@@ -132,6 +138,37 @@ static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t
 // two record arrays at a time and stops early if the budget or the device
 // cannot; CENTRA_SLOT_SEARCH=0 turns it off.  It synchronises the stream,
 // so stream-ordered launches skip it.
+// Wide samples: a BFS about to expand a level of more than kWideNodes
+// nodes, or past kWideArcs scanned entries, is left to the device-wide BFS
+// (wide_sample in sample.hip); at most kWideCap per launch (the rest finish
+// on their workgroups).
+constexpr uint32_t kWideNodes = 65536;
+constexpr uint64_t kWideArcs = uint64_t(1) << 21;   // about 30 ms of one workgroup's scanning
+constexpr uint32_t kWideCap = 4096;
+
+static bool wide_enabled() {
+  const char* e = getenv("CENTRA_WIDE");
+  return !(e && !strcmp(e, "0"));
+}
+
+// Turns deferral on in `a` (its list in ctx->wide_ws, its counter the u32
+// at byte 32 of work_ctr) and clears the counter.
+static int defer_args(centra_ctx* ctx, SampleArgs& a, hipStream_t s) {
+  int rc;
+  if ((rc = ensure(ctx, ctx->wide_ws, 64 + size_t(kWideCap) * 4, false, s))) return rc;
+  a.defer_nodes = kWideNodes;
+  a.defer_arcs = kWideArcs;
+  if (const char* e = getenv("CENTRA_WIDE_NODES")) {   // tests: a lower threshold
+    const long v = atol(e);
+    if (v >= 1 && v <= 0x7FFFFFFFl) a.defer_nodes = static_cast<uint32_t>(v);
+  }
+  a.defer_cap = kWideCap;
+  a.defer_list = reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->wide_ws.ptr) + 64);
+  a.defer_count = reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 32);
+  fill_u64(reinterpret_cast<uint64_t*>(a.defer_count), 0, 1, s);
+  return CENTRA_OK;
+}
+
 constexpr int kPlaceCandidates = 4;
 constexpr uint32_t kPlaceProbe = 65536;
 constexpr size_t kPlaceMinBytes = size_t(4) << 30;
@@ -161,6 +198,11 @@ static void launch_args(centra_ctx* ctx, SampleArgs& a, const SamplePlan& plan, 
   a.he_len = static_cast<uint32_t*>(ctx->stage_len.ptr);
   a.flags = ctx->d_flags;
   a.stats = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 16);
+  a.defer_nodes = 0;
+  a.defer_arcs = 0;
+  a.defer_cap = 0;
+  a.defer_list = nullptr;
+  a.defer_count = nullptr;
 }
 
 // Stamps: a launch numbers its work items stamp_next, stamp_next + 1, ...;
@@ -187,13 +229,16 @@ static int probe_slots(centra_ctx* ctx, SampleArgs a, const SamplePlan& plan, bo
     fill_u32(static_cast<uint32_t*>(ctx->work_ctr.ptr), 0, 1, s);
     fill_u64(reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 8), 0, 3, s);
     launch_args(ctx, a, plan, count, ctx->stage_nodes.bytes / 4);
+    // a flooding sample would hold every probe as long as itself: it is
+    // left out, as the timed launches leave it to the device-wide BFS
+    int rc;
+    if (!multi && !plan.lds_bits && wide_enabled() && (rc = defer_args(ctx, a, s))) return rc;
     const uint32_t grid = count < ctx->slots ? count : ctx->slots;
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
     sample_kernel_launch(a, plan.block, plan.lds_bits, multi, grid, plan.dyn_lds, s);
     CENTRA_HIP(ctx, hipGetLastError());
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[7], s));
     CENTRA_HIP(ctx, hipStreamSynchronize(s));
-    int rc;
     if ((rc = check_flags(ctx, s, "sample_paths (placement probe)"))) return rc;
     if (hipEventElapsedTime(ms, ctx->ev[6], ctx->ev[7]) != hipSuccess) *ms = 0.f;
   }
@@ -272,16 +317,43 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
     fill_u64(used, 0, 1, s);
     reserve_stamps(ctx, count, s);
     launch_args(ctx, a, plan, count, cap);
+    const bool wide = !async_cap && !multi && !plan.lds_bits && wide_enabled();
+    if (wide && (rc = defer_args(ctx, a, s))) return rc;
     fill_u64(a.stats, 0, 2, s);
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[6], s));
     sample_kernel_launch(a, plan.block, plan.lds_bits, multi, grid, plan.dyn_lds, s);
     CENTRA_HIP(ctx, hipGetLastError());
     if (async_cap) return CENTRA_OK;
     CENTRA_HIP(ctx, hipEventRecord(ctx->ev[7], s));
-    uint64_t host_ctr[4] = {0, 0, 0, 0};   // work, used, arcs, nodes
-    CENTRA_HIP(ctx, hipMemcpyAsync(host_ctr, ctx->work_ctr.ptr, 32, hipMemcpyDeviceToHost, s));
+    uint64_t host_ctr[5] = {0, 0, 0, 0, 0};   // work, used, arcs, nodes, deferred
+    CENTRA_HIP(ctx, hipMemcpyAsync(host_ctr, ctx->work_ctr.ptr, 40, hipMemcpyDeviceToHost, s));
     CENTRA_HIP(ctx, hipStreamSynchronize(s));
     if ((rc = check_flags(ctx, s, "sample_paths"))) return rc;
+    const uint32_t n_wide = wide ? static_cast<uint32_t>(std::min<uint64_t>(host_ctr[4] & 0xFFFFFFFFull, kWideCap)) : 0u;
+    if (n_wide) {
+      // the deferred samples, one device-wide BFS each, on slot 0's state
+      std::vector<uint32_t> list(n_wide);
+      CENTRA_HIP(ctx, hipMemcpyAsync(list.data(), a.defer_list, size_t(n_wide) * 4, hipMemcpyDeviceToHost, s));
+      CENTRA_HIP(ctx, hipStreamSynchronize(s));
+      uint64_t* ctl = static_cast<uint64_t*>(ctx->wide_ws.ptr);
+      uint64_t host_ctl[8] = {};
+      const auto w0 = std::chrono::steady_clock::now();
+      for (uint32_t idx : list) {
+        reserve_stamps(ctx, 1, s);
+        const uint64_t base = uint64_t(ctx->stamp_next) << 32;
+        ctx->stamp_next += 1;
+        uint32_t d = 0;
+        if (wide_sample(a, idx, base, ctl, host_ctl, &d, s) != CENTRA_OK)
+          return hip_fail(ctx, hipGetLastError(), "sample_paths (device-wide BFS)");
+        ctx->st.wide_arcs += host_ctl[6];
+      }
+      ctx->st.wide_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+      CENTRA_HIP(ctx, hipMemcpyAsync(&host_ctr[1], static_cast<char*>(ctx->work_ctr.ptr) + 8, 8,
+                                     hipMemcpyDeviceToHost, s));
+      CENTRA_HIP(ctx, hipStreamSynchronize(s));
+      if ((rc = check_flags(ctx, s, "sample_paths (device-wide BFS)"))) return rc;
+      ctx->st.wide += n_wide;
+    }
     const uint64_t host_used = host_ctr[1];
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]) != hipSuccess) ms = 0.f;

@@ -4,6 +4,9 @@ frontiers, hubs wider than a workgroup, count normalisation, unreachable
 targets, long diameters that overflow the staging area), batch splits, the
 first configuration in full and the large sparse configuration on sampled
 indices."""
+import contextlib
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -13,6 +16,19 @@ from paper_2306_03651_amd import binding, inputs
 from tests.gpu_util import check_graph_info, nodes_np, off_np, oracle_paths, say
 
 pytestmark = pytest.mark.gpu
+
+
+@contextlib.contextmanager
+def monkeypatch_env(key, value):
+    old = os.environ.get(key)
+    os.environ[key] = value
+    try:
+        yield
+    finally:
+        if old is None:
+            del os.environ[key]
+        else:
+            os.environ[key] = old
 
 
 def random_digraph(n, p, seed):
@@ -466,3 +482,61 @@ def test_slot_placement_search_skipped_near_stamp_wrap(monkeypatch):
             dg.release()
     finally:
         binding.centra_destroy(ctx)
+
+
+@pytest.mark.parametrize("name", ["ba2000", "grid40_c8", "grid40", "rmat12", "dir300", "dense1200", "funnel3000",
+                                  "layered", "star3000", "chain1500"])
+def test_wide_bfs_bit_exact(ctx, name, monkeypatch):
+    # With the threshold lowered to one node, nearly every BFS is handed
+    # from its workgroup to the device-wide BFS, which redraws the sample
+    # with full levels (no ring tests) and the same backtrack; hyperedges,
+    # pairs and distances must still be the oracle's (count shifts on the
+    # 8-bit grid and the layered graph, unreachable targets on the funnel).
+    monkeypatch.setenv("CENTRA_WIDE_NODES", "1")
+    build, cbo = CASES[name]
+    g = build()
+    count = 40 if name == "chain1500" else 200
+    say(f"device-wide BFS parity {name}: {count} samples")
+    binding.centra_sampler_stats_get(ctx, reset=True)
+    check_batch(ctx, g, cbo, seed=11, inst=2, first=5, count=count)
+    st = binding.centra_sampler_stats_get(ctx)
+    say(f"  {st.wide} samples went wide")
+    if name in ("grid40_c8", "grid40", "chain1500", "layered"):
+        assert st.wide > 0
+
+
+def test_wide_bfs_on_a_flood(ctx):
+    # R-MAT scale 22: sample 260,231 (seed 1, instance 0) floods the ~2M
+    # nodes its source reaches (63M arcs).  It goes to the device-wide BFS
+    # at the default threshold; the batch around it equals the workgroup
+    # kernel's (CENTRA_WIDE=0) and the oracle on sampled indices.
+    g = inputs.rmat_graph(22, 16, seed=1)
+    dg = binding.DeviceGraph(ctx, g)
+    first, count = 260_000, 2_000
+    try:
+        say("R-MAT 22 batch with a flooding sample: device-wide BFS on")
+        binding.centra_sampler_stats_get(ctx, reset=True)
+        off1, nodes1, st1, dist1 = binding.sample_paths(ctx, dg, 1, 0, first, count, with_st=True)
+        torch.cuda.synchronize()
+        s1 = binding.centra_sampler_stats_get(ctx)
+        off1, nodes1, dist1 = off_np(off1), nodes_np(nodes1), dist1.cpu().numpy().view(np.uint32)[:count].copy()
+        say(f"  {s1.wide} wide, {s1.kernel_ms:.1f} ms")
+        assert s1.wide >= 1
+        say("same batch, device-wide BFS off")
+        with monkeypatch_env("CENTRA_WIDE", "0"):
+            binding.centra_sampler_stats_get(ctx, reset=True)
+            off0, nodes0, st0, dist0 = binding.sample_paths(ctx, dg, 1, 0, first, count, with_st=True)
+            torch.cuda.synchronize()
+            s0 = binding.centra_sampler_stats_get(ctx)
+        say(f"  {s0.wide} wide, {s0.kernel_ms:.1f} ms")
+        assert s0.wide == 0
+        assert np.array_equal(off1, off_np(off0)) and np.array_equal(nodes1, nodes_np(nodes0))
+        assert np.array_equal(dist1, dist0.cpu().numpy().view(np.uint32)[:count])
+        c_bits = check_graph_info(dg, g)
+    finally:
+        dg.release()
+    idx = np.array([231, 0, 1999] + list(range(5, count, 97)), dtype=np.int64)
+    say("  oracle on sampled indices (the flood included)")
+    for i, (h, info) in zip(idx, oracle_paths(g, 1, 0, idx + first, c_bits)):
+        assert np.array_equal(nodes1[int(off1[i]):int(off1[i + 1])], h), i
+        assert dist1[i] == info.dist, i
