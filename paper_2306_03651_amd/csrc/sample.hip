@@ -1102,8 +1102,10 @@ constexpr int kWideBlock = 256;
 constexpr unsigned kWideGrid = 2048;
 
 // ctl: [0] queue length, [1] largest raw count of the new level, [2] 1 if
-// t is on the new level, [3] s, [4] t (traversal ids), [5] 0, [6] arcs
-// scanned, [7] nodes given a level
+// t is on the new level, [3] out-arcs of the last level (the cost of
+// pushing it), [4] t (traversal id), [5] in-arcs of the visited nodes
+// (the graph's in-arcs less the cost of pulling), [6] arcs scanned, [7]
+// nodes given a level
 __global__ void k_wide_start(SampleArgs a, uint32_t idx, uint64_t base, uint64_t* ctl) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   WordStream st(a.seed, a.first + idx, a.instance, 0);
@@ -1118,9 +1120,9 @@ __global__ void k_wide_start(SampleArgs a, uint32_t idx, uint64_t base, uint64_t
   ctl[0] = 1;
   ctl[1] = 0;
   ctl[2] = 0;
-  ctl[3] = s;
+  ctl[3] = a.row_ptr[s + 1] - a.row_ptr[s];
   ctl[4] = t;
-  ctl[5] = 0;
+  ctl[5] = a.in_ptr[s + 1] - a.in_ptr[s];
   ctl[6] = 0;
   ctl[7] = 1;
 }
@@ -1200,6 +1202,50 @@ __global__ __launch_bounds__(kWideBlock) void k_wide_level(SampleArgs a, uint32_
     atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[0]), static_cast<unsigned long long>(arcs));
 }
 
+// Level nl pulled instead of pushed (late levels of a flood, when the
+// unvisited nodes' in-arcs are fewer than the frontier's out-arcs): every
+// unvisited node sums the counts of its in-neighbours on level nl - 1; a
+// positive sum puts it on level nl with that raw count.  Each node is
+// written by its own thread only, so no atomics on the records.
+__global__ __launch_bounds__(kWideBlock) void k_wide_pull(SampleArgs a, uint64_t base, uint32_t nl, uint64_t* ctl) {
+  __shared__ uint64_t red[kWideBlock / kWave];
+  const int lane = lane_id();
+  const uint64_t tag_new = level_tag(base, nl), tag_prev = level_tag(base, nl - 1);
+  const uint64_t lane_lt = (1ull << lane) - 1ull;
+  uint64_t arcs = 0;
+  const uint64_t n_pad = (uint64_t(a.n) + kWideBlock - 1) / kWideBlock * kWideBlock;   // uniform trip count
+  for (uint64_t v0 = uint64_t(blockIdx.x) * kWideBlock; v0 < n_pad; v0 += uint64_t(gridDim.x) * kWideBlock) {
+    const uint64_t v = v0 + threadIdx.x;
+    bool claimed = false;
+    if (v < a.n && ld_u64(tag_of(a.rec, static_cast<uint32_t>(v))) < base) {
+      const uint32_t ib = a.in_ptr[v], ie = a.in_ptr[v + 1];
+      uint64_t raw = 0;
+      for (uint32_t e = ib; e < ie; ++e) {
+        const uint32_t w = a.in_idx[e];
+        if (ld_u64(tag_of(a.rec, w)) == tag_prev) raw += ld_u64(sig_of(a.rec, w));
+      }
+      arcs += ie - ib;
+      if (raw) {
+        st_u64(sig_of(a.rec, static_cast<uint32_t>(v)), raw);
+        st_u64(tag_of(a.rec, static_cast<uint32_t>(v)), tag_new);
+        claimed = true;
+      }
+    }
+    const uint64_t m = __ballot(claimed);
+    if (m) {
+      const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+      uint64_t wb = 0;
+      if (lane == leader)
+        wb = atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[0]), static_cast<unsigned long long>(__popcll(m)));
+      wb = __shfl(wb, leader, kWave);
+      if (claimed) st_u32(&a.q[wb + __popcll(m & lane_lt)], static_cast<uint32_t>(v));
+    }
+  }
+  arcs = block_sum_u64<kWideBlock>(arcs, red);
+  if (threadIdx.x == 0 && a.stats && arcs)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[0]), static_cast<unsigned long long>(arcs));
+}
+
 // The new level [le, ne = ctl[0]): its largest raw count into ctl[1]
 // (zeroed by the caller), whether t is on it into ctl[2], its size into
 // the node statistics.
@@ -1207,13 +1253,22 @@ __global__ __launch_bounds__(kWideBlock) void k_wide_close(SampleArgs a, uint32_
                                                            uint32_t t, uint64_t* ctl) {
   __shared__ uint64_t red[kWideBlock / kWave];
   const uint32_t ne = static_cast<uint32_t>(ctl[0]);
-  uint64_t mx = 0;
+  uint64_t mx = 0, out_arcs = 0, in_arcs = 0;
   for (uint64_t i = le + uint64_t(blockIdx.x) * kWideBlock + threadIdx.x; i < ne; i += uint64_t(gridDim.x) * kWideBlock) {
-    const uint64_t x = ld_u64(sig_of(a.rec, ld_u32(&a.q[i])));
+    const uint32_t v = ld_u32(&a.q[i]);
+    const uint64_t x = ld_u64(sig_of(a.rec, v));
     mx = x > mx ? x : mx;
+    out_arcs += a.row_ptr[v + 1] - a.row_ptr[v];
+    in_arcs += a.in_ptr[v + 1] - a.in_ptr[v];
   }
   mx = block_max_u64<kWideBlock>(mx, red);
-  if (threadIdx.x == 0 && mx) atomicMax(reinterpret_cast<unsigned long long*>(&ctl[1]), static_cast<unsigned long long>(mx));
+  out_arcs = block_sum_u64<kWideBlock>(out_arcs, red);
+  in_arcs = block_sum_u64<kWideBlock>(in_arcs, red);
+  if (threadIdx.x == 0) {
+    if (mx) atomicMax(reinterpret_cast<unsigned long long*>(&ctl[1]), static_cast<unsigned long long>(mx));
+    if (out_arcs) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[3]), static_cast<unsigned long long>(out_arcs));
+    if (in_arcs) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[5]), static_cast<unsigned long long>(in_arcs));
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl[2] = ld_u64(tag_of(a.rec, t)) == level_tag(base, nl) ? 1u : 0u;
     if (a.stats) atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[1]), static_cast<unsigned long long>(ne - le));
@@ -1293,14 +1348,23 @@ int wide_sample(const SampleArgs& a_in, uint32_t idx, uint64_t base, uint64_t* c
   uint32_t lb = 0, le = 1, L = 0, d = kUnseen;
   // one synchronisation per level: claims, counts and the level's close,
   // then the host reads its size, maximum and whether t is on it
+  // push a level (scan the frontier's out-arcs twice) unless pulling it
+  // (scan the unvisited nodes' in-arcs once, plus every node's tag) is
+  // cheaper; both give the same level and raw counts
+  uint64_t push_cost = host_ctl[3], visited_in = host_ctl[5];
   for (;;) {
     const uint32_t nl = L + 1;
-    const unsigned grid = std::min<uint64_t>(kWideGrid, (uint64_t(le - lb) + kWideBlock - 1) / kWideBlock);
-    fill_u64(ctl + 1, 0, 2, s);
-    hipLaunchKernelGGL(k_wide_level<0>, dim3(grid), dim3(kWideBlock), 0, s, a, lb, le, base, nl, ctl);
-    hipLaunchKernelGGL(k_wide_level<1>, dim3(grid), dim3(kWideBlock), 0, s, a, lb, le, base, nl, ctl);
+    const uint64_t pull_cost = (a.n_arcs - visited_in) + a.n / 4;
+    fill_u64(ctl + 1, 0, 3, s);
+    if (pull_cost < 2 * push_cost) {
+      hipLaunchKernelGGL(k_wide_pull, dim3(kWideGrid), dim3(kWideBlock), 0, s, a, base, nl, ctl);
+    } else {
+      const unsigned grid = std::min<uint64_t>(kWideGrid, (uint64_t(le - lb) + kWideBlock - 1) / kWideBlock);
+      hipLaunchKernelGGL(k_wide_level<0>, dim3(grid), dim3(kWideBlock), 0, s, a, lb, le, base, nl, ctl);
+      hipLaunchKernelGGL(k_wide_level<1>, dim3(grid), dim3(kWideBlock), 0, s, a, lb, le, base, nl, ctl);
+    }
     hipLaunchKernelGGL(k_wide_close, dim3(kWideGrid), dim3(kWideBlock), 0, s, a, le, base, nl, t, ctl);
-    if (hipMemcpyAsync(host_ctl, ctl, 3 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
+    if (hipMemcpyAsync(host_ctl, ctl, 6 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return CENTRA_EHIP;
     const uint32_t ne = static_cast<uint32_t>(host_ctl[0]);
     if (ne == le) break;   // nothing new: t unreachable
@@ -1315,6 +1379,8 @@ int wide_sample(const SampleArgs& a_in, uint32_t idx, uint64_t base, uint64_t* c
       const unsigned gc = std::min<uint64_t>(kWideGrid, (uint64_t(ne - le) + kWideBlock - 1) / kWideBlock);
       hipLaunchKernelGGL(k_wide_shift, dim3(gc), dim3(kWideBlock), 0, s, a, le, ne, shift);
     }
+    push_cost = host_ctl[3];
+    visited_in = host_ctl[5];
     lb = le;
     le = ne;
     L = nl;

@@ -28,6 +28,7 @@ struct SampleInst {
 
 struct SampleArgs {
   uint32_t n;
+  uint64_t n_arcs;
   uint32_t c_bits;
   uint32_t max_out_deg;
   const uint32_t* row_ptr;

@@ -380,6 +380,7 @@ int sample_to_stage(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint3
   if (count == 0) return CENTRA_OK;
   SampleArgs a{};
   a.n = g->n;
+  a.n_arcs = g->n_arcs;
   a.c_bits = g->count_bits;
   a.max_out_deg = g->max_out_degree;
   a.row_ptr = g->bfs_row_ptr;
@@ -490,6 +491,7 @@ int sample_append(centra_ctx* ctx, const centra_graph* g, uint64_t seed, uint32_
   if (count == 0) return CENTRA_OK;
   SampleArgs a{};
   a.n = g->n;
+  a.n_arcs = g->n_arcs;
   a.c_bits = g->count_bits;
   a.max_out_deg = g->max_out_degree;
   a.row_ptr = g->bfs_row_ptr;
