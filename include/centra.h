@@ -68,10 +68,12 @@ CENTRA_API uint32_t centra_abi_version(void);
  * Placement: the sampler's speed depends on where the device allocator puts
  * the pages of that state's per-BFS node records (the same launch varies
  * by up to ~18% from one allocation to the next, and not within one).
- * When a synchronous sampling call allocates at least 4 GiB of records, the
- * context times a launch of the call's first 65,536 work items on each of
- * up to four allocations of them, holding two at a time, and keeps the
- * fastest; results do not depend on it.  The environment variable CENTRA_SLOT_SEARCH=0
+ * When a synchronous sampling call first allocates at least 4 GiB of
+ * records on a context, the context times a launch of the call's first
+ * 65,536 work items on each of up to four allocations of them, holding two
+ * at a time, and keeps the fastest; it stops once a step takes more than
+ * 60 ms (a slow probe, or memory the device must clear first).  Results do
+ * not depend on it.  The environment variable CENTRA_SLOT_SEARCH=0
  * turns this off; centra_context_log reports the times.  (Tests only:
  * the environment variable CENTRA_STAMP_START sets the context's first BFS
  * stamp, to exercise the sampler's 32-bit stamp wrap.)
@@ -359,8 +361,9 @@ CENTRA_API int centra_check(centra_ctx *ctx, void *stream);
  * checks around t, the backtrack is not included); nodes counts every node
  * given a level.  A re-launch after a staging overflow counts again.
  * Wide samples: a BFS about to expand a level of more than 65,536 nodes,
- * or that has scanned more than 2^21 CSR entries (a flood of a skewed
- * graph's reachable set), is handed from its workgroup to a device-wide BFS that redraws the sample level by level
+ * or a level of at least 4,096 nodes after scanning more than 2^21 CSR
+ * entries (a flood of a skewed graph's reachable set; long narrow searches
+ * such as grids stay), is handed from its workgroup to a device-wide BFS that redraws the sample level by level
  * with the whole GPU (same hyperedge).  kernel_ms, arcs and nodes stay
  * those of the workgroup kernel (a handed-over BFS's partial work
  * included); `wide` counts such samples, wide_ms is the wall time of their

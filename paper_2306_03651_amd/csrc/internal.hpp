@@ -32,6 +32,7 @@ struct centra_ctx {
   centra::DevBuf slot_rec, slot_q, slot_praw, slot_pinfo;
   centra::DevBuf wide_ws;   // device-wide BFS: u64 ctl[8], then the deferred work items
   std::string log;   // one-time choices of the context (slot placement), one line each
+  bool placed = false;   // the slot records' placement was searched
   uint32_t slots = 0;
   uint32_t slot_n = 0;
   uint32_t stamp_next = 1;   // BFS stamp of the next sample (records start at stamp 0)

@@ -348,6 +348,11 @@ __device__ __forceinline__ uint64_t pred_weight(const Bits& bits, uint64_t* rec,
 
 __device__ __forceinline__ uint32_t caller_id(const SampleArgs& a, uint32_t v) { return a.orig_of ? a.orig_of[v] : v; }
 
+// A BFS past its scan budget is handed over only on a level of at least
+// this many nodes: the device-wide BFS pays a host round trip per level, so
+// deep, narrow searches (long grids) stay on their workgroups.
+constexpr uint32_t kWideMinWidth = 4096;
+
 // Appends work item idx to the deferred list (workgroup uniform); true if
 // it fit, the sample then being left to the device-wide BFS.
 template <int BLOCK>
@@ -750,10 +755,11 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 6 : 1) void k_sample_paths(Sa
         }
       }
       if constexpr (!LDS_BITS && !MULTI) {
-        // a level too wide for one workgroup, or a BFS that has already
-        // scanned millions of entries: the sample goes to the device-wide
-        // BFS (if the list has room), which redraws it in full
-        if (a.defer_nodes && (le - lb > a.defer_nodes || n_arcs - arcs0 > a.defer_arcs) &&
+        // a level too wide for one workgroup, or a wide level of a BFS that
+        // has already scanned millions of entries: the sample goes to the
+        // device-wide BFS (if the list has room), which redraws it in full
+        if (a.defer_nodes &&
+            (le - lb > a.defer_nodes || (n_arcs - arcs0 > a.defer_arcs && le - lb >= kWideMinWidth)) &&
             defer_sample<BLOCK>(a, idx, sh)) {
           deferred = true;
           break;
@@ -779,7 +785,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 6 : 1) void k_sample_paths(Sa
           // a level whose arcs run past the scan budget (hub frontiers): the
           // device-wide BFS redraws the sample (uniform; the partial level
           // is abandoned with the BFS's stamp)
-          if (a.defer_nodes && n_arcs - arcs0 > a.defer_arcs && defer_sample<BLOCK>(a, idx, sh)) {
+          if (a.defer_nodes && n_arcs - arcs0 > a.defer_arcs && le - lb >= kWideMinWidth &&
+              defer_sample<BLOCK>(a, idx, sh)) {
             deferred = true;
             break;
           }

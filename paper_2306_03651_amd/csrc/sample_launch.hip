@@ -134,9 +134,13 @@ static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t
 // allocations as the full one does, so fresh records of at least
 // kPlaceMinBytes are chosen among kPlaceCandidates allocations by timing
 // the batch's first kPlaceProbe work items on each (second of two launches;
-// results discarded, stamps used up as by any launch).  The search holds
+// results discarded, stamps used up as by any launch).  It runs for the
+// context's first large slot state only (a context that re-allocates as
+// its graphs change size would pay the search each time).  The search holds
 // two record arrays at a time and stops early if the budget or the device
-// cannot; CENTRA_SLOT_SEARCH=0 turns it off.  It synchronises the stream,
+// cannot, or once a step takes more than kPlaceStepMs of wall time (slow
+// probes, or freed memory the device must clear first);
+// CENTRA_SLOT_SEARCH=0 turns it off.  It synchronises the stream,
 // so stream-ordered launches skip it.
 // Wide samples: a BFS about to expand a level of more than kWideNodes
 // nodes, or past kWideArcs scanned entries, is left to the device-wide BFS
@@ -170,6 +174,7 @@ static int defer_args(centra_ctx* ctx, SampleArgs& a, hipStream_t s) {
 }
 
 constexpr int kPlaceCandidates = 4;
+constexpr double kPlaceStepMs = 60.0;   // wall time of one step (allocation, clear, two probes)
 constexpr uint32_t kPlaceProbe = 65536;
 constexpr size_t kPlaceMinBytes = size_t(4) << 30;
 
@@ -251,6 +256,7 @@ static int place_slots(centra_ctx* ctx, const SampleArgs& a, const SamplePlan& p
                        hipStream_t s) {
   const size_t rec_b = ctx->slot_rec.bytes;
   if (rec_b < kPlaceMinBytes) return CENTRA_OK;
+  ctx->placed = true;   // once per context: a later re-allocation keeps what it gets
   const uint32_t pc = count < kPlaceProbe ? count : kPlaceProbe;
   // every slot state held during the search must stay consistent with the
   // stamps: start numbering if nothing has been drawn yet, and skip the
@@ -259,11 +265,19 @@ static int place_slots(centra_ctx* ctx, const SampleArgs& a, const SamplePlan& p
   reserve_stamps(ctx, 0, s);
   if (uint64_t(ctx->stamp_next) + uint64_t(2 * kPlaceCandidates) * pc + count > 0xFFFFFFFFull) return CENTRA_OK;
   const auto t0 = std::chrono::steady_clock::now();
+  auto since = [](std::chrono::steady_clock::time_point x) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - x).count();
+  };
   float best = 0.f;
   int rc;
   if ((rc = probe_slots(ctx, a, plan, multi, pc, s, &best))) return rc;
   std::string line = "slot placement: " + std::to_string(best);
-  for (int c = 1; c < kPlaceCandidates && best > 0.f; ++c) {
+  // the search stops where it would cost more than it can win: a probe
+  // that is slow (long searches) or a step that is (the device clearing
+  // freed memory before handing it out again takes seconds for tens of GB)
+  bool go = since(t0) <= kPlaceStepMs;
+  for (int c = 1; go && c < kPlaceCandidates && best > 0.f; ++c) {
+    const auto tc = std::chrono::steady_clock::now();
     if (ctx->budget && ctx->allocated + rec_b > ctx->budget) break;
     void* r2 = nullptr;
     if (hipMalloc(&r2, rec_b) != hipSuccess) {
@@ -280,9 +294,11 @@ static int place_slots(centra_ctx* ctx, const SampleArgs& a, const SamplePlan& p
     (void)hipStreamSynchronize(s);
     (void)hipFree(r2);
     if (rc) return rc;
+    go = since(tc) <= kPlaceStepMs;
   }
+  const std::string stop = go ? "" : "; stopped: a step took over " + std::to_string(int(kPlaceStepMs)) + " ms";
   const double took = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  ctx->log += line + " ms -> " + std::to_string(best) + " ms (search " + std::to_string(took) + " ms)\n";
+  ctx->log += line + " ms -> " + std::to_string(best) + " ms (search " + std::to_string(took) + " ms" + stop + ")\n";
   return CENTRA_OK;
 }
 
@@ -305,7 +321,8 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
   if ((rc = ensure(ctx, ctx->stage_pos, size_t(count) * 8, false, s))) return rc;
   if ((rc = ensure(ctx, ctx->stage_len, size_t(count) * 4 + 8 + 8 * (size_t(count) + 1), false, s))) return rc;
   if ((rc = ensure(ctx, ctx->work_ctr, 64, false, s))) return rc;
-  if (fresh && !async_cap && slot_search_enabled() && (rc = place_slots(ctx, a, plan, multi, count, s))) return rc;
+  if (fresh && !ctx->placed && !async_cap && slot_search_enabled() && (rc = place_slots(ctx, a, plan, multi, count, s)))
+    return rc;
   uint64_t cap = async_cap ? async_cap : size_t(count) * 8 + 1024;
   if (ctx->stage_nodes.bytes / 4 > cap) cap = ctx->stage_nodes.bytes / 4;
   for (int attempt = 0; attempt < 3; ++attempt) {
