@@ -30,7 +30,7 @@ struct centra_ctx {
   // queue, stored pair counts), one set per concurrent BFS, sized for the
   // largest graph
   centra::DevBuf slot_rec, slot_q, slot_praw, slot_pinfo;
-  centra::DevBuf wide_ws;   // device-wide BFS: u64 ctl[8], then the deferred work items
+  centra::DevBuf wide_ws;   // device-wide BFS: u64 ctl[8] per sample of a group, then the deferred work items
   std::string log;   // one-time choices of the context (slot placement), one line each
   bool placed = false;   // the slot records' placement was searched
   uint32_t slots = 0;

@@ -1107,6 +1107,10 @@ void sample_kernel_launch(const SampleArgs& a, int block, bool lds_bits, bool mu
 // sample has finished) under a stamp of its own.
 constexpr int kWideBlock = 256;
 constexpr unsigned kWideGrid = 2048;
+// a level is pulled when the unvisited nodes' in-arcs (plus a quarter of n
+// for reading every tag) are fewer than kPullRatio times the frontier's
+// out-arcs: a push scans them twice and claims with returning atomics
+constexpr uint64_t kPullRatio = 8;
 
 // ctl: [0] queue length, [1] largest raw count of the new level, [2] 1 if
 // t is on the new level, [3] out-arcs of the last level (the cost of
@@ -1344,59 +1348,94 @@ __global__ __launch_bounds__(kWideBlock) void k_wide_backtrack(SampleArgs a, uin
   }
 }
 
-int wide_sample(const SampleArgs& a_in, uint32_t idx, uint64_t base, uint64_t* ctl, uint64_t* host_ctl,
-                uint32_t* d_out, hipStream_t s) {
-  SampleArgs a = a_in;
-  a.stats = ctl + 6;   // this BFS's arcs and nodes, apart from the workgroup kernel's
-  hipLaunchKernelGGL(k_wide_start, dim3(1), dim3(64), 0, s, a, idx, base, ctl);
-  if (hipMemcpyAsync(host_ctl, ctl, 5 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return CENTRA_EHIP;
-  const uint32_t t = static_cast<uint32_t>(host_ctl[4]);
-  uint32_t lb = 0, le = 1, L = 0, d = kUnseen;
-  // one synchronisation per level: claims, counts and the level's close,
-  // then the host reads its size, maximum and whether t is on it
-  // push a level (scan the frontier's out-arcs twice) unless pulling it
-  // (scan the unvisited nodes' in-arcs once, plus every node's tag) is
-  // cheaper; both give the same level and raw counts
-  uint64_t push_cost = host_ctl[3], visited_in = host_ctl[5];
-  for (;;) {
-    const uint32_t nl = L + 1;
-    const uint64_t pull_cost = (a.n_arcs - visited_in) + a.n / 4;
-    fill_u64(ctl + 1, 0, 3, s);
-    if (pull_cost < 2 * push_cost) {
-      hipLaunchKernelGGL(k_wide_pull, dim3(kWideGrid), dim3(kWideBlock), 0, s, a, base, nl, ctl);
-    } else {
-      const unsigned grid = std::min<uint64_t>(kWideGrid, (uint64_t(le - lb) + kWideBlock - 1) / kWideBlock);
-      hipLaunchKernelGGL(k_wide_level<0>, dim3(grid), dim3(kWideBlock), 0, s, a, lb, le, base, nl, ctl);
-      hipLaunchKernelGGL(k_wide_level<1>, dim3(grid), dim3(kWideBlock), 0, s, a, lb, le, base, nl, ctl);
-    }
-    hipLaunchKernelGGL(k_wide_close, dim3(kWideGrid), dim3(kWideBlock), 0, s, a, le, base, nl, t, ctl);
-    if (hipMemcpyAsync(host_ctl, ctl, 6 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return CENTRA_EHIP;
-    const uint32_t ne = static_cast<uint32_t>(host_ctl[0]);
-    if (ne == le) break;   // nothing new: t unreachable
-    if (host_ctl[2]) {     // t on level nl: its predecessors' levels are final
-      d = nl;
-      break;
-    }
-    uint32_t bl = 0;
-    for (uint64_t x = host_ctl[1]; x; x >>= 1) ++bl;
-    const uint32_t shift = bl > a.c_bits ? bl - a.c_bits : 0u;
-    if (shift) {
-      const unsigned gc = std::min<uint64_t>(kWideGrid, (uint64_t(ne - le) + kWideBlock - 1) / kWideBlock);
-      hipLaunchKernelGGL(k_wide_shift, dim3(gc), dim3(kWideBlock), 0, s, a, le, ne, shift);
-    }
-    push_cost = host_ctl[3];
-    visited_in = host_ctl[5];
-    lb = le;
-    le = ne;
-    L = nl;
+int wide_samples(const SampleArgs& a_in, const uint32_t* idx, uint32_t n_items, uint64_t stamp0, uint64_t* ctl,
+                 uint64_t* host_ctl, uint64_t* arcs, hipStream_t s) {
+  // per sample j: slot j's records and queue, ctl + 8 j, stamp stamp0 + j
+  struct Walk {
+    SampleArgs a;
+    uint64_t base, push_cost, visited_in;
+    uint32_t t, lb, le, L, d;
+    bool live;
+  };
+  std::vector<Walk> w(n_items);
+  for (uint32_t j = 0; j < n_items; ++j) {
+    Walk& x = w[j];
+    x.a = a_in;
+    x.a.rec = a_in.rec + 2 * size_t(j) * a_in.slot_stride;
+    x.a.q = a_in.q + size_t(j) * a_in.slot_stride;
+    x.a.stats = ctl + 8 * size_t(j) + 6;   // its arcs and nodes, apart from the workgroup kernel's
+    x.base = (stamp0 + j) << 32;
+    hipLaunchKernelGGL(k_wide_start, dim3(1), dim3(64), 0, s, x.a, idx[j], x.base, ctl + 8 * size_t(j));
   }
-  hipLaunchKernelGGL(k_wide_backtrack, dim3(1), dim3(kWideBlock), 0, s, a, idx, base, d);
-  if (hipGetLastError() != hipSuccess) return CENTRA_EHIP;
-  if (hipMemcpyAsync(host_ctl + 6, ctl + 6, 16, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
+  const size_t ctl_bytes = size_t(n_items) * 8 * 8;
+  if (hipMemcpyAsync(host_ctl, ctl, ctl_bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return CENTRA_EHIP;
-  *d_out = d;
+  for (uint32_t j = 0; j < n_items; ++j) {
+    Walk& x = w[j];
+    x.t = static_cast<uint32_t>(host_ctl[8 * j + 4]);
+    x.lb = 0;
+    x.le = 1;
+    x.L = 0;
+    x.d = kUnseen;
+    x.live = true;
+    x.push_cost = host_ctl[8 * j + 3];
+    x.visited_in = host_ctl[8 * j + 5];
+  }
+  // rounds: every live sample expands one level (pushed, or pulled when the
+  // unvisited nodes' in-arcs cost less than pushing the frontier twice)
+  // and closes it; one synchronisation per round reads every sample's new
+  // level size, maximum, costs and whether t is on it
+  for (uint32_t live = n_items; live;) {
+    for (uint32_t j = 0; j < n_items; ++j) {
+      Walk& x = w[j];
+      if (!x.live) continue;
+      uint64_t* c = ctl + 8 * size_t(j);
+      const uint32_t nl = x.L + 1;
+      const uint64_t pull_cost = (x.a.n_arcs - x.visited_in) + x.a.n / 4;
+      fill_u64(c + 1, 0, 3, s);
+      if (pull_cost < kPullRatio * x.push_cost) {
+        hipLaunchKernelGGL(k_wide_pull, dim3(kWideGrid), dim3(kWideBlock), 0, s, x.a, x.base, nl, c);
+      } else {
+        const unsigned grid = std::min<uint64_t>(kWideGrid, (uint64_t(x.le - x.lb) + kWideBlock - 1) / kWideBlock);
+        hipLaunchKernelGGL(k_wide_level<0>, dim3(grid), dim3(kWideBlock), 0, s, x.a, x.lb, x.le, x.base, nl, c);
+        hipLaunchKernelGGL(k_wide_level<1>, dim3(grid), dim3(kWideBlock), 0, s, x.a, x.lb, x.le, x.base, nl, c);
+      }
+      hipLaunchKernelGGL(k_wide_close, dim3(kWideGrid), dim3(kWideBlock), 0, s, x.a, x.le, x.base, nl, x.t, c);
+    }
+    if (hipMemcpyAsync(host_ctl, ctl, ctl_bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return CENTRA_EHIP;
+    for (uint32_t j = 0; j < n_items; ++j) {
+      Walk& x = w[j];
+      if (!x.live) continue;
+      const uint64_t* h = host_ctl + 8 * size_t(j);
+      const uint32_t nl = x.L + 1, ne = static_cast<uint32_t>(h[0]);
+      if (ne == x.le || h[2]) {   // nothing new (t unreachable), or t on level nl
+        x.d = ne == x.le ? kUnseen : nl;
+        x.live = false;
+        --live;
+        continue;
+      }
+      uint32_t bl = 0;
+      for (uint64_t v = h[1]; v; v >>= 1) ++bl;
+      const uint32_t shift = bl > x.a.c_bits ? bl - x.a.c_bits : 0u;
+      if (shift) {
+        const unsigned gc = std::min<uint64_t>(kWideGrid, (uint64_t(ne - x.le) + kWideBlock - 1) / kWideBlock);
+        hipLaunchKernelGGL(k_wide_shift, dim3(gc), dim3(kWideBlock), 0, s, x.a, x.le, ne, shift);
+      }
+      x.push_cost = h[3];
+      x.visited_in = h[5];
+      x.lb = x.le;
+      x.le = ne;
+      x.L = nl;
+    }
+  }
+  for (uint32_t j = 0; j < n_items; ++j)
+    hipLaunchKernelGGL(k_wide_backtrack, dim3(1), dim3(kWideBlock), 0, s, w[j].a, idx[j], w[j].base, w[j].d);
+  if (hipGetLastError() != hipSuccess) return CENTRA_EHIP;
+  if (hipMemcpyAsync(host_ctl, ctl, ctl_bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return CENTRA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return CENTRA_EHIP;
+  *arcs = 0;
+  for (uint32_t j = 0; j < n_items; ++j) *arcs += host_ctl[8 * j + 6];
   return CENTRA_OK;
 }
 

@@ -79,15 +79,17 @@ hipError_t sample_kernel_occupancy(int block, bool lds_bits, bool multi, size_t 
 size_t sample_lds_variant_bytes();
 void sample_kernel_launch(const SampleArgs& a, int block, bool lds_bits, bool multi, uint32_t grid, size_t dyn_lds,
                           hipStream_t s);
-// Device-wide BFS of one deferred work item idx of a single-graph launch
-// (a.first, a.seed, a.instance and the graph as in that launch): every
-// level expanded by the whole GPU (claims, then counts, then the level's
-// normalisation), the backtrack by one workgroup, the hyperedge staged
-// like the workgroup kernel's.  Uses slot 0's records and queue with stamp
-// base >> 32; ctl: u64[8] of device memory.  Returns the distance of t
-// (kUnseen if unreachable) through *d; synchronises the stream per level.
-int wide_sample(const SampleArgs& a, uint32_t idx, uint64_t base, uint64_t* ctl, uint64_t* host_ctl, uint32_t* d,
-                hipStream_t s);
+// Device-wide BFS of the deferred work items idx[0..n_items) of a
+// single-graph launch (a.first, a.seed, a.instance and the graph as in that
+// launch), advanced together: every round expands one level of each live
+// sample with the whole GPU (claims and counts pushed, or the level pulled),
+// then one synchronisation reads them all; then each backtrack by one
+// workgroup, the hyperedges staged like the workgroup kernel's.  Sample j
+// uses slot j's records and queue (n_items <= slots) with stamp stamp0 + j
+// and ctl[8 j .. 8 j + 8) of device memory (host_ctl: as many words on
+// the host).  *arcs receives the CSR entries they scanned.
+int wide_samples(const SampleArgs& a, const uint32_t* idx, uint32_t n_items, uint64_t stamp0, uint64_t* ctl,
+                 uint64_t* host_ctl, uint64_t* arcs, hipStream_t s);
 void stage_gather_launch(uint32_t count, const uint64_t* stage_pos, const uint32_t* he_len, const uint64_t* rel_off,
                          uint64_t base, const uint32_t* stage, uint64_t* he_off, uint32_t* he_nodes, hipStream_t s);
 

@@ -149,6 +149,7 @@ static int ensure_slots(centra_ctx* ctx, uint32_t gn, uint32_t want, hipStream_t
 constexpr uint32_t kWideNodes = 65536;
 constexpr uint64_t kWideArcs = uint64_t(1) << 21;   // about 30 ms of one workgroup's scanning
 constexpr uint32_t kWideCap = 4096;
+constexpr uint32_t kWideGroup = 64;   // deferred samples advanced together
 
 static bool wide_enabled() {
   const char* e = getenv("CENTRA_WIDE");
@@ -159,7 +160,7 @@ static bool wide_enabled() {
 // at byte 32 of work_ctr) and clears the counter.
 static int defer_args(centra_ctx* ctx, SampleArgs& a, hipStream_t s) {
   int rc;
-  if ((rc = ensure(ctx, ctx->wide_ws, 64 + size_t(kWideCap) * 4, false, s))) return rc;
+  if ((rc = ensure(ctx, ctx->wide_ws, size_t(kWideGroup) * 64 + size_t(kWideCap) * 4, false, s))) return rc;
   a.defer_nodes = kWideNodes;
   a.defer_arcs = kWideArcs;
   if (const char* e = getenv("CENTRA_WIDE_NODES")) {   // tests: a lower threshold
@@ -167,7 +168,7 @@ static int defer_args(centra_ctx* ctx, SampleArgs& a, hipStream_t s) {
     if (v >= 1 && v <= 0x7FFFFFFFl) a.defer_nodes = static_cast<uint32_t>(v);
   }
   a.defer_cap = kWideCap;
-  a.defer_list = reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->wide_ws.ptr) + 64);
+  a.defer_list = reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->wide_ws.ptr) + size_t(kWideGroup) * 64);
   a.defer_count = reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 32);
   fill_u64(reinterpret_cast<uint64_t*>(a.defer_count), 0, 1, s);
   return CENTRA_OK;
@@ -353,16 +354,18 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
       CENTRA_HIP(ctx, hipMemcpyAsync(list.data(), a.defer_list, size_t(n_wide) * 4, hipMemcpyDeviceToHost, s));
       CENTRA_HIP(ctx, hipStreamSynchronize(s));
       uint64_t* ctl = static_cast<uint64_t*>(ctx->wide_ws.ptr);
-      uint64_t host_ctl[8] = {};
+      std::vector<uint64_t> host_ctl(size_t(kWideGroup) * 8);
       const auto w0 = std::chrono::steady_clock::now();
-      for (uint32_t idx : list) {
-        reserve_stamps(ctx, 1, s);
-        const uint64_t base = uint64_t(ctx->stamp_next) << 32;
-        ctx->stamp_next += 1;
-        uint32_t d = 0;
-        if (wide_sample(a, idx, base, ctl, host_ctl, &d, s) != CENTRA_OK)
+      const uint32_t group = std::min<uint32_t>(kWideGroup, ctx->slots);
+      for (uint32_t j0 = 0; j0 < n_wide; j0 += group) {   // a group at a time, one slot each
+        const uint32_t nj = std::min<uint32_t>(group, n_wide - j0);
+        reserve_stamps(ctx, nj, s);
+        const uint64_t stamp0 = ctx->stamp_next;
+        ctx->stamp_next += nj;
+        uint64_t arcs = 0;
+        if (wide_samples(a, list.data() + j0, nj, stamp0, ctl, host_ctl.data(), &arcs, s) != CENTRA_OK)
           return hip_fail(ctx, hipGetLastError(), "sample_paths (device-wide BFS)");
-        ctx->st.wide_arcs += host_ctl[6];
+        ctx->st.wide_arcs += arcs;
       }
       ctx->st.wide_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
       CENTRA_HIP(ctx, hipMemcpyAsync(&host_ctr[1], static_cast<char*>(ctx->work_ctr.ptr) + 8, 8,
