@@ -1017,7 +1017,9 @@ __global__ __launch_bounds__(BLOCK, BLOCK <= 512 ? 6 : 1) void k_sample_paths(Sa
       __syncthreads();
     }
   }
-  if (tid == 0 && a.stats && n_arcs) {
+  // (a workgroup whose targets all lacked in-neighbours scanned no arc but
+  // still gave every source a level)
+  if (tid == 0 && a.stats && (n_arcs || n_nodes)) {
     atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[0]), static_cast<unsigned long long>(n_arcs));
     atomicAdd(reinterpret_cast<unsigned long long*>(&a.stats[1]), static_cast<unsigned long long>(n_nodes));
   }

@@ -60,16 +60,9 @@ def same_result(a, b):
 
 def same_iteration(x, y, work=True):
     # arcs and nodes count the sampling work done, which includes the redraw
-    # of samples [0, m_i) in the first iteration of a resume elsewhere.  The
-    # node count of the Bloom-filter kernels varies between identical
-    # launches by a few nodes in 10^4-10^5 (the hyperedges and the scanned
-    # arcs do not), so nodes are compared to 0.1%: a hidden redraw would
-    # double them.
+    # of samples [0, m_i) in the first iteration of a resume elsewhere
     for f in IT_FIELDS:
-        if f == "nodes":
-            if work:
-                assert abs(int(x.nodes) - int(y.nodes)) <= max(1, int(y.nodes) // 1000), f
-        elif work or f != "arcs":
+        if work or f not in ("arcs", "nodes"):
             assert getattr(x, f) == getattr(y, f), f
 
 
@@ -201,17 +194,15 @@ def driver(tmp, extra_env=None, resume=False, name="run"):
 
 
 def strip_ms(lines, redrawn_i=0):
-    """Records without timings and node counts (compared apart, to 0.1%),
-    and without the work counts of the first iteration of a resume, which
-    redraws the earlier samples.  Returns (records, node counts)."""
-    out, nodes = [], []
+    """Records without timings (and without the work counts of the first
+    iteration of a resume, which redraws the earlier samples)."""
+    out = []
     for line in lines:
         d = json.loads(line)
-        nodes.append(None if d["i"] == redrawn_i else d["nodes"])
-        for f in ("ms_sample", "ms_cover", "ms_mcera", "nodes") + (("arcs",) if d["i"] == redrawn_i else ()):
+        for f in ("ms_sample", "ms_cover", "ms_mcera") + (("arcs", "nodes") if d["i"] == redrawn_i else ()):
             d.pop(f)
         out.append(d)
-    return out, nodes
+    return out
 
 
 def test_driver_fault_and_resume(tmp_path):
@@ -235,9 +226,7 @@ def test_driver_fault_and_resume(tmp_path):
     a = json.loads((tmp_path / "full.res.json").read_text())
     b = json.loads((tmp_path / "cut.res.json").read_text())
     assert a == b
-    la, na = strip_ms((tmp_path / "full.jsonl").read_text().splitlines(), redrawn_i=3)
-    lb, nb = strip_ms((tmp_path / "cut.jsonl").read_text().splitlines(), redrawn_i=3)
+    la = strip_ms((tmp_path / "full.jsonl").read_text().splitlines(), redrawn_i=3)
+    lb = strip_ms((tmp_path / "cut.jsonl").read_text().splitlines(), redrawn_i=3)
     assert la == lb and [d["i"] for d in la] == list(range(1, a["iterations"] + 1))
-    for x, y in zip(na, nb):
-        assert (x is None) == (y is None) and (x is None or abs(x - y) <= max(1, y // 1000))
     assert a["iterations"] >= 3 and a["rc"] in (binding.CENTRA_OK, binding.CENTRA_NOT_CERTIFIED)
