@@ -187,7 +187,8 @@ void centra_destroy(centra_ctx* ctx) {
   if (!ctx) return;
   DeviceGuard guard(ctx->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&ctx->slot_rec, &ctx->slot_q, &ctx->slot_praw, &ctx->slot_pinfo, &ctx->wide_ws, &ctx->stage_nodes, &ctx->stage_pos,
+  DevBuf* bufs[] = {&ctx->slot_rec, &ctx->slot_q, &ctx->slot_praw, &ctx->slot_pinfo, &ctx->wide_ws,
+                    &ctx->stage_nodes, &ctx->stage_pos,
                     &ctx->stage_len, &ctx->work_ctr, &ctx->scan_tmp, &ctx->deg, &ctx->inc_off,
                     &ctx->inc_cursor, &ctx->inc, &ctx->inc_node, &ctx->gain, &ctx->covered, &ctx->best,
                     &ctx->newcov, &ctx->words, &ctx->P, &ctx->Rtm, &ctx->topk_tmp, &ctx->misc,

@@ -540,3 +540,25 @@ def test_wide_bfs_on_a_flood(ctx):
     for i, (h, info) in zip(idx, oracle_paths(g, 1, 0, idx + first, c_bits)):
         assert np.array_equal(nodes1[int(off1[i]):int(off1[i + 1])], h), i
         assert dist1[i] == info.dist, i
+
+
+def test_work_counts_are_deterministic(ctx):
+    # Half the nodes of a directed R-MAT graph have no in-neighbour, so with
+    # about one sample per workgroup some workgroups draw only targets that
+    # need no BFS (no arc scanned); their sources' levels still count.  The
+    # arcs and nodes of a launch must not depend on how the work items were
+    # spread over the workgroups.
+    g = inputs.rmat_graph(11, 8, seed=5)
+    dg = binding.DeviceGraph(ctx, g)
+    seen = set()
+    try:
+        for rep in range(6):
+            binding.centra_sampler_stats_get(ctx, reset=True)
+            binding.sample_paths(ctx, dg, 5, 2, 0, 3000)
+            torch.cuda.synchronize()
+            st = binding.centra_sampler_stats_get(ctx)
+            seen.add((st.arcs, st.nodes))
+    finally:
+        dg.release()
+    say(f"  work counts over 6 launches: {sorted(seen)}")
+    assert len(seen) == 1
