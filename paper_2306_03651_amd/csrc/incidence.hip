@@ -231,7 +231,8 @@ struct IncWs {
 IncWs carve(void* ws, uint32_t n, uint64_t span_cap, size_t* total) {
   const size_t B = buckets_of(n), BG = B * kPartGrid;
   const size_t tile_n = scan_tile_words(BG > n ? BG : n);
-  char* p = static_cast<char*>(ws);
+  // addresses are formed as integers: ws is NULL when only the size is asked for
+  const uintptr_t p = reinterpret_cast<uintptr_t>(ws);
   size_t o = 0;
   IncWs w{};
   w.cnt = reinterpret_cast<uint32_t*>(p + o);
