@@ -43,6 +43,9 @@ struct centra_ctx {
   uint32_t bi_n = 0;
   // sampling staging area
   centra::DevBuf stage_nodes, stage_pos, stage_len, work_ctr, multi_tab;
+  // hyperedge entries and samples staged by the context's synchronous
+  // launches so far (the first staging size of the next launch follows them)
+  uint64_t staged_entries = 0, staged_samples = 0;
   // scan scratch
   centra::DevBuf scan_tmp;
   // incidence (node -> samples) and greedy / AMCERA workspaces

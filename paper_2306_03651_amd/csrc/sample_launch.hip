@@ -324,10 +324,23 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
   if ((rc = ensure(ctx, ctx->work_ctr, 64, false, s))) return rc;
   if (fresh && !ctx->placed && !async_cap && slot_search_enabled() && (rc = place_slots(ctx, a, plan, multi, count, s)))
     return rc;
-  uint64_t cap = async_cap ? async_cap : size_t(count) * 8 + 1024;
+  const uint64_t base_cap = async_cap ? async_cap : size_t(count) * 8 + 1024;
+  uint64_t cap = base_cap;
+  if (!async_cap && ctx->staged_samples) {
+    // entries per sample staged on this context so far, with half again as
+    // a margin: an area too small makes the whole launch run twice
+    const double per = 1.5 * double(ctx->staged_entries) / double(ctx->staged_samples);
+    const uint64_t est = static_cast<uint64_t>(per * double(count)) + 1024;
+    if (est > cap) cap = est;
+  }
   if (ctx->stage_nodes.bytes / 4 > cap) cap = ctx->stage_nodes.bytes / 4;
   for (int attempt = 0; attempt < 3; ++attempt) {
-    if ((rc = ensure(ctx, ctx->stage_nodes, cap * 4, false, s))) return rc;
+    rc = ensure(ctx, ctx->stage_nodes, cap * 4, false, s);
+    if (rc == CENTRA_ENOMEM && attempt == 0 && cap > base_cap && ctx->stage_nodes.bytes / 4 < cap) {
+      cap = base_cap;   // the estimate does not fit the budget: start from the plain size
+      rc = ensure(ctx, ctx->stage_nodes, cap * 4, false, s);
+    }
+    if (rc) return rc;
     cap = ctx->stage_nodes.bytes / 4;
     uint32_t* work = static_cast<uint32_t*>(ctx->work_ctr.ptr);
     uint64_t* used = reinterpret_cast<uint64_t*>(static_cast<char*>(ctx->work_ctr.ptr) + 8);
@@ -387,6 +400,8 @@ static int launch_sampler(centra_ctx* ctx, SampleArgs a, uint32_t count, uint32_
     ctx->st.slots = grid;
     if (host_used <= cap) {
       *total = host_used;
+      ctx->staged_entries += host_used;
+      ctx->staged_samples += count;
       return CENTRA_OK;
     }
     cap = host_used + 1024;   // staging overflowed: the batch is redrawn identically
