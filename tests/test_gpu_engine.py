@@ -276,3 +276,35 @@ def test_fused_launch_after_placement_search():
         assert "slot placement:" in clog
     finally:
         binding.centra_destroy(ctx)
+
+
+def test_fused_launch_stages_in_one_attempt_after_plain_runs():
+    # A launch's first staging size follows the entries per sample the
+    # context has staged so far.  A grid's paths have tens of nodes, far
+    # above the 8 entries per sample a context starts from: the plain run
+    # overflows once and is redrawn, and the larger fused launch after it on
+    # the same context must then stage in one attempt (the staging area the
+    # plain run left is too small for it), with the standalone result.
+    ctx = binding.centra_create(0, 0)
+    g = inputs.grid_graph(96)
+    dg = binding.DeviceGraph(ctx, g)
+    eng = binding.Engine(ctx, 0, binding.CENTRA_ENGINE_NO_TUNE)
+    try:
+        binding.centra_progressive(ctx, dg.handle, 5, 8, 0.05, 0.1, 3, 1, 5000, 5000)
+        st0 = binding.centra_sampler_stats_get(ctx)   # attempts count their samples; entries only once
+        per_sample = st0.hyperedge_nodes / 5000
+        say(f"plain run: {st0.launches} launch attempts, {per_sample:.1f} entries per sample")
+        assert per_sample > 16 and st0.launches == 2 and st0.samples == 10000
+        pool = (3, 0, 8, 40000, 40000)
+        pid = eng.add_pool(dg.handle, *pool)
+        qid = eng.submit(pid, 5, 8, 0.05, 0.1)
+        eng.run()
+        got = eng.result(qid)
+        st1 = binding.centra_sampler_stats_get(ctx)
+        assert eng.stats().sampler_launches == 1
+        assert st1.launches - st0.launches == 1 and st1.samples - st0.samples == 40000
+        same(got, standalone(ctx, dg, pool, (5, 8, 0.05, 0.1)))
+    finally:
+        eng.destroy()
+        dg.release()
+        binding.centra_destroy(ctx)
